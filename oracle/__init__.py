@@ -1,0 +1,296 @@
+"""CPU FP64 oracle for the constraint multigrid (test infrastructure only).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It wraps ``liboracle.so`` built from
+``mg_oracle.c`` (plain C, FP64) and shares no code with the GPU library.
+
+The discrete system, the boundary rule and the multigrid algorithm it follows
+are stated at the top of ``mg_oracle.c``; the problem is the paper's
+Hamiltonian and momentum constraints (Summary, eqs. Ham and Mom) in CTT form,
+solved by multigrid (Key features, "Fast"), with per-iteration constraint
+norms (Key features, "Diagnostics").
+
+Pins (tests marked ``not gpu``): polynomial exactness and Fourier symbols of
+the stencils, FFT-exact linear solves, uniform density (psi = 1), vacuum
+puncture (u = 0), the Gaussian-source closed form under the Robin rule,
+brute-force dense solves, and 4th-order convergence to manufactured
+solutions.  No oracle function is left "parity unpinned".
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+SRC_PATH = os.path.join(_HERE, "mg_oracle.c")
+
+BC_PERIODIC = 0
+BC_ROBIN = 1
+
+
+def build(verbose: bool = False) -> str:
+    """Compile liboracle.so with gcc (FP64, no fast-math, no FMA contraction)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-ffp-contract=off",
+           "-fPIC", "-shared", "-Wall", "-o", LIB_PATH + ".tmp", SRC_PATH, "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.check_call(cmd)
+    os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+class OrcParams(C.Structure):
+    _fields_ = [("n", C.c_int32), ("levels", C.c_int32), ("bc", C.c_int32),
+                ("nu_pre", C.c_int32), ("nu_post", C.c_int32),
+                ("solve_momentum", C.c_int32), ("pad0", C.c_int32), ("pad1", C.c_int32),
+                ("length", C.c_double), ("origin", C.c_double * 3), ("K", C.c_double),
+                ("puncture_mass", C.c_double), ("puncture_pos", C.c_double * 3)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        _lib = C.CDLL(LIB_PATH)
+        dp = C.POINTER(C.c_double)
+        pp = C.POINTER(OrcParams)
+        ip = C.c_int
+        sig = {
+            "orc_residuals": [pp, dp, dp, dp, dp, dp, dp, dp, dp, dp],
+            "orc_norms": [ip, dp, dp, dp],
+            "orc_apply_lap": [pp, ip, dp, dp],
+            "orc_apply_d1": [pp, ip, dp, ip, dp],
+            "orc_apply_deltaL": [pp, ip, dp, dp],
+            "orc_pass_psi": [pp, ip, dp, dp, dp, dp, ip],
+            "orc_pass_W": [pp, ip, dp, dp, dp, ip],
+            "orc_restrict": [ip, dp, dp],
+            "orc_prolong_add": [pp, ip, dp, dp],
+            "orc_interp_cubic": [pp, ip, dp, dp],
+            "orc_coarse_solve_psi": [pp, ip, dp, dp, dp],
+            "orc_coarse_solve_W": [pp, ip, dp, dp],
+            "orc_vcycle_psi": [pp, dp, dp, dp],
+            "orc_vcycle_W": [pp, dp, dp],
+            "orc_step": [pp, ip, dp, dp, dp, dp, dp, dp],
+            "orc_solve": [pp, dp, dp, dp, dp, dp, dp, C.c_double, ip, dp, ip,
+                          C.POINTER(C.c_int), dp],
+            "orc_scalar_sources": [pp, ip, dp, ip, dp, C.c_double, dp, dp, dp],
+            "orc_shell_sources": [pp, C.c_double, C.c_double, C.c_double, C.c_double,
+                                  dp, dp, dp],
+            "orc_num_threads": [],
+        }
+        for name, args in sig.items():
+            f = getattr(_lib, name)
+            f.argtypes = args
+            f.restype = C.c_int if name in ("orc_coarse_solve_psi", "orc_coarse_solve_W",
+                                            "orc_vcycle_psi", "orc_vcycle_W", "orc_step",
+                                            "orc_solve", "orc_num_threads") else None
+    return _lib
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous, "float64 C-contiguous array expected"
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def params(n, levels=1, bc=BC_PERIODIC, length=1.0, origin=(0.0, 0.0, 0.0), K=0.0,
+           nu_pre=2, nu_post=2, solve_momentum=False, puncture_mass=0.0,
+           puncture_pos=(0.0, 0.0, 0.0)) -> OrcParams:
+    p = OrcParams()
+    p.n, p.levels, p.bc = n, levels, bc
+    p.nu_pre, p.nu_post = nu_pre, nu_post
+    p.solve_momentum = 1 if solve_momentum else 0
+    p.length = length
+    for a in range(3):
+        p.origin[a] = origin[a]
+        p.puncture_pos[a] = puncture_pos[a]
+    p.K = K
+    p.puncture_mass = puncture_mass
+    return p
+
+
+def params_from_workload(w, K=0.0) -> OrcParams:
+    return params(w.n, w.levels, w.bc, w.length, w.origin, K, w.nu_pre, w.nu_post,
+                  w.solve_momentum, w.puncture_mass, w.puncture_pos)
+
+
+def _z(n, comps=1):
+    return np.zeros((comps, n, n, n) if comps > 1 else (n, n, n), dtype=np.float64)
+
+
+# ---- sources (matter projections) ------------------------------------------------
+
+def scalar_sources(p: OrcParams, phi_modes, pi_modes, mass=1.0):
+    n = p.n
+    rho5, rho1, S = _z(n), _z(n), _z(n, 3)
+    phi_modes = np.ascontiguousarray(phi_modes, dtype=np.float64)
+    pi_modes = np.ascontiguousarray(pi_modes, dtype=np.float64)
+    lib().orc_scalar_sources(C.byref(p), len(phi_modes), _ptr(phi_modes) if len(phi_modes) else None,
+                             len(pi_modes), _ptr(pi_modes) if len(pi_modes) else None, mass,
+                             _ptr(rho5), _ptr(rho1), _ptr(S))
+    return rho5, rho1, S
+
+
+def shell_sources(p: OrcParams, amplitude, r0, width2, mass=1.0):
+    n = p.n
+    rho5, rho1, S = _z(n), _z(n), _z(n, 3)
+    lib().orc_shell_sources(C.byref(p), amplitude, r0, width2, mass, _ptr(rho5), _ptr(rho1), _ptr(S))
+    return rho5, rho1, S
+
+
+def K_from_mean_density(rho5, rho1):
+    """K^2 = 24 pi <rho> at psi = 1 (periodic workloads)."""
+    return float(np.sqrt(24.0 * np.pi * np.mean(rho5 + rho1)))
+
+
+def sources_for(w):
+    """Sources and K for a synthetic workload (periodic: K from the mean density;
+    puncture: K = 0)."""
+    p = params_from_workload(w)
+    if w.shell is not None:
+        rho5, rho1, S = shell_sources(p, w.shell["amplitude"], w.shell["r0"], w.shell["width2"],
+                                      w.scalar_mass)
+        K = 0.0
+    else:
+        rho5, rho1, S = scalar_sources(p, w.phi_modes, w.pi_modes, w.scalar_mass)
+        K = K_from_mean_density(rho5, rho1)
+    return rho5, rho1, S, K
+
+
+# ---- residuals and norms ---------------------------------------------------------
+
+def residuals(p, u, W, rho5, rho1, S, f=None):
+    n = p.n
+    H, M, c = _z(n), _z(n, 3), _z(n)
+    lib().orc_residuals(C.byref(p), _ptr(u), _ptr(W), _ptr(rho5), _ptr(rho1), _ptr(S), _ptr(f),
+                        _ptr(H), _ptr(M), _ptr(c))
+    return H, M, c
+
+
+def norms(H, M=None):
+    out = np.zeros(4)
+    lib().orc_norms(H.shape[0], _ptr(np.ascontiguousarray(H)),
+                    _ptr(np.ascontiguousarray(M)) if M is not None else None, _ptr(out))
+    return out
+
+
+# ---- operators -------------------------------------------------------------------
+
+def apply_lap(p, a):
+    out = np.zeros_like(a)
+    lib().orc_apply_lap(C.byref(p), a.shape[-1], _ptr(a), _ptr(out))
+    return out
+
+
+def apply_d1(p, a, axis):
+    out = np.zeros_like(a)
+    lib().orc_apply_d1(C.byref(p), a.shape[-1], _ptr(a), axis, _ptr(out))
+    return out
+
+
+def apply_deltaL(p, W):
+    out = np.zeros_like(W)
+    lib().orc_apply_deltaL(C.byref(p), W.shape[-1], _ptr(W), _ptr(out))
+    return out
+
+
+def pass_psi(p, d, r, c, colour):
+    out = np.zeros_like(d)
+    lib().orc_pass_psi(C.byref(p), d.shape[-1], _ptr(d), _ptr(out), _ptr(r), _ptr(c), colour)
+    return out
+
+
+def pass_W(p, d, r, colour):
+    out = np.zeros_like(d)
+    lib().orc_pass_W(C.byref(p), d.shape[-1], _ptr(d), _ptr(out), _ptr(r), colour)
+    return out
+
+
+def restrict(fine):
+    nf = fine.shape[-1]
+    coarse = np.zeros((nf // 2,) * 3)
+    lib().orc_restrict(nf, _ptr(np.ascontiguousarray(fine)), _ptr(coarse))
+    return coarse
+
+
+def prolong_add(p, coarse, fine):
+    fine = fine.copy()
+    lib().orc_prolong_add(C.byref(p), coarse.shape[-1], _ptr(np.ascontiguousarray(coarse)), _ptr(fine))
+    return fine
+
+
+def interp_cubic(p, coarse):
+    nc = coarse.shape[-1]
+    fine = np.zeros((2 * nc,) * 3)
+    lib().orc_interp_cubic(C.byref(p), nc, _ptr(np.ascontiguousarray(coarse)), _ptr(fine))
+    return fine
+
+
+def coarse_solve_psi(p, c, r):
+    x = np.zeros_like(r)
+    rc = lib().orc_coarse_solve_psi(C.byref(p), r.shape[-1], _ptr(c), _ptr(r), _ptr(x))
+    if rc:
+        raise ArithmeticError("singular coarse matrix")
+    return x
+
+
+def coarse_solve_W(p, r):
+    x = np.zeros_like(r)
+    rc = lib().orc_coarse_solve_W(C.byref(p), r.shape[-1], _ptr(r), _ptr(x))
+    if rc:
+        raise ArithmeticError("singular coarse matrix")
+    return x
+
+
+def vcycle_psi(p, c, r):
+    d = np.zeros_like(r)
+    rc = lib().orc_vcycle_psi(C.byref(p), _ptr(c), _ptr(r), _ptr(d))
+    if rc:
+        raise ArithmeticError("singular coarse matrix")
+    return d
+
+
+def vcycle_W(p, r):
+    d = np.zeros_like(r)
+    rc = lib().orc_vcycle_W(C.byref(p), _ptr(r), _ptr(d))
+    if rc:
+        raise ArithmeticError("singular coarse matrix")
+    return d
+
+
+def step(p, eq, u, W, rho5, rho1, S, f=None):
+    """One outer update (eq 1: psi, 2: W, 3: W then psi), in place on u and W."""
+    rc = lib().orc_step(C.byref(p), eq, _ptr(u), _ptr(W), _ptr(rho5), _ptr(rho1), _ptr(S), _ptr(f))
+    if rc:
+        raise ArithmeticError("singular coarse matrix")
+
+
+class SolveResult:
+    def __init__(self, status, iters, history, norms):
+        self.status, self.iters, self.history, self.norms = status, iters, history, norms
+
+    def __repr__(self):
+        return f"SolveResult(status={self.status}, iters={self.iters}, norms={self.norms})"
+
+
+def solve(p, u, W, rho5, rho1, S, f=None, tol=1e-10, max_outer=60):
+    """Newton-multigrid solve in place on (u, W); returns a SolveResult."""
+    hist = np.zeros((max_outer + 1, 4))
+    it = C.c_int(0)
+    nr = np.zeros(4)
+    st = lib().orc_solve(C.byref(p), _ptr(u), _ptr(W), _ptr(rho5), _ptr(rho1), _ptr(S), _ptr(f),
+                         tol, max_outer, _ptr(hist), max_outer + 1, C.byref(it), _ptr(nr))
+    return SolveResult(st, it.value, hist[: min(it.value + 1, max_outer + 1)], nr)
+
+
+def num_threads() -> int:
+    return lib().orc_num_threads()

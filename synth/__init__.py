@@ -1,0 +1,152 @@
+"""Seeded synthetic inputs for the constraint solve.
+
+This module only draws random numbers and fixes workload parameters: the
+wavevectors, phases and amplitudes of the scalar-field Fourier modes, grid
+sizes and box geometry.  It evaluates no field and computes no density,
+residual or operator: both the CPU oracle and the GPU library turn these
+tables into sources (rho, S_i) on their own.
+
+Workloads (scalar-field matter, the paper's periodic-cosmology and
+black-hole scenarios, Key features):
+
+* ``hamiltonian_32``  periodic cube L=1, 32^3, 4 levels, 3 modes of
+  amplitude 0.01, Pi = 0, plain FP64, momentum trivial.
+* ``coupled_128``     periodic cube L=1, 128^3, 6 levels, phi: 8 modes of
+  amplitude 0.05; Pi: 8 modes of amplitude 0.02 (own stream).
+* ``puncture_shell``  box [-32,32]^3, M=1 puncture at the centre, scalar
+  shell phi = 0.1 exp(-(r-10)^2/4) Y_11, Pi = 0, Robin outer boundary.
+* ``scan_96``         96 periodic instances, N uniform on {32,48,64,96},
+  phi amplitude uniform on [0.01, 0.1], Pi amplitude 0.02.
+
+Mode tables are float64 arrays of shape (count, 5): kx, ky, kz (integers
+stored as float), amplitude, phase.  A field is meant as
+sum_m amp_m * cos(2 pi k_m . x / L + phase_m).
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional
+
+import numpy as np
+
+BC_PERIODIC = 0
+BC_ROBIN = 1
+PREC_FP64 = 0
+PREC_FP32_IR = 1
+
+
+def wavevectors(kmax: int = 3) -> np.ndarray:
+    """All integer vectors k with 0 < |k|^2 <= kmax^2, in a fixed order (122 for kmax=3)."""
+    out = []
+    r = range(-kmax, kmax + 1)
+    for a in r:
+        for b in r:
+            for c in r:
+                q = a * a + b * b + c * c
+                if 0 < q <= kmax * kmax:
+                    out.append((a, b, c))
+    return np.asarray(out, dtype=np.int64)
+
+
+def fourier_modes(rng: np.random.Generator, count: int, amplitude: float) -> np.ndarray:
+    """Draw ``count`` distinct wavevectors uniformly from ``wavevectors()``, with
+    uniform phases on [0, 2 pi) and a common amplitude."""
+    ks = wavevectors()
+    pick = rng.choice(len(ks), size=count, replace=False)
+    phases = rng.uniform(0.0, 2.0 * np.pi, size=count)
+    tab = np.zeros((count, 5), dtype=np.float64)
+    tab[:, 0:3] = ks[pick]
+    tab[:, 3] = amplitude
+    tab[:, 4] = phases
+    return tab
+
+
+@dataclasses.dataclass
+class Workload:
+    """One initial-data instance: geometry, solver options and matter draws."""
+    name: str
+    n: int
+    levels: int
+    length: float = 1.0
+    origin: tuple = (0.0, 0.0, 0.0)
+    bc: int = BC_PERIODIC
+    precision: int = PREC_FP64
+    solve_momentum: bool = False
+    nu_pre: int = 2
+    nu_post: int = 2
+    scalar_mass: float = 1.0
+    phi_modes: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 5)))
+    pi_modes: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 5)))
+    # puncture + shell scenario
+    puncture_mass: float = 0.0
+    puncture_pos: tuple = (0.0, 0.0, 0.0)
+    shell: Optional[dict] = None
+    seed: Optional[int] = None
+    tol: float = 1e-10
+
+    @property
+    def h(self) -> float:
+        return self.length / self.n
+
+
+def coarsest_levels(n: int) -> int:
+    """Number of levels when halving while n is even and n/2 >= 3."""
+    lv = 1
+    while n % 2 == 0 and n // 2 >= 3:
+        n //= 2
+        lv += 1
+    return lv
+
+
+def hamiltonian_32(seed: int = 0) -> Workload:
+    rng = np.random.default_rng(seed)
+    return Workload(name="hamiltonian_32", n=32, levels=4, seed=seed,
+                    phi_modes=fourier_modes(rng, 3, 0.01),
+                    precision=PREC_FP64, solve_momentum=False)
+
+
+def coupled(n: int = 128, seed: int = 0, phi_amp: float = 0.05,
+            precision: int = PREC_FP32_IR, levels: Optional[int] = None) -> Workload:
+    rng_phi = np.random.default_rng(seed)
+    rng_pi = np.random.default_rng([seed, 1])
+    return Workload(name=f"coupled_{n}", n=n,
+                    levels=levels if levels is not None else coarsest_levels(n),
+                    seed=seed, phi_modes=fourier_modes(rng_phi, 8, phi_amp),
+                    pi_modes=fourier_modes(rng_pi, 8, 0.02),
+                    precision=precision, solve_momentum=True)
+
+
+def coupled_128(seed: int = 0, precision: int = PREC_FP32_IR) -> Workload:
+    return coupled(128, seed, 0.05, precision)
+
+
+def puncture_shell(n: int = 256, precision: int = PREC_FP32_IR,
+                   levels: int = 6) -> Workload:
+    return Workload(name=f"puncture_shell_{n}", n=n, levels=levels, length=64.0,
+                    origin=(-32.0, -32.0, -32.0), bc=BC_ROBIN, precision=precision,
+                    solve_momentum=False, puncture_mass=1.0,
+                    puncture_pos=(0.0, 0.0, 0.0),
+                    shell=dict(amplitude=0.1, r0=10.0, width2=4.0))
+
+
+def scan_96(count: int = 96, size_seed: int = 12345,
+            sizes=(32, 48, 64, 96)) -> List[Workload]:
+    rng = np.random.default_rng(size_seed)
+    ns = rng.choice(np.asarray(sizes), size=count)
+    amps = rng.uniform(0.01, 0.1, size=count)
+    out = []
+    for i in range(count):
+        w = coupled(int(ns[i]), seed=i, phi_amp=float(amps[i]), precision=PREC_FP32_IR)
+        w.name = f"scan_{i}"
+        out.append(w)
+    return out
+
+
+def random_smooth_field(seed: int, n: int, count: int = 4, amplitude: float = 0.1) -> np.ndarray:
+    """A mode table for a smooth periodic test field (initial guesses, forcing)."""
+    return fourier_modes(np.random.default_rng([seed, 7]), count, amplitude)
+
+
+def uniform_random(seed: int, shape, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
+    """Plain seeded uniform noise (float64), for operator-level parity inputs."""
+    return np.random.default_rng([seed, 11]).uniform(lo, hi, size=shape)
