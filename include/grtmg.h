@@ -1,0 +1,246 @@
+/*
+ * grtmg.h -- C ABI of the MI355X multigrid solver for the initial-data
+ * constraints of numerical relativity.
+ *
+ * The problem is the pair of constraint equations of the paper's Summary:
+ * the Hamiltonian constraint (eq. Ham) and the momentum constraint (eq. Mom),
+ * with the matter projections rho and S_i of a scalar field, solved in
+ * conformal transverse-traceless (CTT) form for the conformal factor psi and
+ * the vector potential W_i of the longitudinal extrinsic curvature.  The
+ * solver is geometric multigrid (Key features: "Fast", a multigrid method
+ * over a hierarchy of discretisations) and reports the constraint norms at
+ * every iteration (Key features: "Diagnostics").
+ *
+ * Discrete system solved (cell-centred N^3 grid, h = L/N, 4th-order central
+ * differences D_a, D_aa, D_ab = D_a D_b; psi = psi0 + u):
+ *   H_h = L_h u + 2 pi rho5 psi^5 + 2 pi rho1 psi - (K^2/12) psi^5
+ *         + (1/8) A2 psi^-7 + f                                   -> 0
+ *   M_h = Delta_L,h W - (8 pi psi^6 S - mean(8 pi psi^6 S))       -> 0
+ * with Abar_ab = D_a W_b + D_b W_a - (2/3) delta_ab D_c W_c, A2 = Abar_ab Abar_ab,
+ * (Delta_L W)_a = sum_b D_bb W_a + (1/3)(D_aa W_a + sum_{b!=a} D_ab W_b),
+ * rho = rho5 + psi^-4 rho1 (rho5 = Pi^2/2 + V(phi), rho1 = |d phi|^2/2),
+ * S_a = -Pi d_a phi, constant K; psi0 = 1, or 1 + M/(2r) with a puncture.
+ * The mean of the momentum source is removed on periodic grids.
+ *
+ * Conventions for every call:
+ *  - Arrays are structure-of-arrays, cell-centred, z fastest:
+ *    element (i,j,k) of an N^3 field is at (i*N + j)*N + k; a 3-vector field
+ *    stores its x, y, z components as three consecutive N^3 blocks.
+ *  - Names starting with d_ are device pointers, h_ host pointers.
+ *  - The caller owns every array and the workspace; the library never
+ *    allocates device memory and only carves the workspace it is given.  It
+ *    owns the host-side mg_ctx until mg_destroy, plus a few bytes of pinned
+ *    host memory per context for the norms.
+ *  - Source arrays passed to mg_setup are borrowed and must outlive the ctx.
+ *  - All work is enqueued on the HIP stream given at setup (a hipStream_t
+ *    passed as void*; NULL means the default stream).  Calls that return host
+ *    scalars (norms, reports) synchronise that stream.
+ *  - No call throws.  Arguments are validated before any HIP call; a non-OK
+ *    status leaves device arrays untouched unless stated otherwise.
+ */
+#ifndef GRTMG_H
+#define GRTMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum mg_status {
+    MG_OK = 0,
+    MG_ERR_INVALID = 1,       /* bad argument (checked before any HIP call)        */
+    MG_ERR_WORKSPACE = 2,     /* workspace missing, too small or misaligned        */
+    MG_ERR_HIP = 3,           /* a HIP runtime call failed                         */
+    MG_ERR_NOT_CONVERGED = 4, /* max_outer updates done without reaching tol        */
+    MG_ERR_DIVERGED = 5,      /* non-finite or exploding constraint norm            */
+    MG_ERR_SINGULAR = 6       /* coarsest-level matrix could not be factorised      */
+} mg_status;
+
+enum { MG_BC_PERIODIC = 0, MG_BC_ROBIN = 1 };
+enum { MG_PREC_FP64 = 0, MG_PREC_FP32_IR = 1 };
+enum { MG_EQ_PSI = 1, MG_EQ_W = 2, MG_EQ_BOTH = 3 };
+enum { MG_FLAG_CONFORMAL_MATTER = 1 };
+
+/*
+ * Problem and solver parameters.
+ *  n              cells per axis; every level but the coarsest must have n_l
+ *                 even and n_l >= 6, the coarsest n >> (levels-1) >= 3.
+ *  levels         number of multigrid levels (1..16).
+ *  bc             MG_BC_PERIODIC, or MG_BC_ROBIN: ghost a(g) = a(b)|x_b|/|x_g|,
+ *                 b = grid cell nearest g, radii from puncture_pos.  The
+ *                 momentum equation is supported on periodic grids only.
+ *  precision      MG_PREC_FP64: every kernel in FP64.  MG_PREC_FP32_IR: V-cycle
+ *                 interior (smoothers, transfers, defects) in FP32 inside FP64
+ *                 iterative refinement; residual, update and coarsest solve FP64.
+ *  nu_pre/nu_post red-black sweeps before/after the coarse correction (>= 1).
+ *  solve_momentum 0: W frozen at the caller's values; 1: coupled solve.
+ *  flags          bit MG_FLAG_CONFORMAL_MATTER: the matter arrays are the
+ *                 conformally rescaled free data rho_bar = psi^8 rho (taken as
+ *                 rho5 + rho1) and S_bar = psi^6 S; H_h then carries
+ *                 2 pi rho_bar psi^-3 and M_h the source 8 pi S_bar (the
+ *                 textbook CTT rescaling that keeps dH_h/dpsi negative).
+ *                 Other bits must be 0.
+ *  length, origin box side L and corner of the box (cell centres at
+ *                 origin + (i + 1/2) L/n).
+ *  K              constant trace of the extrinsic curvature.
+ *  puncture_mass  0: psi0 = 1; > 0: psi0 = 1 + M / (2 |x - puncture_pos|).
+ */
+typedef struct mg_params {
+    int32_t n, levels, bc, precision, nu_pre, nu_post, solve_momentum, flags;
+    double length;
+    double origin[3];
+    double K;
+    double puncture_mass;
+    double puncture_pos[3];
+} mg_params;
+
+/* Per-solve report.  history (host, caller-owned, may be NULL) receives
+ * 4 doubles per recorded iteration: rms H, rms |M|, max |H|, max |M|. */
+typedef struct mg_report {
+    int32_t outer_iters, vcycles_psi, vcycles_W, status;
+    double h_rms, m_rms, h_max, m_max;
+    double seconds;
+    double *history;
+    int32_t history_cap, history_len;
+} mg_report;
+
+typedef struct mg_ctx mg_ctx;
+
+/* Bytes of device workspace mg_setup needs for these parameters.  Host only. */
+mg_status mg_workspace_size(const mg_params *p, size_t *bytes);
+
+/*
+ * Create a context.  d_workspace: caller-owned device buffer of at least
+ * mg_workspace_size bytes, 256-byte aligned.  d_rho5, d_rho1: n^3 FP64 each;
+ * d_S: 3 n^3 FP64 (may be NULL when solve_momentum is 0 and no momentum
+ * norm is wanted); d_f: n^3 FP64 forcing added to H_h, or NULL.  The coarse
+ * operator of the momentum equation is factorised here (enqueued on stream).
+ */
+mg_status mg_setup(const mg_params *p, void *d_workspace, size_t bytes, void *stream,
+                   const double *d_rho5, const double *d_rho1, const double *d_S,
+                   const double *d_f, mg_ctx **out);
+
+/*
+ * One outer multigrid step at the current state (d_u: n^3, d_W: 3 n^3, FP64,
+ * updated in place).  eq = MG_EQ_W: r = -M_h(u, W), one W V-cycle, W += dW -
+ * mean(dW).  eq = MG_EQ_PSI: r = -H_h(u, W), c = dH_h/dpsi, one psi V-cycle,
+ * u += d.  eq = MG_EQ_BOTH: the W step then the psi step (one Newton outer
+ * iteration).  Enqueued only (does not synchronise).
+ */
+mg_status mg_vcycle(mg_ctx *ctx, int32_t eq, double *d_u, double *d_W);
+
+/*
+ * Newton-multigrid solve from the initial guess in (d_u, d_W) until
+ * rms(H_h) <= tol and (if solve_momentum) rms(|M_h|) <= tol, or max_outer
+ * outer updates.  Returns MG_OK, MG_ERR_NOT_CONVERGED or MG_ERR_DIVERGED;
+ * rep (may be NULL) is filled in every case, and (u, W) hold the last finite
+ * iterate.  Synchronises the stream once per outer iteration.
+ */
+mg_status mg_solve_constraints(mg_ctx *ctx, double *d_u, double *d_W, double tol,
+                               int32_t max_outer, mg_report *rep);
+
+/* Constraint norms at (d_u, d_W): out[4] (host) = rms H_h, rms |M_h|, max |H_h|,
+ * max |M_h| (the momentum entries are 0 when d_S was NULL).  Synchronises. */
+mg_status mg_residual_norm(mg_ctx *ctx, const double *d_u, const double *d_W, double out[4]);
+
+/* The residual fields themselves: d_H (n^3), d_M (3 n^3), d_c (n^3, dH_h/dpsi),
+ * FP64; any may be NULL.  Enqueued only. */
+mg_status mg_residual_fields(mg_ctx *ctx, const double *d_u, const double *d_W, double *d_H,
+                             double *d_M, double *d_c);
+
+void mg_destroy(mg_ctx *ctx);
+const char *mg_status_str(mg_status s);
+
+/*
+ * Matter sources of a scalar field given as Fourier modes (Summary: rho and
+ * S_i as projections of the stress-energy; Key features: analytic matter data).
+ * h_phi_modes, h_pi_modes: host tables of 5 doubles per mode (kx, ky, kz,
+ * amplitude, phase); field = sum amp cos(2 pi k.x / L + phase); up to 64 modes
+ * each.  V(phi) = mass^2 phi^2 / 2.  Writes d_rho5 = Pi^2/2 + V, d_rho1 =
+ * |d phi|^2/2, d_S = -Pi d phi (3 n^3), all FP64.  If h_mean_rho is not NULL
+ * the grid mean of rho5 + rho1 is returned there (synchronises); this needs a
+ * caller-owned device scratch d_scratch of at least MG_SOURCES_SCRATCH_BYTES
+ * (otherwise d_scratch may be NULL).  Uses p->n, p->length and p->origin only.
+ */
+#define MG_SOURCES_SCRATCH_BYTES 32768
+mg_status mg_scalar_field_sources(const mg_params *p, int32_t n_phi, const double *h_phi_modes,
+                                  int32_t n_pi, const double *h_pi_modes, double mass,
+                                  double *d_rho5, double *d_rho1, double *d_S,
+                                  void *d_scratch, size_t scratch_bytes, double *h_mean_rho,
+                                  void *stream);
+
+/*
+ * Scalar shell around the puncture: phi = amp exp(-(r - r0)^2 / width2) Y_11
+ * with the real dipole harmonic Y_11 = sqrt(3/(4 pi)) x/r about puncture_pos,
+ * Pi = 0.  Writes d_rho5 = mass^2 phi^2/2, d_rho1 = |d phi|^2/2, d_S = 0.
+ */
+mg_status mg_shell_field_sources(const mg_params *p, double amp, double r0, double width2,
+                                 double mass, double *d_rho5, double *d_rho1, double *d_S,
+                                 void *stream);
+
+/*
+ * Fourth-order (four-point cubic Lagrange, weights (-5, 35, 105, -7)/128 and
+ * mirror) interpolation of an FP64 field from the coarse grid described by
+ * *pc (n = coarse cells) to the grid with 2n cells per axis: d_fine = Q d_coarse.
+ * Used to start a fine solve from a coarse one.
+ */
+mg_status mg_interp_cubic(const mg_params *pc, const double *d_coarse, double *d_fine,
+                          void *stream);
+
+/*
+ * Single-kernel entry points on one level of a context, for diagnostics and
+ * kernel-level parity checks.  Arrays are in the context's V-cycle type
+ * (double for MG_PREC_FP64, float for MG_PREC_FP32_IR), on level `level`
+ * (n_l = n >> level cells per axis).
+ *  MG_OP_PASS_PSI   out = colour pass (colour = arg) of (L_h + c) d = r, in = d
+ *  MG_OP_PASS_W     out = colour pass of Delta_L,h d = r (3 components)
+ *  MG_OP_DEFECT_RESTRICT_PSI  out (coarse) = average of 8 children of r - (L_h + c) in
+ *  MG_OP_DEFECT_RESTRICT_W    the same for Delta_L,h (3 components)
+ *  MG_OP_PROLONG_ADD out (level l) += trilinear interpolation of in (level l+1),
+ *                   arg = number of components
+ *  MG_OP_COARSE_PSI out = (L_h + c)^-1 r on the coarsest level (r = in)
+ *  MG_OP_COARSE_W   out = mean-free Delta_L,h^-1 (r - mean r) on the coarsest level
+ * Unused pointers may be NULL.  Enqueued only.
+ */
+enum {
+    MG_OP_PASS_PSI = 1,
+    MG_OP_PASS_W = 2,
+    MG_OP_DEFECT_RESTRICT_PSI = 3,
+    MG_OP_DEFECT_RESTRICT_W = 4,
+    MG_OP_PROLONG_ADD = 5,
+    MG_OP_COARSE_PSI = 6,
+    MG_OP_COARSE_W = 7
+};
+mg_status mg_kernel_op(mg_ctx *ctx, int32_t op, int32_t level, int32_t arg, const void *d_in,
+                       void *d_out, const void *d_r, const void *d_c);
+
+/*
+ * Kernel timing probe (measurement support).  mg_probe(ctx, kernel, level)
+ * starts recording a HIP event pair around every later launch of one kernel
+ * family on one level (kernel = MG_PROBE_*, level = multigrid level, or -1
+ * for all levels); kernel = MG_PROBE_NONE stops recording.  Up to 4096
+ * launches are recorded; later ones are not.  mg_probe_result synchronises
+ * the stream and returns the number of recorded launches and the summed
+ * event-to-event time in milliseconds, then clears the record.  Events are
+ * created on the first mg_probe call and released by mg_destroy.
+ */
+enum {
+    MG_PROBE_NONE = 0,
+    MG_PROBE_PASS_PSI = 1,
+    MG_PROBE_PASS_W = 2,
+    MG_PROBE_RESIDUAL = 3,
+    MG_PROBE_DEFECT_RESTRICT_PSI = 4,
+    MG_PROBE_DEFECT_RESTRICT_W = 5,
+    MG_PROBE_PROLONG = 6,
+    MG_PROBE_COARSE = 7,
+    MG_PROBE_UPDATE = 8
+};
+mg_status mg_probe(mg_ctx *ctx, int32_t kernel, int32_t level);
+mg_status mg_probe_result(mg_ctx *ctx, int32_t *launches, double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GRTMG_H */

@@ -30,6 +30,7 @@ SRC_PATH = os.path.join(_HERE, "mg_oracle.c")
 
 BC_PERIODIC = 0
 BC_ROBIN = 1
+FLAG_CONFORMAL_MATTER = 1
 
 
 def build(verbose: bool = False) -> str:
@@ -46,7 +47,7 @@ def build(verbose: bool = False) -> str:
 class OrcParams(C.Structure):
     _fields_ = [("n", C.c_int32), ("levels", C.c_int32), ("bc", C.c_int32),
                 ("nu_pre", C.c_int32), ("nu_post", C.c_int32),
-                ("solve_momentum", C.c_int32), ("pad0", C.c_int32), ("pad1", C.c_int32),
+                ("solve_momentum", C.c_int32), ("flags", C.c_int32), ("pad1", C.c_int32),
                 ("length", C.c_double), ("origin", C.c_double * 3), ("K", C.c_double),
                 ("puncture_mass", C.c_double), ("puncture_pos", C.c_double * 3)]
 
@@ -104,8 +105,9 @@ def _ptr(a):
 
 def params(n, levels=1, bc=BC_PERIODIC, length=1.0, origin=(0.0, 0.0, 0.0), K=0.0,
            nu_pre=2, nu_post=2, solve_momentum=False, puncture_mass=0.0,
-           puncture_pos=(0.0, 0.0, 0.0)) -> OrcParams:
+           puncture_pos=(0.0, 0.0, 0.0), conformal_matter=False) -> OrcParams:
     p = OrcParams()
+    p.flags = FLAG_CONFORMAL_MATTER if conformal_matter else 0
     p.n, p.levels, p.bc = n, levels, bc
     p.nu_pre, p.nu_post = nu_pre, nu_post
     p.solve_momentum = 1 if solve_momentum else 0
@@ -120,7 +122,7 @@ def params(n, levels=1, bc=BC_PERIODIC, length=1.0, origin=(0.0, 0.0, 0.0), K=0.
 
 def params_from_workload(w, K=0.0) -> OrcParams:
     return params(w.n, w.levels, w.bc, w.length, w.origin, K, w.nu_pre, w.nu_post,
-                  w.solve_momentum, w.puncture_mass, w.puncture_pos)
+                  w.solve_momentum, w.puncture_mass, w.puncture_pos, w.conformal_matter)
 
 
 def _z(n, comps=1):

@@ -126,19 +126,29 @@ def psi0(g: Grid, puncture_mass):
     return np.ones((g.n,) * 3)
 
 
-def residuals(g: Grid, u, W, rho5, rho1, S, K, puncture_mass=0.0, f=None):
-    """H_h, mean-free M_h (periodic) and c = dH_h/dpsi, as whole arrays."""
+def residuals(g: Grid, u, W, rho5, rho1, S, K, puncture_mass=0.0, f=None,
+              conformal_matter=False):
+    """H_h, mean-free M_h (periodic) and c = dH_h/dpsi, as whole arrays.
+    conformal_matter: sources are rho_bar = psi^8 rho (= rho5 + rho1) and
+    S_bar = psi^6 S, entering as 2 pi rho_bar psi^-3 and 8 pi S_bar."""
     psi = psi0(g, puncture_mass) + u
     a2 = A2(g, W) if W is not None else 0.0
     K2 = K * K
-    H = (lap(g, u) + 2 * np.pi * rho5 * psi ** 5 + 2 * np.pi * rho1 * psi
-         - K2 / 12.0 * psi ** 5 + a2 * psi ** -7 / 8.0)
+    if conformal_matter:
+        rbar = rho5 + rho1
+        matter = 2 * np.pi * rbar * psi ** -3
+        dmatter = -6 * np.pi * rbar * psi ** -4
+    else:
+        matter = 2 * np.pi * rho5 * psi ** 5 + 2 * np.pi * rho1 * psi
+        dmatter = 10 * np.pi * rho5 * psi ** 4 + 2 * np.pi * rho1
+    H = lap(g, u) + matter - K2 / 12.0 * psi ** 5 + a2 * psi ** -7 / 8.0
     if f is not None:
         H = H + f
-    c = 10 * np.pi * rho5 * psi ** 4 + 2 * np.pi * rho1 - 5 * K2 / 12.0 * psi ** 4 - 7.0 / 8.0 * a2 * psi ** -8
+    c = dmatter - 5 * K2 / 12.0 * psi ** 4 - 7.0 / 8.0 * a2 * psi ** -8
     M = None
     if W is not None:
-        src = 8 * np.pi * psi[None] ** 6 * S
+        w6 = 1.0 if conformal_matter else psi[None] ** 6
+        src = 8 * np.pi * w6 * S
         if g.bc == BC_PERIODIC:
             src = src - src.mean(axis=(1, 2, 3), keepdims=True)
         M = deltaL(g, W) - src
@@ -199,3 +209,59 @@ def fft_solve_W(f, h):
     rhs[0, 0, 0] = 0.0
     sol = np.linalg.solve(Mx, rhs)[..., 0]
     return np.stack([np.real(np.fft.ifftn(sol[..., a])) for a in range(3)])
+
+
+# ---- residuals at selected cells (full-size checks without whole-grid arrays) ------
+
+def _at(g: Grid, a, i, j, k):
+    """Boundary-ruled values of a at integer cells (arrays i, j, k, possibly outside)."""
+    n = g.n
+    if g.bc == BC_PERIODIC:
+        return a[i % n, j % n, k % n]
+    ci, cj, ck = np.clip(i, 0, n - 1), np.clip(j, 0, n - 1), np.clip(k, 0, n - 1)
+
+    def rad(x, y, z):
+        return np.sqrt((g.origin[0] + (x + 0.5) * g.h - g.centre[0]) ** 2 +
+                       (g.origin[1] + (y + 0.5) * g.h - g.centre[1]) ** 2 +
+                       (g.origin[2] + (z + 0.5) * g.h - g.centre[2]) ** 2)
+    return a[ci, cj, ck] * rad(ci, cj, ck) / rad(i, j, k)
+
+
+def hamiltonian_at(g: Grid, u, W, rho5, rho1, K, cells, puncture_mass=0.0,
+                   conformal_matter=False):
+    """H_h at the given cells (array of shape (m, 3)); same definition as residuals()."""
+    i, j, k = cells[:, 0], cells[:, 1], cells[:, 2]
+    w2 = {-2: -1.0, -1: 16.0, 0: -30.0, 1: 16.0, 2: -1.0}
+    w1 = {-2: 1.0, -1: -8.0, 1: 8.0, 2: -1.0}
+    lapu = 0.0
+    for ax in range(3):
+        for d, c in w2.items():
+            o = [0, 0, 0]
+            o[ax] = d
+            lapu = lapu + c * _at(g, u, i + o[0], j + o[1], k + o[2])
+    lapu = lapu / (12.0 * g.h ** 2)
+    a2 = 0.0
+    if W is not None:
+        dW = [[0.0] * 3 for _ in range(3)]
+        for a in range(3):
+            for b in range(3):
+                s = 0.0
+                for d, c in w1.items():
+                    o = [0, 0, 0]
+                    o[a] = d
+                    s = s + c * _at(g, W[b], i + o[0], j + o[1], k + o[2])
+                dW[a][b] = s / (12.0 * g.h)
+        div = dW[0][0] + dW[1][1] + dW[2][2]
+        for a in range(3):
+            for b in range(3):
+                Ab = dW[a][b] + dW[b][a] - (2.0 / 3.0 * div if a == b else 0.0)
+                a2 = a2 + Ab * Ab
+    x = [g.origin[ax] + (cells[:, ax] + 0.5) * g.h - g.centre[ax] for ax in range(3)]
+    r = np.sqrt(x[0] ** 2 + x[1] ** 2 + x[2] ** 2)
+    psi = (1.0 + puncture_mass / (2.0 * r) if puncture_mass > 0.0 else 1.0) + u[i, j, k]
+    r5, r1 = rho5[i, j, k], rho1[i, j, k]
+    if conformal_matter:
+        matter = 2 * np.pi * (r5 + r1) * psi ** -3
+    else:
+        matter = 2 * np.pi * r5 * psi ** 5 + 2 * np.pi * r1 * psi
+    return lapu + matter - K * K / 12.0 * psi ** 5 + a2 * psi ** -7 / 8.0

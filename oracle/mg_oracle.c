@@ -32,6 +32,13 @@
  * The analytic Laplacian of psi0 = 1 + M/(2r) vanishes away from the puncture
  * and is not added.
  *
+ * Conformally rescaled matter (flags bit 0; the textbook CTT choice of free
+ * data rho_bar = psi^8 rho, S_bar_a = psi^6 S_a, which keeps dH/dpsi negative):
+ * with rho_bar = rho5 + rho1,
+ *   H_h = L_h u + 2 pi rho_bar psi^-3 - (K^2/12) psi^5 + A2 psi^-7 / 8 + f
+ *   c   = -6 pi rho_bar psi^-4 - (5 K^2/12) psi^4 - (7/8) A2 psi^-8
+ *   M_h = Delta_L,h W - (8 pi S - mean(8 pi S))
+ *
  * Boundary conditions (Key features lists periodic among them; the 1/r Robin
  * rule serves the isolated black hole): periodic wrap, or a ghost value
  * a(g) = a(b) |x_b| / |x_g| with b the grid cell nearest to g (coordinates
@@ -60,8 +67,11 @@
 #define OBC_ROBIN 1
 #define OMAXLEV 16
 
+/* flags bit 0: conformally rescaled matter (see orc_residuals) */
+#define OFLAG_CONFORMAL_MATTER 1
+
 typedef struct {
-    int32_t n, levels, bc, nu_pre, nu_post, solve_momentum, pad0, pad1;
+    int32_t n, levels, bc, nu_pre, nu_post, solve_momentum, flags, pad1;
     double length, origin[3], K, puncture_mass, puncture_pos[3];
 } orc_params;
 
@@ -287,16 +297,23 @@ void orc_residuals(const orc_params *p, const double *u, const double *W, const 
                     double psi = psi0_at(p, &g, i, j, k) + u[q];
                     double A2 = A2_at(&g, W, i, j, k);
                     double psi4 = pow(psi, 4), psi5 = pow(psi, 5);
+                    double matter, dmatter; /* matter term of H and its psi-derivative */
+                    if (p->flags & OFLAG_CONFORMAL_MATTER) {
+                        double rbar = rho5[q] + rho1[q];
+                        matter = 2.0 * pi * rbar * pow(psi, -3);
+                        dmatter = -6.0 * pi * rbar * pow(psi, -4);
+                    } else {
+                        matter = 2.0 * pi * rho5[q] * psi5 + 2.0 * pi * rho1[q] * psi;
+                        dmatter = 10.0 * pi * rho5[q] * psi4 + 2.0 * pi * rho1[q];
+                    }
                     if (H) {
-                        double v = lap(&g, u, i, j, k) + 2.0 * pi * rho5[q] * psi5 +
-                                   2.0 * pi * rho1[q] * psi - (K2 / 12.0) * psi5 +
+                        double v = lap(&g, u, i, j, k) + matter - (K2 / 12.0) * psi5 +
                                    0.125 * A2 * pow(psi, -7);
                         if (f) v += f[q];
                         H[q] = v;
                     }
                     if (c)
-                        c[q] = 10.0 * pi * rho5[q] * psi4 + 2.0 * pi * rho1[q] -
-                               (5.0 * K2 / 12.0) * psi4 - 0.875 * A2 * pow(psi, -8);
+                        c[q] = dmatter - (5.0 * K2 / 12.0) * psi4 - 0.875 * A2 * pow(psi, -8);
                 }
     }
     if (M) {
@@ -308,8 +325,9 @@ void orc_residuals(const orc_params *p, const double *u, const double *W, const 
                 for (int k = 0; k < n; k++) {
                     long q = idx3(n, i, j, k);
                     double psi = psi0_at(p, &g, i, j, k) + u[q];
+                    double w6 = (p->flags & OFLAG_CONFORMAL_MATTER) ? 1.0 : pow(psi, 6);
                     for (int a = 0; a < 3; a++)
-                        src[a * m + q] = S ? 8.0 * pi * pow(psi, 6) * S[a * m + q] : 0.0;
+                        src[a * m + q] = S ? 8.0 * pi * w6 * S[a * m + q] : 0.0;
                 }
         if (p->bc == OBC_PERIODIC) {
             for (int a = 0; a < 3; a++) {

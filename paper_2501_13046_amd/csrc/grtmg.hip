@@ -1,0 +1,839 @@
+// grtmg.hip -- host runtime and C ABI of the constraint multigrid.
+//
+// The runtime owns nothing on the device: mg_setup carves the caller's
+// workspace into per-level buffers, the reduction partials, a few device
+// scalars and the coarsest-level matrices.  Every kernel is enqueued on the
+// caller's stream; the only host/device crossing per outer iteration is the
+// copy of four norms (plus status flags) to pinned host memory.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+
+#include "grtmg.h"
+#include "mg_kernels.hpp"
+
+using namespace grtmg;
+
+namespace {
+
+constexpr int kMaxLevels = 16;
+constexpr int kMaxCoarsePsi = 1728; // coarsest psi unknowns (12^3)
+constexpr int kMaxCoarseW = 1536;   // coarsest W unknowns (3 * 8^3)
+constexpr int kSrcBlocks = 2048;    // grid of the source kernel (partials in scratch)
+
+// device scalar slots
+enum { S_NORM = 0, S_MEANS = 4, S_MEAND = 8, S_FLAG_PSI = 12, S_FLAG_W = 13, S_COUNT = 16 };
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct Carver {
+    char *base;
+    size_t off = 0;
+    void *take(size_t bytes)
+    {
+        off = align_up(off, 256);
+        void *p = base ? base + off : nullptr;
+        off += bytes;
+        return p;
+    }
+};
+
+unsigned nblk(int64_t count) { return (unsigned)((count + kBlock - 1) / kBlock); }
+
+constexpr int kProbeMax = 4096;
+
+} // namespace
+
+struct mg_ctx {
+    mg_params p;
+    hipStream_t s;
+    int L;
+    bool f32;
+    bool momentum;
+    size_t esz;
+    int n[kMaxLevels];
+    int64_t cells[kMaxLevels];
+    Geo geo[kMaxLevels];
+    void *pd0[kMaxLevels], *pd1[kMaxLevels], *pr[kMaxLevels], *pc[kMaxLevels];
+    void *wd0[kMaxLevels], *wd1[kMaxLevels], *wr[kMaxLevels];
+    double *part;
+    double *scal;
+    int m_psi, m_W;
+    double *A_psi, *aug_psi, *inv_psi;
+    double *A_W, *aug_W, *inv_W;
+    double *hpin;
+    const double *rho5, *rho1, *S, *f;
+    double K2;
+    int vc_psi, vc_W;
+    // timing probe
+    int probe_kernel, probe_level, probe_count;
+    hipEvent_t *probe_ev; // 2 * kProbeMax events, created on first use
+};
+
+namespace {
+
+mg_status validate(const mg_params *p)
+{
+    if (!p) return MG_ERR_INVALID;
+    if (p->levels < 1 || p->levels > kMaxLevels) return MG_ERR_INVALID;
+    if (p->n < 3 || p->n > 4096) return MG_ERR_INVALID;
+    if (p->bc != MG_BC_PERIODIC && p->bc != MG_BC_ROBIN) return MG_ERR_INVALID;
+    if (p->precision != MG_PREC_FP64 && p->precision != MG_PREC_FP32_IR) return MG_ERR_INVALID;
+    if (p->nu_pre < 0 || p->nu_post < 0 || p->nu_pre + p->nu_post < 1 || p->nu_pre > 16 ||
+        p->nu_post > 16)
+        return MG_ERR_INVALID;
+    if (p->solve_momentum != 0 && p->solve_momentum != 1) return MG_ERR_INVALID;
+    if (p->solve_momentum && p->bc != MG_BC_PERIODIC) return MG_ERR_INVALID;
+    if ((p->flags & ~MG_FLAG_CONFORMAL_MATTER) != 0) return MG_ERR_INVALID;
+    if (!(p->length > 0.0) || !std::isfinite(p->length)) return MG_ERR_INVALID;
+    if (!std::isfinite(p->K) || !(p->puncture_mass >= 0.0) || !std::isfinite(p->puncture_mass))
+        return MG_ERR_INVALID;
+    for (int a = 0; a < 3; a++)
+        if (!std::isfinite(p->origin[a]) || !std::isfinite(p->puncture_pos[a])) return MG_ERR_INVALID;
+    int n = p->n;
+    for (int l = 0; l + 1 < p->levels; l++) {
+        if (n % 2 != 0 || n < 6) return MG_ERR_INVALID;
+        n /= 2;
+    }
+    if (n < 3) return MG_ERR_INVALID;
+    const int64_t mc = (int64_t)n * n * n;
+    if (mc > kMaxCoarsePsi) return MG_ERR_INVALID;
+    if (p->solve_momentum && 3 * mc > kMaxCoarseW) return MG_ERR_INVALID;
+    return MG_OK;
+}
+
+// Lay out (or measure, when base is null) every device buffer of a context.
+void carve(mg_ctx *c, Carver &cv)
+{
+    const mg_params &p = c->p;
+    int n = p.n;
+    for (int l = 0; l < c->L; l++) {
+        const int64_t m = (int64_t)n * n * n;
+        c->n[l] = n;
+        c->cells[l] = m;
+        c->pd0[l] = cv.take(m * c->esz);
+        c->pd1[l] = cv.take(m * c->esz);
+        c->pr[l] = cv.take(m * c->esz);
+        c->pc[l] = cv.take(m * c->esz);
+        if (c->momentum) {
+            c->wd0[l] = cv.take(3 * m * c->esz);
+            c->wd1[l] = cv.take(3 * m * c->esz);
+            c->wr[l] = cv.take(3 * m * c->esz);
+        } else {
+            c->wd0[l] = c->wd1[l] = c->wr[l] = nullptr;
+        }
+        n /= 2;
+    }
+    const int64_t nb = nblk(c->cells[0]);
+    c->part = (double *)cv.take((size_t)nb * 4 * sizeof(double));
+    c->scal = (double *)cv.take(S_COUNT * sizeof(double));
+    c->m_psi = (int)c->cells[c->L - 1];
+    const size_t mp = (size_t)c->m_psi;
+    c->A_psi = (double *)cv.take(mp * mp * sizeof(double));
+    c->aug_psi = (double *)cv.take(2 * mp * mp * sizeof(double));
+    c->inv_psi = (double *)cv.take(mp * mp * sizeof(double));
+    if (c->momentum) {
+        c->m_W = 3 * c->m_psi;
+        const size_t mw = (size_t)c->m_W;
+        c->A_W = (double *)cv.take(mw * mw * sizeof(double));
+        c->aug_W = (double *)cv.take(2 * mw * mw * sizeof(double));
+        c->inv_W = (double *)cv.take(mw * mw * sizeof(double));
+    } else {
+        c->m_W = 0;
+        c->A_W = c->aug_W = c->inv_W = nullptr;
+    }
+}
+
+void init_geo(mg_ctx *c)
+{
+    for (int l = 0; l < c->L; l++)
+        c->geo[l] = make_geo(c->n[l], c->p.bc, c->p.length, c->p.origin, c->p.puncture_pos);
+}
+
+// Records an event pair around the launches in its scope when (kernel, level)
+// matches the probe set by mg_probe.
+struct Probe {
+    mg_ctx *c;
+    bool on;
+    Probe(mg_ctx *ctx, int kernel, int level) : c(ctx)
+    {
+        on = c->probe_ev && c->probe_kernel == kernel &&
+             (c->probe_level < 0 || c->probe_level == level) && c->probe_count < kProbeMax;
+        if (on) (void)hipEventRecord(c->probe_ev[2 * c->probe_count], c->s);
+    }
+    ~Probe()
+    {
+        if (on) {
+            (void)hipEventRecord(c->probe_ev[2 * c->probe_count + 1], c->s);
+            c->probe_count++;
+        }
+    }
+};
+
+template <typename T>
+void fill(hipStream_t s, T *a, int64_t count, T v)
+{
+    if (count > 0) hipLaunchKernelGGL(k_fill<T>, dim3(nblk(count)), dim3(kBlock), 0, s, a, count, v);
+}
+
+// ---- coarsest level -----------------------------------------------------------------
+
+void factor(hipStream_t s, double *A, double *aug, double *inv, int m, double *flag)
+{
+    hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(kGjThreads), 0, s, (const double *)A, aug, inv,
+                       m, flag);
+}
+
+template <typename T>
+void coarse_psi(mg_ctx *c, const T *r, T *x)
+{
+    const int l = c->L - 1;
+    Probe pr(c, MG_PROBE_COARSE, l);
+    const int m = c->m_psi;
+    fill<double>(c->s, c->A_psi, (int64_t)m * m, 0.0);
+    if (c->p.bc == MG_BC_PERIODIC)
+        hipLaunchKernelGGL((k_assemble_psi<kBcPeriodic, T>), dim3(nblk(m)), dim3(kBlock), 0, c->s,
+                           c->geo[l], (const T *)c->pc[l], c->A_psi);
+    else
+        hipLaunchKernelGGL((k_assemble_psi<kBcRobin, T>), dim3(nblk(m)), dim3(kBlock), 0, c->s,
+                           c->geo[l], (const T *)c->pc[l], c->A_psi);
+    factor(c->s, c->A_psi, c->aug_psi, c->inv_psi, m, c->scal + S_FLAG_PSI);
+    hipLaunchKernelGGL(k_coarse_apply<T>, dim3(nblk(m)), dim3(kBlock), m * sizeof(double), c->s,
+                       (const double *)c->inv_psi, m, r, x, 0);
+}
+
+template <typename T>
+void coarse_W(mg_ctx *c, const T *r, T *x)
+{
+    const int m = c->m_W;
+    Probe pr(c, MG_PROBE_COARSE, c->L - 1);
+    hipLaunchKernelGGL(k_coarse_apply<T>, dim3(nblk(m)), dim3(kBlock), m * sizeof(double), c->s,
+                       (const double *)c->inv_W, m, r, x, 3);
+}
+
+// ---- psi V-cycle ----------------------------------------------------------------------
+
+template <typename T>
+void pass_psi(mg_ctx *c, int l, const T *in, T *out, int colour)
+{
+    Probe pr(c, MG_PROBE_PASS_PSI, l);
+    const Geo &g = c->geo[l];
+    const unsigned nb = nblk(c->cells[l]);
+    if (c->p.bc == MG_BC_PERIODIC)
+        hipLaunchKernelGGL((k_pass_psi<kBcPeriodic, T>), dim3(nb), dim3(kBlock), 0, c->s, g, in, out,
+                           (const T *)c->pr[l], (const T *)c->pc[l], colour);
+    else
+        hipLaunchKernelGGL((k_pass_psi<kBcRobin, T>), dim3(nb), dim3(kBlock), 0, c->s, g, in, out,
+                           (const T *)c->pr[l], (const T *)c->pc[l], colour);
+}
+
+template <typename T>
+void smooth_psi(mg_ctx *c, int l, int sweeps)
+{
+    for (int s = 0; s < sweeps; s++) {
+        pass_psi<T>(c, l, (const T *)c->pd0[l], (T *)c->pd1[l], 0);
+        pass_psi<T>(c, l, (const T *)c->pd1[l], (T *)c->pd0[l], 1);
+    }
+}
+
+template <typename T>
+void defect_restrict_psi(mg_ctx *c, int l, const T *d, const T *r, const T *cf, T *rc, T *cc)
+{
+    Probe pr(c, MG_PROBE_DEFECT_RESTRICT_PSI, l);
+    const Geo &g = c->geo[l];
+    const unsigned nb = nblk(c->cells[l + 1]);
+    if (c->p.bc == MG_BC_PERIODIC)
+        hipLaunchKernelGGL((k_defect_restrict_psi<kBcPeriodic, T>), dim3(nb), dim3(kBlock), 0, c->s, g,
+                           d, r, cf, rc, cc);
+    else
+        hipLaunchKernelGGL((k_defect_restrict_psi<kBcRobin, T>), dim3(nb), dim3(kBlock), 0, c->s, g, d,
+                           r, cf, rc, cc);
+}
+
+template <typename T>
+void prolong_add(mg_ctx *c, int lc, const T *coarse, T *fine, int ncomp)
+{
+    Probe pr(c, MG_PROBE_PROLONG, lc - 1);
+    const Geo &gc = c->geo[lc];
+    const unsigned nb = nblk(c->cells[lc - 1]);
+    if (c->p.bc == MG_BC_PERIODIC)
+        hipLaunchKernelGGL((k_prolong_add<kBcPeriodic, T>), dim3(nb), dim3(kBlock), 0, c->s, gc, coarse,
+                           fine, ncomp);
+    else
+        hipLaunchKernelGGL((k_prolong_add<kBcRobin, T>), dim3(nb), dim3(kBlock), 0, c->s, gc, coarse,
+                           fine, ncomp);
+}
+
+template <typename T>
+void vcycle_psi(mg_ctx *c, int l)
+{
+    if (l == c->L - 1) {
+        coarse_psi<T>(c, (const T *)c->pr[l], (T *)c->pd0[l]);
+        return;
+    }
+    fill<T>(c->s, (T *)c->pd0[l], c->cells[l], T(0));
+    smooth_psi<T>(c, l, c->p.nu_pre);
+    defect_restrict_psi<T>(c, l, (const T *)c->pd0[l], (const T *)c->pr[l], (const T *)c->pc[l],
+                           (T *)c->pr[l + 1], (T *)c->pc[l + 1]);
+    vcycle_psi<T>(c, l + 1);
+    prolong_add<T>(c, l + 1, (const T *)c->pd0[l + 1], (T *)c->pd0[l], 1);
+    smooth_psi<T>(c, l, c->p.nu_post);
+}
+
+// ---- W V-cycle ------------------------------------------------------------------------
+
+template <typename T>
+void smooth_W(mg_ctx *c, int l, int sweeps)
+{
+    const unsigned nb = nblk(c->cells[l]);
+    for (int s = 0; s < sweeps; s++) {
+        {
+            Probe pr(c, MG_PROBE_PASS_W, l);
+            hipLaunchKernelGGL(k_pass_W<T>, dim3(nb), dim3(kBlock), 0, c->s, c->geo[l],
+                               (const T *)c->wd0[l], (T *)c->wd1[l], (const T *)c->wr[l], 0);
+        }
+        {
+            Probe pr(c, MG_PROBE_PASS_W, l);
+            hipLaunchKernelGGL(k_pass_W<T>, dim3(nb), dim3(kBlock), 0, c->s, c->geo[l],
+                               (const T *)c->wd1[l], (T *)c->wd0[l], (const T *)c->wr[l], 1);
+        }
+    }
+}
+
+template <typename T>
+void vcycle_W(mg_ctx *c, int l)
+{
+    if (l == c->L - 1) {
+        coarse_W<T>(c, (const T *)c->wr[l], (T *)c->wd0[l]);
+        return;
+    }
+    fill<T>(c->s, (T *)c->wd0[l], 3 * c->cells[l], T(0));
+    smooth_W<T>(c, l, c->p.nu_pre);
+    {
+        Probe pr(c, MG_PROBE_DEFECT_RESTRICT_W, l);
+        hipLaunchKernelGGL(k_defect_restrict_W<T>, dim3(nblk(c->cells[l + 1])), dim3(kBlock), 0, c->s,
+                           c->geo[l], (const T *)c->wd0[l], (const T *)c->wr[l], (T *)c->wr[l + 1]);
+    }
+    vcycle_W<T>(c, l + 1);
+    prolong_add<T>(c, l + 1, (const T *)c->wd0[l + 1], (T *)c->wd0[l], 3);
+    smooth_W<T>(c, l, c->p.nu_post);
+}
+
+// ---- residuals and outer steps ----------------------------------------------------------
+
+bool source_mean_needed(const mg_ctx *c) { return c->S && c->p.bc == MG_BC_PERIODIC; }
+
+void source_mean(mg_ctx *c, const double *u)
+{
+    if (!source_mean_needed(c)) return;
+    const Geo &g = c->geo[0];
+    const int64_t nb = nblk(c->cells[0]);
+    if (c->p.bc == MG_BC_PERIODIC)
+        hipLaunchKernelGGL(k_source_sum<kBcPeriodic>, dim3(nb), dim3(kBlock), 0, c->s, g, u, c->S,
+                           c->p.puncture_mass, (c->p.flags & MG_FLAG_CONFORMAL_MATTER) ? 1 : 0,
+                           c->part);
+    hipLaunchKernelGGL(k_reduce_final<3>, dim3(1), dim3(kBlock), 0, c->s, (const double *)c->part, nb,
+                       0u, 1.0 / (double)c->cells[0], c->scal + S_MEANS);
+}
+
+template <typename T>
+void residual(mg_ctx *c, const double *u, const double *W, bool want_M, double *H, double *M,
+              double *cc, void *r, void *rc, void *rW, bool norms)
+{
+    ResArgs a;
+    a.u = u;
+    a.W = W;
+    a.rho5 = c->rho5;
+    a.rho1 = c->rho1;
+    a.S = c->S;
+    a.f = c->f;
+    a.meanS = c->scal + S_MEANS;
+    a.K2 = c->K2;
+    a.pmass = c->p.puncture_mass;
+    a.H = H;
+    a.M = M;
+    a.c = cc;
+    a.r = r;
+    a.rc = rc;
+    a.rW = rW;
+    a.partials = norms ? c->part : nullptr;
+    a.want_M = want_M ? 1 : 0;
+    a.conformal = (c->p.flags & MG_FLAG_CONFORMAL_MATTER) ? 1 : 0;
+    const int64_t nb = nblk(c->cells[0]);
+    {
+        Probe pr(c, MG_PROBE_RESIDUAL, 0);
+        if (c->p.bc == MG_BC_PERIODIC)
+            hipLaunchKernelGGL((k_residual<kBcPeriodic, T>), dim3(nb), dim3(kBlock), 0, c->s, c->geo[0], a);
+        else
+            hipLaunchKernelGGL((k_residual<kBcRobin, T>), dim3(nb), dim3(kBlock), 0, c->s, c->geo[0], a);
+    }
+    if (norms)
+        hipLaunchKernelGGL(k_reduce_final<4>, dim3(1), dim3(kBlock), 0, c->s, (const double *)c->part, nb,
+                           0xAu, 0.0, c->scal + S_NORM);
+}
+
+template <typename T>
+void step_W(mg_ctx *c, const double *u, double *W, bool residual_done)
+{
+    if (!residual_done) {
+        source_mean(c, u);
+        residual<T>(c, u, W, true, nullptr, nullptr, nullptr, nullptr, nullptr, c->wr[0], false);
+    }
+    vcycle_W<T>(c, 0);
+    const int64_t m = c->cells[0];
+    const int64_t nb = nblk(m);
+    hipLaunchKernelGGL(k_sum3<T>, dim3(nb), dim3(kBlock), 0, c->s, (const T *)c->wd0[0], m, c->part);
+    hipLaunchKernelGGL(k_reduce_final<3>, dim3(1), dim3(kBlock), 0, c->s, (const double *)c->part, nb, 0u,
+                       1.0 / (double)m, c->scal + S_MEAND);
+    {
+        Probe pr(c, MG_PROBE_UPDATE, 0);
+        hipLaunchKernelGGL(k_update_W<T>, dim3(nb), dim3(kBlock), 0, c->s, W, (const T *)c->wd0[0],
+                           (const double *)(c->scal + S_MEAND), m);
+    }
+    c->vc_W++;
+}
+
+template <typename T>
+void step_psi(mg_ctx *c, double *u, const double *W, bool residual_done)
+{
+    if (!residual_done)
+        residual<T>(c, u, W, false, nullptr, nullptr, nullptr, c->pr[0], c->pc[0], nullptr, false);
+    vcycle_psi<T>(c, 0);
+    const int64_t m = c->cells[0];
+    {
+        Probe pr(c, MG_PROBE_UPDATE, 0);
+        hipLaunchKernelGGL(k_update_u<T>, dim3(nblk(m)), dim3(kBlock), 0, c->s, u, (const T *)c->pd0[0], m);
+    }
+    c->vc_psi++;
+}
+
+mg_status hip_status()
+{
+    return hipPeekAtLastError() == hipSuccess ? MG_OK : MG_ERR_HIP;
+}
+
+// Copy the device scalars to pinned memory and wait; converts sums to RMS.
+mg_status fetch_norms(mg_ctx *c, double out[4], double *flag_psi)
+{
+    if (hipMemcpyAsync(c->hpin, c->scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, c->s) !=
+        hipSuccess)
+        return MG_ERR_HIP;
+    if (hipStreamSynchronize(c->s) != hipSuccess) return MG_ERR_HIP;
+    const double inv = 1.0 / (double)c->cells[0];
+    out[0] = std::sqrt(c->hpin[S_NORM + 0] * inv);
+    out[1] = std::sqrt(c->hpin[S_NORM + 2] * inv);
+    out[2] = c->hpin[S_NORM + 1];
+    out[3] = c->hpin[S_NORM + 3];
+    if (flag_psi) *flag_psi = c->hpin[S_FLAG_PSI];
+    return MG_OK;
+}
+
+template <typename T>
+mg_status solve(mg_ctx *c, double *u, double *W, double tol, int max_outer, mg_report *rep)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    c->vc_psi = c->vc_W = 0;
+    mg_status st = MG_ERR_NOT_CONVERGED;
+    double nr[4] = {0, 0, 0, 0}, first = -1.0;
+    int it = 0, hist_len = 0;
+    const bool mom = c->momentum;
+    const bool want_M = mom || (c->S != nullptr && W != nullptr);
+    fill<double>(c->s, c->scal + S_FLAG_PSI, 2, 0.0);
+    for (;; it++) {
+        source_mean(c, u);
+        if (mom)
+            residual<T>(c, u, W, true, nullptr, nullptr, nullptr, nullptr, nullptr, c->wr[0], true);
+        else
+            residual<T>(c, u, W, want_M, nullptr, nullptr, nullptr, c->pr[0], c->pc[0], nullptr, true);
+        double flag = 0.0;
+        if (hip_status() != MG_OK) return MG_ERR_HIP;
+        mg_status fs = fetch_norms(c, nr, &flag);
+        if (fs != MG_OK) return fs;
+        if (rep && rep->history && hist_len < rep->history_cap) {
+            std::memcpy(rep->history + 4 * hist_len, nr, sizeof(nr));
+            hist_len++;
+        }
+        const double worst = mom ? std::fmax(nr[0], nr[1]) : nr[0];
+        if (flag != 0.0) {
+            st = MG_ERR_SINGULAR;
+            break;
+        }
+        if (!std::isfinite(nr[0]) || !std::isfinite(nr[1])) {
+            st = MG_ERR_DIVERGED;
+            break;
+        }
+        if (first < 0.0) first = worst;
+        if (nr[0] <= tol && (!mom || nr[1] <= tol)) {
+            st = MG_OK;
+            break;
+        }
+        if (worst > 1e6 * std::fmax(first, tol)) {
+            st = MG_ERR_DIVERGED;
+            break;
+        }
+        if (it >= max_outer) {
+            st = MG_ERR_NOT_CONVERGED;
+            break;
+        }
+        if (mom) {
+            step_W<T>(c, u, W, true);
+            step_psi<T>(c, u, W, false);
+        } else {
+            step_psi<T>(c, u, W, true);
+        }
+    }
+    auto t1 = std::chrono::steady_clock::now();
+    if (rep) {
+        rep->outer_iters = it;
+        rep->vcycles_psi = c->vc_psi;
+        rep->vcycles_W = c->vc_W;
+        rep->status = st;
+        rep->h_rms = nr[0];
+        rep->m_rms = nr[1];
+        rep->h_max = nr[2];
+        rep->m_max = nr[3];
+        rep->seconds = std::chrono::duration<double>(t1 - t0).count();
+        rep->history_len = hist_len;
+    }
+    return st;
+}
+
+template <typename T>
+mg_status kernel_op(mg_ctx *c, int op, int l, int arg, const void *in, void *out, const void *r,
+                    const void *cf)
+{
+    if (l < 0 || l >= c->L) return MG_ERR_INVALID;
+    const bool coarsest = (l == c->L - 1);
+    switch (op) {
+    case MG_OP_PASS_PSI: {
+        if (!in || !out || !r || !cf || (arg != 0 && arg != 1) || coarsest) return MG_ERR_INVALID;
+        const Geo &g = c->geo[l];
+        const unsigned nb = nblk(c->cells[l]);
+        if (c->p.bc == MG_BC_PERIODIC)
+            hipLaunchKernelGGL((k_pass_psi<kBcPeriodic, T>), dim3(nb), dim3(kBlock), 0, c->s, g, (const T *)in,
+                               (T *)out, (const T *)r, (const T *)cf, arg);
+        else
+            hipLaunchKernelGGL((k_pass_psi<kBcRobin, T>), dim3(nb), dim3(kBlock), 0, c->s, g, (const T *)in,
+                               (T *)out, (const T *)r, (const T *)cf, arg);
+        break;
+    }
+    case MG_OP_PASS_W:
+        if (!in || !out || !r || (arg != 0 && arg != 1) || c->p.bc != MG_BC_PERIODIC || coarsest)
+            return MG_ERR_INVALID;
+        hipLaunchKernelGGL(k_pass_W<T>, dim3(nblk(c->cells[l])), dim3(kBlock), 0, c->s, c->geo[l],
+                           (const T *)in, (T *)out, (const T *)r, arg);
+        break;
+    case MG_OP_DEFECT_RESTRICT_PSI:
+        if (!in || !out || !r || !cf || coarsest) return MG_ERR_INVALID;
+        defect_restrict_psi<T>(c, l, (const T *)in, (const T *)r, (const T *)cf, (T *)out, nullptr);
+        break;
+    case MG_OP_DEFECT_RESTRICT_W:
+        if (!in || !out || !r || coarsest || c->p.bc != MG_BC_PERIODIC) return MG_ERR_INVALID;
+        hipLaunchKernelGGL(k_defect_restrict_W<T>, dim3(nblk(c->cells[l + 1])), dim3(kBlock), 0, c->s,
+                           c->geo[l], (const T *)in, (const T *)r, (T *)out);
+        break;
+    case MG_OP_PROLONG_ADD:
+        if (!in || !out || coarsest || (arg != 1 && arg != 3)) return MG_ERR_INVALID;
+        prolong_add<T>(c, l + 1, (const T *)in, (T *)out, arg);
+        break;
+    case MG_OP_COARSE_PSI: {
+        if (!in || !out || !cf || !coarsest) return MG_ERR_INVALID;
+        // the coarse coefficient lives in the context: copy the caller's first
+        if (hipMemcpyAsync(c->pc[l], cf, c->cells[l] * sizeof(T), hipMemcpyDeviceToDevice, c->s) !=
+            hipSuccess)
+            return MG_ERR_HIP;
+        coarse_psi<T>(c, (const T *)in, (T *)out);
+        break;
+    }
+    case MG_OP_COARSE_W:
+        if (!in || !out || !coarsest || !c->momentum) return MG_ERR_INVALID;
+        coarse_W<T>(c, (const T *)in, (T *)out);
+        break;
+    default:
+        return MG_ERR_INVALID;
+    }
+    return hip_status();
+}
+
+} // namespace
+
+// ======================================================================================
+// C ABI
+// ======================================================================================
+
+extern "C" {
+
+mg_status mg_workspace_size(const mg_params *p, size_t *bytes)
+{
+    if (!bytes) return MG_ERR_INVALID;
+    mg_status st = validate(p);
+    if (st != MG_OK) return st;
+    mg_ctx tmp;
+    std::memset(&tmp, 0, sizeof(tmp));
+    tmp.p = *p;
+    tmp.L = p->levels;
+    tmp.f32 = p->precision == MG_PREC_FP32_IR;
+    tmp.esz = tmp.f32 ? sizeof(float) : sizeof(double);
+    tmp.momentum = p->solve_momentum != 0;
+    Carver cv{nullptr};
+    carve(&tmp, cv);
+    *bytes = align_up(cv.off, 256);
+    return MG_OK;
+}
+
+mg_status mg_setup(const mg_params *p, void *d_workspace, size_t bytes, void *stream,
+                   const double *d_rho5, const double *d_rho1, const double *d_S, const double *d_f,
+                   mg_ctx **out)
+{
+    if (!out) return MG_ERR_INVALID;
+    *out = nullptr;
+    mg_status st = validate(p);
+    if (st != MG_OK) return st;
+    if (!d_rho5 || !d_rho1) return MG_ERR_INVALID;
+    if (p->solve_momentum && !d_S) return MG_ERR_INVALID;
+    size_t need = 0;
+    mg_workspace_size(p, &need);
+    if (!d_workspace || bytes < need || ((uintptr_t)d_workspace % 256) != 0) return MG_ERR_WORKSPACE;
+    mg_ctx *c = new (std::nothrow) mg_ctx;
+    if (!c) return MG_ERR_INVALID;
+    std::memset(c, 0, sizeof(*c));
+    c->p = *p;
+    c->s = (hipStream_t)stream;
+    c->L = p->levels;
+    c->f32 = p->precision == MG_PREC_FP32_IR;
+    c->esz = c->f32 ? sizeof(float) : sizeof(double);
+    c->momentum = p->solve_momentum != 0;
+    c->rho5 = d_rho5;
+    c->rho1 = d_rho1;
+    c->S = d_S;
+    c->f = d_f;
+    c->K2 = p->K * p->K;
+    Carver cv{(char *)d_workspace};
+    carve(c, cv);
+    init_geo(c);
+    if (hipHostMalloc((void **)&c->hpin, S_COUNT * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return MG_ERR_HIP;
+    }
+    fill<double>(c->s, c->scal, S_COUNT, 0.0);
+    if (c->momentum) {
+        const int m = c->m_W;
+        fill<double>(c->s, c->A_W, (int64_t)m * m, 0.0);
+        hipLaunchKernelGGL(k_assemble_W, dim3(nblk(m)), dim3(kBlock), 0, c->s, c->geo[c->L - 1], c->A_W);
+        factor(c->s, c->A_W, c->aug_W, c->inv_W, m, c->scal + S_FLAG_W);
+        if (hipMemcpyAsync(c->hpin, c->scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, c->s) !=
+                hipSuccess ||
+            hipStreamSynchronize(c->s) != hipSuccess) {
+            (void)hipHostFree(c->hpin);
+            delete c;
+            return MG_ERR_HIP;
+        }
+        if (c->hpin[S_FLAG_W] != 0.0) {
+            (void)hipHostFree(c->hpin);
+            delete c;
+            return MG_ERR_SINGULAR;
+        }
+    }
+    if (hip_status() != MG_OK) {
+        (void)hipHostFree(c->hpin);
+        delete c;
+        return MG_ERR_HIP;
+    }
+    *out = c;
+    return MG_OK;
+}
+
+mg_status mg_vcycle(mg_ctx *c, int32_t eq, double *d_u, double *d_W)
+{
+    if (!c || !d_u || eq < 1 || eq > 3) return MG_ERR_INVALID;
+    if ((eq & MG_EQ_W) && (!c->momentum || !d_W)) return MG_ERR_INVALID;
+    if (c->f32) {
+        if (eq & MG_EQ_W) step_W<float>(c, d_u, d_W, false);
+        if (eq & MG_EQ_PSI) step_psi<float>(c, d_u, d_W, false);
+    } else {
+        if (eq & MG_EQ_W) step_W<double>(c, d_u, d_W, false);
+        if (eq & MG_EQ_PSI) step_psi<double>(c, d_u, d_W, false);
+    }
+    return hip_status();
+}
+
+mg_status mg_solve_constraints(mg_ctx *c, double *d_u, double *d_W, double tol, int32_t max_outer,
+                               mg_report *rep)
+{
+    if (!c || !d_u || !(tol > 0.0) || max_outer < 0) return MG_ERR_INVALID;
+    if (c->momentum && !d_W) return MG_ERR_INVALID;
+    if (rep && rep->history && rep->history_cap < 0) return MG_ERR_INVALID;
+    return c->f32 ? solve<float>(c, d_u, d_W, tol, max_outer, rep)
+                  : solve<double>(c, d_u, d_W, tol, max_outer, rep);
+}
+
+mg_status mg_residual_norm(mg_ctx *c, const double *d_u, const double *d_W, double out[4])
+{
+    if (!c || !d_u || !out) return MG_ERR_INVALID;
+    const bool want_M = c->S != nullptr;
+    source_mean(c, d_u);
+    if (c->f32)
+        residual<float>(c, d_u, d_W, want_M, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, true);
+    else
+        residual<double>(c, d_u, d_W, want_M, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, true);
+    if (hip_status() != MG_OK) return MG_ERR_HIP;
+    return fetch_norms(c, out, nullptr);
+}
+
+mg_status mg_residual_fields(mg_ctx *c, const double *d_u, const double *d_W, double *d_H, double *d_M,
+                             double *d_c)
+{
+    if (!c || !d_u) return MG_ERR_INVALID;
+    const bool want_M = d_M != nullptr;
+    if (want_M && !c->S) return MG_ERR_INVALID;
+    source_mean(c, d_u);
+    residual<double>(c, d_u, d_W, want_M, d_H, d_M, d_c, nullptr, nullptr, nullptr, false);
+    return hip_status();
+}
+
+void mg_destroy(mg_ctx *c)
+{
+    if (!c) return;
+    if (c->hpin) (void)hipHostFree(c->hpin);
+    if (c->probe_ev) {
+        for (int q = 0; q < 2 * kProbeMax; q++) (void)hipEventDestroy(c->probe_ev[q]);
+        delete[] c->probe_ev;
+    }
+    delete c;
+}
+
+mg_status mg_probe(mg_ctx *c, int32_t kernel, int32_t level)
+{
+    if (!c || kernel < MG_PROBE_NONE || kernel > MG_PROBE_UPDATE || level < -1 || level >= c->L)
+        return MG_ERR_INVALID;
+    if (kernel != MG_PROBE_NONE && !c->probe_ev) {
+        c->probe_ev = new (std::nothrow) hipEvent_t[2 * kProbeMax];
+        if (!c->probe_ev) return MG_ERR_INVALID;
+        for (int q = 0; q < 2 * kProbeMax; q++)
+            if (hipEventCreate(&c->probe_ev[q]) != hipSuccess) {
+                for (int r = 0; r < q; r++) (void)hipEventDestroy(c->probe_ev[r]);
+                delete[] c->probe_ev;
+                c->probe_ev = nullptr;
+                return MG_ERR_HIP;
+            }
+    }
+    c->probe_kernel = kernel;
+    c->probe_level = level;
+    c->probe_count = 0;
+    return MG_OK;
+}
+
+mg_status mg_probe_result(mg_ctx *c, int32_t *launches, double *total_ms)
+{
+    if (!c || !launches || !total_ms) return MG_ERR_INVALID;
+    *launches = 0;
+    *total_ms = 0.0;
+    if (!c->probe_ev || c->probe_count == 0) return MG_OK;
+    if (hipStreamSynchronize(c->s) != hipSuccess) return MG_ERR_HIP;
+    double sum = 0.0;
+    for (int q = 0; q < c->probe_count; q++) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, c->probe_ev[2 * q], c->probe_ev[2 * q + 1]) != hipSuccess)
+            return MG_ERR_HIP;
+        sum += ms;
+    }
+    *launches = c->probe_count;
+    *total_ms = sum;
+    c->probe_count = 0;
+    return MG_OK;
+}
+
+const char *mg_status_str(mg_status s)
+{
+    switch (s) {
+    case MG_OK: return "ok";
+    case MG_ERR_INVALID: return "invalid argument";
+    case MG_ERR_WORKSPACE: return "workspace missing, too small or misaligned";
+    case MG_ERR_HIP: return "HIP runtime error";
+    case MG_ERR_NOT_CONVERGED: return "not converged within max_outer";
+    case MG_ERR_DIVERGED: return "diverged (non-finite or exploding norm)";
+    case MG_ERR_SINGULAR: return "singular coarsest-level matrix";
+    }
+    return "unknown status";
+}
+
+mg_status mg_scalar_field_sources(const mg_params *p, int32_t n_phi, const double *h_phi_modes,
+                                  int32_t n_pi, const double *h_pi_modes, double mass, double *d_rho5,
+                                  double *d_rho1, double *d_S, void *d_scratch, size_t scratch_bytes,
+                                  double *h_mean_rho, void *stream)
+{
+    if (!p || p->n < 1 || p->n > 4096 || !(p->length > 0.0)) return MG_ERR_INVALID;
+    if (n_phi < 0 || n_phi > kMaxModes || n_pi < 0 || n_pi > kMaxModes) return MG_ERR_INVALID;
+    if ((n_phi && !h_phi_modes) || (n_pi && !h_pi_modes)) return MG_ERR_INVALID;
+    if (!d_rho5 || !d_rho1 || !d_S || !std::isfinite(mass)) return MG_ERR_INVALID;
+    if (h_mean_rho && (!d_scratch || scratch_bytes < MG_SOURCES_SCRATCH_BYTES ||
+                       ((uintptr_t)d_scratch % 256) != 0))
+        return MG_ERR_WORKSPACE;
+    ModeTable t;
+    std::memset(&t, 0, sizeof(t));
+    t.nphi = n_phi;
+    t.npi = n_pi;
+    for (int q = 0; q < n_phi; q++)
+        for (int e = 0; e < 5; e++) t.phi[q][e] = h_phi_modes[5 * q + e];
+    for (int q = 0; q < n_pi; q++)
+        for (int e = 0; e < 5; e++) t.pi[q][e] = h_pi_modes[5 * q + e];
+    const Geo g = make_geo(p->n, p->bc, p->length, p->origin, p->puncture_pos);
+    const int64_t m = (int64_t)p->n * p->n * p->n;
+    const unsigned nb = std::min<unsigned>(nblk(m), kSrcBlocks);
+    hipStream_t s = (hipStream_t)stream;
+    double *part = h_mean_rho ? (double *)d_scratch : nullptr;
+    hipLaunchKernelGGL(k_sources_modes, dim3(nb), dim3(kBlock), 0, s, g, p->length, t, mass, d_rho5,
+                       d_rho1, d_S, part);
+    if (h_mean_rho) {
+        double *res = (double *)d_scratch + kSrcBlocks;
+        hipLaunchKernelGGL(k_reduce_final<1>, dim3(1), dim3(kBlock), 0, s, (const double *)part,
+                           (int64_t)nb, 0u, 1.0 / (double)m, res);
+        if (hipMemcpyAsync(h_mean_rho, res, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
+            return MG_ERR_HIP;
+        if (hipStreamSynchronize(s) != hipSuccess) return MG_ERR_HIP;
+    }
+    return hip_status();
+}
+
+mg_status mg_shell_field_sources(const mg_params *p, double amp, double r0, double width2, double mass,
+                                 double *d_rho5, double *d_rho1, double *d_S, void *stream)
+{
+    if (!p || p->n < 1 || p->n > 4096 || !(p->length > 0.0) || !(width2 > 0.0)) return MG_ERR_INVALID;
+    if (!d_rho5 || !d_rho1 || !d_S) return MG_ERR_INVALID;
+    const Geo g = make_geo(p->n, p->bc, p->length, p->origin, p->puncture_pos);
+    const int64_t m = (int64_t)p->n * p->n * p->n;
+    hipLaunchKernelGGL(k_sources_shell, dim3(nblk(m)), dim3(kBlock), 0, (hipStream_t)stream, g, amp, r0,
+                       width2, mass, d_rho5, d_rho1, d_S);
+    return hip_status();
+}
+
+mg_status mg_interp_cubic(const mg_params *pc, const double *d_coarse, double *d_fine, void *stream)
+{
+    if (!pc || pc->n < 2 || pc->n > 2048 || !(pc->length > 0.0) || !d_coarse || !d_fine)
+        return MG_ERR_INVALID;
+    if (pc->bc != MG_BC_PERIODIC && pc->bc != MG_BC_ROBIN) return MG_ERR_INVALID;
+    const Geo gc = make_geo(pc->n, pc->bc, pc->length, pc->origin, pc->puncture_pos);
+    const int64_t mf = 8 * (int64_t)pc->n * pc->n * pc->n;
+    if (pc->bc == MG_BC_PERIODIC)
+        hipLaunchKernelGGL(k_interp_cubic<kBcPeriodic>, dim3(nblk(mf)), dim3(kBlock), 0, (hipStream_t)stream,
+                           gc, d_coarse, d_fine);
+    else
+        hipLaunchKernelGGL(k_interp_cubic<kBcRobin>, dim3(nblk(mf)), dim3(kBlock), 0, (hipStream_t)stream, gc,
+                           d_coarse, d_fine);
+    return hip_status();
+}
+
+mg_status mg_kernel_op(mg_ctx *c, int32_t op, int32_t level, int32_t arg, const void *d_in, void *d_out,
+                       const void *d_r, const void *d_c)
+{
+    if (!c) return MG_ERR_INVALID;
+    return c->f32 ? kernel_op<float>(c, op, level, arg, d_in, d_out, d_r, d_c)
+                  : kernel_op<double>(c, op, level, arg, d_in, d_out, d_r, d_c);
+}
+
+} // extern "C"

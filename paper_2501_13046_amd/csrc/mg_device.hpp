@@ -1,0 +1,232 @@
+// mg_device.hpp -- device-side building blocks of the constraint multigrid:
+// grid geometry, boundary accessors, 4th-order stencils and block reductions.
+//
+// Layout: cell-centred N^3 fields, z fastest, element (i,j,k) at (i*N+j)*N+k;
+// 3-vector fields are three consecutive N^3 blocks.  Boundary values come
+// from the accessor: periodic wrap, or the 1/r Robin rule a(g) = a(b)|x_b|/|x_g|
+// with b the nearest grid cell (coordinates clamped) and radii measured from
+// the puncture position.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace grtmg {
+
+constexpr int kBlock = 256;
+constexpr int kWave = 64;
+constexpr int kBcPeriodic = 0;
+constexpr int kBcRobin = 1;
+
+struct Geo {
+    int n;
+    int bc;
+    double h;
+    double inv12h;   // 1 / (12 h)
+    double inv12h2;  // 1 / (12 h^2)
+    double inv144h2; // 1 / (144 h^2)
+    double org[3];
+    double ctr[3];
+};
+
+__host__ __device__ inline Geo make_geo(int n, int bc, double length, const double org[3],
+                                        const double ctr[3])
+{
+    Geo g;
+    g.n = n;
+    g.bc = bc;
+    g.h = length / n;
+    g.inv12h = 1.0 / (12.0 * g.h);
+    g.inv12h2 = 1.0 / (12.0 * g.h * g.h);
+    g.inv144h2 = 1.0 / (144.0 * g.h * g.h);
+    for (int a = 0; a < 3; a++) {
+        g.org[a] = org[a];
+        g.ctr[a] = ctr[a];
+    }
+    return g;
+}
+
+__device__ __forceinline__ int64_t lidx(int n, int i, int j, int k)
+{
+    return ((int64_t)i * n + j) * n + k;
+}
+
+__device__ __forceinline__ double cell_radius(const Geo &g, int i, int j, int k)
+{
+    double x = g.org[0] + (i + 0.5) * g.h - g.ctr[0];
+    double y = g.org[1] + (j + 0.5) * g.h - g.ctr[1];
+    double z = g.org[2] + (k + 0.5) * g.h - g.ctr[2];
+    return sqrt(x * x + y * y + z * z);
+}
+
+__device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+__device__ __forceinline__ int clampc(int i, int n) { return i < 0 ? 0 : (i >= n ? n - 1 : i); }
+
+// Read-only field accessor with the boundary rule applied.
+template <int BC, typename T>
+struct Acc {
+    const T *__restrict__ a;
+    Geo g;
+    __device__ __forceinline__ T operator()(int i, int j, int k) const
+    {
+        const int n = g.n;
+        if constexpr (BC == kBcPeriodic) {
+            return a[lidx(n, wrap(i, n), wrap(j, n), wrap(k, n))];
+        } else {
+            if ((unsigned)i < (unsigned)n && (unsigned)j < (unsigned)n && (unsigned)k < (unsigned)n)
+                return a[lidx(n, i, j, k)];
+            int bi = clampc(i, n), bj = clampc(j, n), bk = clampc(k, n);
+            double v = (double)a[lidx(n, bi, bj, bk)] * cell_radius(g, bi, bj, bk);
+            return (T)(v / cell_radius(g, i, j, k));
+        }
+    }
+};
+
+// Weight with which the boundary-ruled value at (i,j,k)+offset depends on the
+// stored value at (i,j,k) itself (1 for the centre tap).
+template <int BC>
+__device__ __forceinline__ double self_weight(const Geo &g, int i, int j, int k, int di, int dj,
+                                              int dk)
+{
+    const int n = g.n;
+    int ii = i + di, jj = j + dj, kk = k + dk;
+    if constexpr (BC == kBcPeriodic) {
+        return (wrap(ii, n) == i && wrap(jj, n) == j && wrap(kk, n) == k) ? 1.0 : 0.0;
+    } else {
+        if ((unsigned)ii < (unsigned)n && (unsigned)jj < (unsigned)n && (unsigned)kk < (unsigned)n)
+            return (di == 0 && dj == 0 && dk == 0) ? 1.0 : 0.0;
+        int bi = clampc(ii, n), bj = clampc(jj, n), bk = clampc(kk, n);
+        if (bi != i || bj != j || bk != k) return 0.0;
+        return cell_radius(g, bi, bj, bk) / cell_radius(g, ii, jj, kk);
+    }
+}
+
+// ---- stencils (unscaled sums; the caller multiplies by 1/(12h) or 1/(12h^2)) ----
+
+template <int AX>
+__device__ __forceinline__ void off(int d, int &di, int &dj, int &dk)
+{
+    di = (AX == 0) ? d : 0;
+    dj = (AX == 1) ? d : 0;
+    dk = (AX == 2) ? d : 0;
+}
+
+// f(-2) - 8 f(-1) + 8 f(+1) - f(+2) along AX
+template <int AX, typename T, typename F>
+__device__ __forceinline__ T d1_sum(const F &f, int i, int j, int k)
+{
+    int a, b, c;
+    off<AX>(1, a, b, c);
+    return (f(i - 2 * a, j - 2 * b, k - 2 * c) - f(i + 2 * a, j + 2 * b, k + 2 * c)) +
+           T(8) * (f(i + a, j + b, k + c) - f(i - a, j - b, k - c));
+}
+
+// -f(-2) + 16 f(-1) - 30 f(0) + 16 f(+1) - f(+2) along AX (centre passed in)
+template <int AX, typename T, typename F>
+__device__ __forceinline__ T d2_sum(const F &f, int i, int j, int k, T centre)
+{
+    int a, b, c;
+    off<AX>(1, a, b, c);
+    return T(16) * (f(i - a, j - b, k - c) + f(i + a, j + b, k + c)) -
+           (f(i - 2 * a, j - 2 * b, k - 2 * c) + f(i + 2 * a, j + 2 * b, k + 2 * c)) -
+           T(30) * centre;
+}
+
+template <typename T, typename F>
+__device__ __forceinline__ T lap_sum(const F &f, int i, int j, int k, T centre)
+{
+    return d2_sum<0, T>(f, i, j, k, centre) + d2_sum<1, T>(f, i, j, k, centre) +
+           d2_sum<2, T>(f, i, j, k, centre);
+}
+
+// sum_{d,e} w1[d] w1[e] f(x + d e_P + e e_Q), w1 = (1, -8, 0, 8, -1): D_P D_Q * 144 h^2
+template <int P, int Q, typename T, typename F>
+__device__ __forceinline__ T dmix_sum(const F &f, int i, int j, int k)
+{
+    int pa, pb, pc, qa, qb, qc;
+    off<P>(1, pa, pb, pc);
+    off<Q>(1, qa, qb, qc);
+    T s = T(0);
+#pragma unroll
+    for (int d = -2; d <= 2; d++) {
+        if (d == 0) continue;
+        const T wd = (d == -2) ? T(1) : (d == -1) ? T(-8) : (d == 1) ? T(8) : T(-1);
+        T t = T(0);
+#pragma unroll
+        for (int e = -2; e <= 2; e++) {
+            if (e == 0) continue;
+            const T we = (e == -2) ? T(1) : (e == -1) ? T(-8) : (e == 1) ? T(8) : T(-1);
+            t += we * f(i + d * pa + e * qa, j + d * pb + e * qb, k + d * pc + e * qc);
+        }
+        s += wd * t;
+    }
+    return s;
+}
+
+// Diagonal of the unscaled Laplacian sum at (i,j,k) with the boundary rule.
+template <int BC>
+__device__ __forceinline__ double lap_diag_sum(const Geo &g, int i, int j, int k)
+{
+    if constexpr (BC == kBcPeriodic) {
+        return -90.0;
+    } else {
+        const int n = g.n;
+        double s = -90.0;
+        // only cells on the boundary see their own value through a ghost
+        if (i == 0 || i == n - 1 || j == 0 || j == n - 1 || k == 0 || k == n - 1) {
+            const double w[5] = {-1.0, 16.0, 0.0, 16.0, -1.0};
+#pragma unroll
+            for (int d = -2; d <= 2; d++) {
+                if (d == 0) continue;
+                s += w[d + 2] * self_weight<BC>(g, i, j, k, d, 0, 0);
+                s += w[d + 2] * self_weight<BC>(g, i, j, k, 0, d, 0);
+                s += w[d + 2] * self_weight<BC>(g, i, j, k, 0, 0, d);
+            }
+        }
+        return s;
+    }
+}
+
+// ---- reductions ---------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// Deterministic block reduction of NV values (bit v of max_mask set: max,
+// else sum); thread 0 writes the block's results to out[0..NV).
+template <int NV>
+__device__ __forceinline__ void block_reduce_store(double (&v)[NV], unsigned max_mask,
+                                                   double *out)
+{
+    __shared__ double sh[NV][kBlock / kWave];
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+#pragma unroll
+    for (int q = 0; q < NV; q++) v[q] = ((max_mask >> q) & 1u) ? wave_max(v[q]) : wave_sum(v[q]);
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; q++) sh[q][wid] = v[q];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; q++) {
+            double a = sh[q][0];
+            for (int w = 1; w < kBlock / kWave; w++)
+                a = ((max_mask >> q) & 1u) ? fmax(a, sh[q][w]) : a + sh[q][w];
+            out[q] = a;
+        }
+    }
+}
+
+} // namespace grtmg

@@ -1,0 +1,707 @@
+// mg_kernels.hpp -- HIP kernels of the constraint multigrid (gfx950).
+//
+// Every multigrid kernel here is bound by HBM bandwidth: one thread per cell
+// (z fastest, so a wavefront reads 64 consecutive cells of a z-line), stencil
+// neighbours served by the L1/L2 caches.  The residual and the update stay
+// FP64; the V-cycle kernels are templated on the working type T (float for
+// the FP32 V-cycle inside FP64 iterative refinement, double otherwise).
+#pragma once
+
+#include "mg_device.hpp"
+
+namespace grtmg {
+
+constexpr double kPi = 3.14159265358979323846;
+
+__device__ __forceinline__ bool cell_of(int64_t tid, int n, int &i, int &j, int &k)
+{
+    const int64_t cells = (int64_t)n * n * n;
+    if (tid >= cells) return false;
+    k = (int)(tid % n);
+    int64_t t = tid / n;
+    j = (int)(t % n);
+    i = (int)(t / n);
+    return true;
+}
+
+__device__ __forceinline__ double psi0_at(const Geo &g, double pmass, int i, int j, int k)
+{
+    return pmass > 0.0 ? 1.0 + pmass / (2.0 * cell_radius(g, i, j, k)) : 1.0;
+}
+
+// ---------------------------------------------------------------------------------------
+// Nonlinear residuals (FP64).  Per cell: psi = psi0 + u,
+//   H = L_h u + 2 pi rho5 psi^5 + 2 pi rho1 psi - (K^2/12) psi^5 + A2 psi^-7/8 + f
+//   c = 10 pi rho5 psi^4 + 2 pi rho1 - (5 K^2/12) psi^4 - (7/8) A2 psi^-8
+//   M_a = (Delta_L W)_a - (8 pi psi^6 S_a - meanS_a)
+// Outputs are optional: H, M, c as FP64 fields; r = -H, rc = c, rW = -M in T;
+// per-block partials (sum H^2, max |H|, sum |M|^2, max |M|).
+// ---------------------------------------------------------------------------------------
+struct ResArgs {
+    const double *u, *W, *rho5, *rho1, *S, *f;
+    const double *meanS; // device, 3 values (periodic momentum source mean)
+    double K2, pmass;
+    double *H, *M, *c;
+    void *r, *rc, *rW; // T
+    double *partials;  // 4 per block
+    int want_M;        // compute momentum residual
+    int conformal;     // matter given as rho_bar = psi^8 rho, S_bar = psi^6 S
+};
+
+template <int BC, typename T>
+__global__ void __launch_bounds__(kBlock) k_residual(Geo g, ResArgs a)
+{
+    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int n = g.n;
+    const int64_t m = (int64_t)n * n * n;
+    int i, j, k;
+    double hv = 0.0, m2 = 0.0;
+    if (cell_of(tid, n, i, j, k)) {
+        const int64_t q = tid;
+        const double psi = psi0_at(g, a.pmass, i, j, k) + a.u[q];
+        Acc<BC, double> U{a.u, g};
+        double A2 = 0.0;
+        double Mv[3] = {0.0, 0.0, 0.0};
+        if (a.W) {
+            Acc<BC, double> W0{a.W, g}, W1{a.W + m, g}, W2{a.W + 2 * m, g};
+            // dW[a][b] = D_a W_b
+            double dW[3][3];
+            dW[0][0] = d1_sum<0, double>(W0, i, j, k) * g.inv12h;
+            dW[1][0] = d1_sum<1, double>(W0, i, j, k) * g.inv12h;
+            dW[2][0] = d1_sum<2, double>(W0, i, j, k) * g.inv12h;
+            dW[0][1] = d1_sum<0, double>(W1, i, j, k) * g.inv12h;
+            dW[1][1] = d1_sum<1, double>(W1, i, j, k) * g.inv12h;
+            dW[2][1] = d1_sum<2, double>(W1, i, j, k) * g.inv12h;
+            dW[0][2] = d1_sum<0, double>(W2, i, j, k) * g.inv12h;
+            dW[1][2] = d1_sum<1, double>(W2, i, j, k) * g.inv12h;
+            dW[2][2] = d1_sum<2, double>(W2, i, j, k) * g.inv12h;
+            const double div = dW[0][0] + dW[1][1] + dW[2][2];
+#pragma unroll
+            for (int p = 0; p < 3; p++)
+#pragma unroll
+                for (int s = 0; s < 3; s++) {
+                    double Ab = dW[p][s] + dW[s][p] - (p == s ? 2.0 * div / 3.0 : 0.0);
+                    A2 += Ab * Ab;
+                }
+            if (a.want_M) {
+                const double w0 = a.W[q], w1 = a.W[m + q], w2 = a.W[2 * m + q];
+                const double xx0 = d2_sum<0, double>(W0, i, j, k, w0);
+                const double xx1 = d2_sum<1, double>(W1, i, j, k, w1);
+                const double xx2 = d2_sum<2, double>(W2, i, j, k, w2);
+                const double l0 = (xx0 + d2_sum<1, double>(W0, i, j, k, w0) +
+                                   d2_sum<2, double>(W0, i, j, k, w0)) * g.inv12h2;
+                const double l1 = (d2_sum<0, double>(W1, i, j, k, w1) + xx1 +
+                                   d2_sum<2, double>(W1, i, j, k, w1)) * g.inv12h2;
+                const double l2 = (d2_sum<0, double>(W2, i, j, k, w2) +
+                                   d2_sum<1, double>(W2, i, j, k, w2) + xx2) * g.inv12h2;
+                const double t0 = xx0 * g.inv12h2 + (dmix_sum<0, 1, double>(W1, i, j, k) +
+                                                     dmix_sum<0, 2, double>(W2, i, j, k)) * g.inv144h2;
+                const double t1 = xx1 * g.inv12h2 + (dmix_sum<1, 0, double>(W0, i, j, k) +
+                                                     dmix_sum<1, 2, double>(W2, i, j, k)) * g.inv144h2;
+                const double t2 = xx2 * g.inv12h2 + (dmix_sum<2, 0, double>(W0, i, j, k) +
+                                                     dmix_sum<2, 1, double>(W1, i, j, k)) * g.inv144h2;
+                Mv[0] = l0 + t0 / 3.0;
+                Mv[1] = l1 + t1 / 3.0;
+                Mv[2] = l2 + t2 / 3.0;
+            }
+        }
+        if (a.want_M && a.S) {
+            const double psi2 = psi * psi;
+            const double w6 = a.conformal ? 1.0 : psi2 * psi2 * psi2;
+#pragma unroll
+            for (int s = 0; s < 3; s++) Mv[s] -= 8.0 * kPi * w6 * a.S[s * m + q] - a.meanS[s];
+        }
+        const double psi2 = psi * psi, psi4 = psi2 * psi2, psi5 = psi4 * psi;
+        const double ipsi = 1.0 / psi, ipsi4 = 1.0 / psi4;
+        const double ipsi7 = ipsi4 * ipsi * ipsi * ipsi, ipsi8 = ipsi7 * ipsi;
+        const double r5 = a.rho5[q], r1 = a.rho1[q];
+        double matter, dmatter;
+        if (a.conformal) {
+            const double rbar = r5 + r1;
+            matter = 2.0 * kPi * rbar * (ipsi4 * psi);
+            dmatter = -6.0 * kPi * rbar * ipsi4;
+        } else {
+            matter = 2.0 * kPi * r5 * psi5 + 2.0 * kPi * r1 * psi;
+            dmatter = 10.0 * kPi * r5 * psi4 + 2.0 * kPi * r1;
+        }
+        double H = lap_sum<double>(U, i, j, k, a.u[q]) * g.inv12h2 + matter -
+                   (a.K2 / 12.0) * psi5 + 0.125 * A2 * ipsi7;
+        if (a.f) H += a.f[q];
+        const double c = dmatter - (5.0 * a.K2 / 12.0) * psi4 - 0.875 * A2 * ipsi8;
+        if (a.H) a.H[q] = H;
+        if (a.c) a.c[q] = c;
+        if (a.r) ((T *)a.r)[q] = (T)(-H);
+        if (a.rc) ((T *)a.rc)[q] = (T)c;
+        if (a.want_M) {
+            if (a.M) {
+                a.M[q] = Mv[0];
+                a.M[m + q] = Mv[1];
+                a.M[2 * m + q] = Mv[2];
+            }
+            if (a.rW) {
+                ((T *)a.rW)[q] = (T)(-Mv[0]);
+                ((T *)a.rW)[m + q] = (T)(-Mv[1]);
+                ((T *)a.rW)[2 * m + q] = (T)(-Mv[2]);
+            }
+            m2 = Mv[0] * Mv[0] + Mv[1] * Mv[1] + Mv[2] * Mv[2];
+        }
+        hv = H;
+    }
+    if (a.partials) {
+        double v[4] = {hv * hv, fabs(hv), m2, sqrt(m2)};
+        block_reduce_store<4>(v, 0xAu, a.partials + 4 * (int64_t)blockIdx.x);
+    }
+}
+
+// Per-block partial sums of 8 pi psi^6 S_a (for the periodic mean removal).
+template <int BC>
+__global__ void __launch_bounds__(kBlock) k_source_sum(Geo g, const double *u, const double *S,
+                                                       double pmass, int conformal,
+                                                       double *partials)
+{
+    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int n = g.n;
+    const int64_t m = (int64_t)n * n * n;
+    int i, j, k;
+    double v[3] = {0.0, 0.0, 0.0};
+    if (cell_of(tid, n, i, j, k)) {
+        const double psi = psi0_at(g, pmass, i, j, k) + u[tid];
+        const double p2 = psi * psi, p6 = conformal ? 1.0 : p2 * p2 * p2;
+#pragma unroll
+        for (int s = 0; s < 3; s++) v[s] = 8.0 * kPi * p6 * S[s * m + tid];
+    }
+    block_reduce_store<3>(v, 0u, partials + 3 * (int64_t)blockIdx.x);
+}
+
+// Per-block partial sums of the three components of a vector field.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_sum3(const T *a, int64_t m, double *partials)
+{
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double v[3] = {0.0, 0.0, 0.0};
+    if (q < m) {
+        v[0] = (double)a[q];
+        v[1] = (double)a[m + q];
+        v[2] = (double)a[2 * m + q];
+    }
+    block_reduce_store<3>(v, 0u, partials + 3 * (int64_t)blockIdx.x);
+}
+
+// Single-block final reduction: out[v] = combine over blocks of partials[b*NV+v];
+// scale (if non-zero) multiplies the sums.
+template <int NV>
+__global__ void __launch_bounds__(kBlock) k_reduce_final(const double *partials, int64_t nblocks,
+                                                         unsigned max_mask, double scale,
+                                                         double *out)
+{
+    double v[NV];
+#pragma unroll
+    for (int q = 0; q < NV; q++) v[q] = 0.0;
+    for (int64_t b = threadIdx.x; b < nblocks; b += kBlock)
+#pragma unroll
+        for (int q = 0; q < NV; q++) {
+            double x = partials[b * NV + q];
+            v[q] = ((max_mask >> q) & 1u) ? fmax(v[q], x) : v[q] + x;
+        }
+    __shared__ double res[NV];
+    double tmp[NV];
+#pragma unroll
+    for (int q = 0; q < NV; q++) tmp[q] = v[q];
+    block_reduce_store<NV>(tmp, max_mask, res);
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int q = 0; q < NV; q++)
+            out[q] = ((max_mask >> q) & 1u) || scale == 0.0 ? res[q] : res[q] * scale;
+}
+
+// ---------------------------------------------------------------------------------------
+// Smoothers: one colour pass of double-buffered red-black Gauss-Seidel.  Cells
+// of the active colour ((i+j+k) mod 2) get d + (r - A d)/diag(A); the others
+// are copied.  Every read is from `in` (the state before the pass).
+// ---------------------------------------------------------------------------------------
+template <int BC, typename T>
+__global__ void __launch_bounds__(kBlock) k_pass_psi(Geo g, const T *__restrict__ in,
+                                                     T *__restrict__ out, const T *__restrict__ r,
+                                                     const T *__restrict__ c, int colour)
+{
+    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int i, j, k;
+    if (!cell_of(tid, g.n, i, j, k)) return;
+    const T x = in[tid];
+    if (((i + j + k) & 1) != colour) {
+        out[tid] = x;
+        return;
+    }
+    Acc<BC, T> D{in, g};
+    const T cv = c[tid];
+    const T h2 = (T)g.inv12h2;
+    const T Ad = lap_sum<T>(D, i, j, k, x) * h2 + cv * x;
+    const T diag = (T)(lap_diag_sum<BC>(g, i, j, k) * g.inv12h2) + cv;
+    out[tid] = x + (r[tid] - Ad) / diag;
+}
+
+// (Delta_L d)_a at a cell for the three components (periodic).
+template <typename T>
+__device__ __forceinline__ void deltaL_apply(const Geo &g, const T *d, int64_t m, int i, int j,
+                                             int k, int64_t q, T out[3])
+{
+    Acc<kBcPeriodic, T> D0{d, g}, D1{d + m, g}, D2{d + 2 * m, g};
+    const T c0 = d[q], c1 = d[m + q], c2 = d[2 * m + q];
+    const T xx0 = d2_sum<0, T>(D0, i, j, k, c0);
+    const T xx1 = d2_sum<1, T>(D1, i, j, k, c1);
+    const T xx2 = d2_sum<2, T>(D2, i, j, k, c2);
+    const T h2 = (T)g.inv12h2, m2 = (T)g.inv144h2, third = T(1) / T(3);
+    const T l0 = (xx0 + d2_sum<1, T>(D0, i, j, k, c0) + d2_sum<2, T>(D0, i, j, k, c0)) * h2;
+    const T l1 = (d2_sum<0, T>(D1, i, j, k, c1) + xx1 + d2_sum<2, T>(D1, i, j, k, c1)) * h2;
+    const T l2 = (d2_sum<0, T>(D2, i, j, k, c2) + d2_sum<1, T>(D2, i, j, k, c2) + xx2) * h2;
+    const T t0 = xx0 * h2 + (dmix_sum<0, 1, T>(D1, i, j, k) + dmix_sum<0, 2, T>(D2, i, j, k)) * m2;
+    const T t1 = xx1 * h2 + (dmix_sum<1, 0, T>(D0, i, j, k) + dmix_sum<1, 2, T>(D2, i, j, k)) * m2;
+    const T t2 = xx2 * h2 + (dmix_sum<2, 0, T>(D0, i, j, k) + dmix_sum<2, 1, T>(D1, i, j, k)) * m2;
+    out[0] = l0 + t0 * third;
+    out[1] = l1 + t1 * third;
+    out[2] = l2 + t2 * third;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_pass_W(Geo g, const T *__restrict__ in,
+                                                   T *__restrict__ out, const T *__restrict__ r,
+                                                   int colour)
+{
+    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int n = g.n;
+    const int64_t m = (int64_t)n * n * n;
+    int i, j, k;
+    if (!cell_of(tid, n, i, j, k)) return;
+    if (((i + j + k) & 1) != colour) {
+        out[tid] = in[tid];
+        out[m + tid] = in[m + tid];
+        out[2 * m + tid] = in[2 * m + tid];
+        return;
+    }
+    T Ad[3];
+    deltaL_apply<T>(g, in, m, i, j, k, tid, Ad);
+    // diagonal of Delta_L,h: (-90 - 30/3) / (12 h^2) = -25 / (3 h^2)
+    const T diag = (T)(-100.0 * g.inv12h2);
+#pragma unroll
+    for (int s = 0; s < 3; s++) out[s * m + tid] = in[s * m + tid] + (r[s * m + tid] - Ad[s]) / diag;
+}
+
+// ---------------------------------------------------------------------------------------
+// Defect + restriction: coarse(I) = average over the 8 children of r - A d;
+// optionally the coefficient c is restricted the same way.
+// ---------------------------------------------------------------------------------------
+template <int BC, typename T>
+__global__ void __launch_bounds__(kBlock) k_defect_restrict_psi(Geo g, const T *__restrict__ d,
+                                                                const T *__restrict__ r,
+                                                                const T *__restrict__ c,
+                                                                T *__restrict__ rc_out,
+                                                                T *__restrict__ cc_out)
+{
+    const int nc = g.n / 2;
+    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int I, J, K;
+    if (!cell_of(tid, nc, I, J, K)) return;
+    Acc<BC, T> D{d, g};
+    const T h2 = (T)g.inv12h2;
+    T sd = T(0), sc = T(0);
+#pragma unroll
+    for (int di = 0; di < 2; di++)
+#pragma unroll
+        for (int dj = 0; dj < 2; dj++)
+#pragma unroll
+            for (int dk = 0; dk < 2; dk++) {
+                const int i = 2 * I + di, j = 2 * J + dj, k = 2 * K + dk;
+                const int64_t q = lidx(g.n, i, j, k);
+                const T x = d[q], cv = c[q];
+                sd += r[q] - (lap_sum<T>(D, i, j, k, x) * h2 + cv * x);
+                sc += cv;
+            }
+    rc_out[tid] = sd * T(0.125);
+    if (cc_out) cc_out[tid] = sc * T(0.125);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_defect_restrict_W(Geo g, const T *__restrict__ d,
+                                                              const T *__restrict__ r,
+                                                              T *__restrict__ rc_out)
+{
+    const int nc = g.n / 2;
+    const int64_t mf = (int64_t)g.n * g.n * g.n, mc = (int64_t)nc * nc * nc;
+    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int I, J, K;
+    if (!cell_of(tid, nc, I, J, K)) return;
+    T s[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int di = 0; di < 2; di++)
+#pragma unroll
+        for (int dj = 0; dj < 2; dj++)
+#pragma unroll
+            for (int dk = 0; dk < 2; dk++) {
+                const int i = 2 * I + di, j = 2 * J + dj, k = 2 * K + dk;
+                const int64_t q = lidx(g.n, i, j, k);
+                T Ad[3];
+                deltaL_apply<T>(g, d, mf, i, j, k, q, Ad);
+#pragma unroll
+                for (int a = 0; a < 3; a++) s[a] += r[a * mf + q] - Ad[a];
+            }
+#pragma unroll
+    for (int a = 0; a < 3; a++) rc_out[a * mc + tid] = s[a] * T(0.125);
+}
+
+// ---------------------------------------------------------------------------------------
+// Trilinear cell-centred prolongation: fine += P coarse (weights 3/4, 1/4 per
+// axis toward the nearer coarse neighbour), ncomp components.  gc: coarse grid.
+// ---------------------------------------------------------------------------------------
+template <int BC, typename T>
+__global__ void __launch_bounds__(kBlock) k_prolong_add(Geo gc, const T *__restrict__ coarse,
+                                                        T *__restrict__ fine, int ncomp)
+{
+    const int nf = 2 * gc.n;
+    const int64_t mf = (int64_t)nf * nf * nf, mc = (int64_t)gc.n * gc.n * gc.n;
+    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int i, j, k;
+    if (!cell_of(tid, nf, i, j, k)) return;
+    const int I = i >> 1, J = j >> 1, K = k >> 1;
+    const int I1 = (i & 1) ? I + 1 : I - 1;
+    const int J1 = (j & 1) ? J + 1 : J - 1;
+    const int K1 = (k & 1) ? K + 1 : K - 1;
+    const T a = T(0.75), b = T(0.25);
+    for (int s = 0; s < ncomp; s++) {
+        Acc<BC, T> C{coarse + s * mc, gc};
+        const T v = a * (a * (a * C(I, J, K) + b * C(I, J, K1)) + b * (a * C(I, J1, K) + b * C(I, J1, K1))) +
+                    b * (a * (a * C(I1, J, K) + b * C(I1, J, K1)) + b * (a * C(I1, J1, K) + b * C(I1, J1, K1)));
+        fine[s * mf + tid] += v;
+    }
+}
+
+// Four-point cubic interpolation (FP64), fine = Q coarse.
+template <int BC>
+__global__ void __launch_bounds__(kBlock) k_interp_cubic(Geo gc, const double *__restrict__ coarse,
+                                                         double *__restrict__ fine)
+{
+    const int nf = 2 * gc.n;
+    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int i, j, k;
+    if (!cell_of(tid, nf, i, j, k)) return;
+    // weights for nodes base..base+3 (even fine index: base = I-2, offset -1/4;
+    // odd: base = I-1, offset +1/4)
+    const double we[4] = {-5.0 / 128.0, 35.0 / 128.0, 105.0 / 128.0, -7.0 / 128.0};
+    const double wo[4] = {-7.0 / 128.0, 105.0 / 128.0, 35.0 / 128.0, -5.0 / 128.0};
+    const double *wi = (i & 1) ? wo : we;
+    const double *wj = (j & 1) ? wo : we;
+    const double *wk = (k & 1) ? wo : we;
+    const int bi = (i >> 1) - ((i & 1) ? 1 : 2);
+    const int bj = (j >> 1) - ((j & 1) ? 1 : 2);
+    const int bk = (k >> 1) - ((k & 1) ? 1 : 2);
+    Acc<BC, double> C{coarse, gc};
+    double s = 0.0;
+    for (int a = 0; a < 4; a++) {
+        double sa = 0.0;
+        for (int b = 0; b < 4; b++) {
+            double sb = 0.0;
+            for (int e = 0; e < 4; e++) sb += wk[e] * C(bi + a, bj + b, bk + e);
+            sa += wj[b] * sb;
+        }
+        s += wi[a] * sa;
+    }
+    fine[tid] = s;
+}
+
+// ---------------------------------------------------------------------------------------
+// Coarsest level: dense operator assembly, Gauss-Jordan inverse (partial
+// pivoting, FP64, one workgroup), and x = A^-1 r as a column-major mat-vec.
+// ---------------------------------------------------------------------------------------
+
+// Row `row` of (L_h + c): A[row][col] accumulated over the 13 taps, boundary
+// rule included.  A is zeroed by the caller.
+template <int BC, typename T>
+__global__ void __launch_bounds__(kBlock) k_assemble_psi(Geo g, const T *c, double *A)
+{
+    const int n = g.n;
+    const int64_t m = (int64_t)n * n * n;
+    const int64_t row = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int i, j, k;
+    if (!cell_of(row, n, i, j, k)) return;
+    const double w[5] = {-1.0, 16.0, -30.0, 16.0, -1.0};
+    for (int ax = 0; ax < 3; ax++)
+        for (int d = -2; d <= 2; d++) {
+            int ii = i + (ax == 0 ? d : 0), jj = j + (ax == 1 ? d : 0), kk = k + (ax == 2 ? d : 0);
+            double fac = 1.0;
+            if (BC == kBcPeriodic) {
+                ii = wrap(ii, n);
+                jj = wrap(jj, n);
+                kk = wrap(kk, n);
+            } else if (!((unsigned)ii < (unsigned)n && (unsigned)jj < (unsigned)n &&
+                         (unsigned)kk < (unsigned)n)) {
+                int bi = clampc(ii, n), bj = clampc(jj, n), bk = clampc(kk, n);
+                fac = cell_radius(g, bi, bj, bk) / cell_radius(g, ii, jj, kk);
+                ii = bi;
+                jj = bj;
+                kk = bk;
+            }
+            A[row * m + lidx(n, ii, jj, kk)] += w[d + 2] * g.inv12h2 * fac;
+        }
+    A[row * m + row] += (double)c[row];
+}
+
+// Rows of Delta_L,h on a periodic grid (3 n^3 unknowns) plus -(1/(n^3 h^2))
+// on every same-component entry, which fixes each component's mean to zero.
+__global__ void __launch_bounds__(kBlock) k_assemble_W(Geo g, double *A)
+{
+    const int n = g.n;
+    const int64_t cn = (int64_t)n * n * n, m = 3 * cn;
+    const int64_t row = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (row >= m) return;
+    const int a = (int)(row / cn);
+    int i, j, k;
+    cell_of(row % cn, n, i, j, k);
+    double *Ar = A + row * m;
+    const double reg = 1.0 / ((double)cn * g.h * g.h);
+    for (int64_t col = a * cn; col < (a + 1) * cn; col++) Ar[col] -= reg;
+    const double w2[5] = {-1.0, 16.0, -30.0, 16.0, -1.0};
+    const double w1[5] = {1.0, -8.0, 0.0, 8.0, -1.0};
+    for (int ax = 0; ax < 3; ax++) {
+        const double s = (ax == a) ? 1.0 + 1.0 / 3.0 : 1.0;
+        for (int d = -2; d <= 2; d++) {
+            int ii = wrap(i + (ax == 0 ? d : 0), n), jj = wrap(j + (ax == 1 ? d : 0), n),
+                kk = wrap(k + (ax == 2 ? d : 0), n);
+            Ar[a * cn + lidx(n, ii, jj, kk)] += s * w2[d + 2] * g.inv12h2;
+        }
+    }
+    for (int b = 0; b < 3; b++) {
+        if (b == a) continue;
+        for (int d = -2; d <= 2; d++)
+            for (int e = -2; e <= 2; e++) {
+                if (d == 0 || e == 0) continue;
+                int o[3] = {0, 0, 0};
+                o[a] += d;
+                o[b] += e;
+                int ii = wrap(i + o[0], n), jj = wrap(j + o[1], n), kk = wrap(k + o[2], n);
+                Ar[b * cn + lidx(n, ii, jj, kk)] += w1[d + 2] * w1[e + 2] * g.inv144h2 / 3.0;
+            }
+    }
+}
+
+// Gauss-Jordan inversion with partial pivoting of the m x m row-major matrix
+// A (destroyed); writes the inverse column-major into Ainv.  One workgroup of
+// 1024 threads; aug is an m x 2m scratch.  *flag = 1 if a pivot is zero.
+constexpr int kGjThreads = 1024;
+__global__ void __launch_bounds__(kGjThreads) k_gauss_jordan(const double *A, double *aug,
+                                                             double *Ainv, int m, double *flag)
+{
+    const int tid = threadIdx.x;
+    const int64_t w = 2 * (int64_t)m;
+    for (int64_t e = tid; e < (int64_t)m * w; e += kGjThreads) {
+        const int64_t r = e / w, col = e % w;
+        aug[e] = col < m ? A[r * m + col] : (col - m == r ? 1.0 : 0.0);
+    }
+    __shared__ double sv[kGjThreads / kWave];
+    __shared__ int si[kGjThreads / kWave];
+    __shared__ int piv_row;
+    __shared__ int bad;
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    for (int kcol = 0; kcol < m; kcol++) {
+        // pivot search over rows kcol..m-1 (lowest index wins ties)
+        double best = -1.0;
+        int bi = m;
+        for (int r = kcol + tid; r < m; r += kGjThreads) {
+            double v = fabs(aug[(int64_t)r * w + kcol]);
+            if (v > best) {
+                best = v;
+                bi = r;
+            }
+        }
+        for (int o = kWave / 2; o > 0; o >>= 1) {
+            double ov = __shfl_xor(best, o, kWave);
+            int oi = __shfl_xor(bi, o, kWave);
+            if (ov > best || (ov == best && oi < bi)) {
+                best = ov;
+                bi = oi;
+            }
+        }
+        if (tid % kWave == 0) {
+            sv[tid / kWave] = best;
+            si[tid / kWave] = bi;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double b = sv[0];
+            int idx = si[0];
+            for (int q = 1; q < kGjThreads / kWave; q++)
+                if (sv[q] > b || (sv[q] == b && si[q] < idx)) {
+                    b = sv[q];
+                    idx = si[q];
+                }
+            piv_row = idx;
+            if (!(b > 0.0)) bad = 1;
+        }
+        __syncthreads();
+        if (bad) break;
+        const int pr = piv_row;
+        if (pr != kcol)
+            for (int64_t col = tid; col < w; col += kGjThreads) {
+                double t = aug[(int64_t)kcol * w + col];
+                aug[(int64_t)kcol * w + col] = aug[(int64_t)pr * w + col];
+                aug[(int64_t)pr * w + col] = t;
+            }
+        __syncthreads();
+        const double inv = 1.0 / aug[(int64_t)kcol * w + kcol];
+        __syncthreads();
+        for (int64_t col = tid; col < w; col += kGjThreads) aug[(int64_t)kcol * w + col] *= inv;
+        __syncthreads();
+        // eliminate column kcol from every other row
+        for (int64_t e = tid; e < (int64_t)m * w; e += kGjThreads) {
+            const int64_t r = e / w, col = e % w;
+            if (r == kcol || col == kcol) continue;
+            aug[e] -= aug[r * w + kcol] * aug[(int64_t)kcol * w + col];
+        }
+        __syncthreads();
+        for (int64_t r = tid; r < m; r += kGjThreads)
+            if (r != kcol) aug[r * w + kcol] = 0.0;
+        __syncthreads();
+    }
+    if (tid == 0) *flag = bad ? 1.0 : 0.0;
+    for (int64_t e = tid; e < (int64_t)m * m; e += kGjThreads) {
+        const int64_t r = e / m, col = e % m;
+        Ainv[col * m + r] = aug[r * w + m + col]; // column-major
+    }
+}
+
+// x = Ainv (r - mean r per component when ncomp_project > 0), Ainv column-major.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_coarse_apply(const double *Ainv, int m,
+                                                         const T *r, T *x, int ncomp_project)
+{
+    extern __shared__ double rs[];
+    for (int q = threadIdx.x; q < m; q += kBlock) rs[q] = (double)r[q];
+    __syncthreads();
+    if (ncomp_project > 0) {
+        __shared__ double mean[3];
+        const int cn = m / ncomp_project;
+        if (threadIdx.x < ncomp_project) {
+            double s = 0.0;
+            for (int q = 0; q < cn; q++) s += rs[threadIdx.x * cn + q];
+            mean[threadIdx.x] = s / (double)cn;
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < m; q += kBlock) rs[q] -= mean[q / cn];
+        __syncthreads();
+    }
+    const int row = blockIdx.x * kBlock + threadIdx.x;
+    if (row >= m) return;
+    double s = 0.0;
+    for (int col = 0; col < m; col++) s += Ainv[(int64_t)col * m + row] * rs[col];
+    x[row] = (T)s;
+}
+
+// ---------------------------------------------------------------------------------------
+// Elementwise helpers
+// ---------------------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fill(T *a, int64_t count, T v)
+{
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q < count) a[q] = v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_update_u(double *u, const T *d, int64_t m)
+{
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q < m) u[q] += (double)d[q];
+}
+
+// W_a += dW_a - mean_a (mean: device, 3 values)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_update_W(double *W, const T *d, const double *mean,
+                                                     int64_t m)
+{
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q >= m) return;
+#pragma unroll
+    for (int s = 0; s < 3; s++) W[s * m + q] += (double)d[s * m + q] - mean[s];
+}
+
+// ---------------------------------------------------------------------------------------
+// Scalar-field sources from Fourier modes and the puncture shell.
+// ---------------------------------------------------------------------------------------
+constexpr int kMaxModes = 32;
+struct ModeTable {
+    int nphi, npi;
+    double phi[kMaxModes][5];
+    double pi[kMaxModes][5];
+};
+
+__global__ void __launch_bounds__(kBlock) k_sources_modes(Geo g, double length, ModeTable t,
+                                                          double mass, double *rho5, double *rho1,
+                                                          double *S, double *partials)
+{
+    const int n = g.n;
+    const int64_t m = (int64_t)n * n * n;
+    const double tw = 2.0 * kPi / length;
+    double acc[1] = {0.0};
+    for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < m;
+         q += (int64_t)gridDim.x * kBlock) {
+        int i, j, k;
+        cell_of(q, n, i, j, k);
+        const double x = g.org[0] + (i + 0.5) * g.h, y = g.org[1] + (j + 0.5) * g.h,
+                     z = g.org[2] + (k + 0.5) * g.h;
+        double phi = 0.0, d0 = 0.0, d1 = 0.0, d2 = 0.0, Pi = 0.0;
+        for (int p = 0; p < t.nphi; p++) {
+            const double *md = t.phi[p];
+            double s, c;
+            sincos(tw * (md[0] * x + md[1] * y + md[2] * z) + md[4], &s, &c);
+            phi += md[3] * c;
+            d0 -= md[3] * tw * md[0] * s;
+            d1 -= md[3] * tw * md[1] * s;
+            d2 -= md[3] * tw * md[2] * s;
+        }
+        for (int p = 0; p < t.npi; p++) {
+            const double *md = t.pi[p];
+            Pi += md[3] * cos(tw * (md[0] * x + md[1] * y + md[2] * z) + md[4]);
+        }
+        const double r5 = 0.5 * Pi * Pi + 0.5 * mass * mass * phi * phi;
+        const double r1 = 0.5 * (d0 * d0 + d1 * d1 + d2 * d2);
+        rho5[q] = r5;
+        rho1[q] = r1;
+        S[q] = -Pi * d0;
+        S[m + q] = -Pi * d1;
+        S[2 * m + q] = -Pi * d2;
+        acc[0] += r5 + r1;
+    }
+    if (partials) block_reduce_store<1>(acc, 0u, partials + blockIdx.x);
+}
+
+__global__ void __launch_bounds__(kBlock) k_sources_shell(Geo g, double amp, double r0,
+                                                          double width2, double mass, double *rho5,
+                                                          double *rho1, double *S)
+{
+    const int n = g.n;
+    const int64_t m = (int64_t)n * n * n;
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int i, j, k;
+    if (!cell_of(q, n, i, j, k)) return;
+    const double x[3] = {g.org[0] + (i + 0.5) * g.h - g.ctr[0], g.org[1] + (j + 0.5) * g.h - g.ctr[1],
+                         g.org[2] + (k + 0.5) * g.h - g.ctr[2]};
+    const double r = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    const double ylm = sqrt(3.0 / (4.0 * kPi));
+    const double fr = amp * exp(-(r - r0) * (r - r0) / width2);
+    const double dfr = -2.0 * (r - r0) / width2 * fr;
+    const double phi = fr * ylm * x[0] / r;
+    double g2 = 0.0;
+    for (int a = 0; a < 3; a++) {
+        // d_a [f(r) x/r] = f'(r) (x_a/r)(x/r) + f(r) (delta_a0/r - x x_a/r^3)
+        const double da = ylm * (dfr * (x[a] / r) * (x[0] / r) +
+                                 fr * ((a == 0 ? 1.0 : 0.0) / r - x[0] * x[a] / (r * r * r)));
+        g2 += da * da;
+    }
+    rho5[q] = 0.5 * mass * mass * phi * phi;
+    rho1[q] = 0.5 * g2;
+    S[q] = 0.0;
+    S[m + q] = 0.0;
+    S[2 * m + q] = 0.0;
+}
+
+} // namespace grtmg

@@ -1,0 +1,268 @@
+"""ctypes binding of libgrtmg.so (the C ABI declared in include/grtmg.h).
+
+Argument marshalling only: PyTorch supplies device memory and the current
+HIP stream; every step of the solve runs in the library's HIP kernels.  There
+is no fallback: if the library is missing, importing it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libgrtmg.so")
+
+MG_OK, MG_ERR_INVALID, MG_ERR_WORKSPACE, MG_ERR_HIP = 0, 1, 2, 3
+MG_ERR_NOT_CONVERGED, MG_ERR_DIVERGED, MG_ERR_SINGULAR = 4, 5, 6
+BC_PERIODIC, BC_ROBIN = 0, 1
+PREC_FP64, PREC_FP32_IR = 0, 1
+EQ_PSI, EQ_W, EQ_BOTH = 1, 2, 3
+FLAG_CONFORMAL_MATTER = 1
+OP_PASS_PSI, OP_PASS_W, OP_DEFECT_RESTRICT_PSI, OP_DEFECT_RESTRICT_W = 1, 2, 3, 4
+OP_PROLONG_ADD, OP_COARSE_PSI, OP_COARSE_W = 5, 6, 7
+PROBE_NONE, PROBE_PASS_PSI, PROBE_PASS_W, PROBE_RESIDUAL = 0, 1, 2, 3
+PROBE_DEFECT_RESTRICT_PSI, PROBE_DEFECT_RESTRICT_W, PROBE_PROLONG = 4, 5, 6
+PROBE_COARSE, PROBE_UPDATE = 7, 8
+SOURCES_SCRATCH_BYTES = 32768
+
+
+class MgParams(C.Structure):
+    _fields_ = [("n", C.c_int32), ("levels", C.c_int32), ("bc", C.c_int32),
+                ("precision", C.c_int32), ("nu_pre", C.c_int32), ("nu_post", C.c_int32),
+                ("solve_momentum", C.c_int32), ("flags", C.c_int32),
+                ("length", C.c_double), ("origin", C.c_double * 3), ("K", C.c_double),
+                ("puncture_mass", C.c_double), ("puncture_pos", C.c_double * 3)]
+
+
+class MgReport(C.Structure):
+    _fields_ = [("outer_iters", C.c_int32), ("vcycles_psi", C.c_int32),
+                ("vcycles_W", C.c_int32), ("status", C.c_int32),
+                ("h_rms", C.c_double), ("m_rms", C.c_double), ("h_max", C.c_double),
+                ("m_max", C.c_double), ("seconds", C.c_double),
+                ("history", C.POINTER(C.c_double)), ("history_cap", C.c_int32),
+                ("history_len", C.c_int32)]
+
+
+class MGError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_str(status)} (status {status})")
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        vp, dp, pp = C.c_void_p, C.POINTER(C.c_double), C.POINTER(MgParams)
+        i32, st = C.c_int32, C.c_int
+        L.mg_workspace_size.argtypes = [pp, C.POINTER(C.c_size_t)]
+        L.mg_setup.argtypes = [pp, vp, C.c_size_t, vp, vp, vp, vp, vp, C.POINTER(vp)]
+        L.mg_vcycle.argtypes = [vp, i32, vp, vp]
+        L.mg_solve_constraints.argtypes = [vp, vp, vp, C.c_double, i32, C.POINTER(MgReport)]
+        L.mg_residual_norm.argtypes = [vp, vp, vp, dp]
+        L.mg_residual_fields.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.mg_destroy.argtypes = [vp]
+        L.mg_destroy.restype = None
+        L.mg_status_str.argtypes = [st]
+        L.mg_status_str.restype = C.c_char_p
+        L.mg_scalar_field_sources.argtypes = [pp, i32, dp, i32, dp, C.c_double, vp, vp, vp, vp,
+                                              C.c_size_t, dp, vp]
+        L.mg_shell_field_sources.argtypes = [pp, C.c_double, C.c_double, C.c_double, C.c_double,
+                                             vp, vp, vp, vp]
+        L.mg_interp_cubic.argtypes = [pp, vp, vp, vp]
+        L.mg_kernel_op.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp]
+        L.mg_probe.argtypes = [vp, i32, i32]
+        L.mg_probe_result.argtypes = [vp, C.POINTER(i32), C.POINTER(C.c_double)]
+        for f in ("mg_workspace_size", "mg_setup", "mg_vcycle", "mg_solve_constraints",
+                  "mg_residual_norm", "mg_residual_fields", "mg_scalar_field_sources",
+                  "mg_shell_field_sources", "mg_interp_cubic", "mg_kernel_op", "mg_probe",
+                  "mg_probe_result"):
+            getattr(L, f).restype = st
+        _lib = L
+    return _lib
+
+
+def status_str(s: int) -> str:
+    return lib().mg_status_str(s).decode()
+
+
+def _check(st: int, where: str, ok=(MG_OK,)):
+    if st not in ok:
+        raise MGError(st, where)
+    return st
+
+
+def params(n: int, levels: int = 1, bc: int = BC_PERIODIC, precision: int = PREC_FP64,
+           length: float = 1.0, origin=(0.0, 0.0, 0.0), K: float = 0.0, nu_pre: int = 2,
+           nu_post: int = 2, solve_momentum: bool = False, puncture_mass: float = 0.0,
+           puncture_pos=(0.0, 0.0, 0.0), conformal_matter: bool = False) -> MgParams:
+    p = MgParams()
+    p.n, p.levels, p.bc, p.precision = n, levels, bc, precision
+    p.nu_pre, p.nu_post = nu_pre, nu_post
+    p.solve_momentum = 1 if solve_momentum else 0
+    p.flags = FLAG_CONFORMAL_MATTER if conformal_matter else 0
+    p.length = length
+    for a in range(3):
+        p.origin[a] = origin[a]
+        p.puncture_pos[a] = puncture_pos[a]
+    p.K = K
+    p.puncture_mass = puncture_mass
+    return p
+
+
+def workspace_size(p: MgParams) -> int:
+    b = C.c_size_t(0)
+    _check(lib().mg_workspace_size(C.byref(p), C.byref(b)), "mg_workspace_size")
+    return b.value
+
+
+def _dptr(t: Optional[torch.Tensor], dtype=torch.float64, numel: Optional[int] = None):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError(f"expected a contiguous CUDA tensor of {dtype}, got {t.dtype} on {t.device}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"expected {numel} elements, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(device) -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Solver:
+    """One mg_ctx: borrowed sources, a torch-allocated workspace, the current stream."""
+
+    def __init__(self, p: MgParams, rho5: torch.Tensor, rho1: torch.Tensor,
+                 S: Optional[torch.Tensor] = None, f: Optional[torch.Tensor] = None):
+        self.p = p
+        n = p.n
+        self.cells = n ** 3
+        self.device = rho5.device
+        self.vtype = torch.float32 if p.precision == PREC_FP32_IR else torch.float64
+        self._keep = (rho5, rho1, S, f)
+        nbytes = workspace_size(p)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = _stream(self.device)
+        ctx = C.c_void_p(None)
+        _check(lib().mg_setup(C.byref(p), C.c_void_p(self.ws.data_ptr()), nbytes, self.stream,
+                              _dptr(rho5, numel=self.cells), _dptr(rho1, numel=self.cells),
+                              _dptr(S, numel=3 * self.cells), _dptr(f, numel=self.cells),
+                              C.byref(ctx)), "mg_setup")
+        self.ctx = ctx
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            lib().mg_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _W(self, W):
+        return _dptr(W, numel=3 * self.cells) if W is not None else None
+
+    def vcycle(self, eq: int, u: torch.Tensor, W: Optional[torch.Tensor] = None):
+        _check(lib().mg_vcycle(self.ctx, eq, _dptr(u, numel=self.cells), self._W(W)), "mg_vcycle")
+
+    def solve(self, u: torch.Tensor, W: Optional[torch.Tensor] = None, tol: float = 1e-10,
+              max_outer: int = 100, raise_on_failure: bool = True) -> dict:
+        hist = np.zeros((max_outer + 2, 4))
+        rep = MgReport()
+        rep.history = hist.ctypes.data_as(C.POINTER(C.c_double))
+        rep.history_cap = max_outer + 2
+        st = lib().mg_solve_constraints(self.ctx, _dptr(u, numel=self.cells), self._W(W), tol,
+                                        max_outer, C.byref(rep))
+        out = dict(status=st, outer_iters=rep.outer_iters, vcycles_psi=rep.vcycles_psi,
+                   vcycles_W=rep.vcycles_W, h_rms=rep.h_rms, m_rms=rep.m_rms, h_max=rep.h_max,
+                   m_max=rep.m_max, seconds=rep.seconds, history=hist[: rep.history_len].copy())
+        if raise_on_failure:
+            _check(st, "mg_solve_constraints")
+        return out
+
+    def residual_norm(self, u: torch.Tensor, W: Optional[torch.Tensor] = None) -> np.ndarray:
+        out = np.zeros(4)
+        _check(lib().mg_residual_norm(self.ctx, _dptr(u, numel=self.cells), self._W(W),
+                                      out.ctypes.data_as(C.POINTER(C.c_double))), "mg_residual_norm")
+        return out
+
+    def residual_fields(self, u: torch.Tensor, W: Optional[torch.Tensor] = None, want_M=True):
+        n = self.p.n
+        H = torch.empty((n, n, n), dtype=torch.float64, device=self.device)
+        c = torch.empty_like(H)
+        M = torch.empty((3, n, n, n), dtype=torch.float64, device=self.device) if want_M else None
+        _check(lib().mg_residual_fields(self.ctx, _dptr(u, numel=self.cells), self._W(W),
+                                        _dptr(H), _dptr(M), _dptr(c)), "mg_residual_fields")
+        return H, M, c
+
+    def probe(self, kernel: int, level: int = 0):
+        _check(lib().mg_probe(self.ctx, kernel, level), "mg_probe")
+
+    def probe_result(self):
+        n = C.c_int32(0)
+        ms = C.c_double(0.0)
+        _check(lib().mg_probe_result(self.ctx, C.byref(n), C.byref(ms)), "mg_probe_result")
+        return n.value, ms.value
+
+    def kernel_op(self, op: int, level: int, arg: int, inp, out, r=None, c=None):
+        vt = self.vtype
+        _check(lib().mg_kernel_op(self.ctx, op, level, arg, _dptr(inp, vt), _dptr(out, vt),
+                                  _dptr(r, vt), _dptr(c, vt)), "mg_kernel_op")
+
+
+def scalar_field_sources(p: MgParams, phi_modes: np.ndarray, pi_modes: np.ndarray,
+                         mass: float = 1.0, device="cuda", want_mean=True):
+    n = p.n
+    rho5 = torch.empty((n, n, n), dtype=torch.float64, device=device)
+    rho1 = torch.empty_like(rho5)
+    S = torch.empty((3, n, n, n), dtype=torch.float64, device=device)
+    phi = np.ascontiguousarray(phi_modes, dtype=np.float64).reshape(-1, 5)
+    pim = np.ascontiguousarray(pi_modes, dtype=np.float64).reshape(-1, 5)
+    dp = C.POINTER(C.c_double)
+    mean = C.c_double(0.0)
+    scratch = torch.empty(SOURCES_SCRATCH_BYTES, dtype=torch.uint8, device=device) if want_mean else None
+    _check(lib().mg_scalar_field_sources(
+        C.byref(p), len(phi), phi.ctypes.data_as(dp) if len(phi) else None,
+        len(pim), pim.ctypes.data_as(dp) if len(pim) else None, mass,
+        _dptr(rho5), _dptr(rho1), _dptr(S),
+        C.c_void_p(scratch.data_ptr()) if want_mean else None,
+        SOURCES_SCRATCH_BYTES if want_mean else 0,
+        C.byref(mean) if want_mean else None, _stream(rho5.device)), "mg_scalar_field_sources")
+    return rho5, rho1, S, (mean.value if want_mean else None)
+
+
+def shell_field_sources(p: MgParams, amplitude: float, r0: float, width2: float,
+                        mass: float = 1.0, device="cuda"):
+    n = p.n
+    rho5 = torch.empty((n, n, n), dtype=torch.float64, device=device)
+    rho1 = torch.empty_like(rho5)
+    S = torch.empty((3, n, n, n), dtype=torch.float64, device=device)
+    _check(lib().mg_shell_field_sources(C.byref(p), amplitude, r0, width2, mass, _dptr(rho5),
+                                        _dptr(rho1), _dptr(S), _stream(rho5.device)),
+           "mg_shell_field_sources")
+    return rho5, rho1, S
+
+
+def interp_cubic(pc: MgParams, coarse: torch.Tensor) -> torch.Tensor:
+    nc = pc.n
+    fine = torch.empty((2 * nc,) * 3, dtype=torch.float64, device=coarse.device)
+    _check(lib().mg_interp_cubic(C.byref(pc), _dptr(coarse, numel=nc ** 3), _dptr(fine),
+                                 _stream(coarse.device)), "mg_interp_cubic")
+    return fine
+
+
+def K_from_mean_density(mean_rho: float) -> float:
+    """Constant K with K^2 = 24 pi <rho> at psi = 1 (the periodic workloads)."""
+    return float(np.sqrt(24.0 * np.pi * mean_rho))

@@ -14,7 +14,8 @@ black-hole scenarios, Key features):
 * ``coupled_128``     periodic cube L=1, 128^3, 6 levels, phi: 8 modes of
   amplitude 0.05; Pi: 8 modes of amplitude 0.02 (own stream).
 * ``puncture_shell``  box [-32,32]^3, M=1 puncture at the centre, scalar
-  shell phi = 0.1 exp(-(r-10)^2/4) Y_11, Pi = 0, Robin outer boundary.
+  shell phi = 0.1 exp(-(r-10)^2/4) Y_11, Pi = 0, Robin outer boundary; the
+  shell's density is taken as conformally rescaled free data.
 * ``scan_96``         96 periodic instances, N uniform on {32,48,64,96},
   phi amplitude uniform on [0.01, 0.1], Pi amplitude 0.02.
 
@@ -81,6 +82,8 @@ class Workload:
     puncture_mass: float = 0.0
     puncture_pos: tuple = (0.0, 0.0, 0.0)
     shell: Optional[dict] = None
+    # sources given as conformally rescaled rho_bar = psi^8 rho, S_bar = psi^6 S
+    conformal_matter: bool = False
     seed: Optional[int] = None
     tol: float = 1e-10
 
@@ -125,7 +128,7 @@ def puncture_shell(n: int = 256, precision: int = PREC_FP32_IR,
     return Workload(name=f"puncture_shell_{n}", n=n, levels=levels, length=64.0,
                     origin=(-32.0, -32.0, -32.0), bc=BC_ROBIN, precision=precision,
                     solve_momentum=False, puncture_mass=1.0,
-                    puncture_pos=(0.0, 0.0, 0.0),
+                    puncture_pos=(0.0, 0.0, 0.0), conformal_matter=True,
                     shell=dict(amplitude=0.1, r0=10.0, width2=4.0))
 
 

@@ -1,0 +1,62 @@
+"""Write the stored oracle results used by the full-size GPU parity tests.
+
+Runs only the CPU oracle (oracle/) on the seeded synthetic workloads and
+stores, per workload, the solve statistics and psi / W at a fixed seeded
+sample of cells (the full 128^3 fields are too large to commit).
+
+    python tests/golden/make_golden.py [coupled_128] [puncture_shell_128]
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+
+SAMPLES = 1024
+
+
+def sample_cells(n, seed=2024):
+    rng = np.random.default_rng([seed, n])
+    return rng.integers(0, n, size=(SAMPLES, 3))
+
+
+def run(name):
+    if name == "coupled_128":
+        w = synth.coupled_128(seed=0, precision=synth.PREC_FP64)
+    elif name == "puncture_shell_128":
+        w = synth.puncture_shell(128, precision=synth.PREC_FP64, levels=6)
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    rho5, rho1, S, K = oracle.sources_for(w)
+    p = oracle.params_from_workload(w, K)
+    n = w.n
+    u = np.zeros((n,) * 3)
+    W = np.zeros((3, n, n, n))
+    t0 = time.time()
+    res = oracle.solve(p, u, W, rho5, rho1, S, tol=1e-11, max_outer=80)
+    dt = time.time() - t0
+    assert res.status == 0, res
+    cells = sample_cells(n)
+    i, j, k = cells[:, 0], cells[:, 1], cells[:, 2]
+    Wm = W - W.mean(axis=(1, 2, 3), keepdims=True)
+    out = dict(workload=name, n=n, levels=w.levels, K=K, tol=1e-11, status=res.status,
+               outer_iters=res.iters, seconds=dt, threads=oracle.num_threads(),
+               history=res.history.tolist(), cells=cells.tolist(), u=u[i, j, k].tolist(),
+               W_meanfree=[Wm[a][i, j, k].tolist() for a in range(3)],
+               note="written by tests/golden/make_golden.py from the CPU oracle only")
+    path = os.path.join(HERE, f"{name}.json")
+    with open(path, "w") as f:
+        json.dump(out, f)
+    print(f"{name}: iters={res.iters} time={dt:.1f}s -> {path}", flush=True)
+
+
+if __name__ == "__main__":
+    for nm in (sys.argv[1:] or ["coupled_128", "puncture_shell_128"]):
+        run(nm)

@@ -1,0 +1,166 @@
+"""Kernel-level parity of the HIP path against the CPU oracle (FP64, element by
+element), called through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle import judge
+from paper_2501_13046_amd import grtmg as g
+from gpu_helpers import N, T, dev, gparams, oracle_problem, random_state, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("n", [32, 20])
+def test_scalar_sources_match_oracle(n):
+    w = synth.coupled(n, seed=3)
+    p = gparams(w)
+    rho5, rho1, S, mean = g.scalar_field_sources(p, w.phi_modes, w.pi_modes, w.scalar_mass, dev())
+    o5, o1, oS, K = oracle_problem(w)[:4]
+    for a, b in ((rho5, o5), (rho1, o1), (S, oS)):
+        np.testing.assert_allclose(N(a), b, rtol=0, atol=1e-13 * max(1.0, np.abs(b).max()))
+    assert abs(mean - np.mean(o5 + o1)) <= 1e-14 * np.mean(o5 + o1)
+
+
+def test_shell_sources_match_oracle():
+    w = synth.puncture_shell(64)
+    p = gparams(w)
+    rho5, rho1, S = g.shell_field_sources(p, 0.1, 10.0, 4.0, 1.0, dev())
+    o5, o1, oS, K = oracle_problem(w)[:4]
+    np.testing.assert_allclose(N(rho5), o5, rtol=1e-13, atol=1e-22)
+    np.testing.assert_allclose(N(rho1), o1, rtol=1e-12, atol=1e-22)
+    assert np.all(N(S) == 0.0)
+
+
+@pytest.mark.parametrize("n,levels", [(24, 3), (20, 3)])
+def test_residual_fields_periodic(n, levels):
+    K = 2.7
+    p = g.params(n, levels, K=K, solve_momentum=True)
+    po = oracle.params(n, levels, K=K, solve_momentum=True)
+    u, W = random_state(n, 5)
+    rho5 = synth.uniform_random(7, (n, n, n), 0, 1)
+    rho1 = synth.uniform_random(8, (n, n, n), 0, 1)
+    S = synth.uniform_random(9, (3, n, n, n))
+    f = synth.uniform_random(10, (n, n, n))
+    s = g.Solver(p, T(rho5), T(rho1), T(S), T(f))
+    H, M, c = s.residual_fields(T(u), T(W))
+    Ho, Mo, co = oracle.residuals(po, u, W, rho5, rho1, S, f)
+    assert rel_err(N(H), Ho) < 1e-12
+    assert rel_err(N(M), Mo) < 1e-12
+    assert rel_err(N(c), co) < 1e-13
+    nr = s.residual_norm(T(u), T(W))
+    no = oracle.norms(Ho, Mo)
+    np.testing.assert_allclose(nr, no, rtol=1e-11)
+
+
+def test_residual_fields_robin_puncture():
+    n = 16
+    p = g.params(n, 2, bc=g.BC_ROBIN, length=8.0, origin=(-4, -4, -4), puncture_mass=1.0)
+    po = oracle.params(n, 2, bc=oracle.BC_ROBIN, length=8.0, origin=(-4, -4, -4), puncture_mass=1.0)
+    u, _ = random_state(n, 11)
+    rho5 = synth.uniform_random(12, (n, n, n), 0, 0.1)
+    rho1 = synth.uniform_random(13, (n, n, n), 0, 0.1)
+    s = g.Solver(p, T(rho5), T(rho1))
+    H, _, c = s.residual_fields(T(u), None, want_M=False)
+    Ho, _, co = oracle.residuals(po, u, np.zeros((3, n, n, n)), rho5, rho1, np.zeros((3, n, n, n)))
+    assert rel_err(N(H), Ho) < 1e-12
+    assert rel_err(N(c), co) < 1e-13
+
+
+def _ctx(n, levels, bc=g.BC_PERIODIC, momentum=True):
+    L = 2.0 if bc == g.BC_ROBIN else 1.0
+    org = (-1.0, -1.0, -1.0) if bc == g.BC_ROBIN else (0.0, 0.0, 0.0)
+    p = g.params(n, levels, bc=bc, length=L, origin=org, solve_momentum=momentum and bc == 0)
+    po = oracle.params(n, levels, bc=bc, length=L, origin=org)
+    z = torch.zeros((n, n, n), dtype=torch.float64, device=dev())
+    S = torch.zeros((3, n, n, n), dtype=torch.float64, device=dev())
+    return g.Solver(p, z, z, S), po
+
+
+@pytest.mark.parametrize("bc", [g.BC_PERIODIC, g.BC_ROBIN])
+def test_smoother_and_transfer_ops(bc):
+    n, levels = 16, 3
+    s, po = _ctx(n, levels, bc)
+    d = synth.uniform_random(20, (n, n, n))
+    r = synth.uniform_random(21, (n, n, n))
+    c = -1.0 - synth.uniform_random(22, (n, n, n), 0, 2)
+    for colour in (0, 1):
+        out = torch.empty((n,) * 3, dtype=torch.float64, device=dev())
+        s.kernel_op(g.OP_PASS_PSI, 0, colour, T(d), out, T(r), T(c))
+        ref = oracle.pass_psi(po, d, r, c, colour)
+        assert rel_err(N(out), ref) < 1e-13, colour
+    out = torch.empty((n // 2,) * 3, dtype=torch.float64, device=dev())
+    s.kernel_op(g.OP_DEFECT_RESTRICT_PSI, 0, 0, T(d), out, T(r), T(c))
+    ref = oracle.restrict(np.ascontiguousarray(r - (oracle.apply_lap(po, d) + c * d)))
+    assert rel_err(N(out), ref) < 1e-12
+    coarse = synth.uniform_random(23, (n // 2,) * 3)
+    fine = torch.from_numpy(d.copy()).to(dev())
+    s.kernel_op(g.OP_PROLONG_ADD, 0, 1, T(coarse), fine)
+    ref = oracle.prolong_add(po, coarse, d)
+    assert rel_err(N(fine), ref) < 1e-14
+    # coarsest psi solve
+    nc = n >> (levels - 1)
+    rc = synth.uniform_random(24, (nc,) * 3)
+    cc = -1.0 - synth.uniform_random(25, (nc,) * 3, 0, 2)
+    out = torch.empty((nc,) * 3, dtype=torch.float64, device=dev())
+    s.kernel_op(g.OP_COARSE_PSI, levels - 1, 0, T(rc), out, None, T(cc))
+    pc = oracle.params(nc, 1, bc=po.bc, length=po.length, origin=tuple(po.origin))
+    ref = oracle.coarse_solve_psi(pc, cc, rc)
+    assert rel_err(N(out), ref) < 1e-12
+
+
+def test_momentum_ops():
+    n, levels = 16, 3
+    s, po = _ctx(n, levels)
+    d = synth.uniform_random(30, (3, n, n, n))
+    r = synth.uniform_random(31, (3, n, n, n))
+    for colour in (0, 1):
+        out = torch.empty((3, n, n, n), dtype=torch.float64, device=dev())
+        s.kernel_op(g.OP_PASS_W, 0, colour, T(d), out, T(r))
+        assert rel_err(N(out), oracle.pass_W(po, d, r, colour)) < 1e-13
+    out = torch.empty((3,) + (n // 2,) * 3, dtype=torch.float64, device=dev())
+    s.kernel_op(g.OP_DEFECT_RESTRICT_W, 0, 0, T(d), out, T(r))
+    defect = r - oracle.apply_deltaL(po, d)
+    ref = np.stack([oracle.restrict(np.ascontiguousarray(defect[a])) for a in range(3)])
+    assert rel_err(N(out), ref) < 1e-12
+    coarse = synth.uniform_random(32, (3,) + (n // 2,) * 3)
+    fine = torch.from_numpy(d.copy()).to(dev())
+    s.kernel_op(g.OP_PROLONG_ADD, 0, 3, T(coarse), fine)
+    ref = np.stack([oracle.prolong_add(po, coarse[a], d[a]) for a in range(3)])
+    assert rel_err(N(fine), ref) < 1e-14
+    nc = n >> (levels - 1)
+    rc = synth.uniform_random(33, (3,) + (nc,) * 3)
+    out = torch.empty((3,) + (nc,) * 3, dtype=torch.float64, device=dev())
+    s.kernel_op(g.OP_COARSE_W, levels - 1, 0, T(rc), out)
+    ref = oracle.coarse_solve_W(oracle.params(nc, 1), rc)
+    assert rel_err(N(out), ref) < 1e-11
+
+
+@pytest.mark.parametrize("bc", [g.BC_PERIODIC, g.BC_ROBIN])
+def test_cubic_interp_matches_oracle(bc):
+    nc = 12
+    L = 2.0
+    org = (-1.0, -1.0, -1.0)
+    pc = g.params(nc, 1, bc=bc, length=L, origin=org)
+    po = oracle.params(nc, 1, bc=bc, length=L, origin=org)
+    coarse = synth.uniform_random(40, (nc,) * 3)
+    fine = g.interp_cubic(pc, T(coarse))
+    assert rel_err(N(fine), oracle.interp_cubic(po, coarse)) < 1e-14
+
+
+def test_residual_fields_conformal_matter():
+    n, levels, K = 16, 2, 1.3
+    p = g.params(n, levels, K=K, solve_momentum=True, conformal_matter=True)
+    po = oracle.params(n, levels, K=K, solve_momentum=True, conformal_matter=True)
+    u, W = random_state(n, 50)
+    rho5 = synth.uniform_random(51, (n, n, n), 0, 1)
+    rho1 = synth.uniform_random(52, (n, n, n), 0, 1)
+    S = synth.uniform_random(53, (3, n, n, n))
+    s = g.Solver(p, T(rho5), T(rho1), T(S))
+    H, M, c = s.residual_fields(T(u), T(W))
+    Ho, Mo, co = oracle.residuals(po, u, W, rho5, rho1, S)
+    assert rel_err(N(H), Ho) < 1e-12
+    assert rel_err(N(M), Mo) < 1e-12
+    assert rel_err(N(c), co) < 1e-13

@@ -248,3 +248,39 @@ def test_hamiltonian_32_converges_below_1e11():
     assert judge.norms(H)[0] <= 1e-11
     # psi stays on the positive branch near 1
     assert np.all(np.abs(u) < 0.1)
+
+
+def test_mms_conformal_matter_fourth_order():
+    # rho_bar := (-lap psi + (K^2/12) psi^5 - A2 psi^-7/8) psi^3 / (2 pi) and
+    # S_bar := Delta_L W / (8 pi) make (psi_e, W_e) a solution of the rescaled system
+    x, y, z = sp.symbols("x y z", real=True)
+    tp = 2 * sp.pi
+    psi = 1 + sp.Rational(1, 10) * sp.sin(tp * x) * sp.sin(tp * y) * sp.sin(tp * z)
+    W = [sp.Rational(1, 100) * sp.sin(tp * x) * sp.cos(tp * y),
+         sp.Rational(1, 100) * sp.sin(tp * y) * sp.cos(tp * z),
+         sp.Rational(1, 100) * sp.sin(tp * z) * sp.cos(tp * x)]
+    X = (x, y, z)
+    K2 = 150
+    div = sum(sp.diff(W[a], X[a]) for a in range(3))
+    A2 = sum((sp.diff(W[b], X[a]) + sp.diff(W[a], X[b]) - (sp.Rational(2, 3) * div if a == b else 0)) ** 2
+             for a in range(3) for b in range(3))
+    lap = lambda f: sum(sp.diff(f, v, 2) for v in X)
+    rbar = (-lap(psi) + sp.Rational(K2, 12) * psi ** 5 - A2 * psi ** -7 / 8) * psi ** 3 / (2 * sp.pi)
+    Sb = [(lap(W[a]) + sp.diff(div, X[a]) / 3) / (8 * sp.pi) for a in range(3)]
+    fn = lambda e: sp.lambdify((x, y, z), e, "numpy")
+    f_psi, f_r, f_S = fn(psi), fn(rbar), [fn(s) for s in Sb]
+    errs = []
+    for n in (16, 32):
+        Xc, Yc, Zc = centres(n)
+        p = oracle.params(n, levels=synth.coarsest_levels(n), K=np.sqrt(K2), solve_momentum=True,
+                          conformal_matter=True)
+        S = np.ascontiguousarray(np.stack([f_S[a](Xc, Yc, Zc) * np.ones_like(Xc) for a in range(3)]))
+        # rho_bar split arbitrarily between the two arrays: only the sum enters
+        r = f_r(Xc, Yc, Zc)
+        u = np.zeros((n, n, n))
+        Wd = np.zeros((3, n, n, n))
+        res = oracle.solve(p, u, Wd, np.ascontiguousarray(0.25 * r), np.ascontiguousarray(0.75 * r), S,
+                           tol=1e-11, max_outer=60)
+        assert res.status == 0, res
+        errs.append(np.abs(1.0 + u - f_psi(Xc, Yc, Zc)).max())
+    assert errs[0] / errs[1] > 13.0, errs

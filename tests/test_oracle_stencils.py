@@ -238,3 +238,20 @@ def test_shell_sources_match_symbolic_gradient():
     np.testing.assert_allclose(rho1, f_rho1(X, Y, Z), rtol=1e-12, atol=1e-18)
     np.testing.assert_allclose(rho5, f_phi(X, Y, Z) ** 2 / 2, rtol=1e-12, atol=1e-20)
     assert np.all(S == 0.0)
+
+
+@pytest.mark.parametrize("bc", [judge.BC_PERIODIC, judge.BC_ROBIN])
+def test_judge_sampled_hamiltonian_matches_full(bc):
+    n = 12
+    g = judge.Grid(n, 6.0, bc, (-3, -3, -3))
+    u = 0.05 * RNG.standard_normal((n, n, n))
+    W = 0.02 * RNG.standard_normal((3, n, n, n))
+    rho5 = RNG.uniform(0, 1, (n, n, n))
+    rho1 = RNG.uniform(0, 1, (n, n, n))
+    S = np.zeros((3, n, n, n))
+    cells = RNG.integers(0, n, size=(200, 3))
+    cells[:6] = [[0, 0, 0], [n - 1, n - 1, n - 1], [0, 5, n - 1], [1, 1, 1], [n - 2, 0, 3], [6, 6, 6]]
+    for conf in (False, True):
+        H, _, _ = judge.residuals(g, u, W, rho5, rho1, S, 1.7, 0.5 if bc else 0.0, conformal_matter=conf)
+        Hs = judge.hamiltonian_at(g, u, W, rho5, rho1, 1.7, cells, 0.5 if bc else 0.0, conformal_matter=conf)
+        np.testing.assert_allclose(Hs, H[cells[:, 0], cells[:, 1], cells[:, 2]], rtol=1e-12, atol=1e-12)
