@@ -8,7 +8,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libgrtmg.so")
 SOURCES = [os.path.join(PKG, "csrc", "grtmg.hip")]
-HEADERS = [os.path.join(PKG, "csrc", f) for f in ("mg_device.hpp", "mg_kernels.hpp")] + \
+HEADERS = [os.path.join(PKG, "csrc", f) for f in ("mg_device.hpp", "mg_kernels.hpp", "mg_tiled.hpp")] + \
     [os.path.join(ROOT, "include", "grtmg.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

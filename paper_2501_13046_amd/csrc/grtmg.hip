@@ -16,6 +16,7 @@
 
 #include "grtmg.h"
 #include "mg_kernels.hpp"
+#include "mg_tiled.hpp"
 
 using namespace grtmg;
 
@@ -46,6 +47,8 @@ struct Carver {
 unsigned nblk(int64_t count) { return (unsigned)((count + kBlock - 1) / kBlock); }
 
 constexpr int kProbeMax = 4096;
+constexpr int kBrickPsi = 4; // brick depth along x of the tiled psi smoother
+constexpr int kBrickW = 2;   // brick depth along x of the tiled W smoother
 
 } // namespace
 
@@ -59,6 +62,8 @@ struct mg_ctx {
     int n[kMaxLevels];
     int64_t cells[kMaxLevels];
     Geo geo[kMaxLevels];
+    TileMap tile[kMaxLevels];  // brick map of the psi smoother per level (tx == 0: not tiled)
+    TileMap tileW[kMaxLevels]; // brick map of the W smoother per level
     void *pd0[kMaxLevels], *pd1[kMaxLevels], *pr[kMaxLevels], *pc[kMaxLevels];
     void *wd0[kMaxLevels], *wd1[kMaxLevels], *wr[kMaxLevels];
     double *part;
@@ -151,9 +156,14 @@ void carve(mg_ctx *c, Carver &cv)
 
 void init_geo(mg_ctx *c)
 {
-    for (int l = 0; l < c->L; l++)
+    for (int l = 0; l < c->L; l++) {
         c->geo[l] = make_geo(c->n[l], c->p.bc, c->p.length, c->p.origin, c->p.puncture_pos);
+        c->tile[l] = make_tilemap<kBrickPsi>(c->n[l]);
+        c->tileW[l] = make_tilemap<kBrickW>(c->n[l]);
+    }
 }
+
+unsigned ntiles(const TileMap &t) { return (unsigned)(t.nx * t.ny * t.nz); }
 
 // Records an event pair around the launches in its scope when (kernel, level)
 // matches the probe set by mg_probe.
@@ -195,6 +205,15 @@ void coarse_psi(mg_ctx *c, const T *r, T *x)
     const int l = c->L - 1;
     Probe pr(c, MG_PROBE_COARSE, l);
     const int m = c->m_psi;
+    if (m <= kGjRegMax) {
+        if (c->p.bc == MG_BC_PERIODIC)
+            hipLaunchKernelGGL((k_coarse_psi_reg<kBcPeriodic, T>), dim3(1), dim3(256), 0, c->s, c->geo[l],
+                               (const T *)c->pc[l], r, x, c->scal + S_FLAG_PSI);
+        else
+            hipLaunchKernelGGL((k_coarse_psi_reg<kBcRobin, T>), dim3(1), dim3(256), 0, c->s, c->geo[l],
+                               (const T *)c->pc[l], r, x, c->scal + S_FLAG_PSI);
+        return;
+    }
     fill<double>(c->s, c->A_psi, (int64_t)m * m, 0.0);
     if (c->p.bc == MG_BC_PERIODIC)
         hipLaunchKernelGGL((k_assemble_psi<kBcPeriodic, T>), dim3(nblk(m)), dim3(kBlock), 0, c->s,
@@ -203,8 +222,8 @@ void coarse_psi(mg_ctx *c, const T *r, T *x)
         hipLaunchKernelGGL((k_assemble_psi<kBcRobin, T>), dim3(nblk(m)), dim3(kBlock), 0, c->s,
                            c->geo[l], (const T *)c->pc[l], c->A_psi);
     factor(c->s, c->A_psi, c->aug_psi, c->inv_psi, m, c->scal + S_FLAG_PSI);
-    hipLaunchKernelGGL(k_coarse_apply<T>, dim3(nblk(m)), dim3(kBlock), m * sizeof(double), c->s,
-                       (const double *)c->inv_psi, m, r, x, 0);
+    hipLaunchKernelGGL(k_coarse_apply<T>, dim3((m + kApplyRows - 1) / kApplyRows), dim3(kBlock),
+                       m * sizeof(double), c->s, (const double *)c->inv_psi, m, r, x, 0);
 }
 
 template <typename T>
@@ -212,8 +231,8 @@ void coarse_W(mg_ctx *c, const T *r, T *x)
 {
     const int m = c->m_W;
     Probe pr(c, MG_PROBE_COARSE, c->L - 1);
-    hipLaunchKernelGGL(k_coarse_apply<T>, dim3(nblk(m)), dim3(kBlock), m * sizeof(double), c->s,
-                       (const double *)c->inv_W, m, r, x, 3);
+    hipLaunchKernelGGL(k_coarse_apply<T>, dim3((m + kApplyRows - 1) / kApplyRows), dim3(kBlock),
+                       m * sizeof(double), c->s, (const double *)c->inv_W, m, r, x, 3);
 }
 
 // ---- psi V-cycle ----------------------------------------------------------------------
@@ -224,6 +243,17 @@ void pass_psi(mg_ctx *c, int l, const T *in, T *out, int colour)
     Probe pr(c, MG_PROBE_PASS_PSI, l);
     const Geo &g = c->geo[l];
     const unsigned nb = nblk(c->cells[l]);
+    const TileMap &tm = c->tile[l];
+    if (tm.tx > 0) {
+        const dim3 blk(kLanes, kTY);
+        if (c->p.bc == MG_BC_PERIODIC)
+            hipLaunchKernelGGL((k_pass_psi_tiled<kBcPeriodic, T, kBrickPsi>), dim3(ntiles(tm)), blk, 0, c->s, g,
+                               tm, in, out, (const T *)c->pr[l], (const T *)c->pc[l], colour);
+        else
+            hipLaunchKernelGGL((k_pass_psi_tiled<kBcRobin, T, kBrickPsi>), dim3(ntiles(tm)), blk, 0, c->s, g, tm,
+                               in, out, (const T *)c->pr[l], (const T *)c->pc[l], colour);
+        return;
+    }
     if (c->p.bc == MG_BC_PERIODIC)
         hipLaunchKernelGGL((k_pass_psi<kBcPeriodic, T>), dim3(nb), dim3(kBlock), 0, c->s, g, in, out,
                            (const T *)c->pr[l], (const T *)c->pc[l], colour);
@@ -288,20 +318,24 @@ void vcycle_psi(mg_ctx *c, int l)
 // ---- W V-cycle ------------------------------------------------------------------------
 
 template <typename T>
+void pass_W(mg_ctx *c, int l, const T *in, T *out, const T *r, int colour)
+{
+    Probe pr(c, MG_PROBE_PASS_W, l);
+    const TileMap &tm = c->tileW[l];
+    if (tm.tx > 0)
+        hipLaunchKernelGGL((k_pass_W_tiled<T, kBrickW>), dim3(ntiles(tm)), dim3(kLanes, kTY), 0, c->s, c->geo[l],
+                           tm, in, out, r, colour);
+    else
+        hipLaunchKernelGGL(k_pass_W<T>, dim3(nblk(c->cells[l])), dim3(kBlock), 0, c->s, c->geo[l], in, out, r,
+                           colour);
+}
+
+template <typename T>
 void smooth_W(mg_ctx *c, int l, int sweeps)
 {
-    const unsigned nb = nblk(c->cells[l]);
     for (int s = 0; s < sweeps; s++) {
-        {
-            Probe pr(c, MG_PROBE_PASS_W, l);
-            hipLaunchKernelGGL(k_pass_W<T>, dim3(nb), dim3(kBlock), 0, c->s, c->geo[l],
-                               (const T *)c->wd0[l], (T *)c->wd1[l], (const T *)c->wr[l], 0);
-        }
-        {
-            Probe pr(c, MG_PROBE_PASS_W, l);
-            hipLaunchKernelGGL(k_pass_W<T>, dim3(nb), dim3(kBlock), 0, c->s, c->geo[l],
-                               (const T *)c->wd1[l], (T *)c->wd0[l], (const T *)c->wr[l], 1);
-        }
+        pass_W<T>(c, l, (const T *)c->wd0[l], (T *)c->wd1[l], (const T *)c->wr[l], 0);
+        pass_W<T>(c, l, (const T *)c->wd1[l], (T *)c->wd0[l], (const T *)c->wr[l], 1);
     }
 }
 
@@ -512,21 +546,17 @@ mg_status kernel_op(mg_ctx *c, int op, int l, int arg, const void *in, void *out
     switch (op) {
     case MG_OP_PASS_PSI: {
         if (!in || !out || !r || !cf || (arg != 0 && arg != 1) || coarsest) return MG_ERR_INVALID;
-        const Geo &g = c->geo[l];
-        const unsigned nb = nblk(c->cells[l]);
-        if (c->p.bc == MG_BC_PERIODIC)
-            hipLaunchKernelGGL((k_pass_psi<kBcPeriodic, T>), dim3(nb), dim3(kBlock), 0, c->s, g, (const T *)in,
-                               (T *)out, (const T *)r, (const T *)cf, arg);
-        else
-            hipLaunchKernelGGL((k_pass_psi<kBcRobin, T>), dim3(nb), dim3(kBlock), 0, c->s, g, (const T *)in,
-                               (T *)out, (const T *)r, (const T *)cf, arg);
+        // the pass reads r and c from the context's level buffers: stage the caller's
+        if (hipMemcpyAsync(c->pr[l], r, c->cells[l] * sizeof(T), hipMemcpyDeviceToDevice, c->s) != hipSuccess ||
+            hipMemcpyAsync(c->pc[l], cf, c->cells[l] * sizeof(T), hipMemcpyDeviceToDevice, c->s) != hipSuccess)
+            return MG_ERR_HIP;
+        pass_psi<T>(c, l, (const T *)in, (T *)out, arg);
         break;
     }
     case MG_OP_PASS_W:
         if (!in || !out || !r || (arg != 0 && arg != 1) || c->p.bc != MG_BC_PERIODIC || coarsest)
             return MG_ERR_INVALID;
-        hipLaunchKernelGGL(k_pass_W<T>, dim3(nblk(c->cells[l])), dim3(kBlock), 0, c->s, c->geo[l],
-                           (const T *)in, (T *)out, (const T *)r, arg);
+        pass_W<T>(c, l, (const T *)in, (T *)out, (const T *)r, arg);
         break;
     case MG_OP_DEFECT_RESTRICT_PSI:
         if (!in || !out || !r || !cf || coarsest) return MG_ERR_INVALID;

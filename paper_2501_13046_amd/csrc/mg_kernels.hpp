@@ -570,6 +570,8 @@ __global__ void __launch_bounds__(kGjThreads) k_gauss_jordan(const double *A, do
 }
 
 // x = Ainv (r - mean r per component when ncomp_project > 0), Ainv column-major.
+// Each block covers 64 rows with 4 threads per row (interleaved columns).
+constexpr int kApplyRows = kBlock / 4;
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_coarse_apply(const double *Ainv, int m,
                                                          const T *r, T *x, int ncomp_project)
@@ -589,11 +591,132 @@ __global__ void __launch_bounds__(kBlock) k_coarse_apply(const double *Ainv, int
         for (int q = threadIdx.x; q < m; q += kBlock) rs[q] -= mean[q / cn];
         __syncthreads();
     }
-    const int row = blockIdx.x * kBlock + threadIdx.x;
-    if (row >= m) return;
+    const int row = blockIdx.x * kApplyRows + threadIdx.x / 4;
+    const int part = threadIdx.x % 4;
     double s = 0.0;
-    for (int col = 0; col < m; col++) s += Ainv[(int64_t)col * m + row] * rs[col];
-    x[row] = (T)s;
+    if (row < m)
+        for (int col = part; col < m; col += 4) s += Ainv[(int64_t)col * m + row] * rs[col];
+    s += __shfl_xor(s, 1, kWave);
+    s += __shfl_xor(s, 2, kWave);
+    if (row < m && part == 0) x[row] = (T)s;
+}
+
+// ---------------------------------------------------------------------------------------
+// Fused coarsest-level psi solve: one workgroup assembles [L_h + c | r] and runs
+// Gauss-Jordan elimination with partial pivoting (rows are never swapped: a
+// used-row mask records the pivots), then writes x; *flag = 1 if no non-zero
+// pivot exists.
+// Register-resident for m <= 64 unknowns: 256 threads, 4 per matrix
+// row; thread (row, part) holds columns part, part+4, ... of [A | b] in
+// registers.  Per pivot step only the pivot column and the scaled pivot row
+// pass through LDS.
+constexpr int kGjRegMax = 64;
+constexpr int kGjRegCols = (kGjRegMax + 1 + 3) / 4;
+
+__device__ __forceinline__ double reg_get(const double (&v)[kGjRegCols], int jj)
+{
+    double out = 0.0;
+#pragma unroll
+    for (int j = 0; j < kGjRegCols; j++) out = (j == jj) ? v[j] : out;
+    return out;
+}
+
+__device__ __forceinline__ void reg_add(double (&v)[kGjRegCols], int jj, double val)
+{
+#pragma unroll
+    for (int j = 0; j < kGjRegCols; j++)
+        if (j == jj) v[j] += val;
+}
+
+template <int BC, typename T>
+__global__ void __launch_bounds__(256) k_coarse_psi_reg(Geo g, const T *c, const T *r, T *x,
+                                                        double *flag)
+{
+    const int tid = threadIdx.x, row = tid >> 2, part = tid & 3;
+    const int n = g.n, m = n * n * n, w = m + 1;
+    __shared__ double colk[kGjRegMax], prow[4 * kGjRegCols], rhs[kGjRegMax];
+    __shared__ int used[kGjRegMax], perm[kGjRegMax];
+    __shared__ int piv;
+    double v[kGjRegCols];
+#pragma unroll
+    for (int j = 0; j < kGjRegCols; j++) v[j] = 0.0;
+    if (row < m) {
+        const int k = row % n, j = (row / n) % n, i = row / (n * n);
+        const double wt[5] = {-1.0, 16.0, -30.0, 16.0, -1.0};
+        for (int ax = 0; ax < 3; ax++)
+            for (int d = -2; d <= 2; d++) {
+                int ii = i + (ax == 0 ? d : 0), jj = j + (ax == 1 ? d : 0), kk = k + (ax == 2 ? d : 0);
+                double fac = 1.0;
+                if (BC == kBcPeriodic) {
+                    ii = wrap(ii, n);
+                    jj = wrap(jj, n);
+                    kk = wrap(kk, n);
+                } else if (!((unsigned)ii < (unsigned)n && (unsigned)jj < (unsigned)n &&
+                             (unsigned)kk < (unsigned)n)) {
+                    int bi = clampc(ii, n), bj = clampc(jj, n), bk = clampc(kk, n);
+                    fac = cell_radius(g, bi, bj, bk) / cell_radius(g, ii, jj, kk);
+                    ii = bi;
+                    jj = bj;
+                    kk = bk;
+                }
+                const int col = (ii * n + jj) * n + kk;
+                if ((col & 3) == part) reg_add(v, col >> 2, wt[d + 2] * g.inv12h2 * fac);
+            }
+        if ((row & 3) == part) reg_add(v, row >> 2, (double)c[row]);
+        if ((m & 3) == part) reg_add(v, m >> 2, (double)r[row]);
+    }
+    if (tid < kGjRegMax) used[tid] = 0;
+    __syncthreads();
+    int bad = 0;
+    for (int kc = 0; kc < m; kc++) {
+        if (row < m && part == (kc & 3)) colk[row] = reg_get(v, kc >> 2);
+        __syncthreads();
+        if (tid < kWave) {
+            double best = (tid < m && !used[tid]) ? fabs(colk[tid]) : -1.0;
+            int bi = tid;
+            for (int o = kWave / 2; o > 0; o >>= 1) {
+                double ov = __shfl_xor(best, o, kWave);
+                int oi = __shfl_xor(bi, o, kWave);
+                if (ov > best || (ov == best && oi < bi)) {
+                    best = ov;
+                    bi = oi;
+                }
+            }
+            if (tid == 0) {
+                piv = (best > 0.0) ? bi : -1;
+                if (best > 0.0) {
+                    perm[kc] = bi;
+                    used[bi] = 1;
+                }
+            }
+        }
+        __syncthreads();
+        const int p = piv;
+        if (p < 0) {
+            bad = 1;
+            break;
+        }
+        const double inv = 1.0 / colk[p];
+        if (row == p)
+#pragma unroll
+            for (int j = 0; j < kGjRegCols; j++) prow[part + 4 * j] = v[j] * inv;
+        __syncthreads();
+        if (row < m) {
+            const double f = colk[row];
+#pragma unroll
+            for (int j = 0; j < kGjRegCols; j++) {
+                const int col = part + 4 * j;
+                if (col > kc && col < w) v[j] = (row == p) ? prow[col] : v[j] - f * prow[col];
+            }
+        }
+    }
+    if (bad) {
+        if (tid == 0) *flag = 1.0;
+        return;
+    }
+    if (row < m && part == (m & 3)) rhs[row] = reg_get(v, m >> 2);
+    __syncthreads();
+    if (tid < m) x[tid] = (T)rhs[perm[tid]];
 }
 
 // ---------------------------------------------------------------------------------------

@@ -1,0 +1,66 @@
+"""Element-by-element parity of the 2.5D LDS-tiled finest-level kernels (the
+launch configuration used from 128^3 up) with the CPU oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from paper_2501_13046_amd import grtmg as g
+from gpu_helpers import N, T, dev, rel_err
+
+pytestmark = pytest.mark.gpu
+
+n = 128
+
+
+@pytest.mark.parametrize("precision", [g.PREC_FP64, g.PREC_FP32_IR])
+@pytest.mark.parametrize("bc", [g.BC_PERIODIC, g.BC_ROBIN])
+def test_tiled_psi_pass(precision, bc):
+    L, org = (1.0, (0.0,) * 3) if bc == g.BC_PERIODIC else (64.0, (-32.0,) * 3)
+    p = g.params(n, 6, bc=bc, precision=precision, length=L, origin=org)
+    po = oracle.params(n, 6, bc=bc, length=L, origin=org)
+    z = torch.zeros((n,) * 3, dtype=torch.float64, device=dev())
+    s = g.Solver(p, z, z)
+    d = synth.uniform_random(60, (n,) * 3)
+    r = synth.uniform_random(61, (n,) * 3)
+    c = -1.0 - synth.uniform_random(62, (n,) * 3, 0, 2)
+    vt = s.vtype
+    if vt == torch.float32:  # compare on the same rounded inputs
+        d, r, c = (a.astype(np.float32).astype(np.float64) for a in (d, r, c))
+    tol = 1e-13 if vt == torch.float64 else 2e-6
+    for colour in (0, 1):
+        out = torch.empty((n,) * 3, dtype=vt, device=dev())
+        s.kernel_op(g.OP_PASS_PSI, 0, colour, T(d, vt), out, T(r, vt), T(c, vt))
+        assert rel_err(N(out), oracle.pass_psi(po, d, r, c, colour)) < tol, colour
+
+
+@pytest.mark.parametrize("precision", [g.PREC_FP64, g.PREC_FP32_IR])
+def test_tiled_W_pass(precision):
+    p = g.params(n, 6, precision=precision, solve_momentum=True)
+    po = oracle.params(n, 6)
+    z = torch.zeros((n,) * 3, dtype=torch.float64, device=dev())
+    S = torch.zeros((3, n, n, n), dtype=torch.float64, device=dev())
+    s = g.Solver(p, z, z, S)
+    d = synth.uniform_random(63, (3, n, n, n))
+    r = synth.uniform_random(64, (3, n, n, n))
+    vt = s.vtype
+    if vt == torch.float32:
+        d, r = (a.astype(np.float32).astype(np.float64) for a in (d, r))
+    tol = 1e-13 if vt == torch.float64 else 2e-6
+    for colour in (0, 1):
+        out = torch.empty((3, n, n, n), dtype=vt, device=dev())
+        s.kernel_op(g.OP_PASS_W, 0, colour, T(d, vt), out, T(r, vt))
+        assert rel_err(N(out), oracle.pass_W(po, d, r, colour)) < tol, colour
+
+
+def test_report_lds_limit():
+    import ctypes as C
+    hip = C.CDLL("libamdhip64.so")
+    v = C.c_int(0)
+    # hipDeviceAttributeMaxSharedMemoryPerBlock
+    for name, attr in (("max_shared_per_block", 74), ("max_shared_per_multiprocessor", 10002)):
+        rc = hip.hipDeviceGetAttribute(C.byref(v), attr, 0)
+        print(f"{name} (attr {attr}): rc={rc} value={v.value}")
+    props = torch.cuda.get_device_properties(0)
+    print("torch props:", {k: getattr(props, k) for k in dir(props) if "shared" in k or "multi" in k})
