@@ -32,9 +32,15 @@
  *    owns the host-side mg_ctx until mg_destroy, plus a few bytes of pinned
  *    host memory per context for the norms.
  *  - Source arrays passed to mg_setup are borrowed and must outlive the ctx.
- *  - All work is enqueued on the HIP stream given at setup (a hipStream_t
- *    passed as void*; NULL means the default stream).  Calls that return host
- *    scalars (norms, reports) synchronise that stream.
+ *  - All work is ordered on the HIP stream given at setup (a hipStream_t
+ *    passed as void*; NULL means the default stream): each call waits for
+ *    the work already on that stream and that stream waits for the call's
+ *    work.  Internally a context runs on two streams of its own (created at
+ *    setup with default priority): the main stream, whose outer-iteration
+ *    body is captured once into a hipGraph and replayed, and a side stream
+ *    that restricts the Newton coefficient and inverts the coarsest psi
+ *    operator while the main stream smooths.  Calls that return host scalars
+ *    (norms, reports) wait for the context's own work only.
  *  - No call throws.  Arguments are validated before any HIP call; a non-OK
  *    status leaves device arrays untouched unless stated otherwise.
  */
@@ -61,7 +67,7 @@ typedef enum mg_status {
 enum { MG_BC_PERIODIC = 0, MG_BC_ROBIN = 1 };
 enum { MG_PREC_FP64 = 0, MG_PREC_FP32_IR = 1 };
 enum { MG_EQ_PSI = 1, MG_EQ_W = 2, MG_EQ_BOTH = 3 };
-enum { MG_FLAG_CONFORMAL_MATTER = 1 };
+enum { MG_FLAG_CONFORMAL_MATTER = 1, MG_FLAG_EAGER = 2 };
 
 /*
  * Problem and solver parameters.
@@ -81,7 +87,9 @@ enum { MG_FLAG_CONFORMAL_MATTER = 1 };
  *                 rho5 + rho1) and S_bar = psi^6 S; H_h then carries
  *                 2 pi rho_bar psi^-3 and M_h the source 8 pi S_bar (the
  *                 textbook CTT rescaling that keeps dH_h/dpsi negative).
- *                 Other bits must be 0.
+ *                 bit MG_FLAG_EAGER: launch every kernel from the host instead
+ *                 of replaying the captured outer-iteration graph (results are
+ *                 identical; for measurement and tests).  Other bits must be 0.
  *  length, origin box side L and corner of the box (cell centres at
  *                 origin + (i + 1/2) L/n).
  *  K              constant trace of the extrinsic curvature.

@@ -49,12 +49,16 @@ unsigned nblk(int64_t count) { return (unsigned)((count + kBlock - 1) / kBlock);
 constexpr int kProbeMax = 4096;
 constexpr int kBrickPsi = 4; // brick depth along x of the tiled psi smoother
 constexpr int kBrickW = 2;   // brick depth along x of the tiled W smoother
+constexpr int kBrickR = 2;   // brick depth along x of the tiled residual
 
 } // namespace
 
 struct mg_ctx {
     mg_params p;
-    hipStream_t s;
+    hipStream_t user_s; // the caller's stream: every call is ordered after / before it by events
+    hipStream_t s;      // internal main stream (captured into the outer-iteration graph)
+    hipStream_t side;   // internal side stream: coefficient restriction and coarse inverse
+    hipEvent_t ev_in, ev_out, ev_fork, ev_gj, ev_c[16];
     int L;
     bool f32;
     bool momentum;
@@ -64,6 +68,7 @@ struct mg_ctx {
     Geo geo[kMaxLevels];
     TileMap tile[kMaxLevels];  // brick map of the psi smoother per level (tx == 0: not tiled)
     TileMap tileW[kMaxLevels]; // brick map of the W smoother per level
+    TileMap tileR;             // brick map of the finest-level residual
     void *pd0[kMaxLevels], *pd1[kMaxLevels], *pr[kMaxLevels], *pc[kMaxLevels];
     void *wd0[kMaxLevels], *wd1[kMaxLevels], *wr[kMaxLevels];
     double *part;
@@ -75,6 +80,9 @@ struct mg_ctx {
     const double *rho5, *rho1, *S, *f;
     double K2;
     int vc_psi, vc_W;
+    // outer-iteration graph (keyed by the state pointers it was captured for)
+    hipGraphExec_t gexec;
+    const double *g_u, *g_W;
     // timing probe
     int probe_kernel, probe_level, probe_count;
     hipEvent_t *probe_ev; // 2 * kProbeMax events, created on first use
@@ -94,7 +102,7 @@ mg_status validate(const mg_params *p)
         return MG_ERR_INVALID;
     if (p->solve_momentum != 0 && p->solve_momentum != 1) return MG_ERR_INVALID;
     if (p->solve_momentum && p->bc != MG_BC_PERIODIC) return MG_ERR_INVALID;
-    if ((p->flags & ~MG_FLAG_CONFORMAL_MATTER) != 0) return MG_ERR_INVALID;
+    if ((p->flags & ~(MG_FLAG_CONFORMAL_MATTER | MG_FLAG_EAGER)) != 0) return MG_ERR_INVALID;
     if (!(p->length > 0.0) || !std::isfinite(p->length)) return MG_ERR_INVALID;
     if (!std::isfinite(p->K) || !(p->puncture_mass >= 0.0) || !std::isfinite(p->puncture_mass))
         return MG_ERR_INVALID;
@@ -161,6 +169,7 @@ void init_geo(mg_ctx *c)
         c->tile[l] = make_tilemap<kBrickPsi>(c->n[l]);
         c->tileW[l] = make_tilemap<kBrickW>(c->n[l]);
     }
+    c->tileR = make_rtilemap<kBrickR>(c->n[0]);
 }
 
 unsigned ntiles(const TileMap &t) { return (unsigned)(t.nx * t.ny * t.nz); }
@@ -199,19 +208,33 @@ void factor(hipStream_t s, double *A, double *aug, double *inv, int m, double *f
                        m, flag);
 }
 
+// Coarsest sizes solved by the single-wavefront Gauss-Jordan kernel.
+bool wave_solvable(int m) { return m == 8 || m == 27 || m == 64; }
+
+template <int BC, typename T>
+void launch_coarse_wave(mg_ctx *c, int l, const T *r, T *x)
+{
+    const Geo &g = c->geo[l];
+    const T *cf = (const T *)c->pc[l];
+    double *flag = c->scal + S_FLAG_PSI;
+    switch (c->m_psi) {
+    case 8: hipLaunchKernelGGL((k_coarse_psi_wave<BC, T, 8>), dim3(1), dim3(kWave), 0, c->s, g, cf, r, x, flag); break;
+    case 27: hipLaunchKernelGGL((k_coarse_psi_wave<BC, T, 27>), dim3(1), dim3(kWave), 0, c->s, g, cf, r, x, flag); break;
+    default: hipLaunchKernelGGL((k_coarse_psi_wave<BC, T, 64>), dim3(1), dim3(kWave), 0, c->s, g, cf, r, x, flag); break;
+    }
+}
+
 template <typename T>
 void coarse_psi(mg_ctx *c, const T *r, T *x)
 {
     const int l = c->L - 1;
     Probe pr(c, MG_PROBE_COARSE, l);
     const int m = c->m_psi;
-    if (m <= kGjRegMax) {
+    if (wave_solvable(m)) {
         if (c->p.bc == MG_BC_PERIODIC)
-            hipLaunchKernelGGL((k_coarse_psi_reg<kBcPeriodic, T>), dim3(1), dim3(256), 0, c->s, c->geo[l],
-                               (const T *)c->pc[l], r, x, c->scal + S_FLAG_PSI);
+            launch_coarse_wave<kBcPeriodic, T>(c, l, r, x);
         else
-            hipLaunchKernelGGL((k_coarse_psi_reg<kBcRobin, T>), dim3(1), dim3(256), 0, c->s, c->geo[l],
-                               (const T *)c->pc[l], r, x, c->scal + S_FLAG_PSI);
+            launch_coarse_wave<kBcRobin, T>(c, l, r, x);
         return;
     }
     fill<double>(c->s, c->A_psi, (int64_t)m * m, 0.0);
@@ -299,17 +322,59 @@ void prolong_add(mg_ctx *c, int lc, const T *coarse, T *fine, int ncomp)
                            fine, ncomp);
 }
 
+// Side stream, forked after the residual wrote the finest c: restrict c level by
+// level (event per level) and invert the coarsest operator (event ev_gj), while
+// the main stream smooths the finer levels.
+template <typename T>
+void fork_coefficients(mg_ctx *c)
+{
+    (void)hipEventRecord(c->ev_fork, c->s);
+    (void)hipStreamWaitEvent(c->side, c->ev_fork, 0);
+    for (int l = 0; l + 1 < c->L; l++) {
+        hipLaunchKernelGGL(k_restrict<T>, dim3(nblk(c->cells[l + 1])), dim3(kBlock), 0, c->side, c->n[l],
+                           (const T *)c->pc[l], (T *)c->pc[l + 1]);
+        (void)hipEventRecord(c->ev_c[l + 1], c->side);
+    }
+    const int l = c->L - 1;
+    const int m = c->m_psi;
+    if (wave_solvable(m)) {
+        // solved directly at the bottom of the V-cycle (coarse_psi)
+    } else {
+        fill<double>(c->side, c->A_psi, (int64_t)m * m, 0.0);
+        if (c->p.bc == MG_BC_PERIODIC)
+            hipLaunchKernelGGL((k_assemble_psi<kBcPeriodic, T>), dim3(nblk(m)), dim3(kBlock), 0, c->side,
+                               c->geo[l], (const T *)c->pc[l], c->A_psi);
+        else
+            hipLaunchKernelGGL((k_assemble_psi<kBcRobin, T>), dim3(nblk(m)), dim3(kBlock), 0, c->side, c->geo[l],
+                               (const T *)c->pc[l], c->A_psi);
+        factor(c->side, c->A_psi, c->aug_psi, c->inv_psi, m, c->scal + S_FLAG_PSI);
+    }
+    (void)hipEventRecord(c->ev_gj, c->side);
+}
+
+// psi V-cycle on level l; the coefficients of levels > 0 and the coarsest
+// inverse come from fork_coefficients.
 template <typename T>
 void vcycle_psi(mg_ctx *c, int l)
 {
     if (l == c->L - 1) {
-        coarse_psi<T>(c, (const T *)c->pr[l], (T *)c->pd0[l]);
+        (void)hipStreamWaitEvent(c->s, c->ev_gj, 0);
+        const int m = c->m_psi;
+        if (wave_solvable(m)) {
+            coarse_psi<T>(c, (const T *)c->pr[l], (T *)c->pd0[l]);
+            return;
+        }
+        Probe pr(c, MG_PROBE_COARSE, l);
+        hipLaunchKernelGGL(k_coarse_apply<T>, dim3((m + kApplyRows - 1) / kApplyRows), dim3(kBlock),
+                           m * sizeof(double), c->s, (const double *)c->inv_psi, m, (const T *)c->pr[l],
+                           (T *)c->pd0[l], 0);
         return;
     }
+    if (l > 0) (void)hipStreamWaitEvent(c->s, c->ev_c[l], 0);
     fill<T>(c->s, (T *)c->pd0[l], c->cells[l], T(0));
     smooth_psi<T>(c, l, c->p.nu_pre);
     defect_restrict_psi<T>(c, l, (const T *)c->pd0[l], (const T *)c->pr[l], (const T *)c->pc[l],
-                           (T *)c->pr[l + 1], (T *)c->pc[l + 1]);
+                           (T *)c->pr[l + 1], nullptr);
     vcycle_psi<T>(c, l + 1);
     prolong_add<T>(c, l + 1, (const T *)c->pd0[l + 1], (T *)c->pd0[l], 1);
     smooth_psi<T>(c, l, c->p.nu_post);
@@ -398,10 +463,29 @@ void residual(mg_ctx *c, const double *u, const double *W, bool want_M, double *
     a.partials = norms ? c->part : nullptr;
     a.want_M = want_M ? 1 : 0;
     a.conformal = (c->p.flags & MG_FLAG_CONFORMAL_MATTER) ? 1 : 0;
-    const int64_t nb = nblk(c->cells[0]);
+    int64_t nb = nblk(c->cells[0]);
     {
         Probe pr(c, MG_PROBE_RESIDUAL, 0);
-        if (c->p.bc == MG_BC_PERIODIC)
+        const TileMap &tm = c->tileR;
+        if (tm.tx > 0) {
+            nb = ntiles(tm);
+            const dim3 blk(kLanes, kTY);
+            if (c->p.bc == MG_BC_PERIODIC) {
+                if (W)
+                    hipLaunchKernelGGL((k_residual_tiled<kBcPeriodic, T, kBrickR, true>), dim3(nb), blk, 0, c->s,
+                                       c->geo[0], tm, a);
+                else
+                    hipLaunchKernelGGL((k_residual_tiled<kBcPeriodic, T, kBrickR, false>), dim3(nb), blk, 0, c->s,
+                                       c->geo[0], tm, a);
+            } else {
+                if (W)
+                    hipLaunchKernelGGL((k_residual_tiled<kBcRobin, T, kBrickR, true>), dim3(nb), blk, 0, c->s,
+                                       c->geo[0], tm, a);
+                else
+                    hipLaunchKernelGGL((k_residual_tiled<kBcRobin, T, kBrickR, false>), dim3(nb), blk, 0, c->s,
+                                       c->geo[0], tm, a);
+            }
+        } else if (c->p.bc == MG_BC_PERIODIC)
             hipLaunchKernelGGL((k_residual<kBcPeriodic, T>), dim3(nb), dim3(kBlock), 0, c->s, c->geo[0], a);
         else
             hipLaunchKernelGGL((k_residual<kBcRobin, T>), dim3(nb), dim3(kBlock), 0, c->s, c->geo[0], a);
@@ -437,6 +521,7 @@ void step_psi(mg_ctx *c, double *u, const double *W, bool residual_done)
 {
     if (!residual_done)
         residual<T>(c, u, W, false, nullptr, nullptr, nullptr, c->pr[0], c->pc[0], nullptr, false);
+    fork_coefficients<T>(c);
     vcycle_psi<T>(c, 0);
     const int64_t m = c->cells[0];
     {
@@ -467,6 +552,62 @@ mg_status fetch_norms(mg_ctx *c, double out[4], double *flag_psi)
     return MG_OK;
 }
 
+// Evaluation of a state: norms (+ the residual the next update step uses).
+template <typename T>
+void evaluate(mg_ctx *c, const double *u, const double *W, bool want_M)
+{
+    source_mean(c, u);
+    if (c->momentum)
+        residual<T>(c, u, W, true, nullptr, nullptr, nullptr, nullptr, nullptr, c->wr[0], true);
+    else
+        residual<T>(c, u, W, want_M, nullptr, nullptr, nullptr, c->pr[0], c->pc[0], nullptr, true);
+}
+
+// One outer update (W step, psi step) followed by the evaluation of the new state.
+template <typename T>
+void outer_body(mg_ctx *c, double *u, double *W, bool want_M)
+{
+    if (c->momentum) {
+        step_W<T>(c, u, W, true);
+        step_psi<T>(c, u, W, false);
+    } else {
+        step_psi<T>(c, u, W, true);
+    }
+    evaluate<T>(c, u, W, want_M);
+}
+
+void drop_graph(mg_ctx *c)
+{
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+    c->g_u = c->g_W = nullptr;
+}
+
+// Capture outer_body for (u, W) into an executable graph (reused while the
+// state pointers stay the same).
+template <typename T>
+mg_status capture_body(mg_ctx *c, double *u, double *W, bool want_M)
+{
+    if (c->gexec && c->g_u == u && c->g_W == W) return MG_OK;
+    drop_graph(c);
+    if (hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal) != hipSuccess) return MG_ERR_HIP;
+    const int vp = c->vc_psi, vw = c->vc_W;
+    outer_body<T>(c, u, W, want_M);
+    c->vc_psi = vp;
+    c->vc_W = vw;
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(c->s, &g) != hipSuccess || !g) return MG_ERR_HIP;
+    hipError_t e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        c->gexec = nullptr;
+        return MG_ERR_HIP;
+    }
+    c->g_u = u;
+    c->g_W = W;
+    return MG_OK;
+}
+
 template <typename T>
 mg_status solve(mg_ctx *c, double *u, double *W, double tol, int max_outer, mg_report *rep)
 {
@@ -477,13 +618,11 @@ mg_status solve(mg_ctx *c, double *u, double *W, double tol, int max_outer, mg_r
     int it = 0, hist_len = 0;
     const bool mom = c->momentum;
     const bool want_M = mom || (c->S != nullptr && W != nullptr);
+    // graphs replay fixed launch parameters; the probe needs eager launches
+    const bool graph = !(c->p.flags & MG_FLAG_EAGER) && c->probe_kernel == MG_PROBE_NONE;
     fill<double>(c->s, c->scal + S_FLAG_PSI, 2, 0.0);
+    evaluate<T>(c, u, W, want_M);
     for (;; it++) {
-        source_mean(c, u);
-        if (mom)
-            residual<T>(c, u, W, true, nullptr, nullptr, nullptr, nullptr, nullptr, c->wr[0], true);
-        else
-            residual<T>(c, u, W, want_M, nullptr, nullptr, nullptr, c->pr[0], c->pc[0], nullptr, true);
         double flag = 0.0;
         if (hip_status() != MG_OK) return MG_ERR_HIP;
         mg_status fs = fetch_norms(c, nr, &flag);
@@ -514,11 +653,14 @@ mg_status solve(mg_ctx *c, double *u, double *W, double tol, int max_outer, mg_r
             st = MG_ERR_NOT_CONVERGED;
             break;
         }
-        if (mom) {
-            step_W<T>(c, u, W, true);
-            step_psi<T>(c, u, W, false);
+        if (graph) {
+            mg_status gs = capture_body<T>(c, u, W, want_M);
+            if (gs != MG_OK) return gs;
+            if (hipGraphLaunch(c->gexec, c->s) != hipSuccess) return MG_ERR_HIP;
+            c->vc_psi++;
+            if (mom) c->vc_W++;
         } else {
-            step_psi<T>(c, u, W, true);
+            outer_body<T>(c, u, W, want_M);
         }
     }
     auto t1 = std::chrono::steady_clock::now();
@@ -535,6 +677,52 @@ mg_status solve(mg_ctx *c, double *u, double *W, double tol, int max_outer, mg_r
         rep->history_len = hist_len;
     }
     return st;
+}
+
+// Order the internal streams after the caller's stream (enter) and the
+// caller's stream after the internal main stream (leave).
+void enter(mg_ctx *c)
+{
+    (void)hipEventRecord(c->ev_in, c->user_s);
+    (void)hipStreamWaitEvent(c->s, c->ev_in, 0);
+}
+
+void leave(mg_ctx *c)
+{
+    (void)hipEventRecord(c->ev_out, c->s);
+    (void)hipStreamWaitEvent(c->user_s, c->ev_out, 0);
+}
+
+void release(mg_ctx *c)
+{
+    drop_graph(c);
+    if (c->s) (void)hipStreamSynchronize(c->s);
+    if (c->side) (void)hipStreamSynchronize(c->side);
+    hipEvent_t *evs[] = {&c->ev_in, &c->ev_out, &c->ev_fork, &c->ev_gj};
+    for (hipEvent_t *e : evs)
+        if (*e) (void)hipEventDestroy(*e);
+    for (int l = 0; l < 16; l++)
+        if (c->ev_c[l]) (void)hipEventDestroy(c->ev_c[l]);
+    if (c->s) (void)hipStreamDestroy(c->s);
+    if (c->side) (void)hipStreamDestroy(c->side);
+    if (c->hpin) (void)hipHostFree(c->hpin);
+    if (c->probe_ev) {
+        for (int q = 0; q < 2 * kProbeMax; q++) (void)hipEventDestroy(c->probe_ev[q]);
+        delete[] c->probe_ev;
+    }
+    delete c;
+}
+
+mg_status create_streams(mg_ctx *c)
+{
+    if (hipStreamCreateWithFlags(&c->s, hipStreamNonBlocking) != hipSuccess) return MG_ERR_HIP;
+    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) return MG_ERR_HIP;
+    hipEvent_t *evs[] = {&c->ev_in, &c->ev_out, &c->ev_fork, &c->ev_gj};
+    for (hipEvent_t *e : evs)
+        if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) return MG_ERR_HIP;
+    for (int l = 0; l < 16; l++)
+        if (hipEventCreateWithFlags(&c->ev_c[l], hipEventDisableTiming) != hipSuccess) return MG_ERR_HIP;
+    return MG_OK;
 }
 
 template <typename T>
@@ -633,7 +821,7 @@ mg_status mg_setup(const mg_params *p, void *d_workspace, size_t bytes, void *st
     if (!c) return MG_ERR_INVALID;
     std::memset(c, 0, sizeof(*c));
     c->p = *p;
-    c->s = (hipStream_t)stream;
+    c->user_s = (hipStream_t)stream;
     c->L = p->levels;
     c->f32 = p->precision == MG_PREC_FP32_IR;
     c->esz = c->f32 ? sizeof(float) : sizeof(double);
@@ -646,10 +834,12 @@ mg_status mg_setup(const mg_params *p, void *d_workspace, size_t bytes, void *st
     Carver cv{(char *)d_workspace};
     carve(c, cv);
     init_geo(c);
-    if (hipHostMalloc((void **)&c->hpin, S_COUNT * sizeof(double), hipHostMallocDefault) != hipSuccess) {
-        delete c;
+    if (create_streams(c) != MG_OK ||
+        hipHostMalloc((void **)&c->hpin, S_COUNT * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        release(c);
         return MG_ERR_HIP;
     }
+    enter(c);
     fill<double>(c->s, c->scal, S_COUNT, 0.0);
     if (c->momentum) {
         const int m = c->m_W;
@@ -659,21 +849,19 @@ mg_status mg_setup(const mg_params *p, void *d_workspace, size_t bytes, void *st
         if (hipMemcpyAsync(c->hpin, c->scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, c->s) !=
                 hipSuccess ||
             hipStreamSynchronize(c->s) != hipSuccess) {
-            (void)hipHostFree(c->hpin);
-            delete c;
+            release(c);
             return MG_ERR_HIP;
         }
         if (c->hpin[S_FLAG_W] != 0.0) {
-            (void)hipHostFree(c->hpin);
-            delete c;
+            release(c);
             return MG_ERR_SINGULAR;
         }
     }
     if (hip_status() != MG_OK) {
-        (void)hipHostFree(c->hpin);
-        delete c;
+        release(c);
         return MG_ERR_HIP;
     }
+    leave(c);
     *out = c;
     return MG_OK;
 }
@@ -682,6 +870,7 @@ mg_status mg_vcycle(mg_ctx *c, int32_t eq, double *d_u, double *d_W)
 {
     if (!c || !d_u || eq < 1 || eq > 3) return MG_ERR_INVALID;
     if ((eq & MG_EQ_W) && (!c->momentum || !d_W)) return MG_ERR_INVALID;
+    enter(c);
     if (c->f32) {
         if (eq & MG_EQ_W) step_W<float>(c, d_u, d_W, false);
         if (eq & MG_EQ_PSI) step_psi<float>(c, d_u, d_W, false);
@@ -689,6 +878,7 @@ mg_status mg_vcycle(mg_ctx *c, int32_t eq, double *d_u, double *d_W)
         if (eq & MG_EQ_W) step_W<double>(c, d_u, d_W, false);
         if (eq & MG_EQ_PSI) step_psi<double>(c, d_u, d_W, false);
     }
+    leave(c);
     return hip_status();
 }
 
@@ -698,21 +888,27 @@ mg_status mg_solve_constraints(mg_ctx *c, double *d_u, double *d_W, double tol, 
     if (!c || !d_u || !(tol > 0.0) || max_outer < 0) return MG_ERR_INVALID;
     if (c->momentum && !d_W) return MG_ERR_INVALID;
     if (rep && rep->history && rep->history_cap < 0) return MG_ERR_INVALID;
-    return c->f32 ? solve<float>(c, d_u, d_W, tol, max_outer, rep)
-                  : solve<double>(c, d_u, d_W, tol, max_outer, rep);
+    enter(c);
+    mg_status st = c->f32 ? solve<float>(c, d_u, d_W, tol, max_outer, rep)
+                          : solve<double>(c, d_u, d_W, tol, max_outer, rep);
+    leave(c);
+    return st;
 }
 
 mg_status mg_residual_norm(mg_ctx *c, const double *d_u, const double *d_W, double out[4])
 {
     if (!c || !d_u || !out) return MG_ERR_INVALID;
     const bool want_M = c->S != nullptr;
+    enter(c);
     source_mean(c, d_u);
     if (c->f32)
         residual<float>(c, d_u, d_W, want_M, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, true);
     else
         residual<double>(c, d_u, d_W, want_M, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, true);
     if (hip_status() != MG_OK) return MG_ERR_HIP;
-    return fetch_norms(c, out, nullptr);
+    mg_status st = fetch_norms(c, out, nullptr);
+    leave(c);
+    return st;
 }
 
 mg_status mg_residual_fields(mg_ctx *c, const double *d_u, const double *d_W, double *d_H, double *d_M,
@@ -721,20 +917,17 @@ mg_status mg_residual_fields(mg_ctx *c, const double *d_u, const double *d_W, do
     if (!c || !d_u) return MG_ERR_INVALID;
     const bool want_M = d_M != nullptr;
     if (want_M && !c->S) return MG_ERR_INVALID;
+    enter(c);
     source_mean(c, d_u);
     residual<double>(c, d_u, d_W, want_M, d_H, d_M, d_c, nullptr, nullptr, nullptr, false);
+    leave(c);
     return hip_status();
 }
 
 void mg_destroy(mg_ctx *c)
 {
     if (!c) return;
-    if (c->hpin) (void)hipHostFree(c->hpin);
-    if (c->probe_ev) {
-        for (int q = 0; q < 2 * kProbeMax; q++) (void)hipEventDestroy(c->probe_ev[q]);
-        delete[] c->probe_ev;
-    }
-    delete c;
+    release(c);
 }
 
 mg_status mg_probe(mg_ctx *c, int32_t kernel, int32_t level)
@@ -862,8 +1055,11 @@ mg_status mg_kernel_op(mg_ctx *c, int32_t op, int32_t level, int32_t arg, const 
                        const void *d_r, const void *d_c)
 {
     if (!c) return MG_ERR_INVALID;
-    return c->f32 ? kernel_op<float>(c, op, level, arg, d_in, d_out, d_r, d_c)
-                  : kernel_op<double>(c, op, level, arg, d_in, d_out, d_r, d_c);
+    enter(c);
+    mg_status st = c->f32 ? kernel_op<float>(c, op, level, arg, d_in, d_out, d_r, d_c)
+                          : kernel_op<double>(c, op, level, arg, d_in, d_out, d_r, d_c);
+    leave(c);
+    return st;
 }
 
 } // extern "C"

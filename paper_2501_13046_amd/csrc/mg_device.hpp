@@ -204,13 +204,15 @@ __device__ __forceinline__ double wave_max(double v)
 }
 
 // Deterministic block reduction of NV values (bit v of max_mask set: max,
-// else sum); thread 0 writes the block's results to out[0..NV).
+// else sum) over a block of kBlock threads (1D or 2D); thread 0 writes the
+// block's results to out[0..NV).
 template <int NV>
 __device__ __forceinline__ void block_reduce_store(double (&v)[NV], unsigned max_mask,
                                                    double *out)
 {
     __shared__ double sh[NV][kBlock / kWave];
-    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+    const int lane = tid % kWave, wid = tid / kWave;
 #pragma unroll
     for (int q = 0; q < NV; q++) v[q] = ((max_mask >> q) & 1u) ? wave_max(v[q]) : wave_sum(v[q]);
     if (lane == 0) {
@@ -218,7 +220,7 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[NV], unsigned max
         for (int q = 0; q < NV; q++) sh[q][wid] = v[q];
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
 #pragma unroll
         for (int q = 0; q < NV; q++) {
             double a = sh[q][0];

@@ -570,8 +570,9 @@ __global__ void __launch_bounds__(kGjThreads) k_gauss_jordan(const double *A, do
 }
 
 // x = Ainv (r - mean r per component when ncomp_project > 0), Ainv column-major.
-// Each block covers 64 rows with 4 threads per row (interleaved columns).
-constexpr int kApplyRows = kBlock / 4;
+// Each block covers 16 rows with 16 threads per row (interleaved columns).
+constexpr int kApplySplit = 16;
+constexpr int kApplyRows = kBlock / kApplySplit;
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_coarse_apply(const double *Ainv, int m,
                                                          const T *r, T *x, int ncomp_project)
@@ -591,57 +592,67 @@ __global__ void __launch_bounds__(kBlock) k_coarse_apply(const double *Ainv, int
         for (int q = threadIdx.x; q < m; q += kBlock) rs[q] -= mean[q / cn];
         __syncthreads();
     }
-    const int row = blockIdx.x * kApplyRows + threadIdx.x / 4;
-    const int part = threadIdx.x % 4;
+    const int row = blockIdx.x * kApplyRows + threadIdx.x % kApplyRows;
+    const int part = threadIdx.x / kApplyRows;
     double s = 0.0;
     if (row < m)
-        for (int col = part; col < m; col += 4) s += Ainv[(int64_t)col * m + row] * rs[col];
-    s += __shfl_xor(s, 1, kWave);
-    s += __shfl_xor(s, 2, kWave);
-    if (row < m && part == 0) x[row] = (T)s;
+        for (int col = part; col < m; col += kApplySplit) s += Ainv[(int64_t)col * m + row] * rs[col];
+    __shared__ double red[kApplySplit][kApplyRows];
+    red[part][threadIdx.x % kApplyRows] = s;
+    __syncthreads();
+    if (threadIdx.x < kApplyRows && row < m) {
+        double t = 0.0;
+        for (int q = 0; q < kApplySplit; q++) t += red[q][threadIdx.x];
+        x[row] = (T)t;
+    }
+}
+
+// coarse = average of the 8 children of fine (coefficient restriction alone);
+// same summation order as the fused defect-restriction kernels.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_restrict(int nf, const T *__restrict__ fine, T *__restrict__ coarse)
+{
+    const int nc = nf / 2;
+    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int I, J, K;
+    if (!cell_of(tid, nc, I, J, K)) return;
+    T s = T(0);
+#pragma unroll
+    for (int di = 0; di < 2; di++)
+#pragma unroll
+        for (int dj = 0; dj < 2; dj++)
+#pragma unroll
+            for (int dk = 0; dk < 2; dk++) s += fine[lidx(nf, 2 * I + di, 2 * J + dj, 2 * K + dk)];
+    coarse[tid] = s * T(0.125);
 }
 
 // ---------------------------------------------------------------------------------------
-// Fused coarsest-level psi solve: one workgroup assembles [L_h + c | r] and runs
-// Gauss-Jordan elimination with partial pivoting (rows are never swapped: a
-// used-row mask records the pivots), then writes x; *flag = 1 if no non-zero
-// pivot exists.
-// Register-resident for m <= 64 unknowns: 256 threads, 4 per matrix
-// row; thread (row, part) holds columns part, part+4, ... of [A | b] in
-// registers.  Per pivot step only the pivot column and the scaled pivot row
-// pass through LDS.
-constexpr int kGjRegMax = 64;
-constexpr int kGjRegCols = (kGjRegMax + 1 + 3) / 4;
-
-__device__ __forceinline__ double reg_get(const double (&v)[kGjRegCols], int jj)
+// Coarsest psi solve in one wavefront, for m = M unknowns (M <= 64, a compile-
+// time constant so the pivot steps unroll with static register indexing).
+// Lane i holds row i of [A | r] in registers.  Pivot: the largest |a_ik| over
+// unused rows, found with one wave max of a packed key (float bits of |a_ik|,
+// low 6 bits replaced by 63 - lane so ties go to the lowest row); the pivot
+// row is broadcast lane-to-scalar with readlane.  No barrier inside the
+// elimination.  *flag = 1 if no non-zero pivot exists.
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ double readlane_d(double v, int lane)
 {
-    double out = 0.0;
-#pragma unroll
-    for (int j = 0; j < kGjRegCols; j++) out = (j == jj) ? v[j] : out;
-    return out;
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
 }
 
-__device__ __forceinline__ void reg_add(double (&v)[kGjRegCols], int jj, double val)
+template <int BC, typename T, int M>
+__global__ void __launch_bounds__(kWave) k_coarse_psi_wave(Geo g, const T *c, const T *r, T *x, double *flag)
 {
-#pragma unroll
-    for (int j = 0; j < kGjRegCols; j++)
-        if (j == jj) v[j] += val;
-}
-
-template <int BC, typename T>
-__global__ void __launch_bounds__(256) k_coarse_psi_reg(Geo g, const T *c, const T *r, T *x,
-                                                        double *flag)
-{
-    const int tid = threadIdx.x, row = tid >> 2, part = tid & 3;
-    const int n = g.n, m = n * n * n, w = m + 1;
-    __shared__ double colk[kGjRegMax], prow[4 * kGjRegCols], rhs[kGjRegMax];
-    __shared__ int used[kGjRegMax], perm[kGjRegMax];
-    __shared__ int piv;
-    double v[kGjRegCols];
-#pragma unroll
-    for (int j = 0; j < kGjRegCols; j++) v[j] = 0.0;
-    if (row < m) {
-        const int k = row % n, j = (row / n) % n, i = row / (n * n);
+    constexpr int NC = M + 1;
+    __shared__ double A[M][NC + 1];
+    __shared__ int perm[M];
+    const int lane = threadIdx.x;
+    const int n = g.n;
+    if (lane < M) {
+        for (int j = 0; j < NC; j++) A[lane][j] = 0.0;
+        const int k = lane % n, j = (lane / n) % n, i = lane / (n * n);
         const double wt[5] = {-1.0, 16.0, -30.0, 16.0, -1.0};
         for (int ax = 0; ax < 3; ax++)
             for (int d = -2; d <= 2; d++) {
@@ -659,64 +670,50 @@ __global__ void __launch_bounds__(256) k_coarse_psi_reg(Geo g, const T *c, const
                     jj = bj;
                     kk = bk;
                 }
-                const int col = (ii * n + jj) * n + kk;
-                if ((col & 3) == part) reg_add(v, col >> 2, wt[d + 2] * g.inv12h2 * fac);
+                A[lane][(ii * n + jj) * n + kk] += wt[d + 2] * g.inv12h2 * fac;
             }
-        if ((row & 3) == part) reg_add(v, row >> 2, (double)c[row]);
-        if ((m & 3) == part) reg_add(v, m >> 2, (double)r[row]);
+        A[lane][lane] += (double)c[lane];
+        A[lane][M] = (double)r[lane];
     }
-    if (tid < kGjRegMax) used[tid] = 0;
     __syncthreads();
-    int bad = 0;
-    for (int kc = 0; kc < m; kc++) {
-        if (row < m && part == (kc & 3)) colk[row] = reg_get(v, kc >> 2);
-        __syncthreads();
-        if (tid < kWave) {
-            double best = (tid < m && !used[tid]) ? fabs(colk[tid]) : -1.0;
-            int bi = tid;
-            for (int o = kWave / 2; o > 0; o >>= 1) {
-                double ov = __shfl_xor(best, o, kWave);
-                int oi = __shfl_xor(bi, o, kWave);
-                if (ov > best || (ov == best && oi < bi)) {
-                    best = ov;
-                    bi = oi;
-                }
-            }
-            if (tid == 0) {
-                piv = (best > 0.0) ? bi : -1;
-                if (best > 0.0) {
-                    perm[kc] = bi;
-                    used[bi] = 1;
-                }
-            }
+    double v[NC];
+#pragma unroll
+    for (int j = 0; j < NC; j++) v[j] = lane < M ? A[lane][j] : 0.0;
+    uint64_t used = 0;
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < M; k++) {
+        const double a = v[k];
+        unsigned key = 0u;
+        if (lane < M && !((used >> lane) & 1ull)) {
+            const unsigned bits = __float_as_uint((float)fabs(a));
+            key = (bits & ~63u) | (63u - (unsigned)lane);
         }
-        __syncthreads();
-        const int p = piv;
-        if (p < 0) {
-            bad = 1;
+        const unsigned kmax = __reduce_max_sync(~0ull, key);
+        if ((kmax >> 6) == 0u) {
+            bad = true;
             break;
         }
-        const double inv = 1.0 / colk[p];
-        if (row == p)
+        const int p = 63 - (int)(kmax & 63u);
+        used |= 1ull << p;
+        if (lane == 0) perm[k] = p;
+        const double inv = 1.0 / readlane_d(a, p);
+        const double f = a * inv;
 #pragma unroll
-            for (int j = 0; j < kGjRegCols; j++) prow[part + 4 * j] = v[j] * inv;
-        __syncthreads();
-        if (row < m) {
-            const double f = colk[row];
-#pragma unroll
-            for (int j = 0; j < kGjRegCols; j++) {
-                const int col = part + 4 * j;
-                if (col > kc && col < w) v[j] = (row == p) ? prow[col] : v[j] - f * prow[col];
-            }
+        for (int j = k + 1; j < NC; j++) {
+            const double pj = readlane_d(v[j], p);
+            v[j] = (lane == p) ? v[j] * inv : v[j] - f * pj;
         }
     }
     if (bad) {
-        if (tid == 0) *flag = 1.0;
+        if (lane == 0) *flag = 1.0;
         return;
     }
-    if (row < m && part == (m & 3)) rhs[row] = reg_get(v, m >> 2);
+    // the scaled row perm[q] now carries x_q in its last column
     __syncthreads();
-    if (tid < m) x[tid] = (T)rhs[perm[tid]];
+    if (lane < M) A[lane][M] = v[M];
+    __syncthreads();
+    if (lane < M) x[lane] = (T)A[perm[lane]][M];
 }
 
 // ---------------------------------------------------------------------------------------

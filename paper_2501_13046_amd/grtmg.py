@@ -22,6 +22,7 @@ BC_PERIODIC, BC_ROBIN = 0, 1
 PREC_FP64, PREC_FP32_IR = 0, 1
 EQ_PSI, EQ_W, EQ_BOTH = 1, 2, 3
 FLAG_CONFORMAL_MATTER = 1
+FLAG_EAGER = 2
 OP_PASS_PSI, OP_PASS_W, OP_DEFECT_RESTRICT_PSI, OP_DEFECT_RESTRICT_W = 1, 2, 3, 4
 OP_PROLONG_ADD, OP_COARSE_PSI, OP_COARSE_W = 5, 6, 7
 PROBE_NONE, PROBE_PASS_PSI, PROBE_PASS_W, PROBE_RESIDUAL = 0, 1, 2, 3
@@ -104,12 +105,13 @@ def _check(st: int, where: str, ok=(MG_OK,)):
 def params(n: int, levels: int = 1, bc: int = BC_PERIODIC, precision: int = PREC_FP64,
            length: float = 1.0, origin=(0.0, 0.0, 0.0), K: float = 0.0, nu_pre: int = 2,
            nu_post: int = 2, solve_momentum: bool = False, puncture_mass: float = 0.0,
-           puncture_pos=(0.0, 0.0, 0.0), conformal_matter: bool = False) -> MgParams:
+           puncture_pos=(0.0, 0.0, 0.0), conformal_matter: bool = False,
+           eager: bool = False) -> MgParams:
     p = MgParams()
     p.n, p.levels, p.bc, p.precision = n, levels, bc, precision
     p.nu_pre, p.nu_post = nu_pre, nu_post
     p.solve_momentum = 1 if solve_momentum else 0
-    p.flags = FLAG_CONFORMAL_MATTER if conformal_matter else 0
+    p.flags = (FLAG_CONFORMAL_MATTER if conformal_matter else 0) | (FLAG_EAGER if eager else 0)
     p.length = length
     for a in range(3):
         p.origin[a] = origin[a]

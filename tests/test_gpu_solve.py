@@ -157,3 +157,32 @@ def test_uniform_density_zero_cycles():
     u = torch.zeros((n,) * 3, dtype=torch.float64, device=dev())
     rep = s.solve(u, None, tol=1e-13)
     assert rep["outer_iters"] == 0 and float(u.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("precision", [g.PREC_FP64, g.PREC_FP32_IR])
+def test_graph_replays_match_eager(precision):
+    # the captured outer-iteration graph is replayed many times per solve and
+    # across solves; every result must equal the eagerly launched solve
+    w = synth.coupled(32, seed=6, precision=precision)
+    rho5, rho1, S, K, po = oracle_problem(w)
+    outs = {}
+    for eager in (True, False):
+        p = gparams(w, K)
+        p.flags |= g.FLAG_EAGER if eager else 0
+        s = g.Solver(p, T(rho5), T(rho1), T(S))
+        res = []
+        u = torch.zeros((32,) * 3, dtype=torch.float64, device=dev())
+        W = torch.zeros((3, 32, 32, 32), dtype=torch.float64, device=dev())
+        for rep_i in range(3):
+            u.zero_()
+            W.zero_()
+            torch.cuda.synchronize()
+            r = s.solve(u, W, tol=1e-10)
+            res.append((N(u), N(W), r["outer_iters"], r["h_rms"], r["m_rms"]))
+            # eager work between replays
+            _ = s.residual_norm(u, W)
+        outs[eager] = res
+    for a in outs[True] + outs[False]:
+        b = outs[True][0]
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+        assert a[2:] == b[2:]

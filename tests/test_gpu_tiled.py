@@ -64,3 +64,37 @@ def test_report_lds_limit():
         print(f"{name} (attr {attr}): rc={rc} value={v.value}")
     props = torch.cuda.get_device_properties(0)
     print("torch props:", {k: getattr(props, k) for k in dir(props) if "shared" in k or "multi" in k})
+
+
+def test_tiled_residual_periodic_coupled():
+    K = 2.3
+    p = g.params(n, 6, K=K, solve_momentum=True)
+    po = oracle.params(n, 6, K=K, solve_momentum=True)
+    u = synth.uniform_random(70, (n,) * 3, -0.05, 0.05)
+    W = synth.uniform_random(71, (3, n, n, n), -0.02, 0.02)
+    rho5 = synth.uniform_random(72, (n,) * 3, 0, 1)
+    rho1 = synth.uniform_random(73, (n,) * 3, 0, 1)
+    S = synth.uniform_random(74, (3, n, n, n))
+    s = g.Solver(p, T(rho5), T(rho1), T(S))
+    H, M, c = s.residual_fields(T(u), T(W))
+    Ho, Mo, co = oracle.residuals(po, u, W, rho5, rho1, S)
+    assert rel_err(N(H), Ho) < 1e-12
+    assert rel_err(N(M), Mo) < 1e-12
+    assert rel_err(N(c), co) < 1e-13
+    np.testing.assert_allclose(s.residual_norm(T(u), T(W)), oracle.norms(Ho, Mo), rtol=1e-11)
+
+
+def test_tiled_residual_robin_puncture():
+    p = g.params(n, 6, bc=g.BC_ROBIN, length=64.0, origin=(-32.0,) * 3, puncture_mass=1.0,
+                 conformal_matter=True)
+    po = oracle.params(n, 6, bc=oracle.BC_ROBIN, length=64.0, origin=(-32.0,) * 3, puncture_mass=1.0,
+                       conformal_matter=True)
+    u = synth.uniform_random(75, (n,) * 3, -0.05, 0.05)
+    rho5 = synth.uniform_random(76, (n,) * 3, 0, 0.01)
+    rho1 = synth.uniform_random(77, (n,) * 3, 0, 0.01)
+    s = g.Solver(p, T(rho5), T(rho1))
+    H, _, c = s.residual_fields(T(u), None, want_M=False)
+    z3 = np.zeros((3, n, n, n))
+    Ho, _, co = oracle.residuals(po, u, z3, rho5, rho1, z3)
+    assert rel_err(N(H), Ho) < 1e-12
+    assert rel_err(N(c), co) < 1e-13
