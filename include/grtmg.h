@@ -225,6 +225,35 @@ mg_status mg_kernel_op(mg_ctx *ctx, int32_t op, int32_t level, int32_t arg, cons
                        void *d_out, const void *d_r, const void *d_c);
 
 /*
+ * Batches of independent instances (a parameter scan of uneven grid sizes).
+ * One batch context holds one member context per instance, all carved from
+ * one caller-owned workspace; the members' outer iterations are captured
+ * into a single hipGraph as parallel branches (up to 4 run concurrently), so
+ * each outer iteration of the whole batch is one graph launch followed by one
+ * copy of every member's norms.  A member that has converged (or diverged)
+ * keeps its state: its update kernels are gated by a device-side flag set by
+ * a check kernel after each evaluation.
+ *  p: host array of count parameter sets (same precision for all; momentum
+ *     members need periodic boundaries as for mg_setup).
+ *  d_rho5, d_rho1, d_S: host arrays of count device pointers (n_i^3, n_i^3,
+ *     3 n_i^3 FP64); d_S may be NULL when no member solves the momentum
+ *     equation.  Sources are borrowed.
+ *  mg_solve_batch: d_u, d_W host arrays of device pointers (d_W may be NULL
+ *     when no member solves the momentum equation); reps (may be NULL) gets
+ *     count reports (no per-iteration history).  Returns MG_OK when every
+ *     member converged, else the first non-OK member status.  Synchronises
+ *     the batch's streams once per outer iteration.
+ */
+typedef struct mg_batch mg_batch;
+mg_status mg_batch_workspace_size(const mg_params *p, int32_t count, size_t *bytes);
+mg_status mg_setup_batch(const mg_params *p, int32_t count, void *d_workspace, size_t bytes, void *stream,
+                         const double *const *d_rho5, const double *const *d_rho1,
+                         const double *const *d_S, mg_batch **out);
+mg_status mg_solve_batch(mg_batch *b, double *const *d_u, double *const *d_W, double tol, int32_t max_outer,
+                         mg_report *reps);
+void mg_destroy_batch(mg_batch *b);
+
+/*
  * Kernel timing probe (measurement support).  mg_probe(ctx, kernel, level)
  * starts recording a HIP event pair around every later launch of one kernel
  * family on one level (kernel = MG_PROBE_*, level = multigrid level, or -1

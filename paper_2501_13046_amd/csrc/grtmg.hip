@@ -28,7 +28,17 @@ constexpr int kMaxCoarseW = 1536;   // coarsest W unknowns (3 * 8^3)
 constexpr int kSrcBlocks = 2048;    // grid of the source kernel (partials in scratch)
 
 // device scalar slots
-enum { S_NORM = 0, S_MEANS = 4, S_MEAND = 8, S_FLAG_PSI = 12, S_FLAG_W = 13, S_COUNT = 16 };
+enum {
+    S_NORM = 0,
+    S_MEANS = 4,
+    S_ACTIVE = 7,
+    S_MEAND = 8,
+    S_ITERS = 11,
+    S_FLAG_PSI = 12,
+    S_FLAG_W = 13,
+    S_DIVERGED = 14,
+    S_COUNT = 16
+};
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -80,6 +90,10 @@ struct mg_ctx {
     const double *rho5, *rho1, *S, *f;
     double K2;
     int vc_psi, vc_W;
+    // batch membership: streams borrowed from the batch, updates gated by the
+    // instance's active flag, a convergence check after every evaluation
+    bool batched, own_streams;
+    double batch_tol;
     // outer-iteration graph (keyed by the state pointers it was captured for)
     hipGraphExec_t gexec;
     const double *g_u, *g_W;
@@ -511,7 +525,8 @@ void step_W(mg_ctx *c, const double *u, double *W, bool residual_done)
     {
         Probe pr(c, MG_PROBE_UPDATE, 0);
         hipLaunchKernelGGL(k_update_W<T>, dim3(nb), dim3(kBlock), 0, c->s, W, (const T *)c->wd0[0],
-                           (const double *)(c->scal + S_MEAND), m);
+                           (const double *)(c->scal + S_MEAND), m,
+                           c->batched ? (const double *)(c->scal + S_ACTIVE) : nullptr);
     }
     c->vc_W++;
 }
@@ -526,7 +541,8 @@ void step_psi(mg_ctx *c, double *u, const double *W, bool residual_done)
     const int64_t m = c->cells[0];
     {
         Probe pr(c, MG_PROBE_UPDATE, 0);
-        hipLaunchKernelGGL(k_update_u<T>, dim3(nblk(m)), dim3(kBlock), 0, c->s, u, (const T *)c->pd0[0], m);
+        hipLaunchKernelGGL(k_update_u<T>, dim3(nblk(m)), dim3(kBlock), 0, c->s, u, (const T *)c->pd0[0], m,
+                           c->batched ? (const double *)(c->scal + S_ACTIVE) : nullptr);
     }
     c->vc_psi++;
 }
@@ -552,15 +568,20 @@ mg_status fetch_norms(mg_ctx *c, double out[4], double *flag_psi)
     return MG_OK;
 }
 
-// Evaluation of a state: norms (+ the residual the next update step uses).
+// Evaluation of a state: norms (+ the residual the next update step uses);
+// batch members also update their convergence flags.
 template <typename T>
-void evaluate(mg_ctx *c, const double *u, const double *W, bool want_M)
+void evaluate(mg_ctx *c, const double *u, const double *W, bool want_M, bool after_update = true)
 {
     source_mean(c, u);
     if (c->momentum)
         residual<T>(c, u, W, true, nullptr, nullptr, nullptr, nullptr, nullptr, c->wr[0], true);
     else
         residual<T>(c, u, W, want_M, nullptr, nullptr, nullptr, c->pr[0], c->pc[0], nullptr, true);
+    if (c->batched)
+        hipLaunchKernelGGL(k_batch_check, dim3(1), dim3(64), 0, c->s, c->scal, (int)S_ACTIVE, (int)S_ITERS,
+                           (int)S_DIVERGED, 1.0 / (double)c->cells[0], c->batch_tol, c->momentum ? 1 : 0,
+                           after_update ? 1 : 0);
 }
 
 // One outer update (W step, psi step) followed by the evaluation of the new state.
@@ -583,13 +604,12 @@ void drop_graph(mg_ctx *c)
     c->g_u = c->g_W = nullptr;
 }
 
-// Capture outer_body for (u, W) into an executable graph (reused while the
-// state pointers stay the same).
+// Capture one outer_body for (u, W) on the context's own streams into a graph
+// (the host-side V-cycle counters are left as they were).
 template <typename T>
-mg_status capture_body(mg_ctx *c, double *u, double *W, bool want_M)
+mg_status capture_graph(mg_ctx *c, double *u, double *W, bool want_M, hipGraph_t *out)
 {
-    if (c->gexec && c->g_u == u && c->g_W == W) return MG_OK;
-    drop_graph(c);
+    *out = nullptr;
     if (hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal) != hipSuccess) return MG_ERR_HIP;
     const int vp = c->vc_psi, vw = c->vc_W;
     outer_body<T>(c, u, W, want_M);
@@ -597,6 +617,20 @@ mg_status capture_body(mg_ctx *c, double *u, double *W, bool want_M)
     c->vc_W = vw;
     hipGraph_t g = nullptr;
     if (hipStreamEndCapture(c->s, &g) != hipSuccess || !g) return MG_ERR_HIP;
+    *out = g;
+    return MG_OK;
+}
+
+// Capture outer_body for (u, W) into an executable graph (reused while the
+// state pointers stay the same).
+template <typename T>
+mg_status capture_body(mg_ctx *c, double *u, double *W, bool want_M)
+{
+    if (c->gexec && c->g_u == u && c->g_W == W) return MG_OK;
+    drop_graph(c);
+    hipGraph_t g = nullptr;
+    mg_status st = capture_graph<T>(c, u, W, want_M, &g);
+    if (st != MG_OK) return st;
     hipError_t e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
@@ -703,8 +737,10 @@ void release(mg_ctx *c)
         if (*e) (void)hipEventDestroy(*e);
     for (int l = 0; l < 16; l++)
         if (c->ev_c[l]) (void)hipEventDestroy(c->ev_c[l]);
-    if (c->s) (void)hipStreamDestroy(c->s);
-    if (c->side) (void)hipStreamDestroy(c->side);
+    if (c->own_streams) {
+        if (c->s) (void)hipStreamDestroy(c->s);
+        if (c->side) (void)hipStreamDestroy(c->side);
+    }
     if (c->hpin) (void)hipHostFree(c->hpin);
     if (c->probe_ev) {
         for (int q = 0; q < 2 * kProbeMax; q++) (void)hipEventDestroy(c->probe_ev[q]);
@@ -713,10 +749,15 @@ void release(mg_ctx *c)
     delete c;
 }
 
+// Create the context's events, and its two streams unless they are borrowed
+// (already set: batch members).
 mg_status create_streams(mg_ctx *c)
 {
-    if (hipStreamCreateWithFlags(&c->s, hipStreamNonBlocking) != hipSuccess) return MG_ERR_HIP;
-    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) return MG_ERR_HIP;
+    if (!c->s) {
+        c->own_streams = true;
+        if (hipStreamCreateWithFlags(&c->s, hipStreamNonBlocking) != hipSuccess) return MG_ERR_HIP;
+        if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) return MG_ERR_HIP;
+    }
     hipEvent_t *evs[] = {&c->ev_in, &c->ev_out, &c->ev_fork, &c->ev_gj};
     for (hipEvent_t *e : evs)
         if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) return MG_ERR_HIP;
@@ -804,11 +845,16 @@ mg_status mg_workspace_size(const mg_params *p, size_t *bytes)
     return MG_OK;
 }
 
-mg_status mg_setup(const mg_params *p, void *d_workspace, size_t bytes, void *stream,
-                   const double *d_rho5, const double *d_rho1, const double *d_S, const double *d_f,
-                   mg_ctx **out)
+} // extern "C"
+
+namespace {
+
+// Create a context on a caller-provided workspace.  s_main / s_side: streams
+// borrowed from a batch, or null to create the context's own.
+mg_status ctx_create(const mg_params *p, void *d_workspace, size_t bytes, hipStream_t user_s,
+                     const double *d_rho5, const double *d_rho1, const double *d_S, const double *d_f,
+                     hipStream_t s_main, hipStream_t s_side, mg_ctx **out)
 {
-    if (!out) return MG_ERR_INVALID;
     *out = nullptr;
     mg_status st = validate(p);
     if (st != MG_OK) return st;
@@ -821,7 +867,9 @@ mg_status mg_setup(const mg_params *p, void *d_workspace, size_t bytes, void *st
     if (!c) return MG_ERR_INVALID;
     std::memset(c, 0, sizeof(*c));
     c->p = *p;
-    c->user_s = (hipStream_t)stream;
+    c->user_s = user_s;
+    c->s = s_main;
+    c->side = s_side;
     c->L = p->levels;
     c->f32 = p->precision == MG_PREC_FP32_IR;
     c->esz = c->f32 ? sizeof(float) : sizeof(double);
@@ -865,6 +913,296 @@ mg_status mg_setup(const mg_params *p, void *d_workspace, size_t bytes, void *st
     *out = c;
     return MG_OK;
 }
+
+} // namespace
+
+// ---- batches ---------------------------------------------------------------------------
+
+constexpr int kBatchLanes = 4; // concurrent branches (stream pairs) of a batch
+
+struct mg_batch {
+    int count;
+    mg_ctx **ctx;
+    hipStream_t user_s, s;
+    hipStream_t lane_s[kBatchLanes], lane_side[kBatchLanes];
+    hipEvent_t ev_in, ev_out, ev_root;
+    hipEvent_t *ev_join;
+    double *scal_all; // device: count x S_COUNT, the members' scalar blocks
+    double *hpin;     // pinned copy of scal_all
+    hipGraphExec_t gexec;
+    double **g_u, **g_W; // state pointers the graph was captured for
+    double g_tol;
+};
+
+namespace {
+
+size_t batch_layout(const mg_params *p, int count, size_t *offsets)
+{
+    size_t off = align_up((size_t)count * S_COUNT * sizeof(double), 256);
+    for (int i = 0; i < count; i++) {
+        size_t b = 0;
+        mg_workspace_size(&p[i], &b);
+        if (offsets) offsets[i] = off;
+        off = align_up(off + b, 256);
+    }
+    return off;
+}
+
+void batch_release(mg_batch *b)
+{
+    if (!b) return;
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->s) (void)hipStreamSynchronize(b->s);
+    if (b->ctx)
+        for (int i = 0; i < b->count; i++)
+            if (b->ctx[i]) release(b->ctx[i]);
+    for (int q = 0; q < kBatchLanes; q++) {
+        if (b->lane_s[q]) (void)hipStreamDestroy(b->lane_s[q]);
+        if (b->lane_side[q]) (void)hipStreamDestroy(b->lane_side[q]);
+    }
+    if (b->ev_join) {
+        for (int i = 0; i < b->count; i++)
+            if (b->ev_join[i]) (void)hipEventDestroy(b->ev_join[i]);
+        delete[] b->ev_join;
+    }
+    hipEvent_t evs[] = {b->ev_in, b->ev_out, b->ev_root};
+    for (hipEvent_t e : evs)
+        if (e) (void)hipEventDestroy(e);
+    if (b->s) (void)hipStreamDestroy(b->s);
+    if (b->hpin) (void)hipHostFree(b->hpin);
+    delete[] b->ctx;
+    delete[] b->g_u;
+    delete[] b->g_W;
+    delete b;
+}
+
+// Fork every member from the batch stream, run fn(member) on its lane, join.
+template <typename F>
+void batch_fork_join(mg_batch *b, F fn)
+{
+    (void)hipEventRecord(b->ev_root, b->s);
+    for (int i = 0; i < b->count; i++) {
+        mg_ctx *c = b->ctx[i];
+        (void)hipStreamWaitEvent(c->s, b->ev_root, 0);
+        fn(i, c);
+        (void)hipEventRecord(b->ev_join[i], c->s);
+        (void)hipStreamWaitEvent(b->s, b->ev_join[i], 0);
+    }
+}
+
+template <typename T>
+mg_status batch_solve(mg_batch *b, double *const *u, double *const *W, double tol, int max_outer, mg_report *reps)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    const int n = b->count;
+    for (int i = 0; i < n; i++) b->ctx[i]->batch_tol = tol;
+    // reset flags; evaluate every member (eager)
+    batch_fork_join(b, [&](int i, mg_ctx *c) {
+        fill<double>(c->s, c->scal + S_FLAG_PSI, 2, 0.0);
+        fill<double>(c->s, c->scal + S_ITERS, 1, 0.0);
+        fill<double>(c->s, c->scal + S_DIVERGED, 1, 0.0);
+        fill<double>(c->s, c->scal + S_ACTIVE, 1, 1.0);
+        evaluate<T>(c, u[i], W[i], c->momentum || (c->S && W[i]), false);
+    });
+    bool same = b->gexec && b->g_tol == tol;
+    for (int i = 0; same && i < n; i++) same = b->g_u[i] == u[i] && b->g_W[i] == W[i];
+    if (!same) {
+        if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+        // every member's outer iteration is captured on the member's own
+        // streams and becomes an independent child of one batch graph
+        hipGraph_t parent = nullptr;
+        if (hipGraphCreate(&parent, 0) != hipSuccess) return MG_ERR_HIP;
+        mg_status st = MG_OK;
+        for (int i = 0; i < n && st == MG_OK; i++) {
+            mg_ctx *c = b->ctx[i];
+            hipGraph_t g = nullptr;
+            st = capture_graph<T>(c, u[i], W[i], c->momentum || (c->S && W[i]), &g);
+            if (st != MG_OK) break;
+            hipGraphNode_t node = nullptr;
+            if (hipGraphAddChildGraphNode(&node, parent, nullptr, 0, g) != hipSuccess) st = MG_ERR_HIP;
+            (void)hipGraphDestroy(g);
+        }
+        if (st == MG_OK && hipGraphInstantiate(&b->gexec, parent, nullptr, nullptr, 0) != hipSuccess) {
+            b->gexec = nullptr;
+            st = MG_ERR_HIP;
+        }
+        (void)hipGraphDestroy(parent);
+        if (st != MG_OK) return st;
+        for (int i = 0; i < n; i++) {
+            b->g_u[i] = u[i];
+            b->g_W[i] = W[i];
+        }
+        b->g_tol = tol;
+    }
+    int it = 0;
+    for (;; it++) {
+        if (hipMemcpyAsync(b->hpin, b->scal_all, (size_t)n * S_COUNT * sizeof(double), hipMemcpyDeviceToHost,
+                           b->s) != hipSuccess ||
+            hipStreamSynchronize(b->s) != hipSuccess)
+            return MG_ERR_HIP;
+        int active = 0;
+        for (int i = 0; i < n; i++) active += b->hpin[i * S_COUNT + S_ACTIVE] != 0.0;
+        if (active == 0 || it >= max_outer) break;
+        if (hipGraphLaunch(b->gexec, b->s) != hipSuccess) return MG_ERR_HIP;
+    }
+    auto t1 = std::chrono::steady_clock::now();
+    mg_status worst = MG_OK;
+    for (int i = 0; i < n; i++) {
+        const double *h = b->hpin + i * S_COUNT;
+        const double inv = 1.0 / (double)b->ctx[i]->cells[0];
+        mg_status st = h[S_ACTIVE] != 0.0 ? MG_ERR_NOT_CONVERGED : MG_OK;
+        if (h[S_DIVERGED] != 0.0) st = MG_ERR_DIVERGED;
+        if (h[S_FLAG_PSI] != 0.0) st = MG_ERR_SINGULAR;
+        if (st != MG_OK && worst == MG_OK) worst = st;
+        if (reps) {
+            mg_report &r = reps[i];
+            r.outer_iters = (int)h[S_ITERS];
+            r.vcycles_psi = r.outer_iters;
+            r.vcycles_W = b->ctx[i]->momentum ? r.outer_iters : 0;
+            r.status = st;
+            r.h_rms = std::sqrt(h[S_NORM + 0] * inv);
+            r.m_rms = std::sqrt(h[S_NORM + 2] * inv);
+            r.h_max = h[S_NORM + 1];
+            r.m_max = h[S_NORM + 3];
+            r.seconds = std::chrono::duration<double>(t1 - t0).count();
+            r.history_len = 0;
+        }
+    }
+    (void)it;
+    return worst;
+}
+
+} // namespace
+
+extern "C" {
+
+mg_status mg_setup(const mg_params *p, void *d_workspace, size_t bytes, void *stream,
+                   const double *d_rho5, const double *d_rho1, const double *d_S, const double *d_f,
+                   mg_ctx **out)
+{
+    if (!out) return MG_ERR_INVALID;
+    return ctx_create(p, d_workspace, bytes, (hipStream_t)stream, d_rho5, d_rho1, d_S, d_f, nullptr, nullptr, out);
+}
+
+mg_status mg_batch_workspace_size(const mg_params *p, int32_t count, size_t *bytes)
+{
+    if (!p || !bytes || count < 1 || count > 4096) return MG_ERR_INVALID;
+    for (int i = 0; i < count; i++) {
+        mg_status st = validate(&p[i]);
+        if (st != MG_OK) return st;
+        if (p[i].precision != p[0].precision) return MG_ERR_INVALID;
+    }
+    *bytes = batch_layout(p, count, nullptr);
+    return MG_OK;
+}
+
+mg_status mg_setup_batch(const mg_params *p, int32_t count, void *d_workspace, size_t bytes, void *stream,
+                         const double *const *d_rho5, const double *const *d_rho1, const double *const *d_S,
+                         mg_batch **out)
+{
+    if (!out) return MG_ERR_INVALID;
+    *out = nullptr;
+    size_t need = 0;
+    mg_status st = mg_batch_workspace_size(p, count, &need);
+    if (st != MG_OK) return st;
+    if (!d_rho5 || !d_rho1) return MG_ERR_INVALID;
+    for (int i = 0; i < count; i++) {
+        if (!d_rho5[i] || !d_rho1[i]) return MG_ERR_INVALID;
+        if (p[i].solve_momentum && (!d_S || !d_S[i])) return MG_ERR_INVALID;
+    }
+    if (!d_workspace || bytes < need || ((uintptr_t)d_workspace % 256) != 0) return MG_ERR_WORKSPACE;
+    mg_batch *b = new (std::nothrow) mg_batch;
+    if (!b) return MG_ERR_INVALID;
+    std::memset(b, 0, sizeof(*b));
+    b->count = count;
+    b->user_s = (hipStream_t)stream;
+    b->ctx = new (std::nothrow) mg_ctx *[count]();
+    b->ev_join = new (std::nothrow) hipEvent_t[count]();
+    b->g_u = new (std::nothrow) double *[count]();
+    b->g_W = new (std::nothrow) double *[count]();
+    if (!b->ctx || !b->ev_join || !b->g_u || !b->g_W) {
+        batch_release(b);
+        return MG_ERR_INVALID;
+    }
+    bool ok = hipStreamCreateWithFlags(&b->s, hipStreamNonBlocking) == hipSuccess;
+    for (int q = 0; q < kBatchLanes && ok; q++)
+        ok = hipStreamCreateWithFlags(&b->lane_s[q], hipStreamNonBlocking) == hipSuccess &&
+             hipStreamCreateWithFlags(&b->lane_side[q], hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&b->ev_root, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; i < count && ok; i++)
+        ok = hipEventCreateWithFlags(&b->ev_join[i], hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipHostMalloc((void **)&b->hpin, (size_t)count * S_COUNT * sizeof(double),
+                             hipHostMallocDefault) == hipSuccess;
+    if (!ok) {
+        batch_release(b);
+        return MG_ERR_HIP;
+    }
+    b->scal_all = (double *)d_workspace;
+    size_t *offs = new (std::nothrow) size_t[count];
+    if (!offs) {
+        batch_release(b);
+        return MG_ERR_INVALID;
+    }
+    batch_layout(p, count, offs);
+    // members run after the work already on the caller's stream
+    (void)hipEventRecord(b->ev_in, b->user_s);
+    for (int q = 0; q < kBatchLanes; q++) (void)hipStreamWaitEvent(b->lane_s[q], b->ev_in, 0);
+    for (int i = 0; i < count; i++) {
+        size_t wb = 0;
+        mg_workspace_size(&p[i], &wb);
+        st = ctx_create(&p[i], (char *)d_workspace + offs[i], wb, b->lane_s[i % kBatchLanes], d_rho5[i],
+                        d_rho1[i], d_S ? d_S[i] : nullptr, nullptr, b->lane_s[i % kBatchLanes],
+                        b->lane_side[i % kBatchLanes], &b->ctx[i]);
+        if (st != MG_OK) {
+            delete[] offs;
+            batch_release(b);
+            return st;
+        }
+        mg_ctx *c = b->ctx[i];
+        c->batched = true;
+        c->scal = b->scal_all + (size_t)i * S_COUNT;
+        c->user_s = b->s;
+        fill<double>(c->s, c->scal, S_COUNT, 0.0);
+    }
+    delete[] offs;
+    for (int q = 0; q < kBatchLanes; q++) (void)hipStreamSynchronize(b->lane_s[q]);
+    if (hip_status() != MG_OK) {
+        batch_release(b);
+        return MG_ERR_HIP;
+    }
+    *out = b;
+    return MG_OK;
+}
+
+mg_status mg_solve_batch(mg_batch *b, double *const *d_u, double *const *d_W, double tol, int32_t max_outer,
+                         mg_report *reps)
+{
+    if (!b || !d_u || !(tol > 0.0) || max_outer < 0) return MG_ERR_INVALID;
+    for (int i = 0; i < b->count; i++) {
+        if (!d_u[i]) return MG_ERR_INVALID;
+        if (b->ctx[i]->momentum && (!d_W || !d_W[i])) return MG_ERR_INVALID;
+    }
+    (void)hipEventRecord(b->ev_in, b->user_s);
+    (void)hipStreamWaitEvent(b->s, b->ev_in, 0);
+    double *const *W = d_W;
+    double **Wn = nullptr;
+    if (!d_W) {
+        Wn = new (std::nothrow) double *[b->count]();
+        if (!Wn) return MG_ERR_INVALID;
+        W = Wn;
+    }
+    mg_status st = b->ctx[0]->f32 ? batch_solve<float>(b, d_u, W, tol, max_outer, reps)
+                                  : batch_solve<double>(b, d_u, W, tol, max_outer, reps);
+    delete[] Wn;
+    (void)hipEventRecord(b->ev_out, b->s);
+    (void)hipStreamWaitEvent(b->user_s, b->ev_out, 0);
+    return st;
+}
+
+void mg_destroy_batch(mg_batch *b) { batch_release(b); }
 
 mg_status mg_vcycle(mg_ctx *c, int32_t eq, double *d_u, double *d_W)
 {

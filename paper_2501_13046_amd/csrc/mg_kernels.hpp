@@ -726,22 +726,48 @@ __global__ void __launch_bounds__(kBlock) k_fill(T *a, int64_t count, T v)
     if (q < count) a[q] = v;
 }
 
+// u += d.  gate (nullable): the update is skipped when *gate == 0 (an instance
+// of a batch that has already converged).
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_update_u(double *u, const T *d, int64_t m)
+__global__ void __launch_bounds__(kBlock) k_update_u(double *u, const T *d, int64_t m, const double *gate)
 {
+    if (gate && *gate == 0.0) return;
     const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (q < m) u[q] += (double)d[q];
 }
 
-// W_a += dW_a - mean_a (mean: device, 3 values)
+// W_a += dW_a - mean_a (mean: device, 3 values); gate as for k_update_u
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_update_W(double *W, const T *d, const double *mean,
-                                                     int64_t m)
+                                                     int64_t m, const double *gate)
 {
+    if (gate && *gate == 0.0) return;
     const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (q >= m) return;
 #pragma unroll
     for (int s = 0; s < 3; s++) W[s * m + q] += (double)d[s * m + q] - mean[s];
+}
+
+// Convergence bookkeeping of one batch instance after an evaluation.
+// scal: the instance's scalar block (norm sums / maxima at 0..3).  If the
+// instance was active, its update count is incremented (the evaluation follows
+// an update step, except the first one, which passes count_update = 0); the
+// instance stays active while rms H > tol or (momentum) rms |M| > tol and the
+// norms are finite; a non-finite norm marks it diverged.
+__global__ void k_batch_check(double *scal, int active_slot, int iters_slot, int div_slot, double inv_cells,
+                              double tol, int momentum, int count_update)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double was = scal[active_slot];
+    if (was == 0.0) return;
+    if (count_update) scal[iters_slot] += 1.0;
+    const double h = sqrt(scal[0] * inv_cells), mm = sqrt(scal[2] * inv_cells);
+    if (!isfinite(h) || !isfinite(mm)) {
+        scal[div_slot] = 1.0;
+        scal[active_slot] = 0.0;
+        return;
+    }
+    if (h <= tol && (!momentum || mm <= tol)) scal[active_slot] = 0.0;
 }
 
 // ---------------------------------------------------------------------------------------

@@ -81,12 +81,19 @@ def lib() -> C.CDLL:
                                              vp, vp, vp, vp]
         L.mg_interp_cubic.argtypes = [pp, vp, vp, vp]
         L.mg_kernel_op.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp]
+        L.mg_batch_workspace_size.argtypes = [pp, i32, C.POINTER(C.c_size_t)]
+        L.mg_setup_batch.argtypes = [pp, i32, vp, C.c_size_t, vp, C.POINTER(vp), C.POINTER(vp),
+                                     C.POINTER(vp), C.POINTER(vp)]
+        L.mg_solve_batch.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.c_double, i32,
+                                     C.POINTER(MgReport)]
+        L.mg_destroy_batch.argtypes = [vp]
+        L.mg_destroy_batch.restype = None
         L.mg_probe.argtypes = [vp, i32, i32]
         L.mg_probe_result.argtypes = [vp, C.POINTER(i32), C.POINTER(C.c_double)]
         for f in ("mg_workspace_size", "mg_setup", "mg_vcycle", "mg_solve_constraints",
                   "mg_residual_norm", "mg_residual_fields", "mg_scalar_field_sources",
                   "mg_shell_field_sources", "mg_interp_cubic", "mg_kernel_op", "mg_probe",
-                  "mg_probe_result"):
+                  "mg_probe_result", "mg_batch_workspace_size", "mg_setup_batch", "mg_solve_batch"):
             getattr(L, f).restype = st
         _lib = L
     return _lib
@@ -222,6 +229,56 @@ class Solver:
         vt = self.vtype
         _check(lib().mg_kernel_op(self.ctx, op, level, arg, _dptr(inp, vt), _dptr(out, vt),
                                   _dptr(r, vt), _dptr(c, vt)), "mg_kernel_op")
+
+
+def _ptr_array(ts, dtype=torch.float64):
+    arr = (C.c_void_p * len(ts))()
+    for i, t in enumerate(ts):
+        arr[i] = None if t is None else _dptr(t, dtype).value
+    return arr
+
+
+class Batch:
+    """A batch of independent instances solved together (one graph launch per
+    outer iteration for the whole batch)."""
+
+    def __init__(self, plist, rho5s, rho1s, Ss=None):
+        self.count = len(plist)
+        self.params = (MgParams * self.count)(*plist)
+        self.device = rho5s[0].device
+        self._keep = (list(rho5s), list(rho1s), list(Ss) if Ss is not None else None)
+        nb = C.c_size_t(0)
+        _check(lib().mg_batch_workspace_size(self.params, self.count, C.byref(nb)),
+               "mg_batch_workspace_size")
+        self.ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        self._r5, self._r1 = _ptr_array(rho5s), _ptr_array(rho1s)
+        self._S = _ptr_array(Ss) if Ss is not None else None
+        b = C.c_void_p(None)
+        _check(lib().mg_setup_batch(self.params, self.count, C.c_void_p(self.ws.data_ptr()), nb.value,
+                                    _stream(self.device), self._r5, self._r1, self._S, C.byref(b)),
+               "mg_setup_batch")
+        self.b = b
+
+    def close(self):
+        if getattr(self, "b", None) is not None and self.b.value:
+            lib().mg_destroy_batch(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, us, Ws=None, tol=1e-10, max_outer=100, raise_on_failure=True):
+        reps = (MgReport * self.count)()
+        st = lib().mg_solve_batch(self.b, _ptr_array(us), _ptr_array(Ws) if Ws is not None else None,
+                                  tol, max_outer, reps)
+        out = [dict(status=r.status, outer_iters=r.outer_iters, h_rms=r.h_rms, m_rms=r.m_rms,
+                    h_max=r.h_max, m_max=r.m_max, seconds=r.seconds) for r in reps]
+        if raise_on_failure:
+            _check(st, "mg_solve_batch")
+        return st, out
 
 
 def scalar_field_sources(p: MgParams, phi_modes: np.ndarray, pi_modes: np.ndarray,
