@@ -153,3 +153,15 @@ def random_smooth_field(seed: int, n: int, count: int = 4, amplitude: float = 0.
 def uniform_random(seed: int, shape, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
     """Plain seeded uniform noise (float64), for operator-level parity inputs."""
     return np.random.default_rng([seed, 11]).uniform(lo, hi, size=shape)
+
+
+def nn_init(shapes, seed: int, bias_scale: float = 0.0) -> np.ndarray:
+    """Seeded initial parameters of a stack of 3x3x3 convolutions, laid out per layer
+    as W[co][ci][3][3][3] then b[co] (float32): W ~ N(0, 2 / (27 ci)) (He
+    initialisation), b ~ U(-bias_scale, bias_scale)."""
+    rng = np.random.default_rng([seed, 23])
+    parts = []
+    for ci, co in shapes:
+        parts.append(rng.normal(0.0, np.sqrt(2.0 / (27.0 * ci)), size=27 * ci * co))
+        parts.append(rng.uniform(-bias_scale, bias_scale, size=co) if bias_scale > 0 else np.zeros(co))
+    return np.concatenate(parts).astype(np.float32)
