@@ -20,14 +20,17 @@ def g():
 
 
 def declared_functions():
-    text = open(os.path.join(ROOT, "include", "grtmg.h")).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(mg_[a-z_0-9]+)\s*\(", text)))
+    names = set()
+    for h in ("grtmg.h", "grtnn.h"):
+        text = open(os.path.join(ROOT, "include", h)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b((?:mg|nn)_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_exports_every_declared_symbol(g):
     names = declared_functions()
-    assert len(names) >= 12, names
+    assert len(names) >= 30, names
     lib = C.CDLL(g.LIB_PATH)
     for name in names:
         assert hasattr(lib, name), name
@@ -82,3 +85,28 @@ def test_entry_points_reject_null_context(g):
     assert lib.mg_interp_cubic(C.byref(p), None, None, None) == g.MG_ERR_INVALID
     assert lib.mg_scalar_field_sources(C.byref(p), 40, None, 0, None, 1.0, None, None, None,
                                        None, 0, None, None) == g.MG_ERR_INVALID
+
+
+def test_network_abi(g):
+    from paper_2501_13046_amd import grtnn as gn
+    from oracle import nn_oracle as nn
+    assert C.sizeof(gn.NnConfig) == 8 * 4
+    assert C.sizeof(gn.NnNorm) == 16 * 8
+    for n, levels, ch in ((128, 4, (16, 32, 48, 64)), (16, 3, (16, 32, 48)), (8, 1, (16,))):
+        cfg = nn.NetConfig(n=n, levels=levels, ch=ch)
+        assert gn.param_count(gn.config(n, levels, ch)) == nn.param_count(cfg)
+    assert gn.workspace_size(gn.config(32), True) > gn.workspace_size(gn.config(32), False) > 0
+    for bad in (gn.config(30), gn.config(8, 4), gn.config(32, 4, (16, 24, 48, 64)),
+                gn.config(32, 4, c_in=9), gn.config(32, 5)):
+        with pytest.raises(g.MGError) as e:
+            gn.workspace_size(bad, False)
+        assert e.value.status == g.MG_ERR_INVALID
+    lib = gn.lib()
+    ctx = C.c_void_p(None)
+    cfg = gn.config(32)
+    # null / misaligned workspace: rejected before any HIP call
+    assert lib.nn_setup(C.byref(cfg), 0, None, 0, None, C.byref(ctx)) == g.MG_ERR_WORKSPACE
+    assert lib.nn_setup(C.byref(cfg), 0, C.c_void_p(256 * 3 + 8), 1 << 40, None, C.byref(ctx)) == g.MG_ERR_WORKSPACE
+    assert lib.nn_forward(None, None, None) == g.MG_ERR_INVALID
+    assert lib.nn_op_scratch_bytes(12, 16, 8) == 0
+    assert lib.nn_conv3_forward(8, 12, 16, None, 0, None, None, None, None, 0, None) == g.MG_ERR_INVALID
