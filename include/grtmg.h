@@ -198,6 +198,19 @@ mg_status mg_interp_cubic(const mg_params *pc, const double *d_coarse, double *d
                           void *stream);
 
 /*
+ * Full-multigrid start of a fine solve from the coarse problem: solves the
+ * coarse context cc (grid n/2 of the same box and boundary rule, sources
+ * evaluated on that grid) from (d_uc, d_Wc) to tol_c with mg_solve_constraints
+ * (rep_c may be NULL), then interpolates u and, when both W arrays are given,
+ * every W component to the fine grid of cf with the cubic of mg_interp_cubic
+ * (d_uf: (2n)^3, d_Wf: 3 (2n)^3).  The fine arrays are written also when the
+ * coarse solve stops at max_outer (status MG_ERR_NOT_CONVERGED); other
+ * failures leave them untouched.  Both contexts must use the same stream.
+ */
+mg_status mg_fmg_start(mg_ctx *cc, mg_ctx *cf, double *d_uc, double *d_Wc, double tol_c,
+                       int32_t max_outer, double *d_uf, double *d_Wf, mg_report *rep_c);
+
+/*
  * Single-kernel entry points on one level of a context, for diagnostics and
  * kernel-level parity checks.  Arrays are in the context's V-cycle type
  * (double for MG_PREC_FP64, float for MG_PREC_FP32_IR), on level `level`

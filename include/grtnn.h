@@ -126,16 +126,20 @@ mg_status nn_pack_target(nn_ctx *ctx, const double *d_u, const double *d_W, cons
 mg_status nn_unpack_output(nn_ctx *ctx, const float *d_out, const nn_norm *norm, double *d_u,
                            double *d_W);
 
-/* Sum and sum of squares of an FP64 array (for the standardisation
- * statistics); h_out[0] = sum, h_out[1] = sum of squares; waits. */
-mg_status nn_moments(nn_ctx *ctx, const double *d_x, int64_t count, double h_out[2]);
+/* Sum and sum of squares of v = x + y over count FP64 values (d_y may be
+ * null: v = x), for the standardisation statistics; h_out[0] = sum of v,
+ * h_out[1] = sum of v^2; waits. */
+mg_status nn_moments(nn_ctx *ctx, const double *d_x, const double *d_y, int64_t count, double h_out[2]);
 
-/* Warm start of a constraint solve: predicts (u, W) from the context's input
- * sources into d_u, d_W, compares the RMS Hamiltonian residual of the
- * prediction with that of the zero state (mg_residual_norm of the solver
- * context), and keeps the prediction only if it is finite and smaller
- * (*h_used = 1); otherwise d_u and d_W are set to zero (*h_used = 0).
- * h_norms receives the two residual RMS pairs (prediction H, M; zero H, M). */
+/* Warm start of a constraint solve: predicts (u, W) from the sources into
+ * d_u, d_W, applies one outer iteration of the solver to it (mg_vcycle with
+ * MG_EQ_BOTH, or MG_EQ_PSI for a context without the momentum equation: the
+ * smoother removes the BF16-level roughness of the prediction at once), and
+ * keeps the result (*h_used = 1) only if its RMS constraint residuals are
+ * finite and their maximum is below that of the zero state u = 0, W = 0;
+ * otherwise d_u and d_W are set to zero (*h_used = 0).  The solver context
+ * must belong to the same grid (n^3, periodic) and use the same stream.
+ * h_norms (may be NULL): RMS H, M after the iteration; RMS H, M of the zero state. */
 mg_status nn_warm_start(nn_ctx *ctx, mg_ctx *solver, const double *d_rho5, const double *d_rho1,
                         const double *d_S, const nn_norm *norm, double *d_u, double *d_W,
                         int32_t *h_used, double h_norms[4]);

@@ -1389,6 +1389,35 @@ mg_status mg_interp_cubic(const mg_params *pc, const double *d_coarse, double *d
     return hip_status();
 }
 
+mg_status mg_fmg_start(mg_ctx *cc, mg_ctx *cf, double *d_uc, double *d_Wc, double tol_c, int32_t max_outer,
+                       double *d_uf, double *d_Wf, mg_report *rep_c)
+{
+    if (!cc || !cf || !d_uc || !d_uf || !(tol_c > 0.0) || max_outer < 0) return MG_ERR_INVALID;
+    const mg_params &a = cc->p, &b = cf->p;
+    if (b.n != 2 * a.n || a.bc != b.bc || a.length != b.length || cc->momentum != cf->momentum) return MG_ERR_INVALID;
+    for (int q = 0; q < 3; q++)
+        if (a.origin[q] != b.origin[q] || a.puncture_pos[q] != b.puncture_pos[q]) return MG_ERR_INVALID;
+    if (cf->momentum && (!d_Wc || !d_Wf)) return MG_ERR_INVALID;
+    const mg_status st = mg_solve_constraints(cc, d_uc, d_Wc, tol_c, max_outer, rep_c);
+    if (st != MG_OK && st != MG_ERR_NOT_CONVERGED) return st;
+    // the fine context's stream waits for the caller's stream (after the coarse solve)
+    enter(cf);
+    const Geo gc = make_geo(a.n, a.bc, a.length, a.origin, a.puncture_pos);
+    const int64_t mc = (int64_t)a.n * a.n * a.n, mf = 8 * mc;
+    const int ncomp = (cf->momentum || (d_Wc && d_Wf)) ? 4 : 1;
+    for (int q = 0; q < ncomp; q++) {
+        const double *src = q == 0 ? d_uc : d_Wc + (q - 1) * mc;
+        double *dst = q == 0 ? d_uf : d_Wf + (q - 1) * mf;
+        if (a.bc == MG_BC_PERIODIC)
+            hipLaunchKernelGGL(k_interp_cubic<kBcPeriodic>, dim3(nblk(mf)), dim3(kBlock), 0, cf->s, gc, src, dst);
+        else
+            hipLaunchKernelGGL(k_interp_cubic<kBcRobin>, dim3(nblk(mf)), dim3(kBlock), 0, cf->s, gc, src, dst);
+    }
+    leave(cf);
+    if (hip_status() != MG_OK) return MG_ERR_HIP;
+    return st;
+}
+
 mg_status mg_kernel_op(mg_ctx *c, int32_t op, int32_t level, int32_t arg, const void *d_in, void *d_out,
                        const void *d_r, const void *d_c)
 {

@@ -21,7 +21,7 @@ using namespace grtnn;
 namespace {
 
 constexpr int kMaxLayers = 15;      // 4 levels: 8 encoder + 6 decoder convolutions + head
-constexpr int kWgradBlocks = 1024;  // target grid of the weight-gradient kernel
+constexpr int kWgradBlocks = 512;   // target grid of the weight-gradient kernel
 constexpr int kMomentBlocks = 1024; // grid of the moments kernel
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -44,25 +44,48 @@ struct Layer {
     int cin, cout;        // real channels
     int cin_pad, cout8;   // stored input channels; cout rounded up to 8
     int64_t w_off, b_off; // offsets in the parameter array
+    int c1, c2;           // the input as a concatenation of two tensors (c2 = 0: one)
+    KOrder ko, ko_t;      // K order of the forward / backward-data GEMM
     int nchunk, ntile;    // forward GEMM: K steps, N tiles
     int nchunk_t, ntile_t; // backward-data GEMM (0 tiles: not needed)
     u32x4 *wf, *wt;       // packed weights
     float *bias;          // FP32 copy of the biases
 };
 
-void make_layer(Layer &ly, int cin, int cout, int cin_pad, bool need_bwd_data, int64_t &off)
+// Channel slice of the K order: the largest of 32, 16, 8 dividing both inputs.
+int slice_width(int c1, int c2)
+{
+    for (int cs = 32; cs >= 8; cs /= 2)
+        if (c1 % cs == 0 && c2 % cs == 0) return cs;
+    return 8;
+}
+
+KOrder korder(int c1, int c2, int &nchunk)
+{
+    KOrder k;
+    k.cs = slice_width(c1, c2);
+    k.spp = ceil_div(27 * k.cs, 32);
+    nchunk = (c1 + c2) / k.cs * k.spp;
+    return k;
+}
+
+// A convolution cin -> cout whose input is stored as [c1 channels, c2 channels]
+// (c1 + c2 = cin_pad >= cin).
+void make_layer(Layer &ly, int cin, int cout, int c1, int c2, bool need_bwd_data, int64_t &off)
 {
     ly.cin = cin;
     ly.cout = cout;
-    ly.cin_pad = cin_pad;
+    ly.c1 = c1;
+    ly.c2 = c2;
+    ly.cin_pad = c1 + c2;
     ly.cout8 = (cout + 7) / 8 * 8;
     ly.w_off = off;
     off += (int64_t)27 * cin * cout;
     ly.b_off = off;
     off += cout;
-    ly.nchunk = ceil_div(27 * (cin_pad / 8), 4);
+    ly.ko = korder(c1, c2, ly.nchunk);
     ly.ntile = ceil_div(cout, 16);
-    ly.nchunk_t = ceil_div(27 * (ly.cout8 / 8), 4);
+    ly.ko_t = korder(ly.cout8, 0, ly.nchunk_t);
     ly.ntile_t = need_bwd_data ? ceil_div(cin, 16) : 0;
     ly.wf = ly.wt = nullptr;
     ly.bias = nullptr;
@@ -72,19 +95,26 @@ size_t packed_bytes(int ntile, int nchunk) { return (size_t)ntile * nchunk * 64 
 
 // Split of the weight-gradient reduction over cells for one layer.
 struct WSplit {
-    int cot, cit, nsplit, steps;
+    int cot, cit, nsplit, steps, bricks;
 };
 
-WSplit wsplit(int cin_pad, int cout, int64_t V)
+bool brick_ok(int n) { return n >= 16 && n % 16 == 0; }
+
+// Cells of one weight-gradient launch are split into nsplit ranges: 32-cell
+// steps (general kernel) or 4 x 4 x 16 bricks (brick kernel, brick = true).
+WSplit wsplit(int cin_pad, int cout, int n, bool brick)
 {
     WSplit w;
+    const int64_t V = (int64_t)n * n * n;
     w.cot = ceil_div(cout, 16);
     w.cit = ceil_div(cin_pad, 16);
-    const int64_t nsteps = (V + 31) / 32;
+    const int64_t units = brick ? V / 256 : (V + 31) / 32;
     int ns = ceil_div(kWgradBlocks, (int64_t)w.cot * w.cit);
-    ns = std::max(1, std::min<int>(ns, ceil_div(nsteps, 4)));
-    w.steps = ceil_div(nsteps, ns);
-    w.nsplit = ceil_div(nsteps, w.steps);
+    ns = std::max(1, std::min<int>(ns, brick ? (int)units : ceil_div(units, 4)));
+    const int per = ceil_div(units, ns);
+    w.nsplit = ceil_div(units, per);
+    w.steps = brick ? 0 : per;
+    w.bricks = brick ? per : 0;
     return w;
 }
 
@@ -114,7 +144,12 @@ struct nn_ctx {
     int64_t V[4];
     Layer layer[kMaxLayers];
     int64_t nparams;
-    u16 *za[4], *zb[4], *pl[4], *upb[4], *zda[4], *zdb[4];
+    // per level: pre-activations z* (training only) and activations a* of the
+    // encoder convolutions (a, b), the decoder convolutions (da, db), the
+    // pooled input pl and the upsampled decoder input upb
+    u16 *za[4], *zb[4], *zda[4], *zdb[4];
+    u16 *aa[4], *ab[4], *ada[4], *adb[4];
+    u16 *pl[4], *upb[4];
     u16 *x;
     float *out;
     u16 *dzH, *dzA, *dzB;
@@ -143,15 +178,14 @@ void plan(nn_ctx *c)
     int k = 0;
     for (int l = 0; l < c->L; l++) {
         const int cin = l == 0 ? g.c_in : g.ch[l - 1];
-        make_layer(c->layer[k++], cin, g.ch[l], l == 0 ? 8 : cin, l > 0, off);
-        make_layer(c->layer[k++], g.ch[l], g.ch[l], g.ch[l], true, off);
+        make_layer(c->layer[k++], cin, g.ch[l], l == 0 ? 8 : cin, 0, l > 0, off);
+        make_layer(c->layer[k++], g.ch[l], g.ch[l], g.ch[l], 0, true, off);
     }
     for (int l = c->L - 2; l >= 0; l--) {
-        const int cin = g.ch[l] + g.ch[l + 1];
-        make_layer(c->layer[k++], cin, g.ch[l], cin, true, off);
-        make_layer(c->layer[k++], g.ch[l], g.ch[l], g.ch[l], true, off);
+        make_layer(c->layer[k++], g.ch[l] + g.ch[l + 1], g.ch[l], g.ch[l], g.ch[l + 1], true, off);
+        make_layer(c->layer[k++], g.ch[l], g.ch[l], g.ch[l], 0, true, off);
     }
-    make_layer(c->layer[k++], g.ch[0], g.c_out, g.ch[0], true, off);
+    make_layer(c->layer[k++], g.ch[0], g.c_out, g.ch[0], 0, true, off);
     c->nlayers = k;
     c->nparams = off;
 }
@@ -167,17 +201,18 @@ void carve(nn_ctx *c, Carver &cv)
         ly.bias = (float *)cv.take((size_t)ly.cout * sizeof(float));
     }
     for (int l = 0; l < L; l++) {
-        const size_t V = (size_t)c->V[l];
-        c->za[l] = (u16 *)cv.take(V * g.ch[l] * 2);
-        c->zb[l] = (u16 *)cv.take(V * g.ch[l] * 2);
-        c->pl[l] = l > 0 ? (u16 *)cv.take(V * g.ch[l - 1] * 2) : nullptr;
-        if (l <= L - 2) {
-            c->upb[l] = (u16 *)cv.take(V * g.ch[l + 1] * 2);
-            c->zda[l] = (u16 *)cv.take(V * g.ch[l] * 2);
-            c->zdb[l] = (u16 *)cv.take(V * g.ch[l] * 2);
-        } else {
-            c->upb[l] = c->zda[l] = c->zdb[l] = nullptr;
-        }
+        const size_t bytes = (size_t)c->V[l] * g.ch[l] * 2;
+        const bool dec = l <= L - 2;
+        c->aa[l] = (u16 *)cv.take(bytes);
+        c->ab[l] = (u16 *)cv.take(bytes);
+        c->za[l] = c->training ? (u16 *)cv.take(bytes) : nullptr;
+        c->zb[l] = c->training ? (u16 *)cv.take(bytes) : nullptr;
+        c->ada[l] = dec ? (u16 *)cv.take(bytes) : nullptr;
+        c->adb[l] = dec ? (u16 *)cv.take(bytes) : nullptr;
+        c->zda[l] = dec && c->training ? (u16 *)cv.take(bytes) : nullptr;
+        c->zdb[l] = dec && c->training ? (u16 *)cv.take(bytes) : nullptr;
+        c->pl[l] = l > 0 ? (u16 *)cv.take((size_t)c->V[l] * g.ch[l - 1] * 2) : nullptr;
+        c->upb[l] = dec ? (u16 *)cv.take((size_t)c->V[l] * g.ch[l + 1] * 2) : nullptr;
     }
     c->x = (u16 *)cv.take((size_t)c->V[0] * 8 * 2);
     c->out = (float *)cv.take((size_t)c->V[0] * g.c_out * 4);
@@ -207,9 +242,11 @@ void carve(nn_ctx *c, Carver &cv)
         // every layer of level l runs its weight gradient on V[l] cells
         for (int k = 0; k < c->nlayers; k++) {
             const Layer &ly = c->layer[k];
-            const WSplit w = wsplit(ly.cin_pad, ly.cout, c->V[l]);
-            pf = std::max(pf, wsplit_floats(w));
-            pb = std::max(pb, (size_t)w.nsplit * w.cot * 16);
+            for (int br = 0; br < 2; br++) {
+                const WSplit w = wsplit(ly.cin_pad, ly.cout, c->nl[l], br == 1 && brick_ok(c->nl[l]));
+                pf = std::max(pf, wsplit_floats(w));
+                pb = std::max(pb, (size_t)w.nsplit * w.cot * 16);
+            }
         }
     }
     c->part = (float *)cv.take(pf * 4);
@@ -222,7 +259,23 @@ struct Out {
     int channels = 0, mode = kEpStoreBf16;
     void *ptr = nullptr;
     const u16 *zref = nullptr;
+    u16 *zout = nullptr; // kEpSiluBf16: pre-activations (first destination only)
 };
+
+
+
+// Brick kernel launch: one block per 4 x 4 x 16 brick (n a multiple of 16).
+template <int NTB>
+void launch_conv_brick(hipStream_t s, const ConvArgs &a, int n, int cs, unsigned gy)
+{
+    const dim3 grid((unsigned)((int64_t)n * n * n / 256), gy);
+    if (cs == 32)
+        hipLaunchKernelGGL((k_conv3_brick<NTB, 32>), grid, dim3(kNBlock), 0, s, a);
+    else if (cs == 16)
+        hipLaunchKernelGGL((k_conv3_brick<NTB, 16>), grid, dim3(kNBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_conv3_brick<NTB, 8>), grid, dim3(kNBlock), 0, s, a);
+}
 
 void launch_conv(hipStream_t s, const Layer &ly, bool transposed, int n, const u16 *in1, int c1, int act1,
                  const u16 *in2, int c2, int act2, const float *bias, Out o1, Out o2)
@@ -237,6 +290,7 @@ void launch_conv(hipStream_t s, const Layer &ly, bool transposed, int n, const u
     a.w = transposed ? ly.wt : ly.wf;
     a.bias = bias;
     a.n = n;
+    a.ko = transposed ? ly.ko_t : ly.ko;
     a.nchunk = transposed ? ly.nchunk_t : ly.nchunk;
     a.ntile = transposed ? ly.ntile_t : ly.ntile;
     a.oc1 = o1.channels;
@@ -248,24 +302,37 @@ void launch_conv(hipStream_t s, const Layer &ly, bool transposed, int n, const u
     a.out2 = o2.ptr;
     a.zref1 = o1.zref;
     a.zref2 = o2.zref;
-    const int64_t V = (int64_t)n * n * n;
-    const unsigned gx = (unsigned)ceil_div(V, (int64_t)(kNBlock / 64) * 16 * kRows);
+    a.zout1 = o1.zout;
+    // the brick kernel reads activations as stored (no SiLU on load)
+    const bool brick = brick_ok(n) && !act1 && !act2;
     const int ntb = std::min(a.ntile, 4);
-    const dim3 grid(gx, (unsigned)ceil_div(a.ntile, ntb));
+    const unsigned gy = (unsigned)ceil_div(a.ntile, ntb);
+    if (!brick) {
+        const int64_t V = (int64_t)n * n * n;
+        const dim3 grid((unsigned)ceil_div(V, (int64_t)(kNBlock / 64) * 16 * kRows), gy);
+        switch (ntb) {
+        case 1: hipLaunchKernelGGL(k_conv3<1>, grid, dim3(kNBlock), 0, s, a); break;
+        case 2: hipLaunchKernelGGL(k_conv3<2>, grid, dim3(kNBlock), 0, s, a); break;
+        case 3: hipLaunchKernelGGL(k_conv3<3>, grid, dim3(kNBlock), 0, s, a); break;
+        default: hipLaunchKernelGGL(k_conv3<4>, grid, dim3(kNBlock), 0, s, a); break;
+        }
+        return;
+    }
     switch (ntb) {
-    case 1: hipLaunchKernelGGL(k_conv3<1>, grid, dim3(kNBlock), 0, s, a); break;
-    case 2: hipLaunchKernelGGL(k_conv3<2>, grid, dim3(kNBlock), 0, s, a); break;
-    case 3: hipLaunchKernelGGL(k_conv3<3>, grid, dim3(kNBlock), 0, s, a); break;
-    default: hipLaunchKernelGGL(k_conv3<4>, grid, dim3(kNBlock), 0, s, a); break;
+    case 1: launch_conv_brick<1>(s, a, n, a.ko.cs, gy); break;
+    case 2: launch_conv_brick<2>(s, a, n, a.ko.cs, gy); break;
+    case 3: launch_conv_brick<3>(s, a, n, a.ko.cs, gy); break;
+    default: launch_conv_brick<4>(s, a, n, a.ko.cs, gy); break;
     }
 }
 
 // weight and bias gradients of layer ly (input [in1, in2], output gradient dy)
-void launch_wgrad(hipStream_t s, const Layer &ly, int n, const u16 *in1, int c1, int act1, const u16 *in2, int c2,
-                  int act2, const u16 *dy, int cy, float *part, float *partb, float *grad, int accumulate)
+void launch_wgrad_to(hipStream_t s, const Layer &ly, int n, const u16 *in1, int c1, int act1, const u16 *in2,
+                     int c2, int act2, const u16 *dy, int cy, float *part, float *partb, float *gw, float *gb,
+                     int accumulate)
 {
-    const int64_t V = (int64_t)n * n * n;
-    const WSplit w = wsplit(ly.cin_pad, ly.cout, V);
+    const bool brick = brick_ok(n) && !act1 && !act2;
+    const WSplit w = wsplit(ly.cin_pad, ly.cout, n, brick);
     WgtArgs a;
     a.in1 = in1;
     a.in2 = in2;
@@ -282,22 +349,36 @@ void launch_wgrad(hipStream_t s, const Layer &ly, int n, const u16 *in1, int c1,
     a.cit = w.cit;
     a.part = part;
     a.partb = partb;
-    hipLaunchKernelGGL(k_conv3_wgrad, dim3(w.cot, w.cit, w.nsplit), dim3(kNBlock), 0, s, a);
+    if (brick) {
+        WgtBrick wb;
+        wb.a = a;
+        wb.a.cit = w.cit;
+        wb.bricks_per_split = w.bricks;
+        hipLaunchKernelGGL(k_conv3_wgrad_brick, dim3(w.cot, w.cit, w.nsplit), dim3(kNBlock), 0, s, wb);
+    } else {
+        hipLaunchKernelGGL(k_conv3_wgrad, dim3(w.cot, w.cit, w.nsplit), dim3(kNBlock), 0, s, a);
+    }
     const int64_t nw = (int64_t)ly.cout * ly.cin * 27;
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblk(nw + ly.cout)), dim3(kNBlock), 0, s, (const float *)part,
-                       (const float *)partb, w.nsplit, w.cot, w.cit, ly.cout, ly.cin, grad + ly.w_off,
-                       grad + ly.b_off, accumulate);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(ceil_div(nw + ly.cout, 16)), dim3(kNBlock), 0, s, (const float *)part,
+                       (const float *)partb, w.nsplit, w.cot, w.cit, ly.cout, ly.cin, gw, gb, accumulate);
+}
+
+void launch_wgrad(hipStream_t s, const Layer &ly, int n, const u16 *in1, int c1, int act1, const u16 *in2, int c2,
+                  int act2, const u16 *dy, int cy, float *part, float *partb, float *grad, int accumulate)
+{
+    launch_wgrad_to(s, ly, n, in1, c1, act1, in2, c2, act2, dy, cy, part, partb, grad + ly.w_off, grad + ly.b_off,
+                    accumulate);
 }
 
 void pack_layer(hipStream_t s, const Layer &ly, const float *params)
 {
     const float *W = params + ly.w_off;
     const int64_t nf = (int64_t)ly.ntile * ly.nchunk * 64;
-    hipLaunchKernelGGL(k_pack_weights, dim3(nblk(nf)), dim3(kNBlock), 0, s, W, ly.cin, ly.cout, ly.cin_pad,
-                       ly.nchunk, ly.ntile, 0, ly.wf);
+    hipLaunchKernelGGL(k_pack_weights, dim3(nblk(nf)), dim3(kNBlock), 0, s, W, ly.cin, ly.cout, ly.ko, ly.nchunk,
+                       ly.ntile, 0, ly.wf);
     if (ly.ntile_t) {
         const int64_t nt = (int64_t)ly.ntile_t * ly.nchunk_t * 64;
-        hipLaunchKernelGGL(k_pack_weights, dim3(nblk(nt)), dim3(kNBlock), 0, s, W, ly.cin, ly.cout, ly.cout8,
+        hipLaunchKernelGGL(k_pack_weights, dim3(nblk(nt)), dim3(kNBlock), 0, s, W, ly.cin, ly.cout, ly.ko_t,
                            ly.nchunk_t, ly.ntile_t, 1, ly.wt);
     }
     if (ly.bias)
@@ -329,49 +410,58 @@ bool norm_ok(const nn_norm *nm)
     return true;
 }
 
+// Output descriptor of a forward convolution: SiLU activations (+ pre-activations)
+Out act_out(int channels, u16 *a, u16 *z)
+{
+    Out o;
+    o.channels = channels;
+    o.mode = kEpSiluBf16;
+    o.ptr = a;
+    o.zout = z;
+    return o;
+}
+
 void forward(nn_ctx *c, const u16 *in, float *out)
 {
     const nn_config &g = c->cfg;
     const int L = c->L;
     hipStream_t s = c->s;
+    const Out none;
     c->last_in = in;
     for (int l = 0; l < L; l++) {
         const int n = c->nl[l];
         const Layer &la = c->layer[enc_layer(l, 0)], &lb = c->layer[enc_layer(l, 1)];
-        Out oa, ob, none;
-        oa.channels = ob.channels = g.ch[l];
-        oa.ptr = c->za[l];
-        ob.ptr = c->zb[l];
         if (l == 0) {
-            launch_conv(s, la, false, n, in, 8, 0, nullptr, 0, 0, la.bias, oa, none);
+            launch_conv(s, la, false, n, in, 8, 0, nullptr, 0, 0, la.bias, act_out(g.ch[0], c->aa[0], c->za[0]),
+                        none);
         } else {
             const int64_t e = c->V[l] * (g.ch[l - 1] / 8);
-            hipLaunchKernelGGL(k_pool, dim3(nblk(e)), dim3(kNBlock), 0, s, (const u16 *)c->zb[l - 1], g.ch[l - 1], n,
-                               1, c->pl[l]);
-            launch_conv(s, la, false, n, c->pl[l], g.ch[l - 1], 0, nullptr, 0, 0, la.bias, oa, none);
+            hipLaunchKernelGGL(k_pool, dim3(nblk(e)), dim3(kNBlock), 0, s, (const u16 *)c->ab[l - 1], g.ch[l - 1], n,
+                               0, c->pl[l]);
+            launch_conv(s, la, false, n, c->pl[l], g.ch[l - 1], 0, nullptr, 0, 0, la.bias,
+                        act_out(g.ch[l], c->aa[l], c->za[l]), none);
         }
-        launch_conv(s, lb, false, n, c->za[l], g.ch[l], 1, nullptr, 0, 0, lb.bias, ob, none);
+        launch_conv(s, lb, false, n, c->aa[l], g.ch[l], 0, nullptr, 0, 0, lb.bias,
+                    act_out(g.ch[l], c->ab[l], c->zb[l]), none);
     }
     for (int l = L - 2; l >= 0; l--) {
         const int n = c->nl[l];
-        const u16 *src = (l == L - 2) ? c->zb[L - 1] : c->zdb[l + 1];
+        const u16 *src = (l == L - 2) ? c->ab[L - 1] : c->adb[l + 1];
         const int64_t e = c->V[l] * (g.ch[l + 1] / 8);
-        hipLaunchKernelGGL(k_up, dim3(nblk(e)), dim3(kNBlock), 0, s, src, g.ch[l + 1], c->nl[l + 1], 1, c->upb[l]);
-        Out oa, ob, none;
-        oa.channels = ob.channels = g.ch[l];
-        oa.ptr = c->zda[l];
-        ob.ptr = c->zdb[l];
+        hipLaunchKernelGGL(k_up, dim3(nblk(e)), dim3(kNBlock), 0, s, src, g.ch[l + 1], c->nl[l + 1], 0, c->upb[l]);
         const Layer &da = c->layer[dec_layer(c, l, 0)], &db = c->layer[dec_layer(c, l, 1)];
-        launch_conv(s, da, false, n, c->zb[l], g.ch[l], 1, c->upb[l], g.ch[l + 1], 0, da.bias, oa, none);
-        launch_conv(s, db, false, n, c->zda[l], g.ch[l], 1, nullptr, 0, 0, db.bias, ob, none);
+        launch_conv(s, da, false, n, c->ab[l], g.ch[l], 0, c->upb[l], g.ch[l + 1], 0, da.bias,
+                    act_out(g.ch[l], c->ada[l], c->zda[l]), none);
+        launch_conv(s, db, false, n, c->ada[l], g.ch[l], 0, nullptr, 0, 0, db.bias,
+                    act_out(g.ch[l], c->adb[l], c->zdb[l]), none);
     }
-    const u16 *top = L >= 2 ? c->zdb[0] : c->zb[0];
-    Out oh, none;
+    const u16 *top = L >= 2 ? c->adb[0] : c->ab[0];
+    Out oh;
     oh.channels = g.c_out;
     oh.mode = kEpStoreF32;
     oh.ptr = out;
     const Layer &lh = c->layer[head_layer(c)];
-    launch_conv(s, lh, false, c->nl[0], top, g.ch[0], 1, nullptr, 0, 0, lh.bias, oh, none);
+    launch_conv(s, lh, false, c->nl[0], top, g.ch[0], 0, nullptr, 0, 0, lh.bias, oh, none);
 }
 
 } // namespace
@@ -411,45 +501,52 @@ mg_status nn_workspace_size(const nn_config *cfg, int32_t training, size_t *byte
 
 namespace {
 
+Out dsilu_out(int channels, u16 *dz, const u16 *z)
+{
+    Out o;
+    o.channels = channels;
+    o.mode = kEpDsiluBf16;
+    o.ptr = dz;
+    o.zref = z;
+    return o;
+}
+
+Out f32_out(int channels, float *p)
+{
+    Out o;
+    o.channels = channels;
+    o.mode = kEpStoreF32;
+    o.ptr = p;
+    return o;
+}
+
+// Backward pass for the loss gradient in dzH.  Weight gradients read the stored
+// activations; the SiLU derivative reads the stored pre-activations.
 void backward(nn_ctx *c, float *grad)
 {
     const nn_config &g = c->cfg;
     const int L = c->L;
     hipStream_t s = c->s;
-    const u16 *top = L >= 2 ? c->zdb[0] : c->zb[0];
-    Out none;
-    // head: no activation on its output; dz = loss gradient (8 stored channels)
+    const Out none;
+    const u16 *top_a = L >= 2 ? c->adb[0] : c->ab[0];
+    const u16 *top_z = L >= 2 ? c->zdb[0] : c->zb[0];
     {
         const Layer &lh = c->layer[head_layer(c)];
-        launch_wgrad(s, lh, c->nl[0], top, g.ch[0], 1, nullptr, 0, 0, c->dzH, 8, c->part, c->partb, grad, 1);
-        Out o;
-        o.channels = g.ch[0];
-        o.mode = kEpDsiluBf16;
-        o.ptr = c->dzB;
-        o.zref = top;
-        launch_conv(s, lh, true, c->nl[0], c->dzH, lh.cout8, 0, nullptr, 0, 0, nullptr, o, none);
+        launch_wgrad(s, lh, c->nl[0], top_a, g.ch[0], 0, nullptr, 0, 0, c->dzH, 8, c->part, c->partb, grad, 1);
+        launch_conv(s, lh, true, c->nl[0], c->dzH, lh.cout8, 0, nullptr, 0, 0, nullptr,
+                    dsilu_out(g.ch[0], c->dzB, top_z), none);
     }
     // decoder, from the top level down; dzB holds the gradient of the level's output
     for (int l = 0; l <= L - 2; l++) {
         const int n = c->nl[l];
         const Layer &da = c->layer[dec_layer(c, l, 0)], &db = c->layer[dec_layer(c, l, 1)];
-        launch_wgrad(s, db, n, c->zda[l], g.ch[l], 1, nullptr, 0, 0, c->dzB, g.ch[l], c->part, c->partb, grad, 1);
-        Out oa;
-        oa.channels = g.ch[l];
-        oa.mode = kEpDsiluBf16;
-        oa.ptr = c->dzA;
-        oa.zref = c->zda[l];
-        launch_conv(s, db, true, n, c->dzB, g.ch[l], 0, nullptr, 0, 0, nullptr, oa, none);
-        launch_wgrad(s, da, n, c->zb[l], g.ch[l], 1, c->upb[l], g.ch[l + 1], 0, c->dzA, g.ch[l], c->part, c->partb,
+        launch_wgrad(s, db, n, c->ada[l], g.ch[l], 0, nullptr, 0, 0, c->dzB, g.ch[l], c->part, c->partb, grad, 1);
+        launch_conv(s, db, true, n, c->dzB, g.ch[l], 0, nullptr, 0, 0, nullptr, dsilu_out(g.ch[l], c->dzA, c->zda[l]),
+                    none);
+        launch_wgrad(s, da, n, c->ab[l], g.ch[l], 0, c->upb[l], g.ch[l + 1], 0, c->dzA, g.ch[l], c->part, c->partb,
                      grad, 1);
-        Out o1, o2;
-        o1.channels = g.ch[l];
-        o1.mode = kEpStoreF32;
-        o1.ptr = c->skipg[l];
-        o2.channels = g.ch[l + 1];
-        o2.mode = kEpStoreF32;
-        o2.ptr = c->upg;
-        launch_conv(s, da, true, n, c->dzA, g.ch[l], 0, nullptr, 0, 0, nullptr, o1, o2);
+        launch_conv(s, da, true, n, c->dzA, g.ch[l], 0, nullptr, 0, 0, nullptr, f32_out(g.ch[l], c->skipg[l]),
+                    f32_out(g.ch[l + 1], c->upg));
         const u16 *zref = (l + 1 == L - 1) ? c->zb[L - 1] : c->zdb[l + 1];
         const int64_t e = c->V[l + 1] * g.ch[l + 1];
         hipLaunchKernelGGL(k_up_adjoint_dsilu, dim3(nblk(e)), dim3(kNBlock), 0, s, (const float *)c->upg,
@@ -459,24 +556,16 @@ void backward(nn_ctx *c, float *grad)
     for (int l = L - 1; l >= 0; l--) {
         const int n = c->nl[l];
         const Layer &la = c->layer[enc_layer(l, 0)], &lb = c->layer[enc_layer(l, 1)];
-        launch_wgrad(s, lb, n, c->za[l], g.ch[l], 1, nullptr, 0, 0, c->dzB, g.ch[l], c->part, c->partb, grad, 1);
-        Out oa;
-        oa.channels = g.ch[l];
-        oa.mode = kEpDsiluBf16;
-        oa.ptr = c->dzA;
-        oa.zref = c->za[l];
-        launch_conv(s, lb, true, n, c->dzB, g.ch[l], 0, nullptr, 0, 0, nullptr, oa, none);
+        launch_wgrad(s, lb, n, c->aa[l], g.ch[l], 0, nullptr, 0, 0, c->dzB, g.ch[l], c->part, c->partb, grad, 1);
+        launch_conv(s, lb, true, n, c->dzB, g.ch[l], 0, nullptr, 0, 0, nullptr, dsilu_out(g.ch[l], c->dzA, c->za[l]),
+                    none);
         if (l == 0) {
             launch_wgrad(s, la, n, c->last_in, 8, 0, nullptr, 0, 0, c->dzA, g.ch[0], c->part, c->partb, grad, 1);
             break;
         }
         launch_wgrad(s, la, n, c->pl[l], g.ch[l - 1], 0, nullptr, 0, 0, c->dzA, g.ch[l], c->part, c->partb, grad,
                      1);
-        Out op;
-        op.channels = g.ch[l - 1];
-        op.mode = kEpStoreF32;
-        op.ptr = c->pg;
-        launch_conv(s, la, true, n, c->dzA, g.ch[l], 0, nullptr, 0, 0, nullptr, op, none);
+        launch_conv(s, la, true, n, c->dzA, g.ch[l], 0, nullptr, 0, 0, nullptr, f32_out(g.ch[l - 1], c->pg), none);
         const int64_t e = c->V[l - 1] * g.ch[l - 1];
         hipLaunchKernelGGL(k_pool_adjoint_dsilu, dim3(nblk(e)), dim3(kNBlock), 0, s, (const float *)c->pg,
                            (const float *)c->skipg[l - 1], g.ch[l - 1], n, (const u16 *)c->zb[l - 1], c->dzB);
@@ -607,11 +696,11 @@ mg_status nn_unpack_output(nn_ctx *c, const float *d_out, const nn_norm *norm, d
     return hip_ok();
 }
 
-mg_status nn_moments(nn_ctx *c, const double *d_x, int64_t count, double h_out[2])
+mg_status nn_moments(nn_ctx *c, const double *d_x, const double *d_y, int64_t count, double h_out[2])
 {
     if (!c || !d_x || count < 0 || !h_out) return MG_ERR_INVALID;
     const int B = kMomentBlocks;
-    hipLaunchKernelGGL(k_moments, dim3(B), dim3(kNBlock), 0, c->s, d_x, count, c->dpart);
+    hipLaunchKernelGGL(k_moments, dim3(B), dim3(kNBlock), 0, c->s, d_x, d_y, count, c->dpart);
     hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kNBlock), 0, c->s, (const double *)c->dpart, (int64_t)B,
                        c->dpart + 2 * B);
     hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kNBlock), 0, c->s, (const double *)(c->dpart + B), (int64_t)B,
@@ -648,6 +737,12 @@ mg_status nn_warm_start(nn_ctx *c, mg_ctx *solver, const double *d_rho5, const d
     st = nn_unpack_output(c, c->out, norm, d_u, d_W);
     if (st == MG_OK) st = sync_status(c->s);
     if (st != MG_OK) return st;
+    // one outer iteration first: the smoother removes the BF16-level roughness
+    // of the prediction at once, and the comparison is then about the smooth
+    // error that decides the remaining iterations
+    st = mg_vcycle(solver, MG_EQ_BOTH, d_u, d_W);
+    if (st == MG_ERR_INVALID) st = mg_vcycle(solver, MG_EQ_PSI, d_u, d_W);
+    if (st != MG_OK) return st;
     st = mg_residual_norm(solver, d_u, d_W, pred);
     if (st != MG_OK) return st;
     const double wz = std::max(zero[0], zero[1]), wp = std::max(pred[0], pred[1]);
@@ -682,7 +777,7 @@ Layer op_layer(int cin, int cout)
 {
     Layer ly;
     int64_t off = 0;
-    make_layer(ly, cin, cout, cin, true, off);
+    make_layer(ly, cin, cout, cin, 0, true, off);
     return ly;
 }
 
@@ -693,13 +788,18 @@ struct OpScratch {
 OpScratch op_scratch(int32_t cin, int32_t cout, int32_t n)
 {
     const Layer ly = op_layer(cin, cout);
-    const WSplit w = wsplit(ly.cin_pad, ly.cout, (int64_t)n * n * n);
+    size_t pf = 0, pb = 0;
+    for (int br = 0; br < 2; br++) {
+        const WSplit w = wsplit(ly.cin_pad, ly.cout, n, br == 1 && brick_ok(n));
+        pf = std::max(pf, wsplit_floats(w));
+        pb = std::max(pb, (size_t)w.nsplit * w.cot * 16);
+    }
     OpScratch o;
     o.wf = 0;
     o.wt = align_up(packed_bytes(ly.ntile, ly.nchunk), 256);
     o.part = o.wt + align_up(packed_bytes(ly.ntile_t, ly.nchunk_t), 256);
-    o.partb = o.part + align_up(wsplit_floats(w) * 4, 256);
-    o.total = o.partb + align_up((size_t)w.nsplit * w.cot * 16 * 4, 256);
+    o.partb = o.part + align_up(pf * 4, 256);
+    o.total = o.partb + align_up(pb * 4, 256);
     return o;
 }
 
@@ -724,7 +824,7 @@ mg_status nn_conv3_forward(int32_t n, int32_t cin, int32_t cout, const uint16_t 
     ly.wt = nullptr;
     ly.ntile_t = 0;
     const int64_t nf = (int64_t)ly.ntile * ly.nchunk * 64;
-    hipLaunchKernelGGL(k_pack_weights, dim3(nblk(nf)), dim3(kNBlock), 0, s, d_w, cin, cout, cin, ly.nchunk,
+    hipLaunchKernelGGL(k_pack_weights, dim3(nblk(nf)), dim3(kNBlock), 0, s, d_w, cin, cout, ly.ko, ly.nchunk,
                        ly.ntile, 0, ly.wf);
     Out oy, none;
     oy.channels = cout;
@@ -744,7 +844,7 @@ mg_status nn_conv3_backward_data(int32_t n, int32_t cin, int32_t cout, const uin
     Layer ly = op_layer(cin, cout);
     ly.wt = (u32x4 *)((char *)d_scratch + o.wt);
     const int64_t nt = (int64_t)ly.ntile_t * ly.nchunk_t * 64;
-    hipLaunchKernelGGL(k_pack_weights, dim3(nblk(nt)), dim3(kNBlock), 0, s, d_w, cin, cout, ly.cout8, ly.nchunk_t,
+    hipLaunchKernelGGL(k_pack_weights, dim3(nblk(nt)), dim3(kNBlock), 0, s, d_w, cin, cout, ly.ko_t, ly.nchunk_t,
                        ly.ntile_t, 1, ly.wt);
     Out ox, none;
     ox.channels = cin;
@@ -764,30 +864,9 @@ mg_status nn_conv3_backward_weight(int32_t n, int32_t cin, int32_t cout, const u
     if (scratch_bytes < o.total || ((uintptr_t)d_scratch % 256) != 0) return MG_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     Layer ly = op_layer(cin, cout);
-    // the reduction writes W (cout*cin*27) then b (cout) at these offsets of "grad"
     float *part = (float *)((char *)d_scratch + o.part), *partb = (float *)((char *)d_scratch + o.partb);
-    const int64_t V = (int64_t)n * n * n;
-    const WSplit w = wsplit(ly.cin_pad, ly.cout, V);
-    WgtArgs a;
-    a.in1 = d_x;
-    a.in2 = nullptr;
-    a.c1 = cin;
-    a.c2 = 0;
-    a.act1 = act;
-    a.act2 = 0;
-    a.dy = d_dy;
-    a.cy = ly.cout8;
-    a.cout = cout;
-    a.n = n;
-    a.steps_per_split = w.steps;
-    a.cot = w.cot;
-    a.cit = w.cit;
-    a.part = part;
-    a.partb = partb;
-    hipLaunchKernelGGL(k_conv3_wgrad, dim3(w.cot, w.cit, w.nsplit), dim3(kNBlock), 0, s, a);
-    const int64_t nw = (int64_t)cout * cin * 27;
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblk(nw + cout)), dim3(kNBlock), 0, s, (const float *)part,
-                       (const float *)partb, w.nsplit, w.cot, w.cit, cout, cin, d_dw, d_db, 0);
+    // the reduction overwrites dW (cout*cin*27) and db (cout)
+    launch_wgrad_to(s, ly, n, d_x, cin, act, nullptr, 0, 0, d_dy, ly.cout8, part, partb, d_dw, d_db, 0);
     return hip_ok();
 }
 

@@ -4,9 +4,9 @@
 // of a C-channel tensor is at v*C + c (C a multiple of 8, so one channel
 // octet is one aligned 16-byte load).  Convolutions are implicit GEMMs on
 // the BF16 matrix cores (v_mfma_f32_16x16x32_bf16, FP32 accumulate):
-//   M = cells (16 consecutive cells per tile), N = output channels (16 per
-//   tile), K = 27 taps x input channels, enumerated as channel octets
-//   (tap-major, octet-minor) and consumed 4 octets (32 values) per step.
+//   M = cells (16 per tile), N = output channels (16 per tile), K = 27 taps x
+//   input channels, enumerated as channel octets (see KOrder) and consumed
+//   4 octets (32 values) per step.
 // Lane l of a wave supplies row l%16 of A and column l%16 of B, each with
 // the 8 consecutive K values of octet l/16 of the step; it receives rows
 // 4*(l/16) .. 4*(l/16)+3 of column l%16 of the 16x16 result.
@@ -82,26 +82,78 @@ __device__ __forceinline__ f32x4 mfma(u32x4 a, u32x4 b, f32x4 c)
                                                    __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
-// ---- convolution (forward; backward data with flipped transposed weights) ----------
+// ---- K order shared by the packed weights and the convolution kernels --------------
+//
+// The input channels are processed in slices of cs channels (32, 16 or 8: the
+// largest that divides both concatenated inputs).  K step ch belongs to slice
+// ch / spp (spp = ceil(27 cs / 32) steps per slice); within the slice, lane
+// group g of step ch takes octet o = 4 (ch % spp) + g (octets o >= 27 cs / 8
+// are zero padding), i.e. tap o / (cs/8) and channels
+// slice * cs + 8 (o % (cs/8)) .. + 7.  Tap t = 9 kx + 3 ky + kz is the offset
+// (kx - 1, ky - 1, kz - 1).
 
-enum { kEpStoreBf16 = 0, kEpStoreF32 = 1, kEpAddF32 = 2, kEpDsiluBf16 = 3 };
+struct KOrder {
+    int cs, spp;
+    __device__ __forceinline__ bool at(int ch, int g, int &tap, int &c0) const
+    {
+        const int sl = ch / spp, o = (ch - sl * spp) * 4 + g;
+        const int per = cs >> 3;
+        if (o >= 27 * per) return false;
+        tap = o / per;
+        c0 = sl * cs + (o - tap * per) * 8;
+        return true;
+    }
+};
+
+// ---- convolution (forward; backward data with mirrored transposed weights) ----------
+
+enum { kEpStoreBf16 = 0, kEpStoreF32 = 1, kEpAddF32 = 2, kEpDsiluBf16 = 3, kEpSiluBf16 = 4 };
 
 struct ConvArgs {
     const u16 *in1, *in2; // input = concatenation [in1, in2] along channels
     int c1, c2;           // channels (= strides) of in1 / in2 (c2 = 0: no in2)
-    int act1, act2;       // apply SiLU to values read from in1 / in2
+    int act1, act2;       // apply SiLU to values read from in1 / in2 (general kernel only)
     const u32x4 *w;       // packed weights [tile][chunk][64 lanes] of 8 BF16
     const float *bias;    // per output channel, or null
     int n;                // cells per axis
-    int nchunk;           // K steps of 32
+    KOrder ko;            // K order of the packed weights
+    int nchunk;           // K steps
     int ntile;            // 16-wide output channel tiles of the layer
     int cout;             // output channels written = oc1 + oc2
     int oc1, oc2;         // output channels [0, oc1) -> out1, [oc1, cout) -> out2
     int mode1, mode2;     // epilogue per destination (kEp*)
     void *out1, *out2;
     const u16 *zref1, *zref2; // pre-activations (layout of out1 / out2) for kEpDsiluBf16
+    u16 *zout1;           // kEpSiluBf16: pre-activations of destination 1 (may be null)
 };
 
+// Epilogue of one value: output channel co of cell v
+__device__ __forceinline__ void conv_store(const ConvArgs &a, int co, int64_t v, float acc)
+{
+    const float val = acc + (a.bias ? a.bias[co] : 0.0f);
+    const bool first = co < a.oc1;
+    const int cc = first ? co : co - a.oc1;
+    const int oc = first ? a.oc1 : a.oc2;
+    const int mode = first ? a.mode1 : a.mode2;
+    void *out = first ? a.out1 : a.out2;
+    const int64_t idx = v * oc + cc;
+    if (mode == kEpSiluBf16) {
+        ((u16 *)out)[idx] = (u16)f2bf(silu(val));
+        if (a.zout1) a.zout1[idx] = (u16)f2bf(val);
+    } else if (mode == kEpStoreBf16) {
+        ((u16 *)out)[idx] = (u16)f2bf(val);
+    } else if (mode == kEpStoreF32) {
+        ((float *)out)[idx] = val;
+    } else if (mode == kEpAddF32) {
+        ((float *)out)[idx] += val;
+    } else {
+        const u16 *zr = first ? a.zref1 : a.zref2;
+        ((u16 *)out)[idx] = (u16)f2bf(val * dsilu(bf2f(zr[idx])));
+    }
+}
+
+// General kernel (any n): every wave computes 4 M tiles of 16 consecutive
+// cells and reads its A operands straight from global memory.
 template <int NTB>
 __global__ void __launch_bounds__(kNBlock) k_conv3(ConvArgs a)
 {
@@ -127,32 +179,19 @@ __global__ void __launch_bounds__(kNBlock) k_conv3(ConvArgs a)
     for (int q = 0; q < kRows; q++)
 #pragma unroll
         for (int t = 0; t < NTB; t++) acc[q][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int opt = (a.c1 + a.c2) >> 3; // channel octets per tap
-    const int G = 27 * opt;
     const u32x4 zero = {0u, 0u, 0u, 0u};
     for (int ch = 0; ch < a.nchunk; ch++) {
         u32x4 b[NTB];
 #pragma unroll
         for (int t = 0; t < NTB; t++)
             b[t] = (t0 + t < a.ntile) ? a.w[((int64_t)(t0 + t) * a.nchunk + ch) * 64 + lane] : zero;
-        const int oct = ch * 4 + g;
+        int tap, cg;
         u32x4 av[kRows];
-        if (oct < G) {
-            const int tap = oct / opt, o8 = oct - tap * opt;
+        if (a.ko.at(ch, g, tap, cg)) {
             const int dx = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dz = tap % 3 - 1;
-            const u16 *src;
-            int cs, c0, act;
-            if (o8 * 8 < a.c1) {
-                src = a.in1;
-                cs = a.c1;
-                c0 = o8 * 8;
-                act = a.act1;
-            } else {
-                src = a.in2;
-                cs = a.c2;
-                c0 = o8 * 8 - a.c1;
-                act = a.act2;
-            }
+            const bool one = cg < a.c1;
+            const u16 *src = one ? a.in1 : a.in2;
+            const int cs = one ? a.c1 : a.c2, c0 = one ? cg : cg - a.c1, act = one ? a.act1 : a.act2;
 #pragma unroll
             for (int q = 0; q < kRows; q++) {
                 const int x = wrapn(px[q] + dx, n), y = wrapn(py[q] + dy, n), z = wrapn(pz[q] + dz, n);
@@ -173,30 +212,191 @@ __global__ void __launch_bounds__(kNBlock) k_conv3(ConvArgs a)
     for (int t = 0; t < NTB; t++) {
         const int co = (t0 + t) * 16 + r;
         if (co >= a.cout) continue;
-        const float bias = a.bias ? a.bias[co] : 0.0f;
-        const bool first = co < a.oc1;
-        void *out = first ? a.out1 : a.out2;
-        const int cc = first ? co : co - a.oc1;
-        const int oc = first ? a.oc1 : a.oc2;
-        const int mode = first ? a.mode1 : a.mode2;
-        const u16 *zr = first ? a.zref1 : a.zref2;
 #pragma unroll
         for (int q = 0; q < kRows; q++)
 #pragma unroll
             for (int i = 0; i < 4; i++) {
                 const int64_t v = vb + q * 16 + 4 * g + i;
-                if (v >= V) continue;
-                const float val = acc[q][t][i] + bias;
-                const int64_t idx = v * oc + cc;
-                if (mode == kEpStoreBf16)
-                    ((u16 *)out)[idx] = (u16)f2bf(val);
-                else if (mode == kEpStoreF32)
-                    ((float *)out)[idx] = val;
-                else if (mode == kEpAddF32)
-                    ((float *)out)[idx] += val;
-                else
-                    ((u16 *)out)[idx] = (u16)f2bf(val * dsilu(bf2f(zr[idx])));
+                if (v < V) conv_store(a, co, v, acc[q][t][i]);
             }
+    }
+}
+
+// Brick kernel (n a multiple of 16): a block computes a brick of 4 x 4 x 16
+// cells (wave w: x0 + w; M tile q: y0 + q; row r: z0 + r).  For every channel
+// slice the block stages the brick's halo (6 x 6 x 18 cells x CS channels,
+// wrapped periodically) in LDS; every A operand is then one 16-byte LDS read,
+// and the 16 rows x 4 octets of a step are contiguous (conflict-free).
+constexpr int kHX = 6, kHY = 6, kHZ = 18;
+constexpr int kHalo = kHX * kHY * kHZ;
+
+__device__ __forceinline__ int brick_block(int nblocks)
+{
+    // consecutive bricks (which share halo cells) go to the same XCD
+    const int b = blockIdx.x;
+    return (nblocks % 8 == 0) ? (b % 8) * (nblocks / 8) + b / 8 : b;
+}
+
+// Epilogue of 8 consecutive output channels co0 .. co0+7 of cell v (values
+// without bias); vector stores where the octet is whole.
+__device__ __forceinline__ void conv_store8(const ConvArgs &a, int co0, int64_t v, const float (&acc)[8])
+{
+    if (co0 >= a.cout) return;
+    const bool first = co0 < a.oc1;
+    const int cc = first ? co0 : co0 - a.oc1;
+    const int oc = first ? a.oc1 : a.oc2;
+    const int mode = first ? a.mode1 : a.mode2;
+    void *out = first ? a.out1 : a.out2;
+    const int nv = min(8, a.cout - co0);
+    float f[8];
+#pragma unroll
+    for (int j = 0; j < 8; j++) f[j] = acc[j] + ((a.bias && j < nv) ? a.bias[co0 + j] : 0.0f);
+    const int64_t idx = v * oc + cc;
+    if (nv == 8 && mode != kEpStoreF32 && mode != kEpAddF32) {
+        if (mode == kEpSiluBf16) {
+            float s8[8];
+#pragma unroll
+            for (int j = 0; j < 8; j++) s8[j] = silu(f[j]);
+            *(u32x4 *)((u16 *)out + idx) = pack8(s8);
+            if (a.zout1) *(u32x4 *)(a.zout1 + idx) = pack8(f);
+        } else if (mode == kEpStoreBf16) {
+            *(u32x4 *)((u16 *)out + idx) = pack8(f);
+        } else {
+            const u16 *zr = first ? a.zref1 : a.zref2;
+            float z[8];
+            unpack8(*(const u32x4 *)(zr + idx), z);
+#pragma unroll
+            for (int j = 0; j < 8; j++) f[j] *= dsilu(z[j]);
+            *(u32x4 *)((u16 *)out + idx) = pack8(f);
+        }
+        return;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+        if (j >= nv) break;
+        if (mode == kEpStoreF32)
+            ((float *)out)[idx + j] = f[j];
+        else if (mode == kEpAddF32)
+            ((float *)out)[idx + j] += f[j];
+        else if (mode == kEpStoreBf16)
+            ((u16 *)out)[idx + j] = (u16)f2bf(f[j]);
+        else if (mode == kEpSiluBf16) {
+            ((u16 *)out)[idx + j] = (u16)f2bf(silu(f[j]));
+            if (a.zout1) a.zout1[idx + j] = (u16)f2bf(f[j]);
+        } else {
+            const u16 *zr = first ? a.zref1 : a.zref2;
+            ((u16 *)out)[idx + j] = (u16)f2bf(f[j] * dsilu(bf2f(zr[idx + j])));
+        }
+    }
+}
+
+template <int NTB, int CS>
+__global__ void __launch_bounds__(kNBlock) k_conv3_brick(ConvArgs a)
+{
+    constexpr int P = CS / 8;
+    constexpr int kTile = kHalo * P;                     // 16-byte halo elements
+    constexpr int kOutRow = 17;                          // floats per staged output cell (padded)
+    constexpr int kOut = (256 * kOutRow + 3) / 4;        // 16-byte elements of the output stage
+    constexpr int kSmem = kTile > kOut ? kTile : kOut;
+    constexpr int NE = (kTile + kNBlock - 1) / kNBlock;  // staging loads per thread
+    __shared__ u32x4 smem[kSmem];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, r = lane & 15;
+    const int n = a.n;
+    const int nbz = n / 16, nby = n / 4;
+    int b = brick_block(gridDim.x);
+    const int bz = b % nbz;
+    b /= nbz;
+    const int by = b % nby, bx = b / nby;
+    const int x0 = bx * 4, y0 = by * 4, z0 = bz * 16;
+    const int t0 = blockIdx.y * NTB;
+    f32x4 acc[4][NTB];
+#pragma unroll
+    for (int q = 0; q < 4; q++)
+#pragma unroll
+        for (int t = 0; t < NTB; t++) acc[q][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const u32x4 zero = {0u, 0u, 0u, 0u};
+    const int nslice = (a.c1 + a.c2) / CS;
+    const int spp = a.ko.spp;
+    auto wload = [&](int ch, u32x4 (&bw)[NTB]) {
+#pragma unroll
+        for (int t = 0; t < NTB; t++)
+            bw[t] = (t0 + t < a.ntile) ? a.w[((int64_t)(t0 + t) * a.nchunk + ch) * 64 + lane] : zero;
+    };
+    for (int sl = 0; sl < nslice; sl++) {
+        const int cb = sl * CS;
+        const bool one = cb < a.c1;
+        const u16 *src = one ? a.in1 : a.in2;
+        const int cs = one ? a.c1 : a.c2, c0 = one ? cb : cb - a.c1;
+        // issue every staging load of the slice before the first LDS store
+        u32x4 stg[NE];
+#pragma unroll
+        for (int k = 0; k < NE; k++) {
+            const int e = threadIdx.x + k * kNBlock;
+            stg[k] = zero;
+            if (e < kTile) {
+                const int o = e % P, hv = e / P;
+                const int hz = hv % kHZ, hy = (hv / kHZ) % kHY, hx = hv / (kHZ * kHY);
+                const int gx = wrapn(x0 + hx - 1, n), gy = wrapn(y0 + hy - 1, n), gz = wrapn(z0 + hz - 1, n);
+                stg[k] = *(const u32x4 *)(src + (((int64_t)gx * n + gy) * n + gz) * cs + c0 + o * 8);
+            }
+        }
+        u32x4 bw[NTB];
+        wload(sl * spp, bw);
+        __syncthreads(); // previous slice consumed
+#pragma unroll
+        for (int k = 0; k < NE; k++) {
+            const int e = threadIdx.x + k * kNBlock;
+            if (e < kTile) smem[e] = stg[k];
+        }
+        __syncthreads();
+        for (int st = 0; st < spp; st++) {
+            const int ch = sl * spp + st;
+            u32x4 bn[NTB];
+            if (st + 1 < spp) wload(ch + 1, bn);
+            const int o = st * 4 + g;
+            u32x4 av[4];
+            if (o < 27 * P) {
+                const int tap = o / P, o8 = o - tap * P;
+                const int hx = wave + tap / 9, hy0 = (tap / 3) % 3, hz = r + tap % 3;
+#pragma unroll
+                for (int q = 0; q < 4; q++) av[q] = smem[((hx * kHY + hy0 + q) * kHZ + hz) * P + o8];
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; q++) av[q] = zero;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+#pragma unroll
+                for (int t = 0; t < NTB; t++) acc[q][t] = mfma(av[q], bw[t], acc[q][t]);
+            if (st + 1 < spp) {
+#pragma unroll
+                for (int t = 0; t < NTB; t++) bw[t] = bn[t];
+            }
+        }
+    }
+    // epilogue through LDS: every thread then writes whole channel octets
+    float *os = (float *)smem;
+#pragma unroll
+    for (int t = 0; t < NTB; t++) {
+        if ((t0 + t) * 16 >= a.cout) break;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+#pragma unroll
+            for (int i = 0; i < 4; i++) os[(wave * 64 + q * 16 + 4 * g + i) * kOutRow + r] = acc[q][t][i];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 2; k++) {
+            const int e = threadIdx.x + k * kNBlock; // 256 cells x 2 octets
+            const int cell = e >> 1, o = e & 1;
+            const int vx = cell >> 6, vy = (cell >> 4) & 3, vz = cell & 15;
+            float f[8];
+#pragma unroll
+            for (int j = 0; j < 8; j++) f[j] = os[cell * kOutRow + o * 8 + j];
+            const int64_t v = ((int64_t)(x0 + vx) * n + (y0 + vy)) * n + (z0 + vz);
+            conv_store8(a, (t0 + t) * 16 + o * 8, v, f);
+        }
     }
 }
 
@@ -315,39 +515,210 @@ __global__ void __launch_bounds__(kNBlock) k_conv3_wgrad(WgtArgs a)
         a.partb[(int64_t)split * a.cot * 16 + cotile * 16 + threadIdx.x] = red[16 * 16 * 27 + threadIdx.x];
 }
 
-// grad[(co*cin + ci)*27 + t] (+)= sum_s part[s][co][ci][t]; gradb[co] (+)= sum_s partb[s][co]
+// Brick version (n a multiple of 16), ci tiles of 16 channels.  Per brick of
+// 4 x 4 x 16 cells the block stages dy of its co tile transposed,
+// dyT[co][cell], and the input halo transposed as three copies shifted by the
+// z offset, hT[dz][ci][x][y][z'] = a(x, y, z' + dz) (z' = 0..15): every A and
+// B operand of the MFMA (8 consecutive z cells of one channel) is then one
+// aligned 16-byte LDS read.  Row strides are padded so that the 16 lanes of a
+// read hit distinct banks.  Blocks take contiguous ranges of bricks.
+constexpr int kDyStride = 256 + 8;          // u16 per co row of dyT
+constexpr int kHtStride = kHX * kHY * 16 + 8; // u16 per ci plane of one hT copy
+
+struct WgtBrick {
+    WgtArgs a;
+    int bricks_per_split;
+};
+
+__global__ void __launch_bounds__(kNBlock) k_conv3_wgrad_brick(WgtBrick wb)
+{
+    __shared__ __attribute__((aligned(16))) u16 dyT[16 * kDyStride];
+    __shared__ __attribute__((aligned(16))) u16 hT[3 * 16 * kHtStride];
+    const WgtArgs &a = wb.a;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, r = lane & 15;
+    const int n = a.n;
+    const int nbz = n / 16, nby = n / 4;
+    const int nbricks = nbz * nby * (n / 4);
+    const int cotile = blockIdx.x, citile = blockIdx.y, split = blockIdx.z;
+    const int cin = a.c1 + a.c2;
+    // the ci tile's source: one input (tiles never straddle in1 / in2), octets present
+    const int cb = citile * 16;
+    const bool one = cb < a.c1;
+    const u16 *src = one ? a.in1 : a.in2;
+    const int cs = one ? a.c1 : a.c2, c0 = one ? cb : cb - a.c1;
+    const int nci8 = min(2, (min(cin, cb + 16) - cb) / 8); // 1 or 2 octets of real channels
+    const int nco8 = min(2, (a.cy - cotile * 16) / 8);
+    f32x4 acc[27];
+#pragma unroll
+    for (int t = 0; t < 27; t++) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float dbias = 0.0f;
+    const int b0 = split * wb.bricks_per_split;
+    const int b1 = min(nbricks, b0 + wb.bricks_per_split);
+    for (int bi = b0; bi < b1; bi++) {
+        const int bz = bi % nbz, by = (bi / nbz) % nby, bx = bi / (nbz * nby);
+        const int x0 = bx * 4, y0 = by * 4, z0 = bz * 16;
+        // staging: threads 0..143 build the three shifted halo copies for one
+        // (x, y, z quad) from 6 consecutive halo cells; threads 144..207 the
+        // transposed dy of one (x, y, z quad); every LDS write is 8 bytes
+        // (4 consecutive z of one channel)
+        const int tid = threadIdx.x;
+        u32x4 ld[12];
+        int kind = 0, ix = 0, iy = 0, iq = 0;
+        if (tid < 144) {
+            kind = 1;
+            iq = tid & 3;
+            iy = (tid >> 2) % kHY;
+            ix = (tid >> 2) / kHY;
+            const int gx = wrapn(x0 + ix - 1, n), gy = wrapn(y0 + iy - 1, n);
+#pragma unroll
+            for (int k = 0; k < 6; k++) {
+                const int gz = wrapn(z0 + 4 * iq + k - 1, n);
+                const int64_t v = ((int64_t)gx * n + gy) * n + gz;
+#pragma unroll
+                for (int o = 0; o < 2; o++)
+                    ld[2 * k + o] = (o < nci8) ? *(const u32x4 *)(src + v * cs + c0 + o * 8) : u32x4{0u, 0u, 0u, 0u};
+            }
+        } else if (tid < 208) {
+            kind = 2;
+            const int t = tid - 144;
+            iq = t & 3;
+            iy = (t >> 2) & 3;
+            ix = t >> 4;
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const int64_t v = ((int64_t)(x0 + ix) * n + (y0 + iy)) * n + (z0 + 4 * iq + k);
+#pragma unroll
+                for (int o = 0; o < 2; o++)
+                    ld[2 * k + o] = (o < nco8) ? *(const u32x4 *)(a.dy + v * a.cy + cotile * 16 + o * 8)
+                                               : u32x4{0u, 0u, 0u, 0u};
+            }
+        }
+        __syncthreads(); // the previous brick's operands are consumed
+        if (kind == 1) {
+#pragma unroll
+            for (int c = 0; c < 16; c++) {
+                const int o = c >> 3, w = (c & 7) >> 1, hi = c & 1;
+                uint32_t h[6];
+#pragma unroll
+                for (int k = 0; k < 6; k++) h[k] = hi ? (ld[2 * k + o][w] >> 16) : (ld[2 * k + o][w] & 0xffffu);
+#pragma unroll
+                for (int d = 0; d < 3; d++) {
+                    // copy d holds z' = hz - d: z' = 4 iq + k' reads halo cell 4 iq + k' + d
+                    uint2 q;
+                    q.x = h[d] | (h[d + 1] << 16);
+                    q.y = h[d + 2] | (h[d + 3] << 16);
+                    *(uint2 *)&hT[(d * 16 + c) * kHtStride + (ix * kHY + iy) * 16 + 4 * iq] = q;
+                }
+            }
+        } else if (kind == 2) {
+#pragma unroll
+            for (int c = 0; c < 16; c++) {
+                const int o = c >> 3, w = (c & 7) >> 1, hi = c & 1;
+                const bool ok = cotile * 16 + c < a.cout;
+                uint32_t h[4];
+#pragma unroll
+                for (int k = 0; k < 4; k++)
+                    h[k] = ok ? (hi ? (ld[2 * k + o][w] >> 16) : (ld[2 * k + o][w] & 0xffffu)) : 0u;
+                uint2 q;
+                q.x = h[0] | (h[1] << 16);
+                q.y = h[2] | (h[3] << 16);
+                *(uint2 *)&dyT[c * kDyStride + (ix * 4 + iy) * 16 + 4 * iq] = q;
+            }
+        }
+        __syncthreads();
+        // wave: x row x0 + wave; K steps of 32 cells = rows (2s, 2s + 1) of y, all 16 z
+#pragma unroll
+        for (int s = 0; s < 2; s++) {
+            const int row = 2 * s + (g >> 1), zh = (g & 1) * 8;
+            const u32x4 A = *(const u32x4 *)&dyT[r * kDyStride + (wave * 4 + row) * 16 + zh];
+            if (citile == 0) {
+                float h[8];
+                unpack8(A, h);
+#pragma unroll
+                for (int j = 0; j < 8; j++) dbias += h[j];
+            }
+#pragma unroll
+            for (int t = 0; t < 27; t++) {
+                const int dx = t / 9, dy = (t / 3) % 3, dz = t % 3;
+                const u32x4 B =
+                    *(const u32x4 *)&hT[(dz * 16 + r) * kHtStride + ((wave + dx) * kHY + row + dy) * 16 + zh];
+                acc[t] = mfma(A, B, acc[t]);
+            }
+        }
+    }
+    // reduce the waves in LDS (reusing hT) in a fixed order and write the partial
+    float *red = (float *)hT; // 16*16*27 + 16 floats fit in hT
+    dbias += __shfl_xor(dbias, 16, 64);
+    dbias += __shfl_xor(dbias, 32, 64);
+    for (int w = 0; w < kNBlock / 64; w++) {
+        __syncthreads();
+        if (wave == w) {
+#pragma unroll
+            for (int t = 0; t < 27; t++)
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    const int idx = ((4 * g + i) * 16 + r) * 27 + t;
+                    red[idx] = (w == 0 ? 0.0f : red[idx]) + acc[t][i];
+                }
+            if (g == 0) red[16 * 16 * 27 + r] = (w == 0 ? 0.0f : red[16 * 16 * 27 + r]) + dbias;
+        }
+    }
+    __syncthreads();
+    const int64_t ldco = (int64_t)a.cit * 16 * 27;
+    float *dst = a.part + (int64_t)split * a.cot * 16 * ldco;
+    for (int e = threadIdx.x; e < 16 * 16 * 27; e += kNBlock) {
+        const int rco = e / (16 * 27), rem = e - rco * 16 * 27;
+        dst[(int64_t)(cotile * 16 + rco) * ldco + (int64_t)citile * 16 * 27 + rem] = red[e];
+    }
+    if (citile == 0 && threadIdx.x < 16)
+        a.partb[(int64_t)split * a.cot * 16 + cotile * 16 + threadIdx.x] = red[16 * 16 * 27 + threadIdx.x];
+}
+
+// grad[(co*cin + ci)*27 + t] (+)= sum_s part[s][co][ci][t]; gradb[co] (+)= sum_s partb[s][co].
+// A block reduces 16 values with 16 threads each (thread k sums splits
+// k, k + 16, ...); the 16 sums are added in a fixed order.
 __global__ void __launch_bounds__(kNBlock) k_wgrad_reduce(const float *part, const float *partb, int nsplit,
                                                          int cot, int cit, int cout, int cin, float *grad,
                                                          float *gradb, int accumulate)
 {
+    __shared__ float sh[16][17];
+    const int el = threadIdx.x & 15, k = threadIdx.x >> 4;
     const int64_t nw = (int64_t)cout * cin * 27;
-    const int64_t e = (int64_t)blockIdx.x * kNBlock + threadIdx.x;
+    const int64_t e = (int64_t)blockIdx.x * 16 + el;
     const int64_t per = (int64_t)cot * 16 * cit * 16 * 27;
+    float s = 0.0f;
     if (e < nw) {
         const int co = (int)(e / ((int64_t)cin * 27));
         const int rem = (int)(e - (int64_t)co * cin * 27);
         const int ci = rem / 27, t = rem - ci * 27;
         const int64_t off = ((int64_t)co * cit * 16 + ci) * 27 + t;
-        float s = 0.0f;
-        for (int q = 0; q < nsplit; q++) s += part[q * per + off];
-        grad[e] = accumulate ? grad[e] + s : s;
+        for (int q = k; q < nsplit; q += 16) s += part[q * per + off];
     } else if (e < nw + cout) {
         const int co = (int)(e - nw);
-        float s = 0.0f;
-        for (int q = 0; q < nsplit; q++) s += partb[(int64_t)q * cot * 16 + co];
-        gradb[co] = accumulate ? gradb[co] + s : s;
+        for (int q = k; q < nsplit; q += 16) s += partb[(int64_t)q * cot * 16 + co];
+    }
+    sh[el][k] = s;
+    __syncthreads();
+    if (k == 0 && e < nw + cout) {
+        float t = 0.0f;
+        for (int q = 0; q < 16; q++) t += sh[el][q];
+        if (e < nw)
+            grad[e] = accumulate ? grad[e] + t : t;
+        else
+            gradb[e - nw] = accumulate ? gradb[e - nw] + t : t;
     }
 }
 
 // ---- weight packing -------------------------------------------------------------------
 //
-// Forward pack of a layer W[co][ci][27] (cin_real real input channels stored in
-// cin_pad channels): element (tile, chunk, lane) holds, for the octet
-// oct = 4*chunk + lane/16 (tap = oct / (cin_pad/8)), the 8 weights
-// W[tile*16 + lane%16][8*(oct % (cin_pad/8)) + j][tap].  The transposed pack
-// (backward data) does the same for W'[ci][co][26 - tap], i.e. the layer with
-// inputs and outputs exchanged and the taps mirrored.
-__global__ void __launch_bounds__(kNBlock) k_pack_weights(const float *W, int cin_real, int cout, int cin_pad,
+// Forward pack of a layer W[co][ci][27] (cin_real real input channels):
+// element (tile, chunk, lane) holds the 8 weights W[tile*16 + lane%16][c0 + j][tap]
+// of the octet (tap, c0) that KOrder assigns to (chunk, lane/16), zero where
+// the channel or the octet does not exist.  The transposed pack (backward
+// data) does the same for W'[ci][co][26 - tap], i.e. the layer with inputs and
+// outputs exchanged and the taps mirrored.
+__global__ void __launch_bounds__(kNBlock) k_pack_weights(const float *W, int cin_real, int cout, KOrder ko,
                                                          int nchunk, int ntile, int transposed, u32x4 *out)
 {
     const int64_t e = (int64_t)blockIdx.x * kNBlock + threadIdx.x;
@@ -356,17 +727,15 @@ __global__ void __launch_bounds__(kNBlock) k_pack_weights(const float *W, int ci
     const int lane = (int)(e % 64);
     const int64_t tc = e / 64;
     const int chunk = (int)(tc % nchunk), tile = (int)(tc / nchunk);
-    const int opt = cin_pad / 8;
-    const int oct = chunk * 4 + lane / 16;
     const int col = tile * 16 + lane % 16; // output channel of the (possibly transposed) layer
     float f[8];
 #pragma unroll
     for (int j = 0; j < 8; j++) f[j] = 0.0f;
-    if (oct < 27 * opt) {
-        const int tap = oct / opt, o8 = oct - tap * opt;
+    int tap, c0;
+    if (ko.at(chunk, lane / 16, tap, c0)) {
 #pragma unroll
         for (int j = 0; j < 8; j++) {
-            const int k = o8 * 8 + j; // input channel of the (possibly transposed) layer
+            const int k = c0 + j; // input channel of the (possibly transposed) layer
             if (!transposed) {
                 if (col < cout && k < cin_real) f[j] = W[((int64_t)col * cin_real + k) * 27 + tap];
             } else {
@@ -534,14 +903,15 @@ __global__ void __launch_bounds__(kNBlock) k_sum_final(const double *x, int64_t 
     if (threadIdx.x == 0) out[0] = sh[0];
 }
 
-// Block partial sums of x and x^2 (grid-stride): partials[block] and
-// partials[gridDim.x + block]
-__global__ void __launch_bounds__(kNBlock) k_moments(const double *x, int64_t count, double *partials)
+// Block partial sums of v and v^2, v = x + y (y may be null), grid-stride:
+// partials[block] and partials[gridDim.x + block]
+__global__ void __launch_bounds__(kNBlock) k_moments(const double *x, const double *y, int64_t count,
+                                                    double *partials)
 {
     __shared__ double sh[2][kNBlock / 64];
     double s = 0.0, s2 = 0.0;
     for (int64_t q = (int64_t)blockIdx.x * kNBlock + threadIdx.x; q < count; q += (int64_t)gridDim.x * kNBlock) {
-        const double v = x[q];
+        const double v = y ? x[q] + y[q] : x[q];
         s += v;
         s2 += v * v;
     }

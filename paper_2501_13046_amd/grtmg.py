@@ -88,12 +88,14 @@ def lib() -> C.CDLL:
                                      C.POINTER(MgReport)]
         L.mg_destroy_batch.argtypes = [vp]
         L.mg_destroy_batch.restype = None
+        L.mg_fmg_start.argtypes = [vp, vp, vp, vp, C.c_double, i32, vp, vp, C.POINTER(MgReport)]
         L.mg_probe.argtypes = [vp, i32, i32]
         L.mg_probe_result.argtypes = [vp, C.POINTER(i32), C.POINTER(C.c_double)]
         for f in ("mg_workspace_size", "mg_setup", "mg_vcycle", "mg_solve_constraints",
                   "mg_residual_norm", "mg_residual_fields", "mg_scalar_field_sources",
                   "mg_shell_field_sources", "mg_interp_cubic", "mg_kernel_op", "mg_probe",
-                  "mg_probe_result", "mg_batch_workspace_size", "mg_setup_batch", "mg_solve_batch"):
+                  "mg_probe_result", "mg_batch_workspace_size", "mg_setup_batch", "mg_solve_batch",
+                  "mg_fmg_start"):
             getattr(L, f).restype = st
         _lib = L
     return _lib
@@ -320,6 +322,16 @@ def interp_cubic(pc: MgParams, coarse: torch.Tensor) -> torch.Tensor:
     _check(lib().mg_interp_cubic(C.byref(pc), _dptr(coarse, numel=nc ** 3), _dptr(fine),
                                  _stream(coarse.device)), "mg_interp_cubic")
     return fine
+
+
+def fmg_start(coarse: "Solver", fine: "Solver", uc: torch.Tensor, Wc: Optional[torch.Tensor],
+              uf: torch.Tensor, Wf: Optional[torch.Tensor], tol: float = 1e-10, max_outer: int = 100) -> dict:
+    """Solve the coarse problem, then interpolate its state to the fine arrays."""
+    rep = MgReport()
+    st = lib().mg_fmg_start(coarse.ctx, fine.ctx, _dptr(uc, numel=coarse.cells), coarse._W(Wc), tol, max_outer,
+                            _dptr(uf, numel=fine.cells), fine._W(Wf), C.byref(rep))
+    _check(st, "mg_fmg_start", ok=(MG_OK, MG_ERR_NOT_CONVERGED))
+    return dict(status=st, outer_iters=rep.outer_iters, h_rms=rep.h_rms, m_rms=rep.m_rms, seconds=rep.seconds)
 
 
 def K_from_mean_density(mean_rho: float) -> float:

@@ -49,7 +49,7 @@ def lib() -> C.CDLL:
         L.nn_pack_input.argtypes = [vp, vp, vp, vp, np_, vp]
         L.nn_pack_target.argtypes = [vp, vp, vp, np_, vp]
         L.nn_unpack_output.argtypes = [vp, vp, np_, vp, vp]
-        L.nn_moments.argtypes = [vp, vp, i64, dp]
+        L.nn_moments.argtypes = [vp, vp, vp, i64, dp]
         L.nn_warm_start.argtypes = [vp, vp, vp, vp, vp, np_, vp, vp, C.POINTER(i32), dp]
         L.nn_destroy.argtypes = [vp]
         L.nn_destroy.restype = None
@@ -83,6 +83,19 @@ def norm(in_mean, in_std, out_mean, out_std) -> NnNorm:
         m.in_mean[q], m.in_std[q] = float(in_mean[q]), float(in_std[q])
         m.out_mean[q], m.out_std[q] = float(out_mean[q]), float(out_std[q])
     return m
+
+
+def layer_shapes(cfg: NnConfig):
+    """(c_in, c_out) of every convolution in the parameter order of grtnn.h."""
+    L, ch = cfg.levels, list(cfg.ch)
+    out, cin = [], cfg.c_in
+    for l in range(L):
+        out += [(cin, ch[l]), (ch[l], ch[l])]
+        cin = ch[l]
+    for l in range(L - 2, -1, -1):
+        out += [(ch[l] + ch[l + 1], ch[l]), (ch[l], ch[l])]
+    out.append((ch[0], cfg.c_out))
+    return out
 
 
 def param_count(cfg: NnConfig) -> int:
@@ -178,9 +191,10 @@ class Net:
                                       _dptr(u, numel=self.cells), _dptr(W, numel=3 * self.cells)),
                "nn_unpack_output")
 
-    def moments(self, x: torch.Tensor):
+    def moments(self, x: torch.Tensor, y: Optional[torch.Tensor] = None):
         out = (C.c_double * 2)()
-        _check(lib().nn_moments(self.ctx, _dptr(x), x.numel(), out), "nn_moments")
+        _check(lib().nn_moments(self.ctx, _dptr(x), _dptr(y, numel=x.numel()) if y is not None else None,
+                                x.numel(), out), "nn_moments")
         return out[0], out[1]
 
     def warm_start(self, solver: "_mg.Solver", rho5, rho1, S, nm: NnNorm, u, W):

@@ -110,3 +110,10 @@ def test_network_abi(g):
     assert lib.nn_forward(None, None, None) == g.MG_ERR_INVALID
     assert lib.nn_op_scratch_bytes(12, 16, 8) == 0
     assert lib.nn_conv3_forward(8, 12, 16, None, 0, None, None, None, None, 0, None) == g.MG_ERR_INVALID
+
+
+def test_network_layer_shapes_follow_the_documented_order(g):
+    from paper_2501_13046_amd import grtnn as gn
+    from oracle import nn_oracle as nn
+    for n, levels, ch in ((128, 4, (16, 32, 48, 64)), (16, 2, (32, 16))):
+        assert gn.layer_shapes(gn.config(n, levels, ch)) == nn.layer_shapes(nn.NetConfig(n=n, levels=levels, ch=ch))

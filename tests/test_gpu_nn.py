@@ -45,8 +45,11 @@ def silu_bf(x):
     return bf(x / (1.0 + np.exp(-x)))
 
 
+# n a multiple of 16 without SiLU on load runs the brick kernel (slices of 8, 16, 32
+# channels); the other cases run the general kernel
 @pytest.mark.parametrize("n,cin,cout,act", [(6, 8, 4, False), (8, 16, 16, True), (5, 48, 48, False),
-                                            (16, 32, 48, True), (4, 112, 48, False)])
+                                            (16, 32, 48, True), (4, 112, 48, False), (32, 48, 16, False),
+                                            (16, 64, 64, False), (32, 8, 16, False), (16, 112, 80, False)])
 def test_conv_forward(n, cin, cout, act):
     rng = np.random.default_rng(n * 1000 + cin + cout)
     x = bf(rng.standard_normal((cin, n, n, n)))
@@ -63,7 +66,8 @@ def test_conv_forward(n, cin, cout, act):
     assert err < (1e-2 if act else 1e-4)
 
 
-@pytest.mark.parametrize("n,cin,cout", [(6, 16, 4), (8, 48, 16), (5, 80, 32), (16, 16, 16)])
+@pytest.mark.parametrize("n,cin,cout", [(6, 16, 4), (8, 48, 16), (5, 80, 32), (16, 16, 16), (32, 48, 4),
+                                        (16, 112, 32), (32, 16, 64)])
 def test_conv_backward_data(n, cin, cout):
     rng = np.random.default_rng(7 * n + cin + cout)
     cout8 = (cout + 7) // 8 * 8
@@ -81,7 +85,8 @@ def test_conv_backward_data(n, cin, cout):
 
 
 @pytest.mark.parametrize("n,cin,cout,act", [(6, 8, 4, False), (8, 16, 16, False), (5, 48, 32, True),
-                                            (16, 32, 16, False), (3, 16, 48, False)])
+                                            (16, 32, 16, False), (3, 16, 48, False), (32, 48, 4, False),
+                                            (16, 8, 16, False), (32, 24, 48, False), (16, 16, 16, True)])
 def test_conv_backward_weight(n, cin, cout, act):
     rng = np.random.default_rng(11 * n + cin + cout)
     cout8 = (cout + 7) // 8 * 8
@@ -219,6 +224,9 @@ def test_field_packing_and_moments():
     s, s2 = net.moments(T(S))
     assert s == pytest.approx(S.sum(), rel=1e-12, abs=1e-12)
     assert s2 == pytest.approx((S ** 2).sum(), rel=1e-12)
+    s, s2 = net.moments(T(rho5), T(rho1))
+    assert s == pytest.approx((rho5 + rho1).sum(), rel=1e-12)
+    assert s2 == pytest.approx(((rho5 + rho1) ** 2).sum(), rel=1e-12)
 
 
 def test_forward_is_shift_equivariant_at_full_size():
