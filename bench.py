@@ -26,6 +26,28 @@ sys.path.insert(0, ROOT)
 
 METRIC = "s to 1e-10 constraint residual @128^3: FP64 MG vs mixed+learned; HBM GB/s"
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of the finest-level W pass from FETCH_SIZE / WRITE_SIZE runs,
+# valid only for the kernel sources they were measured on (sha256 prefixes)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pass_W_tiled_coupled_128_traffic.md")
+TRAFFIC_SOURCES = {"paper_2501_13046_amd/csrc/mg_tiled.hpp": "d360c78c62e46937",
+                   "paper_2501_13046_amd/csrc/mg_device.hpp": "4ee763eb646743f1"}
+
+
+def measured_traffic():
+    """Bytes per launch from the committed counter summary, or None when the
+    kernel sources changed since the counters were taken."""
+    import hashlib
+    for rel, pre in TRAFFIC_SOURCES.items():
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest()[:16] != pre:
+                return None
+    try:
+        for line in open(TRAFFIC_FILE):
+            if line.startswith("traffic_bytes_per_launch:"):
+                return int(line.split(":")[1])
+    except OSError:
+        return None
+    return None
 
 
 def log(*a):
@@ -43,6 +65,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=2)
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison solves")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one plain device copy of 256 MiB (the reference dispatch that scales "
+                         "the FETCH_SIZE / WRITE_SIZE counters of a profiling run)")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2501_13046_amd", "weights", "warmstart_128.npz"),
                     help="trained warm-start network (python -m paper_2501_13046_amd.warmstart)")
     args = ap.parse_args()
@@ -58,6 +83,13 @@ def main():
     from paper_2501_13046_amd import grtmg as g
 
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {src.numel() * 4} bytes read, {dst.numel() * 4} bytes written")
+        del src, dst
     w = synth.coupled(args.n, seed=args.seed, precision=synth.PREC_FP32_IR)
     n = w.n
     # ---- setup (off the clock): sources on the GPU, K from the mean density
@@ -245,7 +277,7 @@ def main():
         "roofline": {
             "kernel": "k_pass_W<float> (finest level)",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
             "launches": launches, "avg_us": avg_s * 1e6, "bytes_per_launch": bytes_per_launch,
         },
         "cpu_baseline": cpu,

@@ -35,11 +35,9 @@
  *  - All work is ordered on the HIP stream given at setup (a hipStream_t
  *    passed as void*; NULL means the default stream): each call waits for
  *    the work already on that stream and that stream waits for the call's
- *    work.  Internally a context runs on two streams of its own (created at
- *    setup with default priority): the main stream, whose outer-iteration
- *    body is captured once into a hipGraph and replayed, and a side stream
- *    that restricts the Newton coefficient and inverts the coarsest psi
- *    operator while the main stream smooths.  Calls that return host scalars
+ *    work.  Internally a context runs on a stream of its own (created at
+ *    setup with default priority), whose outer-iteration body is captured
+ *    once into a hipGraph and replayed.  Calls that return host scalars
  *    (norms, reports) wait for the context's own work only.
  *  - No call throws.  Arguments are validated before any HIP call; a non-OK
  *    status leaves device arrays untouched unless stated otherwise.
@@ -240,10 +238,10 @@ mg_status mg_kernel_op(mg_ctx *ctx, int32_t op, int32_t level, int32_t arg, cons
 /*
  * Batches of independent instances (a parameter scan of uneven grid sizes).
  * One batch context holds one member context per instance, all carved from
- * one caller-owned workspace; the members' outer iterations are captured
- * into a single hipGraph as parallel branches (up to 4 run concurrently), so
- * each outer iteration of the whole batch is one graph launch followed by one
- * copy of every member's norms.  A member that has converged (or diverged)
+ * one caller-owned workspace; every member's outer iteration is captured on
+ * the member's stream and added as an independent child graph of one batch
+ * hipGraph, so each outer iteration of the whole batch is one graph launch
+ * followed by one copy of every member's norms.  A member that has converged (or diverged)
  * keeps its state: its update kernels are gated by a device-side flag set by
  * a check kernel after each evaluation.
  *  p: host array of count parameter sets (same precision for all; momentum

@@ -66,9 +66,8 @@ constexpr int kBrickR = 2;   // brick depth along x of the tiled residual
 struct mg_ctx {
     mg_params p;
     hipStream_t user_s; // the caller's stream: every call is ordered after / before it by events
-    hipStream_t s;      // internal main stream (captured into the outer-iteration graph)
-    hipStream_t side;   // internal side stream: coefficient restriction and coarse inverse
-    hipEvent_t ev_in, ev_out, ev_fork, ev_gj, ev_c[16];
+    hipStream_t s;      // internal stream (captured into the outer-iteration graph)
+    hipEvent_t ev_in, ev_out;
     int L;
     bool f32;
     bool momentum;
@@ -214,6 +213,10 @@ void fill(hipStream_t s, T *a, int64_t count, T v)
     if (count > 0) hipLaunchKernelGGL(k_fill<T>, dim3(nblk(count)), dim3(kBlock), 0, s, a, count, v);
 }
 
+// Defect+restriction form: one thread per fine cell on grids of at most 32^3
+// cells (latency-bound), one per coarse cell above (register reuse).
+bool fine_threads(int n_fine) { return n_fine <= 32; }
+
 // ---- coarsest level -----------------------------------------------------------------
 
 void factor(hipStream_t s, double *A, double *aug, double *inv, int m, double *flag)
@@ -313,13 +316,35 @@ void defect_restrict_psi(mg_ctx *c, int l, const T *d, const T *r, const T *cf, 
 {
     Probe pr(c, MG_PROBE_DEFECT_RESTRICT_PSI, l);
     const Geo &g = c->geo[l];
-    const unsigned nb = nblk(c->cells[l + 1]);
-    if (c->p.bc == MG_BC_PERIODIC)
-        hipLaunchKernelGGL((k_defect_restrict_psi<kBcPeriodic, T>), dim3(nb), dim3(kBlock), 0, c->s, g,
-                           d, r, cf, rc, cc);
+    if (fine_threads(c->n[l])) {
+        const unsigned nb = nblk(8 * c->cells[l + 1]);
+        if (c->p.bc == MG_BC_PERIODIC)
+            hipLaunchKernelGGL((k_defect_restrict_psi_fine<kBcPeriodic, T>), dim3(nb), dim3(kBlock), 0, c->s, g, d, r,
+                               cf, rc, cc);
+        else
+            hipLaunchKernelGGL((k_defect_restrict_psi_fine<kBcRobin, T>), dim3(nb), dim3(kBlock), 0, c->s, g, d, r,
+                               cf, rc, cc);
+    } else {
+        const unsigned nb = nblk(c->cells[l + 1]);
+        if (c->p.bc == MG_BC_PERIODIC)
+            hipLaunchKernelGGL((k_defect_restrict_psi<kBcPeriodic, T>), dim3(nb), dim3(kBlock), 0, c->s, g, d, r, cf,
+                               rc, cc);
+        else
+            hipLaunchKernelGGL((k_defect_restrict_psi<kBcRobin, T>), dim3(nb), dim3(kBlock), 0, c->s, g, d, r, cf,
+                               rc, cc);
+    }
+}
+
+template <typename T>
+void defect_restrict_W(mg_ctx *c, int l, const T *d, const T *r, T *rc)
+{
+    Probe pr(c, MG_PROBE_DEFECT_RESTRICT_W, l);
+    if (fine_threads(c->n[l]))
+        hipLaunchKernelGGL(k_defect_restrict_W_fine<T>, dim3(nblk(8 * c->cells[l + 1])), dim3(kBlock), 0, c->s,
+                           c->geo[l], d, r, rc);
     else
-        hipLaunchKernelGGL((k_defect_restrict_psi<kBcRobin, T>), dim3(nb), dim3(kBlock), 0, c->s, g, d,
-                           r, cf, rc, cc);
+        hipLaunchKernelGGL(k_defect_restrict_W<T>, dim3(nblk(c->cells[l + 1])), dim3(kBlock), 0, c->s, c->geo[l], d,
+                           r, rc);
 }
 
 template <typename T>
@@ -336,43 +361,35 @@ void prolong_add(mg_ctx *c, int lc, const T *coarse, T *fine, int ncomp)
                            fine, ncomp);
 }
 
-// Side stream, forked after the residual wrote the finest c: restrict c level by
-// level (event per level) and invert the coarsest operator (event ev_gj), while
-// the main stream smooths the finer levels.
+// After the residual wrote the finest c: restrict c level by level and, when
+// the coarsest system is too large for the one-wave solver, assemble and
+// invert it.  All on the context's stream: the V-cycle kernels that follow
+// stay on one queue of the graph.
 template <typename T>
-void fork_coefficients(mg_ctx *c)
+void restrict_coefficients(mg_ctx *c)
 {
-    (void)hipEventRecord(c->ev_fork, c->s);
-    (void)hipStreamWaitEvent(c->side, c->ev_fork, 0);
-    for (int l = 0; l + 1 < c->L; l++) {
-        hipLaunchKernelGGL(k_restrict<T>, dim3(nblk(c->cells[l + 1])), dim3(kBlock), 0, c->side, c->n[l],
+    for (int l = 0; l + 1 < c->L; l++)
+        hipLaunchKernelGGL(k_restrict<T>, dim3(nblk(c->cells[l + 1])), dim3(kBlock), 0, c->s, c->n[l],
                            (const T *)c->pc[l], (T *)c->pc[l + 1]);
-        (void)hipEventRecord(c->ev_c[l + 1], c->side);
-    }
     const int l = c->L - 1;
     const int m = c->m_psi;
-    if (wave_solvable(m)) {
-        // solved directly at the bottom of the V-cycle (coarse_psi)
-    } else {
-        fill<double>(c->side, c->A_psi, (int64_t)m * m, 0.0);
-        if (c->p.bc == MG_BC_PERIODIC)
-            hipLaunchKernelGGL((k_assemble_psi<kBcPeriodic, T>), dim3(nblk(m)), dim3(kBlock), 0, c->side,
-                               c->geo[l], (const T *)c->pc[l], c->A_psi);
-        else
-            hipLaunchKernelGGL((k_assemble_psi<kBcRobin, T>), dim3(nblk(m)), dim3(kBlock), 0, c->side, c->geo[l],
-                               (const T *)c->pc[l], c->A_psi);
-        factor(c->side, c->A_psi, c->aug_psi, c->inv_psi, m, c->scal + S_FLAG_PSI);
-    }
-    (void)hipEventRecord(c->ev_gj, c->side);
+    if (wave_solvable(m)) return; // solved directly at the bottom of the V-cycle (coarse_psi)
+    fill<double>(c->s, c->A_psi, (int64_t)m * m, 0.0);
+    if (c->p.bc == MG_BC_PERIODIC)
+        hipLaunchKernelGGL((k_assemble_psi<kBcPeriodic, T>), dim3(nblk(m)), dim3(kBlock), 0, c->s, c->geo[l],
+                           (const T *)c->pc[l], c->A_psi);
+    else
+        hipLaunchKernelGGL((k_assemble_psi<kBcRobin, T>), dim3(nblk(m)), dim3(kBlock), 0, c->s, c->geo[l],
+                           (const T *)c->pc[l], c->A_psi);
+    factor(c->s, c->A_psi, c->aug_psi, c->inv_psi, m, c->scal + S_FLAG_PSI);
 }
 
 // psi V-cycle on level l; the coefficients of levels > 0 and the coarsest
-// inverse come from fork_coefficients.
+// inverse come from restrict_coefficients.
 template <typename T>
 void vcycle_psi(mg_ctx *c, int l)
 {
     if (l == c->L - 1) {
-        (void)hipStreamWaitEvent(c->s, c->ev_gj, 0);
         const int m = c->m_psi;
         if (wave_solvable(m)) {
             coarse_psi<T>(c, (const T *)c->pr[l], (T *)c->pd0[l]);
@@ -384,7 +401,6 @@ void vcycle_psi(mg_ctx *c, int l)
                            (T *)c->pd0[l], 0);
         return;
     }
-    if (l > 0) (void)hipStreamWaitEvent(c->s, c->ev_c[l], 0);
     fill<T>(c->s, (T *)c->pd0[l], c->cells[l], T(0));
     smooth_psi<T>(c, l, c->p.nu_pre);
     defect_restrict_psi<T>(c, l, (const T *)c->pd0[l], (const T *)c->pr[l], (const T *)c->pc[l],
@@ -427,11 +443,7 @@ void vcycle_W(mg_ctx *c, int l)
     }
     fill<T>(c->s, (T *)c->wd0[l], 3 * c->cells[l], T(0));
     smooth_W<T>(c, l, c->p.nu_pre);
-    {
-        Probe pr(c, MG_PROBE_DEFECT_RESTRICT_W, l);
-        hipLaunchKernelGGL(k_defect_restrict_W<T>, dim3(nblk(c->cells[l + 1])), dim3(kBlock), 0, c->s,
-                           c->geo[l], (const T *)c->wd0[l], (const T *)c->wr[l], (T *)c->wr[l + 1]);
-    }
+    defect_restrict_W<T>(c, l, (const T *)c->wd0[l], (const T *)c->wr[l], (T *)c->wr[l + 1]);
     vcycle_W<T>(c, l + 1);
     prolong_add<T>(c, l + 1, (const T *)c->wd0[l + 1], (T *)c->wd0[l], 3);
     smooth_W<T>(c, l, c->p.nu_post);
@@ -536,7 +548,7 @@ void step_psi(mg_ctx *c, double *u, const double *W, bool residual_done)
 {
     if (!residual_done)
         residual<T>(c, u, W, false, nullptr, nullptr, nullptr, c->pr[0], c->pc[0], nullptr, false);
-    fork_coefficients<T>(c);
+    restrict_coefficients<T>(c);
     vcycle_psi<T>(c, 0);
     const int64_t m = c->cells[0];
     {
@@ -731,16 +743,10 @@ void release(mg_ctx *c)
 {
     drop_graph(c);
     if (c->s) (void)hipStreamSynchronize(c->s);
-    if (c->side) (void)hipStreamSynchronize(c->side);
-    hipEvent_t *evs[] = {&c->ev_in, &c->ev_out, &c->ev_fork, &c->ev_gj};
+    hipEvent_t *evs[] = {&c->ev_in, &c->ev_out};
     for (hipEvent_t *e : evs)
         if (*e) (void)hipEventDestroy(*e);
-    for (int l = 0; l < 16; l++)
-        if (c->ev_c[l]) (void)hipEventDestroy(c->ev_c[l]);
-    if (c->own_streams) {
-        if (c->s) (void)hipStreamDestroy(c->s);
-        if (c->side) (void)hipStreamDestroy(c->side);
-    }
+    if (c->own_streams && c->s) (void)hipStreamDestroy(c->s);
     if (c->hpin) (void)hipHostFree(c->hpin);
     if (c->probe_ev) {
         for (int q = 0; q < 2 * kProbeMax; q++) (void)hipEventDestroy(c->probe_ev[q]);
@@ -749,20 +755,17 @@ void release(mg_ctx *c)
     delete c;
 }
 
-// Create the context's events, and its two streams unless they are borrowed
-// (already set: batch members).
+// Create the context's events, and its stream unless it is borrowed (already
+// set: batch members).
 mg_status create_streams(mg_ctx *c)
 {
     if (!c->s) {
         c->own_streams = true;
         if (hipStreamCreateWithFlags(&c->s, hipStreamNonBlocking) != hipSuccess) return MG_ERR_HIP;
-        if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) return MG_ERR_HIP;
     }
-    hipEvent_t *evs[] = {&c->ev_in, &c->ev_out, &c->ev_fork, &c->ev_gj};
+    hipEvent_t *evs[] = {&c->ev_in, &c->ev_out};
     for (hipEvent_t *e : evs)
         if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) return MG_ERR_HIP;
-    for (int l = 0; l < 16; l++)
-        if (hipEventCreateWithFlags(&c->ev_c[l], hipEventDisableTiming) != hipSuccess) return MG_ERR_HIP;
     return MG_OK;
 }
 
@@ -793,8 +796,7 @@ mg_status kernel_op(mg_ctx *c, int op, int l, int arg, const void *in, void *out
         break;
     case MG_OP_DEFECT_RESTRICT_W:
         if (!in || !out || !r || coarsest || c->p.bc != MG_BC_PERIODIC) return MG_ERR_INVALID;
-        hipLaunchKernelGGL(k_defect_restrict_W<T>, dim3(nblk(c->cells[l + 1])), dim3(kBlock), 0, c->s,
-                           c->geo[l], (const T *)in, (const T *)r, (T *)out);
+        defect_restrict_W<T>(c, l, (const T *)in, (const T *)r, (T *)out);
         break;
     case MG_OP_PROLONG_ADD:
         if (!in || !out || coarsest || (arg != 1 && arg != 3)) return MG_ERR_INVALID;
@@ -849,11 +851,11 @@ mg_status mg_workspace_size(const mg_params *p, size_t *bytes)
 
 namespace {
 
-// Create a context on a caller-provided workspace.  s_main / s_side: streams
-// borrowed from a batch, or null to create the context's own.
+// Create a context on a caller-provided workspace.  s_main: a stream borrowed
+// from a batch, or null to create the context's own.
 mg_status ctx_create(const mg_params *p, void *d_workspace, size_t bytes, hipStream_t user_s,
                      const double *d_rho5, const double *d_rho1, const double *d_S, const double *d_f,
-                     hipStream_t s_main, hipStream_t s_side, mg_ctx **out)
+                     hipStream_t s_main, mg_ctx **out)
 {
     *out = nullptr;
     mg_status st = validate(p);
@@ -869,7 +871,6 @@ mg_status ctx_create(const mg_params *p, void *d_workspace, size_t bytes, hipStr
     c->p = *p;
     c->user_s = user_s;
     c->s = s_main;
-    c->side = s_side;
     c->L = p->levels;
     c->f32 = p->precision == MG_PREC_FP32_IR;
     c->esz = c->f32 ? sizeof(float) : sizeof(double);
@@ -924,7 +925,7 @@ struct mg_batch {
     int count;
     mg_ctx **ctx;
     hipStream_t user_s, s;
-    hipStream_t lane_s[kBatchLanes], lane_side[kBatchLanes];
+    hipStream_t lane_s[kBatchLanes];
     hipEvent_t ev_in, ev_out, ev_root;
     hipEvent_t *ev_join;
     double *scal_all; // device: count x S_COUNT, the members' scalar blocks
@@ -956,10 +957,8 @@ void batch_release(mg_batch *b)
     if (b->ctx)
         for (int i = 0; i < b->count; i++)
             if (b->ctx[i]) release(b->ctx[i]);
-    for (int q = 0; q < kBatchLanes; q++) {
+    for (int q = 0; q < kBatchLanes; q++)
         if (b->lane_s[q]) (void)hipStreamDestroy(b->lane_s[q]);
-        if (b->lane_side[q]) (void)hipStreamDestroy(b->lane_side[q]);
-    }
     if (b->ev_join) {
         for (int i = 0; i < b->count; i++)
             if (b->ev_join[i]) (void)hipEventDestroy(b->ev_join[i]);
@@ -1082,7 +1081,7 @@ mg_status mg_setup(const mg_params *p, void *d_workspace, size_t bytes, void *st
                    mg_ctx **out)
 {
     if (!out) return MG_ERR_INVALID;
-    return ctx_create(p, d_workspace, bytes, (hipStream_t)stream, d_rho5, d_rho1, d_S, d_f, nullptr, nullptr, out);
+    return ctx_create(p, d_workspace, bytes, (hipStream_t)stream, d_rho5, d_rho1, d_S, d_f, nullptr, out);
 }
 
 mg_status mg_batch_workspace_size(const mg_params *p, int32_t count, size_t *bytes)
@@ -1127,8 +1126,7 @@ mg_status mg_setup_batch(const mg_params *p, int32_t count, void *d_workspace, s
     }
     bool ok = hipStreamCreateWithFlags(&b->s, hipStreamNonBlocking) == hipSuccess;
     for (int q = 0; q < kBatchLanes && ok; q++)
-        ok = hipStreamCreateWithFlags(&b->lane_s[q], hipStreamNonBlocking) == hipSuccess &&
-             hipStreamCreateWithFlags(&b->lane_side[q], hipStreamNonBlocking) == hipSuccess;
+        ok = hipStreamCreateWithFlags(&b->lane_s[q], hipStreamNonBlocking) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) == hipSuccess &&
          hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) == hipSuccess &&
          hipEventCreateWithFlags(&b->ev_root, hipEventDisableTiming) == hipSuccess;
@@ -1154,8 +1152,7 @@ mg_status mg_setup_batch(const mg_params *p, int32_t count, void *d_workspace, s
         size_t wb = 0;
         mg_workspace_size(&p[i], &wb);
         st = ctx_create(&p[i], (char *)d_workspace + offs[i], wb, b->lane_s[i % kBatchLanes], d_rho5[i],
-                        d_rho1[i], d_S ? d_S[i] : nullptr, nullptr, b->lane_s[i % kBatchLanes],
-                        b->lane_side[i % kBatchLanes], &b->ctx[i]);
+                        d_rho1[i], d_S ? d_S[i] : nullptr, nullptr, b->lane_s[i % kBatchLanes], &b->ctx[i]);
         if (st != MG_OK) {
             delete[] offs;
             batch_release(b);

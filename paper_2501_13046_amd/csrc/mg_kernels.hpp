@@ -291,6 +291,36 @@ __global__ void __launch_bounds__(kBlock) k_pass_W(Geo g, const T *__restrict__ 
 // Defect + restriction: coarse(I) = average over the 8 children of r - A d;
 // optionally the coefficient c is restricted the same way.
 // ---------------------------------------------------------------------------------------
+// Sum of a value over the 8 lanes of an aligned lane group (the 8 children of
+// one coarse cell), in a fixed butterfly order; every lane of the group gets it.
+template <typename T>
+__device__ __forceinline__ T child_sum(T v)
+{
+    v += __shfl_xor(v, 1, kWave);
+    v += __shfl_xor(v, 2, kWave);
+    v += __shfl_xor(v, 4, kWave);
+    return v;
+}
+
+// One thread per fine cell: thread 8 qc + (4 di + 2 dj + dk) owns child
+// (di, dj, dk) of coarse cell qc, so the 8 children are adjacent lanes.
+__device__ __forceinline__ bool child_of(int64_t tid, int nc, int64_t &qc, int &i, int &j, int &k)
+{
+    qc = tid >> 3;
+    int I, J, K;
+    if (!cell_of(qc, nc, I, J, K)) return false;
+    const int ch = (int)(tid & 7);
+    i = 2 * I + (ch >> 2);
+    j = 2 * J + ((ch >> 1) & 1);
+    k = 2 * K + (ch & 1);
+    return true;
+}
+
+// Defect r - A d restricted to the coarse grid (8-child average), and the
+// coefficient c restricted the same way (cc_out may be null).  Two forms:
+// one thread per coarse cell (the 8 children's overlapping stencils share
+// loads in registers: large grids), or one thread per fine cell with a lane
+// group per coarse cell (8x the parallelism: small, latency-bound grids).
 template <int BC, typename T>
 __global__ void __launch_bounds__(kBlock) k_defect_restrict_psi(Geo g, const T *__restrict__ d,
                                                                 const T *__restrict__ r,
@@ -321,6 +351,30 @@ __global__ void __launch_bounds__(kBlock) k_defect_restrict_psi(Geo g, const T *
     if (cc_out) cc_out[tid] = sc * T(0.125);
 }
 
+template <int BC, typename T>
+__global__ void __launch_bounds__(kBlock) k_defect_restrict_psi_fine(Geo g, const T *__restrict__ d,
+                                                                     const T *__restrict__ r,
+                                                                     const T *__restrict__ c,
+                                                                     T *__restrict__ rc_out,
+                                                                     T *__restrict__ cc_out)
+{
+    const int nc = g.n / 2;
+    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int64_t qc;
+    int i, j, k;
+    if (!child_of(tid, nc, qc, i, j, k)) return; // whole groups of 8 leave together
+    Acc<BC, T> D{d, g};
+    const T h2 = (T)g.inv12h2;
+    const int64_t q = lidx(g.n, i, j, k);
+    const T x = d[q], cv = c[q];
+    const T sd = child_sum(r[q] - (lap_sum<T>(D, i, j, k, x) * h2 + cv * x));
+    const T sc = child_sum(cv);
+    if ((tid & 7) == 0) {
+        rc_out[qc] = sd * T(0.125);
+        if (cc_out) cc_out[qc] = sc * T(0.125);
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_defect_restrict_W(Geo g, const T *__restrict__ d,
                                                               const T *__restrict__ r,
@@ -347,6 +401,29 @@ __global__ void __launch_bounds__(kBlock) k_defect_restrict_W(Geo g, const T *__
             }
 #pragma unroll
     for (int a = 0; a < 3; a++) rc_out[a * mc + tid] = s[a] * T(0.125);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_defect_restrict_W_fine(Geo g, const T *__restrict__ d,
+                                                                   const T *__restrict__ r,
+                                                                   T *__restrict__ rc_out)
+{
+    const int nc = g.n / 2;
+    const int64_t mf = (int64_t)g.n * g.n * g.n, mc = (int64_t)nc * nc * nc;
+    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int64_t qc;
+    int i, j, k;
+    if (!child_of(tid, nc, qc, i, j, k)) return;
+    const int64_t q = lidx(g.n, i, j, k);
+    T Ad[3];
+    deltaL_apply<T>(g, d, mf, i, j, k, q, Ad);
+    T s[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) s[a] = child_sum(r[a * mf + q] - Ad[a]);
+    if ((tid & 7) == 0) {
+#pragma unroll
+        for (int a = 0; a < 3; a++) rc_out[a * mc + qc] = s[a] * T(0.125);
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -632,15 +709,9 @@ __global__ void __launch_bounds__(kBlock) k_restrict(int nf, const T *__restrict
 // Lane i holds row i of [A | r] in registers.  Pivot: the largest |a_ik| over
 // unused rows, found with one wave max of a packed key (float bits of |a_ik|,
 // low 6 bits replaced by 63 - lane so ties go to the lowest row); the pivot
-// row is broadcast lane-to-scalar with readlane.  No barrier inside the
-// elimination.  *flag = 1 if no non-zero pivot exists.
+// lane writes its row to LDS and every lane reads it back (one wave, so the
+// barriers only order the LDS traffic).  *flag = 1 if no non-zero pivot exists.
 // ---------------------------------------------------------------------------------------
-__device__ __forceinline__ double readlane_d(double v, int lane)
-{
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
-    return __hiloint2double(hi, lo);
-}
 
 template <int BC, typename T, int M>
 __global__ void __launch_bounds__(kWave) k_coarse_psi_wave(Geo g, const T *c, const T *r, T *x, double *flag)
@@ -679,6 +750,9 @@ __global__ void __launch_bounds__(kWave) k_coarse_psi_wave(Geo g, const T *c, co
     double v[NC];
 #pragma unroll
     for (int j = 0; j < NC; j++) v[j] = lane < M ? A[lane][j] : 0.0;
+    // pivot row broadcast through LDS: the pivot lane writes its row, every
+    // lane reads it (a register broadcast per value would serialise)
+    __shared__ double prow[NC];
     uint64_t used = 0;
     bool bad = false;
 #pragma unroll
@@ -697,13 +771,19 @@ __global__ void __launch_bounds__(kWave) k_coarse_psi_wave(Geo g, const T *c, co
         const int p = 63 - (int)(kmax & 63u);
         used |= 1ull << p;
         if (lane == 0) perm[k] = p;
-        const double inv = 1.0 / readlane_d(a, p);
+        if (lane == p) {
+#pragma unroll
+            for (int j = k; j < NC; j++) prow[j] = v[j];
+        }
+        __syncthreads();
+        const double inv = 1.0 / prow[k];
         const double f = a * inv;
 #pragma unroll
         for (int j = k + 1; j < NC; j++) {
-            const double pj = readlane_d(v[j], p);
+            const double pj = prow[j];
             v[j] = (lane == p) ? v[j] * inv : v[j] - f * pj;
         }
+        __syncthreads();
     }
     if (bad) {
         if (lane == 0) *flag = 1.0;
