@@ -256,6 +256,7 @@ mg_status mg_kernel_op(mg_ctx *ctx, int32_t op, int32_t level, int32_t arg, cons
  *     the batch's streams once per outer iteration.
  */
 typedef struct mg_batch mg_batch;
+enum { MG_BATCH_AUTO = 0, MG_BATCH_GRAPH = 1, MG_BATCH_LANES = 2 };
 mg_status mg_batch_workspace_size(const mg_params *p, int32_t count, size_t *bytes);
 mg_status mg_setup_batch(const mg_params *p, int32_t count, void *d_workspace, size_t bytes, void *stream,
                          const double *const *d_rho5, const double *const *d_rho1,
@@ -263,6 +264,20 @@ mg_status mg_setup_batch(const mg_params *p, int32_t count, void *d_workspace, s
 mg_status mg_solve_batch(mg_batch *b, double *const *d_u, double *const *d_W, double tol, int32_t max_outer,
                          mg_report *reps);
 void mg_destroy_batch(mg_batch *b);
+
+/*
+ * Launch mode of a batch's outer iterations (the autotuned choice of the
+ * batched execution).  MG_BATCH_GRAPH: the one batch graph (every member runs,
+ * converged members with their updates gated off).  MG_BATCH_LANES: every
+ * still-active member's own graph, spread over 4 streams so that members run
+ * concurrently, converged members skipped.  MG_BATCH_AUTO (the default): the
+ * first solve times one outer iteration in each mode (wall clock, launch to
+ * completion) and keeps the faster; both replay the same member graphs, so
+ * results are identical in every mode.  request = -1 only queries.  *chosen
+ * (may be NULL): the mode in use (MG_BATCH_AUTO until tuned); h_ms (may be
+ * NULL): the tuning times in ms (graph, lanes; -1 if not measured).
+ */
+mg_status mg_batch_launch_mode(mg_batch *b, int32_t request, int32_t *chosen, double h_ms[2]);
 
 /*
  * Kernel timing probe (measurement support).  mg_probe(ctx, kernel, level)

@@ -930,9 +930,13 @@ struct mg_batch {
     hipEvent_t *ev_join;
     double *scal_all; // device: count x S_COUNT, the members' scalar blocks
     double *hpin;     // pinned copy of scal_all
-    hipGraphExec_t gexec;
-    double **g_u, **g_W; // state pointers the graph was captured for
+    hipGraphExec_t gexec; // the whole batch as one graph (launch mode MG_BATCH_GRAPH)
+    double **g_u, **g_W;  // state pointers the graphs were captured for
     double g_tol;
+    // launch mode: requested (MG_BATCH_AUTO tunes on the first solve), in use,
+    // and the wall time of the tuning iteration in each mode
+    int mode_req, mode;
+    double ms_graph, ms_lanes;
 };
 
 namespace {
@@ -989,6 +993,72 @@ void batch_fork_join(mg_batch *b, F fn)
     }
 }
 
+// Capture every member's outer iteration on the member's stream: each member
+// keeps its own executable graph (launch mode MG_BATCH_LANES) and the batch
+// graph holds them all as independent children (MG_BATCH_GRAPH).
+template <typename T>
+mg_status batch_capture(mg_batch *b, double *const *u, double *const *W, double tol)
+{
+    const int n = b->count;
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+    hipGraph_t parent = nullptr;
+    if (hipGraphCreate(&parent, 0) != hipSuccess) return MG_ERR_HIP;
+    mg_status st = MG_OK;
+    for (int i = 0; i < n && st == MG_OK; i++) {
+        mg_ctx *c = b->ctx[i];
+        drop_graph(c);
+        hipGraph_t g = nullptr;
+        st = capture_graph<T>(c, u[i], W[i], c->momentum || (c->S && W[i]), &g);
+        if (st != MG_OK) break;
+        hipGraphNode_t node = nullptr;
+        if (hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+            c->gexec = nullptr;
+            st = MG_ERR_HIP;
+        } else if (hipGraphAddChildGraphNode(&node, parent, nullptr, 0, g) != hipSuccess) {
+            st = MG_ERR_HIP;
+        }
+        c->g_u = u[i];
+        c->g_W = W[i];
+        (void)hipGraphDestroy(g);
+    }
+    if (st == MG_OK && hipGraphInstantiate(&b->gexec, parent, nullptr, nullptr, 0) != hipSuccess) {
+        b->gexec = nullptr;
+        st = MG_ERR_HIP;
+    }
+    (void)hipGraphDestroy(parent);
+    if (st != MG_OK) return st;
+    for (int i = 0; i < n; i++) {
+        b->g_u[i] = u[i];
+        b->g_W[i] = W[i];
+    }
+    b->g_tol = tol;
+    return MG_OK;
+}
+
+// One outer iteration of the batch in launch mode `mode`: the batch graph on
+// the batch stream, or every still-active member's graph on the lane streams
+// (members spread round-robin over kBatchLanes streams, joined on the batch
+// stream).
+mg_status batch_launch(mg_batch *b, int mode)
+{
+    if (mode == MG_BATCH_GRAPH) return hipGraphLaunch(b->gexec, b->s) == hipSuccess ? MG_OK : MG_ERR_HIP;
+    const int lanes = std::min(kBatchLanes, b->count);
+    if (hipEventRecord(b->ev_root, b->s) != hipSuccess) return MG_ERR_HIP;
+    for (int q = 0; q < lanes; q++)
+        if (hipStreamWaitEvent(b->lane_s[q], b->ev_root, 0) != hipSuccess) return MG_ERR_HIP;
+    for (int i = 0; i < b->count; i++) {
+        if (b->hpin[i * S_COUNT + S_ACTIVE] == 0.0) continue; // converged or diverged: nothing to do
+        if (hipGraphLaunch(b->ctx[i]->gexec, b->ctx[i]->s) != hipSuccess) return MG_ERR_HIP;
+    }
+    for (int q = 0; q < lanes; q++) {
+        if (hipEventRecord(b->ev_join[q], b->lane_s[q]) != hipSuccess ||
+            hipStreamWaitEvent(b->s, b->ev_join[q], 0) != hipSuccess)
+            return MG_ERR_HIP;
+    }
+    return MG_OK;
+}
+
 template <typename T>
 mg_status batch_solve(mg_batch *b, double *const *u, double *const *W, double tol, int max_outer, mg_report *reps)
 {
@@ -1006,33 +1076,8 @@ mg_status batch_solve(mg_batch *b, double *const *u, double *const *W, double to
     bool same = b->gexec && b->g_tol == tol;
     for (int i = 0; same && i < n; i++) same = b->g_u[i] == u[i] && b->g_W[i] == W[i];
     if (!same) {
-        if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
-        b->gexec = nullptr;
-        // every member's outer iteration is captured on the member's own
-        // streams and becomes an independent child of one batch graph
-        hipGraph_t parent = nullptr;
-        if (hipGraphCreate(&parent, 0) != hipSuccess) return MG_ERR_HIP;
-        mg_status st = MG_OK;
-        for (int i = 0; i < n && st == MG_OK; i++) {
-            mg_ctx *c = b->ctx[i];
-            hipGraph_t g = nullptr;
-            st = capture_graph<T>(c, u[i], W[i], c->momentum || (c->S && W[i]), &g);
-            if (st != MG_OK) break;
-            hipGraphNode_t node = nullptr;
-            if (hipGraphAddChildGraphNode(&node, parent, nullptr, 0, g) != hipSuccess) st = MG_ERR_HIP;
-            (void)hipGraphDestroy(g);
-        }
-        if (st == MG_OK && hipGraphInstantiate(&b->gexec, parent, nullptr, nullptr, 0) != hipSuccess) {
-            b->gexec = nullptr;
-            st = MG_ERR_HIP;
-        }
-        (void)hipGraphDestroy(parent);
+        mg_status st = batch_capture<T>(b, u, W, tol);
         if (st != MG_OK) return st;
-        for (int i = 0; i < n; i++) {
-            b->g_u[i] = u[i];
-            b->g_W[i] = W[i];
-        }
-        b->g_tol = tol;
     }
     int it = 0;
     for (;; it++) {
@@ -1043,7 +1088,24 @@ mg_status batch_solve(mg_batch *b, double *const *u, double *const *W, double to
         int active = 0;
         for (int i = 0; i < n; i++) active += b->hpin[i * S_COUNT + S_ACTIVE] != 0.0;
         if (active == 0 || it >= max_outer) break;
-        if (hipGraphLaunch(b->gexec, b->s) != hipSuccess) return MG_ERR_HIP;
+        // launch-mode tuning: one timed outer iteration in each mode (the two
+        // modes replay the same member graphs, so the results do not change)
+        int mode = b->mode;
+        const bool tune = b->mode_req == MG_BATCH_AUTO && b->mode == MG_BATCH_AUTO;
+        if (tune) mode = (b->ms_graph < 0.0) ? MG_BATCH_GRAPH : MG_BATCH_LANES;
+        const auto l0 = std::chrono::steady_clock::now();
+        mg_status ls = batch_launch(b, mode);
+        if (ls != MG_OK) return ls;
+        if (tune) {
+            if (hipStreamSynchronize(b->s) != hipSuccess) return MG_ERR_HIP;
+            const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - l0).count();
+            if (mode == MG_BATCH_GRAPH)
+                b->ms_graph = ms;
+            else {
+                b->ms_lanes = ms;
+                b->mode = b->ms_lanes < b->ms_graph ? MG_BATCH_LANES : MG_BATCH_GRAPH;
+            }
+        }
     }
     auto t1 = std::chrono::steady_clock::now();
     mg_status worst = MG_OK;
@@ -1116,6 +1178,8 @@ mg_status mg_setup_batch(const mg_params *p, int32_t count, void *d_workspace, s
     std::memset(b, 0, sizeof(*b));
     b->count = count;
     b->user_s = (hipStream_t)stream;
+    b->mode_req = b->mode = MG_BATCH_AUTO;
+    b->ms_graph = b->ms_lanes = -1.0;
     b->ctx = new (std::nothrow) mg_ctx *[count]();
     b->ev_join = new (std::nothrow) hipEvent_t[count]();
     b->g_u = new (std::nothrow) double *[count]();
@@ -1200,6 +1264,22 @@ mg_status mg_solve_batch(mg_batch *b, double *const *d_u, double *const *d_W, do
 }
 
 void mg_destroy_batch(mg_batch *b) { batch_release(b); }
+
+mg_status mg_batch_launch_mode(mg_batch *b, int32_t request, int32_t *chosen, double h_ms[2])
+{
+    if (!b || request < -1 || request > MG_BATCH_LANES) return MG_ERR_INVALID;
+    if (request >= 0) {
+        b->mode_req = request;
+        b->mode = request;
+        if (request == MG_BATCH_AUTO) b->ms_graph = b->ms_lanes = -1.0;
+    }
+    if (chosen) *chosen = b->mode;
+    if (h_ms) {
+        h_ms[0] = b->ms_graph;
+        h_ms[1] = b->ms_lanes;
+    }
+    return MG_OK;
+}
 
 mg_status mg_vcycle(mg_ctx *c, int32_t eq, double *d_u, double *d_W)
 {

@@ -88,6 +88,7 @@ def lib() -> C.CDLL:
                                      C.POINTER(MgReport)]
         L.mg_destroy_batch.argtypes = [vp]
         L.mg_destroy_batch.restype = None
+        L.mg_batch_launch_mode.argtypes = [vp, i32, C.POINTER(i32), dp]
         L.mg_fmg_start.argtypes = [vp, vp, vp, vp, C.c_double, i32, vp, vp, C.POINTER(MgReport)]
         L.mg_probe.argtypes = [vp, i32, i32]
         L.mg_probe_result.argtypes = [vp, C.POINTER(i32), C.POINTER(C.c_double)]
@@ -95,7 +96,7 @@ def lib() -> C.CDLL:
                   "mg_residual_norm", "mg_residual_fields", "mg_scalar_field_sources",
                   "mg_shell_field_sources", "mg_interp_cubic", "mg_kernel_op", "mg_probe",
                   "mg_probe_result", "mg_batch_workspace_size", "mg_setup_batch", "mg_solve_batch",
-                  "mg_fmg_start"):
+                  "mg_fmg_start", "mg_batch_launch_mode"):
             getattr(L, f).restype = st
         _lib = L
     return _lib
@@ -240,6 +241,9 @@ def _ptr_array(ts, dtype=torch.float64):
     return arr
 
 
+BATCH_AUTO, BATCH_GRAPH, BATCH_LANES = 0, 1, 2
+
+
 class Batch:
     """A batch of independent instances solved together (one graph launch per
     outer iteration for the whole batch)."""
@@ -271,6 +275,13 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+    def launch_mode(self, request: int = -1):
+        """Set (request >= 0) and/or query the launch mode: (mode in use, [ms graph, ms lanes])."""
+        chosen = C.c_int32(0)
+        ms = (C.c_double * 2)()
+        _check(lib().mg_batch_launch_mode(self.b, request, C.byref(chosen), ms), "mg_batch_launch_mode")
+        return chosen.value, [ms[0], ms[1]]
 
     def solve(self, us, Ws=None, tol=1e-10, max_outer=100, raise_on_failure=True):
         reps = (MgReport * self.count)()

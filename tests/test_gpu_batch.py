@@ -87,3 +87,26 @@ def test_batch_gates_converged_members():
     st, reps = batch.solve(us, Ws, tol=1e-10)
     assert reps[0]["outer_iters"] == 0 and torch.equal(us[0], solved[0])
     assert reps[1]["outer_iters"] > 0 and torch.equal(us[1], solved[1])
+
+
+def test_batch_launch_modes_agree_and_autotune():
+    """Both launch modes replay the same member graphs: identical results;
+    the automatic mode times one outer iteration in each and keeps one."""
+    ws = synth.scan_96(count=5, sizes=(32, 48))
+    plist, r5s, r1s, Ss, Ks = make_members(ws, g.PREC_FP32_IR)
+    batch = g.Batch(plist, r5s, r1s, Ss)
+    results = {}
+    for mode in (g.BATCH_GRAPH, g.BATCH_LANES, g.BATCH_AUTO):
+        batch.launch_mode(mode)
+        us = [torch.zeros((w.n,) * 3, dtype=torch.float64, device=dev()) for w in ws]
+        Ws = [torch.zeros((3,) + (w.n,) * 3, dtype=torch.float64, device=dev()) for w in ws]
+        st, reps = batch.solve(us, Ws, tol=1e-10, max_outer=60)
+        assert st == 0
+        results[mode] = ([N(u) for u in us], [r["outer_iters"] for r in reps])
+    chosen, ms = batch.launch_mode()
+    print(f"autotuned launch mode {chosen}: graph {ms[0]:.2f} ms, lanes {ms[1]:.2f} ms per outer iteration")
+    assert chosen in (g.BATCH_GRAPH, g.BATCH_LANES) and ms[0] > 0 and ms[1] > 0
+    for mode in (g.BATCH_LANES, g.BATCH_AUTO):
+        assert results[mode][1] == results[g.BATCH_GRAPH][1]
+        for a, b in zip(results[mode][0], results[g.BATCH_GRAPH][0]):
+            assert np.array_equal(a, b)
