@@ -101,6 +101,11 @@ def main():
     mixed = g.Solver(p, rho5, rho1, S)
     u = torch.zeros((n,) * 3, dtype=torch.float64, device=dev)
     W = torch.zeros((3, n, n, n), dtype=torch.float64, device=dev)
+    # brick depths of the tiled kernels, autotuned on this workload (off the clock)
+    tuning = mixed.autotune(u, W, reps=20)
+    for e in tuning:
+        log(f"[bench] autotune family {e['family']} level {e['level']}: chosen {e['chosen']} "
+            + " ".join(f"{k}:{v:.2f}us" for k, v in e["candidates"].items()))
 
     def step(solver):
         u.zero_()
@@ -271,6 +276,8 @@ def main():
             "fp64_seconds": fp64["seconds"] if fp64 else None,
             "fp64_outer_iters": fp64["outer_iters"] if fp64 else None,
             "speedup_vs_fp64": (fp64["seconds"] / headline) if fp64 else None,
+            "autotuned_bricks": [{"family": e["family"], "level": e["level"], "depth": e["chosen"]}
+                                 for e in tuning],
             "learned": learned,
             "fmg_start": fmg,
         },

@@ -209,6 +209,31 @@ mg_status mg_fmg_start(mg_ctx *cc, mg_ctx *cf, double *d_uc, double *d_Wc, doubl
                        int32_t max_outer, double *d_uf, double *d_Wf, mg_report *rep_c);
 
 /*
+ * Autotuning of the tiled kernels' brick depth (the x extent of the LDS brick
+ * of the finest-level smoothers and residual; other levels are not tiled).
+ * For every tileable (family, level) of the context, mg_autotune times each
+ * candidate depth with HIP events around `reps` launches on the context's own
+ * data (the residuals of the state (d_u, d_W), zero corrections; the state is
+ * not changed), keeps the fastest in the context and drops the captured
+ * outer-iteration graph.  The candidates compute every cell with the same
+ * arithmetic, so the solution does not depend on the choice.  h_out (cap
+ * entries, may be NULL with cap 0) receives one mg_tune per tuned (family,
+ * level); *h_count (may be NULL) the number of entries.  Waits for the
+ * stream.  mg_set_tile applies a stored choice (a candidate of the family;
+ * MG_ERR_INVALID otherwise).  Candidates: psi pass {2, 4, 8}; W pass {1, 2, 4}
+ * (FP32) or {1, 2} (FP64); residual {1, 2, 4}.
+ */
+enum { MG_TUNE_PASS_PSI = 1, MG_TUNE_PASS_W = 2, MG_TUNE_RESIDUAL = 3 };
+typedef struct mg_tune {
+    int32_t family, level, chosen, ncand;
+    int32_t cand[4];
+    double us[4]; /* mean microseconds per launch, -1 if the candidate does not fit */
+} mg_tune;
+mg_status mg_autotune(mg_ctx *ctx, const double *d_u, const double *d_W, int32_t reps, mg_tune *h_out,
+                      int32_t cap, int32_t *h_count);
+mg_status mg_set_tile(mg_ctx *ctx, int32_t family, int32_t level, int32_t tx);
+
+/*
  * Single-kernel entry points on one level of a context, for diagnostics and
  * kernel-level parity checks.  Arrays are in the context's V-cycle type
  * (double for MG_PREC_FP64, float for MG_PREC_FP32_IR), on level `level`

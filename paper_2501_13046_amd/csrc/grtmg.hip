@@ -57,9 +57,17 @@ struct Carver {
 unsigned nblk(int64_t count) { return (unsigned)((count + kBlock - 1) / kBlock); }
 
 constexpr int kProbeMax = 4096;
-constexpr int kBrickPsi = 4; // brick depth along x of the tiled psi smoother
-constexpr int kBrickW = 2;   // brick depth along x of the tiled W smoother
-constexpr int kBrickR = 2;   // brick depth along x of the tiled residual
+// Brick depths along x of the tiled kernels: defaults and the candidates the
+// autotuner times (per-cell arithmetic does not depend on the depth, so every
+// candidate gives bitwise the same fields).  The FP64 W brick is limited by
+// LDS (depth 2 uses 152 KB).
+constexpr int kBrickPsi = 4;
+constexpr int kBrickW = 2;
+constexpr int kBrickR = 2;
+constexpr int kCandPsi[] = {2, 4, 8};
+constexpr int kCandW32[] = {1, 2, 4};
+constexpr int kCandW64[] = {1, 2};
+constexpr int kCandR[] = {1, 2, 4};
 
 } // namespace
 
@@ -175,6 +183,27 @@ void carve(mg_ctx *c, Carver &cv)
     }
 }
 
+TileMap tilemap_rt(int n, int tx)
+{
+    switch (tx) {
+    case 1: return make_tilemap<1>(n);
+    case 2: return make_tilemap<2>(n);
+    case 4: return make_tilemap<4>(n);
+    case 8: return make_tilemap<8>(n);
+    default: return TileMap{0, 0, 0, 0};
+    }
+}
+
+TileMap rtilemap_rt(int n, int tx)
+{
+    switch (tx) {
+    case 1: return make_rtilemap<1>(n);
+    case 2: return make_rtilemap<2>(n);
+    case 4: return make_rtilemap<4>(n);
+    default: return TileMap{0, 0, 0, 0};
+    }
+}
+
 void init_geo(mg_ctx *c)
 {
     for (int l = 0; l < c->L; l++) {
@@ -277,6 +306,18 @@ void coarse_W(mg_ctx *c, const T *r, T *x)
 
 // ---- psi V-cycle ----------------------------------------------------------------------
 
+template <int BC, typename T>
+void launch_psi_tiled(hipStream_t s, const Geo &g, const TileMap &tm, const T *in, T *out, const T *r, const T *cf,
+                      int colour)
+{
+    const dim3 blk(kLanes, kTY), grid(ntiles(tm));
+    switch (tm.tx) {
+    case 2: hipLaunchKernelGGL((k_pass_psi_tiled<BC, T, 2>), grid, blk, 0, s, g, tm, in, out, r, cf, colour); break;
+    case 8: hipLaunchKernelGGL((k_pass_psi_tiled<BC, T, 8>), grid, blk, 0, s, g, tm, in, out, r, cf, colour); break;
+    default: hipLaunchKernelGGL((k_pass_psi_tiled<BC, T, 4>), grid, blk, 0, s, g, tm, in, out, r, cf, colour); break;
+    }
+}
+
 template <typename T>
 void pass_psi(mg_ctx *c, int l, const T *in, T *out, int colour)
 {
@@ -285,13 +326,11 @@ void pass_psi(mg_ctx *c, int l, const T *in, T *out, int colour)
     const unsigned nb = nblk(c->cells[l]);
     const TileMap &tm = c->tile[l];
     if (tm.tx > 0) {
-        const dim3 blk(kLanes, kTY);
+        const T *r = (const T *)c->pr[l], *cf = (const T *)c->pc[l];
         if (c->p.bc == MG_BC_PERIODIC)
-            hipLaunchKernelGGL((k_pass_psi_tiled<kBcPeriodic, T, kBrickPsi>), dim3(ntiles(tm)), blk, 0, c->s, g,
-                               tm, in, out, (const T *)c->pr[l], (const T *)c->pc[l], colour);
+            launch_psi_tiled<kBcPeriodic, T>(c->s, g, tm, in, out, r, cf, colour);
         else
-            hipLaunchKernelGGL((k_pass_psi_tiled<kBcRobin, T, kBrickPsi>), dim3(ntiles(tm)), blk, 0, c->s, g, tm,
-                               in, out, (const T *)c->pr[l], (const T *)c->pc[l], colour);
+            launch_psi_tiled<kBcRobin, T>(c->s, g, tm, in, out, r, cf, colour);
         return;
     }
     if (c->p.bc == MG_BC_PERIODIC)
@@ -413,13 +452,25 @@ void vcycle_psi(mg_ctx *c, int l)
 // ---- W V-cycle ------------------------------------------------------------------------
 
 template <typename T>
+void launch_W_tiled(hipStream_t s, const Geo &g, const TileMap &tm, const T *in, T *out, const T *r, int colour)
+{
+    const dim3 blk(kLanes, kTY), grid(ntiles(tm));
+    if (tm.tx == 1)
+        hipLaunchKernelGGL((k_pass_W_tiled<T, 1>), grid, blk, 0, s, g, tm, in, out, r, colour);
+    else if (tm.tx == 4 && sizeof(T) == 4)
+        hipLaunchKernelGGL((k_pass_W_tiled<float, 4>), grid, blk, 0, s, g, tm, (const float *)in, (float *)out,
+                           (const float *)r, colour);
+    else
+        hipLaunchKernelGGL((k_pass_W_tiled<T, 2>), grid, blk, 0, s, g, tm, in, out, r, colour);
+}
+
+template <typename T>
 void pass_W(mg_ctx *c, int l, const T *in, T *out, const T *r, int colour)
 {
     Probe pr(c, MG_PROBE_PASS_W, l);
     const TileMap &tm = c->tileW[l];
     if (tm.tx > 0)
-        hipLaunchKernelGGL((k_pass_W_tiled<T, kBrickW>), dim3(ntiles(tm)), dim3(kLanes, kTY), 0, c->s, c->geo[l],
-                           tm, in, out, r, colour);
+        launch_W_tiled<T>(c->s, c->geo[l], tm, in, out, r, colour);
     else
         hipLaunchKernelGGL(k_pass_W<T>, dim3(nblk(c->cells[l])), dim3(kBlock), 0, c->s, c->geo[l], in, out, r,
                            colour);
@@ -466,6 +517,27 @@ void source_mean(mg_ctx *c, const double *u)
                        0u, 1.0 / (double)c->cells[0], c->scal + S_MEANS);
 }
 
+template <int BC, typename T, int TX>
+void launch_residual_tx(hipStream_t s, const Geo &g, const TileMap &tm, const ResArgs &a, bool hasW)
+{
+    const dim3 blk(kLanes, kTY), grid(ntiles(tm));
+    if (hasW)
+        hipLaunchKernelGGL((k_residual_tiled<BC, T, TX, true>), grid, blk, 0, s, g, tm, a);
+    else
+        hipLaunchKernelGGL((k_residual_tiled<BC, T, TX, false>), grid, blk, 0, s, g, tm, a);
+}
+
+template <int BC, typename T>
+void launch_residual_tiled(hipStream_t s, const Geo &g, const TileMap &tm, const ResArgs &a, bool hasW)
+{
+    if (tm.tx == 1)
+        launch_residual_tx<BC, T, 1>(s, g, tm, a, hasW);
+    else if (tm.tx == 4)
+        launch_residual_tx<BC, T, 4>(s, g, tm, a, hasW);
+    else
+        launch_residual_tx<BC, T, 2>(s, g, tm, a, hasW);
+}
+
 template <typename T>
 void residual(mg_ctx *c, const double *u, const double *W, bool want_M, double *H, double *M,
               double *cc, void *r, void *rc, void *rW, bool norms)
@@ -495,22 +567,10 @@ void residual(mg_ctx *c, const double *u, const double *W, bool want_M, double *
         const TileMap &tm = c->tileR;
         if (tm.tx > 0) {
             nb = ntiles(tm);
-            const dim3 blk(kLanes, kTY);
-            if (c->p.bc == MG_BC_PERIODIC) {
-                if (W)
-                    hipLaunchKernelGGL((k_residual_tiled<kBcPeriodic, T, kBrickR, true>), dim3(nb), blk, 0, c->s,
-                                       c->geo[0], tm, a);
-                else
-                    hipLaunchKernelGGL((k_residual_tiled<kBcPeriodic, T, kBrickR, false>), dim3(nb), blk, 0, c->s,
-                                       c->geo[0], tm, a);
-            } else {
-                if (W)
-                    hipLaunchKernelGGL((k_residual_tiled<kBcRobin, T, kBrickR, true>), dim3(nb), blk, 0, c->s,
-                                       c->geo[0], tm, a);
-                else
-                    hipLaunchKernelGGL((k_residual_tiled<kBcRobin, T, kBrickR, false>), dim3(nb), blk, 0, c->s,
-                                       c->geo[0], tm, a);
-            }
+            if (c->p.bc == MG_BC_PERIODIC)
+                launch_residual_tiled<kBcPeriodic, T>(c->s, c->geo[0], tm, a, W != nullptr);
+            else
+                launch_residual_tiled<kBcRobin, T>(c->s, c->geo[0], tm, a, W != nullptr);
         } else if (c->p.bc == MG_BC_PERIODIC)
             hipLaunchKernelGGL((k_residual<kBcPeriodic, T>), dim3(nb), dim3(kBlock), 0, c->s, c->geo[0], a);
         else
@@ -819,6 +879,128 @@ mg_status kernel_op(mg_ctx *c, int op, int l, int arg, const void *in, void *out
         return MG_ERR_INVALID;
     }
     return hip_status();
+}
+
+// ---- autotuning of the brick depths ----------------------------------------------------
+
+const int *tune_candidates(const mg_ctx *c, int family, int &count)
+{
+    switch (family) {
+    case MG_TUNE_PASS_PSI: count = 3; return kCandPsi;
+    case MG_TUNE_PASS_W:
+        if (c->f32) {
+            count = 3;
+            return kCandW32;
+        }
+        count = 2;
+        return kCandW64;
+    case MG_TUNE_RESIDUAL: count = 3; return kCandR;
+    default: count = 0; return nullptr;
+    }
+}
+
+// The brick map of (family, level) for depth tx (tx == 0 in the map: not tileable).
+TileMap tune_map(const mg_ctx *c, int family, int level, int tx)
+{
+    if (family == MG_TUNE_RESIDUAL) return level == 0 ? rtilemap_rt(c->n[0], tx) : TileMap{0, 0, 0, 0};
+    if (family == MG_TUNE_PASS_W && !c->momentum) return TileMap{0, 0, 0, 0};
+    return tilemap_rt(c->n[level], tx);
+}
+
+TileMap &tune_slot(mg_ctx *c, int family, int level)
+{
+    if (family == MG_TUNE_PASS_PSI) return c->tile[level];
+    if (family == MG_TUNE_PASS_W) return c->tileW[level];
+    return c->tileR;
+}
+
+// Times every candidate depth of every tileable (family, level) with HIP events
+// around `reps` launches on the state's own data (residuals of (u, W), zero
+// corrections), keeps the fastest, and drops the captured graph.
+template <typename T>
+mg_status autotune(mg_ctx *c, const double *u, const double *W, int reps, mg_tune *out, int cap, int *count)
+{
+    const int probe = c->probe_kernel;
+    c->probe_kernel = MG_PROBE_NONE;
+    const bool wantM = c->momentum || (c->S != nullptr && W != nullptr);
+    source_mean(c, u);
+    residual<T>(c, u, W, false, nullptr, nullptr, nullptr, c->pr[0], c->pc[0], nullptr, false);
+    restrict_coefficients<T>(c);
+    for (int l = 0; l < c->L; l++) {
+        fill<T>(c->s, (T *)c->pd0[l], c->cells[l], T(0));
+        if (l > 0) fill<T>(c->s, (T *)c->pr[l], c->cells[l], T(0));
+    }
+    if (c->momentum) {
+        residual<T>(c, u, W, true, nullptr, nullptr, nullptr, nullptr, nullptr, c->wr[0], false);
+        for (int l = 0; l < c->L; l++) {
+            fill<T>(c->s, (T *)c->wd0[l], 3 * c->cells[l], T(0));
+            if (l > 0) fill<T>(c->s, (T *)c->wr[l], 3 * c->cells[l], T(0));
+        }
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        c->probe_kernel = probe;
+        return MG_ERR_HIP;
+    }
+    mg_status st = MG_OK;
+    int k = 0;
+    for (int family = MG_TUNE_PASS_PSI; family <= MG_TUNE_RESIDUAL && st == MG_OK; family++) {
+        int nc = 0;
+        const int *cand = tune_candidates(c, family, nc);
+        const int nlev = family == MG_TUNE_RESIDUAL ? 1 : c->L;
+        for (int l = 0; l < nlev && st == MG_OK; l++) {
+            if (tune_map(c, family, l, cand[0]).tx == 0) continue;
+            mg_tune e;
+            std::memset(&e, 0, sizeof(e));
+            e.family = family;
+            e.level = l;
+            e.ncand = nc;
+            double best = 1e300;
+            TileMap bestmap = tune_slot(c, family, l);
+            for (int q = 0; q < nc; q++) {
+                e.cand[q] = cand[q];
+                const TileMap tm = tune_map(c, family, l, cand[q]);
+                e.us[q] = -1.0;
+                if (tm.tx == 0) continue;
+                tune_slot(c, family, l) = tm;
+                auto launch = [&](int r) {
+                    if (family == MG_TUNE_PASS_PSI)
+                        pass_psi<T>(c, l, (const T *)c->pd0[l], (T *)c->pd1[l], r & 1);
+                    else if (family == MG_TUNE_PASS_W)
+                        pass_W<T>(c, l, (const T *)c->wd0[l], (T *)c->wd1[l], (const T *)c->wr[l], r & 1);
+                    else if (c->momentum)
+                        residual<T>(c, u, W, true, nullptr, nullptr, nullptr, nullptr, nullptr, c->wr[0], true);
+                    else
+                        residual<T>(c, u, W, wantM, nullptr, nullptr, nullptr, c->pr[0], c->pc[0], nullptr, true);
+                };
+                for (int r = 0; r < 2; r++) launch(r);
+                float ms = 0.0f;
+                if (hipEventRecord(e0, c->s) != hipSuccess) st = MG_ERR_HIP;
+                for (int r = 0; r < reps && st == MG_OK; r++) launch(r);
+                if (st == MG_OK && (hipEventRecord(e1, c->s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                    st = MG_ERR_HIP;
+                if (st != MG_OK) break;
+                e.us[q] = 1e3 * ms / reps;
+                if (e.us[q] < best) {
+                    best = e.us[q];
+                    bestmap = tm;
+                    e.chosen = cand[q];
+                }
+            }
+            tune_slot(c, family, l) = bestmap;
+            if (out && k < cap) out[k] = e;
+            k++;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->probe_kernel = probe;
+    drop_graph(c);
+    if (count) *count = k;
+    if (st == MG_OK) st = hip_status();
+    return st;
 }
 
 } // namespace
@@ -1493,6 +1675,35 @@ mg_status mg_fmg_start(mg_ctx *cc, mg_ctx *cf, double *d_uc, double *d_Wc, doubl
     leave(cf);
     if (hip_status() != MG_OK) return MG_ERR_HIP;
     return st;
+}
+
+mg_status mg_autotune(mg_ctx *c, const double *d_u, const double *d_W, int32_t reps, mg_tune *h_out, int32_t cap,
+                      int32_t *h_count)
+{
+    if (!c || !d_u || reps < 1 || reps > 1000 || cap < 0 || (cap > 0 && !h_out)) return MG_ERR_INVALID;
+    if (c->momentum && !d_W) return MG_ERR_INVALID;
+    enter(c);
+    int k = 0;
+    mg_status st = c->f32 ? autotune<float>(c, d_u, d_W, reps, h_out, cap, &k)
+                          : autotune<double>(c, d_u, d_W, reps, h_out, cap, &k);
+    leave(c);
+    if (h_count) *h_count = k;
+    return st;
+}
+
+mg_status mg_set_tile(mg_ctx *c, int32_t family, int32_t level, int32_t tx)
+{
+    if (!c || level < 0 || level >= c->L) return MG_ERR_INVALID;
+    int nc = 0;
+    const int *cand = tune_candidates(c, family, nc);
+    bool ok = false;
+    for (int q = 0; q < nc; q++) ok = ok || cand[q] == tx;
+    if (!ok) return MG_ERR_INVALID;
+    const TileMap tm = tune_map(c, family, level, tx);
+    if (tm.tx == 0) return MG_ERR_INVALID;
+    tune_slot(c, family, level) = tm;
+    drop_graph(c);
+    return MG_OK;
 }
 
 mg_status mg_kernel_op(mg_ctx *c, int32_t op, int32_t level, int32_t arg, const void *d_in, void *d_out,

@@ -48,6 +48,14 @@ class MgReport(C.Structure):
                 ("history_len", C.c_int32)]
 
 
+TUNE_PASS_PSI, TUNE_PASS_W, TUNE_RESIDUAL = 1, 2, 3
+
+
+class MgTune(C.Structure):
+    _fields_ = [("family", C.c_int32), ("level", C.c_int32), ("chosen", C.c_int32), ("ncand", C.c_int32),
+                ("cand", C.c_int32 * 4), ("us", C.c_double * 4)]
+
+
 class MGError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
@@ -88,6 +96,8 @@ def lib() -> C.CDLL:
                                      C.POINTER(MgReport)]
         L.mg_destroy_batch.argtypes = [vp]
         L.mg_destroy_batch.restype = None
+        L.mg_autotune.argtypes = [vp, vp, vp, i32, C.POINTER(MgTune), i32, C.POINTER(i32)]
+        L.mg_set_tile.argtypes = [vp, i32, i32, i32]
         L.mg_batch_launch_mode.argtypes = [vp, i32, C.POINTER(i32), dp]
         L.mg_fmg_start.argtypes = [vp, vp, vp, vp, C.c_double, i32, vp, vp, C.POINTER(MgReport)]
         L.mg_probe.argtypes = [vp, i32, i32]
@@ -96,7 +106,7 @@ def lib() -> C.CDLL:
                   "mg_residual_norm", "mg_residual_fields", "mg_scalar_field_sources",
                   "mg_shell_field_sources", "mg_interp_cubic", "mg_kernel_op", "mg_probe",
                   "mg_probe_result", "mg_batch_workspace_size", "mg_setup_batch", "mg_solve_batch",
-                  "mg_fmg_start", "mg_batch_launch_mode"):
+                  "mg_fmg_start", "mg_batch_launch_mode", "mg_autotune", "mg_set_tile"):
             getattr(L, f).restype = st
         _lib = L
     return _lib
@@ -185,6 +195,19 @@ class Solver:
 
     def _W(self, W):
         return _dptr(W, numel=3 * self.cells) if W is not None else None
+
+    def autotune(self, u: torch.Tensor, W: Optional[torch.Tensor] = None, reps: int = 20) -> list:
+        """Time the brick-depth candidates of the tiled kernels on this state; keep the fastest."""
+        cap = 16
+        out = (MgTune * cap)()
+        cnt = C.c_int32(0)
+        _check(lib().mg_autotune(self.ctx, _dptr(u, numel=self.cells), self._W(W), reps, out, cap, C.byref(cnt)),
+               "mg_autotune")
+        return [dict(family=e.family, level=e.level, chosen=e.chosen,
+                     candidates={e.cand[q]: e.us[q] for q in range(e.ncand)}) for e in out[:cnt.value]]
+
+    def set_tile(self, family: int, level: int, tx: int):
+        _check(lib().mg_set_tile(self.ctx, family, level, tx), "mg_set_tile")
 
     def vcycle(self, eq: int, u: torch.Tensor, W: Optional[torch.Tensor] = None):
         _check(lib().mg_vcycle(self.ctx, eq, _dptr(u, numel=self.cells), self._W(W)), "mg_vcycle")
@@ -333,6 +356,38 @@ def interp_cubic(pc: MgParams, coarse: torch.Tensor) -> torch.Tensor:
     _check(lib().mg_interp_cubic(C.byref(pc), _dptr(coarse, numel=nc ** 3), _dptr(fine),
                                  _stream(coarse.device)), "mg_interp_cubic")
     return fine
+
+
+def tune_key(p: MgParams) -> str:
+    return f"n{p.n}_L{p.levels}_prec{p.precision}_bc{p.bc}_mom{p.solve_momentum}"
+
+
+def autotune_cached(solver: "Solver", u: torch.Tensor, W: Optional[torch.Tensor] = None,
+                    path: Optional[str] = None, reps: int = 20) -> list:
+    """Apply the brick depths stored for this configuration in a JSON cache
+    (path, else $GRTMG_TUNE_CACHE, else ~/.cache/grtmg_tune.json); tune and
+    store them when the configuration is not in the cache yet."""
+    import json
+    path = path or os.environ.get("GRTMG_TUNE_CACHE") or os.path.join(os.path.expanduser("~"), ".cache",
+                                                                         "grtmg_tune.json")
+    try:
+        with open(path) as f:
+            cache = json.load(f)
+    except (OSError, ValueError):
+        cache = {}
+    key = tune_key(solver.p)
+    if key in cache:
+        for e in cache[key]:
+            solver.set_tile(e["family"], e["level"], e["chosen"])
+        return cache[key]
+    entries = solver.autotune(u, W, reps)
+    cache[key] = [dict(family=e["family"], level=e["level"], chosen=e["chosen"]) for e in entries]
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1)
+    os.replace(tmp, path)
+    return entries
 
 
 def fmg_start(coarse: "Solver", fine: "Solver", uc: torch.Tensor, Wc: Optional[torch.Tensor],

@@ -1,0 +1,63 @@
+"""Brick-depth autotuning of the tiled kernels: every candidate gives bitwise
+the same solve (the depth does not change per-cell arithmetic), the tuner
+reports a time for every candidate and keeps the fastest, and choices apply
+from a cache file."""
+import json
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from paper_2501_13046_amd import grtmg as g
+from gpu_helpers import N, dev, gparams
+
+pytestmark = pytest.mark.gpu
+
+
+def setup(precision):
+    w = synth.coupled(128, seed=2, precision=precision)
+    p = gparams(w)
+    r5, r1, S, mean = g.scalar_field_sources(p, w.phi_modes, w.pi_modes, w.scalar_mass, dev())
+    p.K = g.K_from_mean_density(mean)
+    return g.Solver(p, r5, r1, S)
+
+
+def solve(s):
+    u = torch.zeros((128,) * 3, dtype=torch.float64, device=dev())
+    W = torch.zeros((3, 128, 128, 128), dtype=torch.float64, device=dev())
+    rep = s.solve(u, W, tol=1e-10, max_outer=60)
+    return N(u), N(W), rep["outer_iters"]
+
+
+@pytest.mark.parametrize("precision", [g.PREC_FP32_IR, g.PREC_FP64])
+def test_every_candidate_gives_the_same_solve(precision, tmp_path):
+    s = setup(precision)
+    u0, W0, it0 = solve(s)
+    entries = s.autotune(torch.zeros((128,) * 3, dtype=torch.float64, device=dev()),
+                         torch.zeros((3, 128, 128, 128), dtype=torch.float64, device=dev()), reps=10)
+    fams = {e["family"] for e in entries}
+    assert fams == {g.TUNE_PASS_PSI, g.TUNE_PASS_W, g.TUNE_RESIDUAL}
+    for e in entries:
+        print(f"family {e['family']} level {e['level']}: chosen {e['chosen']}, us {e['candidates']}")
+        times = {k: v for k, v in e["candidates"].items() if v > 0}
+        assert e["chosen"] in times and times[e["chosen"]] == min(times.values())
+    u1, W1, it1 = solve(s)
+    assert it1 == it0 and np.array_equal(u1, u0) and np.array_equal(W1, W0)
+    for e in entries:
+        for tx in e["candidates"]:
+            s.set_tile(e["family"], e["level"], tx)
+            u2, W2, it2 = solve(s)
+            assert it2 == it0 and np.array_equal(u2, u0) and np.array_equal(W2, W0), (e["family"], tx)
+        s.set_tile(e["family"], e["level"], e["chosen"])
+    with pytest.raises(g.MGError):
+        s.set_tile(g.TUNE_PASS_PSI, 0, 3)
+    # the cache: first call tunes and stores, the second applies the stored choice
+    path = str(tmp_path / "tune.json")
+    z = torch.zeros((128,) * 3, dtype=torch.float64, device=dev())
+    zw = torch.zeros((3, 128, 128, 128), dtype=torch.float64, device=dev())
+    first = g.autotune_cached(s, z, zw, path=path, reps=5)
+    stored = json.load(open(path))[g.tune_key(s.p)]
+    assert [e["chosen"] for e in stored] == [e["chosen"] for e in first]
+    again = g.autotune_cached(s, z, zw, path=path)
+    assert again == stored
