@@ -4,16 +4,20 @@
 Metric: seconds to reach an RMS Hamiltonian and momentum constraint residual
 of 1e-10 on the 128^3 periodic coupled workload (scalar field: phi from 8
 Fourier modes of amplitude 0.05, Pi from 8 modes of amplitude 0.02; K^2 =
-24 pi <rho>), solving for psi and W_i.  One step = one full solve from
-psi = 1, W = 0, inputs resident in HBM.  The headline value is the FP32
-V-cycle inside FP64 iterative refinement; the plain FP64 GPU multigrid is
-timed on the same input and reported beside it.
+24 pi <rho>), solving for psi and W_i.  One step = one full solve, inputs
+resident in HBM, brick depths of the tiled kernels autotuned before timing.
+The headline value is the FP32 V-cycle inside FP64 iterative refinement
+started by the trained warm-start network (prediction, one outer iteration,
+fallback test, solve); the same solve from psi = 1, W = 0, the full-multigrid
+start from the 64^3 problem and the plain FP64 GPU multigrid are timed on the
+same input and reported beside it.
 
 The JSON line also carries the roofline of the dominant kernel (its launches
-inside a real solve timed with HIP event pairs) and the CPU oracle timed on a
-bounded sample of the same workload.
+inside a real solve timed with HIP event pairs; HBM traffic from the committed
+counter summary while the kernel sources match it) and the CPU oracle timed
+on a bounded sample of the same workload.
 
-    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-fp64]
 """
 import argparse
 import json
