@@ -254,7 +254,7 @@ void factor(hipStream_t s, double *A, double *aug, double *inv, int m, double *f
                        m, flag);
 }
 
-// Coarsest sizes solved by the single-wavefront Gauss-Jordan kernel.
+// Coarsest sizes solved by the register-resident Gauss-Jordan kernel (one block).
 bool wave_solvable(int m) { return m == 8 || m == 27 || m == 64; }
 
 template <int BC, typename T>
@@ -264,9 +264,9 @@ void launch_coarse_wave(mg_ctx *c, int l, const T *r, T *x)
     const T *cf = (const T *)c->pc[l];
     double *flag = c->scal + S_FLAG_PSI;
     switch (c->m_psi) {
-    case 8: hipLaunchKernelGGL((k_coarse_psi_wave<BC, T, 8>), dim3(1), dim3(kWave), 0, c->s, g, cf, r, x, flag); break;
-    case 27: hipLaunchKernelGGL((k_coarse_psi_wave<BC, T, 27>), dim3(1), dim3(kWave), 0, c->s, g, cf, r, x, flag); break;
-    default: hipLaunchKernelGGL((k_coarse_psi_wave<BC, T, 64>), dim3(1), dim3(kWave), 0, c->s, g, cf, r, x, flag); break;
+    case 8: hipLaunchKernelGGL((k_coarse_psi_block<BC, T, 8>), dim3(1), dim3(kGjWaves * kWave), 0, c->s, g, cf, r, x, flag); break;
+    case 27: hipLaunchKernelGGL((k_coarse_psi_block<BC, T, 27>), dim3(1), dim3(kGjWaves * kWave), 0, c->s, g, cf, r, x, flag); break;
+    default: hipLaunchKernelGGL((k_coarse_psi_block<BC, T, 64>), dim3(1), dim3(kGjWaves * kWave), 0, c->s, g, cf, r, x, flag); break;
     }
 }
 
@@ -401,7 +401,7 @@ void prolong_add(mg_ctx *c, int lc, const T *coarse, T *fine, int ncomp)
 }
 
 // After the residual wrote the finest c: restrict c level by level and, when
-// the coarsest system is too large for the one-wave solver, assemble and
+// the coarsest system is too large for the register-resident solver, assemble and
 // invert it.  All on the context's stream: the V-cycle kernels that follow
 // stay on one queue of the graph.
 template <typename T>

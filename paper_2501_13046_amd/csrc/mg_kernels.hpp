@@ -704,96 +704,114 @@ __global__ void __launch_bounds__(kBlock) k_restrict(int nf, const T *__restrict
 }
 
 // ---------------------------------------------------------------------------------------
-// Coarsest psi solve in one wavefront, for m = M unknowns (M <= 64, a compile-
-// time constant so the pivot steps unroll with static register indexing).
-// Lane i holds row i of [A | r] in registers.  Pivot: the largest |a_ik| over
-// unused rows, found with one wave max of a packed key (float bits of |a_ik|,
-// low 6 bits replaced by 63 - lane so ties go to the lowest row); the pivot
-// lane writes its row to LDS and every lane reads it back (one wave, so the
-// barriers only order the LDS traffic).  *flag = 1 if no non-zero pivot exists.
+// Coarsest psi solve (m = M unknowns, M <= 64, a compile-time constant so the
+// pivot steps unroll with static register indexing): Gauss-Jordan with
+// partial pivoting on [A | r], A assembled from the level's stencil and c.
+// Pivot: the largest |a_ik| over unused rows, found with one wave max of a
+// packed key (float bits of |a_ik|, low 6 bits replaced by 63 - row so ties go
+// to the lowest row).  *flag = 1 if no non-zero pivot exists.
+// The solve is spread over a block of 16 waves: lanes hold rows, the columns
+// of [A | r] are dealt round-robin to the waves (wave w holds columns w,
+// w + 16, ...).  At step k the wave owning column k picks the pivot and
+// publishes the pivot row index, its reciprocal and the row factors
+// a_ik / a_pk in LDS (double-buffered: one barrier per step); every wave then
+// updates its own columns, reading the pivot row's values from lane p of its
+// own registers.
 // ---------------------------------------------------------------------------------------
+constexpr int kGjWaves = 16;
 
 template <int BC, typename T, int M>
-__global__ void __launch_bounds__(kWave) k_coarse_psi_wave(Geo g, const T *c, const T *r, T *x, double *flag)
+__global__ void __launch_bounds__(kGjWaves * kWave) k_coarse_psi_block(Geo g, const T *c, const T *r, T *x,
+                                                                      double *flag)
 {
     constexpr int NC = M + 1;
+    constexpr int S = (NC + kGjWaves - 1) / kGjWaves;
     __shared__ double A[M][NC + 1];
+    __shared__ double fac[2][kWave];
+    __shared__ double pinv[2];
+    __shared__ int piv[2];
     __shared__ int perm[M];
-    const int lane = threadIdx.x;
+    __shared__ int bad;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const int n = g.n;
-    if (lane < M) {
-        for (int j = 0; j < NC; j++) A[lane][j] = 0.0;
-        const int k = lane % n, j = (lane / n) % n, i = lane / (n * n);
+    if (threadIdx.x < M) {
+        const int row = threadIdx.x;
+        for (int j = 0; j < NC; j++) A[row][j] = 0.0;
+        const int k = row % n, j = (row / n) % n, i = row / (n * n);
         const double wt[5] = {-1.0, 16.0, -30.0, 16.0, -1.0};
         for (int ax = 0; ax < 3; ax++)
             for (int d = -2; d <= 2; d++) {
                 int ii = i + (ax == 0 ? d : 0), jj = j + (ax == 1 ? d : 0), kk = k + (ax == 2 ? d : 0);
-                double fac = 1.0;
+                double fac_bc = 1.0;
                 if (BC == kBcPeriodic) {
                     ii = wrap(ii, n);
                     jj = wrap(jj, n);
                     kk = wrap(kk, n);
-                } else if (!((unsigned)ii < (unsigned)n && (unsigned)jj < (unsigned)n &&
-                             (unsigned)kk < (unsigned)n)) {
+                } else if (!((unsigned)ii < (unsigned)n && (unsigned)jj < (unsigned)n && (unsigned)kk < (unsigned)n)) {
                     int bi = clampc(ii, n), bj = clampc(jj, n), bk = clampc(kk, n);
-                    fac = cell_radius(g, bi, bj, bk) / cell_radius(g, ii, jj, kk);
+                    fac_bc = cell_radius(g, bi, bj, bk) / cell_radius(g, ii, jj, kk);
                     ii = bi;
                     jj = bj;
                     kk = bk;
                 }
-                A[lane][(ii * n + jj) * n + kk] += wt[d + 2] * g.inv12h2 * fac;
+                A[row][(ii * n + jj) * n + kk] += wt[d + 2] * g.inv12h2 * fac_bc;
             }
-        A[lane][lane] += (double)c[lane];
-        A[lane][M] = (double)r[lane];
+        A[row][row] += (double)c[row];
+        A[row][M] = (double)r[row];
     }
+    if (threadIdx.x == 0) bad = 0;
     __syncthreads();
-    double v[NC];
+    double v[S];
 #pragma unroll
-    for (int j = 0; j < NC; j++) v[j] = lane < M ? A[lane][j] : 0.0;
-    // pivot row broadcast through LDS: the pivot lane writes its row, every
-    // lane reads it (a register broadcast per value would serialise)
-    __shared__ double prow[NC];
+    for (int q = 0; q < S; q++) {
+        const int col = wave + kGjWaves * q;
+        v[q] = (lane < M && col < NC) ? A[lane][col] : 0.0;
+    }
     uint64_t used = 0;
-    bool bad = false;
 #pragma unroll
     for (int k = 0; k < M; k++) {
-        const double a = v[k];
-        unsigned key = 0u;
-        if (lane < M && !((used >> lane) & 1ull)) {
-            const unsigned bits = __float_as_uint((float)fabs(a));
-            key = (bits & ~63u) | (63u - (unsigned)lane);
+        const int buf = k & 1;
+        if (wave == k % kGjWaves) {
+            const double a = v[k / kGjWaves];
+            unsigned key = 0u;
+            if (lane < M && !((used >> lane) & 1ull)) {
+                const unsigned bits = __float_as_uint((float)fabs(a));
+                key = (bits & ~63u) | (63u - (unsigned)lane);
+            }
+            const unsigned kmax = __reduce_max_sync(~0ull, key);
+            if ((kmax >> 6) == 0u) {
+                if (lane == 0) bad = 1;
+            } else {
+                const int p = 63 - (int)(kmax & 63u);
+                const double inv = 1.0 / __shfl(a, p, kWave);
+                fac[buf][lane] = a * inv;
+                if (lane == 0) {
+                    piv[buf] = p;
+                    pinv[buf] = inv;
+                    perm[k] = p;
+                }
+            }
         }
-        const unsigned kmax = __reduce_max_sync(~0ull, key);
-        if ((kmax >> 6) == 0u) {
-            bad = true;
-            break;
-        }
-        const int p = 63 - (int)(kmax & 63u);
+        __syncthreads();
+        if (bad) break;
+        const int p = piv[buf];
+        const double inv = pinv[buf], f = fac[buf][lane];
         used |= 1ull << p;
-        if (lane == 0) perm[k] = p;
-        if (lane == p) {
 #pragma unroll
-            for (int j = k; j < NC; j++) prow[j] = v[j];
+        for (int q = 0; q < S; q++) {
+            const int col = wave + kGjWaves * q;
+            const double pj = __shfl(v[q], p, kWave);
+            if (col > k && col < NC) v[q] = (lane == p) ? v[q] * inv : v[q] - f * pj;
         }
-        __syncthreads();
-        const double inv = 1.0 / prow[k];
-        const double f = a * inv;
-#pragma unroll
-        for (int j = k + 1; j < NC; j++) {
-            const double pj = prow[j];
-            v[j] = (lane == p) ? v[j] * inv : v[j] - f * pj;
-        }
-        __syncthreads();
     }
     if (bad) {
-        if (lane == 0) *flag = 1.0;
+        if (threadIdx.x == 0) *flag = 1.0;
         return;
     }
-    // the scaled row perm[q] now carries x_q in its last column
+    // the scaled row perm[q] carries x_q in the last column (held by one wave)
+    if (wave == M % kGjWaves && lane < M) A[lane][M] = v[M / kGjWaves];
     __syncthreads();
-    if (lane < M) A[lane][M] = v[M];
-    __syncthreads();
-    if (lane < M) x[lane] = (T)A[perm[lane]][M];
+    if (threadIdx.x < M) x[threadIdx.x] = (T)A[perm[threadIdx.x]][M];
 }
 
 // ---------------------------------------------------------------------------------------
