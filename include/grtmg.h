@@ -222,8 +222,15 @@ mg_status mg_fmg_start(mg_ctx *cc, mg_ctx *cf, double *d_uc, double *d_Wc, doubl
  * stream.  mg_set_tile applies a stored choice (a candidate of the family;
  * MG_ERR_INVALID otherwise).  Candidates: psi pass {2, 4, 8}; W pass {1, 2, 4}
  * (FP32) or {1, 2} (FP64); residual {1, 2, 4}.
+ * Two further families choose how the coarse levels of each V-cycle run: as
+ * separate grid launches (0, the default) or as one workgroup-resident "tail"
+ * kernel per V-cycle (1) that runs every level from the first of at most 16^3
+ * (psi) / 8^3 (W) cells down to the coarsest and back, phase by phase with
+ * block barriers (same per-cell arithmetic; the restriction sums group the 8
+ * children differently, so results agree to rounding).  Their `level` is the
+ * tail's first level; mg_autotune times one whole V-cycle each way.
  */
-enum { MG_TUNE_PASS_PSI = 1, MG_TUNE_PASS_W = 2, MG_TUNE_RESIDUAL = 3 };
+enum { MG_TUNE_PASS_PSI = 1, MG_TUNE_PASS_W = 2, MG_TUNE_RESIDUAL = 3, MG_TUNE_TAIL_PSI = 4, MG_TUNE_TAIL_W = 5 };
 typedef struct mg_tune {
     int32_t family, level, chosen, ncand;
     int32_t cand[4];

@@ -68,6 +68,7 @@ constexpr int kCandPsi[] = {2, 4, 8};
 constexpr int kCandW32[] = {1, 2, 4};
 constexpr int kCandW64[] = {1, 2};
 constexpr int kCandR[] = {1, 2, 4};
+constexpr int kCandTail[] = {0, 1}; // V-cycle tail off / on
 
 } // namespace
 
@@ -86,6 +87,8 @@ struct mg_ctx {
     TileMap tile[kMaxLevels];  // brick map of the psi smoother per level (tx == 0: not tiled)
     TileMap tileW[kMaxLevels]; // brick map of the W smoother per level
     TileMap tileR;             // brick map of the finest-level residual
+    int tail_psi, tail_W;      // first level of the workgroup-resident V-cycle tail (-1: not possible)
+    bool tail_psi_on, tail_W_on; // tail in use (chosen by mg_autotune / mg_set_tile; off by default)
     void *pd0[kMaxLevels], *pd1[kMaxLevels], *pr[kMaxLevels], *pc[kMaxLevels];
     void *wd0[kMaxLevels], *wd1[kMaxLevels], *wr[kMaxLevels];
     double *part;
@@ -183,6 +186,9 @@ void carve(mg_ctx *c, Carver &cv)
     }
 }
 
+// Coarsest sizes solved by the register-resident Gauss-Jordan kernel (one block).
+bool wave_solvable(int m) { return m == 8 || m == 27 || m == 64; }
+
 TileMap tilemap_rt(int n, int tx)
 {
     switch (tx) {
@@ -212,6 +218,23 @@ void init_geo(mg_ctx *c)
         c->tileW[l] = make_tilemap<kBrickW>(c->n[l]);
     }
     c->tileR = make_rtilemap<kBrickR>(c->n[0]);
+    // V-cycle tails: psi from the first level of at most 16^3 cells (13-point
+    // stencil: cheap in one workgroup), W from at most 8^3 (the Lame stencil of a
+    // 16^3 pass is faster spread over a grid); at least one level above the
+    // coarsest, at most kMaxTail levels, coarsest psi system solvable in registers.
+    c->tail_psi = c->tail_W = -1;
+    c->tail_psi_on = c->tail_W_on = false;
+    for (int l = 0; l + 1 < c->L; l++)
+        if (c->n[l] <= 16 && c->L - l <= kMaxTail && wave_solvable(c->m_psi)) {
+            c->tail_psi = l;
+            break;
+        }
+    if (c->momentum)
+        for (int l = 0; l + 1 < c->L; l++)
+            if (c->n[l] <= 8 && c->L - l <= kMaxTail && c->m_W <= 1536) {
+                c->tail_W = l;
+                break;
+            }
 }
 
 unsigned ntiles(const TileMap &t) { return (unsigned)(t.nx * t.ny * t.nz); }
@@ -254,8 +277,6 @@ void factor(hipStream_t s, double *A, double *aug, double *inv, int m, double *f
                        m, flag);
 }
 
-// Coarsest sizes solved by the register-resident Gauss-Jordan kernel (one block).
-bool wave_solvable(int m) { return m == 8 || m == 27 || m == 64; }
 
 template <int BC, typename T>
 void launch_coarse_wave(mg_ctx *c, int l, const T *r, T *x)
@@ -407,7 +428,8 @@ void prolong_add(mg_ctx *c, int lc, const T *coarse, T *fine, int ncomp)
 template <typename T>
 void restrict_coefficients(mg_ctx *c)
 {
-    for (int l = 0; l + 1 < c->L; l++)
+    const int stop = c->tail_psi_on ? c->tail_psi : c->L - 1; // the tail restricts below its first level
+    for (int l = 0; l < stop; l++)
         hipLaunchKernelGGL(k_restrict<T>, dim3(nblk(c->cells[l + 1])), dim3(kBlock), 0, c->s, c->n[l],
                            (const T *)c->pc[l], (T *)c->pc[l + 1]);
     const int l = c->L - 1;
@@ -423,11 +445,57 @@ void restrict_coefficients(mg_ctx *c)
     factor(c->s, c->A_psi, c->aug_psi, c->inv_psi, m, c->scal + S_FLAG_PSI);
 }
 
+template <typename T>
+TailArgs<T> tail_args(mg_ctx *c, int l0, bool W)
+{
+    TailArgs<T> a;
+    std::memset(&a, 0, sizeof(a));
+    a.nl = c->L - l0;
+    a.nu_pre = c->p.nu_pre;
+    a.nu_post = c->p.nu_post;
+    for (int q = 0; q < a.nl; q++) {
+        const int l = l0 + q;
+        a.geo[q] = c->geo[l];
+        a.d0[q] = (T *)(W ? c->wd0[l] : c->pd0[l]);
+        a.d1[q] = (T *)(W ? c->wd1[l] : c->pd1[l]);
+        a.r[q] = (T *)(W ? c->wr[l] : c->pr[l]);
+        a.c[q] = W ? nullptr : (T *)c->pc[l];
+    }
+    a.inv = c->inv_W;
+    a.flag = c->scal + S_FLAG_PSI;
+    return a;
+}
+
+template <typename T>
+void tail_psi(mg_ctx *c)
+{
+    Probe pr(c, MG_PROBE_COARSE, c->L - 1);
+    const TailArgs<T> a = tail_args<T>(c, c->tail_psi, false);
+    const dim3 g1(1), blk(kTailThreads);
+    if (c->p.bc == MG_BC_PERIODIC) {
+        switch (c->m_psi) {
+        case 8: hipLaunchKernelGGL((k_tail_psi<kBcPeriodic, T, 8>), g1, blk, 0, c->s, a); break;
+        case 27: hipLaunchKernelGGL((k_tail_psi<kBcPeriodic, T, 27>), g1, blk, 0, c->s, a); break;
+        default: hipLaunchKernelGGL((k_tail_psi<kBcPeriodic, T, 64>), g1, blk, 0, c->s, a); break;
+        }
+    } else {
+        switch (c->m_psi) {
+        case 8: hipLaunchKernelGGL((k_tail_psi<kBcRobin, T, 8>), g1, blk, 0, c->s, a); break;
+        case 27: hipLaunchKernelGGL((k_tail_psi<kBcRobin, T, 27>), g1, blk, 0, c->s, a); break;
+        default: hipLaunchKernelGGL((k_tail_psi<kBcRobin, T, 64>), g1, blk, 0, c->s, a); break;
+        }
+    }
+}
+
 // psi V-cycle on level l; the coefficients of levels > 0 and the coarsest
-// inverse come from restrict_coefficients.
+// inverse come from restrict_coefficients (and the tail kernel below its first level).
 template <typename T>
 void vcycle_psi(mg_ctx *c, int l)
 {
+    if (c->tail_psi_on && l == c->tail_psi) {
+        tail_psi<T>(c);
+        return;
+    }
     if (l == c->L - 1) {
         const int m = c->m_psi;
         if (wave_solvable(m)) {
@@ -488,6 +556,11 @@ void smooth_W(mg_ctx *c, int l, int sweeps)
 template <typename T>
 void vcycle_W(mg_ctx *c, int l)
 {
+    if (c->tail_W_on && l == c->tail_W) {
+        Probe pr(c, MG_PROBE_COARSE, c->L - 1);
+        hipLaunchKernelGGL(k_tail_W<T>, dim3(1), dim3(kTailThreads), 0, c->s, tail_args<T>(c, l, true));
+        return;
+    }
     if (l == c->L - 1) {
         coarse_W<T>(c, (const T *)c->wr[l], (T *)c->wd0[l]);
         return;
@@ -895,6 +968,8 @@ const int *tune_candidates(const mg_ctx *c, int family, int &count)
         count = 2;
         return kCandW64;
     case MG_TUNE_RESIDUAL: count = 3; return kCandR;
+    case MG_TUNE_TAIL_PSI:
+    case MG_TUNE_TAIL_W: count = 2; return kCandTail;
     default: count = 0; return nullptr;
     }
 }
@@ -945,6 +1020,49 @@ mg_status autotune(mg_ctx *c, const double *u, const double *W, int reps, mg_tun
     }
     mg_status st = MG_OK;
     int k = 0;
+    // V-cycle tails: one whole V-cycle (with the coefficient restriction it needs)
+    // timed with the tail off and on
+    for (int family = MG_TUNE_TAIL_PSI; family <= MG_TUNE_TAIL_W && st == MG_OK; family++) {
+        const int start = family == MG_TUNE_TAIL_PSI ? c->tail_psi : c->tail_W;
+        if (start < 0) continue;
+        bool &on = family == MG_TUNE_TAIL_PSI ? c->tail_psi_on : c->tail_W_on;
+        mg_tune e;
+        std::memset(&e, 0, sizeof(e));
+        e.family = family;
+        e.level = start;
+        e.ncand = 2;
+        double best = 1e300;
+        bool best_on = on;
+        for (int q = 0; q < 2 && st == MG_OK; q++) {
+            e.cand[q] = kCandTail[q];
+            on = kCandTail[q] != 0;
+            auto cycle = [&]() {
+                if (family == MG_TUNE_TAIL_PSI) {
+                    restrict_coefficients<T>(c);
+                    vcycle_psi<T>(c, 0);
+                } else {
+                    vcycle_W<T>(c, 0);
+                }
+            };
+            cycle();
+            float ms = 0.0f;
+            if (hipEventRecord(e0, c->s) != hipSuccess) st = MG_ERR_HIP;
+            for (int r = 0; r < reps && st == MG_OK; r++) cycle();
+            if (st == MG_OK && (hipEventRecord(e1, c->s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                st = MG_ERR_HIP;
+            if (st != MG_OK) break;
+            e.us[q] = 1e3 * ms / reps;
+            if (e.us[q] < best) {
+                best = e.us[q];
+                best_on = on;
+                e.chosen = kCandTail[q];
+            }
+        }
+        on = best_on;
+        if (out && k < cap) out[k] = e;
+        k++;
+    }
     for (int family = MG_TUNE_PASS_PSI; family <= MG_TUNE_RESIDUAL && st == MG_OK; family++) {
         int nc = 0;
         const int *cand = tune_candidates(c, family, nc);
@@ -1694,6 +1812,13 @@ mg_status mg_autotune(mg_ctx *c, const double *d_u, const double *d_W, int32_t r
 mg_status mg_set_tile(mg_ctx *c, int32_t family, int32_t level, int32_t tx)
 {
     if (!c || level < 0 || level >= c->L) return MG_ERR_INVALID;
+    if (family == MG_TUNE_TAIL_PSI || family == MG_TUNE_TAIL_W) {
+        const int start = family == MG_TUNE_TAIL_PSI ? c->tail_psi : c->tail_W;
+        if (start < 0 || level != start || (tx != 0 && tx != 1)) return MG_ERR_INVALID;
+        (family == MG_TUNE_TAIL_PSI ? c->tail_psi_on : c->tail_W_on) = tx != 0;
+        drop_graph(c);
+        return MG_OK;
+    }
     int nc = 0;
     const int *cand = tune_candidates(c, family, nc);
     bool ok = false;

@@ -220,6 +220,26 @@ __global__ void __launch_bounds__(kBlock) k_reduce_final(const double *partials,
 // of the active colour ((i+j+k) mod 2) get d + (r - A d)/diag(A); the others
 // are copied.  Every read is from `in` (the state before the pass).
 // ---------------------------------------------------------------------------------------
+// One colour pass of the psi smoother at cell q = (i, j, k) (double-buffered:
+// reads in, writes out; the other colour is copied).
+template <int BC, typename T>
+__device__ __forceinline__ void psi_pass_cell(const Geo &g, const T *__restrict__ in, T *__restrict__ out,
+                                              const T *__restrict__ r, const T *__restrict__ c, int colour,
+                                              int64_t q, int i, int j, int k)
+{
+    const T x = in[q];
+    if (((i + j + k) & 1) != colour) {
+        out[q] = x;
+        return;
+    }
+    Acc<BC, T> D{in, g};
+    const T cv = c[q];
+    const T h2 = (T)g.inv12h2;
+    const T Ad = lap_sum<T>(D, i, j, k, x) * h2 + cv * x;
+    const T diag = (T)(lap_diag_sum<BC>(g, i, j, k) * g.inv12h2) + cv;
+    out[q] = x + (r[q] - Ad) / diag;
+}
+
 template <int BC, typename T>
 __global__ void __launch_bounds__(kBlock) k_pass_psi(Geo g, const T *__restrict__ in,
                                                      T *__restrict__ out, const T *__restrict__ r,
@@ -228,17 +248,7 @@ __global__ void __launch_bounds__(kBlock) k_pass_psi(Geo g, const T *__restrict_
     const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     int i, j, k;
     if (!cell_of(tid, g.n, i, j, k)) return;
-    const T x = in[tid];
-    if (((i + j + k) & 1) != colour) {
-        out[tid] = x;
-        return;
-    }
-    Acc<BC, T> D{in, g};
-    const T cv = c[tid];
-    const T h2 = (T)g.inv12h2;
-    const T Ad = lap_sum<T>(D, i, j, k, x) * h2 + cv * x;
-    const T diag = (T)(lap_diag_sum<BC>(g, i, j, k) * g.inv12h2) + cv;
-    out[tid] = x + (r[tid] - Ad) / diag;
+    psi_pass_cell<BC, T>(g, in, out, r, c, colour, tid, i, j, k);
 }
 
 // (Delta_L d)_a at a cell for the three components (periodic).
@@ -263,28 +273,37 @@ __device__ __forceinline__ void deltaL_apply(const Geo &g, const T *d, int64_t m
     out[2] = l2 + t2 * third;
 }
 
+// One colour pass of the W smoother at cell q (periodic, double-buffered).
+template <typename T>
+__device__ __forceinline__ void W_pass_cell(const Geo &g, const T *__restrict__ in, T *__restrict__ out,
+                                            const T *__restrict__ r, int colour, int64_t q,
+                                            int i, int j, int k)
+{
+    const int n = g.n;
+    const int64_t m = (int64_t)n * n * n;
+    if (((i + j + k) & 1) != colour) {
+        out[q] = in[q];
+        out[m + q] = in[m + q];
+        out[2 * m + q] = in[2 * m + q];
+        return;
+    }
+    T Ad[3];
+    deltaL_apply<T>(g, in, m, i, j, k, q, Ad);
+    // diagonal of Delta_L,h: (-90 - 30/3) / (12 h^2) = -25 / (3 h^2)
+    const T diag = (T)(-100.0 * g.inv12h2);
+#pragma unroll
+    for (int s = 0; s < 3; s++) out[s * m + q] = in[s * m + q] + (r[s * m + q] - Ad[s]) / diag;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_pass_W(Geo g, const T *__restrict__ in,
                                                    T *__restrict__ out, const T *__restrict__ r,
                                                    int colour)
 {
     const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int n = g.n;
-    const int64_t m = (int64_t)n * n * n;
     int i, j, k;
-    if (!cell_of(tid, n, i, j, k)) return;
-    if (((i + j + k) & 1) != colour) {
-        out[tid] = in[tid];
-        out[m + tid] = in[m + tid];
-        out[2 * m + tid] = in[2 * m + tid];
-        return;
-    }
-    T Ad[3];
-    deltaL_apply<T>(g, in, m, i, j, k, tid, Ad);
-    // diagonal of Delta_L,h: (-90 - 30/3) / (12 h^2) = -25 / (3 h^2)
-    const T diag = (T)(-100.0 * g.inv12h2);
-#pragma unroll
-    for (int s = 0; s < 3; s++) out[s * m + tid] = in[s * m + tid] + (r[s * m + tid] - Ad[s]) / diag;
+    if (!cell_of(tid, g.n, i, j, k)) return;
+    W_pass_cell<T>(g, in, out, r, colour, tid, i, j, k);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -322,16 +341,10 @@ __device__ __forceinline__ bool child_of(int64_t tid, int nc, int64_t &qc, int &
 // loads in registers: large grids), or one thread per fine cell with a lane
 // group per coarse cell (8x the parallelism: small, latency-bound grids).
 template <int BC, typename T>
-__global__ void __launch_bounds__(kBlock) k_defect_restrict_psi(Geo g, const T *__restrict__ d,
-                                                                const T *__restrict__ r,
-                                                                const T *__restrict__ c,
-                                                                T *__restrict__ rc_out,
-                                                                T *__restrict__ cc_out)
+__device__ __forceinline__ void defect_restrict_psi_coarse(const Geo &g, const T *__restrict__ d, const T *__restrict__ r,
+                                                           const T *__restrict__ c, T *__restrict__ rc_out,
+                                                           T *__restrict__ cc_out, int64_t qc, int I, int J, int K)
 {
-    const int nc = g.n / 2;
-    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    int I, J, K;
-    if (!cell_of(tid, nc, I, J, K)) return;
     Acc<BC, T> D{d, g};
     const T h2 = (T)g.inv12h2;
     T sd = T(0), sc = T(0);
@@ -347,8 +360,48 @@ __global__ void __launch_bounds__(kBlock) k_defect_restrict_psi(Geo g, const T *
                 sd += r[q] - (lap_sum<T>(D, i, j, k, x) * h2 + cv * x);
                 sc += cv;
             }
-    rc_out[tid] = sd * T(0.125);
-    if (cc_out) cc_out[tid] = sc * T(0.125);
+    rc_out[qc] = sd * T(0.125);
+    if (cc_out) cc_out[qc] = sc * T(0.125);
+}
+
+template <int BC, typename T>
+__global__ void __launch_bounds__(kBlock) k_defect_restrict_psi(Geo g, const T *__restrict__ d,
+                                                                const T *__restrict__ r,
+                                                                const T *__restrict__ c,
+                                                                T *__restrict__ rc_out,
+                                                                T *__restrict__ cc_out)
+{
+    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int I, J, K;
+    if (!cell_of(tid, g.n / 2, I, J, K)) return;
+    defect_restrict_psi_coarse<BC, T>(g, d, r, c, rc_out, cc_out, tid, I, J, K);
+}
+
+// Fine-cell form: fine cell tid of the grid of 8 nc^3 threads (child_of), group
+// sums in a fixed order; lane 8 qc writes coarse cell qc.
+template <int BC, typename T>
+__device__ __forceinline__ void defect_restrict_psi_child(const Geo &g, const T *__restrict__ d, const T *__restrict__ r,
+                                                          const T *__restrict__ c, T *__restrict__ rc_out,
+                                                          T *__restrict__ cc_out, int64_t tid)
+{
+    int64_t qc;
+    int i, j, k;
+    const bool live = child_of(tid, g.n / 2, qc, i, j, k);
+    T sd = T(0), cv = T(0);
+    if (live) {
+        Acc<BC, T> D{d, g};
+        const T h2 = (T)g.inv12h2;
+        const int64_t q = lidx(g.n, i, j, k);
+        const T x = d[q];
+        cv = c[q];
+        sd = r[q] - (lap_sum<T>(D, i, j, k, x) * h2 + cv * x);
+    }
+    sd = child_sum(sd);
+    const T sc = child_sum(cv);
+    if (live && (tid & 7) == 0) {
+        rc_out[qc] = sd * T(0.125);
+        if (cc_out) cc_out[qc] = sc * T(0.125);
+    }
 }
 
 template <int BC, typename T>
@@ -358,23 +411,38 @@ __global__ void __launch_bounds__(kBlock) k_defect_restrict_psi_fine(Geo g, cons
                                                                      T *__restrict__ rc_out,
                                                                      T *__restrict__ cc_out)
 {
-    const int nc = g.n / 2;
-    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    int64_t qc;
-    int i, j, k;
-    if (!child_of(tid, nc, qc, i, j, k)) return; // whole groups of 8 leave together
-    Acc<BC, T> D{d, g};
-    const T h2 = (T)g.inv12h2;
-    const int64_t q = lidx(g.n, i, j, k);
-    const T x = d[q], cv = c[q];
-    const T sd = child_sum(r[q] - (lap_sum<T>(D, i, j, k, x) * h2 + cv * x));
-    const T sc = child_sum(cv);
-    if ((tid & 7) == 0) {
-        rc_out[qc] = sd * T(0.125);
-        if (cc_out) cc_out[qc] = sc * T(0.125);
-    }
+    defect_restrict_psi_child<BC, T>(g, d, r, c, rc_out, cc_out, (int64_t)blockIdx.x * kBlock + threadIdx.x);
 }
 
+template <typename T>
+__device__ __forceinline__ void defect_restrict_W_coarse(const Geo &g, const T *__restrict__ d, const T *__restrict__ r,
+                                                         T *__restrict__ rc_out,
+                                                         int64_t qc, int I, int J, int K)
+{
+    const int nc = g.n / 2;
+    const int64_t mf = (int64_t)g.n * g.n * g.n, mc = (int64_t)nc * nc * nc;
+    T s[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int di = 0; di < 2; di++)
+#pragma unroll
+        for (int dj = 0; dj < 2; dj++)
+#pragma unroll
+            for (int dk = 0; dk < 2; dk++) {
+                const int i = 2 * I + di, j = 2 * J + dj, k = 2 * K + dk;
+                const int64_t q = lidx(g.n, i, j, k);
+                T Ad[3];
+                deltaL_apply<T>(g, d, mf, i, j, k, q, Ad);
+#pragma unroll
+                for (int a = 0; a < 3; a++) s[a] += r[a * mf + q] - Ad[a];
+            }
+#pragma unroll
+    for (int a = 0; a < 3; a++) rc_out[a * mc + qc] = s[a] * T(0.125);
+}
+
+// Grid kernel with the body written out (not through defect_restrict_W_coarse):
+// at the 256-register limit the inlined form is scheduled with far fewer
+// loads in flight (mean outstanding loads per wait 4 instead of 21; 1.45x the
+// time at 128^3).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_defect_restrict_W(Geo g, const T *__restrict__ d,
                                                               const T *__restrict__ r,
@@ -404,26 +472,36 @@ __global__ void __launch_bounds__(kBlock) k_defect_restrict_W(Geo g, const T *__
 }
 
 template <typename T>
+__device__ __forceinline__ void defect_restrict_W_child(const Geo &g, const T *__restrict__ d, const T *__restrict__ r,
+                                                        T *__restrict__ rc_out, int64_t tid)
+{
+    const int nc = g.n / 2;
+    const int64_t mf = (int64_t)g.n * g.n * g.n, mc = (int64_t)nc * nc * nc;
+    int64_t qc;
+    int i, j, k;
+    const bool live = child_of(tid, nc, qc, i, j, k);
+    T s[3] = {T(0), T(0), T(0)};
+    if (live) {
+        const int64_t q = lidx(g.n, i, j, k);
+        T Ad[3];
+        deltaL_apply<T>(g, d, mf, i, j, k, q, Ad);
+#pragma unroll
+        for (int a = 0; a < 3; a++) s[a] = r[a * mf + q] - Ad[a];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; a++) s[a] = child_sum(s[a]);
+    if (live && (tid & 7) == 0) {
+#pragma unroll
+        for (int a = 0; a < 3; a++) rc_out[a * mc + qc] = s[a] * T(0.125);
+    }
+}
+
+template <typename T>
 __global__ void __launch_bounds__(kBlock) k_defect_restrict_W_fine(Geo g, const T *__restrict__ d,
                                                                    const T *__restrict__ r,
                                                                    T *__restrict__ rc_out)
 {
-    const int nc = g.n / 2;
-    const int64_t mf = (int64_t)g.n * g.n * g.n, mc = (int64_t)nc * nc * nc;
-    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    int64_t qc;
-    int i, j, k;
-    if (!child_of(tid, nc, qc, i, j, k)) return;
-    const int64_t q = lidx(g.n, i, j, k);
-    T Ad[3];
-    deltaL_apply<T>(g, d, mf, i, j, k, q, Ad);
-    T s[3];
-#pragma unroll
-    for (int a = 0; a < 3; a++) s[a] = child_sum(r[a * mf + q] - Ad[a]);
-    if ((tid & 7) == 0) {
-#pragma unroll
-        for (int a = 0; a < 3; a++) rc_out[a * mc + qc] = s[a] * T(0.125);
-    }
+    defect_restrict_W_child<T>(g, d, r, rc_out, (int64_t)blockIdx.x * kBlock + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -431,14 +509,12 @@ __global__ void __launch_bounds__(kBlock) k_defect_restrict_W_fine(Geo g, const 
 // axis toward the nearer coarse neighbour), ncomp components.  gc: coarse grid.
 // ---------------------------------------------------------------------------------------
 template <int BC, typename T>
-__global__ void __launch_bounds__(kBlock) k_prolong_add(Geo gc, const T *__restrict__ coarse,
-                                                        T *__restrict__ fine, int ncomp)
+__device__ __forceinline__ void prolong_cell(const Geo &gc, const T *__restrict__ coarse, T *__restrict__ fine, int ncomp,
+                                             int64_t q, int i,
+                                             int j, int k)
 {
     const int nf = 2 * gc.n;
     const int64_t mf = (int64_t)nf * nf * nf, mc = (int64_t)gc.n * gc.n * gc.n;
-    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    int i, j, k;
-    if (!cell_of(tid, nf, i, j, k)) return;
     const int I = i >> 1, J = j >> 1, K = k >> 1;
     const int I1 = (i & 1) ? I + 1 : I - 1;
     const int J1 = (j & 1) ? J + 1 : J - 1;
@@ -448,8 +524,18 @@ __global__ void __launch_bounds__(kBlock) k_prolong_add(Geo gc, const T *__restr
         Acc<BC, T> C{coarse + s * mc, gc};
         const T v = a * (a * (a * C(I, J, K) + b * C(I, J, K1)) + b * (a * C(I, J1, K) + b * C(I, J1, K1))) +
                     b * (a * (a * C(I1, J, K) + b * C(I1, J, K1)) + b * (a * C(I1, J1, K) + b * C(I1, J1, K1)));
-        fine[s * mf + tid] += v;
+        fine[s * mf + q] += v;
     }
+}
+
+template <int BC, typename T>
+__global__ void __launch_bounds__(kBlock) k_prolong_add(Geo gc, const T *__restrict__ coarse,
+                                                        T *__restrict__ fine, int ncomp)
+{
+    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int i, j, k;
+    if (!cell_of(tid, 2 * gc.n, i, j, k)) return;
+    prolong_cell<BC, T>(gc, coarse, fine, ncomp, tid, i, j, k);
 }
 
 // Four-point cubic interpolation (FP64), fine = Q coarse.
@@ -720,9 +806,9 @@ __global__ void __launch_bounds__(kBlock) k_restrict(int nf, const T *__restrict
 // ---------------------------------------------------------------------------------------
 constexpr int kGjWaves = 16;
 
+// Called by every thread of a block of kGjWaves waves.
 template <int BC, typename T, int M>
-__global__ void __launch_bounds__(kGjWaves * kWave) k_coarse_psi_block(Geo g, const T *c, const T *r, T *x,
-                                                                      double *flag)
+__device__ __forceinline__ void coarse_psi_block_solve(const Geo &g, const T *c, const T *r, T *x, double *flag)
 {
     constexpr int NC = M + 1;
     constexpr int S = (NC + kGjWaves - 1) / kGjWaves;
@@ -812,6 +898,184 @@ __global__ void __launch_bounds__(kGjWaves * kWave) k_coarse_psi_block(Geo g, co
     if (wave == M % kGjWaves && lane < M) A[lane][M] = v[M / kGjWaves];
     __syncthreads();
     if (threadIdx.x < M) x[threadIdx.x] = (T)A[perm[threadIdx.x]][M];
+}
+
+template <int BC, typename T, int M>
+__global__ void __launch_bounds__(kGjWaves * kWave) k_coarse_psi_block(Geo g, const T *c, const T *r, T *x,
+                                                                      double *flag)
+{
+    coarse_psi_block_solve<BC, T, M>(g, c, r, x, flag);
+}
+
+// ---------------------------------------------------------------------------------------
+// V-cycle tails: the coarse levels of one V-cycle (from level ls down to the
+// coarsest and back) run in one workgroup of kGjWaves waves, phase by phase
+// with block barriers, on data resident in L2 (these levels are too small to
+// fill the GPU: as separate launches every phase would cost a launch).  Each
+// phase calls the same per-cell functions as the grid kernels.
+// ---------------------------------------------------------------------------------------
+constexpr int kTailThreads = kGjWaves * kWave;
+constexpr int kMaxTail = 4;
+
+template <typename T>
+struct TailArgs {
+    int nl;      // levels in the tail (the last one is the coarsest)
+    int nu_pre, nu_post;
+    Geo geo[kMaxTail];
+    T *d0[kMaxTail], *d1[kMaxTail], *r[kMaxTail], *c[kMaxTail];
+    const double *inv; // W: coarsest inverse (column-major m x m), m = 3 cells
+    double *flag;      // psi: set when the coarsest matrix is singular
+};
+
+template <typename T>
+__device__ __forceinline__ void tail_zero(T *a, int64_t count)
+{
+    for (int64_t q = threadIdx.x; q < count; q += kTailThreads) a[q] = T(0);
+}
+
+template <int BC, typename T>
+__device__ __forceinline__ void tail_psi_passes(const TailArgs<T> &a, int l, int sweeps)
+{
+    const Geo &g = a.geo[l];
+    const int n = g.n;
+    const int64_t m = (int64_t)n * n * n;
+    for (int s = 0; s < sweeps; s++)
+        for (int colour = 0; colour < 2; colour++) {
+            const T *in = colour ? a.d1[l] : a.d0[l];
+            T *out = colour ? a.d0[l] : a.d1[l];
+            for (int64_t q = threadIdx.x; q < m; q += kTailThreads) {
+                int i, j, k;
+                cell_of(q, n, i, j, k);
+                psi_pass_cell<BC, T>(g, in, out, a.r[l], a.c[l], colour, q, i, j, k);
+            }
+            __syncthreads();
+        }
+}
+
+// psi tail: restricts c below level 0 of the tail, then the V-cycle from the
+// tail's first level (its residual already restricted into r[0]).
+template <int BC, typename T, int M>
+__global__ void __launch_bounds__(kTailThreads) k_tail_psi(TailArgs<T> a)
+{
+    const int L = a.nl;
+    for (int l = 0; l + 1 < L; l++) {
+        const int nc = a.geo[l + 1].n;
+        const int64_t mc = (int64_t)nc * nc * nc;
+        for (int64_t q = threadIdx.x; q < mc; q += kTailThreads) {
+            int I, J, K;
+            cell_of(q, nc, I, J, K);
+            T s = T(0);
+#pragma unroll
+            for (int di = 0; di < 2; di++)
+#pragma unroll
+                for (int dj = 0; dj < 2; dj++)
+#pragma unroll
+                    for (int dk = 0; dk < 2; dk++) s += a.c[l][lidx(a.geo[l].n, 2 * I + di, 2 * J + dj, 2 * K + dk)];
+            a.c[l + 1][q] = s * T(0.125);
+        }
+        __syncthreads();
+    }
+    for (int l = 0; l + 1 < L; l++) {
+        const Geo &g = a.geo[l];
+        tail_zero(a.d0[l], (int64_t)g.n * g.n * g.n);
+        __syncthreads();
+        tail_psi_passes<BC, T>(a, l, a.nu_pre);
+        const int64_t mf = (int64_t)g.n * g.n * g.n;
+        for (int64_t q = threadIdx.x; q < mf + (kTailThreads - 1); q += kTailThreads) {
+            if (q - threadIdx.x >= mf) break; // the whole block leaves together
+            defect_restrict_psi_child<BC, T>(g, a.d0[l], a.r[l], a.c[l], a.r[l + 1], (T *)nullptr, q);
+        }
+        __syncthreads();
+    }
+    coarse_psi_block_solve<BC, T, M>(a.geo[L - 1], a.c[L - 1], a.r[L - 1], a.d0[L - 1], a.flag);
+    __syncthreads();
+    for (int l = L - 2; l >= 0; l--) {
+        const int nf = a.geo[l].n;
+        const int64_t mf = (int64_t)nf * nf * nf;
+        for (int64_t q = threadIdx.x; q < mf; q += kTailThreads) {
+            int i, j, k;
+            cell_of(q, nf, i, j, k);
+            prolong_cell<BC, T>(a.geo[l + 1], a.d0[l + 1], a.d0[l], 1, q, i, j, k);
+        }
+        __syncthreads();
+        tail_psi_passes<BC, T>(a, l, a.nu_post);
+    }
+}
+
+// W tail (periodic): V-cycle from the tail's first level; the coarsest solve
+// applies the precomputed inverse to the mean-free residual (as k_coarse_apply,
+// one row per thread).
+template <typename T>
+__global__ void __launch_bounds__(kTailThreads) k_tail_W(TailArgs<T> a)
+{
+    __shared__ double rs[1536];
+    __shared__ double mean[3];
+    const int L = a.nl;
+    for (int l = 0; l + 1 < L; l++) {
+        const Geo &g = a.geo[l];
+        const int n = g.n;
+        const int64_t m = (int64_t)n * n * n;
+        tail_zero(a.d0[l], 3 * m);
+        __syncthreads();
+        for (int s = 0; s < a.nu_pre; s++)
+            for (int colour = 0; colour < 2; colour++) {
+                const T *in = colour ? a.d1[l] : a.d0[l];
+                T *out = colour ? a.d0[l] : a.d1[l];
+                for (int64_t q = threadIdx.x; q < m; q += kTailThreads) {
+                    int i, j, k;
+                    cell_of(q, n, i, j, k);
+                    W_pass_cell<T>(g, in, out, a.r[l], colour, q, i, j, k);
+                }
+                __syncthreads();
+            }
+        for (int64_t q = threadIdx.x; q < m + (kTailThreads - 1); q += kTailThreads) {
+            if (q - threadIdx.x >= m) break; // the whole block leaves together
+            defect_restrict_W_child<T>(g, a.d0[l], a.r[l], a.r[l + 1], q);
+        }
+        __syncthreads();
+    }
+    {
+        const int nc = a.geo[L - 1].n;
+        const int cn = nc * nc * nc, m = 3 * cn;
+        for (int q = threadIdx.x; q < m; q += kTailThreads) rs[q] = (double)a.r[L - 1][q];
+        __syncthreads();
+        if (threadIdx.x < 3) {
+            double s = 0.0;
+            for (int q = 0; q < cn; q++) s += rs[threadIdx.x * cn + q];
+            mean[threadIdx.x] = s / (double)cn;
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < m; q += kTailThreads) rs[q] -= mean[q / cn];
+        __syncthreads();
+        for (int row = threadIdx.x; row < m; row += kTailThreads) {
+            double s = 0.0;
+            for (int col = 0; col < m; col++) s += a.inv[(int64_t)col * m + row] * rs[col];
+            a.d0[L - 1][row] = (T)s;
+        }
+        __syncthreads();
+    }
+    for (int l = L - 2; l >= 0; l--) {
+        const Geo &g = a.geo[l];
+        const int nf = g.n;
+        const int64_t mf = (int64_t)nf * nf * nf;
+        for (int64_t q = threadIdx.x; q < mf; q += kTailThreads) {
+            int i, j, k;
+            cell_of(q, nf, i, j, k);
+            prolong_cell<kBcPeriodic, T>(a.geo[l + 1], a.d0[l + 1], a.d0[l], 3, q, i, j, k);
+        }
+        __syncthreads();
+        for (int s = 0; s < a.nu_post; s++)
+            for (int colour = 0; colour < 2; colour++) {
+                const T *in = colour ? a.d1[l] : a.d0[l];
+                T *out = colour ? a.d0[l] : a.d1[l];
+                for (int64_t q = threadIdx.x; q < mf; q += kTailThreads) {
+                    int i, j, k;
+                    cell_of(q, nf, i, j, k);
+                    W_pass_cell<T>(g, in, out, a.r[l], colour, q, i, j, k);
+                }
+                __syncthreads();
+            }
+    }
 }
 
 // ---------------------------------------------------------------------------------------

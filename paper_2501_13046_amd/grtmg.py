@@ -48,7 +48,7 @@ class MgReport(C.Structure):
                 ("history_len", C.c_int32)]
 
 
-TUNE_PASS_PSI, TUNE_PASS_W, TUNE_RESIDUAL = 1, 2, 3
+TUNE_PASS_PSI, TUNE_PASS_W, TUNE_RESIDUAL, TUNE_TAIL_PSI, TUNE_TAIL_W = 1, 2, 3, 4, 5
 
 
 class MgTune(C.Structure):

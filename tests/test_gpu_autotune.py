@@ -37,14 +37,20 @@ def test_every_candidate_gives_the_same_solve(precision, tmp_path):
     entries = s.autotune(torch.zeros((128,) * 3, dtype=torch.float64, device=dev()),
                          torch.zeros((3, 128, 128, 128), dtype=torch.float64, device=dev()), reps=10)
     fams = {e["family"] for e in entries}
-    assert fams == {g.TUNE_PASS_PSI, g.TUNE_PASS_W, g.TUNE_RESIDUAL}
+    assert fams == {g.TUNE_PASS_PSI, g.TUNE_PASS_W, g.TUNE_RESIDUAL, g.TUNE_TAIL_PSI, g.TUNE_TAIL_W}
+    # the tails change the grouping of restriction sums (results agree to rounding, not bitwise):
+    # keep them off while checking that every brick depth gives bitwise the same solve
+    for e in entries:
+        if e["family"] in (g.TUNE_TAIL_PSI, g.TUNE_TAIL_W):
+            s.set_tile(e["family"], e["level"], 0)
+    entries_tiles = [e for e in entries if e["family"] not in (g.TUNE_TAIL_PSI, g.TUNE_TAIL_W)]
     for e in entries:
         print(f"family {e['family']} level {e['level']}: chosen {e['chosen']}, us {e['candidates']}")
         times = {k: v for k, v in e["candidates"].items() if v > 0}
         assert e["chosen"] in times and times[e["chosen"]] == min(times.values())
     u1, W1, it1 = solve(s)
     assert it1 == it0 and np.array_equal(u1, u0) and np.array_equal(W1, W0)
-    for e in entries:
+    for e in entries_tiles:
         for tx in e["candidates"]:
             s.set_tile(e["family"], e["level"], tx)
             u2, W2, it2 = solve(s)

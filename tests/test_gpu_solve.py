@@ -186,3 +186,42 @@ def test_graph_replays_match_eager(precision):
         b = outs[True][0]
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
         assert a[2:] == b[2:]
+
+
+@pytest.mark.parametrize("case", ["hamiltonian_32", "coupled_64", "puncture_128"])
+def test_vcycle_tail_matches_separate_launches(case):
+    """The workgroup-resident V-cycle tail and the separate coarse-level launches
+    solve the same system: same iteration count (within one), psi within 1e-10."""
+    import synth as sy
+    from gpu_helpers import gparams as gp
+    if case == "hamiltonian_32":
+        w = sy.hamiltonian_32(seed=1)
+    elif case == "coupled_64":
+        w = sy.coupled(64, seed=5, precision=g.PREC_FP32_IR)
+    else:
+        w = sy.puncture_shell(128, precision=g.PREC_FP32_IR, levels=6)
+    out = {}
+    for no_tail in (False, True):
+        p = gp(w)
+        if w.shell is not None:
+            r5, r1, S = g.shell_field_sources(p, w.shell["amplitude"], w.shell["r0"], w.shell["width2"],
+                                              w.scalar_mass, dev())
+        else:
+            r5, r1, S, mean = g.scalar_field_sources(p, w.phi_modes, w.pi_modes, w.scalar_mass, dev())
+            p.K = g.K_from_mean_density(mean)
+        s = g.Solver(p, r5, r1, S if w.solve_momentum else None)
+        if not no_tail:
+            # the tail's first level: psi at the first level of at most 16^3 cells, W at most 8^3
+            ns = [w.n >> l for l in range(w.levels)]
+            s.set_tile(g.TUNE_TAIL_PSI, next(l for l, n in enumerate(ns) if n <= 16), 1)
+            if w.solve_momentum:
+                s.set_tile(g.TUNE_TAIL_W, next(l for l, n in enumerate(ns) if n <= 8), 1)
+        u = torch.zeros((w.n,) * 3, dtype=torch.float64, device=dev())
+        W = torch.zeros((3,) + (w.n,) * 3, dtype=torch.float64, device=dev()) if w.solve_momentum else None
+        rep = s.solve(u, W, tol=1e-11, max_outer=80)
+        out[no_tail] = (N(u), rep)
+    (u0, r0), (u1, r1) = out[False], out[True]
+    print(f"{case}: tail {r0['outer_iters']} iterations, separate launches {r1['outer_iters']}")
+    assert r0["h_rms"] <= 1e-11 and r1["h_rms"] <= 1e-11
+    assert abs(r0["outer_iters"] - r1["outer_iters"]) <= 1
+    assert np.max(np.abs(u0 - u1) / (1.0 + np.abs(u1))) < 1e-10
