@@ -220,8 +220,10 @@ mg_status mg_fmg_start(mg_ctx *cc, mg_ctx *cf, double *d_uc, double *d_Wc, doubl
  * entries, may be NULL with cap 0) receives one mg_tune per tuned (family,
  * level); *h_count (may be NULL) the number of entries.  Waits for the
  * stream.  mg_set_tile applies a stored choice (a candidate of the family;
- * MG_ERR_INVALID otherwise).  Candidates: psi pass {2, 4, 8}; W pass {1, 2, 4}
- * (FP32) or {1, 2} (FP64); residual {1, 2, 4}.
+ * MG_ERR_INVALID otherwise).  Candidates: psi pass {2, 4, 8}; W pass {2, 4, 8,
+ * 16} (FP32) or {1, 2, 8} (FP64), where depths up to 4 stage a whole brick and
+ * 8 and 16 march a column of that many x planes through a ring of staged
+ * planes; residual {1, 2, 4}.
  * Two further families choose how the coarse levels of each V-cycle run: as
  * separate grid launches (0, the default) or as one workgroup-resident "tail"
  * kernel per V-cycle (1) that runs every level from the first of at most 16^3

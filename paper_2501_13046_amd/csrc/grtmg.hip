@@ -65,8 +65,9 @@ constexpr int kBrickPsi = 4;
 constexpr int kBrickW = 2;
 constexpr int kBrickR = 2;
 constexpr int kCandPsi[] = {2, 4, 8};
-constexpr int kCandW32[] = {1, 2, 4};
-constexpr int kCandW64[] = {1, 2};
+// W pass depths: 1, 2, 4 are bricks staged whole, 8 and 16 columns marched plane by plane
+constexpr int kCandW32[] = {2, 4, 8, 16};
+constexpr int kCandW64[] = {1, 2, 8};
 constexpr int kCandR[] = {1, 2, 4};
 constexpr int kCandTail[] = {0, 1}; // V-cycle tail off / on
 
@@ -196,9 +197,13 @@ TileMap tilemap_rt(int n, int tx)
     case 2: return make_tilemap<2>(n);
     case 4: return make_tilemap<4>(n);
     case 8: return make_tilemap<8>(n);
+    case 16: return make_tilemap<16>(n);
     default: return TileMap{0, 0, 0, 0};
     }
 }
+
+// The tiled W pass addresses the three components with 32-bit byte offsets.
+bool w_tileable(int n) { return 3.0 * n * n * (double)n * sizeof(double) < 4294967296.0; }
 
 TileMap rtilemap_rt(int n, int tx)
 {
@@ -215,7 +220,7 @@ void init_geo(mg_ctx *c)
     for (int l = 0; l < c->L; l++) {
         c->geo[l] = make_geo(c->n[l], c->p.bc, c->p.length, c->p.origin, c->p.puncture_pos);
         c->tile[l] = make_tilemap<kBrickPsi>(c->n[l]);
-        c->tileW[l] = make_tilemap<kBrickW>(c->n[l]);
+        c->tileW[l] = w_tileable(c->n[l]) ? make_tilemap<kBrickW>(c->n[l]) : TileMap{0, 0, 0, 0};
     }
     c->tileR = make_rtilemap<kBrickR>(c->n[0]);
     // V-cycle tails: psi from the first level of at most 16^3 cells (13-point
@@ -399,7 +404,11 @@ template <typename T>
 void defect_restrict_W(mg_ctx *c, int l, const T *d, const T *r, T *rc)
 {
     Probe pr(c, MG_PROBE_DEFECT_RESTRICT_W, l);
-    if (fine_threads(c->n[l]))
+    const TileMap tm = w_tileable(c->n[l]) ? make_tilemap<8>(c->n[l]) : TileMap{0, 0, 0, 0};
+    if (tm.tx > 0)
+        hipLaunchKernelGGL((k_defect_restrict_W_march<T, 8>), dim3(ntiles(tm)), dim3(kLanes, kTY), 0, c->s,
+                           c->geo[l], tm, d, r, rc);
+    else if (fine_threads(c->n[l]))
         hipLaunchKernelGGL(k_defect_restrict_W_fine<T>, dim3(nblk(8 * c->cells[l + 1])), dim3(kBlock), 0, c->s,
                            c->geo[l], d, r, rc);
     else
@@ -523,7 +532,11 @@ template <typename T>
 void launch_W_tiled(hipStream_t s, const Geo &g, const TileMap &tm, const T *in, T *out, const T *r, int colour)
 {
     const dim3 blk(kLanes, kTY), grid(ntiles(tm));
-    if (tm.tx == 1)
+    if (tm.tx == 8)
+        hipLaunchKernelGGL((k_pass_W_march<T, 8>), grid, blk, 0, s, g, tm, in, out, r, colour);
+    else if (tm.tx == 16)
+        hipLaunchKernelGGL((k_pass_W_march<T, 16>), grid, blk, 0, s, g, tm, in, out, r, colour);
+    else if (tm.tx == 1)
         hipLaunchKernelGGL((k_pass_W_tiled<T, 1>), grid, blk, 0, s, g, tm, in, out, r, colour);
     else if (tm.tx == 4 && sizeof(T) == 4)
         hipLaunchKernelGGL((k_pass_W_tiled<float, 4>), grid, blk, 0, s, g, tm, (const float *)in, (float *)out,
@@ -962,10 +975,10 @@ const int *tune_candidates(const mg_ctx *c, int family, int &count)
     case MG_TUNE_PASS_PSI: count = 3; return kCandPsi;
     case MG_TUNE_PASS_W:
         if (c->f32) {
-            count = 3;
+            count = 4;
             return kCandW32;
         }
-        count = 2;
+        count = 3;
         return kCandW64;
     case MG_TUNE_RESIDUAL: count = 3; return kCandR;
     case MG_TUNE_TAIL_PSI:
@@ -978,7 +991,7 @@ const int *tune_candidates(const mg_ctx *c, int family, int &count)
 TileMap tune_map(const mg_ctx *c, int family, int level, int tx)
 {
     if (family == MG_TUNE_RESIDUAL) return level == 0 ? rtilemap_rt(c->n[0], tx) : TileMap{0, 0, 0, 0};
-    if (family == MG_TUNE_PASS_W && !c->momentum) return TileMap{0, 0, 0, 0};
+    if (family == MG_TUNE_PASS_W && (!c->momentum || !w_tileable(c->n[level]))) return TileMap{0, 0, 0, 0};
     return tilemap_rt(c->n[level], tx);
 }
 

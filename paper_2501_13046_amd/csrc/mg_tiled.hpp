@@ -16,6 +16,9 @@
 
 #include "mg_kernels.hpp"
 
+#include <type_traits>
+#include <utility>
+
 namespace grtmg {
 
 constexpr int kTY = 4;    // brick rows (y) = waves per workgroup
@@ -44,6 +47,15 @@ __device__ __forceinline__ void brick_of(const TileMap &t, int &x0, int &y0, int
     x0 = bx * t.tx;
     y0 = by * kTY;
     z0 = bz * kBZ;
+}
+
+// Element i of an array addressed by a 32-bit byte offset from its (uniform)
+// base: one address register per access instead of a 64-bit sum.
+template <typename P>
+__device__ __forceinline__ P &elt(P *base, unsigned i)
+{
+    return *reinterpret_cast<P *>(reinterpret_cast<char *>(const_cast<std::remove_const_t<P> *>(base)) +
+                                  i * (unsigned)sizeof(P));
 }
 
 // Staged layout: lds[xx][yy][h * kHalf + j] holds the value at staged z index
@@ -261,42 +273,232 @@ __global__ void __launch_bounds__(kTY *kLanes) k_pass_psi_tiled(Geo g, TileMap t
 }
 
 // ---------------------------------------------------------------------------------------
-// W smoother colour pass (periodic) on a brick: three staged fields, same
-// checkerboard lane mapping.
+// W smoother colour pass (periodic) on a brick, one field at a time.  The
+// three components are staged through two LDS buffers of one field each: the
+// global loads of field f + 1 are in flight while the lanes evaluate the taps
+// of field f, and a brick needs a third of the LDS of staging all three fields
+// at once (more workgroups per CU).  The contributions of each field to the
+// three rows of Delta_L are accumulated in registers:
+//   field 0: Laplacian row 0, D_xx (row 0), D_xy (row 1), D_xz (row 2)
+//   field 1: Laplacian row 1, D_yy (row 1), D_xy (row 0), D_yz (row 2)
+//   field 2: Laplacian row 2, D_zz (row 2), D_xz (row 0), D_yz (row 1)
+// Same lane mapping as the psi pass: the lane owning a z pair updates the
+// member of the active colour and copies the other.
 // ---------------------------------------------------------------------------------------
-template <typename T, int PAR, int TT>
-__device__ __forceinline__ void W_cell(const T *row0, const T *row1, const T *row2, const T *__restrict__ r,
-                                       T *__restrict__ out, int m, int qrow, int z0, int lane, T h2, T m2,
-                                       T inv_diag)
+
+// Staging rows of one periodic field, held in registers between the global
+// loads and the LDS stores.  Pair layout as in load_brick.
+template <typename T, int TX>
+struct BrickRegs {
+    using V2 = typename Vec2<T>::type;
+    static constexpr int NROW = (TX + 4) * kPY;
+    static constexpr int RPW = NROW / kTY;
+    static_assert(NROW % kTY == 0 && 2 * NROW <= kTY * kLanes, "staging rows must spread over the block");
+    V2 v[RPW];
+    V2 e;
+    __device__ __forceinline__ void fetch(const T *__restrict__ a, int n, int x0, int y0, int z0)
+    {
+        const int w = threadIdx.y, lane = threadIdx.x, tid = w * kLanes + lane;
+        auto row_off = [&](int row) -> unsigned {
+            return (unsigned)(wrap(x0 + row / kPY - 2, n) * n + wrap(y0 + row % kPY - 2, n)) * (unsigned)n;
+        };
+        const unsigned zp = (unsigned)wrap(z0 - 2 + 2 * lane, n);
+#pragma unroll
+        for (int i = 0; i < RPW; i++)
+            v[i] = *reinterpret_cast<const V2 *>(
+                reinterpret_cast<const char *>(a) + (row_off(w + i * kTY) + zp) * (unsigned)sizeof(T));
+        if (tid < 2 * NROW) {
+            const int erow = tid >> 1, ep = kLanes + (tid & 1);
+            const unsigned ze = (unsigned)wrap(z0 - 2 + 2 * ep, n);
+            e = *reinterpret_cast<const V2 *>(reinterpret_cast<const char *>(a) +
+                                              (row_off(erow) + ze) * (unsigned)sizeof(T));
+        }
+    }
+    __device__ __forceinline__ void store(T (*s)[kPY][kPZ]) const
+    {
+        const int w = threadIdx.y, lane = threadIdx.x, tid = w * kLanes + lane;
+#pragma unroll
+        for (int i = 0; i < RPW; i++) {
+            const int row = w + i * kTY;
+            T *dst = s[row / kPY][row % kPY];
+            dst[lane] = v[i].x;
+            dst[kHalf + lane] = v[i].y;
+        }
+        if (tid < 2 * NROW) {
+            const int erow = tid >> 1, ep = kLanes + (tid & 1);
+            T *dst = s[erow / kPY][erow % kPY];
+            dst[ep] = e.x;
+            dst[kHalf + ep] = e.y;
+        }
+    }
+};
+
+// Per-cell partial sums of the W pass: Laplacian rows (times 1/(12 h^2)), the
+// diagonal second derivatives (times 1/(12 h^2)), the mixed-derivative sums of
+// each row, the centre values.
+template <int... I, typename Fn>
+__device__ __forceinline__ void static_for_impl(std::integer_sequence<int, I...>, Fn &&f)
 {
-    Taps<T, PAR, TT> F0{row0 + lane}, F1{row1 + lane}, F2{row2 + lane};
-    const int za = z0 + 2 * lane + PAR, zb = z0 + 2 * lane + (PAR ^ 1);
-    T Ad[3];
-    deltaL_taps<T, PAR, TT>(F0, F1, F2, h2, m2, Ad);
-    const int qa = qrow + za, qb = qrow + zb;
-    out[qa] = F0.c() + (r[qa] - Ad[0]) * inv_diag;
-    out[m + qa] = F1.c() + (r[m + qa] - Ad[1]) * inv_diag;
-    out[2 * m + qa] = F2.c() + (r[2 * m + qa] - Ad[2]) * inv_diag;
-    constexpr int DZ = PAR ? -1 : 1;
-    out[qb] = F0.template at<0, 0, DZ>();
-    out[m + qb] = F1.template at<0, 0, DZ>();
-    out[2 * m + qb] = F2.template at<0, 0, DZ>();
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename Fn>
+__device__ __forceinline__ void static_for(Fn &&f)
+{
+    static_for_impl(std::make_integer_sequence<int, N>{}, f);
 }
 
-template <typename T, int TX, int TT>
-__device__ __forceinline__ void W_cells(const T *row0, const T *row1, const T *row2, const T *__restrict__ r,
-                                        T *__restrict__ out, int n, int x0, int y, int z0, int lane, int colour,
-                                        T h2, T m2, T inv_diag)
-{
-    if constexpr (TT < TX) {
-        const int x = x0 + TT;
-        const int m = n * n * n, qrow = (x * n + y) * n;
-        if (((colour + x + y + z0) & 1) == 0)
-            W_cell<T, 0, TT>(row0, row1, row2, r, out, m, qrow, z0, lane, h2, m2, inv_diag);
-        else
-            W_cell<T, 1, TT>(row0, row1, row2, r, out, m, qrow, z0, lane, h2, m2, inv_diag);
-        W_cells<T, TX, TT + 1>(row0, row1, row2, r, out, n, x0, y, z0, lane, colour, h2, m2, inv_diag);
+// The taps of one cell read from LDS into registers first, then evaluated.
+// Each read is followed by a compiler-only ordering point: the taps stay
+// single ds_read_b32 with an immediate offset (instead of being paired into
+// ds_read2_b32, whose 8-bit offsets need a fresh base address per pair here),
+// and all of them are in flight before the arithmetic that consumes them.
+template <typename T>
+struct RegTaps {
+    T v[5][5][5]; // (DX + 2, DY + 2, DZ + 2); only the entries read are kept
+    template <int DX, int DY, int DZ>
+    __device__ __forceinline__ T at() const
+    {
+        return v[DX + 2][DY + 2][DZ + 2];
     }
+    template <int DX, int DY, int DZ, typename Src>
+    __device__ __forceinline__ void get(const Src &S)
+    {
+        v[DX + 2][DY + 2][DZ + 2] = S.template at<DX, DY, DZ>();
+        asm volatile("" ::: "memory");
+    }
+    // centre, D_xx, D_yy, D_zz taps
+    template <typename Src>
+    __device__ __forceinline__ void get_lap(const Src &S)
+    {
+        get<0, 0, 0>(S);
+        get<-1, 0, 0>(S), get<1, 0, 0>(S), get<-2, 0, 0>(S), get<2, 0, 0>(S);
+        get<0, -1, 0>(S), get<0, 1, 0>(S), get<0, -2, 0>(S), get<0, 2, 0>(S);
+        get<0, 0, -1>(S), get<0, 0, 1>(S), get<0, 0, -2>(S), get<0, 0, 2>(S);
+    }
+    // the 16 off-axis taps of D_ab in the plane of axes A < B (0 = x, 1 = y, 2 = z)
+    template <int A, int B, typename Src>
+    __device__ __forceinline__ void get_mixed(const Src &S)
+    {
+        static_for<4>([&](auto i) {
+            constexpr int da = (decltype(i)::value & 1 ? 1 : -1) * (decltype(i)::value < 2 ? 1 : 2);
+            static_for<4>([&](auto j) {
+                constexpr int db = (decltype(j)::value & 1 ? 1 : -1) * (decltype(j)::value < 2 ? 1 : 2);
+                constexpr int dx = A == 0 ? da : 0;
+                constexpr int dy = A == 1 ? da : (B == 1 ? db : 0);
+                constexpr int dz = B == 2 ? db : 0;
+                get<dx, dy, dz>(S);
+            });
+        });
+    }
+    __device__ __forceinline__ T c() const { return at<0, 0, 0>(); }
+    __device__ __forceinline__ T dxx(T c) const
+    {
+        return T(16) * (at<-1, 0, 0>() + at<1, 0, 0>()) - (at<-2, 0, 0>() + at<2, 0, 0>()) - T(30) * c;
+    }
+    __device__ __forceinline__ T dyy(T c) const
+    {
+        return T(16) * (at<0, -1, 0>() + at<0, 1, 0>()) - (at<0, -2, 0>() + at<0, 2, 0>()) - T(30) * c;
+    }
+    __device__ __forceinline__ T dzz(T c) const
+    {
+        return T(16) * (at<0, 0, -1>() + at<0, 0, 1>()) - (at<0, 0, -2>() + at<0, 0, 2>()) - T(30) * c;
+    }
+    template <int DX, int DZ>
+    __device__ __forceinline__ T dy_at() const
+    {
+        return (at<DX, -2, DZ>() - at<DX, 2, DZ>()) + T(8) * (at<DX, 1, DZ>() - at<DX, -1, DZ>());
+    }
+    template <int DX, int DY>
+    __device__ __forceinline__ T dz_at() const
+    {
+        return (at<DX, DY, -2>() - at<DX, DY, 2>()) + T(8) * (at<DX, DY, 1>() - at<DX, DY, -1>());
+    }
+    __device__ __forceinline__ T dxy() const
+    {
+        return (dy_at<-2, 0>() - dy_at<2, 0>()) + T(8) * (dy_at<1, 0>() - dy_at<-1, 0>());
+    }
+    __device__ __forceinline__ T dxz() const
+    {
+        return (dz_at<-2, 0>() - dz_at<2, 0>()) + T(8) * (dz_at<1, 0>() - dz_at<-1, 0>());
+    }
+    __device__ __forceinline__ T dyz() const
+    {
+        return (dz_at<0, -2>() - dz_at<0, 2>()) + T(8) * (dz_at<0, 1>() - dz_at<0, -1>());
+    }
+    // first derivatives at the centre (times 12 h)
+    __device__ __forceinline__ T dx() const
+    {
+        return (at<-2, 0, 0>() - at<2, 0, 0>()) + T(8) * (at<1, 0, 0>() - at<-1, 0, 0>());
+    }
+    __device__ __forceinline__ T dy() const { return dy_at<0, 0>(); }
+    __device__ __forceinline__ T dz() const { return dz_at<0, 0>(); }
+};
+
+template <typename T>
+struct WPart {
+    T lap[3], dd[3], mix[3], c[3];
+};
+
+// Contributions of field F at one cell whose taps the source S reads (S.at<DX, DY, DZ>
+// relative to the cell); returns the value of the other member of the z pair.
+template <typename T, int F, int PAR, typename Src>
+__device__ __forceinline__ T W_field_parts(const Src &S, T h2, WPart<T> &P)
+{
+    RegTaps<T> D;
+    D.get_lap(S);
+    if constexpr (F == 0) {
+        D.template get_mixed<0, 1>(S);
+        D.template get_mixed<0, 2>(S);
+    } else if constexpr (F == 1) {
+        D.template get_mixed<0, 1>(S);
+        D.template get_mixed<1, 2>(S);
+    } else {
+        D.template get_mixed<0, 2>(S);
+        D.template get_mixed<1, 2>(S);
+    }
+    const T c = D.c();
+    const T xx = D.dxx(c), yy = D.dyy(c), zz = D.dzz(c);
+    P.c[F] = c;
+    P.lap[F] = (xx + yy + zz) * h2;
+    if constexpr (F == 0) {
+        P.dd[0] = xx * h2;
+        P.mix[1] = D.dxy();
+        P.mix[2] = D.dxz();
+    } else if constexpr (F == 1) {
+        P.dd[1] = yy * h2;
+        P.mix[0] = D.dxy();
+        P.mix[2] = P.mix[2] + D.dyz();
+    } else {
+        P.dd[2] = zz * h2;
+        P.mix[0] = P.mix[0] + D.dxz();
+        P.mix[1] = P.mix[1] + D.dyz();
+    }
+    constexpr int DZ = PAR ? -1 : 1;
+    return D.template at<0, 0, DZ>();
+}
+
+// W_field_parts, and the other member of the z pair copied to out.
+template <typename T, int F, int PAR, typename Src>
+__device__ __forceinline__ void W_field_taps(const Src &S, T *__restrict__ out, unsigned qb, T h2, WPart<T> &P)
+{
+    elt(out, qb) = W_field_parts<T, F, PAR>(S, h2, P);
+}
+
+template <typename T, int F, int PAR, int TT>
+__device__ __forceinline__ void W_field_cell(const T *row0, T *__restrict__ out, unsigned qb, T h2, WPart<T> &P)
+{
+    W_field_taps<T, F, PAR>(Taps<T, PAR, TT>{row0}, out, qb, h2, P);
+}
+
+// Contributions of field F to every cell of the thread; P0 is the parity of
+// the active member of the thread's z pair at x = x0 (it alternates with x).
+template <typename T, int TX, int F, int P0>
+__device__ __forceinline__ void W_field(const T *row0, T *__restrict__ outF, const unsigned *qb, T h2, WPart<T> *P)
+{
+    static_for<TX>([&](auto tt) {
+        constexpr int TT = decltype(tt)::value;
+        W_field_cell<T, F, P0 ^ (TT & 1), TT>(row0, outF, qb[TT], h2, P[TT]);
+    });
 }
 
 // The diagonal of Delta_L,h is the constant -100/(12 h^2); its reciprocal
@@ -306,20 +508,307 @@ __global__ void __launch_bounds__(kTY *kLanes) k_pass_W_tiled(Geo g, TileMap tm,
                                                              T *__restrict__ out, const T *__restrict__ r,
                                                              int colour)
 {
-    __shared__ T lds[3][TX + 4][kPY][kPZ];
+    __shared__ T lds[2][TX + 4][kPY][kPZ];
     int x0, y0, z0;
     brick_of(tm, x0, y0, z0);
     const int n = g.n;
-    const int m = n * n * n;
+    const unsigned m = (unsigned)n * n * n;
     const int ty = threadIdx.y, lane = threadIdx.x;
-    load_brick<kBcPeriodic, T, TX>(lds[0], Acc<kBcPeriodic, T>{in, g}, x0, y0, z0);
-    load_brick<kBcPeriodic, T, TX>(lds[1], Acc<kBcPeriodic, T>{in + m, g}, x0, y0, z0);
-    load_brick<kBcPeriodic, T, TX>(lds[2], Acc<kBcPeriodic, T>{in + 2 * m, g}, x0, y0, z0);
+    const int y = y0 + ty;
+    const int p0 = (colour + x0 + y + z0) & 1;
+    // flat indices of the active (qa) and copied (qb) member of the pair at each x
+    unsigned qa[TX], qb[TX];
+#pragma unroll
+    for (int t = 0; t < TX; t++) {
+        const unsigned row = (unsigned)((x0 + t) * n + y) * (unsigned)n + (unsigned)(z0 + 2 * lane);
+        const unsigned pa = (unsigned)(p0 ^ (t & 1));
+        qa[t] = row + pa;
+        qb[t] = row + (pa ^ 1u);
+    }
+    BrickRegs<T, TX> st;
+    st.fetch(in, n, x0, y0, z0);
+    // 32-bit byte offsets from uniform per-component pointers (one address VGPR per access)
+    const T *rf[3] = {r, r + m, r + 2 * (size_t)m};
+    T *of[3] = {out, out + m, out + 2 * (size_t)m};
+    T rv[3][TX];
+#pragma unroll
+    for (int f = 0; f < 3; f++)
+#pragma unroll
+        for (int t = 0; t < TX; t++)
+            rv[f][t] = *reinterpret_cast<const T *>(reinterpret_cast<const char *>(rf[f]) + qa[t] * (unsigned)sizeof(T));
+    st.store(lds[0]);
     __syncthreads();
     const T h2 = (T)g.inv12h2, m2 = (T)g.inv144h2;
     const T inv_diag = (T)(1.0 / (-100.0 * g.inv12h2));
-    W_cells<T, TX, 0>(&lds[0][0][ty][0], &lds[1][0][ty][0], &lds[2][0][ty][0], r, out, n, x0, y0 + ty, z0, lane,
-                      colour, h2, m2, inv_diag);
+    const T third = T(1) / T(3);
+    WPart<T> P[TX];
+    const T *b0 = &lds[0][0][ty][0] + lane, *b1 = &lds[1][0][ty][0] + lane;
+
+    st.fetch(in + m, n, x0, y0, z0);
+    if (p0) W_field<T, TX, 0, 1>(b0, of[0], qb, h2, P);
+    else W_field<T, TX, 0, 0>(b0, of[0], qb, h2, P);
+    st.store(lds[1]);
+    __syncthreads();
+
+    st.fetch(in + 2 * (size_t)m, n, x0, y0, z0);
+    if (p0) W_field<T, TX, 1, 1>(b1, of[1], qb, h2, P);
+    else W_field<T, TX, 1, 0>(b1, of[1], qb, h2, P);
+    st.store(lds[0]); // every lane finished reading field 0 before the barrier above
+    __syncthreads();
+
+    if (p0) W_field<T, TX, 2, 1>(b0, of[2], qb, h2, P);
+    else W_field<T, TX, 2, 0>(b0, of[2], qb, h2, P);
+
+#pragma unroll
+    for (int t = 0; t < TX; t++)
+#pragma unroll
+        for (int f = 0; f < 3; f++) {
+            const T Ad = P[t].lap[f] + (P[t].dd[f] + P[t].mix[f] * m2) * third;
+            *reinterpret_cast<T *>(reinterpret_cast<char *>(of[f]) + qa[t] * (unsigned)sizeof(T)) =
+                P[t].c[f] + (rv[f][t] - Ad) * inv_diag;
+        }
+}
+
+// ---------------------------------------------------------------------------------------
+// W smoother colour pass marching along x.  A workgroup owns a column of 4 (y)
+// x 128 (z) cells and LX consecutive x planes.  The three components of each
+// staged x plane (rows y0 - 2 .. y0 + 5, z0 - 2 .. z0 + 129, same pair layout as
+// the bricks) live in a ring of six LDS slots: while the lanes evaluate plane x
+// from the slots of x - 2 .. x + 2, the registers hold plane x + 4 in flight
+// from HBM and plane x + 3 is written into the slot that plane x - 3 vacated,
+// so global loads, LDS traffic and arithmetic overlap for the whole column and
+// each staged plane is loaded once per column (x halo amortised over LX).
+// ---------------------------------------------------------------------------------------
+constexpr int kRing = 6;
+
+// One staged x plane of the three components (24 rows of 66 pairs): wave w
+// moves the 64 lane pairs of rows w, w + 4, ..., threads tid < 48 the two
+// remaining pairs of row tid / 2.
+template <typename T>
+struct PlaneRegs {
+    using V2 = typename Vec2<T>::type;
+    static constexpr int NR = 3 * kPY;
+    static constexpr int RPW = NR / kTY;
+    static_assert(NR % kTY == 0 && 2 * NR <= kTY * kLanes, "plane rows must spread over the block");
+    V2 v[RPW];
+    V2 e;
+    __device__ __forceinline__ void fetch(const T *__restrict__ in, unsigned m, int n, int x, int y0, int z0)
+    {
+        const int w = threadIdx.y, lane = threadIdx.x, tid = w * kLanes + lane;
+        const unsigned xo = (unsigned)wrap(x, n) * (unsigned)n;
+        const unsigned zp = (unsigned)wrap(z0 - 2 + 2 * lane, n);
+#pragma unroll
+        for (int i = 0; i < RPW; i++) {
+            const int row = w + i * kTY; // component row / kPY is i * kTY / kPY
+            const T *a = in + (size_t)(i * kTY / kPY) * m;
+            const unsigned off = (xo + (unsigned)wrap(y0 + row % kPY - 2, n)) * (unsigned)n + zp;
+            v[i] = *reinterpret_cast<const V2 *>(reinterpret_cast<const char *>(a) + off * (unsigned)sizeof(T));
+        }
+        if (tid < 2 * NR) {
+            const int erow = tid >> 1, ep = kLanes + (tid & 1);
+            const unsigned off = (xo + (unsigned)wrap(y0 + erow % kPY - 2, n)) * (unsigned)n +
+                                 (unsigned)wrap(z0 - 2 + 2 * ep, n);
+            e = *reinterpret_cast<const V2 *>(reinterpret_cast<const char *>(in) +
+                                              ((size_t)(erow / kPY) * m + off) * sizeof(T));
+        }
+    }
+    __device__ __forceinline__ void store(T (*s)[kPZ]) const // s: 24 staged rows of one slot
+    {
+        const int w = threadIdx.y, lane = threadIdx.x, tid = w * kLanes + lane;
+#pragma unroll
+        for (int i = 0; i < RPW; i++) {
+            T *dst = s[w + i * kTY];
+            dst[lane] = v[i].x;
+            dst[kHalf + lane] = v[i].y;
+        }
+        if (tid < 2 * NR) {
+            const int erow = tid >> 1, ep = kLanes + (tid & 1);
+            s[erow][ep] = e.x;
+            s[erow][kHalf + ep] = e.y;
+        }
+    }
+};
+
+// Taps of component F around the thread's cell: pb[DX + 2] is word lane of
+// staged row ty of the slot holding plane x + DX.
+template <typename T, int PAR, int F>
+struct RingTaps {
+    const T *const *pb;
+    template <int DX, int DY, int DZ>
+    __device__ __forceinline__ T at() const
+    {
+        return pb[DX + 2][F * kPlane + (2 + DY) * kRow + zoff<PAR, DZ>()];
+    }
+};
+
+template <typename T, int PAR>
+__device__ __forceinline__ void W_march_cell(const T *const *pb, T *const *of, unsigned qb, T h2, WPart<T> &P)
+{
+    W_field_taps<T, 0, PAR>(RingTaps<T, PAR, 0>{pb}, of[0], qb, h2, P);
+    W_field_taps<T, 1, PAR>(RingTaps<T, PAR, 1>{pb}, of[1], qb, h2, P);
+    W_field_taps<T, 2, PAR>(RingTaps<T, PAR, 2>{pb}, of[2], qb, h2, P);
+}
+
+template <typename T, int LX>
+__global__ void __launch_bounds__(kTY *kLanes) k_pass_W_march(Geo g, TileMap tm, const T *__restrict__ in,
+                                                             T *__restrict__ out, const T *__restrict__ r,
+                                                             int colour)
+{
+    __shared__ T lds[kRing][3 * kPY][kPZ];
+    int x0, y0, z0;
+    brick_of(tm, x0, y0, z0);
+    const int n = g.n;
+    const unsigned m = (unsigned)n * n * n;
+    const int ty = threadIdx.y, lane = threadIdx.x;
+    const int y = y0 + ty;
+    const T *rf[3] = {r, r + m, r + 2 * (size_t)m};
+    T *of[3] = {out, out + m, out + 2 * (size_t)m};
+    const T h2 = (T)g.inv12h2, m2 = (T)g.inv144h2;
+    const T inv_diag = (T)(1.0 / (-100.0 * g.inv12h2));
+    const T third = T(1) / T(3);
+
+    // staged plane j (0 .. LX + 3) is x = x0 - 2 + j, in slot j % kRing
+    PlaneRegs<T> st;
+#pragma unroll
+    for (int j = 0; j < 5; j++) {
+        st.fetch(in, m, n, x0 - 2 + j, y0, z0);
+        st.store(lds[j]);
+    }
+    st.fetch(in, m, n, x0 + 3, y0, z0);
+    auto row_of = [&](int x) { return (unsigned)(x * n + y) * (unsigned)n + (unsigned)(z0 + 2 * lane); };
+    auto par_of = [&](int x) { return (unsigned)((colour + x + y + z0) & 1); };
+    T rv[3];
+#pragma unroll
+    for (int f = 0; f < 3; f++)
+        rv[f] = *reinterpret_cast<const T *>(reinterpret_cast<const char *>(rf[f]) +
+                                             (row_of(x0) + par_of(x0)) * (unsigned)sizeof(T));
+    __syncthreads();
+
+#pragma unroll 1
+    for (int k = 0; k < LX; k++) {
+        const int x = x0 + k;
+        const unsigned pa = par_of(x);
+        const unsigned qa = row_of(x) + pa, qb = row_of(x) + (pa ^ 1u);
+        const T *pb[5];
+#pragma unroll
+        for (int d = 0; d < 5; d++) pb[d] = &lds[(k + d) % kRing][ty][lane];
+        T rn[3] = {T(0), T(0), T(0)};
+        if (k + 1 < LX) { // r of the next plane's active cells
+            const unsigned qn = row_of(x + 1) + (pa ^ 1u);
+#pragma unroll
+            for (int f = 0; f < 3; f++)
+                rn[f] = *reinterpret_cast<const T *>(reinterpret_cast<const char *>(rf[f]) + qn * (unsigned)sizeof(T));
+        }
+        WPart<T> P;
+        if (pa) W_march_cell<T, 1>(pb, of, qb, h2, P);
+        else W_march_cell<T, 0>(pb, of, qb, h2, P);
+#pragma unroll
+        for (int f = 0; f < 3; f++) {
+            const T Ad = P.lap[f] + (P.dd[f] + P.mix[f] * m2) * third;
+            *reinterpret_cast<T *>(reinterpret_cast<char *>(of[f]) + qa * (unsigned)sizeof(T)) =
+                P.c[f] + (rv[f] - Ad) * inv_diag;
+            rv[f] = rn[f];
+        }
+        if (k + 5 <= LX + 3) { // plane x + 3 into the slot plane x - 3 left
+            st.store(lds[(k + 5) % kRing]);
+            if (k + 6 <= LX + 3) st.fetch(in, m, n, x + 4, y0, z0);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// W defect r - Delta_L d and its restriction (mean of the 8 children) to the
+// next coarser level, marching along x like k_pass_W_march.  Each lane
+// evaluates both members of its z pair on two consecutive x planes; the paired
+// y rows (waves 2 w' and 2 w' + 1) are added through LDS and the even wave
+// writes one coarse cell per lane (coarse z = z0 / 2 + lane, coalesced).
+// ---------------------------------------------------------------------------------------
+template <typename T, int PAR>
+__device__ __forceinline__ void W_defect_cell(const T *const *pb, const T (&rv)[3], T h2, T m2, T third, T (&acc)[3])
+{
+    WPart<T> P;
+    W_field_parts<T, 0, PAR>(RingTaps<T, PAR, 0>{pb}, h2, P);
+    W_field_parts<T, 1, PAR>(RingTaps<T, PAR, 1>{pb}, h2, P);
+    W_field_parts<T, 2, PAR>(RingTaps<T, PAR, 2>{pb}, h2, P);
+#pragma unroll
+    for (int f = 0; f < 3; f++) acc[f] += rv[f] - (P.lap[f] + (P.dd[f] + P.mix[f] * m2) * third);
+}
+
+template <typename T, int LX>
+__global__ void __launch_bounds__(kTY *kLanes) k_defect_restrict_W_march(Geo g, TileMap tm, const T *__restrict__ d,
+                                                                        const T *__restrict__ r,
+                                                                        T *__restrict__ rc_out)
+{
+    static_assert(LX % 2 == 0 && kTY % 2 == 0, "whole coarse cells per column");
+    using V2 = typename Vec2<T>::type;
+    __shared__ T lds[kRing][3 * kPY][kPZ];
+    __shared__ T red[3][kTY / 2][kLanes];
+    int x0, y0, z0;
+    brick_of(tm, x0, y0, z0);
+    const int n = g.n, nc = n / 2;
+    const unsigned m = (unsigned)n * n * n, mc = (unsigned)nc * nc * nc;
+    const int ty = threadIdx.y, lane = threadIdx.x;
+    const int y = y0 + ty;
+    const T *rf[3] = {r, r + m, r + 2 * (size_t)m};
+    const T h2 = (T)g.inv12h2, m2 = (T)g.inv144h2;
+    const T third = T(1) / T(3);
+
+    PlaneRegs<T> st;
+#pragma unroll
+    for (int j = 0; j < 5; j++) {
+        st.fetch(d, m, n, x0 - 2 + j, y0, z0);
+        st.store(lds[j]);
+    }
+    st.fetch(d, m, n, x0 + 3, y0, z0);
+    auto pair_of = [&](int x) { return (unsigned)(x * n + y) * (unsigned)n + (unsigned)(z0 + 2 * lane); };
+    V2 rv[3];
+#pragma unroll
+    for (int f = 0; f < 3; f++) rv[f] = elt(reinterpret_cast<const V2 *>(rf[f]), pair_of(x0) >> 1);
+    __syncthreads();
+
+    T acc[3] = {T(0), T(0), T(0)};
+#pragma unroll 1
+    for (int k = 0; k < LX; k++) {
+        const int x = x0 + k;
+        const T *pb[5];
+#pragma unroll
+        for (int dd = 0; dd < 5; dd++) pb[dd] = &lds[(k + dd) % kRing][ty][lane];
+        V2 rn[3];
+        if (k + 1 < LX) {
+#pragma unroll
+            for (int f = 0; f < 3; f++) rn[f] = elt(reinterpret_cast<const V2 *>(rf[f]), pair_of(x + 1) >> 1);
+        }
+        const T ra[3] = {rv[0].x, rv[1].x, rv[2].x}, rb[3] = {rv[0].y, rv[1].y, rv[2].y};
+        W_defect_cell<T, 0>(pb, ra, h2, m2, third, acc);
+        W_defect_cell<T, 1>(pb, rb, h2, m2, third, acc);
+        if (k & 1) {
+            if (ty & 1) {
+#pragma unroll
+                for (int f = 0; f < 3; f++) red[f][ty >> 1][lane] = acc[f];
+            }
+        }
+        if (k + 5 <= LX + 3) {
+            st.store(lds[(k + 5) % kRing]);
+            if (k + 6 <= LX + 3) st.fetch(d, m, n, x + 4, y0, z0);
+        }
+        __syncthreads();
+        if (k & 1) {
+            if (!(ty & 1)) {
+                const unsigned qc = ((unsigned)(x >> 1) * (unsigned)nc + (unsigned)(y >> 1)) * (unsigned)nc +
+                                    (unsigned)((z0 >> 1) + lane);
+#pragma unroll
+                for (int f = 0; f < 3; f++)
+                    elt(rc_out + (size_t)f * mc, qc) = (acc[f] + red[f][ty >> 1][lane]) * T(0.125);
+            }
+#pragma unroll
+            for (int f = 0; f < 3; f++) acc[f] = T(0);
+        }
+        if (k + 1 < LX) {
+#pragma unroll
+            for (int f = 0; f < 3; f++) rv[f] = rn[f];
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -346,7 +835,8 @@ __device__ __forceinline__ void load_rbrick(T (*s)[kPY][kRPZ], const Acc<BC, T> 
     auto fetch = [&](int row, int zz) -> T {
         const int xg = x0 + row / kPY - 2, yg = y0 + row % kPY - 2, zg = z0 - 2 + zz;
         if (BC == kBcPeriodic)
-            return A.a[(wrap(xg, n) * n + wrap(yg, n)) * n + wrap(zg, n)];
+            return elt(A.a, ((unsigned)wrap(xg, n) * (unsigned)n + (unsigned)wrap(yg, n)) * (unsigned)n +
+                                (unsigned)wrap(zg, n));
         return A(xg, yg, zg);
     };
     T v[RPW];
@@ -364,22 +854,33 @@ __device__ __forceinline__ void load_rbrick(T (*s)[kPY][kRPZ], const Acc<BC, T> 
 }
 
 // 4th-order Laplacian sum of a periodic field at (x, y, z) with wrapped
-// neighbour offsets (the centre value passed in).
+// neighbour indices (the centre value passed in).
 __device__ __forceinline__ double lap_periodic(const double *__restrict__ a, int n, int x, int y, int z, double c)
 {
-    const int nn = n * n;
-    const int q = (x * n + y) * n + z;
-    auto off = [n](int i, int d, int stride) { // stride offset of coordinate i + d, wrapped
+    const unsigned un = (unsigned)n, nn = un * un;
+    const unsigned q = ((unsigned)x * un + (unsigned)y) * un + (unsigned)z;
+    auto at = [&](int i, int d, unsigned stride) { // value at coordinate i + d (wrapped) along one axis
         const int j = i + d;
-        return (j < 0 ? j + n : (j >= n ? j - n : j)) * stride - i * stride;
+        const int w = j < 0 ? j + n : (j >= n ? j - n : j);
+        return elt(a, q + (unsigned)w * stride - (unsigned)i * stride);
     };
     double s = -90.0 * c;
-    s += 16.0 * (a[q + off(x, -1, nn)] + a[q + off(x, 1, nn)] + a[q + off(y, -1, n)] + a[q + off(y, 1, n)] +
-                 a[q + off(z, -1, 1)] + a[q + off(z, 1, 1)]);
-    s -= a[q + off(x, -2, nn)] + a[q + off(x, 2, nn)] + a[q + off(y, -2, n)] + a[q + off(y, 2, n)] +
-         a[q + off(z, -2, 1)] + a[q + off(z, 2, 1)];
+    s += 16.0 * (at(x, -1, nn) + at(x, 1, nn) + at(y, -1, un) + at(y, 1, un) + at(z, -1, 1u) + at(z, 1, 1u));
+    s -= at(x, -2, nn) + at(x, 2, nn) + at(y, -2, un) + at(y, 2, un) + at(z, -2, 1u) + at(z, 2, 1u);
     return s;
 }
+
+// Taps of a residual brick field relative to the staged word of the stencil
+// corner (x - 2, y - 2, z - 2): every offset is non-negative.
+template <typename T>
+struct RCorner {
+    const T *b;
+    template <int DX, int DY, int DZ>
+    __device__ __forceinline__ T at() const
+    {
+        return b[(DX + 2) * kRPlane + (DY + 2) * kRRow + DZ + 2];
+    }
+};
 
 template <typename T>
 struct RTaps {
@@ -455,60 +956,84 @@ __global__ void __launch_bounds__(kTY *kLanes) k_residual_tiled(Geo g, TileMap t
     }
     Acc<BC, double> U{a.u, g};
     const double K2 = a.K2;
-    double hsum = 0.0, hmax = 0.0, msum = 0.0, mmax = 0.0;
+    const double third = 1.0 / 3.0, two_thirds = 2.0 / 3.0;
+    double hsum = 0.0, hmax = 0.0, msum = 0.0, mmax2 = 0.0;
 #pragma unroll
     for (int t = 0; t < TX; t++) {
         const int x = x0 + t;
-        const int q = (x * n + y) * n + z;
-        const double uc = a.u[q];
+        const unsigned q = ((unsigned)x * (unsigned)n + (unsigned)y) * (unsigned)n + (unsigned)z;
+        const double uc = elt(a.u, q);
         const double psi = psi0_at(g, a.pmass, x, y, z) + uc;
         double A2 = 0.0;
         double Mv[3] = {0.0, 0.0, 0.0};
         if constexpr (HAS_W) {
-            const int off = ((t + 2) * kPY + (ty + 2)) * kRPZ + lane + 2;
-            RTaps<double> F0{&lds[0][0][0][0] + off}, F1{&lds[1][0][0][0] + off}, F2{&lds[2][0][0][0] + off};
-            double dW[3][3];
-            dW[0][0] = F0.dx() * g.inv12h;
-            dW[1][0] = F0.dy() * g.inv12h;
-            dW[2][0] = F0.dz() * g.inv12h;
-            dW[0][1] = F1.dx() * g.inv12h;
-            dW[1][1] = F1.dy() * g.inv12h;
-            dW[2][1] = F1.dz() * g.inv12h;
-            dW[0][2] = F2.dx() * g.inv12h;
-            dW[1][2] = F2.dy() * g.inv12h;
-            dW[2][2] = F2.dz() * g.inv12h;
-            const double div = dW[0][0] + dW[1][1] + dW[2][2];
+            // staged word of the stencil corner (x - 2, y - 2, z - 2) of this cell
+            const int off = (t * kPY + ty) * kRPZ + lane;
+            double dW[3][3]; // dW[p][s]: d_p W_s
+            double lap[3], dd[3], mix[3];
+            auto field = [&](auto fc) {
+                constexpr int F = decltype(fc)::value;
+                const RCorner<double> S{&lds[F][0][0][0] + off};
+                RegTaps<double> D;
+                D.get_lap(S);
+                if (a.want_M) {
+                    if constexpr (F == 0) {
+                        D.template get_mixed<0, 1>(S);
+                        D.template get_mixed<0, 2>(S);
+                    } else if constexpr (F == 1) {
+                        D.template get_mixed<0, 1>(S);
+                        D.template get_mixed<1, 2>(S);
+                    } else {
+                        D.template get_mixed<0, 2>(S);
+                        D.template get_mixed<1, 2>(S);
+                    }
+                }
+                dW[0][F] = D.dx() * g.inv12h;
+                dW[1][F] = D.dy() * g.inv12h;
+                dW[2][F] = D.dz() * g.inv12h;
+                if (a.want_M) {
+                    const double c = D.c();
+                    const double xx = D.dxx(c), yy = D.dyy(c), zz = D.dzz(c);
+                    lap[F] = (xx + yy + zz) * g.inv12h2;
+                    if constexpr (F == 0) {
+                        dd[0] = xx * g.inv12h2;
+                        mix[1] = D.dxy();
+                        mix[2] = D.dxz();
+                    } else if constexpr (F == 1) {
+                        dd[1] = yy * g.inv12h2;
+                        mix[0] = D.dxy();
+                        mix[2] = mix[2] + D.dyz();
+                    } else {
+                        dd[2] = zz * g.inv12h2;
+                        mix[0] = mix[0] + D.dxz();
+                        mix[1] = mix[1] + D.dyz();
+                    }
+                }
+            };
+            static_for<3>(field);
+            const double tdiv = (dW[0][0] + dW[1][1] + dW[2][2]) * two_thirds;
 #pragma unroll
             for (int p = 0; p < 3; p++)
 #pragma unroll
                 for (int s2 = 0; s2 < 3; s2++) {
-                    const double Ab = dW[p][s2] + dW[s2][p] - (p == s2 ? 2.0 * div / 3.0 : 0.0);
+                    const double Ab = dW[p][s2] + dW[s2][p] - (p == s2 ? tdiv : 0.0);
                     A2 += Ab * Ab;
                 }
             if (a.want_M) {
-                const double c0 = F0.c(), c1 = F1.c(), c2 = F2.c();
-                const double xx0 = F0.dxx(c0), yy1 = F1.dyy(c1), zz2 = F2.dzz(c2);
-                const double l0 = (xx0 + F0.dyy(c0) + F0.dzz(c0)) * g.inv12h2;
-                const double l1 = (F1.dxx(c1) + yy1 + F1.dzz(c1)) * g.inv12h2;
-                const double l2 = (F2.dxx(c2) + F2.dyy(c2) + zz2) * g.inv12h2;
-                const double t0 = xx0 * g.inv12h2 + (F1.dxy() + F2.dxz()) * g.inv144h2;
-                const double t1 = yy1 * g.inv12h2 + (F0.dxy() + F2.dyz()) * g.inv144h2;
-                const double t2 = zz2 * g.inv12h2 + (F0.dxz() + F1.dyz()) * g.inv144h2;
-                Mv[0] = l0 + t0 / 3.0;
-                Mv[1] = l1 + t1 / 3.0;
-                Mv[2] = l2 + t2 / 3.0;
+#pragma unroll
+                for (int f = 0; f < 3; f++) Mv[f] = lap[f] + (dd[f] + mix[f] * g.inv144h2) * third;
             }
         }
         if (a.want_M && a.S) {
             const double p2 = psi * psi;
             const double w6 = a.conformal ? 1.0 : p2 * p2 * p2;
 #pragma unroll
-            for (int s2 = 0; s2 < 3; s2++) Mv[s2] -= 8.0 * kPi * w6 * a.S[s2 * m + q] - a.meanS[s2];
+            for (int s2 = 0; s2 < 3; s2++) Mv[s2] -= 8.0 * kPi * w6 * elt(a.S + (size_t)s2 * m, q) - a.meanS[s2];
         }
         const double psi2 = psi * psi, psi4 = psi2 * psi2, psi5 = psi4 * psi;
-        const double ipsi = 1.0 / psi, ipsi4 = 1.0 / psi4;
-        const double ipsi7 = ipsi4 * ipsi * ipsi * ipsi, ipsi8 = ipsi7 * ipsi;
-        const double r5 = a.rho5[q], r1 = a.rho1[q];
+        const double ipsi = 1.0 / psi, ipsi2 = ipsi * ipsi, ipsi4 = ipsi2 * ipsi2;
+        const double ipsi7 = ipsi4 * ipsi2 * ipsi, ipsi8 = ipsi4 * ipsi4;
+        const double r5 = elt(a.rho5, q), r1 = elt(a.rho1, q);
         double matter, dmatter;
         if (a.conformal) {
             const double rbar = r5 + r1;
@@ -524,32 +1049,30 @@ __global__ void __launch_bounds__(kTY *kLanes) k_residual_tiled(Geo g, TileMap t
         else
             lu = lap_sum<double>(U, x, y, z, uc);
         double H = lu * g.inv12h2 + matter - (K2 / 12.0) * psi5 + 0.125 * A2 * ipsi7;
-        if (a.f) H += a.f[q];
+        if (a.f) H += elt(a.f, q);
         const double cc = dmatter - (5.0 * K2 / 12.0) * psi4 - 0.875 * A2 * ipsi8;
-        if (a.H) a.H[q] = H;
-        if (a.c) a.c[q] = cc;
-        if (a.r) ((T *)a.r)[q] = (T)(-H);
-        if (a.rc) ((T *)a.rc)[q] = (T)cc;
+        if (a.H) elt(a.H, q) = H;
+        if (a.c) elt(a.c, q) = cc;
+        if (a.r) elt((T *)a.r, q) = (T)(-H);
+        if (a.rc) elt((T *)a.rc, q) = (T)cc;
         if (a.want_M) {
             if (a.M) {
-                a.M[q] = Mv[0];
-                a.M[m + q] = Mv[1];
-                a.M[2 * m + q] = Mv[2];
+#pragma unroll
+                for (int s2 = 0; s2 < 3; s2++) elt(a.M + (size_t)s2 * m, q) = Mv[s2];
             }
             if (a.rW) {
-                ((T *)a.rW)[q] = (T)(-Mv[0]);
-                ((T *)a.rW)[m + q] = (T)(-Mv[1]);
-                ((T *)a.rW)[2 * m + q] = (T)(-Mv[2]);
+#pragma unroll
+                for (int s2 = 0; s2 < 3; s2++) elt((T *)a.rW + (size_t)s2 * m, q) = (T)(-Mv[s2]);
             }
             const double m2 = Mv[0] * Mv[0] + Mv[1] * Mv[1] + Mv[2] * Mv[2];
             msum += m2;
-            mmax = fmax(mmax, sqrt(m2));
+            mmax2 = fmax(mmax2, m2);
         }
         hsum += H * H;
         hmax = fmax(hmax, fabs(H));
     }
     if (a.partials) {
-        double v[4] = {hsum, hmax, msum, mmax};
+        double v[4] = {hsum, hmax, msum, sqrt(mmax2)};
         // 256 threads per block, as block_reduce_store assumes
         block_reduce_store<4>(v, 0xAu, a.partials + 4 * (int64_t)blockIdx.x);
     }
@@ -560,6 +1083,7 @@ inline TileMap make_rtilemap(int n)
 {
     TileMap t{0, 0, 0, 0};
     if (n % kRZ != 0 || n % kTY != 0 || n % TX != 0 || n < 64) return t;
+    if ((double)n * n * n * sizeof(double) >= 4294967296.0) return t; // 32-bit byte offsets per field
     t.nx = n / TX;
     t.ny = n / kTY;
     t.nz = n / kRZ;

@@ -35,13 +35,17 @@ def test_tiled_psi_pass(precision, bc):
         assert rel_err(N(out), oracle.pass_psi(po, d, r, c, colour)) < tol, colour
 
 
-@pytest.mark.parametrize("precision", [g.PREC_FP64, g.PREC_FP32_IR])
-def test_tiled_W_pass(precision):
+@pytest.mark.parametrize("precision,depth", [(g.PREC_FP64, 1), (g.PREC_FP64, 2), (g.PREC_FP64, 8),
+                                             (g.PREC_FP32_IR, 2), (g.PREC_FP32_IR, 4), (g.PREC_FP32_IR, 8),
+                                             (g.PREC_FP32_IR, 16)])
+def test_tiled_W_pass(precision, depth):
+    """Every brick depth (staged bricks 1-4, x-marched columns 8 and 16) against the oracle."""
     p = g.params(n, 6, precision=precision, solve_momentum=True)
     po = oracle.params(n, 6)
     z = torch.zeros((n,) * 3, dtype=torch.float64, device=dev())
     S = torch.zeros((3, n, n, n), dtype=torch.float64, device=dev())
     s = g.Solver(p, z, z, S)
+    s.set_tile(g.TUNE_PASS_W, 0, depth)
     d = synth.uniform_random(63, (3, n, n, n))
     r = synth.uniform_random(64, (3, n, n, n))
     vt = s.vtype
@@ -52,6 +56,27 @@ def test_tiled_W_pass(precision):
         out = torch.empty((3, n, n, n), dtype=vt, device=dev())
         s.kernel_op(g.OP_PASS_W, 0, colour, T(d, vt), out, T(r, vt))
         assert rel_err(N(out), oracle.pass_W(po, d, r, colour)) < tol, colour
+
+
+@pytest.mark.parametrize("precision", [g.PREC_FP64, g.PREC_FP32_IR])
+def test_marched_W_defect_restrict(precision):
+    """W defect r - Delta_L d restricted to 64^3 by the x-marched kernel (finest level)."""
+    p = g.params(n, 6, precision=precision, solve_momentum=True)
+    po = oracle.params(n, 6)
+    z = torch.zeros((n,) * 3, dtype=torch.float64, device=dev())
+    S = torch.zeros((3, n, n, n), dtype=torch.float64, device=dev())
+    s = g.Solver(p, z, z, S)
+    d = synth.uniform_random(65, (3, n, n, n))
+    r = synth.uniform_random(66, (3, n, n, n))
+    vt = s.vtype
+    if vt == torch.float32:
+        d, r = (a.astype(np.float32).astype(np.float64) for a in (d, r))
+    out = torch.empty((3,) + (n // 2,) * 3, dtype=vt, device=dev())
+    s.kernel_op(g.OP_DEFECT_RESTRICT_W, 0, 0, T(d, vt), out, T(r, vt))
+    defect = r - oracle.apply_deltaL(po, d)
+    ref = np.stack([oracle.restrict(np.ascontiguousarray(defect[a])) for a in range(3)])
+    tol = 1e-12 if vt == torch.float64 else 1e-5
+    assert rel_err(N(out), ref) < tol
 
 
 def test_report_lds_limit():
