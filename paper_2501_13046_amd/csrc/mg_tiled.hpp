@@ -294,6 +294,7 @@ struct BrickRegs {
     static constexpr int NROW = (TX + 4) * kPY;
     static constexpr int RPW = NROW / kTY;
     static_assert(NROW % kTY == 0 && 2 * NROW <= kTY * kLanes, "staging rows must spread over the block");
+    static_assert(kPY == 2 * kTY, "each wave stages two y rows of every x plane");
     V2 v[RPW];
     V2 e;
     __device__ __forceinline__ void fetch(const T *__restrict__ a, int n, int x0, int y0, int z0)
@@ -303,10 +304,13 @@ struct BrickRegs {
             return (unsigned)(wrap(x0 + row / kPY - 2, n) * n + wrap(y0 + row % kPY - 2, n)) * (unsigned)n;
         };
         const unsigned zp = (unsigned)wrap(z0 - 2 + 2 * lane, n);
+        // row w + 4 i is y row w + 4 (i & 1) of x plane i / 2 (uniform x wrap)
+        const unsigned yw[2] = {(unsigned)wrap(y0 + w - 2, n), (unsigned)wrap(y0 + w + 2, n)};
 #pragma unroll
         for (int i = 0; i < RPW; i++)
             v[i] = *reinterpret_cast<const V2 *>(
-                reinterpret_cast<const char *>(a) + (row_off(w + i * kTY) + zp) * (unsigned)sizeof(T));
+                reinterpret_cast<const char *>(a) +
+                (((unsigned)wrap(x0 + i / 2 - 2, n) * (unsigned)n + yw[i & 1]) * (unsigned)n + zp) * (unsigned)sizeof(T));
         if (tid < 2 * NROW) {
             const int erow = tid >> 1, ep = kLanes + (tid & 1);
             const unsigned ze = (unsigned)wrap(z0 - 2 + 2 * ep, n);
@@ -590,6 +594,7 @@ struct PlaneRegs {
     static constexpr int NR = 3 * kPY;
     static constexpr int RPW = NR / kTY;
     static_assert(NR % kTY == 0 && 2 * NR <= kTY * kLanes, "plane rows must spread over the block");
+    static_assert(kPY == 2 * kTY, "each wave stages two y rows of every component");
     V2 v[RPW];
     V2 e;
     __device__ __forceinline__ void fetch(const T *__restrict__ in, unsigned m, int n, int x, int y0, int z0)
@@ -597,12 +602,13 @@ struct PlaneRegs {
         const int w = threadIdx.y, lane = threadIdx.x, tid = w * kLanes + lane;
         const unsigned xo = (unsigned)wrap(x, n) * (unsigned)n;
         const unsigned zp = (unsigned)wrap(z0 - 2 + 2 * lane, n);
+        // row w + 4 i is y row w + 4 (i & 1) of component i / 2
+        const unsigned yo[2] = {(xo + (unsigned)wrap(y0 + w - 2, n)) * (unsigned)n + zp,
+                                (xo + (unsigned)wrap(y0 + w + 2, n)) * (unsigned)n + zp};
 #pragma unroll
         for (int i = 0; i < RPW; i++) {
-            const int row = w + i * kTY; // component row / kPY is i * kTY / kPY
-            const T *a = in + (size_t)(i * kTY / kPY) * m;
-            const unsigned off = (xo + (unsigned)wrap(y0 + row % kPY - 2, n)) * (unsigned)n + zp;
-            v[i] = *reinterpret_cast<const V2 *>(reinterpret_cast<const char *>(a) + off * (unsigned)sizeof(T));
+            const T *a = in + (size_t)(i / 2) * m;
+            v[i] = *reinterpret_cast<const V2 *>(reinterpret_cast<const char *>(a) + yo[i & 1] * (unsigned)sizeof(T));
         }
         if (tid < 2 * NR) {
             const int erow = tid >> 1, ep = kLanes + (tid & 1);
@@ -628,6 +634,20 @@ struct PlaneRegs {
         }
     }
 };
+
+// Ring prologue of a marched column: planes x0 - 2 .. x0 + 2 into slots 0..4,
+// plane x0 + 3 left in st; all six fetches are issued before the first store.
+template <typename T>
+__device__ __forceinline__ void march_prologue(T (*lds)[3 * kPY][kPZ], PlaneRegs<T> &st, const T *__restrict__ in,
+                                               unsigned m, int n, int x0, int y0, int z0)
+{
+    PlaneRegs<T> w[5];
+#pragma unroll
+    for (int j = 0; j < 5; j++) w[j].fetch(in, m, n, x0 - 2 + j, y0, z0);
+    st.fetch(in, m, n, x0 + 3, y0, z0);
+#pragma unroll
+    for (int j = 0; j < 5; j++) w[j].store(lds[j]);
+}
 
 // Taps of component F around the thread's cell: pb[DX + 2] is word lane of
 // staged row ty of the slot holding plane x + DX.
@@ -667,14 +687,10 @@ __global__ void __launch_bounds__(kTY *kLanes) k_pass_W_march(Geo g, TileMap tm,
     const T inv_diag = (T)(1.0 / (-100.0 * g.inv12h2));
     const T third = T(1) / T(3);
 
-    // staged plane j (0 .. LX + 3) is x = x0 - 2 + j, in slot j % kRing
+    // staged plane j (0 .. LX + 3) is x = x0 - 2 + j, in slot j % kRing; the
+    // first six planes are all in flight at once
     PlaneRegs<T> st;
-#pragma unroll
-    for (int j = 0; j < 5; j++) {
-        st.fetch(in, m, n, x0 - 2 + j, y0, z0);
-        st.store(lds[j]);
-    }
-    st.fetch(in, m, n, x0 + 3, y0, z0);
+    march_prologue<T>(lds, st, in, m, n, x0, y0, z0);
     auto row_of = [&](int x) { return (unsigned)(x * n + y) * (unsigned)n + (unsigned)(z0 + 2 * lane); };
     auto par_of = [&](int x) { return (unsigned)((colour + x + y + z0) & 1); };
     T rv[3];
@@ -755,12 +771,7 @@ __global__ void __launch_bounds__(kTY *kLanes) k_defect_restrict_W_march(Geo g, 
     const T third = T(1) / T(3);
 
     PlaneRegs<T> st;
-#pragma unroll
-    for (int j = 0; j < 5; j++) {
-        st.fetch(d, m, n, x0 - 2 + j, y0, z0);
-        st.store(lds[j]);
-    }
-    st.fetch(d, m, n, x0 + 3, y0, z0);
+    march_prologue<T>(lds, st, d, m, n, x0, y0, z0);
     auto pair_of = [&](int x) { return (unsigned)(x * n + y) * (unsigned)n + (unsigned)(z0 + 2 * lane); };
     V2 rv[3];
 #pragma unroll
@@ -830,6 +841,7 @@ __device__ __forceinline__ void load_rbrick(T (*s)[kPY][kRPZ], const Acc<BC, T> 
     constexpr int NROW = (TX + 4) * kPY;
     constexpr int RPW = NROW / kTY;
     static_assert(4 * NROW <= kTY * kLanes, "one extra value per thread at most");
+    static_assert(kPY == 2 * kTY, "each wave stages two y rows of every x plane");
     const int n = A.g.n;
     const int w = threadIdx.y, lane = threadIdx.x, tid = w * kLanes + lane;
     auto fetch = [&](int row, int zz) -> T {
@@ -840,8 +852,18 @@ __device__ __forceinline__ void load_rbrick(T (*s)[kPY][kRPZ], const Acc<BC, T> 
         return A(xg, yg, zg);
     };
     T v[RPW];
+    if constexpr (BC == kBcPeriodic) {
+        // row w + 4 i of the block is y row w + 4 (i & 1) of x plane i / 2: the x
+        // wrap is uniform, the y and z wraps are two and one per thread
+        const unsigned un = (unsigned)n, zw = (unsigned)wrap(z0 - 2 + lane, n);
+        const unsigned yw[2] = {(unsigned)wrap(y0 + w - 2, n), (unsigned)wrap(y0 + w + 2, n)};
 #pragma unroll
-    for (int i = 0; i < RPW; i++) v[i] = fetch(w + i * kTY, lane);
+        for (int i = 0; i < RPW; i++)
+            v[i] = elt(A.a, ((unsigned)wrap(x0 + i / 2 - 2, n) * un + yw[i & 1]) * un + zw);
+    } else {
+#pragma unroll
+        for (int i = 0; i < RPW; i++) v[i] = fetch(w + i * kTY, lane);
+    }
     const int erow = tid >> 2, ez = kRZ + (tid & 3);
     T e = T(0);
     if (tid < 4 * NROW) e = fetch(erow, ez);

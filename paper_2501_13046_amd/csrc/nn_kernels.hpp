@@ -12,6 +12,7 @@
 // 4*(l/16) .. 4*(l/16)+3 of column l%16 of the 16x16 result.
 #pragma once
 
+#include <utility>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -23,6 +24,17 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint16_t u16;
 
 constexpr int kNBlock = 256; // threads per block (4 waves)
+
+template <int... I, typename Fn>
+__device__ __forceinline__ void static_for_impl(std::integer_sequence<int, I...>, Fn &&f)
+{
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename Fn>
+__device__ __forceinline__ void static_for(Fn &&f)
+{
+    static_for_impl(std::make_integer_sequence<int, N>{}, f);
+}
 constexpr int kRows = 4;     // 16-cell M tiles per wave in the convolution
 
 // ---- BF16 helpers -------------------------------------------------------------------
@@ -41,7 +53,9 @@ __device__ __forceinline__ uint32_t f2bf(float f)
 }
 __device__ __forceinline__ uint32_t pack2(float lo, float hi) { return f2bf(lo) | (f2bf(hi) << 16); }
 
-__device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + __expf(-z)); }
+// logistic function with the hardware reciprocal (about 1 ulp; the results are
+// rounded to BF16)
+__device__ __forceinline__ float sigm(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 __device__ __forceinline__ float silu(float z) { return z * sigm(z); }
 __device__ __forceinline__ float dsilu(float z)
 {
@@ -290,6 +304,36 @@ __device__ __forceinline__ void conv_store8(const ConvArgs &a, int co0, int64_t 
     }
 }
 
+// Halo element (16-byte units) of K octet o of a slice of P octets per tap,
+// relative to the lane's element ((wave kHY + q) kHZ + r) P; octets past the 27
+// taps point at element 0 (their operands are zeroed).
+template <int P>
+struct TapOffsets {
+    static constexpr int kSteps = (27 * P + 3) / 4;
+    int v[kSteps * 4];
+    constexpr TapOffsets() : v()
+    {
+        for (int o = 0; o < kSteps * 4; o++) {
+            const int oo = o < 27 * P ? o : 0;
+            const int tap = oo / P, o8 = oo % P;
+            v[o] = (((tap / 9) * kHY + (tap / 3) % 3) * kHZ + tap % 3) * P + o8;
+        }
+    }
+};
+
+// Offset of K step ST for lane group g (octet 4 ST + g).
+template <int P, int ST>
+__device__ __forceinline__ int tap_offset(int g)
+{
+    constexpr TapOffsets<P> T{};
+    if constexpr (P == 4)
+        return T.v[4 * ST] + g; // one tap per step, the lane group picks the octet
+    else if constexpr (P == 2)
+        return ((g & 2) ? T.v[4 * ST + 2] : T.v[4 * ST]) + (g & 1);
+    else
+        return g == 0 ? T.v[4 * ST] : g == 1 ? T.v[4 * ST + 1] : g == 2 ? T.v[4 * ST + 2] : T.v[4 * ST + 3];
+}
+
 template <int NTB, int CS>
 __global__ void __launch_bounds__(kNBlock) k_conv3_brick(ConvArgs a)
 {
@@ -317,7 +361,8 @@ __global__ void __launch_bounds__(kNBlock) k_conv3_brick(ConvArgs a)
         for (int t = 0; t < NTB; t++) acc[q][t] = f32x4{0.f, 0.f, 0.f, 0.f};
     const u32x4 zero = {0u, 0u, 0u, 0u};
     const int nslice = (a.c1 + a.c2) / CS;
-    const int spp = a.ko.spp;
+    constexpr int spp = TapOffsets<P>::kSteps; // K steps per slice (the packed order's spp)
+    const int lbase = ((wave * kHY) * kHZ + r) * P;
     auto wload = [&](int ch, u32x4 (&bw)[NTB]) {
 #pragma unroll
         for (int t = 0; t < NTB; t++)
@@ -341,8 +386,8 @@ __global__ void __launch_bounds__(kNBlock) k_conv3_brick(ConvArgs a)
                 stg[k] = *(const u32x4 *)(src + (((int64_t)gx * n + gy) * n + gz) * cs + c0 + o * 8);
             }
         }
-        u32x4 bw[NTB];
-        wload(sl * spp, bw);
+        u32x4 bw[2][NTB]; // weights of the current and the next K step
+        wload(sl * spp, bw[0]);
         __syncthreads(); // previous slice consumed
 #pragma unroll
         for (int k = 0; k < NE; k++) {
@@ -350,30 +395,26 @@ __global__ void __launch_bounds__(kNBlock) k_conv3_brick(ConvArgs a)
             if (e < kTile) smem[e] = stg[k];
         }
         __syncthreads();
-        for (int st = 0; st < spp; st++) {
-            const int ch = sl * spp + st;
-            u32x4 bn[NTB];
-            if (st + 1 < spp) wload(ch + 1, bn);
-            const int o = st * 4 + g;
+        // K steps unrolled: the halo offsets of the taps are compile-time constants
+        // (one select by lane group per step), weights prefetched one step ahead
+        static_for<spp>([&](auto stc) {
+            constexpr int st = decltype(stc)::value;
+            if constexpr (st + 1 < spp) wload(sl * spp + st + 1, bw[(st + 1) & 1]);
+            const u32x4 *ap = smem + lbase + tap_offset<P, st>(g);
             u32x4 av[4];
-            if (o < 27 * P) {
-                const int tap = o / P, o8 = o - tap * P;
-                const int hx = wave + tap / 9, hy0 = (tap / 3) % 3, hz = r + tap % 3;
 #pragma unroll
-                for (int q = 0; q < 4; q++) av[q] = smem[((hx * kHY + hy0 + q) * kHZ + hz) * P + o8];
-            } else {
+            for (int q = 0; q < 4; q++) av[q] = ap[q * kHZ * P];
+            if constexpr (4 * st + 3 >= 27 * P) { // last step: octets past the 27 taps
+                if (4 * st + g >= 27 * P) {
 #pragma unroll
-                for (int q = 0; q < 4; q++) av[q] = zero;
+                    for (int q = 0; q < 4; q++) av[q] = zero;
+                }
             }
 #pragma unroll
             for (int q = 0; q < 4; q++)
 #pragma unroll
-                for (int t = 0; t < NTB; t++) acc[q][t] = mfma(av[q], bw[t], acc[q][t]);
-            if (st + 1 < spp) {
-#pragma unroll
-                for (int t = 0; t < NTB; t++) bw[t] = bn[t];
-            }
-        }
+                for (int t = 0; t < NTB; t++) acc[q][t] = mfma(av[q], bw[st & 1][t], acc[q][t]);
+        });
     }
     // epilogue through LDS: every thread then writes whole channel octets
     float *os = (float *)smem;
