@@ -72,6 +72,9 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain device copy of 256 MiB (the reference dispatch that scales "
                          "the FETCH_SIZE / WRITE_SIZE counters of a profiling run)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON file of brick depths: apply the stored choice for this configuration, or tune "
+                         "and store it (a profiling run can replay the choice of an unprofiled one)")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2501_13046_amd", "weights", "warmstart_128.npz"),
                     help="trained warm-start network (python -m paper_2501_13046_amd.warmstart)")
     args = ap.parse_args()
@@ -106,10 +109,13 @@ def main():
     u = torch.zeros((n,) * 3, dtype=torch.float64, device=dev)
     W = torch.zeros((3, n, n, n), dtype=torch.float64, device=dev)
     # brick depths of the tiled kernels, autotuned on this workload (off the clock)
-    tuning = mixed.autotune(u, W, reps=20)
+    if args.tune_cache:
+        tuning = g.autotune_cached(mixed, u, W, path=args.tune_cache, reps=20)
+    else:
+        tuning = mixed.autotune(u, W, reps=20)
     for e in tuning:
         log(f"[bench] autotune family {e['family']} level {e['level']}: chosen {e['chosen']} "
-            + " ".join(f"{k}:{v:.2f}us" for k, v in e["candidates"].items()))
+            + " ".join(f"{k}:{v:.2f}us" for k, v in e.get("candidates", {}).items()))
 
     def step(solver):
         u.zero_()

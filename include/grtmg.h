@@ -79,7 +79,8 @@ enum { MG_FLAG_CONFORMAL_MATTER = 1, MG_FLAG_EAGER = 2 };
  *                 interior (smoothers, transfers, defects) in FP32 inside FP64
  *                 iterative refinement; residual, update and coarsest solve FP64.
  *  nu_pre/nu_post red-black sweeps before/after the coarse correction (>= 1).
- *  solve_momentum 0: W frozen at the caller's values; 1: coupled solve.
+ *  solve_momentum 0: W frozen at the caller's values; 1: coupled solve
+ *                 (n^3 * 8 bytes below 4 GiB, i.e. n <= 812).
  *  flags          bit MG_FLAG_CONFORMAL_MATTER: the matter arrays are the
  *                 conformally rescaled free data rho_bar = psi^8 rho (taken as
  *                 rho5 + rho1) and S_bar = psi^6 S; H_h then carries

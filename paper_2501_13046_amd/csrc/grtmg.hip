@@ -127,6 +127,9 @@ mg_status validate(const mg_params *p)
         return MG_ERR_INVALID;
     if (p->solve_momentum != 0 && p->solve_momentum != 1) return MG_ERR_INVALID;
     if (p->solve_momentum && p->bc != MG_BC_PERIODIC) return MG_ERR_INVALID;
+    // the W kernels address one component with 32-bit byte offsets
+    if (p->solve_momentum && (double)p->n * p->n * (double)p->n * sizeof(double) >= 4294967296.0)
+        return MG_ERR_INVALID;
     if ((p->flags & ~(MG_FLAG_CONFORMAL_MATTER | MG_FLAG_EAGER)) != 0) return MG_ERR_INVALID;
     if (!(p->length > 0.0) || !std::isfinite(p->length)) return MG_ERR_INVALID;
     if (!std::isfinite(p->K) || !(p->puncture_mass >= 0.0) || !std::isfinite(p->puncture_mass))
@@ -359,7 +362,10 @@ void pass_psi(mg_ctx *c, int l, const T *in, T *out, int colour)
             launch_psi_tiled<kBcRobin, T>(c->s, g, tm, in, out, r, cf, colour);
         return;
     }
-    if (c->p.bc == MG_BC_PERIODIC)
+    if (c->p.bc == MG_BC_PERIODIC && c->n[l] % 2 == 0)
+        hipLaunchKernelGGL(k_pass_psi_pairs<T>, dim3(nblk(c->cells[l] / 2)), dim3(kBlock), 0, c->s, g, in, out,
+                           (const T *)c->pr[l], (const T *)c->pc[l], colour);
+    else if (c->p.bc == MG_BC_PERIODIC)
         hipLaunchKernelGGL((k_pass_psi<kBcPeriodic, T>), dim3(nb), dim3(kBlock), 0, c->s, g, in, out,
                            (const T *)c->pr[l], (const T *)c->pc[l], colour);
     else
@@ -409,7 +415,7 @@ void defect_restrict_W(mg_ctx *c, int l, const T *d, const T *r, T *rc)
         hipLaunchKernelGGL((k_defect_restrict_W_march<T, 8>), dim3(ntiles(tm)), dim3(kLanes, kTY), 0, c->s,
                            c->geo[l], tm, d, r, rc);
     else if (fine_threads(c->n[l]))
-        hipLaunchKernelGGL(k_defect_restrict_W_fine<T>, dim3(nblk(8 * c->cells[l + 1])), dim3(kBlock), 0, c->s,
+        hipLaunchKernelGGL(k_defect_restrict_W_quad<T>, dim3(nblk(32 * c->cells[l + 1])), dim3(kBlock), 0, c->s,
                            c->geo[l], d, r, rc);
     else
         hipLaunchKernelGGL(k_defect_restrict_W<T>, dim3(nblk(c->cells[l + 1])), dim3(kBlock), 0, c->s, c->geo[l], d,
@@ -552,6 +558,9 @@ void pass_W(mg_ctx *c, int l, const T *in, T *out, const T *r, int colour)
     const TileMap &tm = c->tileW[l];
     if (tm.tx > 0)
         launch_W_tiled<T>(c->s, c->geo[l], tm, in, out, r, colour);
+    else if (c->n[l] % 2 == 0 && c->n[l] <= 32)
+        hipLaunchKernelGGL(k_pass_W_quad<T>, dim3(nblk(2 * c->cells[l])), dim3(kBlock), 0, c->s, c->geo[l], in,
+                           out, r, colour);
     else
         hipLaunchKernelGGL(k_pass_W<T>, dim3(nblk(c->cells[l])), dim3(kBlock), 0, c->s, c->geo[l], in, out, r,
                            colour);

@@ -11,6 +11,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+#include <utility>
+
 namespace grtmg {
 
 constexpr int kBlock = 256;
@@ -230,5 +233,184 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[NV], unsigned max
         }
     }
 }
+
+// Element i of an array addressed by a 32-bit byte offset from its (uniform)
+// base: one address register per access instead of a 64-bit sum.
+template <typename P>
+__device__ __forceinline__ P &elt(P *base, unsigned i)
+{
+    return *reinterpret_cast<P *>(reinterpret_cast<char *>(const_cast<std::remove_const_t<P> *>(base)) +
+                                  i * (unsigned)sizeof(P));
+}
+
+template <int... I, typename Fn>
+__device__ __forceinline__ void static_for_impl(std::integer_sequence<int, I...>, Fn &&f)
+{
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename Fn>
+__device__ __forceinline__ void static_for(Fn &&f)
+{
+    static_for_impl(std::make_integer_sequence<int, N>{}, f);
+}
+
+// The taps of one cell read into registers first, then evaluated.  For LDS
+// sources (ORDER) each read is followed by a compiler-only ordering point: the
+// taps stay single ds_read_b32 with an immediate offset (instead of being
+// paired into ds_read2_b32, whose 8-bit offsets need a fresh base address per
+// pair of these taps), and all of them are in flight before the arithmetic.
+template <typename T, bool ORDER = true>
+struct RegTaps {
+    T v[5][5][5]; // (DX + 2, DY + 2, DZ + 2); only the entries read are kept
+    template <int DX, int DY, int DZ>
+    __device__ __forceinline__ T at() const
+    {
+        return v[DX + 2][DY + 2][DZ + 2];
+    }
+    template <int DX, int DY, int DZ, typename Src>
+    __device__ __forceinline__ void get(const Src &S)
+    {
+        v[DX + 2][DY + 2][DZ + 2] = S.template at<DX, DY, DZ>();
+        if constexpr (ORDER) asm volatile("" ::: "memory");
+    }
+    // centre, D_xx, D_yy, D_zz taps
+    template <typename Src>
+    __device__ __forceinline__ void get_lap(const Src &S)
+    {
+        get<0, 0, 0>(S);
+        get<-1, 0, 0>(S), get<1, 0, 0>(S), get<-2, 0, 0>(S), get<2, 0, 0>(S);
+        get<0, -1, 0>(S), get<0, 1, 0>(S), get<0, -2, 0>(S), get<0, 2, 0>(S);
+        get<0, 0, -1>(S), get<0, 0, 1>(S), get<0, 0, -2>(S), get<0, 0, 2>(S);
+    }
+    // the 16 off-axis taps of D_ab in the plane of axes A < B (0 = x, 1 = y, 2 = z)
+    template <int A, int B, typename Src>
+    __device__ __forceinline__ void get_mixed(const Src &S)
+    {
+        static_for<4>([&](auto i) {
+            constexpr int da = (decltype(i)::value & 1 ? 1 : -1) * (decltype(i)::value < 2 ? 1 : 2);
+            static_for<4>([&](auto j) {
+                constexpr int db = (decltype(j)::value & 1 ? 1 : -1) * (decltype(j)::value < 2 ? 1 : 2);
+                constexpr int dx = A == 0 ? da : 0;
+                constexpr int dy = A == 1 ? da : (B == 1 ? db : 0);
+                constexpr int dz = B == 2 ? db : 0;
+                get<dx, dy, dz>(S);
+            });
+        });
+    }
+    __device__ __forceinline__ T c() const { return at<0, 0, 0>(); }
+    __device__ __forceinline__ T dxx(T c) const
+    {
+        return T(16) * (at<-1, 0, 0>() + at<1, 0, 0>()) - (at<-2, 0, 0>() + at<2, 0, 0>()) - T(30) * c;
+    }
+    __device__ __forceinline__ T dyy(T c) const
+    {
+        return T(16) * (at<0, -1, 0>() + at<0, 1, 0>()) - (at<0, -2, 0>() + at<0, 2, 0>()) - T(30) * c;
+    }
+    __device__ __forceinline__ T dzz(T c) const
+    {
+        return T(16) * (at<0, 0, -1>() + at<0, 0, 1>()) - (at<0, 0, -2>() + at<0, 0, 2>()) - T(30) * c;
+    }
+    template <int DX, int DZ>
+    __device__ __forceinline__ T dy_at() const
+    {
+        return (at<DX, -2, DZ>() - at<DX, 2, DZ>()) + T(8) * (at<DX, 1, DZ>() - at<DX, -1, DZ>());
+    }
+    template <int DX, int DY>
+    __device__ __forceinline__ T dz_at() const
+    {
+        return (at<DX, DY, -2>() - at<DX, DY, 2>()) + T(8) * (at<DX, DY, 1>() - at<DX, DY, -1>());
+    }
+    __device__ __forceinline__ T dxy() const
+    {
+        return (dy_at<-2, 0>() - dy_at<2, 0>()) + T(8) * (dy_at<1, 0>() - dy_at<-1, 0>());
+    }
+    __device__ __forceinline__ T dxz() const
+    {
+        return (dz_at<-2, 0>() - dz_at<2, 0>()) + T(8) * (dz_at<1, 0>() - dz_at<-1, 0>());
+    }
+    __device__ __forceinline__ T dyz() const
+    {
+        return (dz_at<0, -2>() - dz_at<0, 2>()) + T(8) * (dz_at<0, 1>() - dz_at<0, -1>());
+    }
+    // first derivatives at the centre (times 12 h)
+    __device__ __forceinline__ T dx() const
+    {
+        return (at<-2, 0, 0>() - at<2, 0, 0>()) + T(8) * (at<1, 0, 0>() - at<-1, 0, 0>());
+    }
+    __device__ __forceinline__ T dy() const { return dy_at<0, 0>(); }
+    __device__ __forceinline__ T dz() const { return dz_at<0, 0>(); }
+};
+
+template <typename T>
+struct WPart {
+    T lap[3], dd[3], mix[3], c[3];
+};
+
+// Contributions of field F at one cell whose taps the source S reads (S.at<DX, DY, DZ>
+// relative to the cell); returns the value of the other member of the z pair.
+template <typename T, int F, int PAR, typename Src>
+__device__ __forceinline__ T W_field_parts(const Src &S, T h2, WPart<T> &P)
+{
+    RegTaps<T, Src::kOrdered> D;
+    D.get_lap(S);
+    if constexpr (F == 0) {
+        D.template get_mixed<0, 1>(S);
+        D.template get_mixed<0, 2>(S);
+    } else if constexpr (F == 1) {
+        D.template get_mixed<0, 1>(S);
+        D.template get_mixed<1, 2>(S);
+    } else {
+        D.template get_mixed<0, 2>(S);
+        D.template get_mixed<1, 2>(S);
+    }
+    const T c = D.c();
+    const T xx = D.dxx(c), yy = D.dyy(c), zz = D.dzz(c);
+    P.c[F] = c;
+    P.lap[F] = (xx + yy + zz) * h2;
+    if constexpr (F == 0) {
+        P.dd[0] = xx * h2;
+        P.mix[1] = D.dxy();
+        P.mix[2] = D.dxz();
+    } else if constexpr (F == 1) {
+        P.dd[1] = yy * h2;
+        P.mix[0] = D.dxy();
+        P.mix[2] = P.mix[2] + D.dyz();
+    } else {
+        P.dd[2] = zz * h2;
+        P.mix[0] = P.mix[0] + D.dxz();
+        P.mix[1] = P.mix[1] + D.dyz();
+    }
+    constexpr int DZ = PAR ? -1 : 1;
+    return D.template at<0, 0, DZ>();
+}
+
+
+// Taps of a periodic field around cell (i, j, k) from wrapped plane, row and
+// column offsets computed once per cell: two integer adds per tap.
+struct WrapOff {
+    unsigned x[5], y[5], z[5];
+    __device__ __forceinline__ WrapOff(int n, int i, int j, int k)
+    {
+        const unsigned un = (unsigned)n;
+#pragma unroll
+        for (int d = -2; d <= 2; d++) {
+            x[d + 2] = (unsigned)wrap(i + d, n) * un * un;
+            y[d + 2] = (unsigned)wrap(j + d, n) * un;
+            z[d + 2] = (unsigned)wrap(k + d, n);
+        }
+    }
+};
+
+template <typename T>
+struct WrapTaps {
+    static constexpr bool kOrdered = false;
+    const T *a;
+    const WrapOff &o;
+    template <int DX, int DY, int DZ>
+    __device__ __forceinline__ T at() const
+    {
+        return elt(a, o.x[DX + 2] + o.y[DY + 2] + o.z[DZ + 2]);
+    }
+};
 
 } // namespace grtmg

@@ -251,26 +251,26 @@ __global__ void __launch_bounds__(kBlock) k_pass_psi(Geo g, const T *__restrict_
     psi_pass_cell<BC, T>(g, in, out, r, c, colour, tid, i, j, k);
 }
 
-// (Delta_L d)_a at a cell for the three components (periodic).
+// (Delta_L d)_a at a cell for the three components (periodic), from taps at
+// wrapped offsets computed once per cell.
+template <typename T>
+__device__ __forceinline__ void deltaL_at(const Geo &g, const T *d, unsigned m, const WrapOff &o, T out[3])
+{
+    const T h2 = (T)g.inv12h2, m2 = (T)g.inv144h2, third = T(1) / T(3);
+    WPart<T> P;
+    W_field_parts<T, 0, 0>(WrapTaps<T>{d, o}, h2, P);
+    W_field_parts<T, 1, 0>(WrapTaps<T>{d + m, o}, h2, P);
+    W_field_parts<T, 2, 0>(WrapTaps<T>{d + 2 * (size_t)m, o}, h2, P);
+#pragma unroll
+    for (int f = 0; f < 3; f++) out[f] = P.lap[f] + (P.dd[f] + P.mix[f] * m2) * third;
+}
+
 template <typename T>
 __device__ __forceinline__ void deltaL_apply(const Geo &g, const T *d, int64_t m, int i, int j,
                                              int k, int64_t q, T out[3])
 {
-    Acc<kBcPeriodic, T> D0{d, g}, D1{d + m, g}, D2{d + 2 * m, g};
-    const T c0 = d[q], c1 = d[m + q], c2 = d[2 * m + q];
-    const T xx0 = d2_sum<0, T>(D0, i, j, k, c0);
-    const T xx1 = d2_sum<1, T>(D1, i, j, k, c1);
-    const T xx2 = d2_sum<2, T>(D2, i, j, k, c2);
-    const T h2 = (T)g.inv12h2, m2 = (T)g.inv144h2, third = T(1) / T(3);
-    const T l0 = (xx0 + d2_sum<1, T>(D0, i, j, k, c0) + d2_sum<2, T>(D0, i, j, k, c0)) * h2;
-    const T l1 = (d2_sum<0, T>(D1, i, j, k, c1) + xx1 + d2_sum<2, T>(D1, i, j, k, c1)) * h2;
-    const T l2 = (d2_sum<0, T>(D2, i, j, k, c2) + d2_sum<1, T>(D2, i, j, k, c2) + xx2) * h2;
-    const T t0 = xx0 * h2 + (dmix_sum<0, 1, T>(D1, i, j, k) + dmix_sum<0, 2, T>(D2, i, j, k)) * m2;
-    const T t1 = xx1 * h2 + (dmix_sum<1, 0, T>(D0, i, j, k) + dmix_sum<1, 2, T>(D2, i, j, k)) * m2;
-    const T t2 = xx2 * h2 + (dmix_sum<2, 0, T>(D0, i, j, k) + dmix_sum<2, 1, T>(D1, i, j, k)) * m2;
-    out[0] = l0 + t0 * third;
-    out[1] = l1 + t1 * third;
-    out[2] = l2 + t2 * third;
+    (void)q;
+    deltaL_at<T>(g, d, (unsigned)m, WrapOff(g.n, i, j, k), out);
 }
 
 // One colour pass of the W smoother at cell q (periodic, double-buffered).
@@ -293,6 +293,165 @@ __device__ __forceinline__ void W_pass_cell(const Geo &g, const T *__restrict__ 
     const T diag = (T)(-100.0 * g.inv12h2);
 #pragma unroll
     for (int s = 0; s < 3; s++) out[s * m + q] = in[s * m + q] + (r[s * m + q] - Ad[s]) / diag;
+}
+
+// Colour passes on levels without bricks (periodic): thread p owns the z pair
+// (2 kp, 2 kp + 1) of row (i, j), updates the member of the active colour and
+// copies the other (no idle lanes on the checkerboard).
+__device__ __forceinline__ bool pair_of(unsigned p, int n, int colour, int &i, int &j, int &ka, int &kb)
+{
+    const unsigned np = (unsigned)n >> 1;
+    if (p >= (unsigned)n * (unsigned)n * np) return false;
+    const unsigned kp = p % np, rest = p / np;
+    j = (int)(rest % (unsigned)n);
+    i = (int)(rest / (unsigned)n);
+    const int par = (colour + i + j) & 1;
+    ka = 2 * (int)kp + par;
+    kb = 2 * (int)kp + (par ^ 1);
+    return true;
+}
+
+// W colour pass with four lanes per z pair: lane f < 3 evaluates the taps of
+// component f (its Laplacian and second derivative, and its two mixed
+// derivatives, which belong to the other two rows of Delta_L), so each lane
+// issues 45 loads instead of 135 and all loads of a lane are in flight at once.
+// The planes of the mixed derivatives are chosen per lane through offset
+// tables, so the lanes run one instruction stream; the cross terms reach
+// their rows through a butterfly over the four lanes (lane 3 contributes
+// zeros), which adds them in the order of the single-lane evaluation.
+// Row f of (Delta_L d) at cell (i, j, k) evaluated by the four lanes of a quad
+// (lane f = t & 3 < 3 holds row f on return; lane 3 takes part in the
+// exchange only).  *c receives component f of d at the cell.
+template <typename T>
+__device__ __forceinline__ T quad_deltaL_row(const Geo &g, const T *__restrict__ d, unsigned m, int f,
+                                             const WrapOff &o, T *c)
+{
+    const int fc = f < 3 ? f : 2;
+    const T *a = d + (size_t)fc * m;
+    // plane 1 of the mixed derivatives: xy (f = 0, 1) or xz (f = 2); plane 2: xz (f = 0) or yz (f = 1, 2)
+    unsigned b1[5], a2[5];
+#pragma unroll
+    for (int q = 0; q < 5; q++) {
+        b1[q] = fc == 2 ? o.y[2] + o.z[q] : o.y[q] + o.z[2];
+        a2[q] = fc == 0 ? o.x[q] + o.y[2] : o.x[2] + o.y[q];
+    }
+    auto tap = [&](unsigned off) { return elt(a, off); };
+    const T cv = tap(o.x[2] + o.y[2] + o.z[2]);
+    auto d2 = [&](T m2v, T p2v, T m1v, T p1v) { return T(16) * (m1v + p1v) - (m2v + p2v) - T(30) * cv; };
+    const T xx = d2(tap(o.x[0] + o.y[2] + o.z[2]), tap(o.x[4] + o.y[2] + o.z[2]), tap(o.x[1] + o.y[2] + o.z[2]),
+                    tap(o.x[3] + o.y[2] + o.z[2]));
+    const T yy = d2(tap(o.x[2] + o.y[0] + o.z[2]), tap(o.x[2] + o.y[4] + o.z[2]), tap(o.x[2] + o.y[1] + o.z[2]),
+                    tap(o.x[2] + o.y[3] + o.z[2]));
+    const T zz = d2(tap(o.x[2] + o.y[2] + o.z[0]), tap(o.x[2] + o.y[2] + o.z[4]), tap(o.x[2] + o.y[2] + o.z[1]),
+                    tap(o.x[2] + o.y[2] + o.z[3]));
+    // D_A D_B: first-derivative weights along B inside, along A outside
+    auto dB1 = [&](int da) {
+        const unsigned xa = o.x[da];
+        return (tap(xa + b1[0]) - tap(xa + b1[4])) + T(8) * (tap(xa + b1[3]) - tap(xa + b1[1]));
+    };
+    auto dB2 = [&](int da) {
+        const unsigned aa = a2[da];
+        return (tap(aa + o.z[0]) - tap(aa + o.z[4])) + T(8) * (tap(aa + o.z[3]) - tap(aa + o.z[1]));
+    };
+    const T mixA = (dB1(0) - dB1(4)) + T(8) * (dB1(3) - dB1(1));
+    const T mixB = (dB2(0) - dB2(4)) + T(8) * (dB2(3) - dB2(1));
+    const T h2 = (T)g.inv12h2, m2 = (T)g.inv144h2, third = T(1) / T(3);
+    const T lap = (xx + yy + zz) * h2;
+    const T dd = (fc == 0 ? xx : fc == 1 ? yy : zz) * h2;
+    // cross terms by target row: field 0 -> rows 1 (xy), 2 (xz); field 1 -> rows 0 (xy), 2 (yz);
+    // field 2 -> rows 0 (xz), 1 (yz)
+    T mt[3];
+    mt[0] = f == 1 || f == 2 ? mixA : T(0);
+    mt[1] = f == 0 ? mixA : (f == 2 ? mixB : T(0));
+    mt[2] = f == 0 ? mixB : (f == 1 ? mixB : T(0));
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+        mt[q] += __shfl_xor(mt[q], 1, kWave);
+        mt[q] += __shfl_xor(mt[q], 2, kWave);
+    }
+    const T mix = f == 0 ? mt[0] : (f == 1 ? mt[1] : mt[2]);
+    *c = cv;
+    return lap + (dd + mix * m2) * third;
+}
+
+// W colour pass with four lanes per z pair (levels of at most 32^3 cells, where
+// a pass is bound by rounds of memory latency): lane f < 3 evaluates the taps
+// of component f (its Laplacian and second derivative, and its two mixed
+// derivatives, which belong to the other two rows of Delta_L), so each lane
+// issues 45 loads instead of 135 and all of them are in flight at once.  The
+// planes of the mixed derivatives are chosen per lane through offset tables,
+// so the lanes run one instruction stream; the cross terms reach their rows
+// through a butterfly over the four lanes (lane 3 contributes zeros), which
+// adds them in the order of the single-lane evaluation.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_pass_W_quad(Geo g, const T *__restrict__ in, T *__restrict__ out,
+                                                        const T *__restrict__ r, int colour)
+{
+    const int n = g.n;
+    const unsigned t = blockIdx.x * kBlock + threadIdx.x;
+    const int f = (int)(t & 3u);
+    int i, j, ka, kb;
+    const bool live = pair_of(t >> 2, n, colour, i, j, ka, kb);
+    if (!live) { // whole quads are live or not; dead ones read cell 0 and store nothing
+        i = j = ka = 0;
+        kb = 1;
+    }
+    const unsigned m = (unsigned)n * n * n, row = ((unsigned)i * n + (unsigned)j) * (unsigned)n;
+    const unsigned qa = row + (unsigned)ka, qb = row + (unsigned)kb;
+    T c;
+    const T Ad = quad_deltaL_row<T>(g, in, m, f, WrapOff(n, i, j, ka), &c);
+    if (!live || f == 3) return;
+    const T *inf = in + (size_t)f * m, *rf = r + (size_t)f * m;
+    T *of = out + (size_t)f * m;
+    elt(of, qb) = elt(inf, qb);
+    elt(of, qa) = c + (elt(rf, qa) - Ad) * (T)(1.0 / (-100.0 * g.inv12h2));
+}
+
+// W defect r - Delta_L d restricted to the next coarser level, four lanes per
+// fine cell and the 8 children of a coarse cell in 32 adjacent lanes: lane
+// 4 child + f; the child sum runs over lanes of the same f.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_defect_restrict_W_quad(Geo g, const T *__restrict__ d,
+                                                                   const T *__restrict__ r, T *__restrict__ rc_out)
+{
+    const int n = g.n, nc = n / 2;
+    const unsigned t = blockIdx.x * kBlock + threadIdx.x;
+    const int f = (int)(t & 3u), ch = (int)((t >> 2) & 7u);
+    const unsigned qc = t >> 5, mc = (unsigned)nc * nc * nc, m = (unsigned)n * n * n;
+    const bool live = qc < mc;
+    const unsigned qq = live ? qc : 0u;
+    const int K = (int)(qq % (unsigned)nc), J = (int)((qq / (unsigned)nc) % (unsigned)nc),
+              I = (int)(qq / ((unsigned)nc * nc));
+    const int i = 2 * I + (ch >> 2), j = 2 * J + ((ch >> 1) & 1), k = 2 * K + (ch & 1);
+    T c;
+    const T Ad = quad_deltaL_row<T>(g, d, m, f, WrapOff(n, i, j, k), &c);
+    const unsigned q = ((unsigned)i * n + (unsigned)j) * (unsigned)n + (unsigned)k;
+    const int fc = f < 3 ? f : 2;
+    T v = elt(r + (size_t)fc * m, q) - Ad;
+    v += __shfl_xor(v, 4, kWave);
+    v += __shfl_xor(v, 8, kWave);
+    v += __shfl_xor(v, 16, kWave);
+    if (live && ch == 0 && f < 3) elt(rc_out + (size_t)f * mc, qc) = v * T(0.125);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_pass_psi_pairs(Geo g, const T *__restrict__ in, T *__restrict__ out,
+                                                           const T *__restrict__ r, const T *__restrict__ c,
+                                                           int colour)
+{
+    const int n = g.n;
+    int i, j, ka, kb;
+    if (!pair_of(blockIdx.x * kBlock + threadIdx.x, n, colour, i, j, ka, kb)) return;
+    const unsigned row = ((unsigned)i * n + (unsigned)j) * (unsigned)n;
+    const unsigned qa = row + (unsigned)ka, qb = row + (unsigned)kb;
+    const WrapOff o(n, i, j, ka);
+    RegTaps<T, false> D;
+    D.get_lap(WrapTaps<T>{in, o});
+    const T v = D.c(), cv = elt(c, qa);
+    const T Ad = (D.dxx(v) + D.dyy(v) + D.dzz(v)) * (T)g.inv12h2 + cv * v;
+    const T diag = (T)(-90.0 * g.inv12h2) + cv;
+    elt(out, qb) = elt(in, qb);
+    elt(out, qa) = v + (elt(r, qa) - Ad) / diag;
 }
 
 template <typename T>
@@ -494,14 +653,6 @@ __device__ __forceinline__ void defect_restrict_W_child(const Geo &g, const T *_
 #pragma unroll
         for (int a = 0; a < 3; a++) rc_out[a * mc + qc] = s[a] * T(0.125);
     }
-}
-
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_defect_restrict_W_fine(Geo g, const T *__restrict__ d,
-                                                                   const T *__restrict__ r,
-                                                                   T *__restrict__ rc_out)
-{
-    defect_restrict_W_child<T>(g, d, r, rc_out, (int64_t)blockIdx.x * kBlock + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------------------
