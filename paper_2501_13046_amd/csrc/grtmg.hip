@@ -63,6 +63,10 @@ constexpr int kProbeMax = 4096;
 // LDS (depth 2 uses 152 KB).
 constexpr int kBrickPsi = 4;
 constexpr int kBrickW = 2;
+// marched columns of 64-cell rows (levels whose side is a multiple of 64 but
+// not of 128): x planes per column of the W pass and of the W defect restriction
+constexpr int kMarch64Pass = 2;
+constexpr int kMarch64Defect = 2;
 constexpr int kBrickR = 2;
 constexpr int kCandPsi[] = {2, 4, 8};
 // W pass depths: 1, 2, 4 are bricks staged whole, 8 and 16 columns marched plane by plane
@@ -410,10 +414,15 @@ template <typename T>
 void defect_restrict_W(mg_ctx *c, int l, const T *d, const T *r, T *rc)
 {
     Probe pr(c, MG_PROBE_DEFECT_RESTRICT_W, l);
-    const TileMap tm = w_tileable(c->n[l]) ? make_tilemap<8>(c->n[l]) : TileMap{0, 0, 0, 0};
+    const int n = c->n[l];
+    const TileMap tm = w_tileable(n) ? make_marchmap<8, 128>(n) : TileMap{0, 0, 0, 0};
+    const TileMap tm64 = w_tileable(n) ? make_marchmap<kMarch64Defect, 64>(n) : TileMap{0, 0, 0, 0};
     if (tm.tx > 0)
-        hipLaunchKernelGGL((k_defect_restrict_W_march<T, 8>), dim3(ntiles(tm)), dim3(kLanes, kTY), 0, c->s,
+        hipLaunchKernelGGL((k_defect_restrict_W_march<T, 8, 128>), dim3(ntiles(tm)), dim3(kLanes, kTY), 0, c->s,
                            c->geo[l], tm, d, r, rc);
+    else if (tm64.tx > 0)
+        hipLaunchKernelGGL((k_defect_restrict_W_march<T, kMarch64Defect, 64>), dim3(ntiles(tm64)),
+                           dim3(kLanes, kTY), 0, c->s, c->geo[l], tm64, d, r, rc);
     else if (fine_threads(c->n[l]))
         hipLaunchKernelGGL(k_defect_restrict_W_quad<T>, dim3(nblk(32 * c->cells[l + 1])), dim3(kBlock), 0, c->s,
                            c->geo[l], d, r, rc);
@@ -539,9 +548,9 @@ void launch_W_tiled(hipStream_t s, const Geo &g, const TileMap &tm, const T *in,
 {
     const dim3 blk(kLanes, kTY), grid(ntiles(tm));
     if (tm.tx == 8)
-        hipLaunchKernelGGL((k_pass_W_march<T, 8>), grid, blk, 0, s, g, tm, in, out, r, colour);
+        hipLaunchKernelGGL((k_pass_W_march<T, 8, 128>), grid, blk, 0, s, g, tm, in, out, r, colour);
     else if (tm.tx == 16)
-        hipLaunchKernelGGL((k_pass_W_march<T, 16>), grid, blk, 0, s, g, tm, in, out, r, colour);
+        hipLaunchKernelGGL((k_pass_W_march<T, 16, 128>), grid, blk, 0, s, g, tm, in, out, r, colour);
     else if (tm.tx == 1)
         hipLaunchKernelGGL((k_pass_W_tiled<T, 1>), grid, blk, 0, s, g, tm, in, out, r, colour);
     else if (tm.tx == 4 && sizeof(T) == 4)
@@ -556,8 +565,13 @@ void pass_W(mg_ctx *c, int l, const T *in, T *out, const T *r, int colour)
 {
     Probe pr(c, MG_PROBE_PASS_W, l);
     const TileMap &tm = c->tileW[l];
+    const TileMap tm64 =
+        tm.tx == 0 && w_tileable(c->n[l]) ? make_marchmap<kMarch64Pass, 64>(c->n[l]) : TileMap{0, 0, 0, 0};
     if (tm.tx > 0)
         launch_W_tiled<T>(c->s, c->geo[l], tm, in, out, r, colour);
+    else if (tm64.tx > 0)
+        hipLaunchKernelGGL((k_pass_W_march<T, kMarch64Pass, 64>), dim3(ntiles(tm64)), dim3(kLanes, kTY), 0, c->s,
+                           c->geo[l], tm64, in, out, r, colour);
     else if (c->n[l] % 2 == 0 && c->n[l] <= 32)
         hipLaunchKernelGGL(k_pass_W_quad<T>, dim3(nblk(2 * c->cells[l])), dim3(kBlock), 0, c->s, c->geo[l], in,
                            out, r, colour);

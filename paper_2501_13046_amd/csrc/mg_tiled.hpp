@@ -425,74 +425,112 @@ __global__ void __launch_bounds__(kTY *kLanes) k_pass_W_tiled(Geo g, TileMap tm,
 }
 
 // ---------------------------------------------------------------------------------------
-// W smoother colour pass marching along x.  A workgroup owns a column of 4 (y)
-// x 128 (z) cells and LX consecutive x planes.  The three components of each
-// staged x plane (rows y0 - 2 .. y0 + 5, z0 - 2 .. z0 + 129, same pair layout as
-// the bricks) live in a ring of six LDS slots: while the lanes evaluate plane x
-// from the slots of x - 2 .. x + 2, the registers hold plane x + 4 in flight
-// from HBM and plane x + 3 is written into the slot that plane x - 3 vacated,
-// so global loads, LDS traffic and arithmetic overlap for the whole column and
-// each staged plane is loaded once per column (x halo amortised over LX).
+// W smoother colour pass marching along x.  A workgroup owns a column of TYB (y)
+// x BZ (z) cells and LX consecutive x planes (BZ = 128: one brick row per wave,
+// 4 rows; BZ = 64: two rows per wave, 32 lanes each, 8 rows).  The three
+// components of each staged x plane (rows y0 - 2 .. y0 + TYB + 1, z0 - 2 ..
+// z0 + BZ + 1, the pair layout of the bricks) live in a ring of six LDS
+// slots: while the lanes evaluate plane x from the slots of x - 2 .. x + 2,
+// the registers hold plane x + 4 in flight from HBM and plane x + 3 is
+// written into the slot that plane x - 3 vacated, so global loads, LDS
+// traffic and arithmetic overlap for the whole column and each staged plane
+// is loaded once per column (x halo amortised over LX).
 // ---------------------------------------------------------------------------------------
 constexpr int kRing = 6;
 
-// One staged x plane of the three components (24 rows of 66 pairs): wave w
-// moves the 64 lane pairs of rows w, w + 4, ..., threads tid < 48 the two
-// remaining pairs of row tid / 2.
-template <typename T>
+template <int BZ>
+struct ZGeom {
+    static_assert(BZ == 128 || BZ == 64, "brick rows of 128 or 64 cells");
+    static constexpr int kRPW = 128 / BZ;       // brick rows per wave
+    static constexpr int kLPR = BZ / 2;         // lanes (z pairs) per row
+    static constexpr int kTYB = kTY * kRPW;     // brick rows (y) per workgroup
+    static constexpr int kPYB = kTYB + 4;       // staged rows per component
+    static constexpr int kPZB = BZ + 4;         // staged words per row
+    static constexpr int kHalfB = kPZB / 2;     // odd z start here
+    static constexpr int kPlaneB = kPYB * kPZB; // one component of a staged plane
+    static constexpr int kNR = 3 * kPYB;        // staged rows of a plane
+    // LDS word of staged z index (2 p + PAR + 2 + DZ) relative to word p of a row
+    template <int PAR, int DZ>
+    static constexpr int zoff()
+    {
+        return ((PAR + DZ) & 1) * kHalfB + ((PAR + 2 + DZ) >> 1);
+    }
+    __device__ static int row() { return threadIdx.y * kRPW + (int)threadIdx.x / kLPR; }
+    __device__ static int pair() { return (int)threadIdx.x % kLPR; }
+};
+
+template <int BZ>
+__device__ __forceinline__ void column_of(const TileMap &t, int &x0, int &y0, int &z0)
+{
+    const int total = t.nx * t.ny * t.nz;
+    const int b = blockIdx.x;
+    int logical = b;
+    if (total % kXCD == 0) logical = (b % kXCD) * (total / kXCD) + b / kXCD;
+    const int bz = logical % t.nz;
+    const int rest = logical / t.nz;
+    x0 = (rest / t.ny) * t.tx;
+    y0 = (rest % t.ny) * ZGeom<BZ>::kTYB;
+    z0 = bz * BZ;
+}
+
+// One staged x plane of the three components (kNR rows of kLPR + 2 pairs):
+// load i of a thread moves main pair p of row i kTYB + (its brick row), threads
+// tid < 2 kNR the two remaining pairs of row tid / 2.
+template <typename T, int BZ>
 struct PlaneRegs {
+    using G = ZGeom<BZ>;
     using V2 = typename Vec2<T>::type;
-    static constexpr int NR = 3 * kPY;
-    static constexpr int RPW = NR / kTY;
-    static_assert(NR % kTY == 0 && 2 * NR <= kTY * kLanes, "plane rows must spread over the block");
-    static_assert(kPY == 2 * kTY, "each wave stages two y rows of every component");
-    V2 v[RPW];
+    static constexpr int NL = (G::kNR + G::kTYB - 1) / G::kTYB;
+    static_assert(2 * G::kNR <= kTY * kLanes, "extra pairs must spread over the block");
+    V2 v[NL];
     V2 e;
     __device__ __forceinline__ void fetch(const T *__restrict__ in, unsigned m, int n, int x, int y0, int z0)
     {
-        const int w = threadIdx.y, lane = threadIdx.x, tid = w * kLanes + lane;
+        const int tid = threadIdx.y * kLanes + threadIdx.x, ty = G::row(), p = G::pair();
         const unsigned xo = (unsigned)wrap(x, n) * (unsigned)n;
-        const unsigned zp = (unsigned)wrap(z0 - 2 + 2 * lane, n);
-        // row w + 4 i is y row w + 4 (i & 1) of component i / 2
-        const unsigned yo[2] = {(xo + (unsigned)wrap(y0 + w - 2, n)) * (unsigned)n + zp,
-                                (xo + (unsigned)wrap(y0 + w + 2, n)) * (unsigned)n + zp};
+        const unsigned zp = (unsigned)wrap(z0 - 2 + 2 * p, n);
 #pragma unroll
-        for (int i = 0; i < RPW; i++) {
-            const T *a = in + (size_t)(i / 2) * m;
-            v[i] = *reinterpret_cast<const V2 *>(reinterpret_cast<const char *>(a) + yo[i & 1] * (unsigned)sizeof(T));
+        for (int i = 0; i < NL; i++) {
+            const int row = i * G::kTYB + ty;
+            if (G::kNR % G::kTYB == 0 || row < G::kNR) {
+                const int f = row / G::kPYB, yr = row - f * G::kPYB;
+                const unsigned off = (xo + (unsigned)wrap(y0 + yr - 2, n)) * (unsigned)n + zp;
+                v[i] = elt(reinterpret_cast<const V2 *>(in + (size_t)f * m), off >> 1);
+            }
         }
-        if (tid < 2 * NR) {
-            const int erow = tid >> 1, ep = kLanes + (tid & 1);
-            const unsigned off = (xo + (unsigned)wrap(y0 + erow % kPY - 2, n)) * (unsigned)n +
-                                 (unsigned)wrap(z0 - 2 + 2 * ep, n);
-            e = *reinterpret_cast<const V2 *>(reinterpret_cast<const char *>(in) +
-                                              ((size_t)(erow / kPY) * m + off) * sizeof(T));
+        if (tid < 2 * G::kNR) {
+            const int erow = tid >> 1, ep = G::kLPR + (tid & 1);
+            const int f = erow / G::kPYB, yr = erow - f * G::kPYB;
+            const unsigned off = (xo + (unsigned)wrap(y0 + yr - 2, n)) * (unsigned)n + (unsigned)wrap(z0 - 2 + 2 * ep, n);
+            e = elt(reinterpret_cast<const V2 *>(in + (size_t)f * m), off >> 1);
         }
     }
-    __device__ __forceinline__ void store(T (*s)[kPZ]) const // s: 24 staged rows of one slot
+    __device__ __forceinline__ void store(T (*s)[G::kPZB]) const // s: the staged rows of one slot
     {
-        const int w = threadIdx.y, lane = threadIdx.x, tid = w * kLanes + lane;
+        const int tid = threadIdx.y * kLanes + threadIdx.x, ty = G::row(), p = G::pair();
 #pragma unroll
-        for (int i = 0; i < RPW; i++) {
-            T *dst = s[w + i * kTY];
-            dst[lane] = v[i].x;
-            dst[kHalf + lane] = v[i].y;
+        for (int i = 0; i < NL; i++) {
+            const int row = i * G::kTYB + ty;
+            if (G::kNR % G::kTYB == 0 || row < G::kNR) {
+                s[row][p] = v[i].x;
+                s[row][G::kHalfB + p] = v[i].y;
+            }
         }
-        if (tid < 2 * NR) {
-            const int erow = tid >> 1, ep = kLanes + (tid & 1);
+        if (tid < 2 * G::kNR) {
+            const int erow = tid >> 1, ep = G::kLPR + (tid & 1);
             s[erow][ep] = e.x;
-            s[erow][kHalf + ep] = e.y;
+            s[erow][G::kHalfB + ep] = e.y;
         }
     }
 };
 
 // Ring prologue of a marched column: planes x0 - 2 .. x0 + 2 into slots 0..4,
 // plane x0 + 3 left in st; all six fetches are issued before the first store.
-template <typename T>
-__device__ __forceinline__ void march_prologue(T (*lds)[3 * kPY][kPZ], PlaneRegs<T> &st, const T *__restrict__ in,
-                                               unsigned m, int n, int x0, int y0, int z0)
+template <typename T, int BZ>
+__device__ __forceinline__ void march_prologue(T (*lds)[ZGeom<BZ>::kNR][ZGeom<BZ>::kPZB], PlaneRegs<T, BZ> &st,
+                                               const T *__restrict__ in, unsigned m, int n, int x0, int y0, int z0)
 {
-    PlaneRegs<T> w[5];
+    PlaneRegs<T, BZ> w[5];
 #pragma unroll
     for (int j = 0; j < 5; j++) w[j].fetch(in, m, n, x0 - 2 + j, y0, z0);
     st.fetch(in, m, n, x0 + 3, y0, z0);
@@ -500,38 +538,40 @@ __device__ __forceinline__ void march_prologue(T (*lds)[3 * kPY][kPZ], PlaneRegs
     for (int j = 0; j < 5; j++) w[j].store(lds[j]);
 }
 
-// Taps of component F around the thread's cell: pb[DX + 2] is word lane of
-// staged row ty of the slot holding plane x + DX.
-template <typename T, int PAR, int F>
+// Taps of component F around the thread's cell: pb[DX + 2] is word p of the
+// thread's staged row of the slot holding plane x + DX.
+template <typename T, int PAR, int F, int BZ>
 struct RingTaps {
+    using G = ZGeom<BZ>;
     static constexpr bool kOrdered = true;
     const T *const *pb;
     template <int DX, int DY, int DZ>
     __device__ __forceinline__ T at() const
     {
-        return pb[DX + 2][F * kPlane + (2 + DY) * kRow + zoff<PAR, DZ>()];
+        return pb[DX + 2][F * G::kPlaneB + (2 + DY) * G::kPZB + G::template zoff<PAR, DZ>()];
     }
 };
 
-template <typename T, int PAR>
+template <typename T, int PAR, int BZ>
 __device__ __forceinline__ void W_march_cell(const T *const *pb, T *const *of, unsigned qb, T h2, WPart<T> &P)
 {
-    W_field_taps<T, 0, PAR>(RingTaps<T, PAR, 0>{pb}, of[0], qb, h2, P);
-    W_field_taps<T, 1, PAR>(RingTaps<T, PAR, 1>{pb}, of[1], qb, h2, P);
-    W_field_taps<T, 2, PAR>(RingTaps<T, PAR, 2>{pb}, of[2], qb, h2, P);
+    W_field_taps<T, 0, PAR>(RingTaps<T, PAR, 0, BZ>{pb}, of[0], qb, h2, P);
+    W_field_taps<T, 1, PAR>(RingTaps<T, PAR, 1, BZ>{pb}, of[1], qb, h2, P);
+    W_field_taps<T, 2, PAR>(RingTaps<T, PAR, 2, BZ>{pb}, of[2], qb, h2, P);
 }
 
-template <typename T, int LX>
+template <typename T, int LX, int BZ>
 __global__ void __launch_bounds__(kTY *kLanes) k_pass_W_march(Geo g, TileMap tm, const T *__restrict__ in,
                                                              T *__restrict__ out, const T *__restrict__ r,
                                                              int colour)
 {
-    __shared__ T lds[kRing][3 * kPY][kPZ];
+    using G = ZGeom<BZ>;
+    __shared__ T lds[kRing][G::kNR][G::kPZB];
     int x0, y0, z0;
-    brick_of(tm, x0, y0, z0);
+    column_of<BZ>(tm, x0, y0, z0);
     const int n = g.n;
     const unsigned m = (unsigned)n * n * n;
-    const int ty = threadIdx.y, lane = threadIdx.x;
+    const int ty = G::row(), p = G::pair();
     const int y = y0 + ty;
     const T *rf[3] = {r, r + m, r + 2 * (size_t)m};
     T *of[3] = {out, out + m, out + 2 * (size_t)m};
@@ -541,15 +581,13 @@ __global__ void __launch_bounds__(kTY *kLanes) k_pass_W_march(Geo g, TileMap tm,
 
     // staged plane j (0 .. LX + 3) is x = x0 - 2 + j, in slot j % kRing; the
     // first six planes are all in flight at once
-    PlaneRegs<T> st;
-    march_prologue<T>(lds, st, in, m, n, x0, y0, z0);
-    auto row_of = [&](int x) { return (unsigned)(x * n + y) * (unsigned)n + (unsigned)(z0 + 2 * lane); };
+    PlaneRegs<T, BZ> st;
+    march_prologue<T, BZ>(lds, st, in, m, n, x0, y0, z0);
+    auto row_of = [&](int x) { return (unsigned)(x * n + y) * (unsigned)n + (unsigned)(z0 + 2 * p); };
     auto par_of = [&](int x) { return (unsigned)((colour + x + y + z0) & 1); };
     T rv[3];
 #pragma unroll
-    for (int f = 0; f < 3; f++)
-        rv[f] = *reinterpret_cast<const T *>(reinterpret_cast<const char *>(rf[f]) +
-                                             (row_of(x0) + par_of(x0)) * (unsigned)sizeof(T));
+    for (int f = 0; f < 3; f++) rv[f] = elt(rf[f], row_of(x0) + par_of(x0));
     __syncthreads();
 
 #pragma unroll 1
@@ -559,22 +597,20 @@ __global__ void __launch_bounds__(kTY *kLanes) k_pass_W_march(Geo g, TileMap tm,
         const unsigned qa = row_of(x) + pa, qb = row_of(x) + (pa ^ 1u);
         const T *pb[5];
 #pragma unroll
-        for (int d = 0; d < 5; d++) pb[d] = &lds[(k + d) % kRing][ty][lane];
+        for (int d = 0; d < 5; d++) pb[d] = &lds[(k + d) % kRing][ty][p];
         T rn[3] = {T(0), T(0), T(0)};
         if (k + 1 < LX) { // r of the next plane's active cells
             const unsigned qn = row_of(x + 1) + (pa ^ 1u);
 #pragma unroll
-            for (int f = 0; f < 3; f++)
-                rn[f] = *reinterpret_cast<const T *>(reinterpret_cast<const char *>(rf[f]) + qn * (unsigned)sizeof(T));
+            for (int f = 0; f < 3; f++) rn[f] = elt(rf[f], qn);
         }
         WPart<T> P;
-        if (pa) W_march_cell<T, 1>(pb, of, qb, h2, P);
-        else W_march_cell<T, 0>(pb, of, qb, h2, P);
+        if (pa) W_march_cell<T, 1, BZ>(pb, of, qb, h2, P);
+        else W_march_cell<T, 0, BZ>(pb, of, qb, h2, P);
 #pragma unroll
         for (int f = 0; f < 3; f++) {
             const T Ad = P.lap[f] + (P.dd[f] + P.mix[f] * m2) * third;
-            *reinterpret_cast<T *>(reinterpret_cast<char *>(of[f]) + qa * (unsigned)sizeof(T)) =
-                P.c[f] + (rv[f] - Ad) * inv_diag;
+            elt(of[f], qa) = P.c[f] + (rv[f] - Ad) * inv_diag;
             rv[f] = rn[f];
         }
         if (k + 5 <= LX + 3) { // plane x + 3 into the slot plane x - 3 left
@@ -588,46 +624,47 @@ __global__ void __launch_bounds__(kTY *kLanes) k_pass_W_march(Geo g, TileMap tm,
 // ---------------------------------------------------------------------------------------
 // W defect r - Delta_L d and its restriction (mean of the 8 children) to the
 // next coarser level, marching along x like k_pass_W_march.  Each lane
-// evaluates both members of its z pair on two consecutive x planes; the paired
-// y rows (waves 2 w' and 2 w' + 1) are added through LDS and the even wave
-// writes one coarse cell per lane (coarse z = z0 / 2 + lane, coalesced).
+// evaluates both members of its z pair on two consecutive x planes; the
+// paired y rows (brick rows 2 w' and 2 w' + 1) are added through LDS and the
+// even row writes one coarse cell per lane (coarse z = z0 / 2 + p, coalesced).
 // ---------------------------------------------------------------------------------------
-template <typename T, int PAR>
+template <typename T, int PAR, int BZ>
 __device__ __forceinline__ void W_defect_cell(const T *const *pb, const T (&rv)[3], T h2, T m2, T third, T (&acc)[3])
 {
     WPart<T> P;
-    W_field_parts<T, 0, PAR>(RingTaps<T, PAR, 0>{pb}, h2, P);
-    W_field_parts<T, 1, PAR>(RingTaps<T, PAR, 1>{pb}, h2, P);
-    W_field_parts<T, 2, PAR>(RingTaps<T, PAR, 2>{pb}, h2, P);
+    W_field_parts<T, 0, PAR>(RingTaps<T, PAR, 0, BZ>{pb}, h2, P);
+    W_field_parts<T, 1, PAR>(RingTaps<T, PAR, 1, BZ>{pb}, h2, P);
+    W_field_parts<T, 2, PAR>(RingTaps<T, PAR, 2, BZ>{pb}, h2, P);
 #pragma unroll
     for (int f = 0; f < 3; f++) acc[f] += rv[f] - (P.lap[f] + (P.dd[f] + P.mix[f] * m2) * third);
 }
 
-template <typename T, int LX>
+template <typename T, int LX, int BZ>
 __global__ void __launch_bounds__(kTY *kLanes) k_defect_restrict_W_march(Geo g, TileMap tm, const T *__restrict__ d,
                                                                         const T *__restrict__ r,
                                                                         T *__restrict__ rc_out)
 {
-    static_assert(LX % 2 == 0 && kTY % 2 == 0, "whole coarse cells per column");
+    using G = ZGeom<BZ>;
+    static_assert(LX % 2 == 0 && G::kTYB % 2 == 0, "whole coarse cells per column");
     using V2 = typename Vec2<T>::type;
-    __shared__ T lds[kRing][3 * kPY][kPZ];
-    __shared__ T red[3][kTY / 2][kLanes];
+    __shared__ T lds[kRing][G::kNR][G::kPZB];
+    __shared__ T red[3][G::kTYB / 2][G::kLPR];
     int x0, y0, z0;
-    brick_of(tm, x0, y0, z0);
+    column_of<BZ>(tm, x0, y0, z0);
     const int n = g.n, nc = n / 2;
     const unsigned m = (unsigned)n * n * n, mc = (unsigned)nc * nc * nc;
-    const int ty = threadIdx.y, lane = threadIdx.x;
+    const int ty = G::row(), p = G::pair();
     const int y = y0 + ty;
     const T *rf[3] = {r, r + m, r + 2 * (size_t)m};
     const T h2 = (T)g.inv12h2, m2 = (T)g.inv144h2;
     const T third = T(1) / T(3);
 
-    PlaneRegs<T> st;
-    march_prologue<T>(lds, st, d, m, n, x0, y0, z0);
-    auto pair_of = [&](int x) { return (unsigned)(x * n + y) * (unsigned)n + (unsigned)(z0 + 2 * lane); };
+    PlaneRegs<T, BZ> st;
+    march_prologue<T, BZ>(lds, st, d, m, n, x0, y0, z0);
+    auto pair_at = [&](int x) { return (unsigned)(x * n + y) * (unsigned)n + (unsigned)(z0 + 2 * p); };
     V2 rv[3];
 #pragma unroll
-    for (int f = 0; f < 3; f++) rv[f] = elt(reinterpret_cast<const V2 *>(rf[f]), pair_of(x0) >> 1);
+    for (int f = 0; f < 3; f++) rv[f] = elt(reinterpret_cast<const V2 *>(rf[f]), pair_at(x0) >> 1);
     __syncthreads();
 
     T acc[3] = {T(0), T(0), T(0)};
@@ -636,20 +673,18 @@ __global__ void __launch_bounds__(kTY *kLanes) k_defect_restrict_W_march(Geo g, 
         const int x = x0 + k;
         const T *pb[5];
 #pragma unroll
-        for (int dd = 0; dd < 5; dd++) pb[dd] = &lds[(k + dd) % kRing][ty][lane];
+        for (int dd = 0; dd < 5; dd++) pb[dd] = &lds[(k + dd) % kRing][ty][p];
         V2 rn[3];
         if (k + 1 < LX) {
 #pragma unroll
-            for (int f = 0; f < 3; f++) rn[f] = elt(reinterpret_cast<const V2 *>(rf[f]), pair_of(x + 1) >> 1);
+            for (int f = 0; f < 3; f++) rn[f] = elt(reinterpret_cast<const V2 *>(rf[f]), pair_at(x + 1) >> 1);
         }
         const T ra[3] = {rv[0].x, rv[1].x, rv[2].x}, rb[3] = {rv[0].y, rv[1].y, rv[2].y};
-        W_defect_cell<T, 0>(pb, ra, h2, m2, third, acc);
-        W_defect_cell<T, 1>(pb, rb, h2, m2, third, acc);
-        if (k & 1) {
-            if (ty & 1) {
+        W_defect_cell<T, 0, BZ>(pb, ra, h2, m2, third, acc);
+        W_defect_cell<T, 1, BZ>(pb, rb, h2, m2, third, acc);
+        if ((k & 1) && (ty & 1)) {
 #pragma unroll
-                for (int f = 0; f < 3; f++) red[f][ty >> 1][lane] = acc[f];
-            }
+            for (int f = 0; f < 3; f++) red[f][ty >> 1][p] = acc[f];
         }
         if (k + 5 <= LX + 3) {
             st.store(lds[(k + 5) % kRing]);
@@ -659,10 +694,10 @@ __global__ void __launch_bounds__(kTY *kLanes) k_defect_restrict_W_march(Geo g, 
         if (k & 1) {
             if (!(ty & 1)) {
                 const unsigned qc = ((unsigned)(x >> 1) * (unsigned)nc + (unsigned)(y >> 1)) * (unsigned)nc +
-                                    (unsigned)((z0 >> 1) + lane);
+                                    (unsigned)((z0 >> 1) + p);
 #pragma unroll
                 for (int f = 0; f < 3; f++)
-                    elt(rc_out + (size_t)f * mc, qc) = (acc[f] + red[f][ty >> 1][lane]) * T(0.125);
+                    elt(rc_out + (size_t)f * mc, qc) = (acc[f] + red[f][ty >> 1][p]) * T(0.125);
             }
 #pragma unroll
             for (int f = 0; f < 3; f++) acc[f] = T(0);
@@ -672,6 +707,20 @@ __global__ void __launch_bounds__(kTY *kLanes) k_defect_restrict_W_march(Geo g, 
             for (int f = 0; f < 3; f++) rv[f] = rn[f];
         }
     }
+}
+
+// Column map of the marched kernels (tx == 0: the level does not fit).
+template <int LX, int BZ>
+inline TileMap make_marchmap(int n)
+{
+    TileMap t{0, 0, 0, 0};
+    constexpr int TYB = ZGeom<BZ>::kTYB;
+    if (n % BZ != 0 || n % TYB != 0 || n % LX != 0) return t;
+    t.nx = n / LX;
+    t.ny = n / TYB;
+    t.nz = n / BZ;
+    t.tx = LX;
+    return t;
 }
 
 // ---------------------------------------------------------------------------------------

@@ -79,6 +79,33 @@ def test_marched_W_defect_restrict(precision):
     assert rel_err(N(out), ref) < tol
 
 
+@pytest.mark.parametrize("precision", [g.PREC_FP64, g.PREC_FP32_IR])
+def test_marched64_W_pass_and_defect(precision):
+    """64^3 level: the W colour passes and the W defect restriction run as x-marched
+    columns of 64-cell rows (two brick rows per wave)."""
+    m = 64
+    p = g.params(m, 5, precision=precision, solve_momentum=True)
+    po = oracle.params(m, 5)
+    z = torch.zeros((m,) * 3, dtype=torch.float64, device=dev())
+    S = torch.zeros((3, m, m, m), dtype=torch.float64, device=dev())
+    s = g.Solver(p, z, z, S)
+    d = synth.uniform_random(67, (3, m, m, m))
+    r = synth.uniform_random(68, (3, m, m, m))
+    vt = s.vtype
+    if vt == torch.float32:
+        d, r = (a.astype(np.float32).astype(np.float64) for a in (d, r))
+    tol = 1e-13 if vt == torch.float64 else 2e-6
+    for colour in (0, 1):
+        out = torch.empty((3, m, m, m), dtype=vt, device=dev())
+        s.kernel_op(g.OP_PASS_W, 0, colour, T(d, vt), out, T(r, vt))
+        assert rel_err(N(out), oracle.pass_W(po, d, r, colour)) < tol, colour
+    out = torch.empty((3,) + (m // 2,) * 3, dtype=vt, device=dev())
+    s.kernel_op(g.OP_DEFECT_RESTRICT_W, 0, 0, T(d, vt), out, T(r, vt))
+    defect = r - oracle.apply_deltaL(po, d)
+    ref = np.stack([oracle.restrict(np.ascontiguousarray(defect[a])) for a in range(3)])
+    assert rel_err(N(out), ref) < (1e-12 if vt == torch.float64 else 1e-5)
+
+
 def test_report_lds_limit():
     import ctypes as C
     hip = C.CDLL("libamdhip64.so")
