@@ -32,26 +32,30 @@ METRIC = "s to 1e-10 constraint residual @128^3: FP64 MG vs mixed+learned; HBM G
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the finest-level W pass from FETCH_SIZE / WRITE_SIZE runs,
 # valid only for the kernel sources they were measured on (sha256 prefixes)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pass_W_tiled_coupled_128_traffic.md")
-TRAFFIC_SOURCES = {"paper_2501_13046_amd/csrc/mg_tiled.hpp": "d360c78c62e46937",
-                   "paper_2501_13046_amd/csrc/mg_device.hpp": "4ee763eb646743f1"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pass_W_march_coupled_128_traffic.md")
+TRAFFIC_SOURCES = {"paper_2501_13046_amd/csrc/mg_tiled.hpp": "c13d4fb5ef8b2995",
+                   "paper_2501_13046_amd/csrc/mg_device.hpp": "2ca445281eca0ab8"}
 
 
-def measured_traffic():
+def measured_traffic(depth):
     """Bytes per launch from the committed counter summary, or None when the
-    kernel sources changed since the counters were taken."""
+    kernel sources changed since the counters were taken or the pass runs at
+    another brick depth than the one measured."""
     import hashlib
     for rel, pre in TRAFFIC_SOURCES.items():
         with open(os.path.join(ROOT, rel), "rb") as f:
             if hashlib.sha256(f.read()).hexdigest()[:16] != pre:
                 return None
+    vals = {}
     try:
         for line in open(TRAFFIC_FILE):
-            if line.startswith("traffic_bytes_per_launch:"):
-                return int(line.split(":")[1])
-    except OSError:
+            if ":" in line and line.split(":")[0] in ("brick_depth", "traffic_bytes_per_launch"):
+                vals[line.split(":")[0]] = int(line.split(":")[1])
+    except (OSError, ValueError):
         return None
-    return None
+    if vals.get("brick_depth") != depth:
+        return None
+    return vals.get("traffic_bytes_per_launch")
 
 
 def log(*a):
@@ -113,6 +117,7 @@ def main():
         tuning = g.autotune_cached(mixed, u, W, path=args.tune_cache, reps=20)
     else:
         tuning = mixed.autotune(u, W, reps=20)
+    w_depth = next((e["chosen"] for e in tuning if e["family"] == g.TUNE_PASS_W and e["level"] == 0), None)
     for e in tuning:
         log(f"[bench] autotune family {e['family']} level {e['level']}: chosen {e['chosen']} "
             + " ".join(f"{k}:{v:.2f}us" for k, v in e.get("candidates", {}).items()))
@@ -292,9 +297,10 @@ def main():
             "fmg_start": fmg,
         },
         "roofline": {
-            "kernel": "k_pass_W<float> (finest level)",
+            "kernel": f"finest-level W colour pass, brick depth {w_depth} "
+                      f"({'x-marched column' if (w_depth or 0) >= 8 else 'staged brick'})",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(w_depth),
             "launches": launches, "avg_us": avg_s * 1e6, "bytes_per_launch": bytes_per_launch,
         },
         "cpu_baseline": cpu,
