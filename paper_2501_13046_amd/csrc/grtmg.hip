@@ -378,57 +378,63 @@ void pass_psi(mg_ctx *c, int l, const T *in, T *out, int colour)
 }
 
 template <typename T>
-void smooth_psi(mg_ctx *c, int l, int sweeps)
+// first_done: the first colour pass from a zero correction was written into
+// pd1 by the producer of this level's right-hand side.
+void smooth_psi(mg_ctx *c, int l, int sweeps, bool first_done = false)
 {
     for (int s = 0; s < sweeps; s++) {
-        pass_psi<T>(c, l, (const T *)c->pd0[l], (T *)c->pd1[l], 0);
+        if (s > 0 || !first_done) pass_psi<T>(c, l, (const T *)c->pd0[l], (T *)c->pd1[l], 0);
         pass_psi<T>(c, l, (const T *)c->pd1[l], (T *)c->pd0[l], 1);
     }
 }
 
 template <typename T>
-void defect_restrict_psi(mg_ctx *c, int l, const T *d, const T *r, const T *cf, T *rc, T *cc)
+// d1 (may be null; needs cc): first colour pass of the coarse level from zero.
+void defect_restrict_psi(mg_ctx *c, int l, const T *d, const T *r, const T *cf, T *rc, T *cc, T *d1 = nullptr)
 {
     Probe pr(c, MG_PROBE_DEFECT_RESTRICT_PSI, l);
-    const Geo &g = c->geo[l];
+    const Geo &g = c->geo[l], &gc = c->geo[l + 1];
+    if (!cc) d1 = nullptr;
     if (fine_threads(c->n[l])) {
         const unsigned nb = nblk(8 * c->cells[l + 1]);
         if (c->p.bc == MG_BC_PERIODIC)
             hipLaunchKernelGGL((k_defect_restrict_psi_fine<kBcPeriodic, T>), dim3(nb), dim3(kBlock), 0, c->s, g, d, r,
-                               cf, rc, cc);
+                               cf, rc, cc, d1, gc);
         else
             hipLaunchKernelGGL((k_defect_restrict_psi_fine<kBcRobin, T>), dim3(nb), dim3(kBlock), 0, c->s, g, d, r,
-                               cf, rc, cc);
+                               cf, rc, cc, d1, gc);
     } else {
         const unsigned nb = nblk(c->cells[l + 1]);
         if (c->p.bc == MG_BC_PERIODIC)
             hipLaunchKernelGGL((k_defect_restrict_psi<kBcPeriodic, T>), dim3(nb), dim3(kBlock), 0, c->s, g, d, r, cf,
-                               rc, cc);
+                               rc, cc, d1, gc);
         else
             hipLaunchKernelGGL((k_defect_restrict_psi<kBcRobin, T>), dim3(nb), dim3(kBlock), 0, c->s, g, d, r, cf,
-                               rc, cc);
+                               rc, cc, d1, gc);
     }
 }
 
+// d1 (may be null): first colour pass of the coarse level from zero.
 template <typename T>
-void defect_restrict_W(mg_ctx *c, int l, const T *d, const T *r, T *rc)
+void defect_restrict_W(mg_ctx *c, int l, const T *d, const T *r, T *rc, T *d1 = nullptr)
 {
     Probe pr(c, MG_PROBE_DEFECT_RESTRICT_W, l);
     const int n = c->n[l];
+    const T idiag = (T)(1.0 / (-100.0 * c->geo[l + 1].inv12h2));
     const TileMap tm = w_tileable(n) ? make_marchmap<8, 128>(n) : TileMap{0, 0, 0, 0};
     const TileMap tm64 = w_tileable(n) ? make_marchmap<kMarch64Defect, 64>(n) : TileMap{0, 0, 0, 0};
     if (tm.tx > 0)
         hipLaunchKernelGGL((k_defect_restrict_W_march<T, 8, 128>), dim3(ntiles(tm)), dim3(kLanes, kTY), 0, c->s,
-                           c->geo[l], tm, d, r, rc);
+                           c->geo[l], tm, d, r, rc, d1, idiag);
     else if (tm64.tx > 0)
         hipLaunchKernelGGL((k_defect_restrict_W_march<T, kMarch64Defect, 64>), dim3(ntiles(tm64)),
-                           dim3(kLanes, kTY), 0, c->s, c->geo[l], tm64, d, r, rc);
-    else if (fine_threads(c->n[l]))
+                           dim3(kLanes, kTY), 0, c->s, c->geo[l], tm64, d, r, rc, d1, idiag);
+    else if (fine_threads(n))
         hipLaunchKernelGGL(k_defect_restrict_W_quad<T>, dim3(nblk(32 * c->cells[l + 1])), dim3(kBlock), 0, c->s,
-                           c->geo[l], d, r, rc);
+                           c->geo[l], d, r, rc, d1, idiag);
     else
         hipLaunchKernelGGL(k_defect_restrict_W<T>, dim3(nblk(c->cells[l + 1])), dim3(kBlock), 0, c->s, c->geo[l], d,
-                           r, rc);
+                           r, rc, d1, idiag);
 }
 
 template <typename T>
@@ -449,9 +455,16 @@ void prolong_add(mg_ctx *c, int lc, const T *coarse, T *fine, int ncomp)
 // the coarsest system is too large for the register-resident solver, assemble and
 // invert it.  All on the context's stream: the V-cycle kernels that follow
 // stay on one queue of the graph.
+// Without a V-cycle tail and with the coarsest psi system solved in registers,
+// the coefficient c of each coarser level is restricted by the defect
+// restriction that produces that level's right-hand side (the level is not
+// smoothed before), so no separate sweep over the levels is needed.
+bool c_with_defect(const mg_ctx *c) { return !c->tail_psi_on && wave_solvable(c->m_psi); }
+
 template <typename T>
 void restrict_coefficients(mg_ctx *c)
 {
+    if (c_with_defect(c)) return; // each level's c comes with its defect restriction
     const int stop = c->tail_psi_on ? c->tail_psi : c->L - 1; // the tail restricts below its first level
     for (int l = 0; l < stop; l++)
         hipLaunchKernelGGL(k_restrict<T>, dim3(nblk(c->cells[l + 1])), dim3(kBlock), 0, c->s, c->n[l],
@@ -514,7 +527,10 @@ void tail_psi(mg_ctx *c)
 // psi V-cycle on level l; the coefficients of levels > 0 and the coarsest
 // inverse come from restrict_coefficients (and the tail kernel below its first level).
 template <typename T>
-void vcycle_psi(mg_ctx *c, int l)
+// first_done: the producer of this level's right-hand side also wrote the
+// first colour pass from a zero correction into pd1 (coarser levels, when c
+// is restricted with the defect).
+void vcycle_psi(mg_ctx *c, int l, bool first_done = false)
 {
     if (c->tail_psi_on && l == c->tail_psi) {
         tail_psi<T>(c);
@@ -532,11 +548,14 @@ void vcycle_psi(mg_ctx *c, int l)
                            (T *)c->pd0[l], 0);
         return;
     }
-    fill<T>(c->s, (T *)c->pd0[l], c->cells[l], T(0));
-    smooth_psi<T>(c, l, c->p.nu_pre);
+    if (!first_done) fill<T>(c->s, (T *)c->pd0[l], c->cells[l], T(0));
+    smooth_psi<T>(c, l, c->p.nu_pre, first_done);
+    // the next level's first pass comes with its defect when that level is smoothed
+    const bool next_first = c_with_defect(c) && l + 2 < c->L;
     defect_restrict_psi<T>(c, l, (const T *)c->pd0[l], (const T *)c->pr[l], (const T *)c->pc[l],
-                           (T *)c->pr[l + 1], nullptr);
-    vcycle_psi<T>(c, l + 1);
+                           (T *)c->pr[l + 1], c_with_defect(c) ? (T *)c->pc[l + 1] : nullptr,
+                           next_first ? (T *)c->pd1[l + 1] : nullptr);
+    vcycle_psi<T>(c, l + 1, next_first);
     prolong_add<T>(c, l + 1, (const T *)c->pd0[l + 1], (T *)c->pd0[l], 1);
     smooth_psi<T>(c, l, c->p.nu_post);
 }
@@ -581,16 +600,16 @@ void pass_W(mg_ctx *c, int l, const T *in, T *out, const T *r, int colour)
 }
 
 template <typename T>
-void smooth_W(mg_ctx *c, int l, int sweeps)
+void smooth_W(mg_ctx *c, int l, int sweeps, bool first_done = false)
 {
     for (int s = 0; s < sweeps; s++) {
-        pass_W<T>(c, l, (const T *)c->wd0[l], (T *)c->wd1[l], (const T *)c->wr[l], 0);
+        if (s > 0 || !first_done) pass_W<T>(c, l, (const T *)c->wd0[l], (T *)c->wd1[l], (const T *)c->wr[l], 0);
         pass_W<T>(c, l, (const T *)c->wd1[l], (T *)c->wd0[l], (const T *)c->wr[l], 1);
     }
 }
 
 template <typename T>
-void vcycle_W(mg_ctx *c, int l)
+void vcycle_W(mg_ctx *c, int l, bool first_done = false)
 {
     if (c->tail_W_on && l == c->tail_W) {
         Probe pr(c, MG_PROBE_COARSE, c->L - 1);
@@ -601,10 +620,12 @@ void vcycle_W(mg_ctx *c, int l)
         coarse_W<T>(c, (const T *)c->wr[l], (T *)c->wd0[l]);
         return;
     }
-    fill<T>(c->s, (T *)c->wd0[l], 3 * c->cells[l], T(0));
-    smooth_W<T>(c, l, c->p.nu_pre);
-    defect_restrict_W<T>(c, l, (const T *)c->wd0[l], (const T *)c->wr[l], (T *)c->wr[l + 1]);
-    vcycle_W<T>(c, l + 1);
+    if (!first_done) fill<T>(c->s, (T *)c->wd0[l], 3 * c->cells[l], T(0));
+    smooth_W<T>(c, l, c->p.nu_pre, first_done);
+    const bool next_first = l + 2 < c->L; // the next level is smoothed (not the coarsest)
+    defect_restrict_W<T>(c, l, (const T *)c->wd0[l], (const T *)c->wr[l], (T *)c->wr[l + 1],
+                         next_first ? (T *)c->wd1[l + 1] : nullptr);
+    vcycle_W<T>(c, l + 1, next_first);
     prolong_add<T>(c, l + 1, (const T *)c->wd0[l + 1], (T *)c->wd0[l], 3);
     smooth_W<T>(c, l, c->p.nu_post);
 }

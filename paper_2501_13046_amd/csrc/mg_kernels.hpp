@@ -412,7 +412,8 @@ __global__ void __launch_bounds__(kBlock) k_pass_W_quad(Geo g, const T *__restri
 // 4 child + f; the child sum runs over lanes of the same f.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_defect_restrict_W_quad(Geo g, const T *__restrict__ d,
-                                                                   const T *__restrict__ r, T *__restrict__ rc_out)
+                                                                   const T *__restrict__ r, T *__restrict__ rc_out,
+                                                                   T *__restrict__ d1_out, T idiag_c)
 {
     const int n = g.n, nc = n / 2;
     const unsigned t = blockIdx.x * kBlock + threadIdx.x;
@@ -431,7 +432,11 @@ __global__ void __launch_bounds__(kBlock) k_defect_restrict_W_quad(Geo g, const 
     v += __shfl_xor(v, 4, kWave);
     v += __shfl_xor(v, 8, kWave);
     v += __shfl_xor(v, 16, kWave);
-    if (live && ch == 0 && f < 3) elt(rc_out + (size_t)f * mc, qc) = v * T(0.125);
+    if (live && ch == 0 && f < 3) {
+        const T rcv = v * T(0.125);
+        elt(rc_out + (size_t)f * mc, qc) = rcv;
+        if (d1_out) elt(d1_out + (size_t)f * mc, qc) = ((I + J + K) & 1) == 0 ? rcv * idiag_c : T(0);
+    }
 }
 
 template <typename T>
@@ -499,10 +504,26 @@ __device__ __forceinline__ bool child_of(int64_t tid, int nc, int64_t &qc, int &
 // one thread per coarse cell (the 8 children's overlapping stencils share
 // loads in registers: large grids), or one thread per fine cell with a lane
 // group per coarse cell (8x the parallelism: small, latency-bound grids).
+// First colour pass of the coarse level from a zero correction at coarse cell
+// (I, J, K): r / diag on colour 0 and 0 on colour 1, with the diagonal as the
+// pass kernels form it.
+template <int BC, typename T>
+__device__ __forceinline__ T first_pass_psi(const Geo &gc, int I, int J, int K, T rcv, T ccv)
+{
+    if (((I + J + K) & 1) != 0) return T(0);
+    T diag;
+    if constexpr (BC == kBcPeriodic)
+        diag = (T)(-90.0 * gc.inv12h2) + ccv;
+    else
+        diag = (T)(lap_diag_sum<BC>(gc, I, J, K) * gc.inv12h2) + ccv;
+    return T(0) + (rcv - T(0)) / diag;
+}
+
 template <int BC, typename T>
 __device__ __forceinline__ void defect_restrict_psi_coarse(const Geo &g, const T *__restrict__ d, const T *__restrict__ r,
                                                            const T *__restrict__ c, T *__restrict__ rc_out,
-                                                           T *__restrict__ cc_out, int64_t qc, int I, int J, int K)
+                                                           T *__restrict__ cc_out, int64_t qc, int I, int J, int K,
+                                                           T *__restrict__ d1_out = nullptr, const Geo *gc = nullptr)
 {
     Acc<BC, T> D{d, g};
     const T h2 = (T)g.inv12h2;
@@ -519,21 +540,26 @@ __device__ __forceinline__ void defect_restrict_psi_coarse(const Geo &g, const T
                 sd += r[q] - (lap_sum<T>(D, i, j, k, x) * h2 + cv * x);
                 sc += cv;
             }
-    rc_out[qc] = sd * T(0.125);
-    if (cc_out) cc_out[qc] = sc * T(0.125);
+    const T rcv = sd * T(0.125), ccv = sc * T(0.125);
+    rc_out[qc] = rcv;
+    if (cc_out) cc_out[qc] = ccv;
+    if (d1_out) d1_out[qc] = first_pass_psi<BC, T>(*gc, I, J, K, rcv, ccv);
 }
 
+// d1_out (may be null; needs cc_out): the coarse level's first colour pass
+// from zero, so that its smoothing starts with the second pass.
 template <int BC, typename T>
 __global__ void __launch_bounds__(kBlock) k_defect_restrict_psi(Geo g, const T *__restrict__ d,
                                                                 const T *__restrict__ r,
                                                                 const T *__restrict__ c,
                                                                 T *__restrict__ rc_out,
-                                                                T *__restrict__ cc_out)
+                                                                T *__restrict__ cc_out, T *__restrict__ d1_out,
+                                                                Geo gc)
 {
     const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     int I, J, K;
     if (!cell_of(tid, g.n / 2, I, J, K)) return;
-    defect_restrict_psi_coarse<BC, T>(g, d, r, c, rc_out, cc_out, tid, I, J, K);
+    defect_restrict_psi_coarse<BC, T>(g, d, r, c, rc_out, cc_out, tid, I, J, K, d1_out, &gc);
 }
 
 // Fine-cell form: fine cell tid of the grid of 8 nc^3 threads (child_of), group
@@ -541,7 +567,8 @@ __global__ void __launch_bounds__(kBlock) k_defect_restrict_psi(Geo g, const T *
 template <int BC, typename T>
 __device__ __forceinline__ void defect_restrict_psi_child(const Geo &g, const T *__restrict__ d, const T *__restrict__ r,
                                                           const T *__restrict__ c, T *__restrict__ rc_out,
-                                                          T *__restrict__ cc_out, int64_t tid)
+                                                          T *__restrict__ cc_out, int64_t tid,
+                                                          T *__restrict__ d1_out = nullptr, const Geo *gc = nullptr)
 {
     int64_t qc;
     int i, j, k;
@@ -558,8 +585,10 @@ __device__ __forceinline__ void defect_restrict_psi_child(const Geo &g, const T 
     sd = child_sum(sd);
     const T sc = child_sum(cv);
     if (live && (tid & 7) == 0) {
-        rc_out[qc] = sd * T(0.125);
-        if (cc_out) cc_out[qc] = sc * T(0.125);
+        const T rcv = sd * T(0.125), ccv = sc * T(0.125);
+        rc_out[qc] = rcv;
+        if (cc_out) cc_out[qc] = ccv;
+        if (d1_out) d1_out[qc] = first_pass_psi<BC, T>(*gc, i >> 1, j >> 1, k >> 1, rcv, ccv);
     }
 }
 
@@ -568,9 +597,11 @@ __global__ void __launch_bounds__(kBlock) k_defect_restrict_psi_fine(Geo g, cons
                                                                      const T *__restrict__ r,
                                                                      const T *__restrict__ c,
                                                                      T *__restrict__ rc_out,
-                                                                     T *__restrict__ cc_out)
+                                                                     T *__restrict__ cc_out, T *__restrict__ d1_out,
+                                                                     Geo gc)
 {
-    defect_restrict_psi_child<BC, T>(g, d, r, c, rc_out, cc_out, (int64_t)blockIdx.x * kBlock + threadIdx.x);
+    defect_restrict_psi_child<BC, T>(g, d, r, c, rc_out, cc_out, (int64_t)blockIdx.x * kBlock + threadIdx.x, d1_out,
+                                     &gc);
 }
 
 template <typename T>
@@ -605,7 +636,8 @@ __device__ __forceinline__ void defect_restrict_W_coarse(const Geo &g, const T *
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_defect_restrict_W(Geo g, const T *__restrict__ d,
                                                               const T *__restrict__ r,
-                                                              T *__restrict__ rc_out)
+                                                              T *__restrict__ rc_out, T *__restrict__ d1_out,
+                                                              T idiag_c)
 {
     const int nc = g.n / 2;
     const int64_t mf = (int64_t)g.n * g.n * g.n, mc = (int64_t)nc * nc * nc;
@@ -626,8 +658,13 @@ __global__ void __launch_bounds__(kBlock) k_defect_restrict_W(Geo g, const T *__
 #pragma unroll
                 for (int a = 0; a < 3; a++) s[a] += r[a * mf + q] - Ad[a];
             }
+    const bool first = ((I + J + K) & 1) == 0;
 #pragma unroll
-    for (int a = 0; a < 3; a++) rc_out[a * mc + tid] = s[a] * T(0.125);
+    for (int a = 0; a < 3; a++) {
+        const T v = s[a] * T(0.125);
+        rc_out[a * mc + tid] = v;
+        if (d1_out) d1_out[a * mc + tid] = first ? v * idiag_c : T(0);
+    }
 }
 
 template <typename T>

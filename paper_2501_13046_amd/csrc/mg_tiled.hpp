@@ -642,7 +642,8 @@ __device__ __forceinline__ void W_defect_cell(const T *const *pb, const T (&rv)[
 template <typename T, int LX, int BZ>
 __global__ void __launch_bounds__(kTY *kLanes) k_defect_restrict_W_march(Geo g, TileMap tm, const T *__restrict__ d,
                                                                         const T *__restrict__ r,
-                                                                        T *__restrict__ rc_out)
+                                                                        T *__restrict__ rc_out, T *__restrict__ d1_out,
+                                                                        T idiag_c)
 {
     using G = ZGeom<BZ>;
     static_assert(LX % 2 == 0 && G::kTYB % 2 == 0, "whole coarse cells per column");
@@ -695,9 +696,13 @@ __global__ void __launch_bounds__(kTY *kLanes) k_defect_restrict_W_march(Geo g, 
             if (!(ty & 1)) {
                 const unsigned qc = ((unsigned)(x >> 1) * (unsigned)nc + (unsigned)(y >> 1)) * (unsigned)nc +
                                     (unsigned)((z0 >> 1) + p);
+                const bool first = (((x >> 1) + (y >> 1) + (z0 >> 1) + p) & 1) == 0;
 #pragma unroll
-                for (int f = 0; f < 3; f++)
-                    elt(rc_out + (size_t)f * mc, qc) = (acc[f] + red[f][ty >> 1][p]) * T(0.125);
+                for (int f = 0; f < 3; f++) {
+                    const T v = (acc[f] + red[f][ty >> 1][p]) * T(0.125);
+                    elt(rc_out + (size_t)f * mc, qc) = v;
+                    if (d1_out) elt(d1_out + (size_t)f * mc, qc) = first ? v * idiag_c : T(0);
+                }
             }
 #pragma unroll
             for (int f = 0; f < 3; f++) acc[f] = T(0);
