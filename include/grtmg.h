@@ -69,8 +69,9 @@ enum { MG_FLAG_CONFORMAL_MATTER = 1, MG_FLAG_EAGER = 2 };
 
 /*
  * Problem and solver parameters.
- *  n              cells per axis; every level but the coarsest must have n_l
- *                 even and n_l >= 6, the coarsest n >> (levels-1) >= 3.
+ *  n              cells per axis (n^3 < 2^32, i.e. n <= 1625); every level but
+ *                 the coarsest must have n_l even and n_l >= 6, the coarsest
+ *                 n >> (levels-1) >= 3.
  *  levels         number of multigrid levels (1..16).
  *  bc             MG_BC_PERIODIC, or MG_BC_ROBIN: ghost a(g) = a(b)|x_b|/|x_g|,
  *                 b = grid cell nearest g, radii from puncture_pos.  The

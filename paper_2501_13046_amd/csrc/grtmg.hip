@@ -124,6 +124,8 @@ mg_status validate(const mg_params *p)
     if (!p) return MG_ERR_INVALID;
     if (p->levels < 1 || p->levels > kMaxLevels) return MG_ERR_INVALID;
     if (p->n < 3 || p->n > 4096) return MG_ERR_INVALID;
+    // cell indices are 32-bit (n^3 < 2^32, n <= 1625)
+    if ((double)p->n * p->n * (double)p->n >= 4294967296.0) return MG_ERR_INVALID;
     if (p->bc != MG_BC_PERIODIC && p->bc != MG_BC_ROBIN) return MG_ERR_INVALID;
     if (p->precision != MG_PREC_FP64 && p->precision != MG_PREC_FP32_IR) return MG_ERR_INVALID;
     if (p->nu_pre < 0 || p->nu_post < 0 || p->nu_pre + p->nu_post < 1 || p->nu_pre > 16 ||
@@ -669,8 +671,10 @@ void launch_residual_tiled(hipStream_t s, const Geo &g, const TileMap &tm, const
 }
 
 template <typename T>
+// first: also write the finest level's first colour pass from a zero
+// correction beside r (pd1) or rW (wd1), for the V-cycle that follows.
 void residual(mg_ctx *c, const double *u, const double *W, bool want_M, double *H, double *M,
-              double *cc, void *r, void *rc, void *rW, bool norms)
+              double *cc, void *r, void *rc, void *rW, bool norms, bool first = false)
 {
     ResArgs a;
     a.u = u;
@@ -689,6 +693,9 @@ void residual(mg_ctx *c, const double *u, const double *W, bool want_M, double *
     a.rc = rc;
     a.rW = rW;
     a.partials = norms ? c->part : nullptr;
+    a.d1 = first && r && rc ? c->pd1[0] : nullptr;
+    a.d1W = first && rW && want_M ? c->wd1[0] : nullptr;
+    a.idiagW = 1.0 / (-100.0 * c->geo[0].inv12h2);
     a.want_M = want_M ? 1 : 0;
     a.conformal = (c->p.flags & MG_FLAG_CONFORMAL_MATTER) ? 1 : 0;
     int64_t nb = nblk(c->cells[0]);
@@ -716,9 +723,10 @@ void step_W(mg_ctx *c, const double *u, double *W, bool residual_done)
 {
     if (!residual_done) {
         source_mean(c, u);
-        residual<T>(c, u, W, true, nullptr, nullptr, nullptr, nullptr, nullptr, c->wr[0], false);
+        residual<T>(c, u, W, true, nullptr, nullptr, nullptr, nullptr, nullptr, c->wr[0], false, true);
     }
-    vcycle_W<T>(c, 0);
+    // the residual (this step's or the evaluation's) wrote the first pass into wd1
+    vcycle_W<T>(c, 0, true);
     const int64_t m = c->cells[0];
     const int64_t nb = nblk(m);
     hipLaunchKernelGGL(k_sum3<T>, dim3(nb), dim3(kBlock), 0, c->s, (const T *)c->wd0[0], m, c->part);
@@ -737,9 +745,10 @@ template <typename T>
 void step_psi(mg_ctx *c, double *u, const double *W, bool residual_done)
 {
     if (!residual_done)
-        residual<T>(c, u, W, false, nullptr, nullptr, nullptr, c->pr[0], c->pc[0], nullptr, false);
+        residual<T>(c, u, W, false, nullptr, nullptr, nullptr, c->pr[0], c->pc[0], nullptr, false, true);
     restrict_coefficients<T>(c);
-    vcycle_psi<T>(c, 0);
+    // the residual (this step's or the evaluation's) wrote the first pass into pd1
+    vcycle_psi<T>(c, 0, true);
     const int64_t m = c->cells[0];
     {
         Probe pr(c, MG_PROBE_UPDATE, 0);
@@ -777,9 +786,9 @@ void evaluate(mg_ctx *c, const double *u, const double *W, bool want_M, bool aft
 {
     source_mean(c, u);
     if (c->momentum)
-        residual<T>(c, u, W, true, nullptr, nullptr, nullptr, nullptr, nullptr, c->wr[0], true);
+        residual<T>(c, u, W, true, nullptr, nullptr, nullptr, nullptr, nullptr, c->wr[0], true, true);
     else
-        residual<T>(c, u, W, want_M, nullptr, nullptr, nullptr, c->pr[0], c->pc[0], nullptr, true);
+        residual<T>(c, u, W, want_M, nullptr, nullptr, nullptr, c->pr[0], c->pc[0], nullptr, true, true);
     if (c->batched)
         hipLaunchKernelGGL(k_batch_check, dim3(1), dim3(64), 0, c->s, c->scal, (int)S_ACTIVE, (int)S_ITERS,
                            (int)S_DIVERGED, 1.0 / (double)c->cells[0], c->batch_tol, c->momentum ? 1 : 0,

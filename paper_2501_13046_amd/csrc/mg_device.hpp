@@ -234,6 +234,17 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[NV], unsigned max
     }
 }
 
+// A value held in one register from here on, rounded on its own: the compiler
+// can neither recompute it nor fuse the operation that produced it into the
+// next one (a diagonal term -90/(12 h^2) + c must round the product first in
+// every kernel, or FP64 results would depend on how often a kernel reuses it).
+template <typename T>
+__device__ __forceinline__ T pinned(T v)
+{
+    asm("" : "+v"(v));
+    return v;
+}
+
 // Element i of an array addressed by a 32-bit byte offset from its (uniform)
 // base: one address register per access instead of a 64-bit sum.
 template <typename P>

@@ -44,9 +44,36 @@ struct ResArgs {
     double *H, *M, *c;
     void *r, *rc, *rW; // T
     double *partials;  // 4 per block
+    // first colour pass of the finest level from a zero correction (T; may be
+    // null): d1 from r and rc (psi), d1W from rW times idiagW (W)
+    void *d1, *d1W;
+    double idiagW;
     int want_M;        // compute momentum residual
     int conformal;     // matter given as rho_bar = psi^8 rho, S_bar = psi^6 S
 };
+
+// The finest level's first colour pass from a zero correction at cell (x, y, z),
+// written beside the right-hand side (colour 0: r / diag as the pass kernels
+// form it; colour 1: 0) so that the V-cycle starts with the second pass.
+template <int BC, typename T>
+__device__ __forceinline__ void first_pass_fine(const Geo &g, const ResArgs &a, unsigned q, int x, int y, int z,
+                                                T r, T rc, const T *rW)
+{
+    const bool first = ((x + y + z) & 1) == 0;
+    if (a.d1) {
+        T diag;
+        if constexpr (BC == kBcPeriodic)
+            diag = pinned((T)(-90.0 * g.inv12h2)) + rc;
+        else
+            diag = pinned((T)(lap_diag_sum<BC>(g, x, y, z) * g.inv12h2)) + rc;
+        elt((T *)a.d1, q) = first ? T(0) + (r - T(0)) / diag : T(0);
+    }
+    if (a.d1W) {
+        const unsigned m = (unsigned)g.n * g.n * g.n;
+#pragma unroll
+        for (int s2 = 0; s2 < 3; s2++) elt((T *)a.d1W + (size_t)s2 * m, q) = first ? rW[s2] * (T)a.idiagW : T(0);
+    }
+}
 
 template <int BC, typename T>
 __global__ void __launch_bounds__(kBlock) k_residual(Geo g, ResArgs a)
@@ -128,10 +155,12 @@ __global__ void __launch_bounds__(kBlock) k_residual(Geo g, ResArgs a)
                    (a.K2 / 12.0) * psi5 + 0.125 * A2 * ipsi7;
         if (a.f) H += a.f[q];
         const double c = dmatter - (5.0 * a.K2 / 12.0) * psi4 - 0.875 * A2 * ipsi8;
+        const T rT = pinned((T)(-H)), rcT = pinned((T)c);
+        const T rW[3] = {pinned((T)(-Mv[0])), pinned((T)(-Mv[1])), pinned((T)(-Mv[2]))};
         if (a.H) a.H[q] = H;
         if (a.c) a.c[q] = c;
-        if (a.r) ((T *)a.r)[q] = (T)(-H);
-        if (a.rc) ((T *)a.rc)[q] = (T)c;
+        if (a.r) ((T *)a.r)[q] = rT;
+        if (a.rc) ((T *)a.rc)[q] = rcT;
         if (a.want_M) {
             if (a.M) {
                 a.M[q] = Mv[0];
@@ -139,12 +168,13 @@ __global__ void __launch_bounds__(kBlock) k_residual(Geo g, ResArgs a)
                 a.M[2 * m + q] = Mv[2];
             }
             if (a.rW) {
-                ((T *)a.rW)[q] = (T)(-Mv[0]);
-                ((T *)a.rW)[m + q] = (T)(-Mv[1]);
-                ((T *)a.rW)[2 * m + q] = (T)(-Mv[2]);
+                ((T *)a.rW)[q] = rW[0];
+                ((T *)a.rW)[m + q] = rW[1];
+                ((T *)a.rW)[2 * m + q] = rW[2];
             }
             m2 = Mv[0] * Mv[0] + Mv[1] * Mv[1] + Mv[2] * Mv[2];
         }
+        if (a.d1 || a.d1W) first_pass_fine<BC, T>(g, a, (unsigned)q, i, j, k, rT, rcT, rW);
         hv = H;
     }
     if (a.partials) {
@@ -236,7 +266,7 @@ __device__ __forceinline__ void psi_pass_cell(const Geo &g, const T *__restrict_
     const T cv = c[q];
     const T h2 = (T)g.inv12h2;
     const T Ad = lap_sum<T>(D, i, j, k, x) * h2 + cv * x;
-    const T diag = (T)(lap_diag_sum<BC>(g, i, j, k) * g.inv12h2) + cv;
+    const T diag = pinned((T)(lap_diag_sum<BC>(g, i, j, k) * g.inv12h2)) + cv;
     out[q] = x + (r[q] - Ad) / diag;
 }
 
@@ -454,7 +484,7 @@ __global__ void __launch_bounds__(kBlock) k_pass_psi_pairs(Geo g, const T *__res
     D.get_lap(WrapTaps<T>{in, o});
     const T v = D.c(), cv = elt(c, qa);
     const T Ad = (D.dxx(v) + D.dyy(v) + D.dzz(v)) * (T)g.inv12h2 + cv * v;
-    const T diag = (T)(-90.0 * g.inv12h2) + cv;
+    const T diag = pinned((T)(-90.0 * g.inv12h2)) + cv;
     elt(out, qb) = elt(in, qb);
     elt(out, qa) = v + (elt(r, qa) - Ad) / diag;
 }
@@ -513,9 +543,9 @@ __device__ __forceinline__ T first_pass_psi(const Geo &gc, int I, int J, int K, 
     if (((I + J + K) & 1) != 0) return T(0);
     T diag;
     if constexpr (BC == kBcPeriodic)
-        diag = (T)(-90.0 * gc.inv12h2) + ccv;
+        diag = pinned((T)(-90.0 * gc.inv12h2)) + ccv;
     else
-        diag = (T)(lap_diag_sum<BC>(gc, I, J, K) * gc.inv12h2) + ccv;
+        diag = pinned((T)(lap_diag_sum<BC>(gc, I, J, K) * gc.inv12h2)) + ccv;
     return T(0) + (rcv - T(0)) / diag;
 }
 

@@ -228,7 +228,7 @@ __device__ __forceinline__ void psi_cell(const Geo &g, const T *row0, const T *_
     if constexpr (BC == kBcPeriodic)
         diag = dlap + cv;
     else
-        diag = (T)(lap_diag_sum<BC>(g, x, y, za) * g.inv12h2) + cv;
+        diag = pinned((T)(lap_diag_sum<BC>(g, x, y, za) * g.inv12h2)) + cv;
     out[qrow + za] = v + (r[qrow + za] - Ad) / diag;
     out[qrow + zb] = D.template at<0, 0, (PAR ? -1 : 1)>();
 }
@@ -260,7 +260,7 @@ __global__ void __launch_bounds__(kTY *kLanes) k_pass_psi_tiled(Geo g, TileMap t
     load_brick<BC, T, TX>(lds, Acc<BC, T>{in, g}, x0, y0, z0);
     __syncthreads();
     const T h2 = (T)g.inv12h2;
-    const T dlap = (T)(-90.0 * g.inv12h2);
+    const T dlap = pinned((T)(-90.0 * g.inv12h2));
     psi_cells<BC, T, TX, 0>(g, &lds[0][ty][0], r, c, out, x0, y0 + ty, z0, lane, colour, h2, dlap);
 }
 
@@ -982,16 +982,28 @@ __global__ void __launch_bounds__(kTY *kLanes) k_residual_tiled(Geo g, TileMap t
         const double cc = dmatter - (5.0 * K2 / 12.0) * psi4 - 0.875 * A2 * ipsi8;
         if (a.H) elt(a.H, q) = H;
         if (a.c) elt(a.c, q) = cc;
-        if (a.r) elt((T *)a.r, q) = (T)(-H);
-        if (a.rc) elt((T *)a.rc, q) = (T)cc;
+        const T rT = pinned((T)(-H)), rcT = pinned((T)cc);
+        if (a.r) elt((T *)a.r, q) = rT;
+        if (a.rc) elt((T *)a.rc, q) = rcT;
+        if (a.d1) {
+            ResArgs ap = a;
+            ap.d1W = nullptr;
+            first_pass_fine<BC, T>(g, ap, q, x, y, z, rT, rcT, nullptr);
+        }
         if (a.want_M) {
             if (a.M) {
 #pragma unroll
                 for (int s2 = 0; s2 < 3; s2++) elt(a.M + (size_t)s2 * m, q) = Mv[s2];
             }
+            const T rW[3] = {pinned((T)(-Mv[0])), pinned((T)(-Mv[1])), pinned((T)(-Mv[2]))};
             if (a.rW) {
 #pragma unroll
-                for (int s2 = 0; s2 < 3; s2++) elt((T *)a.rW + (size_t)s2 * m, q) = (T)(-Mv[s2]);
+                for (int s2 = 0; s2 < 3; s2++) elt((T *)a.rW + (size_t)s2 * m, q) = rW[s2];
+            }
+            if (a.d1W) {
+                ResArgs aw = a;
+                aw.d1 = nullptr;
+                first_pass_fine<BC, T>(g, aw, q, x, y, z, T(0), T(0), rW);
             }
             const double m2 = Mv[0] * Mv[0] + Mv[1] * Mv[1] + Mv[2] * Mv[2];
             msum += m2;
