@@ -305,7 +305,14 @@ void launch_conv(hipStream_t s, const Layer &ly, bool transposed, int n, const u
     a.zout1 = o1.zout;
     // the brick kernel reads activations as stored (no SiLU on load)
     const bool brick = brick_ok(n) && !act1 && !act2;
-    const int ntb = std::min(a.ntile, 4);
+    // output tiles per block: all of them (the staged halo and every A operand
+    // read once per block) unless the grid would then have fewer than ~4 blocks
+    // per CU (32^3 and 16^3 levels: 128 and 16 bricks)
+    int ntb = std::min(a.ntile, 4);
+    if (brick) {
+        const int64_t bricks = (int64_t)n * n * n / 256;
+        while (ntb > 1 && bricks * ceil_div(a.ntile, ntb) < 1024) ntb--;
+    }
     const unsigned gy = (unsigned)ceil_div(a.ntile, ntb);
     if (!brick) {
         const int64_t V = (int64_t)n * n * n;
