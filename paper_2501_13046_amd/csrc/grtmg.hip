@@ -636,12 +636,13 @@ void vcycle_W(mg_ctx *c, int l, bool first_done = false)
 
 bool source_mean_needed(const mg_ctx *c) { return c->S && c->p.bc == MG_BC_PERIODIC; }
 
-void source_mean(mg_ctx *c, const double *u)
+// sums_ready: the psi update just wrote the partial sums at this state.
+void source_mean(mg_ctx *c, const double *u, bool sums_ready = false)
 {
     if (!source_mean_needed(c)) return;
     const Geo &g = c->geo[0];
-    const int64_t nb = nblk(c->cells[0]);
-    if (c->p.bc == MG_BC_PERIODIC)
+    const int64_t nb = sum_blocks(c->cells[0]);
+    if (c->p.bc == MG_BC_PERIODIC && !sums_ready)
         hipLaunchKernelGGL(k_source_sum<kBcPeriodic>, dim3(nb), dim3(kBlock), 0, c->s, g, u, c->S,
                            c->p.puncture_mass, (c->p.flags & MG_FLAG_CONFORMAL_MATTER) ? 1 : 0,
                            c->part);
@@ -728,9 +729,9 @@ void step_W(mg_ctx *c, const double *u, double *W, bool residual_done)
     // the residual (this step's or the evaluation's) wrote the first pass into wd1
     vcycle_W<T>(c, 0, true);
     const int64_t m = c->cells[0];
-    const int64_t nb = nblk(m);
-    hipLaunchKernelGGL(k_sum3<T>, dim3(nb), dim3(kBlock), 0, c->s, (const T *)c->wd0[0], m, c->part);
-    hipLaunchKernelGGL(k_reduce_final<3>, dim3(1), dim3(kBlock), 0, c->s, (const double *)c->part, nb, 0u,
+    const int64_t nb = nblk(m), sb = sum_blocks(m);
+    hipLaunchKernelGGL(k_sum3<T>, dim3(sb), dim3(kBlock), 0, c->s, (const T *)c->wd0[0], m, c->part);
+    hipLaunchKernelGGL(k_reduce_final<3>, dim3(1), dim3(kBlock), 0, c->s, (const double *)c->part, sb, 0u,
                        1.0 / (double)m, c->scal + S_MEAND);
     {
         Probe pr(c, MG_PROBE_UPDATE, 0);
@@ -752,8 +753,14 @@ void step_psi(mg_ctx *c, double *u, const double *W, bool residual_done)
     const int64_t m = c->cells[0];
     {
         Probe pr(c, MG_PROBE_UPDATE, 0);
-        hipLaunchKernelGGL(k_update_u<T>, dim3(nblk(m)), dim3(kBlock), 0, c->s, u, (const T *)c->pd0[0], m,
-                           c->batched ? (const double *)(c->scal + S_ACTIVE) : nullptr);
+        const double *gate = c->batched ? (const double *)(c->scal + S_ACTIVE) : nullptr;
+        if (source_mean_needed(c)) // the update also sums the periodic source of the next evaluation
+            hipLaunchKernelGGL((k_update_u_source<kBcPeriodic, T>), dim3(sum_blocks(m)), dim3(kBlock), 0, c->s,
+                               c->geo[0], u, (const T *)c->pd0[0], gate, c->S, c->p.puncture_mass,
+                               (c->p.flags & MG_FLAG_CONFORMAL_MATTER) ? 1 : 0, c->part);
+        else
+            hipLaunchKernelGGL(k_update_u<T>, dim3(nblk(m)), dim3(kBlock), 0, c->s, u, (const T *)c->pd0[0], m,
+                               gate);
     }
     c->vc_psi++;
 }
@@ -782,9 +789,10 @@ mg_status fetch_norms(mg_ctx *c, double out[4], double *flag_psi)
 // Evaluation of a state: norms (+ the residual the next update step uses);
 // batch members also update their convergence flags.
 template <typename T>
-void evaluate(mg_ctx *c, const double *u, const double *W, bool want_M, bool after_update = true)
+void evaluate(mg_ctx *c, const double *u, const double *W, bool want_M, bool after_update = true,
+              bool sums_ready = false)
 {
-    source_mean(c, u);
+    source_mean(c, u, sums_ready);
     if (c->momentum)
         residual<T>(c, u, W, true, nullptr, nullptr, nullptr, nullptr, nullptr, c->wr[0], true, true);
     else
@@ -805,7 +813,7 @@ void outer_body(mg_ctx *c, double *u, double *W, bool want_M)
     } else {
         step_psi<T>(c, u, W, true);
     }
-    evaluate<T>(c, u, W, want_M);
+    evaluate<T>(c, u, W, want_M, true, true); // the psi update summed the source
 }
 
 void drop_graph(mg_ctx *c)

@@ -183,22 +183,30 @@ __global__ void __launch_bounds__(kBlock) k_residual(Geo g, ResArgs a)
     }
 }
 
+// Cells per thread of the whole-grid sums below (fewer, fuller partial sums
+// for the single-block final reduction).
+constexpr int kSumCells = 8;
+inline unsigned sum_blocks(int64_t m) { return (unsigned)((m + kBlock * kSumCells - 1) / (kBlock * kSumCells)); }
+
 // Per-block partial sums of 8 pi psi^6 S_a (for the periodic mean removal).
 template <int BC>
 __global__ void __launch_bounds__(kBlock) k_source_sum(Geo g, const double *u, const double *S,
                                                        double pmass, int conformal,
                                                        double *partials)
 {
-    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int n = g.n;
     const int64_t m = (int64_t)n * n * n;
-    int i, j, k;
     double v[3] = {0.0, 0.0, 0.0};
-    if (cell_of(tid, n, i, j, k)) {
-        const double psi = psi0_at(g, pmass, i, j, k) + u[tid];
-        const double p2 = psi * psi, p6 = conformal ? 1.0 : p2 * p2 * p2;
 #pragma unroll
-        for (int s = 0; s < 3; s++) v[s] = 8.0 * kPi * p6 * S[s * m + tid];
+    for (int c = 0; c < kSumCells; c++) {
+        const int64_t tid = ((int64_t)blockIdx.x * kSumCells + c) * kBlock + threadIdx.x;
+        int i, j, k;
+        if (cell_of(tid, n, i, j, k)) {
+            const double psi = psi0_at(g, pmass, i, j, k) + u[tid];
+            const double p2 = psi * psi, p6 = conformal ? 1.0 : p2 * p2 * p2;
+#pragma unroll
+            for (int s = 0; s < 3; s++) v[s] += 8.0 * kPi * p6 * S[s * m + tid];
+        }
     }
     block_reduce_store<3>(v, 0u, partials + 3 * (int64_t)blockIdx.x);
 }
@@ -207,12 +215,15 @@ __global__ void __launch_bounds__(kBlock) k_source_sum(Geo g, const double *u, c
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_sum3(const T *a, int64_t m, double *partials)
 {
-    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     double v[3] = {0.0, 0.0, 0.0};
-    if (q < m) {
-        v[0] = (double)a[q];
-        v[1] = (double)a[m + q];
-        v[2] = (double)a[2 * m + q];
+#pragma unroll
+    for (int c = 0; c < kSumCells; c++) {
+        const int64_t q = ((int64_t)blockIdx.x * kSumCells + c) * kBlock + threadIdx.x;
+        if (q < m) {
+            v[0] += (double)a[q];
+            v[1] += (double)a[m + q];
+            v[2] += (double)a[2 * m + q];
+        }
     }
     block_reduce_store<3>(v, 0u, partials + 3 * (int64_t)blockIdx.x);
 }
@@ -227,6 +238,7 @@ __global__ void __launch_bounds__(kBlock) k_reduce_final(const double *partials,
     double v[NV];
 #pragma unroll
     for (int q = 0; q < NV; q++) v[q] = 0.0;
+#pragma unroll 4
     for (int64_t b = threadIdx.x; b < nblocks; b += kBlock)
 #pragma unroll
         for (int q = 0; q < NV; q++) {
@@ -1314,6 +1326,37 @@ __global__ void __launch_bounds__(kBlock) k_update_u(double *u, const T *d, int6
     if (gate && *gate == 0.0) return;
     const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (q < m) u[q] += (double)d[q];
+}
+
+// k_update_u followed by k_source_sum's partial sums of 8 pi psi^6 S_a at the
+// updated state, in one pass (same cells per thread and summation order as
+// k_source_sum).
+template <int BC, typename T>
+__global__ void __launch_bounds__(kBlock) k_update_u_source(Geo g, double *u, const T *d, const double *gate,
+                                                            const double *S, double pmass, int conformal,
+                                                            double *partials)
+{
+    const bool upd = !(gate && *gate == 0.0);
+    const int n = g.n;
+    const int64_t m = (int64_t)n * n * n;
+    double v[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < kSumCells; c++) {
+        const int64_t tid = ((int64_t)blockIdx.x * kSumCells + c) * kBlock + threadIdx.x;
+        int i, j, k;
+        if (cell_of(tid, n, i, j, k)) {
+            double uq = u[tid];
+            if (upd) {
+                uq += (double)d[tid];
+                u[tid] = uq;
+            }
+            const double psi = psi0_at(g, pmass, i, j, k) + uq;
+            const double p2 = psi * psi, p6 = conformal ? 1.0 : p2 * p2 * p2;
+#pragma unroll
+            for (int s = 0; s < 3; s++) v[s] += 8.0 * kPi * p6 * S[s * m + tid];
+        }
+    }
+    block_reduce_store<3>(v, 0u, partials + 3 * (int64_t)blockIdx.x);
 }
 
 // W_a += dW_a - mean_a (mean: device, 3 values); gate as for k_update_u
