@@ -228,11 +228,14 @@ mg_status mg_fmg_start(mg_ctx *cc, mg_ctx *cf, double *d_uc, double *d_Wc, doubl
  * planes; residual {1, 2, 4}.
  * Two further families choose how the coarse levels of each V-cycle run: as
  * separate grid launches (0, the default) or as one workgroup-resident "tail"
- * kernel per V-cycle (1) that runs every level from the first of at most 16^3
- * (psi) / 8^3 (W) cells down to the coarsest and back, phase by phase with
- * block barriers (same per-cell arithmetic; the restriction sums group the 8
- * children differently, so results agree to rounding).  Their `level` is the
- * tail's first level; mg_autotune times one whole V-cycle each way.
+ * kernel per V-cycle (1) that runs every level from its first one down to the
+ * coarsest and back, phase by phase with block barriers, on arrays held in
+ * LDS (same per-cell arithmetic; the restriction sums group the 8 children
+ * differently, so results agree to rounding).  The tail starts at the first
+ * level from which the cells of all levels down to the coarsest sum to at
+ * most 1971 (psi; W in FP32) or 584 (W, FP64), spanning at most 4 levels
+ * (e.g. 8^3 for a hierarchy of powers of two).  Their `level`
+ * is the tail's first level; mg_autotune times one whole V-cycle each way.
  */
 enum { MG_TUNE_PASS_PSI = 1, MG_TUNE_PASS_W = 2, MG_TUNE_RESIDUAL = 3, MG_TUNE_TAIL_PSI = 4, MG_TUNE_TAIL_W = 5 };
 typedef struct mg_tune {

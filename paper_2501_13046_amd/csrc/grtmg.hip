@@ -232,20 +232,26 @@ void init_geo(mg_ctx *c)
         c->tileW[l] = w_tileable(c->n[l]) ? make_tilemap<kBrickW>(c->n[l]) : TileMap{0, 0, 0, 0};
     }
     c->tileR = make_rtilemap<kBrickR>(c->n[0]);
-    // V-cycle tails: psi from the first level of at most 16^3 cells (13-point
-    // stencil: cheap in one workgroup), W from at most 8^3 (the Lame stencil of a
-    // 16^3 pass is faster spread over a grid); at least one level above the
-    // coarsest, at most kMaxTail levels, coarsest psi system solvable in registers.
+    // V-cycle tails: from the first level whose levels down to the coarsest fit
+    // the tail's LDS arrays; at least one level above the coarsest, at most
+    // kMaxTail levels, coarsest psi system solvable in registers.
     c->tail_psi = c->tail_W = -1;
     c->tail_psi_on = c->tail_W_on = false;
+    const int cap_psi = c->f32 ? TailCap<float>::kPsi : TailCap<double>::kPsi;
+    const int cap_W = c->f32 ? TailCap<float>::kW : TailCap<double>::kW;
+    auto cells_from = [&](int l) {
+        int64_t s = 0;
+        for (int q = l; q < c->L; q++) s += c->cells[q];
+        return s;
+    };
     for (int l = 0; l + 1 < c->L; l++)
-        if (c->n[l] <= 16 && c->L - l <= kMaxTail && wave_solvable(c->m_psi)) {
+        if (cells_from(l) <= cap_psi && c->L - l <= kMaxTail && wave_solvable(c->m_psi)) {
             c->tail_psi = l;
             break;
         }
     if (c->momentum)
         for (int l = 0; l + 1 < c->L; l++)
-            if (c->n[l] <= 8 && c->L - l <= kMaxTail && c->m_W <= 1536) {
+            if (cells_from(l) <= cap_W && c->L - l <= kMaxTail && c->m_W <= 1536) {
                 c->tail_W = l;
                 break;
             }
@@ -461,14 +467,14 @@ void prolong_add(mg_ctx *c, int lc, const T *coarse, T *fine, int ncomp)
 // the coefficient c of each coarser level is restricted by the defect
 // restriction that produces that level's right-hand side (the level is not
 // smoothed before), so no separate sweep over the levels is needed.
-bool c_with_defect(const mg_ctx *c) { return !c->tail_psi_on && wave_solvable(c->m_psi); }
+// A tail restricts c below its own first level.
+bool c_with_defect(const mg_ctx *c) { return wave_solvable(c->m_psi); }
 
 template <typename T>
 void restrict_coefficients(mg_ctx *c)
 {
     if (c_with_defect(c)) return; // each level's c comes with its defect restriction
-    const int stop = c->tail_psi_on ? c->tail_psi : c->L - 1; // the tail restricts below its first level
-    for (int l = 0; l < stop; l++)
+    for (int l = 0; l + 1 < c->L; l++)
         hipLaunchKernelGGL(k_restrict<T>, dim3(nblk(c->cells[l + 1])), dim3(kBlock), 0, c->s, c->n[l],
                            (const T *)c->pc[l], (T *)c->pc[l + 1]);
     const int l = c->L - 1;
@@ -492,14 +498,10 @@ TailArgs<T> tail_args(mg_ctx *c, int l0, bool W)
     a.nl = c->L - l0;
     a.nu_pre = c->p.nu_pre;
     a.nu_post = c->p.nu_post;
-    for (int q = 0; q < a.nl; q++) {
-        const int l = l0 + q;
-        a.geo[q] = c->geo[l];
-        a.d0[q] = (T *)(W ? c->wd0[l] : c->pd0[l]);
-        a.d1[q] = (T *)(W ? c->wd1[l] : c->pd1[l]);
-        a.r[q] = (T *)(W ? c->wr[l] : c->pr[l]);
-        a.c[q] = W ? nullptr : (T *)c->pc[l];
-    }
+    for (int q = 0; q < a.nl; q++) a.geo[q] = c->geo[l0 + q];
+    a.r0 = (const T *)(W ? c->wr[l0] : c->pr[l0]);
+    a.c0 = W ? nullptr : (const T *)c->pc[l0];
+    a.d0 = (T *)(W ? c->wd0[l0] : c->pd0[l0]);
     a.inv = c->inv_W;
     a.flag = c->scal + S_FLAG_PSI;
     return a;
@@ -552,8 +554,9 @@ void vcycle_psi(mg_ctx *c, int l, bool first_done = false)
     }
     if (!first_done) fill<T>(c->s, (T *)c->pd0[l], c->cells[l], T(0));
     smooth_psi<T>(c, l, c->p.nu_pre, first_done);
-    // the next level's first pass comes with its defect when that level is smoothed
-    const bool next_first = c_with_defect(c) && l + 2 < c->L;
+    // the next level's first pass comes with its defect when that level is
+    // smoothed by grid launches (a tail starts from zero in LDS)
+    const bool next_first = c_with_defect(c) && l + 2 < c->L && !(c->tail_psi_on && l + 1 == c->tail_psi);
     defect_restrict_psi<T>(c, l, (const T *)c->pd0[l], (const T *)c->pr[l], (const T *)c->pc[l],
                            (T *)c->pr[l + 1], c_with_defect(c) ? (T *)c->pc[l + 1] : nullptr,
                            next_first ? (T *)c->pd1[l + 1] : nullptr);
@@ -624,7 +627,8 @@ void vcycle_W(mg_ctx *c, int l, bool first_done = false)
     }
     if (!first_done) fill<T>(c->s, (T *)c->wd0[l], 3 * c->cells[l], T(0));
     smooth_W<T>(c, l, c->p.nu_pre, first_done);
-    const bool next_first = l + 2 < c->L; // the next level is smoothed (not the coarsest)
+    // the next level is smoothed by grid launches (not the coarsest, not a tail)
+    const bool next_first = l + 2 < c->L && !(c->tail_W_on && l + 1 == c->tail_W);
     defect_restrict_W<T>(c, l, (const T *)c->wd0[l], (const T *)c->wr[l], (T *)c->wr[l + 1],
                          next_first ? (T *)c->wd1[l + 1] : nullptr);
     vcycle_W<T>(c, l + 1, next_first);

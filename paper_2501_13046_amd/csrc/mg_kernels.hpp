@@ -13,14 +13,19 @@ namespace grtmg {
 
 constexpr double kPi = 3.14159265358979323846;
 
+// Cell (i, j, k) of linear index tid (z fastest); false past the grid.  The
+// grids hold fewer than 2^32 cells (validated at the API), so the division
+// runs in 32 bits: a 64-bit division by a runtime n costs ~10x the instructions.
 __device__ __forceinline__ bool cell_of(int64_t tid, int n, int &i, int &j, int &k)
 {
     const int64_t cells = (int64_t)n * n * n;
     if (tid >= cells) return false;
-    k = (int)(tid % n);
-    int64_t t = tid / n;
-    j = (int)(t % n);
-    i = (int)(t / n);
+    const unsigned t = (unsigned)tid, un = (unsigned)n;
+    const unsigned r = t / un;
+    k = (int)(t - r * un);
+    const unsigned s = r / un;
+    j = (int)(r - s * un);
+    i = (int)s;
     return true;
 }
 
@@ -1020,21 +1025,37 @@ __global__ void __launch_bounds__(kBlock) k_restrict(int nf, const T *__restrict
 }
 
 // ---------------------------------------------------------------------------------------
-// Coarsest psi solve (m = M unknowns, M <= 64, a compile-time constant so the
-// pivot steps unroll with static register indexing): Gauss-Jordan with
+// Coarsest psi solve (m = M unknowns, M <= 64, a compile-time constant that
+// fixes the number of columns each wave holds in registers): Gauss-Jordan with
 // partial pivoting on [A | r], A assembled from the level's stencil and c.
 // Pivot: the largest |a_ik| over unused rows, found with one wave max of a
 // packed key (float bits of |a_ik|, low 6 bits replaced by 63 - row so ties go
-// to the lowest row).  *flag = 1 if no non-zero pivot exists.
+// to the lowest row).  *flag = 1 if no non-zero pivot exists (published as
+// pivot row -1).
+// The pivot rows are not scaled: step k subtracts (a_ik / a_pk) times row p
+// from every other row, and the end divides the right-hand side of pivot row
+// perm[q] by that row's pivot a_{perm[q], q} (recorded at its step), so each
+// step is one FMA per matrix element.  Columns already eliminated keep
+// receiving the update (their values are never read again), so no element
+// needs a select.
 // The solve is spread over a block of 16 waves: lanes hold rows, the columns
 // of [A | r] are dealt round-robin to the waves (wave w holds columns w,
 // w + 16, ...).  At step k the wave owning column k picks the pivot and
-// publishes the pivot row index, its reciprocal and the row factors
-// a_ik / a_pk in LDS (double-buffered: one barrier per step); every wave then
-// updates its own columns, reading the pivot row's values from lane p of its
-// own registers.
+// publishes the pivot row index and the row factors in LDS (double-buffered:
+// one barrier per step); every wave then updates its own columns, reading the
+// pivot row's values from lane p of its own registers (v_readlane: p is
+// uniform).  The step loop is not unrolled: the kernel runs once per launch,
+// and an unrolled body of every step would not stay in the instruction cache.
 // ---------------------------------------------------------------------------------------
 constexpr int kGjWaves = 16;
+
+__device__ __forceinline__ double readlane_f64(double x, int l)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(unsigned)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+    return __hiloint2double(hi, lo);
+}
 
 // Called by every thread of a block of kGjWaves waves.
 template <int BC, typename T, int M>
@@ -1044,11 +1065,11 @@ __device__ __forceinline__ void coarse_psi_block_solve(const Geo &g, const T *c,
     constexpr int S = (NC + kGjWaves - 1) / kGjWaves;
     __shared__ double A[M][NC + 1];
     __shared__ double fac[2][kWave];
-    __shared__ double pinv[2];
     __shared__ int piv[2];
     __shared__ int perm[M];
-    __shared__ int bad;
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    __shared__ double pdiag[M];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int n = g.n;
     if (threadIdx.x < M) {
         const int row = threadIdx.x;
@@ -1075,7 +1096,6 @@ __device__ __forceinline__ void coarse_psi_block_solve(const Geo &g, const T *c,
         A[row][row] += (double)c[row];
         A[row][M] = (double)r[row];
     }
-    if (threadIdx.x == 0) bad = 0;
     __syncthreads();
     double v[S];
 #pragma unroll
@@ -1084,50 +1104,57 @@ __device__ __forceinline__ void coarse_psi_block_solve(const Geo &g, const T *c,
         v[q] = (lane < M && col < NC) ? A[lane][col] : 0.0;
     }
     uint64_t used = 0;
-#pragma unroll
+    bool singular = false;
+#pragma unroll 1
     for (int k = 0; k < M; k++) {
         const int buf = k & 1;
         if (wave == k % kGjWaves) {
-            const double a = v[k / kGjWaves];
+            double a = v[0];
+#pragma unroll
+            for (int q = 1; q < S; q++)
+                if (k / kGjWaves == q) a = v[q];
             unsigned key = 0u;
             if (lane < M && !((used >> lane) & 1ull)) {
                 const unsigned bits = __float_as_uint((float)fabs(a));
                 key = (bits & ~63u) | (63u - (unsigned)lane);
             }
-            const unsigned kmax = __reduce_max_sync(~0ull, key);
+            const unsigned kmax = __builtin_amdgcn_readfirstlane(__reduce_max_sync(~0ull, key));
             if ((kmax >> 6) == 0u) {
-                if (lane == 0) bad = 1;
+                if (lane == 0) piv[buf] = -1; // no non-zero pivot left
             } else {
                 const int p = 63 - (int)(kmax & 63u);
-                const double inv = 1.0 / __shfl(a, p, kWave);
-                fac[buf][lane] = a * inv;
+                const double ap = readlane_f64(a, p);
+                const double inv = 1.0 / ap;
+                fac[buf][lane] = lane == p ? 0.0 : a * inv;
                 if (lane == 0) {
                     piv[buf] = p;
-                    pinv[buf] = inv;
+                    pdiag[k] = ap;
                     perm[k] = p;
                 }
             }
         }
         __syncthreads();
-        if (bad) break;
-        const int p = piv[buf];
-        const double inv = pinv[buf], f = fac[buf][lane];
+        const int p = __builtin_amdgcn_readfirstlane(piv[buf]);
+        double f = fac[buf][lane];
+        asm volatile("" : "+v"(f)); // both LDS reads in flight together
+        if (p < 0) {
+            singular = true;
+            break;
+        }
         used |= 1ull << p;
 #pragma unroll
-        for (int q = 0; q < S; q++) {
-            const int col = wave + kGjWaves * q;
-            const double pj = __shfl(v[q], p, kWave);
-            if (col > k && col < NC) v[q] = (lane == p) ? v[q] * inv : v[q] - f * pj;
-        }
+        for (int q = 0; q < S; q++) v[q] = fma(-f, readlane_f64(v[q], p), v[q]);
     }
-    if (bad) {
+    if (singular) {
         if (threadIdx.x == 0) *flag = 1.0;
         return;
     }
-    // the scaled row perm[q] carries x_q in the last column (held by one wave)
-    if (wave == M % kGjWaves && lane < M) A[lane][M] = v[M / kGjWaves];
+    // the right-hand side column (held by one wave) through LDS
+#pragma unroll
+    for (int q = 0; q < S; q++)
+        if (wave + kGjWaves * q == M && lane < M) A[lane][M] = v[q];
     __syncthreads();
-    if (threadIdx.x < M) x[threadIdx.x] = (T)A[perm[threadIdx.x]][M];
+    if (threadIdx.x < M) x[threadIdx.x] = (T)(A[perm[threadIdx.x]][M] / pdiag[threadIdx.x]);
 }
 
 template <int BC, typename T, int M>
@@ -1140,58 +1167,91 @@ __global__ void __launch_bounds__(kGjWaves * kWave) k_coarse_psi_block(Geo g, co
 // ---------------------------------------------------------------------------------------
 // V-cycle tails: the coarse levels of one V-cycle (from level ls down to the
 // coarsest and back) run in one workgroup of kGjWaves waves, phase by phase
-// with block barriers, on data resident in L2 (these levels are too small to
-// fill the GPU: as separate launches every phase would cost a launch).  Each
+// with block barriers, on arrays resident in LDS (these levels are too small
+// to fill the GPU: as separate launches every phase would cost a launch).
+// The tail reads its first level's right-hand side (and psi coefficient) from
+// global memory, keeps every level's corrections, right-hand sides and
+// coefficients in LDS, and writes its first level's correction back.  Each
 // phase calls the same per-cell functions as the grid kernels.
 // ---------------------------------------------------------------------------------------
 constexpr int kTailThreads = kGjWaves * kWave;
 constexpr int kMaxTail = 4;
+
+// Cells of a tail summed over its levels: psi keeps d0, d1, r and c of every
+// level in LDS, W d0, d1 and r of three components.  One workgroup runs a
+// whole level per phase, so a tail pays off only while its first level is
+// small: 16^3 cells already take ~2 us per colour pass on one CU, more than
+// a grid launch of that pass.
+template <typename T>
+struct TailCap {
+    static constexpr int kPsi = 1971;                      // 12^3 + 6^3 + 3^3
+    static constexpr int kW = sizeof(T) == 4 ? 1971 : 584; // 12^3 + 6^3 + 3^3 ; 8^3 + 4^3 + 2^3
+};
 
 template <typename T>
 struct TailArgs {
     int nl;      // levels in the tail (the last one is the coarsest)
     int nu_pre, nu_post;
     Geo geo[kMaxTail];
-    T *d0[kMaxTail], *d1[kMaxTail], *r[kMaxTail], *c[kMaxTail];
+    const T *r0, *c0; // first level: right-hand side (3 components for W), psi coefficient
+    T *d0;            // first level: the correction (output)
     const double *inv; // W: coarsest inverse (column-major m x m), m = 3 cells
     double *flag;      // psi: set when the coarsest matrix is singular
 };
 
-template <typename T>
-__device__ __forceinline__ void tail_zero(T *a, int64_t count)
-{
-    for (int64_t q = threadIdx.x; q < count; q += kTailThreads) a[q] = T(0);
-}
+__device__ __forceinline__ int tail_cells(const Geo &g) { return g.n * g.n * g.n; }
 
 template <int BC, typename T>
-__device__ __forceinline__ void tail_psi_passes(const TailArgs<T> &a, int l, int sweeps)
+__device__ __forceinline__ void tail_psi_passes(const Geo &g, T *d0, T *d1, const T *r, const T *c, int sweeps)
 {
-    const Geo &g = a.geo[l];
-    const int n = g.n;
-    const int64_t m = (int64_t)n * n * n;
+    const int n = g.n, m = tail_cells(g);
     for (int s = 0; s < sweeps; s++)
         for (int colour = 0; colour < 2; colour++) {
-            const T *in = colour ? a.d1[l] : a.d0[l];
-            T *out = colour ? a.d0[l] : a.d1[l];
-            for (int64_t q = threadIdx.x; q < m; q += kTailThreads) {
+            const T *in = colour ? d1 : d0;
+            T *out = colour ? d0 : d1;
+            for (int q = threadIdx.x; q < m; q += kTailThreads) {
                 int i, j, k;
                 cell_of(q, n, i, j, k);
-                psi_pass_cell<BC, T>(g, in, out, a.r[l], a.c[l], colour, q, i, j, k);
+                psi_pass_cell<BC, T>(g, in, out, r, c, colour, q, i, j, k);
             }
             __syncthreads();
         }
 }
 
-// psi tail: restricts c below level 0 of the tail, then the V-cycle from the
-// tail's first level (its residual already restricted into r[0]).
+// psi tail: restricts c below its first level, then the V-cycle from the
+// tail's first level.  LDS: per level d0 | d1 | r | c, levels consecutive.
 template <int BC, typename T, int M>
 __global__ void __launch_bounds__(kTailThreads) k_tail_psi(TailArgs<T> a)
 {
+    __shared__ T buf[4 * TailCap<T>::kPsi];
     const int L = a.nl;
+    int off[kMaxTail] = {0, 0, 0, 0};
+    {
+        int o = 0;
+        for (int l = 0; l < L && l < kMaxTail; l++) {
+            off[l] = o;
+            o += 4 * tail_cells(a.geo[l]);
+        }
+        if (L < 2 || L > kMaxTail || o > 4 * TailCap<T>::kPsi) return; // the host picks tails that fit
+    }
+    auto D0 = [&](int l) { return buf + off[l]; };
+    auto D1 = [&](int l) { return buf + off[l] + tail_cells(a.geo[l]); };
+    auto R = [&](int l) { return buf + off[l] + 2 * tail_cells(a.geo[l]); };
+    auto C = [&](int l) { return buf + off[l] + 3 * tail_cells(a.geo[l]); };
+    {
+        const int m0 = tail_cells(a.geo[0]);
+        T *r0 = R(0), *c0 = C(0);
+        for (int q = threadIdx.x; q < m0; q += kTailThreads) {
+            r0[q] = a.r0[q];
+            c0[q] = a.c0[q];
+        }
+    }
+    __syncthreads();
     for (int l = 0; l + 1 < L; l++) {
-        const int nc = a.geo[l + 1].n;
-        const int64_t mc = (int64_t)nc * nc * nc;
-        for (int64_t q = threadIdx.x; q < mc; q += kTailThreads) {
+        const int nf = a.geo[l].n, nc = a.geo[l + 1].n, mc = tail_cells(a.geo[l + 1]);
+        const T *cf = C(l);
+        T *cc = C(l + 1);
+        for (int q = threadIdx.x; q < mc; q += kTailThreads) {
             int I, J, K;
             cell_of(q, nc, I, J, K);
             T s = T(0);
@@ -1200,74 +1260,111 @@ __global__ void __launch_bounds__(kTailThreads) k_tail_psi(TailArgs<T> a)
 #pragma unroll
                 for (int dj = 0; dj < 2; dj++)
 #pragma unroll
-                    for (int dk = 0; dk < 2; dk++) s += a.c[l][lidx(a.geo[l].n, 2 * I + di, 2 * J + dj, 2 * K + dk)];
-            a.c[l + 1][q] = s * T(0.125);
+                    for (int dk = 0; dk < 2; dk++) s += cf[lidx(nf, 2 * I + di, 2 * J + dj, 2 * K + dk)];
+            cc[q] = s * T(0.125);
         }
         __syncthreads();
     }
     for (int l = 0; l + 1 < L; l++) {
         const Geo &g = a.geo[l];
-        tail_zero(a.d0[l], (int64_t)g.n * g.n * g.n);
+        const int mf = tail_cells(g);
+        T *d0 = D0(l);
+        for (int q = threadIdx.x; q < mf; q += kTailThreads) d0[q] = T(0);
         __syncthreads();
-        tail_psi_passes<BC, T>(a, l, a.nu_pre);
-        const int64_t mf = (int64_t)g.n * g.n * g.n;
-        for (int64_t q = threadIdx.x; q < mf + (kTailThreads - 1); q += kTailThreads) {
-            if (q - threadIdx.x >= mf) break; // the whole block leaves together
-            defect_restrict_psi_child<BC, T>(g, a.d0[l], a.r[l], a.c[l], a.r[l + 1], (T *)nullptr, q);
-        }
-        __syncthreads();
-    }
-    coarse_psi_block_solve<BC, T, M>(a.geo[L - 1], a.c[L - 1], a.r[L - 1], a.d0[L - 1], a.flag);
-    __syncthreads();
-    for (int l = L - 2; l >= 0; l--) {
-        const int nf = a.geo[l].n;
-        const int64_t mf = (int64_t)nf * nf * nf;
-        for (int64_t q = threadIdx.x; q < mf; q += kTailThreads) {
-            int i, j, k;
-            cell_of(q, nf, i, j, k);
-            prolong_cell<BC, T>(a.geo[l + 1], a.d0[l + 1], a.d0[l], 1, q, i, j, k);
-        }
-        __syncthreads();
-        tail_psi_passes<BC, T>(a, l, a.nu_post);
-    }
-}
-
-// W tail (periodic): V-cycle from the tail's first level; the coarsest solve
-// applies the precomputed inverse to the mean-free residual (as k_coarse_apply,
-// one row per thread).
-template <typename T>
-__global__ void __launch_bounds__(kTailThreads) k_tail_W(TailArgs<T> a)
-{
-    __shared__ double rs[1536];
-    __shared__ double mean[3];
-    const int L = a.nl;
-    for (int l = 0; l + 1 < L; l++) {
-        const Geo &g = a.geo[l];
-        const int n = g.n;
-        const int64_t m = (int64_t)n * n * n;
-        tail_zero(a.d0[l], 3 * m);
-        __syncthreads();
-        for (int s = 0; s < a.nu_pre; s++)
-            for (int colour = 0; colour < 2; colour++) {
-                const T *in = colour ? a.d1[l] : a.d0[l];
-                T *out = colour ? a.d0[l] : a.d1[l];
-                for (int64_t q = threadIdx.x; q < m; q += kTailThreads) {
-                    int i, j, k;
-                    cell_of(q, n, i, j, k);
-                    W_pass_cell<T>(g, in, out, a.r[l], colour, q, i, j, k);
-                }
-                __syncthreads();
-            }
-        for (int64_t q = threadIdx.x; q < m + (kTailThreads - 1); q += kTailThreads) {
-            if (q - threadIdx.x >= m) break; // the whole block leaves together
-            defect_restrict_W_child<T>(g, a.d0[l], a.r[l], a.r[l + 1], q);
+        tail_psi_passes<BC, T>(g, D0(l), D1(l), R(l), C(l), a.nu_pre);
+        for (int q = threadIdx.x; q < mf + (kTailThreads - 1); q += kTailThreads) {
+            if (q - (int)threadIdx.x >= mf) break; // the whole block leaves together
+            defect_restrict_psi_child<BC, T>(g, D0(l), R(l), C(l), R(l + 1), (T *)nullptr, q);
         }
         __syncthreads();
     }
     {
-        const int nc = a.geo[L - 1].n;
-        const int cn = nc * nc * nc, m = 3 * cn;
-        for (int q = threadIdx.x; q < m; q += kTailThreads) rs[q] = (double)a.r[L - 1][q];
+        const int mc = tail_cells(a.geo[L - 1]);
+        T *x = D0(L - 1);
+        for (int q = threadIdx.x; q < mc; q += kTailThreads) x[q] = T(0); // stays 0 if singular
+        __syncthreads();
+        coarse_psi_block_solve<BC, T, M>(a.geo[L - 1], C(L - 1), R(L - 1), x, a.flag);
+        __syncthreads();
+    }
+    for (int l = L - 2; l >= 0; l--) {
+        const int nf = a.geo[l].n, mf = tail_cells(a.geo[l]);
+        for (int q = threadIdx.x; q < mf; q += kTailThreads) {
+            int i, j, k;
+            cell_of(q, nf, i, j, k);
+            prolong_cell<BC, T>(a.geo[l + 1], D0(l + 1), D0(l), 1, q, i, j, k);
+        }
+        __syncthreads();
+        tail_psi_passes<BC, T>(a.geo[l], D0(l), D1(l), R(l), C(l), a.nu_post);
+    }
+    {
+        const int m0 = tail_cells(a.geo[0]);
+        const T *d0 = D0(0);
+        for (int q = threadIdx.x; q < m0; q += kTailThreads) a.d0[q] = d0[q];
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void tail_W_passes(const Geo &g, T *d0, T *d1, const T *r, int sweeps)
+{
+    const int n = g.n, m = tail_cells(g);
+    for (int s = 0; s < sweeps; s++)
+        for (int colour = 0; colour < 2; colour++) {
+            const T *in = colour ? d1 : d0;
+            T *out = colour ? d0 : d1;
+            for (int q = threadIdx.x; q < m; q += kTailThreads) {
+                int i, j, k;
+                cell_of(q, n, i, j, k);
+                W_pass_cell<T>(g, in, out, r, colour, q, i, j, k);
+            }
+            __syncthreads();
+        }
+}
+
+// W tail (periodic): V-cycle from the tail's first level; the coarsest solve
+// applies the precomputed inverse to the mean-free residual (as k_coarse_apply).
+// LDS: per level d0 | d1 | r (three components each), levels consecutive.
+template <typename T>
+__global__ void __launch_bounds__(kTailThreads) k_tail_W(TailArgs<T> a)
+{
+    __shared__ T buf[9 * TailCap<T>::kW];
+    __shared__ double rs[1536];
+    __shared__ double mean[3];
+    const int L = a.nl;
+    int off[kMaxTail] = {0, 0, 0, 0};
+    {
+        int o = 0;
+        for (int l = 0; l < L && l < kMaxTail; l++) {
+            off[l] = o;
+            o += 9 * tail_cells(a.geo[l]);
+        }
+        if (L < 2 || L > kMaxTail || o > 9 * TailCap<T>::kW) return; // the host picks tails that fit
+    }
+    auto D0 = [&](int l) { return buf + off[l]; };
+    auto D1 = [&](int l) { return buf + off[l] + 3 * tail_cells(a.geo[l]); };
+    auto R = [&](int l) { return buf + off[l] + 6 * tail_cells(a.geo[l]); };
+    {
+        const int m0 = 3 * tail_cells(a.geo[0]);
+        T *r0 = R(0);
+        for (int q = threadIdx.x; q < m0; q += kTailThreads) r0[q] = a.r0[q];
+    }
+    __syncthreads();
+    for (int l = 0; l + 1 < L; l++) {
+        const Geo &g = a.geo[l];
+        const int m = tail_cells(g);
+        T *d0 = D0(l);
+        for (int q = threadIdx.x; q < 3 * m; q += kTailThreads) d0[q] = T(0);
+        __syncthreads();
+        tail_W_passes<T>(g, D0(l), D1(l), R(l), a.nu_pre);
+        for (int q = threadIdx.x; q < m + (kTailThreads - 1); q += kTailThreads) {
+            if (q - (int)threadIdx.x >= m) break; // the whole block leaves together
+            defect_restrict_W_child<T>(g, D0(l), R(l), R(l + 1), q);
+        }
+        __syncthreads();
+    }
+    {
+        const int cn = tail_cells(a.geo[L - 1]), m = 3 * cn;
+        const T *rc = R(L - 1);
+        for (int q = threadIdx.x; q < m; q += kTailThreads) rs[q] = (double)rc[q];
         __syncthreads();
         if (threadIdx.x < 3) {
             double s = 0.0;
@@ -1277,34 +1374,29 @@ __global__ void __launch_bounds__(kTailThreads) k_tail_W(TailArgs<T> a)
         __syncthreads();
         for (int q = threadIdx.x; q < m; q += kTailThreads) rs[q] -= mean[q / cn];
         __syncthreads();
+        T *x = D0(L - 1);
         for (int row = threadIdx.x; row < m; row += kTailThreads) {
             double s = 0.0;
             for (int col = 0; col < m; col++) s += a.inv[(int64_t)col * m + row] * rs[col];
-            a.d0[L - 1][row] = (T)s;
+            x[row] = (T)s;
         }
         __syncthreads();
     }
     for (int l = L - 2; l >= 0; l--) {
         const Geo &g = a.geo[l];
-        const int nf = g.n;
-        const int64_t mf = (int64_t)nf * nf * nf;
-        for (int64_t q = threadIdx.x; q < mf; q += kTailThreads) {
+        const int nf = g.n, mf = tail_cells(g);
+        for (int q = threadIdx.x; q < mf; q += kTailThreads) {
             int i, j, k;
             cell_of(q, nf, i, j, k);
-            prolong_cell<kBcPeriodic, T>(a.geo[l + 1], a.d0[l + 1], a.d0[l], 3, q, i, j, k);
+            prolong_cell<kBcPeriodic, T>(a.geo[l + 1], D0(l + 1), D0(l), 3, q, i, j, k);
         }
         __syncthreads();
-        for (int s = 0; s < a.nu_post; s++)
-            for (int colour = 0; colour < 2; colour++) {
-                const T *in = colour ? a.d1[l] : a.d0[l];
-                T *out = colour ? a.d0[l] : a.d1[l];
-                for (int64_t q = threadIdx.x; q < mf; q += kTailThreads) {
-                    int i, j, k;
-                    cell_of(q, nf, i, j, k);
-                    W_pass_cell<T>(g, in, out, a.r[l], colour, q, i, j, k);
-                }
-                __syncthreads();
-            }
+        tail_W_passes<T>(g, D0(l), D1(l), R(l), a.nu_post);
+    }
+    {
+        const int m0 = 3 * tail_cells(a.geo[0]);
+        const T *d0 = D0(0);
+        for (int q = threadIdx.x; q < m0; q += kTailThreads) a.d0[q] = d0[q];
     }
 }
 

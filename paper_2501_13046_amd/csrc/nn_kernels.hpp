@@ -183,10 +183,10 @@ __global__ void __launch_bounds__(kNBlock) k_conv3(ConvArgs a)
     for (int q = 0; q < kRows; q++) {
         int64_t v = vb + q * 16 + r;
         if (v >= V) v = V - 1; // rows past the end are computed but not stored
-        pz[q] = (int)(v % n);
-        const int64_t t = v / n;
-        py[q] = (int)(t % n);
-        px[q] = (int)(t / n);
+        const unsigned uv = (unsigned)v, un = (unsigned)n, t = uv / un; // n^3 < 2^32
+        pz[q] = (int)(uv - t * un);
+        py[q] = (int)(t % un);
+        px[q] = (int)(t / un);
     }
     f32x4 acc[kRows][NTB];
 #pragma unroll
@@ -503,10 +503,10 @@ __global__ void __launch_bounds__(kNBlock) k_conv3_wgrad(WgtArgs a)
             int64_t v = v0 + j;
             ok[j] = v < V;
             if (!ok[j]) v = 0;
-            pz[j] = (int)(v % n);
-            const int64_t t = v / n;
-            py[j] = (int)(t % n);
-            px[j] = (int)(t / n);
+            const unsigned uv = (unsigned)v, un = (unsigned)n, t = uv / un; // n^3 < 2^32
+            pz[j] = (int)(uv - t * un);
+            py[j] = (int)(t % un);
+            px[j] = (int)(t / un);
             av[j] = (ok[j] && co < a.cout) ? bf2f(a.dy[v * a.cy + co]) : 0.0f;
             dbias += av[j];
         }
