@@ -225,7 +225,8 @@ mg_status mg_fmg_start(mg_ctx *cc, mg_ctx *cf, double *d_uc, double *d_Wc, doubl
  * MG_ERR_INVALID otherwise).  Candidates: psi pass {2, 4, 8}; W pass {2, 4, 8,
  * 16} (FP32) or {1, 2, 8} (FP64), where depths up to 4 stage a whole brick and
  * 8 and 16 march a column of that many x planes through a ring of staged
- * planes; residual {1, 2, 4}.
+ * planes; residual {2, 4, 8, 16}, where 2 and 4 stage bricks and 8 and 16
+ * (periodic only) march columns of that many x planes.
  * Two further families choose how the coarse levels of each V-cycle run: as
  * separate grid launches (0, the default) or as one workgroup-resident "tail"
  * kernel per V-cycle (1) that runs every level from its first one down to the
@@ -233,8 +234,8 @@ mg_status mg_fmg_start(mg_ctx *cc, mg_ctx *cf, double *d_uc, double *d_Wc, doubl
  * LDS (same per-cell arithmetic; the restriction sums group the 8 children
  * differently, so results agree to rounding).  The tail starts at the first
  * level from which the cells of all levels down to the coarsest sum to at
- * most 1971 (psi; W in FP32) or 584 (W, FP64), spanning at most 4 levels
- * (e.g. 8^3 for a hierarchy of powers of two).  Their `level`
+ * most 1971, spanning at most 4 levels (e.g. 8^3 for a hierarchy of powers
+ * of two).  Their `level`
  * is the tail's first level; mg_autotune times one whole V-cycle each way.
  */
 enum { MG_TUNE_PASS_PSI = 1, MG_TUNE_PASS_W = 2, MG_TUNE_RESIDUAL = 3, MG_TUNE_TAIL_PSI = 4, MG_TUNE_TAIL_W = 5 };

@@ -72,7 +72,7 @@ constexpr int kCandPsi[] = {2, 4, 8};
 // W pass depths: 1, 2, 4 are bricks staged whole, 8 and 16 columns marched plane by plane
 constexpr int kCandW32[] = {2, 4, 8, 16};
 constexpr int kCandW64[] = {1, 2, 8};
-constexpr int kCandR[] = {1, 2, 4};
+constexpr int kCandR[] = {2, 4, 8, 16}; // 8, 16: x-marched columns (periodic)
 constexpr int kCandTail[] = {0, 1}; // V-cycle tail off / on
 
 } // namespace
@@ -220,6 +220,8 @@ TileMap rtilemap_rt(int n, int tx)
     case 1: return make_rtilemap<1>(n);
     case 2: return make_rtilemap<2>(n);
     case 4: return make_rtilemap<4>(n);
+    case 8: return make_rmarchmap<8>(n);
+    case 16: return make_rmarchmap<16>(n);
     default: return TileMap{0, 0, 0, 0};
     }
 }
@@ -664,10 +666,25 @@ void launch_residual_tx(hipStream_t s, const Geo &g, const TileMap &tm, const Re
         hipLaunchKernelGGL((k_residual_tiled<BC, T, TX, false>), grid, blk, 0, s, g, tm, a);
 }
 
+template <typename T, int LX>
+void launch_residual_march(hipStream_t s, const Geo &g, const TileMap &tm, const ResArgs &a, bool hasW)
+{
+    const dim3 blk(kLanes, kTY), grid(ntiles(tm));
+    if (hasW)
+        hipLaunchKernelGGL((k_residual_march<T, LX, true>), grid, blk, 0, s, g, tm, a);
+    else
+        hipLaunchKernelGGL((k_residual_march<T, LX, false>), grid, blk, 0, s, g, tm, a);
+}
+
+// Depths 1, 2, 4 stage bricks; 8 and 16 march columns (periodic only).
 template <int BC, typename T>
 void launch_residual_tiled(hipStream_t s, const Geo &g, const TileMap &tm, const ResArgs &a, bool hasW)
 {
-    if (tm.tx == 1)
+    if (BC == kBcPeriodic && tm.tx == 8)
+        launch_residual_march<T, 8>(s, g, tm, a, hasW);
+    else if (BC == kBcPeriodic && tm.tx == 16)
+        launch_residual_march<T, 16>(s, g, tm, a, hasW);
+    else if (tm.tx == 1)
         launch_residual_tx<BC, T, 1>(s, g, tm, a, hasW);
     else if (tm.tx == 4)
         launch_residual_tx<BC, T, 4>(s, g, tm, a, hasW);
@@ -1045,7 +1062,7 @@ const int *tune_candidates(const mg_ctx *c, int family, int &count)
         }
         count = 3;
         return kCandW64;
-    case MG_TUNE_RESIDUAL: count = 3; return kCandR;
+    case MG_TUNE_RESIDUAL: count = 4; return kCandR;
     case MG_TUNE_TAIL_PSI:
     case MG_TUNE_TAIL_W: count = 2; return kCandTail;
     default: count = 0; return nullptr;
@@ -1055,7 +1072,8 @@ const int *tune_candidates(const mg_ctx *c, int family, int &count)
 // The brick map of (family, level) for depth tx (tx == 0 in the map: not tileable).
 TileMap tune_map(const mg_ctx *c, int family, int level, int tx)
 {
-    if (family == MG_TUNE_RESIDUAL) return level == 0 ? rtilemap_rt(c->n[0], tx) : TileMap{0, 0, 0, 0};
+    if (family == MG_TUNE_RESIDUAL)
+        return level == 0 && (tx < 8 || c->p.bc == MG_BC_PERIODIC) ? rtilemap_rt(c->n[0], tx) : TileMap{0, 0, 0, 0};
     if (family == MG_TUNE_PASS_W && (!c->momentum || !w_tileable(c->n[level]))) return TileMap{0, 0, 0, 0};
     return tilemap_rt(c->n[level], tx);
 }

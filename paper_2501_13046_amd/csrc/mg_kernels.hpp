@@ -1103,48 +1103,56 @@ __device__ __forceinline__ void coarse_psi_block_solve(const Geo &g, const T *c,
         const int col = wave + kGjWaves * q;
         v[q] = (lane < M && col < NC) ? A[lane][col] : 0.0;
     }
+    // step k = kGjWaves * qk + w: pivot column k is register qk of wave w
+    constexpr int QK = (M + kGjWaves - 1) / kGjWaves;
     uint64_t used = 0;
     bool singular = false;
+    static_for<QK>([&](auto qc) {
+        constexpr int qk = decltype(qc)::value;
+        if (singular) return;
 #pragma unroll 1
-    for (int k = 0; k < M; k++) {
-        const int buf = k & 1;
-        if (wave == k % kGjWaves) {
-            double a = v[0];
-#pragma unroll
-            for (int q = 1; q < S; q++)
-                if (k / kGjWaves == q) a = v[q];
-            unsigned key = 0u;
-            if (lane < M && !((used >> lane) & 1ull)) {
-                const unsigned bits = __float_as_uint((float)fabs(a));
-                key = (bits & ~63u) | (63u - (unsigned)lane);
-            }
-            const unsigned kmax = __builtin_amdgcn_readfirstlane(__reduce_max_sync(~0ull, key));
-            if ((kmax >> 6) == 0u) {
-                if (lane == 0) piv[buf] = -1; // no non-zero pivot left
-            } else {
-                const int p = 63 - (int)(kmax & 63u);
-                const double ap = readlane_f64(a, p);
-                const double inv = 1.0 / ap;
-                fac[buf][lane] = lane == p ? 0.0 : a * inv;
-                if (lane == 0) {
-                    piv[buf] = p;
-                    pdiag[k] = ap;
-                    perm[k] = p;
+        for (int w = 0; w < kGjWaves; w++) {
+            const int k = kGjWaves * qk + w;
+            if (k >= M) break;
+            const int buf = k & 1;
+            if (wave == w) {
+                const double a = v[qk];
+                unsigned key = 0u;
+                if (lane < M && !((used >> lane) & 1ull)) {
+                    const unsigned bits = __float_as_uint((float)fabs(a));
+                    key = (bits & ~63u) | (63u - (unsigned)lane);
                 }
+                const unsigned kmax = __builtin_amdgcn_readfirstlane(__reduce_max_sync(~0ull, key));
+                if ((kmax >> 6) == 0u) {
+                    if (lane == 0) piv[buf] = -1; // no non-zero pivot left
+                } else {
+                    const int p = 63 - (int)(kmax & 63u);
+                    const double ap = readlane_f64(a, p);
+                    const double inv = 1.0 / ap;
+                    fac[buf][lane] = lane == p ? 0.0 : a * inv;
+                    if (lane == 0) {
+                        piv[buf] = p;
+                        pdiag[k] = ap;
+                        perm[k] = p;
+                    }
+                }
+                __builtin_amdgcn_s_setprio(0);
             }
-        }
-        __syncthreads();
-        const int p = __builtin_amdgcn_readfirstlane(piv[buf]);
-        double f = fac[buf][lane];
-        asm volatile("" : "+v"(f)); // both LDS reads in flight together
-        if (p < 0) {
-            singular = true;
-            break;
-        }
-        used |= 1ull << p;
+            __syncthreads();
+            const int p = __builtin_amdgcn_readfirstlane(piv[buf]);
+            double f = fac[buf][lane];
+            asm volatile("" : "+v"(f)); // both LDS reads in flight together
+            if (p < 0) {
+                singular = true;
+                break;
+            }
+            // the owner of the next pivot column goes first on its SIMD
+            if (wave == (w + 1) % kGjWaves) __builtin_amdgcn_s_setprio(2);
+            used |= 1ull << p;
 #pragma unroll
-        for (int q = 0; q < S; q++) v[q] = fma(-f, readlane_f64(v[q], p), v[q]);
-    }
+            for (int q = 0; q < S; q++) v[q] = fma(-f, readlane_f64(v[q], p), v[q]);
+        }
+    });
     if (singular) {
         if (threadIdx.x == 0) *flag = 1.0;
         return;
@@ -1178,14 +1186,14 @@ constexpr int kTailThreads = kGjWaves * kWave;
 constexpr int kMaxTail = 4;
 
 // Cells of a tail summed over its levels: psi keeps d0, d1, r and c of every
-// level in LDS, W d0, d1 and r of three components.  One workgroup runs a
+// level in LDS, W d and r of three components (its passes update in place).  One workgroup runs a
 // whole level per phase, so a tail pays off only while its first level is
 // small: 16^3 cells already take ~2 us per colour pass on one CU, more than
 // a grid launch of that pass.
 template <typename T>
 struct TailCap {
-    static constexpr int kPsi = 1971;                      // 12^3 + 6^3 + 3^3
-    static constexpr int kW = sizeof(T) == 4 ? 1971 : 584; // 12^3 + 6^3 + 3^3 ; 8^3 + 4^3 + 2^3
+    static constexpr int kPsi = 1971; // 12^3 + 6^3 + 3^3
+    static constexpr int kW = 1971;
 };
 
 template <typename T>
@@ -1303,31 +1311,101 @@ __global__ void __launch_bounds__(kTailThreads) k_tail_psi(TailArgs<T> a)
     }
 }
 
-template <typename T>
-__device__ __forceinline__ void tail_W_passes(const Geo &g, T *d0, T *d1, const T *r, int sweeps)
+// (Delta_L d)_A at a cell from wrapped offsets, component A alone: the terms
+// W_field_parts forms for that component, in the same order.  centre: d_A at
+// the cell.
+template <typename T, int A>
+__device__ __forceinline__ T deltaL_comp(const T *d, unsigned m, const WrapOff &o, T h2, T m2, T third, T &centre)
 {
-    const int n = g.n, m = tail_cells(g);
-    for (int s = 0; s < sweeps; s++)
-        for (int colour = 0; colour < 2; colour++) {
-            const T *in = colour ? d1 : d0;
-            T *out = colour ? d0 : d1;
-            for (int q = threadIdx.x; q < m; q += kTailThreads) {
-                int i, j, k;
-                cell_of(q, n, i, j, k);
-                W_pass_cell<T>(g, in, out, r, colour, q, i, j, k);
-            }
-            __syncthreads();
-        }
+    RegTaps<T, false> D;
+    D.get_lap(WrapTaps<T>{d + A * m, o});
+    const T c = D.c();
+    centre = c;
+    const T xx = D.dxx(c), yy = D.dyy(c), zz = D.dzz(c);
+    const T lap = (xx + yy + zz) * h2;
+    const T dd = (A == 0 ? xx : (A == 1 ? yy : zz)) * h2;
+    RegTaps<T, false> E, G;
+    T mix;
+    if constexpr (A == 0) {
+        E.template get_mixed<0, 1>(WrapTaps<T>{d + m, o});
+        G.template get_mixed<0, 2>(WrapTaps<T>{d + 2 * m, o});
+        mix = E.dxy();
+        mix = mix + G.dxz();
+    } else if constexpr (A == 1) {
+        E.template get_mixed<0, 1>(WrapTaps<T>{d, o});
+        G.template get_mixed<1, 2>(WrapTaps<T>{d + 2 * m, o});
+        mix = E.dxy();
+        mix = mix + G.dyz();
+    } else {
+        E.template get_mixed<0, 2>(WrapTaps<T>{d, o});
+        G.template get_mixed<1, 2>(WrapTaps<T>{d + m, o});
+        mix = E.dxz();
+        mix = mix + G.dyz();
+    }
+    return lap + (dd + mix * m2) * third;
+}
+
+// Work items of a W tail pass: three components of half the cells of a first
+// level of at most TailCap<T>::kW cells in all (12^3).
+constexpr int kTailWStage = 3 * 1728 / 2;
+
+// One colour pass of the W smoother on an LDS-resident level, in place: the
+// threads evaluate the (component, active cell) items from d into the LDS
+// stage, the block waits, then the values go to d (the same values as the
+// double-buffered pass: the other colour is unchanged).  Items are
+// component-major, so a wave handles one component.
+template <typename T>
+__device__ __forceinline__ void tail_W_pass(const Geo &g, T *d, const T *r, T *stage, int colour)
+{
+    const int n = g.n, np = n >> 1;
+    const unsigned m = (unsigned)(n * n * n);
+    const int half = (int)(m >> 1), items = 3 * half;
+    const T h2 = (T)g.inv12h2, m2 = (T)g.inv144h2, third = T(1) / T(3);
+    const T diag = (T)(-100.0 * g.inv12h2);
+    // item it: component a, active cell h of the colour, (i, j, k) and index q
+    auto cell = [&](int it, int &a, int &i, int &j, int &k) {
+        a = it / half;
+        const int h = it - a * half, row = h / np, kp = h - row * np;
+        i = row / n;
+        j = row - i * n;
+        k = 2 * kp + ((i + j + colour) & 1);
+        return (unsigned)((i * n + j) * n + k);
+    };
+#pragma unroll 1
+    for (int it = threadIdx.x; it < items; it += kTailThreads) {
+        int a, i, j, k;
+        const unsigned q = cell(it, a, i, j, k);
+        const WrapOff o(n, i, j, k);
+        T centre, Ad;
+        if (a == 0)
+            Ad = deltaL_comp<T, 0>(d, m, o, h2, m2, third, centre);
+        else if (a == 1)
+            Ad = deltaL_comp<T, 1>(d, m, o, h2, m2, third, centre);
+        else
+            Ad = deltaL_comp<T, 2>(d, m, o, h2, m2, third, centre);
+        stage[it] = centre + (r[a * m + q] - Ad) / diag;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int it = threadIdx.x; it < items; it += kTailThreads) {
+        int a, i, j, k;
+        const unsigned q = cell(it, a, i, j, k);
+        d[a * m + q] = stage[it];
+    }
+    __syncthreads();
 }
 
 // W tail (periodic): V-cycle from the tail's first level; the coarsest solve
-// applies the precomputed inverse to the mean-free residual (as k_coarse_apply).
-// LDS: per level d0 | d1 | r (three components each), levels consecutive.
+// applies the precomputed inverse to the mean-free residual (as
+// k_coarse_apply, rows in blocks of 64 with the columns split over 16 parts).
+// LDS: per level d | r (three components each), levels consecutive.
 template <typename T>
 __global__ void __launch_bounds__(kTailThreads) k_tail_W(TailArgs<T> a)
 {
-    __shared__ T buf[9 * TailCap<T>::kW];
+    __shared__ T buf[6 * TailCap<T>::kW];
+    __shared__ T stage[kTailWStage];
     __shared__ double rs[1536];
+    __shared__ double red[kTailThreads / kWave][kWave];
     __shared__ double mean[3];
     const int L = a.nl;
     int off[kMaxTail] = {0, 0, 0, 0};
@@ -1335,13 +1413,14 @@ __global__ void __launch_bounds__(kTailThreads) k_tail_W(TailArgs<T> a)
         int o = 0;
         for (int l = 0; l < L && l < kMaxTail; l++) {
             off[l] = o;
-            o += 9 * tail_cells(a.geo[l]);
+            o += 6 * tail_cells(a.geo[l]);
         }
-        if (L < 2 || L > kMaxTail || o > 9 * TailCap<T>::kW) return; // the host picks tails that fit
+        if (L < 2 || L > kMaxTail || o > 6 * TailCap<T>::kW || 3 * tail_cells(a.geo[0]) / 2 > kTailWStage ||
+            3 * tail_cells(a.geo[L - 1]) > 1536)
+            return; // the host picks tails that fit
     }
-    auto D0 = [&](int l) { return buf + off[l]; };
-    auto D1 = [&](int l) { return buf + off[l] + 3 * tail_cells(a.geo[l]); };
-    auto R = [&](int l) { return buf + off[l] + 6 * tail_cells(a.geo[l]); };
+    auto D = [&](int l) { return buf + off[l]; };
+    auto R = [&](int l) { return buf + off[l] + 3 * tail_cells(a.geo[l]); };
     {
         const int m0 = 3 * tail_cells(a.geo[0]);
         T *r0 = R(0);
@@ -1351,13 +1430,16 @@ __global__ void __launch_bounds__(kTailThreads) k_tail_W(TailArgs<T> a)
     for (int l = 0; l + 1 < L; l++) {
         const Geo &g = a.geo[l];
         const int m = tail_cells(g);
-        T *d0 = D0(l);
-        for (int q = threadIdx.x; q < 3 * m; q += kTailThreads) d0[q] = T(0);
+        T *d = D(l);
+        for (int q = threadIdx.x; q < 3 * m; q += kTailThreads) d[q] = T(0);
         __syncthreads();
-        tail_W_passes<T>(g, D0(l), D1(l), R(l), a.nu_pre);
+        for (int s = 0; s < a.nu_pre; s++) {
+            tail_W_pass<T>(g, D(l), R(l), stage, 0);
+            tail_W_pass<T>(g, D(l), R(l), stage, 1);
+        }
         for (int q = threadIdx.x; q < m + (kTailThreads - 1); q += kTailThreads) {
             if (q - (int)threadIdx.x >= m) break; // the whole block leaves together
-            defect_restrict_W_child<T>(g, D0(l), R(l), R(l + 1), q);
+            defect_restrict_W_child<T>(g, D(l), R(l), R(l + 1), q);
         }
         __syncthreads();
     }
@@ -1374,13 +1456,23 @@ __global__ void __launch_bounds__(kTailThreads) k_tail_W(TailArgs<T> a)
         __syncthreads();
         for (int q = threadIdx.x; q < m; q += kTailThreads) rs[q] -= mean[q / cn];
         __syncthreads();
-        T *x = D0(L - 1);
-        for (int row = threadIdx.x; row < m; row += kTailThreads) {
+        T *x = D(L - 1);
+        constexpr int kParts = kTailThreads / kWave;
+        const int rl = threadIdx.x % kWave, part = threadIdx.x / kWave;
+        for (int rb = 0; rb < m; rb += kWave) {
+            const int row = rb + rl;
             double s = 0.0;
-            for (int col = 0; col < m; col++) s += a.inv[(int64_t)col * m + row] * rs[col];
-            x[row] = (T)s;
+            if (row < m)
+                for (int col = part; col < m; col += kParts) s += a.inv[(int64_t)col * m + row] * rs[col];
+            red[part][rl] = s;
+            __syncthreads();
+            if (threadIdx.x < kWave && row < m) {
+                double t = 0.0;
+                for (int q = 0; q < kParts; q++) t += red[q][rl];
+                x[row] = (T)t;
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
     for (int l = L - 2; l >= 0; l--) {
         const Geo &g = a.geo[l];
@@ -1388,14 +1480,17 @@ __global__ void __launch_bounds__(kTailThreads) k_tail_W(TailArgs<T> a)
         for (int q = threadIdx.x; q < mf; q += kTailThreads) {
             int i, j, k;
             cell_of(q, nf, i, j, k);
-            prolong_cell<kBcPeriodic, T>(a.geo[l + 1], D0(l + 1), D0(l), 3, q, i, j, k);
+            prolong_cell<kBcPeriodic, T>(a.geo[l + 1], D(l + 1), D(l), 3, q, i, j, k);
         }
         __syncthreads();
-        tail_W_passes<T>(g, D0(l), D1(l), R(l), a.nu_post);
+        for (int s = 0; s < a.nu_post; s++) {
+            tail_W_pass<T>(g, D(l), R(l), stage, 0);
+            tail_W_pass<T>(g, D(l), R(l), stage, 1);
+        }
     }
     {
         const int m0 = 3 * tail_cells(a.geo[0]);
-        const T *d0 = D0(0);
+        const T *d0 = D(0);
         for (int q = threadIdx.x; q < m0; q += kTailThreads) a.d0[q] = d0[q];
     }
 }

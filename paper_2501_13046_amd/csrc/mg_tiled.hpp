@@ -864,6 +864,143 @@ struct RTaps {
     }
 };
 
+// Residual at cell (x, y, z), linear index q, with the W taps of field F
+// from src_of(integral_constant F) (a RegTaps source, stencil corner at
+// (x - 2, y - 2, z - 2)); accumulates the norm partials.  Outputs as
+// k_residual.
+struct ResSums {
+    double hsum = 0.0, hmax = 0.0, msum = 0.0, mmax2 = 0.0;
+};
+
+template <int BC, typename T, bool HAS_W, typename SrcOf>
+__device__ __forceinline__ void residual_cell(const Geo &g, const ResArgs &a, int x, int y, int z, const SrcOf &src_of,
+                                              ResSums &acc)
+{
+    const int n = g.n;
+    const int m = n * n * n;
+    const double K2 = a.K2;
+    const double third = 1.0 / 3.0, two_thirds = 2.0 / 3.0;
+    const unsigned q = ((unsigned)x * (unsigned)n + (unsigned)y) * (unsigned)n + (unsigned)z;
+    const double uc = elt(a.u, q);
+    const double psi = psi0_at(g, a.pmass, x, y, z) + uc;
+    double A2 = 0.0;
+    double Mv[3] = {0.0, 0.0, 0.0};
+    if constexpr (HAS_W) {
+        double dW[3][3]; // dW[p][s]: d_p W_s
+        double lap[3], dd[3], mix[3];
+        auto field = [&](auto fc) {
+            constexpr int F = decltype(fc)::value;
+            const auto S = src_of(fc);
+            RegTaps<double> D;
+            D.get_lap(S);
+            if (a.want_M) {
+                if constexpr (F == 0) {
+                    D.template get_mixed<0, 1>(S);
+                    D.template get_mixed<0, 2>(S);
+                } else if constexpr (F == 1) {
+                    D.template get_mixed<0, 1>(S);
+                    D.template get_mixed<1, 2>(S);
+                } else {
+                    D.template get_mixed<0, 2>(S);
+                    D.template get_mixed<1, 2>(S);
+                }
+            }
+            dW[0][F] = D.dx() * g.inv12h;
+            dW[1][F] = D.dy() * g.inv12h;
+            dW[2][F] = D.dz() * g.inv12h;
+            if (a.want_M) {
+                const double c = D.c();
+                const double xx = D.dxx(c), yy = D.dyy(c), zz = D.dzz(c);
+                lap[F] = (xx + yy + zz) * g.inv12h2;
+                if constexpr (F == 0) {
+                    dd[0] = xx * g.inv12h2;
+                    mix[1] = D.dxy();
+                    mix[2] = D.dxz();
+                } else if constexpr (F == 1) {
+                    dd[1] = yy * g.inv12h2;
+                    mix[0] = D.dxy();
+                    mix[2] = mix[2] + D.dyz();
+                } else {
+                    dd[2] = zz * g.inv12h2;
+                    mix[0] = mix[0] + D.dxz();
+                    mix[1] = mix[1] + D.dyz();
+                }
+            }
+        };
+        static_for<3>(field);
+        const double tdiv = (dW[0][0] + dW[1][1] + dW[2][2]) * two_thirds;
+#pragma unroll
+        for (int p = 0; p < 3; p++)
+#pragma unroll
+            for (int s2 = 0; s2 < 3; s2++) {
+                const double Ab = dW[p][s2] + dW[s2][p] - (p == s2 ? tdiv : 0.0);
+                A2 += Ab * Ab;
+            }
+        if (a.want_M) {
+#pragma unroll
+            for (int f = 0; f < 3; f++) Mv[f] = lap[f] + (dd[f] + mix[f] * g.inv144h2) * third;
+        }
+    }
+    if (a.want_M && a.S) {
+        const double p2 = psi * psi;
+        const double w6 = a.conformal ? 1.0 : p2 * p2 * p2;
+#pragma unroll
+        for (int s2 = 0; s2 < 3; s2++) Mv[s2] -= 8.0 * kPi * w6 * elt(a.S + (size_t)s2 * m, q) - a.meanS[s2];
+    }
+    const double psi2 = psi * psi, psi4 = psi2 * psi2, psi5 = psi4 * psi;
+    const double ipsi = 1.0 / psi, ipsi2 = ipsi * ipsi, ipsi4 = ipsi2 * ipsi2;
+    const double ipsi7 = ipsi4 * ipsi2 * ipsi, ipsi8 = ipsi4 * ipsi4;
+    const double r5 = elt(a.rho5, q), r1 = elt(a.rho1, q);
+    double matter, dmatter;
+    if (a.conformal) {
+        const double rbar = r5 + r1;
+        matter = 2.0 * kPi * rbar * (ipsi4 * psi);
+        dmatter = -6.0 * kPi * rbar * ipsi4;
+    } else {
+        matter = 2.0 * kPi * r5 * psi5 + 2.0 * kPi * r1 * psi;
+        dmatter = 10.0 * kPi * r5 * psi4 + 2.0 * kPi * r1;
+    }
+    double lu;
+    if constexpr (BC == kBcPeriodic)
+        lu = lap_periodic(a.u, n, x, y, z, uc);
+    else
+        lu = lap_sum<double>(Acc<BC, double>{a.u, g}, x, y, z, uc);
+    double H = lu * g.inv12h2 + matter - (K2 / 12.0) * psi5 + 0.125 * A2 * ipsi7;
+    if (a.f) H += elt(a.f, q);
+    const double cc = dmatter - (5.0 * K2 / 12.0) * psi4 - 0.875 * A2 * ipsi8;
+    if (a.H) elt(a.H, q) = H;
+    if (a.c) elt(a.c, q) = cc;
+    const T rT = pinned((T)(-H)), rcT = pinned((T)cc);
+    if (a.r) elt((T *)a.r, q) = rT;
+    if (a.rc) elt((T *)a.rc, q) = rcT;
+    if (a.d1) {
+        ResArgs ap = a;
+        ap.d1W = nullptr;
+        first_pass_fine<BC, T>(g, ap, q, x, y, z, rT, rcT, nullptr);
+    }
+    if (a.want_M) {
+        if (a.M) {
+#pragma unroll
+            for (int s2 = 0; s2 < 3; s2++) elt(a.M + (size_t)s2 * m, q) = Mv[s2];
+        }
+        const T rW[3] = {pinned((T)(-Mv[0])), pinned((T)(-Mv[1])), pinned((T)(-Mv[2]))};
+        if (a.rW) {
+#pragma unroll
+            for (int s2 = 0; s2 < 3; s2++) elt((T *)a.rW + (size_t)s2 * m, q) = rW[s2];
+        }
+        if (a.d1W) {
+            ResArgs aw = a;
+            aw.d1 = nullptr;
+            first_pass_fine<BC, T>(g, aw, q, x, y, z, T(0), T(0), rW);
+        }
+        const double m2 = Mv[0] * Mv[0] + Mv[1] * Mv[1] + Mv[2] * Mv[2];
+        acc.msum += m2;
+        acc.mmax2 = fmax(acc.mmax2, m2);
+    }
+    acc.hsum += H * H;
+    acc.hmax = fmax(acc.hmax, fabs(H));
+}
+
 template <int BC, typename T, int TX, bool HAS_W>
 __global__ void __launch_bounds__(kTY *kLanes) k_residual_tiled(Geo g, TileMap tm, ResArgs a)
 {
@@ -883,140 +1020,144 @@ __global__ void __launch_bounds__(kTY *kLanes) k_residual_tiled(Geo g, TileMap t
         load_rbrick<BC, double, TX>(lds[2], Acc<BC, double>{a.W + 2 * m, g}, x0, y0, z0);
         __syncthreads();
     }
-    Acc<BC, double> U{a.u, g};
-    const double K2 = a.K2;
-    const double third = 1.0 / 3.0, two_thirds = 2.0 / 3.0;
-    double hsum = 0.0, hmax = 0.0, msum = 0.0, mmax2 = 0.0;
+    ResSums acc;
 #pragma unroll
     for (int t = 0; t < TX; t++) {
-        const int x = x0 + t;
-        const unsigned q = ((unsigned)x * (unsigned)n + (unsigned)y) * (unsigned)n + (unsigned)z;
-        const double uc = elt(a.u, q);
-        const double psi = psi0_at(g, a.pmass, x, y, z) + uc;
-        double A2 = 0.0;
-        double Mv[3] = {0.0, 0.0, 0.0};
-        if constexpr (HAS_W) {
-            // staged word of the stencil corner (x - 2, y - 2, z - 2) of this cell
-            const int off = (t * kPY + ty) * kRPZ + lane;
-            double dW[3][3]; // dW[p][s]: d_p W_s
-            double lap[3], dd[3], mix[3];
-            auto field = [&](auto fc) {
-                constexpr int F = decltype(fc)::value;
-                const RCorner<double> S{&lds[F][0][0][0] + off};
-                RegTaps<double> D;
-                D.get_lap(S);
-                if (a.want_M) {
-                    if constexpr (F == 0) {
-                        D.template get_mixed<0, 1>(S);
-                        D.template get_mixed<0, 2>(S);
-                    } else if constexpr (F == 1) {
-                        D.template get_mixed<0, 1>(S);
-                        D.template get_mixed<1, 2>(S);
-                    } else {
-                        D.template get_mixed<0, 2>(S);
-                        D.template get_mixed<1, 2>(S);
-                    }
-                }
-                dW[0][F] = D.dx() * g.inv12h;
-                dW[1][F] = D.dy() * g.inv12h;
-                dW[2][F] = D.dz() * g.inv12h;
-                if (a.want_M) {
-                    const double c = D.c();
-                    const double xx = D.dxx(c), yy = D.dyy(c), zz = D.dzz(c);
-                    lap[F] = (xx + yy + zz) * g.inv12h2;
-                    if constexpr (F == 0) {
-                        dd[0] = xx * g.inv12h2;
-                        mix[1] = D.dxy();
-                        mix[2] = D.dxz();
-                    } else if constexpr (F == 1) {
-                        dd[1] = yy * g.inv12h2;
-                        mix[0] = D.dxy();
-                        mix[2] = mix[2] + D.dyz();
-                    } else {
-                        dd[2] = zz * g.inv12h2;
-                        mix[0] = mix[0] + D.dxz();
-                        mix[1] = mix[1] + D.dyz();
-                    }
-                }
-            };
-            static_for<3>(field);
-            const double tdiv = (dW[0][0] + dW[1][1] + dW[2][2]) * two_thirds;
-#pragma unroll
-            for (int p = 0; p < 3; p++)
-#pragma unroll
-                for (int s2 = 0; s2 < 3; s2++) {
-                    const double Ab = dW[p][s2] + dW[s2][p] - (p == s2 ? tdiv : 0.0);
-                    A2 += Ab * Ab;
-                }
-            if (a.want_M) {
-#pragma unroll
-                for (int f = 0; f < 3; f++) Mv[f] = lap[f] + (dd[f] + mix[f] * g.inv144h2) * third;
-            }
-        }
-        if (a.want_M && a.S) {
-            const double p2 = psi * psi;
-            const double w6 = a.conformal ? 1.0 : p2 * p2 * p2;
-#pragma unroll
-            for (int s2 = 0; s2 < 3; s2++) Mv[s2] -= 8.0 * kPi * w6 * elt(a.S + (size_t)s2 * m, q) - a.meanS[s2];
-        }
-        const double psi2 = psi * psi, psi4 = psi2 * psi2, psi5 = psi4 * psi;
-        const double ipsi = 1.0 / psi, ipsi2 = ipsi * ipsi, ipsi4 = ipsi2 * ipsi2;
-        const double ipsi7 = ipsi4 * ipsi2 * ipsi, ipsi8 = ipsi4 * ipsi4;
-        const double r5 = elt(a.rho5, q), r1 = elt(a.rho1, q);
-        double matter, dmatter;
-        if (a.conformal) {
-            const double rbar = r5 + r1;
-            matter = 2.0 * kPi * rbar * (ipsi4 * psi);
-            dmatter = -6.0 * kPi * rbar * ipsi4;
-        } else {
-            matter = 2.0 * kPi * r5 * psi5 + 2.0 * kPi * r1 * psi;
-            dmatter = 10.0 * kPi * r5 * psi4 + 2.0 * kPi * r1;
-        }
-        double lu;
-        if constexpr (BC == kBcPeriodic)
-            lu = lap_periodic(a.u, n, x, y, z, uc);
-        else
-            lu = lap_sum<double>(U, x, y, z, uc);
-        double H = lu * g.inv12h2 + matter - (K2 / 12.0) * psi5 + 0.125 * A2 * ipsi7;
-        if (a.f) H += elt(a.f, q);
-        const double cc = dmatter - (5.0 * K2 / 12.0) * psi4 - 0.875 * A2 * ipsi8;
-        if (a.H) elt(a.H, q) = H;
-        if (a.c) elt(a.c, q) = cc;
-        const T rT = pinned((T)(-H)), rcT = pinned((T)cc);
-        if (a.r) elt((T *)a.r, q) = rT;
-        if (a.rc) elt((T *)a.rc, q) = rcT;
-        if (a.d1) {
-            ResArgs ap = a;
-            ap.d1W = nullptr;
-            first_pass_fine<BC, T>(g, ap, q, x, y, z, rT, rcT, nullptr);
-        }
-        if (a.want_M) {
-            if (a.M) {
-#pragma unroll
-                for (int s2 = 0; s2 < 3; s2++) elt(a.M + (size_t)s2 * m, q) = Mv[s2];
-            }
-            const T rW[3] = {pinned((T)(-Mv[0])), pinned((T)(-Mv[1])), pinned((T)(-Mv[2]))};
-            if (a.rW) {
-#pragma unroll
-                for (int s2 = 0; s2 < 3; s2++) elt((T *)a.rW + (size_t)s2 * m, q) = rW[s2];
-            }
-            if (a.d1W) {
-                ResArgs aw = a;
-                aw.d1 = nullptr;
-                first_pass_fine<BC, T>(g, aw, q, x, y, z, T(0), T(0), rW);
-            }
-            const double m2 = Mv[0] * Mv[0] + Mv[1] * Mv[1] + Mv[2] * Mv[2];
-            msum += m2;
-            mmax2 = fmax(mmax2, m2);
-        }
-        hsum += H * H;
-        hmax = fmax(hmax, fabs(H));
+        // staged word of the stencil corner (x - 2, y - 2, z - 2) of this cell
+        const int off = (t * kPY + ty) * kRPZ + lane;
+        residual_cell<BC, T, HAS_W>(
+            g, a, x0 + t, y, z,
+            [&](auto fc) { return RCorner<double>{&lds[HAS_W ? decltype(fc)::value : 0][0][0][0] + off}; }, acc);
     }
     if (a.partials) {
-        double v[4] = {hsum, hmax, msum, sqrt(mmax2)};
+        double v[4] = {acc.hsum, acc.hmax, acc.msum, sqrt(acc.mmax2)};
         // 256 threads per block, as block_reduce_store assumes
         block_reduce_store<4>(v, 0xAu, a.partials + 4 * (int64_t)blockIdx.x);
     }
+}
+
+// ---------------------------------------------------------------------------------------
+// Residual marching along x (periodic): a workgroup owns a column of 4 (y) x
+// 64 (z) cells and LX consecutive x planes, one cell per lane per plane.  The
+// three W fields of each staged x plane (rows y0 - 2 .. y0 + 5, z0 - 2 ..
+// z0 + 65, FP64) live in a ring of six LDS slots: while the lanes evaluate
+// plane x from the slots of x - 2 .. x + 2, the registers hold plane x + 4 in
+// flight from HBM and plane x + 3 is written into the slot plane x - 3
+// vacated.  Each staged plane is loaded once per column, so the x halo costs
+// 4 / LX instead of 4 / TX of the bricks.  Same per-cell arithmetic.
+// ---------------------------------------------------------------------------------------
+constexpr int kRPlaneF = kPY * kRPZ; // one field of a staged plane
+constexpr int kRSlot = 3 * kRPlaneF; // one ring slot
+
+// One staged x plane of the three W fields: 3 kPY rows of kRPZ words; load i
+// of a thread moves word `lane` of row w + kTY i, threads tid < 4 * 3 kPY the
+// four remaining words of row tid / 4.
+struct RPlaneRegs {
+    static constexpr int NROW = 3 * kPY;
+    static constexpr int RPW = NROW / kTY;
+    static_assert(NROW % kTY == 0 && 4 * NROW <= kTY * kLanes, "rows of a plane over the block");
+    double v[RPW];
+    double e;
+    __device__ __forceinline__ void fetch(const double *__restrict__ W, unsigned m, int n, int x, int y0, int z0)
+    {
+        const int w = threadIdx.y, lane = threadIdx.x, tid = w * kLanes + lane;
+        const unsigned un = (unsigned)n, xo = (unsigned)wrap(x, n) * un;
+        const unsigned zw = (unsigned)wrap(z0 - 2 + lane, n);
+#pragma unroll
+        for (int i = 0; i < RPW; i++) {
+            const int row = w + kTY * i, f = row / kPY, yr = row - f * kPY;
+            v[i] = elt(W + (size_t)f * m, (xo + (unsigned)wrap(y0 + yr - 2, n)) * un + zw);
+        }
+        e = 0.0;
+        if (tid < 4 * NROW) {
+            const int row = tid >> 2, f = row / kPY, yr = row - f * kPY;
+            e = elt(W + (size_t)f * m, (xo + (unsigned)wrap(y0 + yr - 2, n)) * un + (unsigned)wrap(z0 + kRZ - 2 + (tid & 3), n));
+        }
+    }
+    __device__ __forceinline__ void store(double *slot) const
+    {
+        const int w = threadIdx.y, lane = threadIdx.x, tid = w * kLanes + lane;
+#pragma unroll
+        for (int i = 0; i < RPW; i++) slot[(w + kTY * i) * kRPZ + lane] = v[i];
+        if (tid < 4 * NROW) slot[(tid >> 2) * kRPZ + kRZ + (tid & 3)] = e;
+    }
+};
+
+// Taps of field F around the thread's cell: pb[DX + 2] is the word of the
+// stencil corner row (y - 2, z - 2) in the slot of plane x + DX.
+template <int F>
+struct RRing {
+    static constexpr bool kOrdered = true;
+    const double *const *pb;
+    template <int DX, int DY, int DZ>
+    __device__ __forceinline__ double at() const
+    {
+        return pb[DX + 2][F * kRPlaneF + (DY + 2) * kRPZ + DZ + 2];
+    }
+};
+
+template <typename T, int LX, bool HAS_W>
+__global__ void __launch_bounds__(kTY *kLanes) k_residual_march(Geo g, TileMap tm, ResArgs a)
+{
+    __shared__ double ring[HAS_W ? kRing : 1][HAS_W ? kRSlot : 1];
+    const int total = tm.nx * tm.ny * tm.nz;
+    int logical = blockIdx.x;
+    if (total % kXCD == 0) logical = (blockIdx.x % kXCD) * (total / kXCD) + blockIdx.x / kXCD;
+    const int bz = logical % tm.nz, rest = logical / tm.nz;
+    const int x0 = (rest / tm.ny) * LX, y0 = (rest % tm.ny) * kTY, z0 = bz * kRZ;
+    const int n = g.n;
+    const unsigned m = (unsigned)n * n * n;
+    const int ty = threadIdx.y, lane = threadIdx.x;
+    const int y = y0 + ty, z = z0 + lane;
+    RPlaneRegs st;
+    if constexpr (HAS_W) {
+        // staged plane j (0 .. LX + 3) is x = x0 - 2 + j, in slot j % kRing; the
+        // first six planes are all in flight at once
+        RPlaneRegs w5[5];
+#pragma unroll
+        for (int j = 0; j < 5; j++) w5[j].fetch(a.W, m, n, x0 - 2 + j, y0, z0);
+        if (LX > 1) st.fetch(a.W, m, n, x0 + 3, y0, z0);
+#pragma unroll
+        for (int j = 0; j < 5; j++) w5[j].store(ring[j]);
+        __syncthreads();
+    }
+    ResSums acc;
+#pragma unroll 1
+    for (int k = 0; k < LX; k++) {
+        const double *pb[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+        if constexpr (HAS_W) {
+#pragma unroll
+            for (int d = 0; d < 5; d++) pb[d] = &ring[(k + d) % kRing][ty * kRPZ + lane];
+        }
+        residual_cell<kBcPeriodic, T, HAS_W>(
+            g, a, x0 + k, y, z, [&](auto fc) { return RRing<decltype(fc)::value>{pb}; }, acc);
+        if constexpr (HAS_W) {
+            if (k + 5 <= LX + 3) { // plane x + 3 into the slot plane x - 3 left
+                st.store(ring[(k + 5) % kRing]);
+                if (k + 6 <= LX + 3) st.fetch(a.W, m, n, x0 + k + 4, y0, z0);
+            }
+            __syncthreads();
+        }
+    }
+    if (a.partials) {
+        double v[4] = {acc.hsum, acc.hmax, acc.msum, sqrt(acc.mmax2)};
+        // 256 threads per block, as block_reduce_store assumes
+        block_reduce_store<4>(v, 0xAu, a.partials + 4 * (int64_t)blockIdx.x);
+    }
+}
+
+// Column map of the marched residual (tx == 0: the level does not fit).
+template <int LX>
+inline TileMap make_rmarchmap(int n)
+{
+    TileMap t{0, 0, 0, 0};
+    if (n % kRZ != 0 || n % kTY != 0 || n % LX != 0) return t;
+    if ((double)n * n * n * sizeof(double) >= 4294967296.0) return t; // 32-bit byte offsets per field
+    t.nx = n / LX;
+    t.ny = n / kTY;
+    t.nz = n / kRZ;
+    t.tx = LX;
+    return t;
 }
 
 template <int TX>

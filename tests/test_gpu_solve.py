@@ -214,13 +214,12 @@ def test_vcycle_tail_matches_separate_launches(case):
             # the tail's first level: the first from which the cells of all levels
             # down to the coarsest fit its LDS arrays (at most 4 levels)
             ns = [w.n >> l for l in range(w.levels)]
-            f32 = w.precision == g.PREC_FP32_IR
 
             def start(cap):
                 return next(l for l in range(len(ns) - 1) if sum(n ** 3 for n in ns[l:]) <= cap and len(ns) - l <= 4)
             s.set_tile(g.TUNE_TAIL_PSI, start(1971), 1)
             if w.solve_momentum:
-                s.set_tile(g.TUNE_TAIL_W, start(1971 if f32 else 584), 1)
+                s.set_tile(g.TUNE_TAIL_W, start(1971), 1)
         u = torch.zeros((w.n,) * 3, dtype=torch.float64, device=dev())
         W = torch.zeros((3,) + (w.n,) * 3, dtype=torch.float64, device=dev()) if w.solve_momentum else None
         rep = s.solve(u, W, tol=1e-11, max_outer=80)

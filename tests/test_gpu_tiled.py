@@ -118,7 +118,9 @@ def test_report_lds_limit():
     print("torch props:", {k: getattr(props, k) for k in dir(props) if "shared" in k or "multi" in k})
 
 
-def test_tiled_residual_periodic_coupled():
+@pytest.mark.parametrize("depth", [2, 4, 8, 16])
+def test_tiled_residual_periodic_coupled(depth):
+    """Bricks (depth 2, 4) and x-marched columns (8, 16) of the finest residual."""
     K = 2.3
     p = g.params(n, 6, K=K, solve_momentum=True)
     po = oracle.params(n, 6, K=K, solve_momentum=True)
@@ -128,12 +130,16 @@ def test_tiled_residual_periodic_coupled():
     rho1 = synth.uniform_random(73, (n,) * 3, 0, 1)
     S = synth.uniform_random(74, (3, n, n, n))
     s = g.Solver(p, T(rho5), T(rho1), T(S))
+    s.set_tile(g.TUNE_RESIDUAL, 0, depth)
     H, M, c = s.residual_fields(T(u), T(W))
     Ho, Mo, co = oracle.residuals(po, u, W, rho5, rho1, S)
     assert rel_err(N(H), Ho) < 1e-12
     assert rel_err(N(M), Mo) < 1e-12
     assert rel_err(N(c), co) < 1e-13
     np.testing.assert_allclose(s.residual_norm(T(u), T(W)), oracle.norms(Ho, Mo), rtol=1e-11)
+    # the psi step's form: H and c without the momentum part
+    H2, _, c2 = s.residual_fields(T(u), T(W), want_M=False)
+    assert np.array_equal(N(H2), N(H)) and np.array_equal(N(c2), N(c))
 
 
 def test_tiled_residual_robin_puncture():
