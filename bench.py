@@ -183,6 +183,11 @@ def main():
     coarse = g.Solver(pc, r5c, r1c, Sc)
     uc = torch.zeros((n // 2,) * 3, dtype=torch.float64, device=dev)
     Wc = torch.zeros((3,) + (n // 2,) * 3, dtype=torch.float64, device=dev)
+    # the coarse solver's kernels are tuned on its own grid too (off the clock)
+    if args.tune_cache:
+        g.autotune_cached(coarse, uc, Wc, path=args.tune_cache, reps=20)
+    else:
+        coarse.autotune(uc, Wc, reps=20)
 
     def step_fmg():
         uc.zero_()

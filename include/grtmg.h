@@ -234,8 +234,8 @@ mg_status mg_fmg_start(mg_ctx *cc, mg_ctx *cf, double *d_uc, double *d_Wc, doubl
  * LDS (same per-cell arithmetic; the restriction sums group the 8 children
  * differently, so results agree to rounding).  The tail starts at the first
  * level from which the cells of all levels down to the coarsest sum to at
- * most 1971, spanning at most 4 levels (e.g. 8^3 for a hierarchy of powers
- * of two).  Their `level`
+ * most 4680 (psi, FP32, periodic) or 1971 (psi otherwise; W), spanning at
+ * most 4 levels (e.g. 16^3 for psi and 8^3 for W, FP32 periodic).  Their `level`
  * is the tail's first level; mg_autotune times one whole V-cycle each way.
  */
 enum { MG_TUNE_PASS_PSI = 1, MG_TUNE_PASS_W = 2, MG_TUNE_RESIDUAL = 3, MG_TUNE_TAIL_PSI = 4, MG_TUNE_TAIL_W = 5 };

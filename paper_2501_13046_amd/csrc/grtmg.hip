@@ -65,7 +65,7 @@ constexpr int kBrickPsi = 4;
 constexpr int kBrickW = 2;
 // marched columns of 64-cell rows (levels whose side is a multiple of 64 but
 // not of 128): x planes per column of the W pass and of the W defect restriction
-constexpr int kMarch64Pass = 2;
+constexpr int kMarch64Pass = 1;
 constexpr int kMarch64Defect = 2;
 constexpr int kBrickR = 2;
 constexpr int kCandPsi[] = {2, 4, 8};
@@ -226,6 +226,8 @@ TileMap rtilemap_rt(int n, int tx)
     }
 }
 
+unsigned ntiles(const TileMap &t) { return (unsigned)(t.nx * t.ny * t.nz); }
+
 void init_geo(mg_ctx *c)
 {
     for (int l = 0; l < c->L; l++) {
@@ -233,13 +235,24 @@ void init_geo(mg_ctx *c)
         c->tile[l] = make_tilemap<kBrickPsi>(c->n[l]);
         c->tileW[l] = w_tileable(c->n[l]) ? make_tilemap<kBrickW>(c->n[l]) : TileMap{0, 0, 0, 0};
     }
+    // finest residual: marched columns (periodic) when they still give two
+    // workgroups per compute unit of a 256-CU device, else bricks
     c->tileR = make_rtilemap<kBrickR>(c->n[0]);
+    if (c->p.bc == MG_BC_PERIODIC) {
+        const TileMap r16 = make_rmarchmap<16>(c->n[0]), r8 = make_rmarchmap<8>(c->n[0]);
+        if (r16.tx > 0 && ntiles(r16) >= 512)
+            c->tileR = r16;
+        else if (r8.tx > 0 && ntiles(r8) >= 512)
+            c->tileR = r8;
+    }
     // V-cycle tails: from the first level whose levels down to the coarsest fit
     // the tail's LDS arrays; at least one level above the coarsest, at most
     // kMaxTail levels, coarsest psi system solvable in registers.
     c->tail_psi = c->tail_W = -1;
     c->tail_psi_on = c->tail_W_on = false;
-    const int cap_psi = c->f32 ? TailCap<float>::kPsi : TailCap<double>::kPsi;
+    const int cap_psi = c->p.bc != MG_BC_PERIODIC ? TailCap<float>::kPsiRobin
+                        : c->f32                   ? TailCap<float>::kPsi
+                                                   : TailCap<double>::kPsi;
     const int cap_W = c->f32 ? TailCap<float>::kW : TailCap<double>::kW;
     auto cells_from = [&](int l) {
         int64_t s = 0;
@@ -259,7 +272,6 @@ void init_geo(mg_ctx *c)
             }
 }
 
-unsigned ntiles(const TileMap &t) { return (unsigned)(t.nx * t.ny * t.nz); }
 
 // Records an event pair around the launches in its scope when (kernel, level)
 // matches the probe set by mg_probe.

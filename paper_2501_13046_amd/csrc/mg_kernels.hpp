@@ -1185,14 +1185,15 @@ __global__ void __launch_bounds__(kGjWaves * kWave) k_coarse_psi_block(Geo g, co
 constexpr int kTailThreads = kGjWaves * kWave;
 constexpr int kMaxTail = 4;
 
-// Cells of a tail summed over its levels: psi keeps d0, d1, r and c of every
-// level in LDS, W d and r of three components (its passes update in place).  One workgroup runs a
-// whole level per phase, so a tail pays off only while its first level is
-// small: 16^3 cells already take ~2 us per colour pass on one CU, more than
-// a grid launch of that pass.
+// Cells of a tail summed over its levels: psi keeps d, r and c of every level
+// in LDS, W d and r of three components (the passes update in place).  One
+// workgroup runs a whole level per phase, so a tail pays off only while its
+// first level is small: a W colour pass over 16^3 cells takes longer on one
+// CU than as a grid launch, a psi pass (13 taps) does not.
 template <typename T>
 struct TailCap {
-    static constexpr int kPsi = 1971; // 12^3 + 6^3 + 3^3
+    static constexpr int kPsi = sizeof(T) == 4 ? 4680 : 1971; // 16^3 + 8^3 + 4^3 + 2^3 ; 12^3 + 6^3 + 3^3
+    static constexpr int kPsiRobin = 1971;
     static constexpr int kW = 1971;
 };
 
@@ -1209,43 +1210,89 @@ struct TailArgs {
 
 __device__ __forceinline__ int tail_cells(const Geo &g) { return g.n * g.n * g.n; }
 
+// New value of an active cell of a psi colour pass (the arithmetic of the
+// grid pass kernels: k_pass_psi_pairs when periodic, psi_pass_cell otherwise).
 template <int BC, typename T>
-__device__ __forceinline__ void tail_psi_passes(const Geo &g, T *d0, T *d1, const T *r, const T *c, int sweeps)
+__device__ __forceinline__ T psi_new_value(const Geo &g, const T *in, const T *r, const T *c, unsigned q, int i,
+                                           int j, int k)
 {
-    const int n = g.n, m = tail_cells(g);
-    for (int s = 0; s < sweeps; s++)
-        for (int colour = 0; colour < 2; colour++) {
-            const T *in = colour ? d1 : d0;
-            T *out = colour ? d0 : d1;
-            for (int q = threadIdx.x; q < m; q += kTailThreads) {
-                int i, j, k;
-                cell_of(q, n, i, j, k);
-                psi_pass_cell<BC, T>(g, in, out, r, c, colour, q, i, j, k);
-            }
-            __syncthreads();
+    if constexpr (BC == kBcPeriodic) {
+        const WrapOff o(g.n, i, j, k);
+        RegTaps<T, false> D;
+        D.get_lap(WrapTaps<T>{in, o});
+        const T v = D.c(), cv = c[q];
+        const T Ad = (D.dxx(v) + D.dyy(v) + D.dzz(v)) * (T)g.inv12h2 + cv * v;
+        const T diag = pinned((T)(-90.0 * g.inv12h2)) + cv;
+        return v + (r[q] - Ad) / diag;
+    } else {
+        Acc<BC, T> D{in, g};
+        const T x = in[q], cv = c[q];
+        const T Ad = lap_sum<T>(D, i, j, k, x) * (T)g.inv12h2 + cv * x;
+        const T diag = pinned((T)(lap_diag_sum<BC>(g, i, j, k) * g.inv12h2)) + cv;
+        return x + (r[q] - Ad) / diag;
+    }
+}
+
+// Active cells of a psi tail pass per thread: half the cells of a first level
+// of at most 16^3 (periodic) or 12^3 (Robin: its ghost-cell taps need the
+// registers of a second item).
+template <int BC>
+constexpr int tail_psi_items()
+{
+    return BC == kBcPeriodic ? 2 : 1;
+}
+
+// One colour pass of the psi smoother on an LDS-resident level, in place: the
+// active cells' new values are formed from d into registers, the block waits,
+// then they are written (the double-buffered pass's values).
+template <int BC, typename T>
+__device__ __forceinline__ void tail_psi_pass(const Geo &g, T *d, const T *r, const T *c, int colour)
+{
+    const int n = g.n, np = n >> 1, half = (n * n * n) >> 1;
+    constexpr int NI = tail_psi_items<BC>();
+    T val[NI];
+    unsigned dst[NI];
+#pragma unroll
+    for (int s = 0; s < NI; s++) {
+        const int it = (int)threadIdx.x + s * kTailThreads;
+        dst[s] = ~0u;
+        val[s] = T(0);
+        if (it < half) {
+            const int row = it / np, kp = it - row * np, i = row / n, j = row - i * n;
+            const int k = 2 * kp + ((i + j + colour) & 1);
+            const unsigned q = (unsigned)((i * n + j) * n + k);
+            val[s] = psi_new_value<BC, T>(g, d, r, c, q, i, j, k);
+            dst[s] = q;
         }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < NI; s++)
+        if (dst[s] != ~0u) d[dst[s]] = val[s];
+    __syncthreads();
 }
 
 // psi tail: restricts c below its first level, then the V-cycle from the
-// tail's first level.  LDS: per level d0 | d1 | r | c, levels consecutive.
+// tail's first level.  LDS: per level d | r | c, levels consecutive.
 template <int BC, typename T, int M>
 __global__ void __launch_bounds__(kTailThreads) k_tail_psi(TailArgs<T> a)
 {
-    __shared__ T buf[4 * TailCap<T>::kPsi];
+    __shared__ T buf[3 * TailCap<T>::kPsi];
     const int L = a.nl;
     int off[kMaxTail] = {0, 0, 0, 0};
     {
         int o = 0;
         for (int l = 0; l < L && l < kMaxTail; l++) {
             off[l] = o;
-            o += 4 * tail_cells(a.geo[l]);
+            o += 3 * tail_cells(a.geo[l]);
         }
-        if (L < 2 || L > kMaxTail || o > 4 * TailCap<T>::kPsi) return; // the host picks tails that fit
+        if (L < 2 || L > kMaxTail || o > 3 * TailCap<T>::kPsi ||
+            tail_cells(a.geo[0]) / 2 > tail_psi_items<BC>() * kTailThreads)
+            return; // the host picks tails that fit
     }
-    auto D0 = [&](int l) { return buf + off[l]; };
-    auto D1 = [&](int l) { return buf + off[l] + tail_cells(a.geo[l]); };
-    auto R = [&](int l) { return buf + off[l] + 2 * tail_cells(a.geo[l]); };
-    auto C = [&](int l) { return buf + off[l] + 3 * tail_cells(a.geo[l]); };
+    auto D = [&](int l) { return buf + off[l]; };
+    auto R = [&](int l) { return buf + off[l] + tail_cells(a.geo[l]); };
+    auto C = [&](int l) { return buf + off[l] + 2 * tail_cells(a.geo[l]); };
     {
         const int m0 = tail_cells(a.geo[0]);
         T *r0 = R(0), *c0 = C(0);
@@ -1276,19 +1323,22 @@ __global__ void __launch_bounds__(kTailThreads) k_tail_psi(TailArgs<T> a)
     for (int l = 0; l + 1 < L; l++) {
         const Geo &g = a.geo[l];
         const int mf = tail_cells(g);
-        T *d0 = D0(l);
-        for (int q = threadIdx.x; q < mf; q += kTailThreads) d0[q] = T(0);
+        T *d = D(l);
+        for (int q = threadIdx.x; q < mf; q += kTailThreads) d[q] = T(0);
         __syncthreads();
-        tail_psi_passes<BC, T>(g, D0(l), D1(l), R(l), C(l), a.nu_pre);
+        for (int s = 0; s < a.nu_pre; s++) {
+            tail_psi_pass<BC, T>(g, D(l), R(l), C(l), 0);
+            tail_psi_pass<BC, T>(g, D(l), R(l), C(l), 1);
+        }
         for (int q = threadIdx.x; q < mf + (kTailThreads - 1); q += kTailThreads) {
             if (q - (int)threadIdx.x >= mf) break; // the whole block leaves together
-            defect_restrict_psi_child<BC, T>(g, D0(l), R(l), C(l), R(l + 1), (T *)nullptr, q);
+            defect_restrict_psi_child<BC, T>(g, D(l), R(l), C(l), R(l + 1), (T *)nullptr, q);
         }
         __syncthreads();
     }
     {
         const int mc = tail_cells(a.geo[L - 1]);
-        T *x = D0(L - 1);
+        T *x = D(L - 1);
         for (int q = threadIdx.x; q < mc; q += kTailThreads) x[q] = T(0); // stays 0 if singular
         __syncthreads();
         coarse_psi_block_solve<BC, T, M>(a.geo[L - 1], C(L - 1), R(L - 1), x, a.flag);
@@ -1299,14 +1349,17 @@ __global__ void __launch_bounds__(kTailThreads) k_tail_psi(TailArgs<T> a)
         for (int q = threadIdx.x; q < mf; q += kTailThreads) {
             int i, j, k;
             cell_of(q, nf, i, j, k);
-            prolong_cell<BC, T>(a.geo[l + 1], D0(l + 1), D0(l), 1, q, i, j, k);
+            prolong_cell<BC, T>(a.geo[l + 1], D(l + 1), D(l), 1, q, i, j, k);
         }
         __syncthreads();
-        tail_psi_passes<BC, T>(a.geo[l], D0(l), D1(l), R(l), C(l), a.nu_post);
+        for (int s = 0; s < a.nu_post; s++) {
+            tail_psi_pass<BC, T>(a.geo[l], D(l), R(l), C(l), 0);
+            tail_psi_pass<BC, T>(a.geo[l], D(l), R(l), C(l), 1);
+        }
     }
     {
         const int m0 = tail_cells(a.geo[0]);
-        const T *d0 = D0(0);
+        const T *d0 = D(0);
         for (int q = threadIdx.x; q < m0; q += kTailThreads) a.d0[q] = d0[q];
     }
 }

@@ -528,12 +528,13 @@ struct PlaneRegs {
 // plane x0 + 3 left in st; all six fetches are issued before the first store.
 template <typename T, int BZ>
 __device__ __forceinline__ void march_prologue(T (*lds)[ZGeom<BZ>::kNR][ZGeom<BZ>::kPZB], PlaneRegs<T, BZ> &st,
-                                               const T *__restrict__ in, unsigned m, int n, int x0, int y0, int z0)
+                                               const T *__restrict__ in, unsigned m, int n, int x0, int y0, int z0,
+                                               bool fetch_next = true)
 {
     PlaneRegs<T, BZ> w[5];
 #pragma unroll
     for (int j = 0; j < 5; j++) w[j].fetch(in, m, n, x0 - 2 + j, y0, z0);
-    st.fetch(in, m, n, x0 + 3, y0, z0);
+    if (fetch_next) st.fetch(in, m, n, x0 + 3, y0, z0); // a column of one plane needs no sixth
 #pragma unroll
     for (int j = 0; j < 5; j++) w[j].store(lds[j]);
 }
@@ -582,7 +583,7 @@ __global__ void __launch_bounds__(kTY *kLanes) k_pass_W_march(Geo g, TileMap tm,
     // staged plane j (0 .. LX + 3) is x = x0 - 2 + j, in slot j % kRing; the
     // first six planes are all in flight at once
     PlaneRegs<T, BZ> st;
-    march_prologue<T, BZ>(lds, st, in, m, n, x0, y0, z0);
+    march_prologue<T, BZ>(lds, st, in, m, n, x0, y0, z0, LX > 1);
     auto row_of = [&](int x) { return (unsigned)(x * n + y) * (unsigned)n + (unsigned)(z0 + 2 * p); };
     auto par_of = [&](int x) { return (unsigned)((colour + x + y + z0) & 1); };
     T rv[3];

@@ -217,7 +217,8 @@ def test_vcycle_tail_matches_separate_launches(case):
 
             def start(cap):
                 return next(l for l in range(len(ns) - 1) if sum(n ** 3 for n in ns[l:]) <= cap and len(ns) - l <= 4)
-            s.set_tile(g.TUNE_TAIL_PSI, start(1971), 1)
+            f32_periodic = w.precision == g.PREC_FP32_IR and w.bc == g.BC_PERIODIC
+            s.set_tile(g.TUNE_TAIL_PSI, start(4680 if f32_periodic else 1971), 1)
             if w.solve_momentum:
                 s.set_tile(g.TUNE_TAIL_W, start(1971), 1)
         u = torch.zeros((w.n,) * 3, dtype=torch.float64, device=dev())
