@@ -400,6 +400,21 @@ def fmg_start(coarse: "Solver", fine: "Solver", uc: torch.Tensor, Wc: Optional[t
     return dict(status=st, outer_iters=rep.outer_iters, h_rms=rep.h_rms, m_rms=rep.m_rms, seconds=rep.seconds)
 
 
+def fmg_coarse_tol(coarse: "Solver", fine: "Solver", uc: torch.Tensor, Wc: Optional[torch.Tensor],
+                   uf: torch.Tensor, Wf: Optional[torch.Tensor], fraction: float = 0.1) -> float:
+    """Coarse tolerance of an FMG start: `fraction` of the rms Hamiltonian
+    residual that the converged coarse solution, interpolated, leaves on the
+    fine grid (the discretisation difference between the two grids, which no
+    coarse iteration removes).  Solves the coarse problem once to 1e-10; the
+    arrays are overwritten."""
+    uc.zero_()
+    if Wc is not None:
+        Wc.zero_()
+    fmg_start(coarse, fine, uc, Wc, uf, Wf, tol=1e-10)
+    h = fine.residual_norm(uf, Wf)[0]
+    return float(fraction * h)
+
+
 def K_from_mean_density(mean_rho: float) -> float:
     """Constant K with K^2 = 24 pi <rho> at psi = 1 (the periodic workloads)."""
     return float(np.sqrt(24.0 * np.pi * mean_rho))

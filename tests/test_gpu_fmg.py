@@ -66,3 +66,35 @@ def test_fmg_start(case):
         psi0 = judge.psi0(gr, wf.puncture_mass)
     assert psi_rel_err(N(uf), N(u0), psi0) < 1e-9
     assert r1["outer_iters"] < r0["outer_iters"]
+
+
+def test_fmg_coarse_tolerance_rule():
+    """A coarse solve stopped at a tenth of the fine residual left by the exact
+    coarse solution costs fewer coarse iterations and at most one more fine
+    iteration, and reaches the same fine solution."""
+    wf = synth.coupled(64, seed=4, precision=g.PREC_FP32_IR)
+    wc = synth.coupled(32, seed=4, precision=g.PREC_FP32_IR)
+    pf, pc = gparams(wf), gparams(wc)
+    r5f, r1f, Sf, meanf = sources(wf, pf)
+    r5c, r1c, Sc, _ = sources(wc, pc)
+    pf.K = pc.K = g.K_from_mean_density(meanf)
+    fine = g.Solver(pf, r5f, r1f, Sf)
+    coarse = g.Solver(pc, r5c, r1c, Sc)
+    z = lambda n: torch.zeros((n,) * 3, dtype=torch.float64, device=dev())
+    zw = lambda n: torch.zeros((3, n, n, n), dtype=torch.float64, device=dev())
+    uc, Wc, uf, Wf = z(32), zw(32), z(64), zw(64)
+    tol_c = g.fmg_coarse_tol(coarse, fine, uc, Wc, uf, Wf)
+    h_exact = fine.residual_norm(uf, Wf)[0]
+    assert 0.0 < tol_c and abs(tol_c - 0.1 * h_exact) <= 1e-12 * h_exact
+    uc.zero_(); Wc.zero_()
+    rc_full = g.fmg_start(coarse, fine, uc, Wc, uf, Wf, tol=1e-10)
+    rf_full = fine.solve(uf, Wf, tol=1e-11, max_outer=80)
+    u_ref = N(uf).copy()
+    uc.zero_(); Wc.zero_()
+    rc = g.fmg_start(coarse, fine, uc, Wc, uf, Wf, tol=tol_c)
+    rf = fine.solve(uf, Wf, tol=1e-11, max_outer=80)
+    print(f"coarse to {tol_c:.1e}: coarse {rc['outer_iters']} + fine {rf['outer_iters']}; "
+          f"to 1e-10: coarse {rc_full['outer_iters']} + fine {rf_full['outer_iters']}")
+    assert rc["status"] == 0 and rc["outer_iters"] < rc_full["outer_iters"]
+    assert rf["outer_iters"] <= rf_full["outer_iters"] + 1
+    assert psi_rel_err(N(uf), u_ref, 1.0) < 1e-9
