@@ -82,6 +82,7 @@ struct mg_ctx {
     hipStream_t user_s; // the caller's stream: every call is ordered after / before it by events
     hipStream_t s;      // internal stream (captured into the outer-iteration graph)
     hipEvent_t ev_in, ev_out;
+    hipEvent_t ev_norm[2];     // norm copies of consecutive iterations (pinned slots hpin[0 / S_COUNT ..])
     int L;
     bool f32;
     bool momentum;
@@ -819,6 +820,31 @@ mg_status fetch_norms(mg_ctx *c, double out[4], double *flag_psi)
     return MG_OK;
 }
 
+// Norms of an evaluation copied into pinned slot `slot` behind the work on the
+// stream (post_norms), and read once that copy is done (read_norms), so that
+// the host can wait for one iteration's norms while the next one runs.
+mg_status post_norms(mg_ctx *c, int slot)
+{
+    if (hipMemcpyAsync(c->hpin + slot * S_COUNT, c->scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost,
+                       c->s) != hipSuccess ||
+        hipEventRecord(c->ev_norm[slot], c->s) != hipSuccess)
+        return MG_ERR_HIP;
+    return MG_OK;
+}
+
+mg_status read_norms(mg_ctx *c, int slot, double out[4], double *flag_psi)
+{
+    if (hipEventSynchronize(c->ev_norm[slot]) != hipSuccess) return MG_ERR_HIP;
+    const double *h = c->hpin + slot * S_COUNT;
+    const double inv = 1.0 / (double)c->cells[0];
+    out[0] = std::sqrt(h[S_NORM + 0] * inv);
+    out[1] = std::sqrt(h[S_NORM + 2] * inv);
+    out[2] = h[S_NORM + 1];
+    out[3] = h[S_NORM + 3];
+    if (flag_psi) *flag_psi = h[S_FLAG_PSI];
+    return MG_OK;
+}
+
 // Evaluation of a state: norms (+ the residual the next update step uses);
 // batch members also update their convergence flags.
 template <typename T>
@@ -901,22 +927,50 @@ mg_status solve(mg_ctx *c, double *u, double *W, double tol, int max_outer, mg_r
     c->vc_psi = c->vc_W = 0;
     mg_status st = MG_ERR_NOT_CONVERGED;
     double nr[4] = {0, 0, 0, 0}, first = -1.0;
-    int it = 0, hist_len = 0;
+    int it = 0, hist_len = 0, launched = 0;
     const bool mom = c->momentum;
     const bool want_M = mom || (c->S != nullptr && W != nullptr);
     // graphs replay fixed launch parameters; the probe needs eager launches
     const bool graph = !(c->p.flags & MG_FLAG_EAGER) && c->probe_kernel == MG_PROBE_NONE;
+    // Lookahead: iteration it + 1 is enqueued before iteration it's norms are
+    // read (the host round trip then overlaps the GPU work) when the
+    // contraction of the last two iterations puts iteration it at least
+    // kAheadMargin times above tol, so it cannot be the last one.
+    constexpr double kAheadMargin = 10.0;
+    double w1 = -1.0, w2 = -1.0; // worst norm after the last and the one-before-last read iteration
     fill<double>(c->s, c->scal + S_FLAG_PSI, 2, 0.0);
     evaluate<T>(c, u, W, want_M);
-    for (;; it++) {
-        double flag = 0.0;
-        if (hip_status() != MG_OK) return MG_ERR_HIP;
-        mg_status fs = fetch_norms(c, nr, &flag);
-        if (fs != MG_OK) return fs;
+    if (post_norms(c, 0) != MG_OK) return MG_ERR_HIP;
+    auto launch_next = [&]() -> mg_status {
+        if (graph) {
+            mg_status gs = capture_body<T>(c, u, W, want_M);
+            if (gs != MG_OK) return gs;
+            if (hipGraphLaunch(c->gexec, c->s) != hipSuccess) return MG_ERR_HIP;
+            c->vc_psi++;
+            if (mom) c->vc_W++;
+        } else {
+            outer_body<T>(c, u, W, want_M);
+        }
+        launched++;
+        return post_norms(c, launched & 1);
+    };
+    auto record = [&]() {
         if (rep && rep->history && hist_len < rep->history_cap) {
             std::memcpy(rep->history + 4 * hist_len, nr, sizeof(nr));
             hist_len++;
         }
+    };
+    for (;; it++) {
+        if (graph && launched == it && it < max_outer && w1 > 0.0 && w2 > 0.0 && w1 < w2 &&
+            w1 * (w1 / w2) > kAheadMargin * tol) {
+            mg_status ls = launch_next();
+            if (ls != MG_OK) return ls;
+        }
+        double flag = 0.0;
+        if (hip_status() != MG_OK) return MG_ERR_HIP;
+        mg_status fs = read_norms(c, it & 1, nr, &flag);
+        if (fs != MG_OK) return fs;
+        record();
         const double worst = mom ? std::fmax(nr[0], nr[1]) : nr[0];
         if (flag != 0.0) {
             st = MG_ERR_SINGULAR;
@@ -939,15 +993,26 @@ mg_status solve(mg_ctx *c, double *u, double *W, double tol, int max_outer, mg_r
             st = MG_ERR_NOT_CONVERGED;
             break;
         }
-        if (graph) {
-            mg_status gs = capture_body<T>(c, u, W, want_M);
-            if (gs != MG_OK) return gs;
-            if (hipGraphLaunch(c->gexec, c->s) != hipSuccess) return MG_ERR_HIP;
-            c->vc_psi++;
-            if (mom) c->vc_W++;
-        } else {
-            outer_body<T>(c, u, W, want_M);
+        if (launched == it) {
+            mg_status ls = launch_next();
+            if (ls != MG_OK) return ls;
         }
+        w2 = w1;
+        w1 = worst;
+    }
+    if (launched > it) {
+        // a lookahead iteration ran past the stop: report the state it left
+        double flag = 0.0;
+        mg_status fs = read_norms(c, launched & 1, nr, &flag);
+        if (fs != MG_OK) return fs;
+        record();
+        it = launched;
+        if (flag != 0.0)
+            st = MG_ERR_SINGULAR;
+        else if (!std::isfinite(nr[0]) || !std::isfinite(nr[1]))
+            st = MG_ERR_DIVERGED;
+        else if (st == MG_OK && !(nr[0] <= tol && (!mom || nr[1] <= tol)))
+            st = MG_ERR_NOT_CONVERGED;
     }
     auto t1 = std::chrono::steady_clock::now();
     if (rep) {
@@ -983,7 +1048,7 @@ void release(mg_ctx *c)
 {
     drop_graph(c);
     if (c->s) (void)hipStreamSynchronize(c->s);
-    hipEvent_t *evs[] = {&c->ev_in, &c->ev_out};
+    hipEvent_t *evs[] = {&c->ev_in, &c->ev_out, &c->ev_norm[0], &c->ev_norm[1]};
     for (hipEvent_t *e : evs)
         if (*e) (void)hipEventDestroy(*e);
     if (c->own_streams && c->s) (void)hipStreamDestroy(c->s);
@@ -1003,7 +1068,7 @@ mg_status create_streams(mg_ctx *c)
         c->own_streams = true;
         if (hipStreamCreateWithFlags(&c->s, hipStreamNonBlocking) != hipSuccess) return MG_ERR_HIP;
     }
-    hipEvent_t *evs[] = {&c->ev_in, &c->ev_out};
+    hipEvent_t *evs[] = {&c->ev_in, &c->ev_out, &c->ev_norm[0], &c->ev_norm[1]};
     for (hipEvent_t *e : evs)
         if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) return MG_ERR_HIP;
     return MG_OK;
@@ -1292,7 +1357,7 @@ mg_status ctx_create(const mg_params *p, void *d_workspace, size_t bytes, hipStr
     carve(c, cv);
     init_geo(c);
     if (create_streams(c) != MG_OK ||
-        hipHostMalloc((void **)&c->hpin, S_COUNT * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void **)&c->hpin, 2 * S_COUNT * sizeof(double), hipHostMallocDefault) != hipSuccess) {
         release(c);
         return MG_ERR_HIP;
     }
