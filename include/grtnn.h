@@ -132,9 +132,9 @@ mg_status nn_unpack_output(nn_ctx *ctx, const float *d_out, const nn_norm *norm,
 mg_status nn_moments(nn_ctx *ctx, const double *d_x, const double *d_y, int64_t count, double h_out[2]);
 
 /* Warm start of a constraint solve: predicts (u, W) from the sources into
- * d_u, d_W, applies one outer iteration of the solver to it (mg_vcycle with
- * MG_EQ_BOTH, or MG_EQ_PSI for a context without the momentum equation: the
- * smoother removes the BF16-level roughness of the prediction at once), and
+ * d_u, d_W, applies one outer iteration of the solver to it (as one outer
+ * iteration of mg_solve_constraints: the smoother removes the BF16-level
+ * roughness of the prediction at once), and
  * keeps the result (*h_used = 1) only if its RMS constraint residuals are
  * finite and their maximum is below that of the zero state u = 0, W = 0;
  * otherwise d_u and d_W are set to zero (*h_used = 0).  The solver context

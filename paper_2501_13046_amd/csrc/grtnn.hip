@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <limits>
 #include <new>
 
 #include "grtnn.h"
@@ -733,25 +734,30 @@ mg_status nn_warm_start(nn_ctx *c, mg_ctx *solver, const double *d_rho5, const d
     if (hipMemsetAsync(d_u, 0, V * sizeof(double), c->s) != hipSuccess ||
         hipMemsetAsync(d_W, 0, 3 * V * sizeof(double), c->s) != hipSuccess)
         return MG_ERR_HIP;
-    mg_status st = sync_status(c->s);
-    if (st != MG_OK) return st;
-    st = mg_residual_norm(solver, d_u, d_W, zero);
+    // (the solver's calls are ordered after this stream's work)
+    mg_status st = mg_residual_norm(solver, d_u, d_W, zero);
     if (st != MG_OK) return st;
     // prediction
     st = nn_pack_input(c, d_rho5, d_rho1, d_S, norm, c->x);
     if (st != MG_OK) return st;
     forward(c, c->x, c->out);
     st = nn_unpack_output(c, c->out, norm, d_u, d_W);
-    if (st == MG_OK) st = sync_status(c->s);
     if (st != MG_OK) return st;
     // one outer iteration first: the smoother removes the BF16-level roughness
     // of the prediction at once, and the comparison is then about the smooth
-    // error that decides the remaining iterations
-    st = mg_vcycle(solver, MG_EQ_BOTH, d_u, d_W);
-    if (st == MG_ERR_INVALID) st = mg_vcycle(solver, MG_EQ_PSI, d_u, d_W);
-    if (st != MG_OK) return st;
-    st = mg_residual_norm(solver, d_u, d_W, pred);
-    if (st != MG_OK) return st;
+    // error that decides the remaining iterations.  The solver runs it as its
+    // own outer iteration (the captured graph the solve that follows replays)
+    // and reports the norms after it; no tolerance can be met (tol 1e-300).
+    mg_report rep;
+    std::memset(&rep, 0, sizeof(rep));
+    st = mg_solve_constraints(solver, d_u, d_W, 1e-300, 1, &rep);
+    if (st != MG_OK && st != MG_ERR_NOT_CONVERGED && st != MG_ERR_DIVERGED) return st;
+    pred[0] = rep.h_rms;
+    pred[1] = rep.m_rms;
+    pred[2] = rep.h_max;
+    pred[3] = rep.m_max;
+    if (st == MG_ERR_DIVERGED && std::isfinite(pred[0]) && std::isfinite(pred[1]))
+        pred[0] = pred[1] = std::numeric_limits<double>::infinity(); // never kept
     const double wz = std::max(zero[0], zero[1]), wp = std::max(pred[0], pred[1]);
     const bool keep = std::isfinite(pred[0]) && std::isfinite(pred[1]) && wp < wz;
     if (!keep) {
