@@ -466,9 +466,9 @@ void prolong_add(mg_ctx *c, int lc, const T *coarse, T *fine, int ncomp)
     Probe pr(c, MG_PROBE_PROLONG, lc - 1);
     const Geo &gc = c->geo[lc];
     const unsigned nb = nblk(c->cells[lc - 1]);
-    if (c->p.bc == MG_BC_PERIODIC)
-        hipLaunchKernelGGL((k_prolong_add<kBcPeriodic, T>), dim3(nb), dim3(kBlock), 0, c->s, gc, coarse,
-                           fine, ncomp);
+    if (c->p.bc == MG_BC_PERIODIC) // one thread per fine z pair
+        hipLaunchKernelGGL(k_prolong_add_pairs<T>, dim3(nblk(c->cells[lc - 1] / 2)), dim3(kBlock), 0, c->s, gc,
+                           coarse, fine, ncomp);
     else
         hipLaunchKernelGGL((k_prolong_add<kBcRobin, T>), dim3(nb), dim3(kBlock), 0, c->s, gc, coarse,
                            fine, ncomp);

@@ -64,6 +64,49 @@ struct Vec2<double> {
     using type = double2;
 };
 
+// ---------------------------------------------------------------------------------------
+// Periodic trilinear prolongation for a z pair of fine cells (2K, 2K + 1):
+// both share coarse z K and their coarse x and y neighbours, and take coarse z
+// K - 1 and K + 1 respectively, so a pair reads 12 coarse values instead of
+// 16 and updates its two fine values with one vector load and store.  Each
+// value is prolong_cell's expression.
+// ---------------------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_prolong_add_pairs(Geo gc, const T *__restrict__ coarse,
+                                                             T *__restrict__ fine, int ncomp)
+{
+    using V2 = typename Vec2<T>::type;
+    const int nc = gc.n, nf = 2 * nc;
+    const unsigned pairs = (unsigned)nf * nf * nc;
+    const unsigned t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= pairs) return;
+    const unsigned row = t / (unsigned)nc;
+    const int K = (int)(t - row * (unsigned)nc);
+    const int i = (int)(row / (unsigned)nf), j = (int)(row - (unsigned)i * nf);
+    const int I = i >> 1, J = j >> 1;
+    const int I1 = wrap((i & 1) ? I + 1 : I - 1, nc), J1 = wrap((j & 1) ? J + 1 : J - 1, nc);
+    const int Km = wrap(K - 1, nc), Kp = wrap(K + 1, nc);
+    const T a = T(0.75), b = T(0.25);
+    const size_t mf = (size_t)nf * nf * nf, mc = (size_t)nc * nc * nc;
+    const unsigned r00 = ((unsigned)I * nc + J) * nc, r01 = ((unsigned)I * nc + J1) * nc;
+    const unsigned r10 = ((unsigned)I1 * nc + J) * nc, r11 = ((unsigned)I1 * nc + J1) * nc;
+    for (int s = 0; s < ncomp; s++) {
+        const T *C = coarse + s * mc;
+        const T c00 = C[r00 + K], c01 = C[r01 + K], c10 = C[r10 + K], c11 = C[r11 + K];
+        const T m00 = C[r00 + Km], m01 = C[r01 + Km], m10 = C[r10 + Km], m11 = C[r11 + Km];
+        const T p00 = C[r00 + Kp], p01 = C[r01 + Kp], p10 = C[r10 + Kp], p11 = C[r11 + Kp];
+        const T v0 = a * (a * (a * c00 + b * m00) + b * (a * c01 + b * m01)) +
+                     b * (a * (a * c10 + b * m10) + b * (a * c11 + b * m11));
+        const T v1 = a * (a * (a * c00 + b * p00) + b * (a * c01 + b * p01)) +
+                     b * (a * (a * c10 + b * p10) + b * (a * c11 + b * p11));
+        V2 *F = reinterpret_cast<V2 *>(fine + s * mf + ((size_t)i * nf + j) * nf + 2 * K);
+        V2 f = *F;
+        f.x += v0;
+        f.y += v1;
+        *F = f;
+    }
+}
+
 // Stage brick + halo of one field.  A staged row (fixed x, y) holds the 66
 // aligned z pairs (z0 - 2 + 2P, z0 - 1 + 2P), P = 0..65; pair P lands at
 // words P (even z) and kHalf + P (odd z).  Every lane of wave w moves pair
