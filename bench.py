@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the finest-level W pass from FETCH_SIZE / WRITE_SIZE runs,
 # valid only for the kernel sources they were measured on (sha256 prefixes)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pass_W_march_coupled_128_traffic.md")
-TRAFFIC_SOURCES = {"paper_2501_13046_amd/csrc/mg_tiled.hpp": "7302b44095927fa3",
+TRAFFIC_SOURCES = {"paper_2501_13046_amd/csrc/mg_tiled.hpp": "3f47065d8fbe5c58",
                    "paper_2501_13046_amd/csrc/mg_device.hpp": "cb330752cce51a61"}
 
 
