@@ -265,17 +265,30 @@ struct Out {
 
 
 
-// Brick kernel launch: one block per 4 x 4 x 16 brick (n a multiple of 16).
+// Brick kernel launch: one block per 4 x 4 x 16 brick (n a multiple of 16).  Grids
+// of fewer than 1024 blocks keep 7 K steps of weights in flight, larger ones 2.
+template <int NTB, int PD>
+void launch_conv_brick_pd(hipStream_t s, const ConvArgs &a, const dim3 &grid, int cs)
+{
+    if (cs == 32)
+        hipLaunchKernelGGL((k_conv3_brick<NTB, 32, PD>), grid, dim3(kNBlock), 0, s, a);
+    else if (cs == 16)
+        hipLaunchKernelGGL((k_conv3_brick<NTB, 16, PD>), grid, dim3(kNBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_conv3_brick<NTB, 8, PD>), grid, dim3(kNBlock), 0, s, a);
+}
+
 template <int NTB>
 void launch_conv_brick(hipStream_t s, const ConvArgs &a, int n, int cs, unsigned gy)
 {
     const dim3 grid((unsigned)((int64_t)n * n * n / 256), gy);
-    if (cs == 32)
-        hipLaunchKernelGGL((k_conv3_brick<NTB, 32>), grid, dim3(kNBlock), 0, s, a);
-    else if (cs == 16)
-        hipLaunchKernelGGL((k_conv3_brick<NTB, 16>), grid, dim3(kNBlock), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_conv3_brick<NTB, 8>), grid, dim3(kNBlock), 0, s, a);
+    if constexpr (NTB == 1) {
+        if ((int64_t)grid.x * gy < 1024) {
+            launch_conv_brick_pd<1, 7>(s, a, grid, cs);
+            return;
+        }
+    }
+    launch_conv_brick_pd<NTB, 2>(s, a, grid, cs);
 }
 
 void launch_conv(hipStream_t s, const Layer &ly, bool transposed, int n, const u16 *in1, int c1, int act1,
@@ -455,8 +468,14 @@ void forward(nn_ctx *c, const u16 *in, float *out)
     for (int l = L - 2; l >= 0; l--) {
         const int n = c->nl[l];
         const u16 *src = (l == L - 2) ? c->ab[L - 1] : c->adb[l + 1];
-        const int64_t e = c->V[l] * (g.ch[l + 1] / 8);
-        hipLaunchKernelGGL(k_up, dim3(nblk(e)), dim3(kNBlock), 0, s, src, g.ch[l + 1], c->nl[l + 1], 0, c->upb[l]);
+        // one thread per fine cell and octet where one per coarse cell would leave the chip idle
+        const int64_t ec = c->V[l + 1] * (g.ch[l + 1] / 8);
+        if (ec >= 65536)
+            hipLaunchKernelGGL(k_up, dim3(nblk(ec)), dim3(kNBlock), 0, s, src, g.ch[l + 1], c->nl[l + 1], 0,
+                               c->upb[l]);
+        else
+            hipLaunchKernelGGL(k_up_fine, dim3(nblk(8 * ec)), dim3(kNBlock), 0, s, src, g.ch[l + 1], c->nl[l + 1],
+                               0, c->upb[l]);
         const Layer &da = c->layer[dec_layer(c, l, 0)], &db = c->layer[dec_layer(c, l, 1)];
         launch_conv(s, da, false, n, c->ab[l], g.ch[l], 0, c->upb[l], g.ch[l + 1], 0, da.bias,
                     act_out(g.ch[l], c->ada[l], c->zda[l]), none);

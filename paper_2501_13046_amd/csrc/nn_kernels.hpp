@@ -334,7 +334,9 @@ __device__ __forceinline__ int tap_offset(int g)
         return g == 0 ? T.v[4 * ST] : g == 1 ? T.v[4 * ST + 1] : g == 2 ? T.v[4 * ST + 2] : T.v[4 * ST + 3];
 }
 
-template <int NTB, int CS>
+// PD: weight prefetch depth in K steps (2 for grids that fill the chip, deeper
+// for the small levels whose few blocks wait on every weight fetch).
+template <int NTB, int CS, int PD>
 __global__ void __launch_bounds__(kNBlock) k_conv3_brick(ConvArgs a)
 {
     constexpr int P = CS / 8;
@@ -362,19 +364,23 @@ __global__ void __launch_bounds__(kNBlock) k_conv3_brick(ConvArgs a)
     const u32x4 zero = {0u, 0u, 0u, 0u};
     const int nslice = (a.c1 + a.c2) / CS;
     constexpr int spp = TapOffsets<P>::kSteps; // K steps per slice (the packed order's spp)
+    static_assert(PD >= 2 && PD <= spp, "prefetch depth");
     const int lbase = ((wave * kHY) * kHZ + r) * P;
-    auto wload = [&](int ch, u32x4 (&bw)[NTB]) {
+    // weights (L2-resident, the same for every block): a ring of PD K steps; step
+    // st + PD - 1 is fetched when step st starts
+    u32x4 bw[PD][NTB];
+    auto wload = [&](int ch, u32x4 (&w)[NTB]) {
 #pragma unroll
         for (int t = 0; t < NTB; t++)
-            bw[t] = (t0 + t < a.ntile) ? a.w[((int64_t)(t0 + t) * a.nchunk + ch) * 64 + lane] : zero;
+            w[t] = (t0 + t < a.ntile) ? a.w[((int64_t)(t0 + t) * a.nchunk + ch) * 64 + lane] : zero;
     };
-    for (int sl = 0; sl < nslice; sl++) {
+    // halo of one channel slice, fetched into registers (wrapped periodically)
+    u32x4 stg[NE];
+    auto stage_load = [&](int sl) {
         const int cb = sl * CS;
         const bool one = cb < a.c1;
         const u16 *src = one ? a.in1 : a.in2;
         const int cs = one ? a.c1 : a.c2, c0 = one ? cb : cb - a.c1;
-        // issue every staging load of the slice before the first LDS store
-        u32x4 stg[NE];
 #pragma unroll
         for (int k = 0; k < NE; k++) {
             const int e = threadIdx.x + k * kNBlock;
@@ -386,8 +392,11 @@ __global__ void __launch_bounds__(kNBlock) k_conv3_brick(ConvArgs a)
                 stg[k] = *(const u32x4 *)(src + (((int64_t)gx * n + gy) * n + gz) * cs + c0 + o * 8);
             }
         }
-        u32x4 bw[2][NTB]; // weights of the current and the next K step
-        wload(sl * spp, bw[0]);
+    };
+    for (int sl = 0; sl < nslice; sl++) {
+        // every staging load of the slice is issued before the first LDS store
+        stage_load(sl);
+        static_for<PD - 1>([&](auto k) { wload(sl * spp + decltype(k)::value, bw[decltype(k)::value]); });
         __syncthreads(); // previous slice consumed
 #pragma unroll
         for (int k = 0; k < NE; k++) {
@@ -396,10 +405,10 @@ __global__ void __launch_bounds__(kNBlock) k_conv3_brick(ConvArgs a)
         }
         __syncthreads();
         // K steps unrolled: the halo offsets of the taps are compile-time constants
-        // (one select by lane group per step), weights prefetched one step ahead
+        // (one select by lane group per step)
         static_for<spp>([&](auto stc) {
             constexpr int st = decltype(stc)::value;
-            if constexpr (st + 1 < spp) wload(sl * spp + st + 1, bw[(st + 1) & 1]);
+            if constexpr (st + PD - 1 < spp) wload(sl * spp + st + PD - 1, bw[(st + PD - 1) % PD]);
             const u32x4 *ap = smem + lbase + tap_offset<P, st>(g);
             u32x4 av[4];
 #pragma unroll
@@ -413,7 +422,7 @@ __global__ void __launch_bounds__(kNBlock) k_conv3_brick(ConvArgs a)
 #pragma unroll
             for (int q = 0; q < 4; q++)
 #pragma unroll
-                for (int t = 0; t < NTB; t++) acc[q][t] = mfma(av[q], bw[st & 1][t], acc[q][t]);
+                for (int t = 0; t < NTB; t++) acc[q][t] = mfma(av[q], bw[st % PD][t], acc[q][t]);
         });
     }
     // epilogue through LDS: every thread then writes whole channel octets
@@ -819,8 +828,68 @@ __global__ void __launch_bounds__(kNBlock) k_pool(const u16 *z, int C, int nc, i
 }
 
 // Per-axis weights of cell-centred x2 interpolation: fine 2I+a takes 3/4 of
-// coarse I and 1/4 of coarse I-1 (a = 0) or I+1 (a = 1).
+// coarse I and 1/4 of coarse I-1 (a = 0) or I+1 (a = 1).  One thread per
+// (coarse cell, octet) fetches the 3 x 3 x 3 coarse neighbourhood once and
+// writes the octet of all 8 children; each child sums its 8 terms in the order
+// (own, neighbour) per axis, x outermost.
 __global__ void __launch_bounds__(kNBlock) k_up(const u16 *z, int C, int nc, int act, u16 *out)
+{
+    const int oc = C / 8;
+    const int64_t Vc = (int64_t)nc * nc * nc;
+    const int64_t e = (int64_t)blockIdx.x * kNBlock + threadIdx.x;
+    if (e >= Vc * oc) return;
+    const int o = (int)(e % oc);
+    const int64_t v = e / oc;
+    const int K = (int)(v % nc), J = (int)((v / nc) % nc), I = (int)(v / ((int64_t)nc * nc));
+    int xi[3], yj[3], zk[3];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        xi[d] = wrapn(I + d - 1, nc);
+        yj[d] = wrapn(J + d - 1, nc);
+        zk[d] = wrapn(K + d - 1, nc);
+    }
+    u32x4 nb[3][3][3];
+#pragma unroll
+    for (int dx = 0; dx < 3; dx++)
+#pragma unroll
+        for (int dy = 0; dy < 3; dy++)
+#pragma unroll
+            for (int dz = 0; dz < 3; dz++) {
+                const int64_t vc = ((int64_t)xi[dx] * nc + yj[dy]) * nc + zk[dz];
+                u32x4 w = *(const u32x4 *)(z + vc * C + 8 * o);
+                nb[dx][dy][dz] = act ? silu8(w) : w;
+            }
+    const float wt[2] = {0.75f, 0.25f};
+    const int nf = 2 * nc;
+#pragma unroll
+    for (int ca = 0; ca < 2; ca++)
+#pragma unroll
+        for (int cb = 0; cb < 2; cb++)
+#pragma unroll
+            for (int cc = 0; cc < 2; cc++) {
+                float s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+                for (int a = 0; a < 2; a++)
+#pragma unroll
+                    for (int b = 0; b < 2; b++)
+#pragma unroll
+                        for (int c = 0; c < 2; c++) {
+                            // own cell (index 1) or the neighbour on the child's side
+                            const int dx = a ? (ca ? 2 : 0) : 1, dy = b ? (cb ? 2 : 0) : 1, dz = c ? (cc ? 2 : 0) : 1;
+                            float f[8];
+                            unpack8(nb[dx][dy][dz], f);
+                            const float ww = wt[a] * wt[b] * wt[c];
+#pragma unroll
+                            for (int q = 0; q < 8; q++) s[q] += ww * f[q];
+                        }
+                const int64_t vf = ((int64_t)(2 * I + ca) * nf + (2 * J + cb)) * nf + (2 * K + cc);
+                *(u32x4 *)(out + vf * C + 8 * o) = pack8(s);
+            }
+}
+
+// The same interpolation with one thread per (fine cell, octet), each reading
+// its 8 coarse cells (the same sums in the same order as k_up).
+__global__ void __launch_bounds__(kNBlock) k_up_fine(const u16 *z, int C, int nc, int act, u16 *out)
 {
     const int oc = C / 8;
     const int nf = 2 * nc;
