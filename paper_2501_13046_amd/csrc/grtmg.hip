@@ -18,6 +18,7 @@
 #include "grtmg.h"
 #include "mg_kernels.hpp"
 #include "mg_tiled.hpp"
+#include "mg_internal.h"
 
 using namespace grtmg;
 
@@ -2030,3 +2031,37 @@ mg_status mg_kernel_op(mg_ctx *c, int32_t op, int32_t level, int32_t arg, const 
 }
 
 } // extern "C"
+
+namespace grtmg {
+
+mg_status zero_norms_begin(mg_ctx *c, double *d_u, double *d_W)
+{
+    if (!c || !d_u || (c->S && !d_W)) return MG_ERR_INVALID;
+    const bool want_M = c->S != nullptr;
+    const int64_t m = c->cells[0];
+    enter(c);
+    if (hipMemsetAsync(d_u, 0, m * sizeof(double), c->s) != hipSuccess ||
+        (d_W && hipMemsetAsync(d_W, 0, 3 * m * sizeof(double), c->s) != hipSuccess)) {
+        leave(c);
+        return MG_ERR_HIP;
+    }
+    source_mean(c, d_u);
+    if (c->f32)
+        residual<float>(c, d_u, d_W, want_M, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, true);
+    else
+        residual<double>(c, d_u, d_W, want_M, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, true);
+    mg_status st = hip_status();
+    if (st == MG_OK) st = post_norms(c, 0);
+    if (st != MG_OK) leave(c);
+    return st;
+}
+
+mg_status zero_norms_end(mg_ctx *c, double out[4])
+{
+    if (!c || !out) return MG_ERR_INVALID;
+    mg_status st = read_norms(c, 0, out, nullptr);
+    leave(c);
+    return st;
+}
+
+} // namespace grtmg

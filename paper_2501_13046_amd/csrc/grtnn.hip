@@ -16,6 +16,7 @@
 
 #include "grtnn.h"
 #include "nn_kernels.hpp"
+#include "mg_internal.h"
 
 using namespace grtnn;
 
@@ -749,17 +750,16 @@ mg_status nn_warm_start(nn_ctx *c, mg_ctx *solver, const double *d_rho5, const d
         return MG_ERR_INVALID;
     const int64_t V = c->V[0];
     double zero[4], pred[4];
-    // residual of the zero start (u = 0, W = 0)
-    if (hipMemsetAsync(d_u, 0, V * sizeof(double), c->s) != hipSuccess ||
-        hipMemsetAsync(d_W, 0, 3 * V * sizeof(double), c->s) != hipSuccess)
-        return MG_ERR_HIP;
-    // (the solver's calls are ordered after this stream's work)
-    mg_status st = mg_residual_norm(solver, d_u, d_W, zero);
+    // residual of the zero start (u = 0, W = 0) on the solver's stream, while the
+    // network runs on this one (the solver's calls are ordered after the work on
+    // its caller stream; the prediction is written into u, W once it is done)
+    mg_status st = grtmg::zero_norms_begin(solver, d_u, d_W);
     if (st != MG_OK) return st;
-    // prediction
     st = nn_pack_input(c, d_rho5, d_rho1, d_S, norm, c->x);
+    if (st == MG_OK) forward(c, c->x, c->out);
+    const mg_status sz = grtmg::zero_norms_end(solver, zero);
     if (st != MG_OK) return st;
-    forward(c, c->x, c->out);
+    if (sz != MG_OK) return sz;
     st = nn_unpack_output(c, c->out, norm, d_u, d_W);
     if (st != MG_OK) return st;
     // one outer iteration first: the smoother removes the BF16-level roughness

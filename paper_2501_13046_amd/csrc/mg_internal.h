@@ -1,0 +1,20 @@
+// Solver functions used by the network runtime in the same library; not part
+// of the C ABI.
+#pragma once
+
+#include "grtmg.h"
+
+namespace grtmg {
+
+// Residual norms of the zero state (u = 0, W_i = 0), in two halves so that the
+// caller can queue other work on its own stream in between: begin zeroes d_u
+// and d_W (cells and 3 x cells doubles) and queues the evaluation on the
+// solver's internal stream, ordered after the work queued on the solver's
+// caller stream so far but not after anything queued there later; end waits
+// for it, returns the norms as mg_residual_norm does, and orders the caller
+// stream after it.  d_u and d_W must not be used by other work in between.
+// Every successful begin must be followed by an end.
+mg_status zero_norms_begin(mg_ctx *c, double *d_u, double *d_W);
+mg_status zero_norms_end(mg_ctx *c, double out[4]);
+
+} // namespace grtmg
