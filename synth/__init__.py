@@ -112,11 +112,13 @@ def coupled(n: int = 128, seed: int = 0, phi_amp: float = 0.05,
             precision: int = PREC_FP32_IR, levels: Optional[int] = None) -> Workload:
     rng_phi = np.random.default_rng(seed)
     rng_pi = np.random.default_rng([seed, 1])
+    # V(1,2) cycles: of nu_pre, nu_post in 1..4 the fastest to rms 1e-10 at 128^3
+    # (17 outer iterations against 15 with V(2,2), each ~15% cheaper)
     return Workload(name=f"coupled_{n}", n=n,
                     levels=levels if levels is not None else coarsest_levels(n),
                     seed=seed, phi_modes=fourier_modes(rng_phi, 8, phi_amp),
                     pi_modes=fourier_modes(rng_pi, 8, 0.02),
-                    precision=precision, solve_momentum=True)
+                    precision=precision, solve_momentum=True, nu_pre=1, nu_post=2)
 
 
 def coupled_128(seed: int = 0, precision: int = PREC_FP32_IR) -> Workload:
