@@ -155,7 +155,8 @@ def main():
 
         def step_learned():
             used, _ = net.warm_start(mixed, rho5, rho1, S, nm, u, W)
-            r = mixed.solve(u, W, tol=args.tol, max_outer=100)
+            # a kept prediction continues from the check iteration's state
+            r = mixed.solve(u, W, tol=args.tol, max_outer=100, resume=used)
             return used, r
 
         for _ in range(args.warmup):

@@ -149,6 +149,21 @@ mg_status mg_vcycle(mg_ctx *ctx, int32_t eq, double *d_u, double *d_W);
 mg_status mg_solve_constraints(mg_ctx *ctx, double *d_u, double *d_W, double tol,
                                int32_t max_outer, mg_report *rep);
 
+/*
+ * Continues the last mg_solve_constraints (or mg_solve_constraints_continue)
+ * call on this context from the state it left in the same d_u, d_W: that
+ * state's evaluation, still held in the workspace, is not repeated, and the
+ * host round trips overlap the GPU work from the first iteration on.  Valid
+ * only while no other call has been made on the context and the arrays have
+ * not been changed since (the caller's guarantee for the arrays; nn_warm_start
+ * leaves a continuable state when it keeps its prediction); otherwise, or after
+ * a call that ended in any status but MG_OK or MG_ERR_NOT_CONVERGED, returns
+ * MG_ERR_INVALID.  Iteration counts and norms as mg_solve_constraints (the
+ * resumed state counts as iteration 0).  A runtime addition, not in the paper.
+ */
+mg_status mg_solve_constraints_continue(mg_ctx *ctx, double *d_u, double *d_W, double tol,
+                                        int32_t max_outer, mg_report *rep);
+
 /* Constraint norms at (d_u, d_W): out[4] (host) = rms H_h, rms |M_h|, max |H_h|,
  * max |M_h| (the momentum entries are 0 when d_S was NULL).  Synchronises. */
 mg_status mg_residual_norm(mg_ctx *ctx, const double *d_u, const double *d_W, double out[4]);

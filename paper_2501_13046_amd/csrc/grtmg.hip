@@ -118,6 +118,11 @@ struct mg_ctx {
     // timing probe
     int probe_kernel, probe_level, probe_count;
     hipEvent_t *probe_ev; // 2 * kProbeMax events, created on first use
+    // continuation: the state the last solve left in (cont_u, cont_W), whose
+    // evaluation is still current in the workspace; cleared by every other call
+    bool cont_valid;
+    const double *cont_u, *cont_W;
+    double cont_nr[4], cont_prev; // its norms; worst norm of the iteration before (< 0: none)
 };
 
 namespace {
@@ -936,7 +941,10 @@ mg_status capture_body(mg_ctx *c, double *u, double *W, bool want_M)
 }
 
 template <typename T>
-mg_status solve(mg_ctx *c, double *u, double *W, double tol, int max_outer, mg_report *rep)
+// resume: (u, W) is the state the last solve on c left (c->cont_valid), whose
+// evaluation is current in the workspace: it is not evaluated again, and the
+// lookahead can start from the first iteration.
+mg_status solve(mg_ctx *c, double *u, double *W, double tol, int max_outer, mg_report *rep, bool resume = false)
 {
     auto t0 = std::chrono::steady_clock::now();
     c->vc_psi = c->vc_W = 0;
@@ -953,9 +961,18 @@ mg_status solve(mg_ctx *c, double *u, double *W, double tol, int max_outer, mg_r
     // kAheadMargin times above tol, so it cannot be the last one.
     constexpr double kAheadMargin = 10.0;
     double w1 = -1.0, w2 = -1.0; // worst norm after the last and the one-before-last read iteration
+    double last_worst = -1.0;      // worst norm of the last read iteration
+    double resumed[4] = {0, 0, 0, 0};
+    if (resume) {
+        std::memcpy(resumed, c->cont_nr, sizeof(resumed));
+        w1 = c->cont_prev;
+    }
+    c->cont_valid = false;
     fill<double>(c->s, c->scal + S_FLAG_PSI, 2, 0.0);
-    evaluate<T>(c, u, W, want_M);
-    if (post_norms(c, 0) != MG_OK) return MG_ERR_HIP;
+    if (!resume) {
+        evaluate<T>(c, u, W, want_M);
+        if (post_norms(c, 0) != MG_OK) return MG_ERR_HIP;
+    }
     auto launch_next = [&]() -> mg_status {
         if (graph) {
             mg_status gs = capture_body<T>(c, u, W, want_M);
@@ -983,10 +1000,15 @@ mg_status solve(mg_ctx *c, double *u, double *W, double tol, int max_outer, mg_r
         }
         double flag = 0.0;
         if (hip_status() != MG_OK) return MG_ERR_HIP;
-        mg_status fs = read_norms(c, it & 1, nr, &flag);
-        if (fs != MG_OK) return fs;
+        if (resume && it == 0) {
+            std::memcpy(nr, resumed, sizeof(nr));
+        } else {
+            mg_status fs = read_norms(c, it & 1, nr, &flag);
+            if (fs != MG_OK) return fs;
+        }
         record();
         const double worst = mom ? std::fmax(nr[0], nr[1]) : nr[0];
+        last_worst = worst;
         if (flag != 0.0) {
             st = MG_ERR_SINGULAR;
             break;
@@ -1015,8 +1037,10 @@ mg_status solve(mg_ctx *c, double *u, double *W, double tol, int max_outer, mg_r
         w2 = w1;
         w1 = worst;
     }
+    double prev_worst = w1; // worst norm of the iteration before the final state
     if (launched > it) {
         // a lookahead iteration ran past the stop: report the state it left
+        prev_worst = last_worst;
         double flag = 0.0;
         mg_status fs = read_norms(c, launched & 1, nr, &flag);
         if (fs != MG_OK) return fs;
@@ -1028,6 +1052,13 @@ mg_status solve(mg_ctx *c, double *u, double *W, double tol, int max_outer, mg_r
             st = MG_ERR_DIVERGED;
         else if (st == MG_OK && !(nr[0] <= tol && (!mom || nr[1] <= tol)))
             st = MG_ERR_NOT_CONVERGED;
+    }
+    if ((st == MG_OK || st == MG_ERR_NOT_CONVERGED) && !c->batched) {
+        c->cont_valid = true;
+        c->cont_u = u;
+        c->cont_W = W;
+        std::memcpy(c->cont_nr, nr, sizeof(nr));
+        c->cont_prev = prev_worst;
     }
     auto t1 = std::chrono::steady_clock::now();
     if (rep) {
@@ -1773,6 +1804,7 @@ mg_status mg_vcycle(mg_ctx *c, int32_t eq, double *d_u, double *d_W)
 {
     if (!c || !d_u || eq < 1 || eq > 3) return MG_ERR_INVALID;
     if ((eq & MG_EQ_W) && (!c->momentum || !d_W)) return MG_ERR_INVALID;
+    c->cont_valid = false;
     enter(c);
     if (c->f32) {
         if (eq & MG_EQ_W) step_W<float>(c, d_u, d_W, false);
@@ -1791,9 +1823,24 @@ mg_status mg_solve_constraints(mg_ctx *c, double *d_u, double *d_W, double tol, 
     if (!c || !d_u || !(tol > 0.0) || max_outer < 0) return MG_ERR_INVALID;
     if (c->momentum && !d_W) return MG_ERR_INVALID;
     if (rep && rep->history && rep->history_cap < 0) return MG_ERR_INVALID;
+    c->cont_valid = false;
     enter(c);
     mg_status st = c->f32 ? solve<float>(c, d_u, d_W, tol, max_outer, rep)
                           : solve<double>(c, d_u, d_W, tol, max_outer, rep);
+    leave(c);
+    return st;
+}
+
+mg_status mg_solve_constraints_continue(mg_ctx *c, double *d_u, double *d_W, double tol, int32_t max_outer,
+                                        mg_report *rep)
+{
+    if (!c || !d_u || !(tol > 0.0) || max_outer < 0) return MG_ERR_INVALID;
+    if (c->momentum && !d_W) return MG_ERR_INVALID;
+    if (rep && rep->history && rep->history_cap < 0) return MG_ERR_INVALID;
+    if (!c->cont_valid || c->cont_u != d_u || c->cont_W != d_W) return MG_ERR_INVALID;
+    enter(c);
+    mg_status st = c->f32 ? solve<float>(c, d_u, d_W, tol, max_outer, rep, true)
+                          : solve<double>(c, d_u, d_W, tol, max_outer, rep, true);
     leave(c);
     return st;
 }
@@ -1802,6 +1849,7 @@ mg_status mg_residual_norm(mg_ctx *c, const double *d_u, const double *d_W, doub
 {
     if (!c || !d_u || !out) return MG_ERR_INVALID;
     const bool want_M = c->S != nullptr;
+    c->cont_valid = false;
     enter(c);
     source_mean(c, d_u);
     if (c->f32)
@@ -1820,6 +1868,7 @@ mg_status mg_residual_fields(mg_ctx *c, const double *d_u, const double *d_W, do
     if (!c || !d_u) return MG_ERR_INVALID;
     const bool want_M = d_M != nullptr;
     if (want_M && !c->S) return MG_ERR_INVALID;
+    c->cont_valid = false;
     enter(c);
     source_mean(c, d_u);
     residual<double>(c, d_u, d_W, want_M, d_H, d_M, d_c, nullptr, nullptr, nullptr, false);
@@ -1958,6 +2007,7 @@ mg_status mg_fmg_start(mg_ctx *cc, mg_ctx *cf, double *d_uc, double *d_Wc, doubl
                        double *d_uf, double *d_Wf, mg_report *rep_c)
 {
     if (!cc || !cf || !d_uc || !d_uf || !(tol_c > 0.0) || max_outer < 0) return MG_ERR_INVALID;
+    cc->cont_valid = cf->cont_valid = false;
     const mg_params &a = cc->p, &b = cf->p;
     if (b.n != 2 * a.n || a.bc != b.bc || a.length != b.length || cc->momentum != cf->momentum) return MG_ERR_INVALID;
     for (int q = 0; q < 3; q++)
@@ -1988,6 +2038,7 @@ mg_status mg_autotune(mg_ctx *c, const double *d_u, const double *d_W, int32_t r
 {
     if (!c || !d_u || reps < 1 || reps > 1000 || cap < 0 || (cap > 0 && !h_out)) return MG_ERR_INVALID;
     if (c->momentum && !d_W) return MG_ERR_INVALID;
+    c->cont_valid = false;
     enter(c);
     int k = 0;
     mg_status st = c->f32 ? autotune<float>(c, d_u, d_W, reps, h_out, cap, &k)
@@ -2000,6 +2051,7 @@ mg_status mg_autotune(mg_ctx *c, const double *d_u, const double *d_W, int32_t r
 mg_status mg_set_tile(mg_ctx *c, int32_t family, int32_t level, int32_t tx)
 {
     if (!c || level < 0 || level >= c->L) return MG_ERR_INVALID;
+    c->cont_valid = false;
     if (family == MG_TUNE_TAIL_PSI || family == MG_TUNE_TAIL_W) {
         const int start = family == MG_TUNE_TAIL_PSI ? c->tail_psi : c->tail_W;
         if (start < 0 || level != start || (tx != 0 && tx != 1)) return MG_ERR_INVALID;
@@ -2023,6 +2075,7 @@ mg_status mg_kernel_op(mg_ctx *c, int32_t op, int32_t level, int32_t arg, const 
                        const void *d_r, const void *d_c)
 {
     if (!c) return MG_ERR_INVALID;
+    c->cont_valid = false;
     enter(c);
     mg_status st = c->f32 ? kernel_op<float>(c, op, level, arg, d_in, d_out, d_r, d_c)
                           : kernel_op<double>(c, op, level, arg, d_in, d_out, d_r, d_c);
@@ -2039,6 +2092,7 @@ mg_status zero_norms_begin(mg_ctx *c, double *d_u, double *d_W)
     if (!c || !d_u || (c->S && !d_W)) return MG_ERR_INVALID;
     const bool want_M = c->S != nullptr;
     const int64_t m = c->cells[0];
+    c->cont_valid = false;
     enter(c);
     if (hipMemsetAsync(d_u, 0, m * sizeof(double), c->s) != hipSuccess ||
         (d_W && hipMemsetAsync(d_W, 0, 3 * m * sizeof(double), c->s) != hipSuccess)) {
@@ -2054,6 +2108,11 @@ mg_status zero_norms_begin(mg_ctx *c, double *d_u, double *d_W)
     if (st == MG_OK) st = post_norms(c, 0);
     if (st != MG_OK) leave(c);
     return st;
+}
+
+void cancel_continue(mg_ctx *c)
+{
+    if (c) c->cont_valid = false;
 }
 
 mg_status zero_norms_end(mg_ctx *c, double out[4])

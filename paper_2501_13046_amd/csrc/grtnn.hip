@@ -780,6 +780,7 @@ mg_status nn_warm_start(nn_ctx *c, mg_ctx *solver, const double *d_rho5, const d
     const double wz = std::max(zero[0], zero[1]), wp = std::max(pred[0], pred[1]);
     const bool keep = std::isfinite(pred[0]) && std::isfinite(pred[1]) && wp < wz;
     if (!keep) {
+        grtmg::cancel_continue(solver);
         if (hipMemsetAsync(d_u, 0, V * sizeof(double), c->s) != hipSuccess ||
             hipMemsetAsync(d_W, 0, 3 * V * sizeof(double), c->s) != hipSuccess)
             return MG_ERR_HIP;

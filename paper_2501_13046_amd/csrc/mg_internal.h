@@ -17,4 +17,8 @@ namespace grtmg {
 mg_status zero_norms_begin(mg_ctx *c, double *d_u, double *d_W);
 mg_status zero_norms_end(mg_ctx *c, double out[4]);
 
+// Forgets the state the last solve left, so that mg_solve_constraints_continue
+// refuses it (its arrays were changed outside the solver).
+void cancel_continue(mg_ctx *c);
+
 } // namespace grtmg

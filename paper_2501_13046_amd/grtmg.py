@@ -77,6 +77,7 @@ def lib() -> C.CDLL:
         L.mg_setup.argtypes = [pp, vp, C.c_size_t, vp, vp, vp, vp, vp, C.POINTER(vp)]
         L.mg_vcycle.argtypes = [vp, i32, vp, vp]
         L.mg_solve_constraints.argtypes = [vp, vp, vp, C.c_double, i32, C.POINTER(MgReport)]
+        L.mg_solve_constraints_continue.argtypes = [vp, vp, vp, C.c_double, i32, C.POINTER(MgReport)]
         L.mg_residual_norm.argtypes = [vp, vp, vp, dp]
         L.mg_residual_fields.argtypes = [vp, vp, vp, vp, vp, vp]
         L.mg_destroy.argtypes = [vp]
@@ -102,7 +103,7 @@ def lib() -> C.CDLL:
         L.mg_fmg_start.argtypes = [vp, vp, vp, vp, C.c_double, i32, vp, vp, C.POINTER(MgReport)]
         L.mg_probe.argtypes = [vp, i32, i32]
         L.mg_probe_result.argtypes = [vp, C.POINTER(i32), C.POINTER(C.c_double)]
-        for f in ("mg_workspace_size", "mg_setup", "mg_vcycle", "mg_solve_constraints",
+        for f in ("mg_workspace_size", "mg_setup", "mg_vcycle", "mg_solve_constraints", "mg_solve_constraints_continue",
                   "mg_residual_norm", "mg_residual_fields", "mg_scalar_field_sources",
                   "mg_shell_field_sources", "mg_interp_cubic", "mg_kernel_op", "mg_probe",
                   "mg_probe_result", "mg_batch_workspace_size", "mg_setup_batch", "mg_solve_batch",
@@ -213,13 +214,15 @@ class Solver:
         _check(lib().mg_vcycle(self.ctx, eq, _dptr(u, numel=self.cells), self._W(W)), "mg_vcycle")
 
     def solve(self, u: torch.Tensor, W: Optional[torch.Tensor] = None, tol: float = 1e-10,
-              max_outer: int = 100, raise_on_failure: bool = True) -> dict:
+              max_outer: int = 100, raise_on_failure: bool = True, resume: bool = False) -> dict:
+        """resume: continue from the state the last solve (or a kept warm start) left
+        in these same arrays (mg_solve_constraints_continue)."""
         hist = np.zeros((max_outer + 2, 4))
         rep = MgReport()
         rep.history = hist.ctypes.data_as(C.POINTER(C.c_double))
         rep.history_cap = max_outer + 2
-        st = lib().mg_solve_constraints(self.ctx, _dptr(u, numel=self.cells), self._W(W), tol,
-                                        max_outer, C.byref(rep))
+        fn = lib().mg_solve_constraints_continue if resume else lib().mg_solve_constraints
+        st = fn(self.ctx, _dptr(u, numel=self.cells), self._W(W), tol, max_outer, C.byref(rep))
         out = dict(status=st, outer_iters=rep.outer_iters, vcycles_psi=rep.vcycles_psi,
                    vcycles_W=rep.vcycles_W, h_rms=rep.h_rms, m_rms=rep.m_rms, h_max=rep.h_max,
                    m_max=rep.m_max, seconds=rep.seconds, history=hist[: rep.history_len].copy())

@@ -287,6 +287,8 @@ def test_warm_start_falls_back_on_a_bad_prediction():
     assert not used
     assert not u.any() and not W.any()
     # the zero start's norms (evaluated beside the network) are those of the zero state
+    with pytest.raises(g.MGError):  # the zeroed state is not the check iteration's
+        s.solve(u, W, resume=True)
     zn = s.residual_norm(u, W)
     assert norms[2] == zn[0] and norms[3] == zn[1]
     rep = s.solve(u, W, tol=1e-10, max_outer=60)

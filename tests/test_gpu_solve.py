@@ -131,6 +131,54 @@ def test_fp32_solves_are_deterministic():
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
 
 
+@pytest.mark.parametrize("precision", [g.PREC_FP64, g.PREC_FP32_IR])
+def test_continued_solve_equals_one_solve(precision):
+    """A solve stopped after 3 outer iterations and continued from the state it
+    left (no re-evaluation) ends bitwise where the uninterrupted solve ends,
+    after the same total number of iterations."""
+    w = synth.coupled(32, seed=5, precision=precision)
+    rho5, rho1, S, K, po = oracle_problem(w)
+    s = solver_for(w, K, rho5, rho1, S, precision)
+    z = lambda: (torch.zeros((32,) * 3, dtype=torch.float64, device=dev()),
+                 torch.zeros((3, 32, 32, 32), dtype=torch.float64, device=dev()))
+    u1, W1 = z()
+    r1 = s.solve(u1, W1, tol=1e-10)
+    u2, W2 = z()
+    ra = s.solve(u2, W2, tol=1e-10, max_outer=3, raise_on_failure=False)
+    assert ra["status"] == g.MG_ERR_NOT_CONVERGED and ra["outer_iters"] == 3
+    rb = s.solve(u2, W2, tol=1e-10, resume=True)
+    print(f"prec {precision}: one solve {r1['outer_iters']}, continued 3 + {rb['outer_iters']}")
+    assert ra["outer_iters"] + rb["outer_iters"] == r1["outer_iters"]
+    assert rb["history"][0].tolist() == ra["history"][-1].tolist()
+    assert torch.equal(u1, u2) and torch.equal(W1, W2)
+    assert rb["h_rms"] == r1["h_rms"] and rb["m_rms"] == r1["m_rms"]
+    # a converged state continues with no iteration
+    rc = s.solve(u2, W2, tol=1e-10, resume=True)
+    assert rc["outer_iters"] == 0 and torch.equal(u1, u2)
+
+
+def test_continue_refused_without_a_current_state():
+    w = synth.coupled(32, seed=5, precision=g.PREC_FP32_IR)
+    rho5, rho1, S, K, po = oracle_problem(w)
+    s = solver_for(w, K, rho5, rho1, S)
+    u = torch.zeros((32,) * 3, dtype=torch.float64, device=dev())
+    W = torch.zeros((3, 32, 32, 32), dtype=torch.float64, device=dev())
+    with pytest.raises(g.MGError) as e:  # nothing solved yet
+        s.solve(u, W, resume=True)
+    assert e.value.status == g.MG_ERR_INVALID
+    s.solve(u, W, tol=1e-10, max_outer=2, raise_on_failure=False)
+    u2, W2 = u.clone(), W.clone()
+    with pytest.raises(g.MGError):  # other arrays
+        s.solve(u2, W2, resume=True)
+    s.residual_norm(u, W)  # any other call on the context ends the continuation
+    with pytest.raises(g.MGError):
+        s.solve(u, W, resume=True)
+    s.solve(u, W, tol=1e-10, max_outer=2, raise_on_failure=False)
+    s.vcycle(g.EQ_BOTH, u, W)
+    with pytest.raises(g.MGError):
+        s.solve(u, W, resume=True)
+
+
 def test_failure_statuses():
     w = synth.hamiltonian_32(seed=0)
     rho5, rho1, S, K, po = oracle_problem(w)
