@@ -940,10 +940,10 @@ mg_status capture_body(mg_ctx *c, double *u, double *W, bool want_M)
     return MG_OK;
 }
 
-template <typename T>
 // resume: (u, W) is the state the last solve on c left (c->cont_valid), whose
 // evaluation is current in the workspace: it is not evaluated again, and the
 // lookahead can start from the first iteration.
+template <typename T>
 mg_status solve(mg_ctx *c, double *u, double *W, double tol, int max_outer, mg_report *rep, bool resume = false)
 {
     auto t0 = std::chrono::steady_clock::now();
