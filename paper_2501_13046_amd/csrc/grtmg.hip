@@ -942,9 +942,12 @@ mg_status capture_body(mg_ctx *c, double *u, double *W, bool want_M)
 
 // resume: (u, W) is the state the last solve on c left (c->cont_valid), whose
 // evaluation is current in the workspace: it is not evaluated again, and the
-// lookahead can start from the first iteration.
+// lookahead can start from the first iteration.  first_ahead: the first
+// iteration is enqueued before the starting state's norms are read (for callers
+// whose tolerance that state cannot meet).
 template <typename T>
-mg_status solve(mg_ctx *c, double *u, double *W, double tol, int max_outer, mg_report *rep, bool resume = false)
+mg_status solve(mg_ctx *c, double *u, double *W, double tol, int max_outer, mg_report *rep, bool resume = false,
+                bool first_ahead = false)
 {
     auto t0 = std::chrono::steady_clock::now();
     c->vc_psi = c->vc_W = 0;
@@ -993,8 +996,8 @@ mg_status solve(mg_ctx *c, double *u, double *W, double tol, int max_outer, mg_r
         }
     };
     for (;; it++) {
-        if (graph && launched == it && it < max_outer && w1 > 0.0 && w2 > 0.0 && w1 < w2 &&
-            w1 * (w1 / w2) > kAheadMargin * tol) {
+        if (graph && launched == it && it < max_outer &&
+            ((w1 > 0.0 && w2 > 0.0 && w1 < w2 && w1 * (w1 / w2) > kAheadMargin * tol) || (it == 0 && first_ahead))) {
             mg_status ls = launch_next();
             if (ls != MG_OK) return ls;
         }
@@ -2113,6 +2116,18 @@ mg_status zero_norms_begin(mg_ctx *c, double *d_u, double *d_W)
 void cancel_continue(mg_ctx *c)
 {
     if (c) c->cont_valid = false;
+}
+
+mg_status check_iteration(mg_ctx *c, double *d_u, double *d_W, mg_report *rep)
+{
+    if (!c || !d_u || (c->momentum && !d_W)) return MG_ERR_INVALID;
+    c->cont_valid = false;
+    enter(c);
+    constexpr double kNever = 1e-300;
+    mg_status st = c->f32 ? solve<float>(c, d_u, d_W, kNever, 1, rep, false, true)
+                          : solve<double>(c, d_u, d_W, kNever, 1, rep, false, true);
+    leave(c);
+    return st;
 }
 
 mg_status zero_norms_end(mg_ctx *c, double out[4])

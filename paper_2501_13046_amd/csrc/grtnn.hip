@@ -769,7 +769,7 @@ mg_status nn_warm_start(nn_ctx *c, mg_ctx *solver, const double *d_rho5, const d
     // and reports the norms after it; no tolerance can be met (tol 1e-300).
     mg_report rep;
     std::memset(&rep, 0, sizeof(rep));
-    st = mg_solve_constraints(solver, d_u, d_W, 1e-300, 1, &rep);
+    st = grtmg::check_iteration(solver, d_u, d_W, &rep);
     if (st != MG_OK && st != MG_ERR_NOT_CONVERGED && st != MG_ERR_DIVERGED) return st;
     pred[0] = rep.h_rms;
     pred[1] = rep.m_rms;

@@ -21,4 +21,9 @@ mg_status zero_norms_end(mg_ctx *c, double out[4]);
 // refuses it (its arrays were changed outside the solver).
 void cancel_continue(mg_ctx *c);
 
+// One outer iteration from (d_u, d_W) as mg_solve_constraints(tol 1e-300,
+// max_outer 1) does it, with the iteration enqueued before the starting state's
+// norms are read (no tolerance can stop it there); rep as that call fills it.
+mg_status check_iteration(mg_ctx *c, double *d_u, double *d_W, mg_report *rep);
+
 } // namespace grtmg
