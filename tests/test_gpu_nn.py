@@ -46,10 +46,12 @@ def silu_bf(x):
 
 
 # n a multiple of 16 without SiLU on load runs the brick kernel (slices of 8, 16, 32
-# channels); the other cases run the general kernel
+# channels; 7 K steps of weights in flight on grids under 1024 blocks, 2 from 64^3 on);
+# the other cases run the general kernel
 @pytest.mark.parametrize("n,cin,cout,act", [(6, 8, 4, False), (8, 16, 16, True), (5, 48, 48, False),
                                             (16, 32, 48, True), (4, 112, 48, False), (32, 48, 16, False),
-                                            (16, 64, 64, False), (32, 8, 16, False), (16, 112, 80, False)])
+                                            (16, 64, 64, False), (32, 8, 16, False), (16, 112, 80, False),
+                                            (64, 48, 16, False), (64, 8, 16, False)])
 def test_conv_forward(n, cin, cout, act):
     rng = np.random.default_rng(n * 1000 + cin + cout)
     x = bf(rng.standard_normal((cin, n, n, n)))
@@ -67,7 +69,7 @@ def test_conv_forward(n, cin, cout, act):
 
 
 @pytest.mark.parametrize("n,cin,cout", [(6, 16, 4), (8, 48, 16), (5, 80, 32), (16, 16, 16), (32, 48, 4),
-                                        (16, 112, 32), (32, 16, 64)])
+                                        (16, 112, 32), (32, 16, 64), (64, 16, 16)])
 def test_conv_backward_data(n, cin, cout):
     rng = np.random.default_rng(7 * n + cin + cout)
     cout8 = (cout + 7) // 8 * 8
@@ -125,8 +127,10 @@ def rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
+# 64^3: upsampling into 64^3 takes one thread per coarse cell, the 64^3 convolutions 2 K steps
+# of weights in flight
 @pytest.mark.parametrize("n,levels,ch", [(16, 3, (16, 32, 48)), (8, 1, (16,)), (16, 2, (32, 16)),
-                                         (32, 4, (16, 32, 48, 64))])
+                                         (32, 4, (16, 32, 48, 64)), (64, 4, (16, 32, 48, 64))])
 def test_network_forward(n, levels, ch):
     cfg, gc = small_cfg(n, levels, ch)
     p, x, _ = net_inputs(cfg, 5)
