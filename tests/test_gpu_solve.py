@@ -157,6 +157,31 @@ def test_continued_solve_equals_one_solve(precision):
     assert rc["outer_iters"] == 0 and torch.equal(u1, u2)
 
 
+def test_timing_probe_counts_each_launch_once():
+    """The probe behind the roofline figure: with it on, a solve launches eagerly
+    and gives the same state bitwise; it times exactly the finest-level W passes
+    (2 nu_pre + 2 nu_post - 1 per outer iteration: the first comes with the
+    residual) or residual evaluations (two per outer iteration and the first)."""
+    w = synth.coupled(32, seed=5, precision=g.PREC_FP32_IR)
+    rho5, rho1, S, K, po = oracle_problem(w)
+    s = solver_for(w, K, rho5, rho1, S)
+    z = lambda: (torch.zeros((32,) * 3, dtype=torch.float64, device=dev()),
+                 torch.zeros((3, 32, 32, 32), dtype=torch.float64, device=dev()))
+    u, W = z()
+    ref = s.solve(u, W, tol=1e-10)
+    for kid, per_iter, extra in ((g.PROBE_PASS_W, 2 * w.nu_pre + 2 * w.nu_post - 1, 0), (g.PROBE_RESIDUAL, 2, 1)):
+        s.probe(kid, 0)
+        u2, W2 = z()
+        r = s.solve(u2, W2, tol=1e-10)
+        cnt, ms = s.probe_result()
+        s.probe(g.PROBE_NONE, 0)
+        print(f"probe {kid}: {cnt} launches, {ms / max(cnt, 1) * 1e3:.2f} us each")
+        assert r["outer_iters"] == ref["outer_iters"]
+        assert torch.equal(u, u2) and torch.equal(W, W2)
+        assert cnt == per_iter * r["outer_iters"] + extra
+        assert 0.0 < ms / cnt < 1.0
+
+
 def test_continue_refused_without_a_current_state():
     w = synth.coupled(32, seed=5, precision=g.PREC_FP32_IR)
     rho5, rho1, S, K, po = oracle_problem(w)
