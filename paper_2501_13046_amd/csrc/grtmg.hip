@@ -961,8 +961,10 @@ mg_status solve(mg_ctx *c, double *u, double *W, double tol, int max_outer, mg_r
     // Lookahead: iteration it + 1 is enqueued before iteration it's norms are
     // read (the host round trip then overlaps the GPU work) when the
     // contraction of the last two iterations puts iteration it at least
-    // kAheadMargin times above tol, so it cannot be the last one.
-    constexpr double kAheadMargin = 10.0;
+    // kAheadMargin times above tol, so it cannot be the last one.  With one read
+    // iteration only, the state must lie kFirstAhead times above tol (no outer
+    // iteration contracts by that much).
+    constexpr double kAheadMargin = 10.0, kFirstAhead = 1e4;
     double w1 = -1.0, w2 = -1.0; // worst norm after the last and the one-before-last read iteration
     double last_worst = -1.0;      // worst norm of the last read iteration
     double resumed[4] = {0, 0, 0, 0};
@@ -997,7 +999,8 @@ mg_status solve(mg_ctx *c, double *u, double *W, double tol, int max_outer, mg_r
     };
     for (;; it++) {
         if (graph && launched == it && it < max_outer &&
-            ((w1 > 0.0 && w2 > 0.0 && w1 < w2 && w1 * (w1 / w2) > kAheadMargin * tol) || (it == 0 && first_ahead))) {
+            ((w1 > 0.0 && w2 > 0.0 && w1 < w2 && w1 * (w1 / w2) > kAheadMargin * tol) ||
+             (w1 > 0.0 && w2 < 0.0 && w1 > kFirstAhead * tol) || (it == 0 && first_ahead))) {
             mg_status ls = launch_next();
             if (ls != MG_OK) return ls;
         }
