@@ -106,8 +106,7 @@ def main():
     # ---- setup (off the clock): sources on the GPU, K from the mean density
     p = g.params(n, w.levels, w.bc, g.PREC_FP32_IR, w.length, w.origin, 0.0, w.nu_pre,
                  w.nu_post, True)
-    rho5, rho1, S, mean_rho = g.scalar_field_sources(p, w.phi_modes, w.pi_modes, w.scalar_mass, dev)
-    K = g.K_from_mean_density(mean_rho)
+    rho5, rho1, S, K = g.scalar_field_sources(p, w.phi_modes, w.pi_modes, w.scalar_mass, dev)
     p.K = K
     mixed = g.Solver(p, rho5, rho1, S)
     u = torch.zeros((n,) * 3, dtype=torch.float64, device=dev)

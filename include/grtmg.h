@@ -120,7 +120,10 @@ typedef struct mg_ctx mg_ctx;
 mg_status mg_workspace_size(const mg_params *p, size_t *bytes);
 
 /*
- * Create a context.  d_workspace: caller-owned device buffer of at least
+ * Create a context for the discrete constraint system above (Summary: eq. Ham
+ * and eq. Mom with the matter projections rho and S_i as sources; the free data
+ * are the flat conformal metric, K and the matter fields).
+ * d_workspace: caller-owned device buffer of at least
  * mg_workspace_size bytes, 256-byte aligned.  d_rho5, d_rho1: n^3 FP64 each;
  * d_S: 3 n^3 FP64 (may be NULL when solve_momentum is 0 and no momentum
  * norm is wanted); d_f: n^3 FP64 forcing added to H_h, or NULL.  The coarse
@@ -131,7 +134,9 @@ mg_status mg_setup(const mg_params *p, void *d_workspace, size_t bytes, void *st
                    const double *d_f, mg_ctx **out);
 
 /*
- * One outer multigrid step at the current state (d_u: n^3, d_W: 3 n^3, FP64,
+ * One outer multigrid step (Key features, "Fast": one multigrid V-cycle over
+ * the hierarchy of discretisations per equation, eq. Mom for W and the Newton
+ * linearisation of eq. Ham for psi) at the current state (d_u: n^3, d_W: 3 n^3, FP64,
  * updated in place).  eq = MG_EQ_W: r = -M_h(u, W), one W V-cycle, W += dW -
  * mean(dW).  eq = MG_EQ_PSI: r = -H_h(u, W), c = dH_h/dpsi, one psi V-cycle,
  * u += d.  eq = MG_EQ_BOTH: the W step then the psi step (one Newton outer
@@ -140,7 +145,9 @@ mg_status mg_setup(const mg_params *p, void *d_workspace, size_t bytes, void *st
 mg_status mg_vcycle(mg_ctx *ctx, int32_t eq, double *d_u, double *d_W);
 
 /*
- * Newton-multigrid solve from the initial guess in (d_u, d_W) until
+ * Newton-multigrid solve of eqs. Ham and Mom (Summary; Key features, "Fast",
+ * with the constraint norms of every iteration recorded as in Key features,
+ * "Diagnostics") from the initial guess in (d_u, d_W) until
  * rms(H_h) <= tol and (if solve_momentum) rms(|M_h|) <= tol, or max_outer
  * outer updates.  Returns MG_OK, MG_ERR_NOT_CONVERGED or MG_ERR_DIVERGED;
  * rep (may be NULL) is filled in every case, and (u, W) hold the last finite
@@ -164,8 +171,10 @@ mg_status mg_solve_constraints(mg_ctx *ctx, double *d_u, double *d_W, double tol
 mg_status mg_solve_constraints_continue(mg_ctx *ctx, double *d_u, double *d_W, double tol,
                                         int32_t max_outer, mg_report *rep);
 
-/* Constraint norms at (d_u, d_W): out[4] (host) = rms H_h, rms |M_h|, max |H_h|,
- * max |M_h| (the momentum entries are 0 when d_S was NULL).  Synchronises. */
+/* Constraint norms (Key features, "Diagnostics": the Hamiltonian and momentum
+ * constraint errors of eqs. Ham and Mom reduced to norms over the grid) at
+ * (d_u, d_W): out[4] (host) = rms H_h, rms |M_h|, max |H_h|, max |M_h| (the
+ * momentum entries are 0 when d_S was NULL).  Synchronises. */
 mg_status mg_residual_norm(mg_ctx *ctx, const double *d_u, const double *d_W, double out[4]);
 
 /* The residual fields themselves: d_H (n^3), d_M (3 n^3), d_c (n^3, dH_h/dpsi),
@@ -178,21 +187,27 @@ const char *mg_status_str(mg_status s);
 
 /*
  * Matter sources of a scalar field given as Fourier modes (Summary: rho and
- * S_i as projections of the stress-energy; Key features: analytic matter data).
+ * S_i as the projections of the stress-energy onto the slice normal; Key
+ * features: scalar-field matter with analytic initial data).
  * h_phi_modes, h_pi_modes: host tables of 5 doubles per mode (kx, ky, kz,
- * amplitude, phase); field = sum amp cos(2 pi k.x / L + phase); up to 64 modes
- * each.  V(phi) = mass^2 phi^2 / 2.  Writes d_rho5 = Pi^2/2 + V, d_rho1 =
- * |d phi|^2/2, d_S = -Pi d phi (3 n^3), all FP64.  If h_mean_rho is not NULL
- * the grid mean of rho5 + rho1 is returned there (synchronises); this needs a
- * caller-owned device scratch d_scratch of at least MG_SOURCES_SCRATCH_BYTES
- * (otherwise d_scratch may be NULL).  Uses p->n, p->length and p->origin only.
+ * amplitude, phase); field = sum amp cos(2 pi k.x / L + phase); up to 32 modes
+ * each, every entry finite.  V(phi) = mass^2 phi^2 / 2.  Writes d_rho5 =
+ * Pi^2/2 + V, d_rho1 = |d phi|^2/2, d_S = -Pi d phi (3 n^3), all FP64.
+ * If h_mean_rho is not NULL the grid mean <rho> of rho5 + rho1 is returned
+ * there; if h_K is not NULL, the constant trace K = sqrt(24 pi <rho>), for which
+ * the uniform part of the Hamiltonian constraint (eq. Ham with psi = 1,
+ * Abar = 0: (2/3) K^2 = 16 pi <rho>) vanishes.  Either output synchronises the
+ * stream and needs a caller-owned device scratch d_scratch, 256-byte aligned,
+ * of at least MG_SOURCES_SCRATCH_BYTES (otherwise d_scratch may be NULL).
+ * Uses p->n (1..4096), p->length and p->origin only.  MG_ERR_INVALID before
+ * any HIP call on bad arguments, MG_ERR_WORKSPACE on a missing or small scratch.
  */
 #define MG_SOURCES_SCRATCH_BYTES 32768
 mg_status mg_scalar_field_sources(const mg_params *p, int32_t n_phi, const double *h_phi_modes,
                                   int32_t n_pi, const double *h_pi_modes, double mass,
                                   double *d_rho5, double *d_rho1, double *d_S,
                                   void *d_scratch, size_t scratch_bytes, double *h_mean_rho,
-                                  void *stream);
+                                  double *h_K, void *stream);
 
 /*
  * Scalar shell around the puncture: phi = amp exp(-(r - r0)^2 / width2) Y_11

@@ -138,7 +138,9 @@ mg_status nn_moments(nn_ctx *ctx, const double *d_x, const double *d_y, int64_t 
  * keeps the result (*h_used = 1) only if its RMS constraint residuals are
  * finite and their maximum is below that of the zero state u = 0, W = 0;
  * otherwise d_u and d_W are set to zero (*h_used = 0).  The solver context
- * must belong to the same grid (n^3, periodic) and use the same stream.
+ * must have the network's grid (n cells per axis), periodic boundaries and
+ * the coupled momentum solve, and must have been set up on the network's
+ * stream; otherwise MG_ERR_INVALID is returned before any work is queued.
  * h_norms (may be NULL): RMS H, M after the iteration; RMS H, M of the zero state. */
 mg_status nn_warm_start(nn_ctx *ctx, mg_ctx *solver, const double *d_rho5, const double *d_rho1,
                         const double *d_S, const nn_norm *norm, double *d_u, double *d_W,

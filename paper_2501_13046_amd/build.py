@@ -1,4 +1,6 @@
-"""Build the HIP library libgrtmg.so in-tree for gfx950 (hipcc, no JIT cache)."""
+"""Build the HIP library libgrtmg.so in-tree for gfx950 (hipcc, no JIT cache).
+
+Each translation unit is compiled to an object in parallel, then linked."""
 from __future__ import annotations
 
 import os
@@ -13,7 +15,7 @@ HEADERS = [os.path.join(PKG, "csrc", f) for f in ("mg_device.hpp", "mg_kernels.h
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
+    "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
@@ -21,12 +23,25 @@ FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
-    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", os.path.join(PKG, "csrc"),
-           *SOURCES, "-o", LIB + ".tmp"]
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(PKG, "csrc")]
+    objs, procs = [], []
+    for src in SOURCES:
+        obj = os.path.join(PKG, "csrc", os.path.basename(src) + ".o")
+        cmd = [HIPCC, *FLAGS, *inc, "-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((subprocess.Popen(cmd), cmd))
+        objs.append(obj)
+    failed = [cmd for p, cmd in procs if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
+    link = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", LIB + ".tmp"]
     if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
+        print(" ".join(link), flush=True)
+    subprocess.check_call(link)
     os.replace(LIB + ".tmp", LIB)
+    for o in objs:
+        os.remove(o)
     return LIB
 
 

@@ -1659,6 +1659,67 @@ mg_status batch_solve(mg_batch *b, double *const *u, double *const *W, double to
     return worst;
 }
 
+// ---------------------------------------------------------------------------------------
+// Scalar-field sources (rho5, rho1, S_a of a field given by Fourier modes) and, on
+// request, the grid mean of rho5 + rho1 and the constant K with K^2 = 24 pi <rho>, the
+// value that makes the uniform part of the Hamiltonian constraint vanish at psi = 1.
+// ---------------------------------------------------------------------------------------
+
+mg_status check_sources_args(const mg_params *p, int n_phi, const double *h_phi_modes, int n_pi,
+                             const double *h_pi_modes, double mass, const double *d_rho5,
+                             const double *d_rho1, const double *d_S)
+{
+    if (!p || p->n < 1 || p->n > 4096 || !(p->length > 0.0)) return MG_ERR_INVALID;
+    if (n_phi < 0 || n_phi > kMaxModes || n_pi < 0 || n_pi > kMaxModes) return MG_ERR_INVALID;
+    if ((n_phi && !h_phi_modes) || (n_pi && !h_pi_modes)) return MG_ERR_INVALID;
+    if (!d_rho5 || !d_rho1 || !d_S || !std::isfinite(mass)) return MG_ERR_INVALID;
+    for (int q = 0; q < 5 * n_phi; q++)
+        if (!std::isfinite(h_phi_modes[q])) return MG_ERR_INVALID;
+    for (int q = 0; q < 5 * n_pi; q++)
+        if (!std::isfinite(h_pi_modes[q])) return MG_ERR_INVALID;
+    return MG_OK;
+}
+
+// Partials of the mean reduction: one per block of the source kernel, then the
+// reduced mean at index kSrcBlocks.
+constexpr size_t kSourcesScratchNeed = (size_t)(kSrcBlocks + 1) * sizeof(double);
+static_assert(kSourcesScratchNeed <= MG_SOURCES_SCRATCH_BYTES, "source scratch");
+
+// Arguments already checked by check_sources_args; scratch_d may be NULL when neither
+// the mean nor K is requested.
+mg_status scalar_sources(const mg_params *p, int n_phi, const double *h_phi_modes, int n_pi,
+                         const double *h_pi_modes, double mass, double *d_rho5, double *d_rho1, double *d_S,
+                         double *scratch_d, double *h_mean_rho, double *h_K, hipStream_t s)
+{
+    ModeTable t;
+    std::memset(&t, 0, sizeof(t));
+    t.nphi = n_phi;
+    t.npi = n_pi;
+    for (int q = 0; q < n_phi; q++)
+        for (int e = 0; e < 5; e++) t.phi[q][e] = h_phi_modes[5 * q + e];
+    for (int q = 0; q < n_pi; q++)
+        for (int e = 0; e < 5; e++) t.pi[q][e] = h_pi_modes[5 * q + e];
+    const Geo g = make_geo(p->n, p->bc, p->length, p->origin, p->puncture_pos);
+    const int64_t m = (int64_t)p->n * p->n * p->n;
+    const unsigned nb = std::min<unsigned>(nblk(m), kSrcBlocks);
+    const bool want_mean = h_mean_rho || h_K;
+    double *part = want_mean ? scratch_d : nullptr;
+    hipLaunchKernelGGL(k_sources_modes, dim3(nb), dim3(kBlock), 0, s, g, p->length, t, mass, d_rho5,
+                       d_rho1, d_S, part);
+    if (want_mean) {
+        double *res = scratch_d + kSrcBlocks;
+        hipLaunchKernelGGL(k_reduce_final<1>, dim3(1), dim3(kBlock), 0, s, (const double *)part,
+                           (int64_t)nb, 0u, 1.0 / (double)m, res);
+        double mean = 0.0;
+        if (hipMemcpyAsync(&mean, res, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
+            return MG_ERR_HIP;
+        if (hipStreamSynchronize(s) != hipSuccess) return MG_ERR_HIP;
+        if (h_mean_rho) *h_mean_rho = mean;
+        if (h_K) *h_K = std::sqrt(24.0 * M_PI * std::max(mean, 0.0));
+    }
+    return hip_status();
+}
+
 } // namespace
 
 extern "C" {
@@ -1946,39 +2007,16 @@ const char *mg_status_str(mg_status s)
 mg_status mg_scalar_field_sources(const mg_params *p, int32_t n_phi, const double *h_phi_modes,
                                   int32_t n_pi, const double *h_pi_modes, double mass, double *d_rho5,
                                   double *d_rho1, double *d_S, void *d_scratch, size_t scratch_bytes,
-                                  double *h_mean_rho, void *stream)
+                                  double *h_mean_rho, double *h_K, void *stream)
 {
-    if (!p || p->n < 1 || p->n > 4096 || !(p->length > 0.0)) return MG_ERR_INVALID;
-    if (n_phi < 0 || n_phi > kMaxModes || n_pi < 0 || n_pi > kMaxModes) return MG_ERR_INVALID;
-    if ((n_phi && !h_phi_modes) || (n_pi && !h_pi_modes)) return MG_ERR_INVALID;
-    if (!d_rho5 || !d_rho1 || !d_S || !std::isfinite(mass)) return MG_ERR_INVALID;
-    if (h_mean_rho && (!d_scratch || scratch_bytes < MG_SOURCES_SCRATCH_BYTES ||
-                       ((uintptr_t)d_scratch % 256) != 0))
+    const mg_status st = check_sources_args(p, n_phi, h_phi_modes, n_pi, h_pi_modes, mass, d_rho5, d_rho1, d_S);
+    if (st != MG_OK) return st;
+    const bool want_mean = h_mean_rho || h_K;
+    if (want_mean && (!d_scratch || scratch_bytes < MG_SOURCES_SCRATCH_BYTES ||
+                      ((uintptr_t)d_scratch % 256) != 0))
         return MG_ERR_WORKSPACE;
-    ModeTable t;
-    std::memset(&t, 0, sizeof(t));
-    t.nphi = n_phi;
-    t.npi = n_pi;
-    for (int q = 0; q < n_phi; q++)
-        for (int e = 0; e < 5; e++) t.phi[q][e] = h_phi_modes[5 * q + e];
-    for (int q = 0; q < n_pi; q++)
-        for (int e = 0; e < 5; e++) t.pi[q][e] = h_pi_modes[5 * q + e];
-    const Geo g = make_geo(p->n, p->bc, p->length, p->origin, p->puncture_pos);
-    const int64_t m = (int64_t)p->n * p->n * p->n;
-    const unsigned nb = std::min<unsigned>(nblk(m), kSrcBlocks);
-    hipStream_t s = (hipStream_t)stream;
-    double *part = h_mean_rho ? (double *)d_scratch : nullptr;
-    hipLaunchKernelGGL(k_sources_modes, dim3(nb), dim3(kBlock), 0, s, g, p->length, t, mass, d_rho5,
-                       d_rho1, d_S, part);
-    if (h_mean_rho) {
-        double *res = (double *)d_scratch + kSrcBlocks;
-        hipLaunchKernelGGL(k_reduce_final<1>, dim3(1), dim3(kBlock), 0, s, (const double *)part,
-                           (int64_t)nb, 0u, 1.0 / (double)m, res);
-        if (hipMemcpyAsync(h_mean_rho, res, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
-            return MG_ERR_HIP;
-        if (hipStreamSynchronize(s) != hipSuccess) return MG_ERR_HIP;
-    }
-    return hip_status();
+    return scalar_sources(p, n_phi, h_phi_modes, n_pi, h_pi_modes, mass, d_rho5, d_rho1, d_S,
+                          (double *)d_scratch, h_mean_rho, h_K, (hipStream_t)stream);
 }
 
 mg_status mg_shell_field_sources(const mg_params *p, double amp, double r0, double width2, double mass,
@@ -2092,6 +2130,16 @@ mg_status mg_kernel_op(mg_ctx *c, int32_t op, int32_t level, int32_t arg, const 
 } // extern "C"
 
 namespace grtmg {
+
+SolverShape solver_shape(const mg_ctx *c)
+{
+    SolverShape sh;
+    sh.n = c->p.n;
+    sh.bc = c->p.bc;
+    sh.momentum = c->momentum;
+    sh.user_stream = (void *)c->user_s;
+    return sh;
+}
 
 mg_status zero_norms_begin(mg_ctx *c, double *d_u, double *d_W)
 {

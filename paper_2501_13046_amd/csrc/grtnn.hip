@@ -748,6 +748,13 @@ mg_status nn_warm_start(nn_ctx *c, mg_ctx *solver, const double *d_rho5, const d
     if (!c || !solver || !d_rho5 || !d_rho1 || !d_S || !d_u || !d_W || !h_used || !norm_ok(norm) ||
         c->cfg.c_in != 4 || c->cfg.c_out != 4)
         return MG_ERR_INVALID;
+    // the prediction is written into the solver's arrays and checked by its own
+    // iteration: both must describe the same periodic grid, the solver must
+    // update W, and both must order their work on the same stream (the check
+    // iteration then follows the unpacked prediction)
+    const grtmg::SolverShape sh = grtmg::solver_shape(solver);
+    if (sh.n != c->cfg.n || sh.bc != MG_BC_PERIODIC || !sh.momentum || sh.user_stream != (void *)c->s)
+        return MG_ERR_INVALID;
     const int64_t V = c->V[0];
     double zero[4], pred[4];
     // residual of the zero start (u = 0, W = 0) on the solver's stream, while the

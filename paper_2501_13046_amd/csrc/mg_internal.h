@@ -21,6 +21,16 @@ mg_status zero_norms_end(mg_ctx *c, double out[4]);
 // refuses it (its arrays were changed outside the solver).
 void cancel_continue(mg_ctx *c);
 
+// Shape of a solver context for callers that hand it arrays sized elsewhere:
+// cells per axis of the finest level, boundary rule, whether it solves the
+// momentum equation, and the caller stream given at setup.
+struct SolverShape {
+    int n, bc;
+    bool momentum;
+    void *user_stream;
+};
+SolverShape solver_shape(const mg_ctx *c);
+
 // One outer iteration from (d_u, d_W) as mg_solve_constraints(tol 1e-300,
 // max_outer 1) does it, with the iteration enqueued before the starting state's
 // norms are read (no tolerance can stop it there); rep as that call fills it.

@@ -1049,6 +1049,22 @@ __global__ void __launch_bounds__(kBlock) k_restrict(int nf, const T *__restrict
 // ---------------------------------------------------------------------------------------
 constexpr int kGjWaves = 16;
 
+// Maximum of an unsigned value over the 64 lanes of a wave, returned in a
+// scalar register: DPP exchanges inside each row of 16 lanes (quad swaps, then
+// the half-row and row mirrors), then the four row results read lane by lane.
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v)
+{
+    v = max(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false));  // quad_perm 1,0,3,2
+    v = max(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false));  // quad_perm 2,3,0,1
+    v = max(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, false)); // row_half_mirror
+    v = max(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, false)); // row_mirror
+    const unsigned r0 = (unsigned)__builtin_amdgcn_readlane((int)v, 0);
+    const unsigned r1 = (unsigned)__builtin_amdgcn_readlane((int)v, 16);
+    const unsigned r2 = (unsigned)__builtin_amdgcn_readlane((int)v, 32);
+    const unsigned r3 = (unsigned)__builtin_amdgcn_readlane((int)v, 48);
+    return max(max(r0, r1), max(r2, r3));
+}
+
 __device__ __forceinline__ double readlane_f64(double x, int l)
 {
     const unsigned long long b = (unsigned long long)__double_as_longlong(x);
@@ -1122,7 +1138,7 @@ __device__ __forceinline__ void coarse_psi_block_solve(const Geo &g, const T *c,
                     const unsigned bits = __float_as_uint((float)fabs(a));
                     key = (bits & ~63u) | (63u - (unsigned)lane);
                 }
-                const unsigned kmax = __builtin_amdgcn_readfirstlane(__reduce_max_sync(~0ull, key));
+                const unsigned kmax = wave_max_u32(key);
                 if ((kmax >> 6) == 0u) {
                     if (lane == 0) piv[buf] = -1; // no non-zero pivot left
                 } else {

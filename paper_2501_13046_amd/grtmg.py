@@ -85,7 +85,7 @@ def lib() -> C.CDLL:
         L.mg_status_str.argtypes = [st]
         L.mg_status_str.restype = C.c_char_p
         L.mg_scalar_field_sources.argtypes = [pp, i32, dp, i32, dp, C.c_double, vp, vp, vp, vp,
-                                              C.c_size_t, dp, vp]
+                                              C.c_size_t, dp, dp, vp]
         L.mg_shell_field_sources.argtypes = [pp, C.c_double, C.c_double, C.c_double, C.c_double,
                                              vp, vp, vp, vp]
         L.mg_interp_cubic.argtypes = [pp, vp, vp, vp]
@@ -321,7 +321,9 @@ class Batch:
 
 
 def scalar_field_sources(p: MgParams, phi_modes: np.ndarray, pi_modes: np.ndarray,
-                         mass: float = 1.0, device="cuda", want_mean=True):
+                         mass: float = 1.0, device="cuda", want_K=True):
+    """Sources (rho5, rho1, S) of the Fourier scalar field and, when want_K,
+    the library's constant K (K^2 = 24 pi <rho>); returns (rho5, rho1, S, K)."""
     n = p.n
     rho5 = torch.empty((n, n, n), dtype=torch.float64, device=device)
     rho1 = torch.empty_like(rho5)
@@ -329,16 +331,16 @@ def scalar_field_sources(p: MgParams, phi_modes: np.ndarray, pi_modes: np.ndarra
     phi = np.ascontiguousarray(phi_modes, dtype=np.float64).reshape(-1, 5)
     pim = np.ascontiguousarray(pi_modes, dtype=np.float64).reshape(-1, 5)
     dp = C.POINTER(C.c_double)
-    mean = C.c_double(0.0)
-    scratch = torch.empty(SOURCES_SCRATCH_BYTES, dtype=torch.uint8, device=device) if want_mean else None
+    K = C.c_double(0.0)
+    scratch = torch.empty(SOURCES_SCRATCH_BYTES, dtype=torch.uint8, device=device) if want_K else None
     _check(lib().mg_scalar_field_sources(
         C.byref(p), len(phi), phi.ctypes.data_as(dp) if len(phi) else None,
         len(pim), pim.ctypes.data_as(dp) if len(pim) else None, mass,
         _dptr(rho5), _dptr(rho1), _dptr(S),
-        C.c_void_p(scratch.data_ptr()) if want_mean else None,
-        SOURCES_SCRATCH_BYTES if want_mean else 0,
-        C.byref(mean) if want_mean else None, _stream(rho5.device)), "mg_scalar_field_sources")
-    return rho5, rho1, S, (mean.value if want_mean else None)
+        C.c_void_p(scratch.data_ptr()) if want_K else None,
+        SOURCES_SCRATCH_BYTES if want_K else 0, None,
+        C.byref(K) if want_K else None, _stream(rho5.device)), "mg_scalar_field_sources")
+    return rho5, rho1, S, (K.value if want_K else None)
 
 
 def shell_field_sources(p: MgParams, amplitude: float, r0: float, width2: float,
@@ -416,8 +418,3 @@ def fmg_coarse_tol(coarse: "Solver", fine: "Solver", uc: torch.Tensor, Wc: Optio
     fmg_start(coarse, fine, uc, Wc, uf, Wf, tol=1e-10)
     h = fine.residual_norm(uf, Wf)[0]
     return float(fraction * h)
-
-
-def K_from_mean_density(mean_rho: float) -> float:
-    """Constant K with K^2 = 24 pi <rho> at psi = 1 (the periodic workloads)."""
-    return float(np.sqrt(24.0 * np.pi * mean_rho))

@@ -198,6 +198,8 @@ class Net:
         return out[0], out[1]
 
     def warm_start(self, solver: "_mg.Solver", rho5, rho1, S, nm: NnNorm, u, W):
+        if solver.cells != self.cells:
+            raise MGError(_mg.MG_ERR_INVALID, "nn_warm_start: solver and network grids differ")
         used = C.c_int32(0)
         norms = (C.c_double * 4)()
         _check(lib().nn_warm_start(self.ctx, solver.ctx, _dptr(rho5, numel=self.cells),

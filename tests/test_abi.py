@@ -84,7 +84,7 @@ def test_entry_points_reject_null_context(g):
     p = g.params(8, 1)
     assert lib.mg_interp_cubic(C.byref(p), None, None, None) == g.MG_ERR_INVALID
     assert lib.mg_scalar_field_sources(C.byref(p), 40, None, 0, None, 1.0, None, None, None,
-                                       None, 0, None, None) == g.MG_ERR_INVALID
+                                       None, 0, None, None, None) == g.MG_ERR_INVALID
 
 
 def test_network_abi(g):

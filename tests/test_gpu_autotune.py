@@ -18,8 +18,7 @@ pytestmark = pytest.mark.gpu
 def setup(precision):
     w = synth.coupled(128, seed=2, precision=precision)
     p = gparams(w)
-    r5, r1, S, mean = g.scalar_field_sources(p, w.phi_modes, w.pi_modes, w.scalar_mass, dev())
-    p.K = g.K_from_mean_density(mean)
+    r5, r1, S, p.K = g.scalar_field_sources(p, w.phi_modes, w.pi_modes, w.scalar_mass, dev())
     return g.Solver(p, r5, r1, S)
 
 

@@ -17,8 +17,7 @@ def make_members(ws_list, precision):
     plist, r5s, r1s, Ss, Ks = [], [], [], [], []
     for w in ws_list:
         p = gparams(w, 0.0, precision)
-        r5, r1, S, mean = g.scalar_field_sources(p, w.phi_modes, w.pi_modes, w.scalar_mass, dev())
-        p.K = g.K_from_mean_density(mean)
+        r5, r1, S, p.K = g.scalar_field_sources(p, w.phi_modes, w.pi_modes, w.scalar_mass, dev())
         plist.append(p)
         r5s.append(r5)
         r1s.append(r1)

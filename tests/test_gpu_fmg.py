@@ -32,9 +32,8 @@ def test_fmg_start(case):
         wf = synth.puncture_shell(128, precision=g.PREC_FP32_IR, levels=6)
         wc = synth.puncture_shell(64, precision=g.PREC_FP32_IR, levels=5)
     pf, pc = gparams(wf), gparams(wc)
-    r5f, r1f, Sf, meanf = sources(wf, pf)
+    r5f, r1f, Sf, K = sources(wf, pf)
     r5c, r1c, Sc, _ = sources(wc, pc)
-    K = g.K_from_mean_density(meanf) if wf.shell is None else 0.0
     pf.K = pc.K = K
     mom = wf.solve_momentum
     fine = g.Solver(pf, r5f, r1f, Sf if mom else None)
@@ -75,9 +74,9 @@ def test_fmg_coarse_tolerance_rule():
     wf = synth.coupled(64, seed=4, precision=g.PREC_FP32_IR)
     wc = synth.coupled(32, seed=4, precision=g.PREC_FP32_IR)
     pf, pc = gparams(wf), gparams(wc)
-    r5f, r1f, Sf, meanf = sources(wf, pf)
+    r5f, r1f, Sf, K = sources(wf, pf)
     r5c, r1c, Sc, _ = sources(wc, pc)
-    pf.K = pc.K = g.K_from_mean_density(meanf)
+    pf.K = pc.K = K
     fine = g.Solver(pf, r5f, r1f, Sf)
     coarse = g.Solver(pc, r5c, r1c, Sc)
     z = lambda n: torch.zeros((n,) * 3, dtype=torch.float64, device=dev())

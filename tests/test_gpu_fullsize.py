@@ -30,8 +30,7 @@ def gpu_sources(w):
         rho5, rho1, S = g.shell_field_sources(p, w.shell["amplitude"], w.shell["r0"],
                                               w.shell["width2"], w.scalar_mass, dev())
         return rho5, rho1, S, 0.0
-    rho5, rho1, S, mean = g.scalar_field_sources(p, w.phi_modes, w.pi_modes, w.scalar_mass, dev())
-    return rho5, rho1, S, g.K_from_mean_density(mean)
+    return g.scalar_field_sources(p, w.phi_modes, w.pi_modes, w.scalar_mass, dev())
 
 
 def sampled_hamiltonian(w, K, u, W, rho5, rho1, cells):

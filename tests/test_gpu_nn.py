@@ -174,11 +174,15 @@ def test_network_gradients(n, levels, ch):
     assert abs(loss - rloss) <= 2e-2 * rloss
     assert rel(gg, rgrad) < 5e-2
     off = 0
+    errs = []
     for k, (ci, co) in enumerate(nn.layer_shapes(cfg)):
         w = slice(off, off + 27 * ci * co)
         bsl = slice(off + 27 * ci * co, off + 27 * ci * co + co)
         off += 27 * ci * co + co
-        ew, eb = rel(gg[w], rgrad[w]), rel(gg[bsl], rgrad[bsl])
+        errs.append((rel(gg[w], rgrad[w]), rel(gg[bsl], rgrad[bsl])))
+    print("per-layer gradient rel err (max weight, max bias):",
+          f"{max(e[0] for e in errs):.2e} {max(e[1] for e in errs):.2e}")
+    for k, (ew, eb) in enumerate(errs):
         assert ew < 1e-1 and eb < 1e-1, (k, ew, eb)
 
 
@@ -275,8 +279,7 @@ def test_warm_start_falls_back_on_a_bad_prediction():
     w = synth.coupled(32, seed=3, precision=g.PREC_FP32_IR, levels=4)
     from gpu_helpers import gparams
     p = gparams(w, 0.0)
-    r5, r1, S, mean = g.scalar_field_sources(p, w.phi_modes, w.pi_modes, w.scalar_mass, dev())
-    p.K = g.K_from_mean_density(mean)
+    r5, r1, S, p.K = g.scalar_field_sources(p, w.phi_modes, w.pi_modes, w.scalar_mass, dev())
     s = g.Solver(p, r5, r1, S)
     cfg, gc = small_cfg(32, 4, (16, 32, 48, 64))
     net = gn.Net(gc, training=False)

@@ -280,8 +280,7 @@ def test_vcycle_tail_matches_separate_launches(case):
             r5, r1, S = g.shell_field_sources(p, w.shell["amplitude"], w.shell["r0"], w.shell["width2"],
                                               w.scalar_mass, dev())
         else:
-            r5, r1, S, mean = g.scalar_field_sources(p, w.phi_modes, w.pi_modes, w.scalar_mass, dev())
-            p.K = g.K_from_mean_density(mean)
+            r5, r1, S, p.K = g.scalar_field_sources(p, w.phi_modes, w.pi_modes, w.scalar_mass, dev())
         s = g.Solver(p, r5, r1, S if w.solve_momentum else None)
         if not no_tail:
             # the tail's first level: the first from which the cells of all levels

@@ -106,18 +106,6 @@ def test_marched64_W_pass_and_defect(precision):
     assert rel_err(N(out), ref) < (1e-12 if vt == torch.float64 else 1e-5)
 
 
-def test_report_lds_limit():
-    import ctypes as C
-    hip = C.CDLL("libamdhip64.so")
-    v = C.c_int(0)
-    # hipDeviceAttributeMaxSharedMemoryPerBlock
-    for name, attr in (("max_shared_per_block", 74), ("max_shared_per_multiprocessor", 10002)):
-        rc = hip.hipDeviceGetAttribute(C.byref(v), attr, 0)
-        print(f"{name} (attr {attr}): rc={rc} value={v.value}")
-    props = torch.cuda.get_device_properties(0)
-    print("torch props:", {k: getattr(props, k) for k in dir(props) if "shared" in k or "multi" in k})
-
-
 @pytest.mark.parametrize("depth", [2, 4, 8, 16])
 def test_tiled_residual_periodic_coupled(depth):
     """Bricks (depth 2, 4) and x-marched columns (8, 16) of the finest residual."""
