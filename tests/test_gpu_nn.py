@@ -171,8 +171,10 @@ def test_network_gradients(n, levels, ch):
     gg = grad.cpu().numpy().astype(np.float64)
     print(f"network gradients n={n} levels={levels}: loss {loss:.6f} vs {rloss:.6f}, "
           f"grad rel err {rel(gg, rgrad):.2e}")
-    assert abs(loss - rloss) <= 2e-2 * rloss
-    assert rel(gg, rgrad) < 5e-2
+    # measured on MI355X: loss 1.2e-4 relative, gradient 7.1e-4, per layer 2.0e-3 (weights)
+    # and 1.2e-3 (biases); bounds about 3x those
+    assert abs(loss - rloss) <= 5e-4 * rloss
+    assert rel(gg, rgrad) < 2.5e-3
     off = 0
     errs = []
     for k, (ci, co) in enumerate(nn.layer_shapes(cfg)):
@@ -183,7 +185,7 @@ def test_network_gradients(n, levels, ch):
     print("per-layer gradient rel err (max weight, max bias):",
           f"{max(e[0] for e in errs):.2e} {max(e[1] for e in errs):.2e}")
     for k, (ew, eb) in enumerate(errs):
-        assert ew < 1e-1 and eb < 1e-1, (k, ew, eb)
+        assert ew < 6e-3 and eb < 4e-3, (k, ew, eb)
 
 
 def test_adam_matches_oracle():
