@@ -210,6 +210,30 @@ mg_status mg_scalar_field_sources(const mg_params *p, int32_t n_phi, const doubl
                                   double *h_K, void *stream);
 
 /*
+ * Allocation-free variant of mg_scalar_field_sources, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the same kernels and the same results,
+ * bit for bit, with the reduction scratch taken from a device array inside the
+ * library instead of a d_scratch argument.  That array holds
+ * MG_SOURCES_STATIC_SCRATCH_BYTES on every GPU the library runs on (its address
+ * is looked up once per device, on the first call that wants the mean or K,
+ * and the array lives until the process ends); the reduction needs 2049
+ * doubles whatever n, so every accepted n (1..4096) fits, and a call whose need
+ * exceeded the array would return MG_ERR_WORKSPACE before any launch.  The
+ * call itself makes no hipMalloc, hipFree or other allocating call.  All calls
+ * on one GPU share the array: calls that overlap in time on one GPU (from
+ * several host threads or on several streams) race and must be serialised by
+ * the caller.  Nothing in the array needs clearing: every call writes each
+ * value it reads.  Arguments, outputs and errors as mg_scalar_field_sources;
+ * the device is the stream's (the current device for a NULL stream).
+ */
+#define MG_SOURCES_STATIC_SCRATCH_BYTES 32768
+mg_status mg_scalar_field_sources_static(const mg_params *p, int32_t n_phi, const double *h_phi_modes,
+                                         int32_t n_pi, const double *h_pi_modes, double mass,
+                                         double *d_rho5, double *d_rho1, double *d_S,
+                                         double *h_mean_rho, double *h_K, void *stream);
+
+/*
  * Scalar shell around the puncture: phi = amp exp(-(r - r0)^2 / width2) Y_11
  * with the real dipole harmonic Y_11 = sqrt(3/(4 pi)) x/r about puncture_pos,
  * Pi = 0.  Writes d_rho5 = mass^2 phi^2/2, d_rho1 = |d phi|^2/2, d_S = 0.

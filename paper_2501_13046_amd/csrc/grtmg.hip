@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "grtmg.h"
@@ -1684,6 +1685,7 @@ mg_status check_sources_args(const mg_params *p, int n_phi, const double *h_phi_
 // reduced mean at index kSrcBlocks.
 constexpr size_t kSourcesScratchNeed = (size_t)(kSrcBlocks + 1) * sizeof(double);
 static_assert(kSourcesScratchNeed <= MG_SOURCES_SCRATCH_BYTES, "source scratch");
+static_assert(kSourcesScratchNeed <= MG_SOURCES_STATIC_SCRATCH_BYTES, "static source scratch");
 
 // Arguments already checked by check_sources_args; scratch_d may be NULL when neither
 // the mean nor K is requested.
@@ -1718,6 +1720,40 @@ mg_status scalar_sources(const mg_params *p, int n_phi, const double *h_phi_mode
         if (h_K) *h_K = std::sqrt(24.0 * M_PI * std::max(mean, 0.0));
     }
     return hip_status();
+}
+
+// Scratch of the allocation-free variant: a file-scope device array, one copy per
+// GPU for the life of the process.  Host code never passes the array's name to a
+// kernel (on the host it is only a stand-in for the symbol); it uses the device
+// address looked up once per device with that device current.
+static __device__ __align__(256) double scratch[MG_SOURCES_STATIC_SCRATCH_BYTES / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices];
+
+mg_status static_scratch_for(hipStream_t s, double **out)
+{
+    int dev = -1;
+    if (s) {
+        if (hipStreamGetDevice(s, &dev) != hipSuccess) return MG_ERR_HIP;
+    } else if (hipGetDevice(&dev) != hipSuccess) {
+        return MG_ERR_HIP;
+    }
+    if (dev < 0 || dev >= kMaxDevices) return MG_ERR_INVALID;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess) return MG_ERR_HIP;
+        if (cur != dev && hipSetDevice(dev) != hipSuccess) return MG_ERR_HIP;
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != dev && hipSetDevice(cur) != hipSuccess) return MG_ERR_HIP;
+        if (e != hipSuccess || !ptr) return MG_ERR_HIP;
+        g_scratch_ptr[dev] = (double *)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return MG_OK;
 }
 
 } // namespace
@@ -2017,6 +2053,25 @@ mg_status mg_scalar_field_sources(const mg_params *p, int32_t n_phi, const doubl
         return MG_ERR_WORKSPACE;
     return scalar_sources(p, n_phi, h_phi_modes, n_pi, h_pi_modes, mass, d_rho5, d_rho1, d_S,
                           (double *)d_scratch, h_mean_rho, h_K, (hipStream_t)stream);
+}
+
+mg_status mg_scalar_field_sources_static(const mg_params *p, int32_t n_phi, const double *h_phi_modes,
+                                         int32_t n_pi, const double *h_pi_modes, double mass,
+                                         double *d_rho5, double *d_rho1, double *d_S, double *h_mean_rho,
+                                         double *h_K, void *stream)
+{
+    const mg_status st = check_sources_args(p, n_phi, h_phi_modes, n_pi, h_pi_modes, mass, d_rho5, d_rho1, d_S);
+    if (st != MG_OK) return st;
+    double *scr = nullptr;
+    if (h_mean_rho || h_K) {
+        const int64_t m = (int64_t)p->n * p->n * p->n;
+        const size_t need = ((size_t)std::min<unsigned>(nblk(m), kSrcBlocks) + 1) * sizeof(double);
+        if (need > MG_SOURCES_STATIC_SCRATCH_BYTES) return MG_ERR_WORKSPACE;
+        const mg_status ss = static_scratch_for((hipStream_t)stream, &scr);
+        if (ss != MG_OK) return ss;
+    }
+    return scalar_sources(p, n_phi, h_phi_modes, n_pi, h_pi_modes, mass, d_rho5, d_rho1, d_S, scr, h_mean_rho,
+                          h_K, (hipStream_t)stream);
 }
 
 mg_status mg_shell_field_sources(const mg_params *p, double amp, double r0, double width2, double mass,

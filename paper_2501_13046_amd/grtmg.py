@@ -86,6 +86,7 @@ def lib() -> C.CDLL:
         L.mg_status_str.restype = C.c_char_p
         L.mg_scalar_field_sources.argtypes = [pp, i32, dp, i32, dp, C.c_double, vp, vp, vp, vp,
                                               C.c_size_t, dp, dp, vp]
+        L.mg_scalar_field_sources_static.argtypes = [pp, i32, dp, i32, dp, C.c_double, vp, vp, vp, dp, dp, vp]
         L.mg_shell_field_sources.argtypes = [pp, C.c_double, C.c_double, C.c_double, C.c_double,
                                              vp, vp, vp, vp]
         L.mg_interp_cubic.argtypes = [pp, vp, vp, vp]
@@ -105,6 +106,7 @@ def lib() -> C.CDLL:
         L.mg_probe_result.argtypes = [vp, C.POINTER(i32), C.POINTER(C.c_double)]
         for f in ("mg_workspace_size", "mg_setup", "mg_vcycle", "mg_solve_constraints", "mg_solve_constraints_continue",
                   "mg_residual_norm", "mg_residual_fields", "mg_scalar_field_sources",
+                  "mg_scalar_field_sources_static",
                   "mg_shell_field_sources", "mg_interp_cubic", "mg_kernel_op", "mg_probe",
                   "mg_probe_result", "mg_batch_workspace_size", "mg_setup_batch", "mg_solve_batch",
                   "mg_fmg_start", "mg_batch_launch_mode", "mg_autotune", "mg_set_tile"):
