@@ -13,14 +13,21 @@ norms (Key features, "Diagnostics").
 Pins (tests marked ``not gpu``): polynomial exactness and Fourier symbols of
 the stencils, FFT-exact linear solves, uniform density (psi = 1), vacuum
 puncture (u = 0), the Gaussian-source closed form under the Robin rule,
-brute-force dense solves, and 4th-order convergence to manufactured
-solutions.  No oracle function is left "parity unpinned".
+brute-force dense solves, 4th-order convergence to manufactured solutions,
+the smoothers' diagonals against the operator's impulse response (periodic
+and Robin, psi with its Newton coefficient, all three W components), the
+exact solution as a fixed point of every colour pass, the colour convention,
+the cycle order and contraction of both V-cycles; each smoother pin is shown
+to fail on a copy of the oracle with a planted mistake (``planted``).  No
+oracle function is left "parity unpinned".
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 import subprocess
+import tempfile
 
 import numpy as np
 
@@ -35,8 +42,7 @@ FLAG_CONFORMAL_MATTER = 1
 
 def build(verbose: bool = False) -> str:
     """Compile liboracle.so with gcc (FP64, no fast-math, no FMA contraction)."""
-    cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-ffp-contract=off",
-           "-fPIC", "-shared", "-Wall", "-o", LIB_PATH + ".tmp", SRC_PATH, "-lm"]
+    cmd = _cc(SRC_PATH, LIB_PATH + ".tmp")
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)
@@ -55,45 +61,81 @@ class OrcParams(C.Structure):
 _lib = None
 
 
+def _cc(src, out):
+    return ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-ffp-contract=off",
+            "-fPIC", "-shared", "-Wall", "-o", out, src, "-lm"]
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             build()
-        _lib = C.CDLL(LIB_PATH)
-        dp = C.POINTER(C.c_double)
-        pp = C.POINTER(OrcParams)
-        ip = C.c_int
-        sig = {
-            "orc_residuals": [pp, dp, dp, dp, dp, dp, dp, dp, dp, dp],
-            "orc_norms": [ip, dp, dp, dp],
-            "orc_apply_lap": [pp, ip, dp, dp],
-            "orc_apply_d1": [pp, ip, dp, ip, dp],
-            "orc_apply_deltaL": [pp, ip, dp, dp],
-            "orc_pass_psi": [pp, ip, dp, dp, dp, dp, ip],
-            "orc_pass_W": [pp, ip, dp, dp, dp, ip],
-            "orc_restrict": [ip, dp, dp],
-            "orc_prolong_add": [pp, ip, dp, dp],
-            "orc_interp_cubic": [pp, ip, dp, dp],
-            "orc_coarse_solve_psi": [pp, ip, dp, dp, dp],
-            "orc_coarse_solve_W": [pp, ip, dp, dp],
-            "orc_vcycle_psi": [pp, dp, dp, dp],
-            "orc_vcycle_W": [pp, dp, dp],
-            "orc_step": [pp, ip, dp, dp, dp, dp, dp, dp],
-            "orc_solve": [pp, dp, dp, dp, dp, dp, dp, C.c_double, ip, dp, ip,
-                          C.POINTER(C.c_int), dp],
-            "orc_scalar_sources": [pp, ip, dp, ip, dp, C.c_double, dp, dp, dp],
-            "orc_shell_sources": [pp, C.c_double, C.c_double, C.c_double, C.c_double,
-                                  dp, dp, dp],
-            "orc_num_threads": [],
-        }
-        for name, args in sig.items():
-            f = getattr(_lib, name)
-            f.argtypes = args
-            f.restype = C.c_int if name in ("orc_coarse_solve_psi", "orc_coarse_solve_W",
-                                            "orc_vcycle_psi", "orc_vcycle_W", "orc_step",
-                                            "orc_solve", "orc_num_threads") else None
+        _lib = _bind(C.CDLL(LIB_PATH))
     return _lib
+
+
+@contextlib.contextmanager
+def planted(substitutions):
+    """Test support: for the duration of the block, every function of this
+    module runs on a copy of mg_oracle.c with a deliberate mistake planted by
+    the given (old, new) text substitutions (each old text must occur exactly
+    once), built on the CPU into a temporary directory.  Used to show that a
+    pin fails when the oracle is wrong."""
+    global _lib
+    with open(SRC_PATH) as fh:
+        src = fh.read()
+    for old, new in substitutions:
+        if src.count(old) != 1:
+            raise ValueError(f"planted substitution must match once: {old!r}")
+        src = src.replace(old, new)
+    with tempfile.TemporaryDirectory() as d:
+        c_path, so_path = os.path.join(d, "planted.c"), os.path.join(d, "libplanted.so")
+        with open(c_path, "w") as fh:
+            fh.write(src)
+        subprocess.check_call(_cc(c_path, so_path))
+        saved = _lib
+        _lib = _bind(C.CDLL(so_path))
+        try:
+            yield
+        finally:
+            _lib = saved
+
+
+def _bind(L):
+    dp = C.POINTER(C.c_double)
+    pp = C.POINTER(OrcParams)
+    ip = C.c_int
+    sig = {
+        "orc_residuals": [pp, dp, dp, dp, dp, dp, dp, dp, dp, dp],
+        "orc_norms": [ip, dp, dp, dp],
+        "orc_apply_lap": [pp, ip, dp, dp],
+        "orc_apply_d1": [pp, ip, dp, ip, dp],
+        "orc_apply_deltaL": [pp, ip, dp, dp],
+        "orc_pass_psi": [pp, ip, dp, dp, dp, dp, ip],
+        "orc_pass_W": [pp, ip, dp, dp, dp, ip],
+        "orc_restrict": [ip, dp, dp],
+        "orc_prolong_add": [pp, ip, dp, dp],
+        "orc_interp_cubic": [pp, ip, dp, dp],
+        "orc_coarse_solve_psi": [pp, ip, dp, dp, dp],
+        "orc_coarse_solve_W": [pp, ip, dp, dp],
+        "orc_vcycle_psi": [pp, dp, dp, dp],
+        "orc_vcycle_W": [pp, dp, dp],
+        "orc_step": [pp, ip, dp, dp, dp, dp, dp, dp],
+        "orc_solve": [pp, dp, dp, dp, dp, dp, dp, C.c_double, ip, dp, ip,
+                      C.POINTER(C.c_int), dp],
+        "orc_scalar_sources": [pp, ip, dp, ip, dp, C.c_double, dp, dp, dp],
+        "orc_shell_sources": [pp, C.c_double, C.c_double, C.c_double, C.c_double,
+                              dp, dp, dp],
+        "orc_num_threads": [],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = C.c_int if name in ("orc_coarse_solve_psi", "orc_coarse_solve_W",
+                                        "orc_vcycle_psi", "orc_vcycle_W", "orc_step",
+                                        "orc_solve", "orc_num_threads") else None
+    return L
 
 
 def _ptr(a):

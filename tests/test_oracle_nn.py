@@ -139,3 +139,34 @@ def test_standardisation_round_trip():
     u2, W2 = nn.net_state(t, mean, std)
     assert np.allclose(u2, u) and np.allclose(W2, W)
     assert np.allclose(t[1], (W[0] + 0.2) / 0.5)
+
+
+def check_silu():
+    # SiLU(z) = z / (1 + e^-z): closed forms at 0 and +-ln 3 (logistic 3/4 and 1/4), its
+    # limits, the identity SiLU(z) - SiLU(-z) = z, and the slope 1/2 at 0
+    ln3 = float(np.log(3.0))
+    z = torch.tensor([0.0, ln3, -ln3, 40.0, -40.0], dtype=torch.float64)
+    s = nn.silu(z).numpy()
+    assert s[0] == 0.0
+    assert abs(s[1] - 0.75 * ln3) <= 1e-15 and abs(s[2] + 0.25 * ln3) <= 1e-15
+    assert abs(s[3] - 40.0) <= 1e-14 and abs(s[4]) <= 1e-15
+    x = torch.tensor(rnd(9, 64), dtype=torch.float64)
+    assert torch.allclose(nn.silu(x) - nn.silu(-x), x, rtol=0, atol=1e-14)
+    z0 = torch.zeros(1, dtype=torch.float64, requires_grad=True)
+    nn.silu(z0).sum().backward()
+    assert abs(float(z0.grad[0]) - 0.5) <= 1e-15
+
+
+def test_silu_closed_forms():
+    check_silu()
+
+
+@pytest.mark.parametrize("wrong", [
+    lambda z: z * torch.sigmoid(-z),          # logistic of the wrong sign
+    lambda z: torch.sigmoid(z),               # the logistic alone
+    lambda z: z * torch.sigmoid(2.0 * z),     # a scaled logistic (the "swish-beta" with beta 2)
+], ids=["sign", "no-z", "beta2"])
+def test_silu_planted_mistake_is_caught(wrong, monkeypatch):
+    monkeypatch.setattr(nn, "silu", wrong)
+    with pytest.raises(AssertionError):
+        check_silu()
