@@ -12,12 +12,15 @@ fallback test, solve); the same solve from psi = 1, W = 0, the full-multigrid
 start from the 64^3 problem and the plain FP64 GPU multigrid are timed on the
 same input and reported beside it.
 
-The JSON line also carries the roofline of the dominant kernel (its launches
-inside a real solve timed with HIP event pairs; HBM traffic from the committed
-counter summary while the kernel sources match it) and the CPU oracle timed
-on a bounded sample of the same workload.
+The JSON line also carries the roofline of the dominant kernel, the finest-level
+residual (its launches inside a real solve timed with HIP event pairs that the
+dispatches record; algorithmic bytes of its two forms; HBM traffic from the
+committed counter summary while the kernel sources match it), the same figures
+for the finest W smoother pass, two further workloads (the 256^3 puncture with
+a scalar shell, the 96-instance parameter scan) and the CPU oracle solving the
+benchmarked workload to the same tolerance on the host cores.
 
-    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-fp64]
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-fp64] [--no-extra]
 """
 import argparse
 import json
@@ -30,32 +33,187 @@ sys.path.insert(0, ROOT)
 
 METRIC = "s to 1e-10 constraint residual @128^3: FP64 MG vs mixed+learned; HBM GB/s"
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per launch of the finest-level W pass from FETCH_SIZE / WRITE_SIZE runs,
-# valid only for the kernel sources they were measured on (sha256 prefixes)
+# HBM bytes per launch from committed FETCH_SIZE / WRITE_SIZE summaries, valid only for the
+# kernel sources they were measured on (sha256 prefixes listed in each summary)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pass_W_march_coupled_128_traffic.md")
-TRAFFIC_SOURCES = {"paper_2501_13046_amd/csrc/mg_tiled.hpp": "3f47065d8fbe5c58",
-                   "paper_2501_13046_amd/csrc/mg_device.hpp": "cb330752cce51a61"}
+RESIDUAL_TRAFFIC = os.path.join(ROOT, "profiles", "k_residual_march_coupled_128_traffic.md")
 
 
-def measured_traffic(depth):
-    """Bytes per launch from the committed counter summary, or None when the
-    kernel sources changed since the counters were taken or the pass runs at
-    another brick depth than the one measured."""
+def measured_traffic(path, depth):
+    """Bytes per launch from a committed counter summary, or None when the
+    kernel sources changed since the counters were taken or the kernel runs at
+    another depth than the one measured."""
     import hashlib
-    for rel, pre in TRAFFIC_SOURCES.items():
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            if hashlib.sha256(f.read()).hexdigest()[:16] != pre:
-                return None
-    vals = {}
+    vals, srcs = {}, {}
     try:
-        for line in open(TRAFFIC_FILE):
-            if ":" in line and line.split(":")[0] in ("brick_depth", "traffic_bytes_per_launch"):
-                vals[line.split(":")[0]] = int(line.split(":")[1])
+        for line in open(path):
+            key, _, val = line.partition(":")
+            if key in ("brick_depth", "traffic_bytes_per_launch"):
+                vals[key] = int(val)
+            elif key == "source_sha256_16":
+                rel, pre = val.split()
+                srcs[rel] = pre
     except (OSError, ValueError):
         return None
+    if not srcs:
+        return None
+    for rel, pre in srcs.items():
+        try:
+            with open(os.path.join(ROOT, rel), "rb") as f:
+                if hashlib.sha256(f.read()).hexdigest()[:16] != pre:
+                    return None
+        except OSError:
+            return None
     if vals.get("brick_depth") != depth:
         return None
     return vals.get("traffic_bytes_per_launch")
+
+
+def mixed_residual_depth(tuning):
+    return next((e["chosen"] for e in tuning if e["family"] == 3 and e["level"] == 0), None)
+
+
+def bench_puncture_256(g, synth, dev, args, log):
+    """Isolated black hole (M = 1 puncture) with a scalar-field shell on the 256^3 box
+    of side 64 M, Robin boundaries, FP32 V-cycles in FP64 refinement, 6 levels."""
+    import torch
+    w = synth.puncture_shell(256, precision=g.PREC_FP32_IR, levels=6)
+    p = g.params(w.n, w.levels, w.bc, g.PREC_FP32_IR, w.length, w.origin, 0.0, w.nu_pre, w.nu_post,
+                 False, w.puncture_mass, w.puncture_pos, w.conformal_matter)
+    r5, r1, S = g.shell_field_sources(p, w.shell["amplitude"], w.shell["r0"], w.shell["width2"],
+                                      w.scalar_mass, dev)
+    s = g.Solver(p, r5, r1)
+    u = torch.zeros((w.n,) * 3, dtype=torch.float64, device=dev)
+    tune = s.autotune(u, None, reps=10)
+    runs, rep = [], None
+    for k in range(1 + max(1, args.steps // 2)):
+        u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep = s.solve(u, None, tol=args.tol, max_outer=100)
+        torch.cuda.synchronize()
+        if k:
+            runs.append(time.perf_counter() - t0)
+    runs.sort()
+    out = dict(seconds=runs[len(runs) // 2], runs=len(runs), n=w.n, levels=w.levels,
+               outer_iters=rep["outer_iters"], h_rms=rep["h_rms"], h_max=rep["h_max"],
+               autotuned=[{"family": e["family"], "level": e["level"], "depth": e["chosen"]} for e in tune])
+    log(f"[bench] puncture_shell_256 mixed: {out['seconds'] * 1e3:.2f} ms/solve (median of {len(runs)}), "
+        f"outer={rep['outer_iters']} rms H={rep['h_rms']:.2e}")
+    s.close()
+    return out
+
+
+def bench_scan_96(g, synth, dev, args, log):
+    """96 periodic instances, n uniform on {32, 48, 64, 96} (size seed 12345), phi amplitude
+    U[0.01, 0.1], Pi 0.02, each to the residual tolerance; one batch context."""
+    import torch
+    ws = synth.scan_96()
+    plist, r5s, r1s, Ss = [], [], [], []
+    for w in ws:
+        p = g.params(w.n, w.levels, w.bc, g.PREC_FP32_IR, w.length, w.origin, 0.0, w.nu_pre, w.nu_post, True)
+        r5, r1, S, p.K = g.scalar_field_sources(p, w.phi_modes, w.pi_modes, w.scalar_mass, dev)
+        plist.append(p)
+        r5s.append(r5)
+        r1s.append(r1)
+        Ss.append(S)
+    batch = g.Batch(plist, r5s, r1s, Ss)
+    us = [torch.zeros((w.n,) * 3, dtype=torch.float64, device=dev) for w in ws]
+    Wsl = [torch.zeros((3,) + (w.n,) * 3, dtype=torch.float64, device=dev) for w in ws]
+    runs, reps = [], None
+    for k in range(1 + max(1, args.steps // 2)):
+        for u, W in zip(us, Wsl):
+            u.zero_()
+            W.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, reps = batch.solve(us, Wsl, tol=args.tol, max_outer=100)
+        torch.cuda.synchronize()
+        if k:
+            runs.append(time.perf_counter() - t0)
+    mode, ms = batch.launch_mode()
+    runs.sort()
+    its = [r["outer_iters"] for r in reps]
+    out = dict(seconds=runs[len(runs) // 2], runs=len(runs), instances=len(ws),
+               cells=int(sum(w.n ** 3 for w in ws)),
+               sizes={str(nn): int(sum(1 for w in ws if w.n == nn)) for nn in (32, 48, 64, 96)},
+               status=int(st), converged=int(sum(1 for r in reps if r["status"] == 0)),
+               outer_iters_min=min(its), outer_iters_max=max(its),
+               worst_h_rms=max(r["h_rms"] for r in reps), worst_m_rms=max(r["m_rms"] for r in reps),
+               launch_mode={1: "graph", 2: "lanes"}.get(mode, str(mode)))
+    log(f"[bench] scan_96: {out['seconds'] * 1e3:.1f} ms/scan (median of {len(runs)}), {out['cells']} cells, "
+        f"iterations {min(its)}-{max(its)}, worst rms H {out['worst_h_rms']:.2e} M {out['worst_m_rms']:.2e}, "
+        f"mode {out['launch_mode']}")
+    batch.close()
+    return out
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+_CPU_SMALL = """
+import json, sys, time
+sys.path.insert(0, {root!r})
+import numpy as np
+import oracle, synth
+w = synth.hamiltonian_32(seed=0)
+r5, r1, S, K = oracle.sources_for(w)
+p = oracle.params_from_workload(w, K)
+ts = []
+for _ in range(3):
+    u = np.zeros((w.n,) * 3); W = np.zeros((3,) + (w.n,) * 3)
+    t0 = time.perf_counter()
+    res = oracle.solve(p, u, W, r5, r1, S, tol={tol!r}, max_outer=60)
+    ts.append(time.perf_counter() - t0)
+ts.sort()
+print(json.dumps(dict(seconds=ts[1], runs=3, iters=res.iters, threads=oracle.num_threads())))
+"""
+
+
+def cpu_baseline(w, args, log):
+    """The oracle (plain C, FP64, OpenMP) on the benchmarked workload, timed to the same
+    tolerance on the host's cores; plus the 32^3 Hamiltonian workload on one thread and on
+    all of them (median of 3 runs each, in child processes with OMP_NUM_THREADS set)."""
+    import subprocess
+    import numpy as np
+    import oracle
+    n = w.n
+    o5, o1, oS, oK = oracle.sources_for(w)
+    po = oracle.params_from_workload(w, oK)
+    runs, res = [], None
+    for _ in range(max(1, args.cpu_runs)):
+        uo = np.zeros((n,) * 3)
+        Wo = np.zeros((3, n, n, n))
+        t0 = time.perf_counter()
+        res = oracle.solve(po, uo, Wo, o5, o1, oS, tol=args.tol, max_outer=100)
+        runs.append(time.perf_counter() - t0)
+    runs.sort()
+    small = {}
+    for label, env_threads in (("one_thread", "1"), ("all_threads", None)):
+        env = dict(os.environ)
+        if env_threads:
+            env["OMP_NUM_THREADS"] = env_threads
+        out = subprocess.run([sys.executable, "-c", _CPU_SMALL.format(root=ROOT, tol=args.tol)],
+                             env=env, capture_output=True, text=True, timeout=600)
+        small[label] = json.loads(out.stdout.strip().splitlines()[-1]) if out.returncode == 0 else None
+    cores = oracle.num_threads()
+    cpu = {"value": runs[len(runs) // 2], "unit": "s", "cores": cores, "kind": "oracle",
+           "sample": f"full FP64 CPU oracle solve of coupled_{n} from psi = 1, W = 0 to rms {args.tol:g} "
+                     f"({res.iters} outer Newton-multigrid iterations, status {res.status}), "
+                     f"{len(runs)} run(s), median; OpenMP threads = {cores}",
+           "status": res.status, "outer_iters": res.iters, "runs": len(runs),
+           "host": {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "model": cpu_model()},
+           "hamiltonian_32": small}
+    log(f"[bench] cpu oracle: {cpu['value']:.2f} s to {args.tol:g} ({res.iters} iterations, {cores} threads); "
+        f"hamiltonian_32: {small}")
+    return cpu
 
 
 def log(*a):
@@ -71,7 +229,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-iters", type=int, default=2)
+    ap.add_argument("--cpu-runs", type=int, default=1, help="oracle solves of the 128^3 workload to time")
+    ap.add_argument("--no-extra", action="store_true", help="skip the 256^3 puncture and 96-instance scan legs")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison solves")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain device copy of 256 MiB (the reference dispatch that scales "
@@ -126,7 +285,7 @@ def main():
         W.zero_()
         return solver.solve(u, W, tol=args.tol, max_outer=100)
 
-    log(f"[bench] workload coupled_{n}: K={K:.6f} <rho>={mean_rho:.6f}; warmup {args.warmup}")
+    log(f"[bench] workload coupled_{n}: K={K:.6f} <rho>={K * K / (24.0 * np.pi):.6f}; warmup {args.warmup}")
     for _ in range(args.warmup):
         step(mixed)
     torch.cuda.synchronize()
@@ -214,26 +373,39 @@ def main():
         f"{rf['outer_iters']} iterations, rms H={ff[0]:.3e} rms M={ff[1]:.3e}")
     coarse.close()
 
-    # ---- dominant kernel: finest-level W smoother pass, timed live in a solve
-    mixed.probe(g.PROBE_PASS_W, 0)
-    step(mixed)
-    launches, ms = mixed.probe_result()
-    mixed.probe(g.PROBE_NONE, 0)
-    avg_s = ms / 1e3 / max(launches, 1)
-    bytes_per_launch = 9 * 4 * n ** 3  # in (3 comps), r (3), out (3), FP32
-    achieved = bytes_per_launch / avg_s / 1e9
-    log(f"[bench] k_pass_W<float> level 0: {launches} launches, avg {avg_s * 1e6:.2f} us, "
-        f"{achieved:.0f} GB/s algorithmic")
-    # other kernels' live averages for the log
-    for name, kid in (("pass_psi", g.PROBE_PASS_PSI), ("residual", g.PROBE_RESIDUAL),
-                      ("defect_restrict_W", g.PROBE_DEFECT_RESTRICT_W),
-                      ("prolong", g.PROBE_PROLONG), ("coarse", g.PROBE_COARSE)):
-        lvl = mixed.p.levels - 1 if kid == g.PROBE_COARSE else 0
-        mixed.probe(kid, lvl)
-        step(mixed)
+    # ---- roofline: the finest-level residual is the kernel with the most time per outer
+    # iteration (two launches: the psi step's and the evaluation's), then the finest W pass.
+    # Both are timed live inside a solve (HIP events recorded by the dispatches themselves).
+    def probe(kid, level):
+        mixed.probe(kid, level)
+        r = step(mixed)
         cnt, t = mixed.probe_result()
         mixed.probe(g.PROBE_NONE, 0)
-        log(f"[bench]   {name:18s} level {lvl}: {cnt:4d} launches avg {t / max(cnt, 1) * 1e3:8.2f} us")
+        return cnt, t / 1e3, r
+
+    cells = n ** 3
+    cnt_r, t_r, rr = probe(g.PROBE_RESIDUAL, 0)
+    # algorithmic bytes per cell of the two forms (FP64 state and sources in, FP32 out):
+    #  evaluation: u, W(3), rho5, rho1, S(3) in (72 B); r_W(3) and the first W pass (3) out (24 B)
+    #  psi step:   u, W(3), rho5, rho1 in (48 B); r, c and the first psi pass out (12 B)
+    # a solve runs one evaluation per outer iteration plus the starting state's, and one psi step
+    n_psi = rr["outer_iters"]
+    n_eval = cnt_r - n_psi
+    res_bytes = (n_eval * 96 + n_psi * 60) * cells / max(cnt_r, 1)
+    res_avg = t_r / max(cnt_r, 1)
+    res_gbs = res_bytes / res_avg / 1e9
+    log(f"[bench] residual level 0: {cnt_r} launches ({n_eval} evaluation, {n_psi} psi step), "
+        f"avg {res_avg * 1e6:.2f} us, {res_bytes / 1e6:.1f} MB/launch, {res_gbs:.0f} GB/s algorithmic")
+    cnt_w, t_w, _ = probe(g.PROBE_PASS_W, 0)
+    w_avg = t_w / max(cnt_w, 1)
+    w_bytes = 9 * 4 * cells  # in (3 comps), r (3), out (3), FP32
+    w_gbs = w_bytes / w_avg / 1e9
+    log(f"[bench] W pass level 0: {cnt_w} launches, avg {w_avg * 1e6:.2f} us, {w_gbs:.0f} GB/s algorithmic")
+    for name, kid in (("pass_psi", g.PROBE_PASS_PSI), ("defect_restrict_W", g.PROBE_DEFECT_RESTRICT_W),
+                      ("prolong", g.PROBE_PROLONG), ("update", g.PROBE_UPDATE), ("coarse", g.PROBE_COARSE)):
+        lvl = mixed.p.levels - 1 if kid == g.PROBE_COARSE else 0
+        cnt, t, _ = probe(kid, lvl)
+        log(f"[bench]   {name:18s} level {lvl}: {cnt:4d} launches avg {t / max(cnt, 1) * 1e6:8.2f} us")
 
     # ---- plain FP64 GPU multigrid on the same input
     fp64 = None
@@ -252,27 +424,17 @@ def main():
         log(f"[bench] fp64: {sec64 * 1e3:.3f} ms/solve, outer={r64['outer_iters']}")
         s64.close()
 
-    # ---- CPU oracle on a bounded sample of the same workload
+    # ---- extra workloads (not the headline): the 256^3 isolated black hole with a scalar
+    # shell (Robin boundaries, mixed precision) and the 96-instance parameter scan
+    extra = {}
+    if not args.no_extra:
+        extra["puncture_shell_256"] = bench_puncture_256(g, synth, dev, args, log)
+        extra["scan_96"] = bench_scan_96(g, synth, dev, args, log)
+
+    # ---- CPU oracle: the same workload solved to the same tolerance on the host cores
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        o5, o1, oS, oK = oracle.sources_for(w)
-        po = oracle.params_from_workload(w, oK)
-        uo = np.zeros((n,) * 3)
-        Wo = np.zeros((3, n, n, n))
-        k = args.cpu_sample_iters
-        t0 = time.perf_counter()
-        res = oracle.solve(po, uo, Wo, o5, o1, oS, tol=args.tol, max_outer=k)
-        tcpu = time.perf_counter() - t0
-        per_iter = tcpu / max(res.iters, 1)
-        iters_full = fp64["outer_iters"] if fp64 else rep["outer_iters"]
-        cpu = {"value": per_iter * iters_full, "unit": "s", "cores": oracle.num_threads(),
-               "kind": "oracle",
-               "sample": f"{res.iters} outer Newton-multigrid iterations of the FP64 CPU oracle on "
-                         f"coupled_{n} ({tcpu:.1f} s), scaled to the {iters_full} iterations "
-                         f"the same algorithm needs to reach {args.tol:g}"}
-        log(f"[bench] cpu oracle: {per_iter:.2f} s/iteration x {iters_full} = {cpu['value']:.1f} s "
-            f"({cpu['cores']} threads)")
+        cpu = cpu_baseline(w, args, log)
 
     headline = learned["seconds"] if learned else sec
     out = {
@@ -304,13 +466,20 @@ def main():
                                  for e in tuning],
             "learned": learned,
             "fmg_start": fmg,
+            "time_saved_vs_zero_start_s": {
+                "learned": (sec - learned["seconds"]) if learned else None,
+                "fmg_start": sec - fmg["seconds"]},
+            **extra,
         },
         "roofline": {
-            "kernel": f"finest-level W colour pass, brick depth {w_depth} "
-                      f"({'x-marched column' if (w_depth or 0) >= 8 else 'staged brick'})",
-            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(w_depth),
-            "launches": launches, "avg_us": avg_s * 1e6, "bytes_per_launch": bytes_per_launch,
+            "kernel": "finest-level residual (k_residual_march, FP64 arithmetic; evaluation and psi-step forms)",
+            "bound": "hbm", "achieved": res_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": res_gbs / HBM_PEAK_GBS,
+            "traffic": measured_traffic(RESIDUAL_TRAFFIC, mixed_residual_depth(tuning)),
+            "launches": cnt_r, "avg_us": res_avg * 1e6, "bytes_per_launch": res_bytes,
+            "w_pass": {"kernel": f"finest-level W colour pass, depth {w_depth}", "achieved": w_gbs,
+                       "frac": w_gbs / HBM_PEAK_GBS, "avg_us": w_avg * 1e6, "bytes_per_launch": w_bytes,
+                       "launches": cnt_w, "traffic": measured_traffic(TRAFFIC_FILE, w_depth)},
         },
         "cpu_baseline": cpu,
     }

@@ -109,3 +109,44 @@ def test_batch_launch_modes_agree_and_autotune():
         assert results[mode][1] == results[g.BATCH_GRAPH][1]
         for a, b in zip(results[mode][0], results[g.BATCH_GRAPH][0]):
             assert np.array_equal(a, b)
+
+
+def test_scan_96_full_batch_and_large_members_match_oracle():
+    """The 96-instance scan itself: every member converges to rms 1e-10 (also by
+    the judge's Hamiltonian at sampled cells), and one 64^3 and one 96^3 member
+    match the CPU oracle's solution (driven to 1e-11) to 1e-9 in psi."""
+    from oracle import judge
+    ws = synth.scan_96()
+    plist, r5s, r1s, Ss, Ks = make_members(ws, g.PREC_FP32_IR)
+    batch = g.Batch(plist, r5s, r1s, Ss)
+    us = [torch.zeros((w.n,) * 3, dtype=torch.float64, device=dev()) for w in ws]
+    Ws = [torch.zeros((3,) + (w.n,) * 3, dtype=torch.float64, device=dev()) for w in ws]
+    st, reps = batch.solve(us, Ws, tol=1e-10, max_outer=60)
+    its = [r["outer_iters"] for r in reps]
+    print(f"scan_96: status {st}, iterations {min(its)}-{max(its)}, worst rms H "
+          f"{max(r['h_rms'] for r in reps):.2e} M {max(r['m_rms'] for r in reps):.2e}", flush=True)
+    assert st == 0
+    rng = np.random.default_rng(96)
+    for i, (w, r) in enumerate(zip(ws, reps)):
+        assert r["status"] == 0 and r["h_rms"] <= 1e-10 and r["m_rms"] <= 1e-10, (i, r)
+        cells = rng.integers(0, w.n, size=(64, 3))
+        gr = judge.Grid(w.n, w.length, w.bc, w.origin)
+        H = judge.hamiltonian_at(gr, N(us[i]), N(Ws[i]), N(r5s[i]), N(r1s[i]), Ks[i], cells)
+        assert np.sqrt(np.mean(H ** 2)) < 5e-10, (i, np.sqrt(np.mean(H ** 2)))
+    for size in (64, 96):
+        i = next(k for k, w in enumerate(ws) if w.n == size)
+        w = ws[i]
+        rho5, rho1, S, K, po = oracle_problem(w)
+        assert abs(K - Ks[i]) <= 1e-13 * K
+        uo = np.zeros((w.n,) * 3)
+        Wo = np.zeros((3,) + (w.n,) * 3)
+        res = oracle.solve(po, uo, Wo, rho5, rho1, S, tol=1e-11, max_outer=60)
+        assert res.status == 0
+        err = psi_rel_err(N(us[i]), uo)
+        Wg = N(Ws[i]) - N(Ws[i]).mean(axis=(1, 2, 3), keepdims=True)
+        Wo -= Wo.mean(axis=(1, 2, 3), keepdims=True)
+        werr = np.abs(Wg - Wo).max()
+        print(f"scan member {i} n={w.n}: batch {reps[i]['outer_iters']} iterations, oracle {res.iters}; "
+              f"psi rel err {err:.2e}, W err {werr:.2e}", flush=True)
+        assert err < 1e-9 and werr < 1e-9
+    batch.close()

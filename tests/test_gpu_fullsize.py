@@ -76,19 +76,21 @@ def test_puncture_shell_128_matches_oracle():
     s = g.Solver(gparams(w, K), rho5, rho1)
     n = w.n
     u = torch.zeros((n,) * 3, dtype=torch.float64, device=dev())
-    rep = s.solve(u, None, tol=1e-10, max_outer=60)
-    assert rep["h_rms"] <= 1e-10
-    # psi is compared after both sides reach 1e-11 (the wide Robin box has a
-    # small lowest eigenvalue, so 1e-10 bounds psi only to ~1e-8)
-    rep = s.solve(u, None, tol=1e-11, max_outer=60)
+    rep10 = s.solve(u, None, tol=1e-10, max_outer=60)
+    assert rep10["h_rms"] <= 1e-10
     cells = np.asarray(gold["cells"])
     i, j, k = cells[:, 0], cells[:, 1], cells[:, 2]
     gr = judge.Grid(n, w.length, w.bc, w.origin, w.puncture_pos)
     psi0 = judge.psi0(gr, w.puncture_mass)[i, j, k]
     uo = np.asarray(gold["u"])
+    err10 = np.max(np.abs(N(u)[i, j, k] - uo) / (psi0 + uo))
+    # psi is compared after both sides reach 1e-11 (the wide Robin box has a
+    # small lowest eigenvalue, so 1e-10 bounds psi only to ~1e-8)
+    rep = s.solve(u, None, tol=1e-11, max_outer=60)
     err = np.max(np.abs(N(u)[i, j, k] - uo) / (psi0 + uo))
-    print(f"puncture_shell_128: iters={rep['outer_iters']} (oracle {gold['outer_iters']}) "
-          f"psi_err={err:.2e} rms H={rep['h_rms']:.2e}")
+    print(f"puncture_shell_128: psi error vs oracle {err10:.2e} at rms H {rep10['h_rms']:.2e} "
+          f"({rep10['outer_iters']} iterations), {err:.2e} at rms H {rep['h_rms']:.2e} "
+          f"(+{rep['outer_iters']} iterations; oracle {gold['outer_iters']} to 1e-11)")
     assert rep["h_rms"] <= 1e-11
     assert err < 1e-9
 
