@@ -359,6 +359,17 @@ void coarse_psi(mg_ctx *c, const T *r, T *x)
             launch_coarse_wave<kBcRobin, T>(c, l, r, x);
         return;
     }
+    if (m <= kKrylovMax) {
+        // conjugate gradients (periodic) or BiCGSTAB (Robin) on one block; a system it
+        // does not solve to 1e-12 raises the singular flag
+        if (c->p.bc == MG_BC_PERIODIC)
+            hipLaunchKernelGGL((k_coarse_psi_krylov<kBcPeriodic, T>), dim3(1), dim3(kGjWaves * kWave), 0, c->s,
+                               c->geo[l], m, (const T *)c->pc[l], r, x, c->scal + S_FLAG_PSI);
+        else
+            hipLaunchKernelGGL((k_coarse_psi_krylov<kBcRobin, T>), dim3(1), dim3(kGjWaves * kWave), 0, c->s,
+                               c->geo[l], m, (const T *)c->pc[l], r, x, c->scal + S_FLAG_PSI);
+        return;
+    }
     fill<double>(c->s, c->A_psi, (int64_t)m * m, 0.0);
     if (c->p.bc == MG_BC_PERIODIC)
         hipLaunchKernelGGL((k_assemble_psi<kBcPeriodic, T>), dim3(nblk(m)), dim3(kBlock), 0, c->s,
@@ -503,7 +514,7 @@ void prolong_add(mg_ctx *c, int lc, const T *coarse, T *fine, int ncomp)
 // restriction that produces that level's right-hand side (the level is not
 // smoothed before), so no separate sweep over the levels is needed.
 // A tail restricts c below its own first level.
-bool c_with_defect(const mg_ctx *c) { return wave_solvable(c->m_psi); }
+bool c_with_defect(const mg_ctx *c) { return wave_solvable(c->m_psi) || c->m_psi <= kKrylovMax; }
 
 template <typename T>
 void restrict_coefficients(mg_ctx *c)
@@ -514,7 +525,7 @@ void restrict_coefficients(mg_ctx *c)
                            (const T *)c->pc[l], (T *)c->pc[l + 1]);
     const int l = c->L - 1;
     const int m = c->m_psi;
-    if (wave_solvable(m)) return; // solved directly at the bottom of the V-cycle (coarse_psi)
+    if (wave_solvable(m) || m <= kKrylovMax) return; // solved directly at the bottom of the V-cycle
     fill<double>(c->s, c->A_psi, (int64_t)m * m, 0.0);
     if (c->p.bc == MG_BC_PERIODIC)
         hipLaunchKernelGGL((k_assemble_psi<kBcPeriodic, T>), dim3(nblk(m)), dim3(kBlock), 0, c->s, c->geo[l],
@@ -577,7 +588,7 @@ void vcycle_psi(mg_ctx *c, int l, bool first_done = false)
     }
     if (l == c->L - 1) {
         const int m = c->m_psi;
-        if (wave_solvable(m)) {
+        if (wave_solvable(m) || m <= kKrylovMax) {
             coarse_psi<T>(c, (const T *)c->pr[l], (T *)c->pd0[l]);
             return;
         }

@@ -1073,6 +1073,376 @@ __device__ __forceinline__ double readlane_f64(double x, int l)
     return __hiloint2double(hi, lo);
 }
 
+// ---------------------------------------------------------------------------------------
+// Krylov solves of the coarsest psi system (L_h + c) x = r in FP64.  Periodic grids
+// give a symmetric matrix: conjugate gradients (Hestenes-Stiefel); Robin ghosts make
+// it slightly non-symmetric: BiCGSTAB (van der Vorst).  Either is accepted only when
+// the true residual |r - A x| is below 1e-12 |r| afterwards; the caller otherwise
+// solves by elimination.
+//
+// The 12 off-centre taps of L_h at a cell, as (source cell, weight) pairs with the
+// boundary rule folded in: a periodic tap wraps, a Robin ghost tap reads the grid
+// cell b nearest the ghost with weight |x_b| / |x_g|.  A tap may name the cell itself.
+// ---------------------------------------------------------------------------------------
+template <int BC>
+__device__ __forceinline__ void coarse_taps(const Geo &g, int q, int src[12], double w[12])
+{
+    const int n = g.n;
+    const int k = q % n, j = (q / n) % n, i = q / (n * n);
+    const double wt[4] = {-1.0, 16.0, 16.0, -1.0}; // offsets -2, -1, +1, +2
+    const int dof[4] = {-2, -1, 1, 2};
+    int t = 0;
+#pragma unroll
+    for (int ax = 0; ax < 3; ax++)
+#pragma unroll
+        for (int e = 0; e < 4; e++, t++) {
+            int ii = i + (ax == 0 ? dof[e] : 0), jj = j + (ax == 1 ? dof[e] : 0), kk = k + (ax == 2 ? dof[e] : 0);
+            double fac = 1.0;
+            if constexpr (BC == kBcPeriodic) {
+                ii = wrap(ii, n);
+                jj = wrap(jj, n);
+                kk = wrap(kk, n);
+            } else if (!((unsigned)ii < (unsigned)n && (unsigned)jj < (unsigned)n && (unsigned)kk < (unsigned)n)) {
+                const int bi = clampc(ii, n), bj = clampc(jj, n), bk = clampc(kk, n);
+                fac = cell_radius(g, bi, bj, bk) / cell_radius(g, ii, jj, kk);
+                ii = bi;
+                jj = bj;
+                kk = bk;
+            }
+            src[t] = (ii * n + jj) * n + kk;
+            w[t] = wt[e] * g.inv12h2 * fac;
+        }
+}
+
+// One 64-bit DPP lane move (both halves with the same control).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wave in a fixed order, the same value in every lane:
+// DPP exchanges inside rows of 16 lanes, then the four row sums read lane by lane.
+__device__ __forceinline__ double wave_sum_dpp(double v)
+{
+    v += dpp_f64<0xB1>(v);  // quad_perm 1,0,3,2
+    v += dpp_f64<0x4E>(v);  // quad_perm 2,3,0,1
+    v += dpp_f64<0x141>(v); // row_half_mirror
+    v += dpp_f64<0x140>(v); // row_mirror
+    return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+
+// One wave, one cell per lane (M <= 64 cells); lanes >= M carry zeros.  Needs no
+// barrier: the taps come from the owning lanes by cross-lane permutes.  Writes x and
+// returns true when accepted.
+template <int BC, typename T, int M>
+__device__ __forceinline__ bool coarse_psi_krylov_wave(const Geo &g, const T *c, const T *r, T *x)
+{
+    static_assert(M <= kWave, "one cell per lane");
+    const int lane = threadIdx.x & (kWave - 1);
+    const bool own = lane < M;
+    int src[12];
+    double w[12];
+    if (own) {
+        coarse_taps<BC>(g, lane, src, w);
+    } else {
+#pragma unroll
+        for (int t = 0; t < 12; t++) {
+            src[t] = lane;
+            w[t] = 0.0;
+        }
+    }
+    const double cq = own ? (double)c[lane] : 0.0;
+    const double dg = own ? -90.0 * g.inv12h2 + cq : 0.0;
+    auto apply = [&](double v) {
+        double y = dg * v;
+#pragma unroll
+        for (int t = 0; t < 12; t++) y += w[t] * __shfl(v, src[t], kWave);
+        return y;
+    };
+    const double b = own ? (double)r[lane] : 0.0;
+    const double bb = wave_sum_dpp(b * b);
+    if (!(bb > 0.0)) {
+        if (own) x[lane] = T(0);
+        return bb == 0.0;
+    }
+    const double tol2 = 1e-28 * bb;
+    double xv = 0.0;
+    bool ok = false;
+    if constexpr (BC == kBcPeriodic) {
+        double rr = b, p = b, rz = bb;
+#pragma unroll 1
+        for (int it = 0; it < 4 * M + 32; it++) {
+            const double ap = apply(p);
+            const double pap = wave_sum_dpp(p * ap);
+            if (!(pap != 0.0)) break;
+            const double alpha = rz / pap;
+            xv += alpha * p;
+            rr -= alpha * ap;
+            const double rz1 = wave_sum_dpp(rr * rr);
+            if (rz1 <= tol2) {
+                ok = true;
+                break;
+            }
+            p = rr + (rz1 / rz) * p;
+            rz = rz1;
+        }
+    } else {
+        double rr = b, rh = b, p = 0.0, v = 0.0, rho = 1.0, alpha = 1.0, omega = 1.0;
+#pragma unroll 1
+        for (int it = 0; it < 4 * M + 32; it++) {
+            const double rho1 = wave_sum_dpp(rh * rr);
+            if (!(rho1 != 0.0)) break;
+            p = rr + (rho1 / rho) * (alpha / omega) * (p - omega * v);
+            v = apply(p);
+            const double rv = wave_sum_dpp(rh * v);
+            if (!(rv != 0.0)) break;
+            alpha = rho1 / rv;
+            const double sv = rr - alpha * v;
+            if (wave_sum_dpp(sv * sv) <= tol2) {
+                xv += alpha * p;
+                ok = true;
+                break;
+            }
+            const double t = apply(sv);
+            const double ts = wave_sum_dpp(t * sv), tt = wave_sum_dpp(t * t);
+            if (!(tt > 0.0)) break;
+            omega = ts / tt;
+            xv += alpha * p + omega * sv;
+            rr = sv - omega * t;
+            rho = rho1;
+            if (wave_sum_dpp(rr * rr) <= tol2) {
+                ok = true;
+                break;
+            }
+            if (!(omega != 0.0)) break;
+        }
+    }
+    const double tr = b - apply(xv);
+    const double trr = wave_sum_dpp(tr * tr);
+    ok = ok && trr <= 1e-24 * bb;
+    if (ok && own) x[lane] = (T)xv;
+    return ok;
+}
+
+// The same for up to kGjWaves * kWave * CPT cells on a block of kGjWaves waves: every
+// thread owns CPT cells (q = tid + kGjWaves * kWave * e), the vector being multiplied
+// is staged in LDS, and inner products are block reductions.  Writes x and returns
+// true (in every thread) when accepted; called by every thread of the block.
+constexpr int kKrylovCpt = 2;
+constexpr int kKrylovMax = kGjWaves * kWave * kKrylovCpt;
+
+template <int NV>
+__device__ __forceinline__ void block_sums(double v[NV], double (*part)[kGjWaves])
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+#pragma unroll
+    for (int q = 0; q < NV; q++) v[q] = wave_sum_dpp(v[q]);
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < NV; q++) part[q][wave] = v[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NV; q++) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < kGjWaves; w++) s += part[q][w];
+        v[q] = s;
+    }
+    __syncthreads();
+}
+
+template <int BC, typename T>
+__device__ __forceinline__ bool coarse_psi_krylov_block(const Geo &g, int m, const T *c, const T *r, T *x)
+{
+    constexpr int E = kKrylovCpt;
+    constexpr int NT = kGjWaves * kWave;
+    __shared__ double vec[kKrylovMax];
+    __shared__ double part[3][kGjWaves];
+    int src[E][12];
+    double w[E][12], dg[E], b[E];
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+        const int q = threadIdx.x + NT * e;
+        if (q < m) {
+            coarse_taps<BC>(g, q, src[e], w[e]);
+            dg[e] = -90.0 * g.inv12h2 + (double)c[q];
+            b[e] = (double)r[q];
+        } else {
+#pragma unroll
+            for (int t = 0; t < 12; t++) {
+                src[e][t] = 0;
+                w[e][t] = 0.0;
+            }
+            dg[e] = 0.0;
+            b[e] = 0.0;
+        }
+    }
+    // y = A v for the owned cells (v staged in LDS by every thread first)
+    auto apply = [&](const double v[E], double y[E]) {
+#pragma unroll
+        for (int e = 0; e < E; e++) {
+            const int q = threadIdx.x + NT * e;
+            if (q < m) vec[q] = v[e];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; e++) {
+            double s = dg[e] * v[e];
+#pragma unroll
+            for (int t = 0; t < 12; t++) s += w[e][t] * vec[src[e][t]];
+            y[e] = s;
+        }
+        __syncthreads();
+    };
+    double t3[3];
+    t3[0] = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; e++) t3[0] += b[e] * b[e];
+    block_sums<1>(t3, part);
+    const double bb = t3[0];
+    const int q0 = threadIdx.x;
+    if (!(bb > 0.0)) {
+#pragma unroll
+        for (int e = 0; e < E; e++)
+            if (q0 + NT * e < m) x[q0 + NT * e] = T(0);
+        return bb == 0.0;
+    }
+    const double tol2 = 1e-28 * bb;
+    double xv[E], rr[E], p[E], ap[E];
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+        xv[e] = 0.0;
+        rr[e] = b[e];
+    }
+    bool ok = false;
+    if constexpr (BC == kBcPeriodic) {
+        double rz = bb;
+#pragma unroll
+        for (int e = 0; e < E; e++) p[e] = b[e];
+#pragma unroll 1
+        for (int it = 0; it < 2 * m + 32; it++) {
+            apply(p, ap);
+            t3[0] = 0.0;
+#pragma unroll
+            for (int e = 0; e < E; e++) t3[0] += p[e] * ap[e];
+            block_sums<1>(t3, part);
+            if (!(t3[0] != 0.0)) break;
+            const double alpha = rz / t3[0];
+            t3[0] = 0.0;
+#pragma unroll
+            for (int e = 0; e < E; e++) {
+                xv[e] += alpha * p[e];
+                rr[e] -= alpha * ap[e];
+                t3[0] += rr[e] * rr[e];
+            }
+            block_sums<1>(t3, part);
+            if (t3[0] <= tol2) {
+                ok = true;
+                break;
+            }
+            const double beta = t3[0] / rz;
+            rz = t3[0];
+#pragma unroll
+            for (int e = 0; e < E; e++) p[e] = rr[e] + beta * p[e];
+        }
+    } else {
+        double rh[E], v[E], sv[E], tv[E];
+        double rho = 1.0, alpha = 1.0, omega = 1.0;
+#pragma unroll
+        for (int e = 0; e < E; e++) {
+            rh[e] = b[e];
+            p[e] = 0.0;
+            v[e] = 0.0;
+        }
+#pragma unroll 1
+        for (int it = 0; it < 2 * m + 32; it++) {
+            t3[0] = 0.0;
+#pragma unroll
+            for (int e = 0; e < E; e++) t3[0] += rh[e] * rr[e];
+            block_sums<1>(t3, part);
+            const double rho1 = t3[0];
+            if (!(rho1 != 0.0)) break;
+            const double beta = (rho1 / rho) * (alpha / omega);
+#pragma unroll
+            for (int e = 0; e < E; e++) p[e] = rr[e] + beta * (p[e] - omega * v[e]);
+            apply(p, v);
+            t3[0] = 0.0;
+#pragma unroll
+            for (int e = 0; e < E; e++) t3[0] += rh[e] * v[e];
+            block_sums<1>(t3, part);
+            if (!(t3[0] != 0.0)) break;
+            alpha = rho1 / t3[0];
+            t3[0] = 0.0;
+#pragma unroll
+            for (int e = 0; e < E; e++) {
+                sv[e] = rr[e] - alpha * v[e];
+                t3[0] += sv[e] * sv[e];
+            }
+            block_sums<1>(t3, part);
+            if (t3[0] <= tol2) {
+#pragma unroll
+                for (int e = 0; e < E; e++) xv[e] += alpha * p[e];
+                ok = true;
+                break;
+            }
+            apply(sv, tv);
+            t3[0] = t3[1] = 0.0;
+#pragma unroll
+            for (int e = 0; e < E; e++) {
+                t3[0] += tv[e] * sv[e];
+                t3[1] += tv[e] * tv[e];
+            }
+            block_sums<2>(t3, part);
+            if (!(t3[1] > 0.0)) break;
+            omega = t3[0] / t3[1];
+            t3[0] = 0.0;
+#pragma unroll
+            for (int e = 0; e < E; e++) {
+                xv[e] += alpha * p[e] + omega * sv[e];
+                rr[e] = sv[e] - omega * tv[e];
+                t3[0] += rr[e] * rr[e];
+            }
+            rho = rho1;
+            block_sums<1>(t3, part);
+            if (t3[0] <= tol2) {
+                ok = true;
+                break;
+            }
+            if (!(omega != 0.0)) break;
+        }
+    }
+    double tr[E];
+    apply(xv, tr);
+    t3[0] = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+        tr[e] = b[e] - tr[e];
+        t3[0] += tr[e] * tr[e];
+    }
+    block_sums<1>(t3, part);
+    ok = ok && t3[0] <= 1e-24 * bb;
+    if (ok)
+#pragma unroll
+        for (int e = 0; e < E; e++)
+            if (q0 + NT * e < m) x[q0 + NT * e] = (T)xv[e];
+    return ok;
+}
+
+// Coarsest psi levels of more than 64 cells: the block Krylov solve; a system it
+// does not solve raises the singular flag.
+template <int BC, typename T>
+__global__ void __launch_bounds__(kGjWaves *kWave) k_coarse_psi_krylov(Geo g, int m, const T *c, const T *r, T *x,
+                                                                      double *flag)
+{
+    const bool ok = coarse_psi_krylov_block<BC, T>(g, m, c, r, x);
+    if (!ok && threadIdx.x == 0) *flag = 1.0;
+}
+
 // Called by every thread of a block of kGjWaves waves.
 template <int BC, typename T, int M>
 __device__ __forceinline__ void coarse_psi_block_solve(const Geo &g, const T *c, const T *r, T *x, double *flag)
@@ -1084,9 +1454,17 @@ __device__ __forceinline__ void coarse_psi_block_solve(const Geo &g, const T *c,
     __shared__ int piv[2];
     __shared__ int perm[M];
     __shared__ double pdiag[M];
+    __shared__ int krylov_ok;
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int n = g.n;
+    // first the Krylov solve on wave 0 alone; elimination only if it is not accepted
+    if (wave == 0) {
+        const bool ok = coarse_psi_krylov_wave<BC, T, M>(g, c, r, x);
+        if (lane == 0) krylov_ok = ok ? 1 : 0;
+    }
+    __syncthreads();
+    if (krylov_ok) return;
     if (threadIdx.x < M) {
         const int row = threadIdx.x;
         for (int j = 0; j < NC; j++) A[row][j] = 0.0;

@@ -165,3 +165,36 @@ def test_residual_fields_conformal_matter():
     assert rel_err(N(H), Ho) < 1e-12
     assert rel_err(N(M), Mo) < 1e-12
     assert rel_err(N(c), co) < 1e-13
+
+
+@pytest.mark.parametrize("bc", [g.BC_PERIODIC, g.BC_ROBIN])
+@pytest.mark.parametrize("n,levels", [(16, 2), (24, 3), (20, 2), (12, 2)])
+def test_coarse_psi_krylov_sizes(bc, n, levels):
+    """Coarsest psi systems of 6^3 .. 10^3 cells (block conjugate gradients or
+    BiCGSTAB) against the oracle's LU with partial pivoting."""
+    s, po = _ctx(n, levels, bc, momentum=False)
+    nc = n >> (levels - 1)
+    rc = synth.uniform_random(40 + n, (nc,) * 3)
+    cc = -1.0 - synth.uniform_random(41 + n, (nc,) * 3, 0, 2)
+    out = torch.full((nc,) * 3, np.nan, dtype=torch.float64, device=dev())
+    s.kernel_op(g.OP_COARSE_PSI, levels - 1, 0, T(rc), out, None, T(cc))
+    pc = oracle.params(nc, 1, bc=po.bc, length=po.length, origin=tuple(po.origin))
+    ref = oracle.coarse_solve_psi(pc, cc, rc)
+    print(f"coarse psi {nc}^3 bc={bc}: rel err {rel_err(N(out), ref):.2e}")
+    assert rel_err(N(out), ref) < 1e-11
+
+
+@pytest.mark.parametrize("bc", [g.BC_PERIODIC, g.BC_ROBIN])
+def test_coarse_psi_4_indefinite(bc):
+    """A 4^3 coarsest system whose coefficient makes the matrix indefinite: the
+    Krylov solve or, if it is not accepted, the elimination must still give the
+    oracle's answer."""
+    s, po = _ctx(16, 3, bc, momentum=False)
+    rc = synth.uniform_random(50, (4,) * 3)
+    cc = synth.uniform_random(51, (4,) * 3, -20.0, 60.0)
+    out = torch.full((4,) * 3, np.nan, dtype=torch.float64, device=dev())
+    s.kernel_op(g.OP_COARSE_PSI, 2, 0, T(rc), out, None, T(cc))
+    pc = oracle.params(4, 1, bc=po.bc, length=po.length, origin=tuple(po.origin))
+    ref = oracle.coarse_solve_psi(pc, cc, rc)
+    print(f"coarse psi 4^3 indefinite bc={bc}: rel err {rel_err(N(out), ref):.2e}")
+    assert rel_err(N(out), ref) < 1e-10
