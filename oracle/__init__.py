@@ -37,6 +37,8 @@ SRC_PATH = os.path.join(_HERE, "mg_oracle.c")
 
 BC_PERIODIC = 0
 BC_ROBIN = 1
+BC_REFLECT = 2
+BC_EXTRAP = 3
 FLAG_CONFORMAL_MATTER = 1
 
 

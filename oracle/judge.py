@@ -17,6 +17,8 @@ import numpy as np
 
 BC_PERIODIC = 0
 BC_ROBIN = 1
+BC_REFLECT = 2
+BC_EXTRAP = 3
 
 
 class Grid:
@@ -42,6 +44,10 @@ class Grid:
         n = self.n
         if self.bc == BC_PERIODIC:
             return np.pad(a, 2, mode="wrap")
+        if self.bc == BC_REFLECT:   # mirror across each face, edge cell repeated
+            return np.pad(a, 2, mode="symmetric")
+        if self.bc == BC_EXTRAP:    # the cell next to each face continued outwards
+            return np.pad(a, 2, mode="edge")
         ii = np.arange(-2, n + 2)
         cl = np.clip(ii, 0, n - 1)
         inner = a[np.ix_(cl, cl, cl)]
@@ -218,6 +224,8 @@ def _at(g: Grid, a, i, j, k):
     n = g.n
     if g.bc == BC_PERIODIC:
         return a[i % n, j % n, k % n]
+    if g.bc in (BC_REFLECT, BC_EXTRAP):
+        return g.pad(a)[i + 2, j + 2, k + 2]
     ci, cj, ck = np.clip(i, 0, n - 1), np.clip(j, 0, n - 1), np.clip(k, 0, n - 1)
 
     def rad(x, y, z):

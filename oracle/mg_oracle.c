@@ -39,10 +39,13 @@
  *   c   = -6 pi rho_bar psi^-4 - (5 K^2/12) psi^4 - (7/8) A2 psi^-8
  *   M_h = Delta_L,h W - (8 pi S - mean(8 pi S))
  *
- * Boundary conditions (Key features lists periodic among them; the 1/r Robin
- * rule serves the isolated black hole): periodic wrap, or a ghost value
- * a(g) = a(b) |x_b| / |x_g| with b the grid cell nearest to g (coordinates
- * clamped into the grid), radii measured from the puncture position.
+ * Boundary conditions (Key features, "Boundary conditions": extrapolating,
+ * reflective and periodic; the 1/r Robin rule serves the isolated black hole):
+ * periodic wrap; Robin: a ghost value a(g) = a(b) |x_b| / |x_g| with b the grid
+ * cell nearest to g (coordinates clamped into the grid), radii measured from
+ * the puncture position; reflective: the mirror image of the grid across the
+ * boundary face (even parity); extrapolating: zeroth-order extrapolation along
+ * the face normal (each ghost takes the value of the grid cell next to the face).
  *
  * Multigrid (Key features, "Fast": errors reduced across a hierarchy of
  * discretisations): V(nu_pre, nu_post) cycles with double-buffered red-black
@@ -65,6 +68,8 @@
 
 #define OBC_PERIODIC 0
 #define OBC_ROBIN 1
+#define OBC_REFLECT 2
+#define OBC_EXTRAP 3
 #define OMAXLEV 16
 
 /* flags bit 0: conformally rescaled matter (see orc_residuals) */
@@ -127,6 +132,28 @@ static int inside(int n, int i, int j, int k)
     return i >= 0 && i < n && j >= 0 && j < n && k >= 0 && k < n;
 }
 
+/* Reflective and extrapolating rules, one axis at a time: the value at index i
+ * (possibly outside 0..n-1) as a grid value idx[0] with weight w[0]; returns
+ * the number of terms (kept general for rules that combine several cells).
+ *   reflective:    the mirror image across the boundary face (-1 -> 0, -2 -> 1,
+ *                  n -> n-1, n+1 -> n-2), weight 1 (even parity);
+ *   extrapolating: zeroth-order extrapolation along the face normal, every
+ *                  ghost layer taking the value of the grid cell next to the
+ *                  face (-1, -2 -> 0; n, n+1 -> n-1).
+ * A cell outside along several axes applies the rule of each axis in turn. */
+static int axis_terms(int bc, int n, int i, int idx[2], double w[2])
+{
+    if (i >= 0 && i < n) {
+        idx[0] = i;
+    } else if (bc == OBC_REFLECT) {
+        idx[0] = i < 0 ? -1 - i : 2 * n - 1 - i;
+    } else {
+        idx[0] = i < 0 ? 0 : n - 1;
+    }
+    w[0] = 1.0;
+    return 1;
+}
+
 /* Field value at cell (i,j,k), which may lie outside the grid (boundary rule). */
 static double at(const geom *g, const double *a, int i, int j, int k)
 {
@@ -134,6 +161,16 @@ static double at(const geom *g, const double *a, int i, int j, int k)
     if (g->bc == OBC_PERIODIC)
         return a[idx3(n, wrapi(i, n), wrapi(j, n), wrapi(k, n))];
     if (inside(n, i, j, k)) return a[idx3(n, i, j, k)];
+    if (g->bc == OBC_REFLECT || g->bc == OBC_EXTRAP) {
+        int I[2], J[2], K[2];
+        double wi[2], wj[2], wk[2], s = 0.0;
+        int ni = axis_terms(g->bc, n, i, I, wi), nj = axis_terms(g->bc, n, j, J, wj),
+            nk = axis_terms(g->bc, n, k, K, wk);
+        for (int x = 0; x < ni; x++)
+            for (int y = 0; y < nj; y++)
+                for (int z = 0; z < nk; z++) s += wi[x] * wj[y] * wk[z] * a[idx3(n, I[x], J[y], K[z])];
+        return s;
+    }
     int bi = clampi(i, n), bj = clampi(j, n), bk = clampi(k, n);
     return a[idx3(n, bi, bj, bk)] * cell_radius(g, bi, bj, bk) / cell_radius(g, i, j, k);
 }
@@ -146,6 +183,17 @@ static double self_weight(const geom *g, int i, int j, int k, int di, int dj, in
     if (g->bc == OBC_PERIODIC)
         return (wrapi(ii, n) == i && wrapi(jj, n) == j && wrapi(kk, n) == k) ? 1.0 : 0.0;
     if (inside(n, ii, jj, kk)) return (di == 0 && dj == 0 && dk == 0) ? 1.0 : 0.0;
+    if (g->bc == OBC_REFLECT || g->bc == OBC_EXTRAP) {
+        int I[2], J[2], K[2];
+        double wi[2], wj[2], wk[2], s = 0.0;
+        int ni = axis_terms(g->bc, n, ii, I, wi), nj = axis_terms(g->bc, n, jj, J, wj),
+            nk = axis_terms(g->bc, n, kk, K, wk);
+        for (int x = 0; x < ni; x++)
+            for (int y = 0; y < nj; y++)
+                for (int z = 0; z < nk; z++)
+                    if (I[x] == i && J[y] == j && K[z] == k) s += wi[x] * wj[y] * wk[z];
+        return s;
+    }
     int bi = clampi(ii, n), bj = clampi(jj, n), bk = clampi(kk, n);
     if (bi != i || bj != j || bk != k) return 0.0;
     return cell_radius(g, bi, bj, bk) / cell_radius(g, ii, jj, kk);
