@@ -62,7 +62,7 @@ typedef enum mg_status {
     MG_ERR_SINGULAR = 6       /* coarsest-level matrix could not be factorised      */
 } mg_status;
 
-enum { MG_BC_PERIODIC = 0, MG_BC_ROBIN = 1 };
+enum { MG_BC_PERIODIC = 0, MG_BC_ROBIN = 1, MG_BC_REFLECT = 2, MG_BC_EXTRAP = 3 };
 enum { MG_PREC_FP64 = 0, MG_PREC_FP32_IR = 1 };
 enum { MG_EQ_PSI = 1, MG_EQ_W = 2, MG_EQ_BOTH = 3 };
 enum { MG_FLAG_CONFORMAL_MATTER = 1, MG_FLAG_EAGER = 2 };
@@ -73,9 +73,16 @@ enum { MG_FLAG_CONFORMAL_MATTER = 1, MG_FLAG_EAGER = 2 };
  *                 the coarsest must have n_l even and n_l >= 6, the coarsest
  *                 n >> (levels-1) >= 3.
  *  levels         number of multigrid levels (1..16).
- *  bc             MG_BC_PERIODIC, or MG_BC_ROBIN: ghost a(g) = a(b)|x_b|/|x_g|,
- *                 b = grid cell nearest g, radii from puncture_pos.  The
- *                 momentum equation is supported on periodic grids only.
+ *  bc             boundary rule for every field on every level, applied as two
+ *                 ghost layers (Key features, "Boundary conditions": periodic,
+ *                 reflective and extrapolating; the Robin rule serves isolated
+ *                 black holes):
+ *                 MG_BC_PERIODIC: wrap.  MG_BC_ROBIN: ghost a(g) = a(b)|x_b|/|x_g|,
+ *                 b = grid cell nearest g, radii from puncture_pos.
+ *                 MG_BC_REFLECT: mirror image across the face (a(-1) = a(0),
+ *                 a(-2) = a(1); even parity).  MG_BC_EXTRAP: zeroth-order
+ *                 extrapolation along the face normal (a(-1) = a(-2) = a(0)).
+ *                 The momentum equation is supported on periodic grids only.
  *  precision      MG_PREC_FP64: every kernel in FP64.  MG_PREC_FP32_IR: V-cycle
  *                 interior (smoothers, transfers, defects) in FP32 inside FP64
  *                 iterative refinement; residual, update and coarsest solve FP64.

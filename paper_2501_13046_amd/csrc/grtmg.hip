@@ -15,6 +15,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <type_traits>
 
 #include "grtmg.h"
 #include "mg_kernels.hpp"
@@ -58,6 +59,18 @@ struct Carver {
 };
 
 unsigned nblk(int64_t count) { return (unsigned)((count + kBlock - 1) / kBlock); }
+
+// Calls f with a non-periodic boundary rule (Robin, reflective, extrapolating) as a
+// compile-time constant: f(std::integral_constant<int, kBc...>{}).
+template <typename F>
+void with_bc(int bc, F &&f)
+{
+    switch (bc) {
+    case MG_BC_REFLECT: f(std::integral_constant<int, kBcReflect>{}); break;
+    case MG_BC_EXTRAP: f(std::integral_constant<int, kBcExtrap>{}); break;
+    default: f(std::integral_constant<int, kBcRobin>{}); break;
+    }
+}
 
 constexpr int kProbeMax = 4096;
 // Brick depths along x of the tiled kernels: defaults and the candidates the
@@ -135,7 +148,7 @@ mg_status validate(const mg_params *p)
     if (p->n < 3 || p->n > 4096) return MG_ERR_INVALID;
     // cell indices are 32-bit (n^3 < 2^32, n <= 1625)
     if ((double)p->n * p->n * (double)p->n >= 4294967296.0) return MG_ERR_INVALID;
-    if (p->bc != MG_BC_PERIODIC && p->bc != MG_BC_ROBIN) return MG_ERR_INVALID;
+    if (p->bc < MG_BC_PERIODIC || p->bc > MG_BC_EXTRAP) return MG_ERR_INVALID;
     if (p->precision != MG_PREC_FP64 && p->precision != MG_PREC_FP32_IR) return MG_ERR_INVALID;
     if (p->nu_pre < 0 || p->nu_post < 0 || p->nu_pre + p->nu_post < 1 || p->nu_pre > 16 ||
         p->nu_post > 16)
@@ -356,7 +369,10 @@ void coarse_psi(mg_ctx *c, const T *r, T *x)
         if (c->p.bc == MG_BC_PERIODIC)
             launch_coarse_wave<kBcPeriodic, T>(c, l, r, x);
         else
-            launch_coarse_wave<kBcRobin, T>(c, l, r, x);
+            with_bc(c->p.bc, [&](auto bcx) {
+                constexpr int BCX = decltype(bcx)::value;
+                launch_coarse_wave<BCX, T>(c, l, r, x);
+            });
         return;
     }
     if (m <= kKrylovMax) {
@@ -366,8 +382,11 @@ void coarse_psi(mg_ctx *c, const T *r, T *x)
             hipLaunchKernelGGL((k_coarse_psi_krylov<kBcPeriodic, T>), dim3(1), dim3(kGjWaves * kWave), 0, c->s,
                                c->geo[l], m, (const T *)c->pc[l], r, x, c->scal + S_FLAG_PSI);
         else
-            hipLaunchKernelGGL((k_coarse_psi_krylov<kBcRobin, T>), dim3(1), dim3(kGjWaves * kWave), 0, c->s,
-                               c->geo[l], m, (const T *)c->pc[l], r, x, c->scal + S_FLAG_PSI);
+            with_bc(c->p.bc, [&](auto bcx) {
+                constexpr int BCX = decltype(bcx)::value;
+                hipLaunchKernelGGL((k_coarse_psi_krylov<BCX, T>), dim3(1), dim3(kGjWaves * kWave), 0, c->s,
+                                   c->geo[l], m, (const T *)c->pc[l], r, x, c->scal + S_FLAG_PSI);
+            });
         return;
     }
     fill<double>(c->s, c->A_psi, (int64_t)m * m, 0.0);
@@ -375,8 +394,11 @@ void coarse_psi(mg_ctx *c, const T *r, T *x)
         hipLaunchKernelGGL((k_assemble_psi<kBcPeriodic, T>), dim3(nblk(m)), dim3(kBlock), 0, c->s,
                            c->geo[l], (const T *)c->pc[l], c->A_psi);
     else
-        hipLaunchKernelGGL((k_assemble_psi<kBcRobin, T>), dim3(nblk(m)), dim3(kBlock), 0, c->s,
-                           c->geo[l], (const T *)c->pc[l], c->A_psi);
+        with_bc(c->p.bc, [&](auto bcx) {
+            constexpr int BCX = decltype(bcx)::value;
+            hipLaunchKernelGGL((k_assemble_psi<BCX, T>), dim3(nblk(m)), dim3(kBlock), 0, c->s,
+                               c->geo[l], (const T *)c->pc[l], c->A_psi);
+        });
     factor(c->s, c->A_psi, c->aug_psi, c->inv_psi, m, c->scal + S_FLAG_PSI);
     hipLaunchKernelGGL(k_coarse_apply<T>, dim3((m + kApplyRows - 1) / kApplyRows), dim3(kBlock),
                        m * sizeof(double), c->s, (const double *)c->inv_psi, m, r, x, 0);
@@ -417,7 +439,10 @@ void pass_psi(mg_ctx *c, int l, const T *in, T *out, int colour)
         if (c->p.bc == MG_BC_PERIODIC)
             launch_psi_tiled<kBcPeriodic, T>(c->s, g, tm, in, out, r, cf, colour);
         else
-            launch_psi_tiled<kBcRobin, T>(c->s, g, tm, in, out, r, cf, colour);
+            with_bc(c->p.bc, [&](auto bcx) {
+                constexpr int BCX = decltype(bcx)::value;
+                launch_psi_tiled<BCX, T>(c->s, g, tm, in, out, r, cf, colour);
+            });
         return;
     }
     if (c->p.bc == MG_BC_PERIODIC && c->n[l] % 2 == 0)
@@ -427,8 +452,11 @@ void pass_psi(mg_ctx *c, int l, const T *in, T *out, int colour)
         hipLaunchKernelGGL((k_pass_psi<kBcPeriodic, T>), dim3(nb), dim3(kBlock), 0, c->s, g, in, out,
                            (const T *)c->pr[l], (const T *)c->pc[l], colour);
     else
-        hipLaunchKernelGGL((k_pass_psi<kBcRobin, T>), dim3(nb), dim3(kBlock), 0, c->s, g, in, out,
-                           (const T *)c->pr[l], (const T *)c->pc[l], colour);
+        with_bc(c->p.bc, [&](auto bcx) {
+            constexpr int BCX = decltype(bcx)::value;
+            hipLaunchKernelGGL((k_pass_psi<BCX, T>), dim3(nb), dim3(kBlock), 0, c->s, g, in, out,
+                               (const T *)c->pr[l], (const T *)c->pc[l], colour);
+        });
 }
 
 template <typename T>
@@ -455,16 +483,22 @@ void defect_restrict_psi(mg_ctx *c, int l, const T *d, const T *r, const T *cf, 
             hipLaunchKernelGGL((k_defect_restrict_psi_fine<kBcPeriodic, T>), dim3(nb), dim3(kBlock), 0, c->s, g, d, r,
                                cf, rc, cc, d1, gc);
         else
-            hipLaunchKernelGGL((k_defect_restrict_psi_fine<kBcRobin, T>), dim3(nb), dim3(kBlock), 0, c->s, g, d, r,
-                               cf, rc, cc, d1, gc);
+            with_bc(c->p.bc, [&](auto bcx) {
+                constexpr int BCX = decltype(bcx)::value;
+                hipLaunchKernelGGL((k_defect_restrict_psi_fine<BCX, T>), dim3(nb), dim3(kBlock), 0, c->s, g, d, r,
+                                   cf, rc, cc, d1, gc);
+            });
     } else {
         const unsigned nb = nblk(c->cells[l + 1]);
         if (c->p.bc == MG_BC_PERIODIC)
             hipLaunchKernelGGL((k_defect_restrict_psi<kBcPeriodic, T>), dim3(nb), dim3(kBlock), 0, c->s, g, d, r, cf,
                                rc, cc, d1, gc);
         else
-            hipLaunchKernelGGL((k_defect_restrict_psi<kBcRobin, T>), dim3(nb), dim3(kBlock), 0, c->s, g, d, r, cf,
-                               rc, cc, d1, gc);
+            with_bc(c->p.bc, [&](auto bcx) {
+                constexpr int BCX = decltype(bcx)::value;
+                hipLaunchKernelGGL((k_defect_restrict_psi<BCX, T>), dim3(nb), dim3(kBlock), 0, c->s, g, d, r, cf,
+                                   rc, cc, d1, gc);
+            });
     }
 }
 
@@ -501,8 +535,11 @@ void prolong_add(mg_ctx *c, int lc, const T *coarse, T *fine, int ncomp)
         hipLaunchKernelGGL(k_prolong_add_pairs<T>, dim3(nblk(c->cells[lc - 1] / 2)), dim3(kBlock), 0, c->s, gc,
                            coarse, fine, ncomp);
     else
-        hipLaunchKernelGGL((k_prolong_add<kBcRobin, T>), dim3(nb), dim3(kBlock), 0, c->s, gc, coarse,
-                           fine, ncomp);
+        with_bc(c->p.bc, [&](auto bcx) {
+            constexpr int BCX = decltype(bcx)::value;
+            hipLaunchKernelGGL((k_prolong_add<BCX, T>), dim3(nb), dim3(kBlock), 0, c->s, gc, coarse,
+                               fine, ncomp);
+        });
 }
 
 // After the residual wrote the finest c: restrict c level by level and, when
@@ -531,8 +568,11 @@ void restrict_coefficients(mg_ctx *c)
         hipLaunchKernelGGL((k_assemble_psi<kBcPeriodic, T>), dim3(nblk(m)), dim3(kBlock), 0, c->s, c->geo[l],
                            (const T *)c->pc[l], c->A_psi);
     else
-        hipLaunchKernelGGL((k_assemble_psi<kBcRobin, T>), dim3(nblk(m)), dim3(kBlock), 0, c->s, c->geo[l],
-                           (const T *)c->pc[l], c->A_psi);
+        with_bc(c->p.bc, [&](auto bcx) {
+            constexpr int BCX = decltype(bcx)::value;
+            hipLaunchKernelGGL((k_assemble_psi<BCX, T>), dim3(nblk(m)), dim3(kBlock), 0, c->s, c->geo[l],
+                               (const T *)c->pc[l], c->A_psi);
+        });
     factor(c->s, c->A_psi, c->aug_psi, c->inv_psi, m, c->scal + S_FLAG_PSI);
 }
 
@@ -566,11 +606,14 @@ void tail_psi(mg_ctx *c)
         default: hipLaunchKernelGGL((k_tail_psi<kBcPeriodic, T, 64>), g1, blk, 0, c->s, a); break;
         }
     } else {
-        switch (c->m_psi) {
-        case 8: hipLaunchKernelGGL((k_tail_psi<kBcRobin, T, 8>), g1, blk, 0, c->s, a); break;
-        case 27: hipLaunchKernelGGL((k_tail_psi<kBcRobin, T, 27>), g1, blk, 0, c->s, a); break;
-        default: hipLaunchKernelGGL((k_tail_psi<kBcRobin, T, 64>), g1, blk, 0, c->s, a); break;
-        }
+        with_bc(c->p.bc, [&](auto bcx) {
+            constexpr int BCX = decltype(bcx)::value;
+            switch (c->m_psi) {
+            case 8: hipLaunchKernelGGL((k_tail_psi<BCX, T, 8>), g1, blk, 0, c->s, a); break;
+            case 27: hipLaunchKernelGGL((k_tail_psi<BCX, T, 27>), g1, blk, 0, c->s, a); break;
+            default: hipLaunchKernelGGL((k_tail_psi<BCX, T, 64>), g1, blk, 0, c->s, a); break;
+            }
+        });
     }
 }
 
@@ -774,11 +817,17 @@ void residual(mg_ctx *c, const double *u, const double *W, bool want_M, double *
             if (c->p.bc == MG_BC_PERIODIC)
                 launch_residual_tiled<kBcPeriodic, T>(c->s, c->geo[0], tm, a, W != nullptr);
             else
-                launch_residual_tiled<kBcRobin, T>(c->s, c->geo[0], tm, a, W != nullptr);
+                with_bc(c->p.bc, [&](auto bcx) {
+                    constexpr int BCX = decltype(bcx)::value;
+                    launch_residual_tiled<BCX, T>(c->s, c->geo[0], tm, a, W != nullptr);
+                });
         } else if (c->p.bc == MG_BC_PERIODIC)
             hipLaunchKernelGGL((k_residual<kBcPeriodic, T>), dim3(nb), dim3(kBlock), 0, c->s, c->geo[0], a);
         else
-            hipLaunchKernelGGL((k_residual<kBcRobin, T>), dim3(nb), dim3(kBlock), 0, c->s, c->geo[0], a);
+            with_bc(c->p.bc, [&](auto bcx) {
+                constexpr int BCX = decltype(bcx)::value;
+                hipLaunchKernelGGL((k_residual<BCX, T>), dim3(nb), dim3(kBlock), 0, c->s, c->geo[0], a);
+            });
     }
     if (norms)
         hipLaunchKernelGGL(k_reduce_final<4>, dim3(1), dim3(kBlock), 0, c->s, (const double *)c->part, nb,
@@ -2101,15 +2150,18 @@ mg_status mg_interp_cubic(const mg_params *pc, const double *d_coarse, double *d
 {
     if (!pc || pc->n < 2 || pc->n > 2048 || !(pc->length > 0.0) || !d_coarse || !d_fine)
         return MG_ERR_INVALID;
-    if (pc->bc != MG_BC_PERIODIC && pc->bc != MG_BC_ROBIN) return MG_ERR_INVALID;
+    if (pc->bc < MG_BC_PERIODIC || pc->bc > MG_BC_EXTRAP) return MG_ERR_INVALID;
     const Geo gc = make_geo(pc->n, pc->bc, pc->length, pc->origin, pc->puncture_pos);
     const int64_t mf = 8 * (int64_t)pc->n * pc->n * pc->n;
     if (pc->bc == MG_BC_PERIODIC)
         hipLaunchKernelGGL(k_interp_cubic<kBcPeriodic>, dim3(nblk(mf)), dim3(kBlock), 0, (hipStream_t)stream,
                            gc, d_coarse, d_fine);
     else
-        hipLaunchKernelGGL(k_interp_cubic<kBcRobin>, dim3(nblk(mf)), dim3(kBlock), 0, (hipStream_t)stream, gc,
-                           d_coarse, d_fine);
+        with_bc(pc->bc, [&](auto bcx) {
+            constexpr int BCX = decltype(bcx)::value;
+            hipLaunchKernelGGL(k_interp_cubic<BCX>, dim3(nblk(mf)), dim3(kBlock), 0, (hipStream_t)stream, gc,
+                               d_coarse, d_fine);
+        });
     return hip_status();
 }
 
@@ -2136,7 +2188,10 @@ mg_status mg_fmg_start(mg_ctx *cc, mg_ctx *cf, double *d_uc, double *d_Wc, doubl
         if (a.bc == MG_BC_PERIODIC)
             hipLaunchKernelGGL(k_interp_cubic<kBcPeriodic>, dim3(nblk(mf)), dim3(kBlock), 0, cf->s, gc, src, dst);
         else
-            hipLaunchKernelGGL(k_interp_cubic<kBcRobin>, dim3(nblk(mf)), dim3(kBlock), 0, cf->s, gc, src, dst);
+            with_bc(a.bc, [&](auto bcx) {
+                constexpr int BCX = decltype(bcx)::value;
+                hipLaunchKernelGGL(k_interp_cubic<BCX>, dim3(nblk(mf)), dim3(kBlock), 0, cf->s, gc, src, dst);
+            });
     }
     leave(cf);
     if (hip_status() != MG_OK) return MG_ERR_HIP;

@@ -20,6 +20,8 @@ constexpr int kBlock = 256;
 constexpr int kWave = 64;
 constexpr int kBcPeriodic = 0;
 constexpr int kBcRobin = 1;
+constexpr int kBcReflect = 2; // mirror image across each boundary face (even parity)
+constexpr int kBcExtrap = 3;  // zeroth-order extrapolation along the face normal
 
 struct Geo {
     int n;
@@ -65,6 +67,45 @@ __device__ __forceinline__ double cell_radius(const Geo &g, int i, int j, int k)
 __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 __device__ __forceinline__ int clampc(int i, int n) { return i < 0 ? 0 : (i >= n ? n - 1 : i); }
 
+// Cell index that a position i (possibly a ghost, at most two cells outside) reads
+// along one axis under the mirror rule (-1 -> 0, -2 -> 1, n -> n-1, n+1 -> n-2).
+__device__ __forceinline__ int mirror(int i, int n) { return i < 0 ? -1 - i : (i >= n ? 2 * n - 1 - i : i); }
+
+// Grid cell (bi, bj, bk) and weight whose product gives the boundary-ruled value
+// at (i, j, k): the cell itself inside the grid; outside it, the periodic image
+// (weight 1), the nearest grid cell scaled by |x_b| / |x_g| (Robin), the mirror
+// image (reflective, weight 1) or the nearest grid cell (extrapolating, weight 1).
+template <int BC>
+__device__ __forceinline__ double ghost_source(const Geo &g, int i, int j, int k, int &bi, int &bj, int &bk)
+{
+    const int n = g.n;
+    if constexpr (BC == kBcPeriodic) {
+        bi = wrap(i, n);
+        bj = wrap(j, n);
+        bk = wrap(k, n);
+        return 1.0;
+    } else {
+        if ((unsigned)i < (unsigned)n && (unsigned)j < (unsigned)n && (unsigned)k < (unsigned)n) {
+            bi = i;
+            bj = j;
+            bk = k;
+            return 1.0;
+        }
+        if constexpr (BC == kBcReflect) {
+            bi = mirror(i, n);
+            bj = mirror(j, n);
+            bk = mirror(k, n);
+            return 1.0;
+        } else {
+            bi = clampc(i, n);
+            bj = clampc(j, n);
+            bk = clampc(k, n);
+            if constexpr (BC == kBcRobin) return cell_radius(g, bi, bj, bk) / cell_radius(g, i, j, k);
+            return 1.0;
+        }
+    }
+}
+
 // Read-only field accessor with the boundary rule applied.
 template <int BC, typename T>
 struct Acc {
@@ -78,9 +119,15 @@ struct Acc {
         } else {
             if ((unsigned)i < (unsigned)n && (unsigned)j < (unsigned)n && (unsigned)k < (unsigned)n)
                 return a[lidx(n, i, j, k)];
-            int bi = clampc(i, n), bj = clampc(j, n), bk = clampc(k, n);
-            double v = (double)a[lidx(n, bi, bj, bk)] * cell_radius(g, bi, bj, bk);
-            return (T)(v / cell_radius(g, i, j, k));
+            if constexpr (BC == kBcRobin) {
+                int bi = clampc(i, n), bj = clampc(j, n), bk = clampc(k, n);
+                double v = (double)a[lidx(n, bi, bj, bk)] * cell_radius(g, bi, bj, bk);
+                return (T)(v / cell_radius(g, i, j, k));
+            } else if constexpr (BC == kBcReflect) {
+                return a[lidx(n, mirror(i, n), mirror(j, n), mirror(k, n))];
+            } else {
+                return a[lidx(n, clampc(i, n), clampc(j, n), clampc(k, n))];
+            }
         }
     }
 };
@@ -91,17 +138,9 @@ template <int BC>
 __device__ __forceinline__ double self_weight(const Geo &g, int i, int j, int k, int di, int dj,
                                               int dk)
 {
-    const int n = g.n;
-    int ii = i + di, jj = j + dj, kk = k + dk;
-    if constexpr (BC == kBcPeriodic) {
-        return (wrap(ii, n) == i && wrap(jj, n) == j && wrap(kk, n) == k) ? 1.0 : 0.0;
-    } else {
-        if ((unsigned)ii < (unsigned)n && (unsigned)jj < (unsigned)n && (unsigned)kk < (unsigned)n)
-            return (di == 0 && dj == 0 && dk == 0) ? 1.0 : 0.0;
-        int bi = clampc(ii, n), bj = clampc(jj, n), bk = clampc(kk, n);
-        if (bi != i || bj != j || bk != k) return 0.0;
-        return cell_radius(g, bi, bj, bk) / cell_radius(g, ii, jj, kk);
-    }
+    int bi, bj, bk;
+    const double w = ghost_source<BC>(g, i + di, j + dj, k + dk, bi, bj, bk);
+    return (bi == i && bj == j && bk == k) ? w : 0.0;
 }
 
 // ---- stencils (unscaled sums; the caller multiplies by 1/(12h) or 1/(12h^2)) ----

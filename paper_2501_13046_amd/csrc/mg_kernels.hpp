@@ -824,21 +824,10 @@ __global__ void __launch_bounds__(kBlock) k_assemble_psi(Geo g, const T *c, doub
     const double w[5] = {-1.0, 16.0, -30.0, 16.0, -1.0};
     for (int ax = 0; ax < 3; ax++)
         for (int d = -2; d <= 2; d++) {
-            int ii = i + (ax == 0 ? d : 0), jj = j + (ax == 1 ? d : 0), kk = k + (ax == 2 ? d : 0);
-            double fac = 1.0;
-            if (BC == kBcPeriodic) {
-                ii = wrap(ii, n);
-                jj = wrap(jj, n);
-                kk = wrap(kk, n);
-            } else if (!((unsigned)ii < (unsigned)n && (unsigned)jj < (unsigned)n &&
-                         (unsigned)kk < (unsigned)n)) {
-                int bi = clampc(ii, n), bj = clampc(jj, n), bk = clampc(kk, n);
-                fac = cell_radius(g, bi, bj, bk) / cell_radius(g, ii, jj, kk);
-                ii = bi;
-                jj = bj;
-                kk = bk;
-            }
-            A[row * m + lidx(n, ii, jj, kk)] += w[d + 2] * g.inv12h2 * fac;
+            int bi, bj, bk;
+            const double fac =
+                ghost_source<BC>(g, i + (ax == 0 ? d : 0), j + (ax == 1 ? d : 0), k + (ax == 2 ? d : 0), bi, bj, bk);
+            A[row * m + lidx(n, bi, bj, bk)] += w[d + 2] * g.inv12h2 * fac;
         }
     A[row * m + row] += (double)c[row];
 }
@@ -1081,8 +1070,7 @@ __device__ __forceinline__ double readlane_f64(double x, int l)
 // solves by elimination.
 //
 // The 12 off-centre taps of L_h at a cell, as (source cell, weight) pairs with the
-// boundary rule folded in: a periodic tap wraps, a Robin ghost tap reads the grid
-// cell b nearest the ghost with weight |x_b| / |x_g|.  A tap may name the cell itself.
+// boundary rule folded in (ghost_source).  A tap may name the cell itself.
 // ---------------------------------------------------------------------------------------
 template <int BC>
 __device__ __forceinline__ void coarse_taps(const Geo &g, int q, int src[12], double w[12])
@@ -1096,20 +1084,10 @@ __device__ __forceinline__ void coarse_taps(const Geo &g, int q, int src[12], do
     for (int ax = 0; ax < 3; ax++)
 #pragma unroll
         for (int e = 0; e < 4; e++, t++) {
-            int ii = i + (ax == 0 ? dof[e] : 0), jj = j + (ax == 1 ? dof[e] : 0), kk = k + (ax == 2 ? dof[e] : 0);
-            double fac = 1.0;
-            if constexpr (BC == kBcPeriodic) {
-                ii = wrap(ii, n);
-                jj = wrap(jj, n);
-                kk = wrap(kk, n);
-            } else if (!((unsigned)ii < (unsigned)n && (unsigned)jj < (unsigned)n && (unsigned)kk < (unsigned)n)) {
-                const int bi = clampc(ii, n), bj = clampc(jj, n), bk = clampc(kk, n);
-                fac = cell_radius(g, bi, bj, bk) / cell_radius(g, ii, jj, kk);
-                ii = bi;
-                jj = bj;
-                kk = bk;
-            }
-            src[t] = (ii * n + jj) * n + kk;
+            int bi, bj, bk;
+            const double fac = ghost_source<BC>(g, i + (ax == 0 ? dof[e] : 0), j + (ax == 1 ? dof[e] : 0),
+                                                k + (ax == 2 ? dof[e] : 0), bi, bj, bk);
+            src[t] = (bi * n + bj) * n + bk;
             w[t] = wt[e] * g.inv12h2 * fac;
         }
 }
@@ -1472,20 +1450,10 @@ __device__ __forceinline__ void coarse_psi_block_solve(const Geo &g, const T *c,
         const double wt[5] = {-1.0, 16.0, -30.0, 16.0, -1.0};
         for (int ax = 0; ax < 3; ax++)
             for (int d = -2; d <= 2; d++) {
-                int ii = i + (ax == 0 ? d : 0), jj = j + (ax == 1 ? d : 0), kk = k + (ax == 2 ? d : 0);
-                double fac_bc = 1.0;
-                if (BC == kBcPeriodic) {
-                    ii = wrap(ii, n);
-                    jj = wrap(jj, n);
-                    kk = wrap(kk, n);
-                } else if (!((unsigned)ii < (unsigned)n && (unsigned)jj < (unsigned)n && (unsigned)kk < (unsigned)n)) {
-                    int bi = clampc(ii, n), bj = clampc(jj, n), bk = clampc(kk, n);
-                    fac_bc = cell_radius(g, bi, bj, bk) / cell_radius(g, ii, jj, kk);
-                    ii = bi;
-                    jj = bj;
-                    kk = bk;
-                }
-                A[row][(ii * n + jj) * n + kk] += wt[d + 2] * g.inv12h2 * fac_bc;
+                int bi, bj, bk;
+                const double fac_bc = ghost_source<BC>(g, i + (ax == 0 ? d : 0), j + (ax == 1 ? d : 0),
+                                                       k + (ax == 2 ? d : 0), bi, bj, bk);
+                A[row][(bi * n + bj) * n + bk] += wt[d + 2] * g.inv12h2 * fac_bc;
             }
         A[row][row] += (double)c[row];
         A[row][M] = (double)r[row];

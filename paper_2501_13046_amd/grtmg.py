@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_PKG, "libgrtmg.so")
 
 MG_OK, MG_ERR_INVALID, MG_ERR_WORKSPACE, MG_ERR_HIP = 0, 1, 2, 3
 MG_ERR_NOT_CONVERGED, MG_ERR_DIVERGED, MG_ERR_SINGULAR = 4, 5, 6
-BC_PERIODIC, BC_ROBIN = 0, 1
+BC_PERIODIC, BC_ROBIN, BC_REFLECT, BC_EXTRAP = 0, 1, 2, 3
 PREC_FP64, PREC_FP32_IR = 0, 1
 EQ_PSI, EQ_W, EQ_BOTH = 1, 2, 3
 FLAG_CONFORMAL_MATTER = 1

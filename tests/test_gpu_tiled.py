@@ -15,7 +15,7 @@ n = 128
 
 
 @pytest.mark.parametrize("precision", [g.PREC_FP64, g.PREC_FP32_IR])
-@pytest.mark.parametrize("bc", [g.BC_PERIODIC, g.BC_ROBIN])
+@pytest.mark.parametrize("bc", [g.BC_PERIODIC, g.BC_ROBIN, g.BC_REFLECT, g.BC_EXTRAP])
 def test_tiled_psi_pass(precision, bc):
     L, org = (1.0, (0.0,) * 3) if bc == g.BC_PERIODIC else (64.0, (-32.0,) * 3)
     p = g.params(n, 6, bc=bc, precision=precision, length=L, origin=org)
@@ -142,5 +142,25 @@ def test_tiled_residual_robin_puncture():
     H, _, c = s.residual_fields(T(u), None, want_M=False)
     z3 = np.zeros((3, n, n, n))
     Ho, _, co = oracle.residuals(po, u, z3, rho5, rho1, z3)
+    assert rel_err(N(H), Ho) < 1e-12
+    assert rel_err(N(c), co) < 1e-13
+
+
+@pytest.mark.parametrize("bc", [g.BC_REFLECT, g.BC_EXTRAP])
+@pytest.mark.parametrize("depth", [2, 4])
+def test_tiled_residual_reflect_extrap(bc, depth):
+    """Residual bricks under the reflective and extrapolating rules, frozen W."""
+    K = 1.7
+    p = g.params(n, 6, bc=bc, K=K)
+    po = oracle.params(n, 6, bc=bc, K=K)
+    u = synth.uniform_random(80, (n,) * 3, -0.05, 0.05)
+    W = synth.uniform_random(81, (3, n, n, n), -0.01, 0.01)
+    rho5 = synth.uniform_random(82, (n,) * 3, 0, 0.5)
+    rho1 = synth.uniform_random(83, (n,) * 3, 0, 0.5)
+    s = g.Solver(p, T(rho5), T(rho1))
+    s.set_tile(g.TUNE_RESIDUAL, 0, depth)
+    H, _, c = s.residual_fields(T(u), T(W), want_M=False)
+    z3 = np.zeros((3, n, n, n))
+    Ho, _, co = oracle.residuals(po, u, W, rho5, rho1, z3)
     assert rel_err(N(H), Ho) < 1e-12
     assert rel_err(N(c), co) < 1e-13
