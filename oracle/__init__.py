@@ -57,7 +57,8 @@ class OrcParams(C.Structure):
                 ("nu_pre", C.c_int32), ("nu_post", C.c_int32),
                 ("solve_momentum", C.c_int32), ("flags", C.c_int32), ("pad1", C.c_int32),
                 ("length", C.c_double), ("origin", C.c_double * 3), ("K", C.c_double),
-                ("puncture_mass", C.c_double), ("puncture_pos", C.c_double * 3)]
+                ("puncture_mass", C.c_double), ("puncture_pos", C.c_double * 3),
+                ("bg_psi0", C.c_void_p), ("bg_A2", C.c_void_p)]
 
 
 _lib = None
@@ -130,6 +131,8 @@ def _bind(L):
         "orc_shell_sources": [pp, C.c_double, C.c_double, C.c_double, C.c_double,
                               dp, dp, dp],
         "orc_num_threads": [],
+        "orc_bowen_york_tensor": [ip, dp, dp, dp],
+        "orc_bowen_york": [pp, ip, dp, dp, dp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -147,10 +150,26 @@ def _ptr(a):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 
 
+class _Params(OrcParams):
+    """OrcParams that keeps the optional background arrays alive."""
+    _keep = None
+
+
 def params(n, levels=1, bc=BC_PERIODIC, length=1.0, origin=(0.0, 0.0, 0.0), K=0.0,
            nu_pre=2, nu_post=2, solve_momentum=False, puncture_mass=0.0,
-           puncture_pos=(0.0, 0.0, 0.0), conformal_matter=False) -> OrcParams:
-    p = OrcParams()
+           puncture_pos=(0.0, 0.0, 0.0), conformal_matter=False, bg_psi0=None,
+           bg_A2=None) -> OrcParams:
+    """bg_psi0, bg_A2: optional n^3 fields (several punctures: psi0 in place of
+    1 + M/(2r); Bowen-York: A2 of the analytic extrinsic curvature)."""
+    p = _Params()
+    keep = []
+    for name, arr in (("bg_psi0", bg_psi0), ("bg_A2", bg_A2)):
+        if arr is not None:
+            arr = np.ascontiguousarray(arr, dtype=np.float64)
+            assert arr.shape == (n, n, n)
+            keep.append(arr)
+            setattr(p, name, arr.ctypes.data)
+    p._keep = keep
     p.flags = FLAG_CONFORMAL_MATTER if conformal_matter else 0
     p.n, p.levels, p.bc = n, levels, bc
     p.nu_pre, p.nu_post = nu_pre, nu_post
@@ -336,6 +355,25 @@ def solve(p, u, W, rho5, rho1, S, f=None, tol=1e-10, max_outer=60):
     st = lib().orc_solve(C.byref(p), _ptr(u), _ptr(W), _ptr(rho5), _ptr(rho1), _ptr(S), _ptr(f),
                          tol, max_outer, _ptr(hist), max_outer + 1, C.byref(it), _ptr(nr))
     return SolveResult(st, it.value, hist[: min(it.value + 1, max_outer + 1)], nr)
+
+
+# ---- Bowen-York punctures -----------------------------------------------------------
+
+def bowen_york_tensor(table, x):
+    """Abar_ij (xx, xy, xz, yy, yz, zz) at point x; table rows (m, C[3], P[3], S[3])."""
+    tab = np.ascontiguousarray(table, dtype=np.float64).reshape(-1, 10)
+    out = np.zeros(6)
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    lib().orc_bowen_york_tensor(len(tab), _ptr(tab), _ptr(xx), _ptr(out))
+    return out
+
+
+def bowen_york(p, table):
+    """psi0 = 1 + sum m/(2r) and A2 = Abar_ij Abar_ij at the cell centres of p's grid."""
+    tab = np.ascontiguousarray(table, dtype=np.float64).reshape(-1, 10)
+    psi0, A2 = _z(p.n), _z(p.n)
+    lib().orc_bowen_york(C.byref(p), len(tab), _ptr(tab), _ptr(psi0), _ptr(A2))
+    return psi0, A2
 
 
 def num_threads() -> int:

@@ -133,12 +133,16 @@ def psi0(g: Grid, puncture_mass):
 
 
 def residuals(g: Grid, u, W, rho5, rho1, S, K, puncture_mass=0.0, f=None,
-              conformal_matter=False):
+              conformal_matter=False, psi0_field=None, A2_bg=None):
     """H_h, mean-free M_h (periodic) and c = dH_h/dpsi, as whole arrays.
     conformal_matter: sources are rho_bar = psi^8 rho (= rho5 + rho1) and
-    S_bar = psi^6 S, entering as 2 pi rho_bar psi^-3 and 8 pi S_bar."""
-    psi = psi0(g, puncture_mass) + u
+    S_bar = psi^6 S, entering as 2 pi rho_bar psi^-3 and 8 pi S_bar.
+    psi0_field replaces 1 + M/(2r) (several punctures); A2_bg is added to the
+    A2 of W (an analytic extrinsic curvature such as Bowen-York's)."""
+    psi = (psi0(g, puncture_mass) if psi0_field is None else psi0_field) + u
     a2 = A2(g, W) if W is not None else 0.0
+    if A2_bg is not None:
+        a2 = a2 + A2_bg
     K2 = K * K
     if conformal_matter:
         rbar = rho5 + rho1

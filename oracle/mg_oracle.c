@@ -78,6 +78,11 @@
 typedef struct {
     int32_t n, levels, bc, nu_pre, nu_post, solve_momentum, flags, pad1;
     double length, origin[3], K, puncture_mass, puncture_pos[3];
+    /* optional fields on the finest grid (NULL: not used): psi0 replacing
+     * 1 + M/(2r) (several punctures), and Abar_ij Abar_ij of an analytic
+     * traceless extrinsic curvature added to the one of W (Bowen-York data,
+     * with W = 0) */
+    const double *bg_psi0, *bg_A2;
 } orc_params;
 
 typedef struct {
@@ -290,6 +295,7 @@ static double deltaL_diag(const geom *g, int i, int j, int k, int a)
 
 static double psi0_at(const orc_params *p, const geom *g, int i, int j, int k)
 {
+    if (p->bg_psi0) return p->bg_psi0[idx3(g->n, i, j, k)];
     if (p->puncture_mass > 0.0) return 1.0 + p->puncture_mass / (2.0 * cell_radius(g, i, j, k));
     return 1.0;
 }
@@ -343,7 +349,7 @@ void orc_residuals(const orc_params *p, const double *u, const double *W, const 
                 for (int k = 0; k < n; k++) {
                     long q = idx3(n, i, j, k);
                     double psi = psi0_at(p, &g, i, j, k) + u[q];
-                    double A2 = A2_at(&g, W, i, j, k);
+                    double A2 = A2_at(&g, W, i, j, k) + (p->bg_A2 ? p->bg_A2[q] : 0.0);
                     double psi4 = pow(psi, 4), psi5 = pow(psi, 5);
                     double matter, dmatter; /* matter term of H and its psi-derivative */
                     if (p->flags & OFLAG_CONFORMAL_MATTER) {
@@ -1002,6 +1008,70 @@ void orc_shell_sources(const orc_params *p, double amp, double r0, double width2
                 rho5[c] = 0.5 * mass * mass * phi * phi;
                 rho1[c] = 0.5 * (dphi[0] * dphi[0] + dphi[1] * dphi[1] + dphi[2] * dphi[2]);
                 for (int a = 0; a < 3; a++) S[a * m + c] = 0.0;
+            }
+}
+
+/*
+ * Bowen-York data for punctures (Key features, "Flexibility": binary black holes
+ * with boosted and/or spinning punctures; the momentum constraint with K = 0 and
+ * no matter is solved analytically, leaving the Hamiltonian constraint for u).
+ * tab: 10 doubles per puncture: mass m, centre C[3], momentum P[3], spin S[3].
+ * With n = (x - C)/r, r = |x - C|, the traceless extrinsic curvature is the sum
+ * over punctures of
+ *   (3 / (2 r^2)) [P_i n_j + P_j n_i - (delta_ij - n_i n_j) P.n]
+ *   + (3 / r^3) [(S x n)_i n_j + (S x n)_j n_i],
+ * and psi0 = 1 + sum m / (2 r).
+ * orc_bowen_york_tensor: the six components xx, xy, xz, yy, yz, zz at point x.
+ * orc_bowen_york: psi0 and A2 = Abar_ij Abar_ij at every cell centre.
+ */
+void orc_bowen_york_tensor(int count, const double *tab, const double x[3], double out[6])
+{
+    double A[3][3] = {{0.0}};
+    for (int q = 0; q < count; q++) {
+        const double *t = tab + 10 * q;
+        double d[3] = {x[0] - t[1], x[1] - t[2], x[2] - t[3]};
+        double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        double nv[3] = {d[0] / r, d[1] / r, d[2] / r};
+        const double *P = t + 4, *S = t + 7;
+        double pn = P[0] * nv[0] + P[1] * nv[1] + P[2] * nv[2];
+        double sxn[3] = {S[1] * nv[2] - S[2] * nv[1], S[2] * nv[0] - S[0] * nv[2], S[0] * nv[1] - S[1] * nv[0]};
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) {
+                double boost = P[a] * nv[b] + P[b] * nv[a] - ((a == b ? 1.0 : 0.0) - nv[a] * nv[b]) * pn;
+                double spin = sxn[a] * nv[b] + sxn[b] * nv[a];
+                A[a][b] += 1.5 / (r * r) * boost + 3.0 / (r * r * r) * spin;
+            }
+    }
+    out[0] = A[0][0];
+    out[1] = A[0][1];
+    out[2] = A[0][2];
+    out[3] = A[1][1];
+    out[4] = A[1][2];
+    out[5] = A[2][2];
+}
+
+void orc_bowen_york(const orc_params *p, int count, const double *tab, double *psi0, double *A2)
+{
+    int n = p->n;
+    geom g = make_geom(p, n);
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n; i++)
+        for (int j = 0; j < n; j++)
+            for (int k = 0; k < n; k++) {
+                double x[3], A[6];
+                x[0] = g.org[0] + (i + 0.5) * g.h;
+                x[1] = g.org[1] + (j + 0.5) * g.h;
+                x[2] = g.org[2] + (k + 0.5) * g.h;
+                orc_bowen_york_tensor(count, tab, x, A);
+                long c = idx3(n, i, j, k);
+                A2[c] = A[0] * A[0] + A[3] * A[3] + A[5] * A[5] + 2.0 * (A[1] * A[1] + A[2] * A[2] + A[4] * A[4]);
+                double s = 1.0;
+                for (int q = 0; q < count; q++) {
+                    const double *t = tab + 10 * q;
+                    double d0 = x[0] - t[1], d1 = x[1] - t[2], d2 = x[2] - t[3];
+                    s += t[0] / (2.0 * sqrt(d0 * d0 + d1 * d1 + d2 * d2));
+                }
+                psi0[c] = s;
             }
 }
 
