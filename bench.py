@@ -16,8 +16,8 @@ The JSON line also carries the roofline of the dominant kernel, the finest-level
 residual (its launches inside a real solve timed with HIP event pairs that the
 dispatches record; algorithmic bytes of its two forms; HBM traffic from the
 committed counter summary while the kernel sources match it), the same figures
-for the finest W smoother pass, two further workloads (the 256^3 puncture with
-a scalar shell, the 96-instance parameter scan) and the CPU oracle solving the
+for the finest W smoother pass, three further workloads (the 256^3 puncture with
+a scalar shell, a 256^3 Bowen-York binary, the 96-instance parameter scan) and the CPU oracle solving the
 benchmarked workload to the same tolerance on the host cores.
 
     python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-fp64] [--no-extra]
@@ -99,6 +99,37 @@ def bench_puncture_256(g, synth, dev, args, log):
                outer_iters=rep["outer_iters"], h_rms=rep["h_rms"], h_max=rep["h_max"],
                autotuned=[{"family": e["family"], "level": e["level"], "depth": e["chosen"]} for e in tune])
     log(f"[bench] puncture_shell_256 mixed: {out['seconds'] * 1e3:.2f} ms/solve (median of {len(runs)}), "
+        f"outer={rep['outer_iters']} rms H={rep['h_rms']:.2e}")
+    s.close()
+    return out
+
+
+def bench_bowen_york_256(g, synth, dev, args, log):
+    """Binary of boosted, spinning Bowen-York punctures in vacuum on the 256^3 box of side
+    64 M, Robin boundaries, FP32 V-cycles in FP64 refinement, 6 levels."""
+    import torch
+    w = synth.bowen_york_binary(256, g.PREC_FP32_IR, 6)
+    p = g.params(w.n, w.levels, w.bc, g.PREC_FP32_IR, w.length, w.origin)
+    psi0, A2 = g.bowen_york_sources(p, w.punctures, dev)
+    z = torch.zeros((w.n,) * 3, dtype=torch.float64, device=dev)
+    s = g.Solver(p, z, z)
+    s.set_background(psi0, A2)
+    u = torch.zeros((w.n,) * 3, dtype=torch.float64, device=dev)
+    s.autotune(u, None, reps=10)
+    runs, rep = [], None
+    for k in range(1 + max(1, args.steps // 2)):
+        u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep = s.solve(u, None, tol=args.tol, max_outer=100)
+        torch.cuda.synchronize()
+        if k:
+            runs.append(time.perf_counter() - t0)
+    runs.sort()
+    out = dict(seconds=runs[len(runs) // 2], runs=len(runs), n=w.n, levels=w.levels,
+               outer_iters=rep["outer_iters"], h_rms=rep["h_rms"], h_max=rep["h_max"],
+               punctures=w.punctures.tolist())
+    log(f"[bench] bowen_york_binary_256 mixed: {out['seconds'] * 1e3:.2f} ms/solve (median of {len(runs)}), "
         f"outer={rep['outer_iters']} rms H={rep['h_rms']:.2e}")
     s.close()
     return out
@@ -429,6 +460,7 @@ def main():
     extra = {}
     if not args.no_extra:
         extra["puncture_shell_256"] = bench_puncture_256(g, synth, dev, args, log)
+        extra["bowen_york_binary_256"] = bench_bowen_york_256(g, synth, dev, args, log)
         extra["scan_96"] = bench_scan_96(g, synth, dev, args, log)
 
     # ---- CPU oracle: the same workload solved to the same tolerance on the host cores

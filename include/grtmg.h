@@ -189,6 +189,36 @@ mg_status mg_residual_norm(mg_ctx *ctx, const double *d_u, const double *d_W, do
 mg_status mg_residual_fields(mg_ctx *ctx, const double *d_u, const double *d_W, double *d_H,
                              double *d_M, double *d_c);
 
+/*
+ * Background fields of a psi-only context (solve_momentum = 0), borrowed, FP64 on
+ * the finest grid (n^3 each, either may be NULL to clear it):
+ *  d_psi0  replaces psi0 = 1 + M/(2r) in psi = psi0 + u (several punctures;
+ *          puncture_mass must then be 0; puncture_pos stays the centre of the
+ *          Robin rule);
+ *  d_A2    Abar_ij Abar_ij of an analytic traceless extrinsic curvature, added to
+ *          the A2 of W in H_h and in c (cross terms with W are not formed, so W is
+ *          meant to be zero: the Bowen-York data below solve the momentum
+ *          constraint themselves).
+ * Key features, "Flexibility": binary black holes with boosted and/or spinning
+ * punctures.  MG_ERR_INVALID for a momentum or batch context, or with
+ * puncture_mass != 0 and d_psi0 given.  Takes effect for the next call.
+ */
+mg_status mg_set_background(mg_ctx *ctx, const double *d_psi0, const double *d_A2);
+
+/*
+ * Bowen-York puncture data (Key features, "Flexibility"; the momentum constraint,
+ * Summary eq. Mom, with K = 0 and no matter, solved analytically): h_table holds
+ * 10 doubles per puncture (mass m, centre C[3], momentum P[3], spin S[3]; up to 8
+ * punctures, all finite).  With n = (x - C)/r and r = |x - C| the traceless
+ * extrinsic curvature is the sum over punctures of
+ *   (3/(2 r^2)) [P_i n_j + P_j n_i - (delta_ij - n_i n_j) P.n]
+ *   + (3/r^3) [(S x n)_i n_j + (S x n)_j n_i];
+ * writes d_psi0 = 1 + sum m/(2r) and d_A2 = Abar_ij Abar_ij at the cell centres of
+ * the grid of p (n, length, origin), FP64 n^3 each.  Enqueued only.
+ */
+mg_status mg_bowen_york_sources(const mg_params *p, int32_t count, const double *h_table, double *d_psi0,
+                                double *d_A2, void *stream);
+
 void mg_destroy(mg_ctx *ctx);
 const char *mg_status_str(mg_status s);
 

@@ -120,6 +120,7 @@ struct mg_ctx {
     double *A_W, *aug_W, *inv_W;
     double *hpin;
     const double *rho5, *rho1, *S, *f;
+    const double *bg_psi0, *bg_A2; // optional background fields (mg_set_background), borrowed
     double K2;
     int vc_psi, vc_W;
     // batch membership: streams borrowed from the batch, updates gated by the
@@ -788,6 +789,8 @@ void residual(mg_ctx *c, const double *u, const double *W, bool want_M, double *
 {
     ResArgs a;
     a.u = u;
+    a.psi0f = c->bg_psi0;
+    a.A2bg = c->bg_A2;
     a.W = W;
     a.rho5 = c->rho5;
     a.rho1 = c->rho1;
@@ -811,7 +814,9 @@ void residual(mg_ctx *c, const double *u, const double *W, bool want_M, double *
     int64_t nb = nblk(c->cells[0]);
     {
         Probe pr(c, MG_PROBE_RESIDUAL, 0);
-        const TileMap &tm = c->tileR;
+        TileMap tm = c->tileR;
+        // marched columns carry no background fields: bricks of depth 2 instead
+        if (tm.tx >= 8 && (c->bg_psi0 || c->bg_A2)) tm = rtilemap_rt(c->n[0], 2);
         if (tm.tx > 0) {
             nb = ntiles(tm);
             if (c->p.bc == MG_BC_PERIODIC)
@@ -1465,6 +1470,8 @@ mg_status ctx_create(const mg_params *p, void *d_workspace, size_t bytes, hipStr
     c->rho1 = d_rho1;
     c->S = d_S;
     c->f = d_f;
+    c->bg_psi0 = nullptr;
+    c->bg_A2 = nullptr;
     c->K2 = p->K * p->K;
     Carver cv{(char *)d_workspace};
     carve(c, cv);
@@ -2036,6 +2043,36 @@ mg_status mg_residual_fields(mg_ctx *c, const double *d_u, const double *d_W, do
     source_mean(c, d_u);
     residual<double>(c, d_u, d_W, want_M, d_H, d_M, d_c, nullptr, nullptr, nullptr, false);
     leave(c);
+    return hip_status();
+}
+
+mg_status mg_set_background(mg_ctx *c, const double *d_psi0, const double *d_A2)
+{
+    if (!c || c->batched || c->momentum) return MG_ERR_INVALID;
+    if (d_psi0 && c->p.puncture_mass != 0.0) return MG_ERR_INVALID;
+    c->bg_psi0 = d_psi0;
+    c->bg_A2 = d_A2;
+    c->cont_valid = false;
+    drop_graph(c); // the captured residual launches carry the old pointers
+    return MG_OK;
+}
+
+mg_status mg_bowen_york_sources(const mg_params *p, int32_t count, const double *h_table, double *d_psi0,
+                                double *d_A2, void *stream)
+{
+    if (!p || p->n < 1 || p->n > 4096 || !(p->length > 0.0) || !d_psi0 || !d_A2) return MG_ERR_INVALID;
+    if (count < 0 || count > kMaxPunctures || (count > 0 && !h_table)) return MG_ERR_INVALID;
+    PunctureTable pt;
+    std::memset(&pt, 0, sizeof(pt));
+    pt.count = count;
+    for (int q = 0; q < count; q++)
+        for (int e = 0; e < 10; e++) {
+            if (!std::isfinite(h_table[10 * q + e])) return MG_ERR_INVALID;
+            pt.t[q][e] = h_table[10 * q + e];
+        }
+    const Geo g = make_geo(p->n, p->bc, p->length, p->origin, p->puncture_pos);
+    const int64_t m = (int64_t)p->n * p->n * p->n;
+    hipLaunchKernelGGL(k_bowen_york, dim3(nblk(m)), dim3(kBlock), 0, (hipStream_t)stream, g, pt, d_psi0, d_A2);
     return hip_status();
 }
 

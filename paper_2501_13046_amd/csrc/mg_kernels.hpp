@@ -44,6 +44,9 @@ __device__ __forceinline__ double psi0_at(const Geo &g, double pmass, int i, int
 // ---------------------------------------------------------------------------------------
 struct ResArgs {
     const double *u, *W, *rho5, *rho1, *S, *f;
+    // optional background (may be null): psi0 in place of 1 + M/(2r), and the A2
+    // of an analytic traceless extrinsic curvature added to the one of W
+    const double *psi0f, *A2bg;
     const double *meanS; // device, 3 values (periodic momentum source mean)
     double K2, pmass;
     double *H, *M, *c;
@@ -90,9 +93,9 @@ __global__ void __launch_bounds__(kBlock) k_residual(Geo g, ResArgs a)
     double hv = 0.0, m2 = 0.0;
     if (cell_of(tid, n, i, j, k)) {
         const int64_t q = tid;
-        const double psi = psi0_at(g, a.pmass, i, j, k) + a.u[q];
+        const double psi = (a.psi0f ? a.psi0f[q] : psi0_at(g, a.pmass, i, j, k)) + a.u[q];
         Acc<BC, double> U{a.u, g};
-        double A2 = 0.0;
+        double A2 = a.A2bg ? a.A2bg[q] : 0.0;
         double Mv[3] = {0.0, 0.0, 0.0};
         if (a.W) {
             Acc<BC, double> W0{a.W, g}, W1{a.W + m, g}, W2{a.W + 2 * m, g};
@@ -2043,6 +2046,51 @@ __global__ void __launch_bounds__(kBlock) k_sources_modes(Geo g, double length, 
         acc[0] += r5 + r1;
     }
     if (partials) block_reduce_store<1>(acc, 0u, partials + blockIdx.x);
+}
+
+// Bowen-York punctures: psi0 = 1 + sum m / (2 r) and A2 = Abar_ij Abar_ij of the sum over
+// punctures of (3 / (2 r^2)) [P_i n_j + P_j n_i - (delta_ij - n_i n_j) P.n]
+// + (3 / r^3) [(S x n)_i n_j + (S x n)_j n_i], n = (x - C) / r, at every cell centre.
+constexpr int kMaxPunctures = 8;
+struct PunctureTable {
+    int count;
+    double t[kMaxPunctures][10]; // m, C[3], P[3], S[3]
+};
+
+__global__ void __launch_bounds__(kBlock) k_bowen_york(Geo g, PunctureTable pt, double *psi0, double *A2)
+{
+    const int n = g.n;
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int i, j, k;
+    if (!cell_of(q, n, i, j, k)) return;
+    const double x[3] = {g.org[0] + (i + 0.5) * g.h, g.org[1] + (j + 0.5) * g.h, g.org[2] + (k + 0.5) * g.h};
+    double A[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+    double s = 1.0;
+    for (int p = 0; p < pt.count; p++) {
+        const double *t = pt.t[p];
+        const double d[3] = {x[0] - t[1], x[1] - t[2], x[2] - t[3]};
+        const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        const double ir = 1.0 / r;
+        const double nv[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
+        const double pn = t[4] * nv[0] + t[5] * nv[1] + t[6] * nv[2];
+        const double sxn[3] = {t[8] * nv[2] - t[9] * nv[1], t[9] * nv[0] - t[7] * nv[2], t[7] * nv[1] - t[8] * nv[0]};
+        const double cb = 1.5 * ir * ir, cs = 3.0 * ir * ir * ir;
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+#pragma unroll
+            for (int b = 0; b < 3; b++) {
+                const double boost = t[4 + a] * nv[b] + t[4 + b] * nv[a] - ((a == b ? 1.0 : 0.0) - nv[a] * nv[b]) * pn;
+                A[a][b] += cb * boost + cs * (sxn[a] * nv[b] + sxn[b] * nv[a]);
+            }
+        s += t[0] * 0.5 * ir;
+    }
+    double a2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+#pragma unroll
+        for (int b = 0; b < 3; b++) a2 += A[a][b] * A[a][b];
+    psi0[q] = s;
+    A2[q] = a2;
 }
 
 __global__ void __launch_bounds__(kBlock) k_sources_shell(Geo g, double amp, double r0,

@@ -916,7 +916,10 @@ struct ResSums {
     double hsum = 0.0, hmax = 0.0, msum = 0.0, mmax2 = 0.0;
 };
 
-template <int BC, typename T, bool HAS_W, typename SrcOf>
+// BG: the background fields (psi0f, A2bg) may be set; the marched columns of the
+// periodic coupled solve are compiled without them (the host does not route a
+// context with a background to them).
+template <int BC, typename T, bool HAS_W, bool BG = true, typename SrcOf>
 __device__ __forceinline__ void residual_cell(const Geo &g, const ResArgs &a, int x, int y, int z, const SrcOf &src_of,
                                               ResSums &acc)
 {
@@ -926,8 +929,8 @@ __device__ __forceinline__ void residual_cell(const Geo &g, const ResArgs &a, in
     const double third = 1.0 / 3.0, two_thirds = 2.0 / 3.0;
     const unsigned q = ((unsigned)x * (unsigned)n + (unsigned)y) * (unsigned)n + (unsigned)z;
     const double uc = elt(a.u, q);
-    const double psi = psi0_at(g, a.pmass, x, y, z) + uc;
-    double A2 = 0.0;
+    const double psi = ((BG && a.psi0f) ? elt(a.psi0f, q) : psi0_at(g, a.pmass, x, y, z)) + uc;
+    double A2 = (BG && a.A2bg) ? elt(a.A2bg, q) : 0.0;
     double Mv[3] = {0.0, 0.0, 0.0};
     if constexpr (HAS_W) {
         double dW[3][3]; // dW[p][s]: d_p W_s
@@ -1173,7 +1176,7 @@ __global__ void __launch_bounds__(kTY *kLanes) k_residual_march(Geo g, TileMap t
 #pragma unroll
             for (int d = 0; d < 5; d++) pb[d] = &ring[(k + d) % kRing][ty * kRPZ + lane];
         }
-        residual_cell<kBcPeriodic, T, HAS_W>(
+        residual_cell<kBcPeriodic, T, HAS_W, false>(
             g, a, x0 + k, y, z, [&](auto fc) { return RRing<decltype(fc)::value>{pb}; }, acc);
         if constexpr (HAS_W) {
             if (k + 5 <= LX + 3) { // plane x + 3 into the slot plane x - 3 left

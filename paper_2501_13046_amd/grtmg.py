@@ -90,6 +90,8 @@ def lib() -> C.CDLL:
         L.mg_shell_field_sources.argtypes = [pp, C.c_double, C.c_double, C.c_double, C.c_double,
                                              vp, vp, vp, vp]
         L.mg_interp_cubic.argtypes = [pp, vp, vp, vp]
+        L.mg_set_background.argtypes = [vp, vp, vp]
+        L.mg_bowen_york_sources.argtypes = [pp, i32, dp, vp, vp, vp]
         L.mg_kernel_op.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp]
         L.mg_batch_workspace_size.argtypes = [pp, i32, C.POINTER(C.c_size_t)]
         L.mg_setup_batch.argtypes = [pp, i32, vp, C.c_size_t, vp, C.POINTER(vp), C.POINTER(vp),
@@ -106,7 +108,7 @@ def lib() -> C.CDLL:
         L.mg_probe_result.argtypes = [vp, C.POINTER(i32), C.POINTER(C.c_double)]
         for f in ("mg_workspace_size", "mg_setup", "mg_vcycle", "mg_solve_constraints", "mg_solve_constraints_continue",
                   "mg_residual_norm", "mg_residual_fields", "mg_scalar_field_sources",
-                  "mg_scalar_field_sources_static",
+                  "mg_scalar_field_sources_static", "mg_set_background", "mg_bowen_york_sources",
                   "mg_shell_field_sources", "mg_interp_cubic", "mg_kernel_op", "mg_probe",
                   "mg_probe_result", "mg_batch_workspace_size", "mg_setup_batch", "mg_solve_batch",
                   "mg_fmg_start", "mg_batch_launch_mode", "mg_autotune", "mg_set_tile"):
@@ -184,6 +186,12 @@ class Solver:
                               _dptr(S, numel=3 * self.cells), _dptr(f, numel=self.cells),
                               C.byref(ctx)), "mg_setup")
         self.ctx = ctx
+
+    def set_background(self, psi0: Optional[torch.Tensor] = None, A2: Optional[torch.Tensor] = None):
+        """Background psi0 (several punctures) and A2 (Bowen-York) fields, borrowed."""
+        self._bg = (psi0, A2)
+        _check(lib().mg_set_background(self.ctx, _dptr(psi0, numel=self.cells), _dptr(A2, numel=self.cells)),
+               "mg_set_background")
 
     def close(self):
         if getattr(self, "ctx", None) is not None and self.ctx.value:
@@ -343,6 +351,18 @@ def scalar_field_sources(p: MgParams, phi_modes: np.ndarray, pi_modes: np.ndarra
         SOURCES_SCRATCH_BYTES if want_K else 0, None,
         C.byref(K) if want_K else None, _stream(rho5.device)), "mg_scalar_field_sources")
     return rho5, rho1, S, (K.value if want_K else None)
+
+
+def bowen_york_sources(p: MgParams, table, device="cuda"):
+    """psi0 = 1 + sum m/(2r) and A2 of the Bowen-York curvature of the punctures
+    (rows m, C[3], P[3], S[3]) on p's grid."""
+    n = p.n
+    tab = np.ascontiguousarray(table, dtype=np.float64).reshape(-1, 10)
+    psi0 = torch.empty((n, n, n), dtype=torch.float64, device=device)
+    A2 = torch.empty_like(psi0)
+    _check(lib().mg_bowen_york_sources(C.byref(p), len(tab), tab.ctypes.data_as(C.POINTER(C.c_double)),
+                                       _dptr(psi0), _dptr(A2), _stream(psi0.device)), "mg_bowen_york_sources")
+    return psi0, A2
 
 
 def shell_field_sources(p: MgParams, amplitude: float, r0: float, width2: float,

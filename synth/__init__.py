@@ -84,6 +84,8 @@ class Workload:
     shell: Optional[dict] = None
     # sources given as conformally rescaled rho_bar = psi^8 rho, S_bar = psi^6 S
     conformal_matter: bool = False
+    # Bowen-York punctures: rows (m, C[3], P[3], S[3]); None when not used
+    punctures: Optional[np.ndarray] = None
     seed: Optional[int] = None
     tol: float = 1e-10
 
@@ -132,6 +134,20 @@ def puncture_shell(n: int = 256, precision: int = PREC_FP32_IR,
                     solve_momentum=False, puncture_mass=1.0,
                     puncture_pos=(0.0, 0.0, 0.0), conformal_matter=True,
                     shell=dict(amplitude=0.1, r0=10.0, width2=4.0))
+
+
+def bowen_york_binary(n: int = 256, precision: int = PREC_FP32_IR, levels: int = 6) -> Workload:
+    """Two unequal boosted and spinning punctures in vacuum on the box [-32, 32]^3
+    (the 64 M box of the isolated black-hole workload), Robin boundaries about
+    the centre, K = 0.  The punctures sit on cell vertices of every grid with
+    h dividing 1 (n = 64, 128, 256)."""
+    table = np.array([
+        [0.5, 3.0, 0.0, 0.0, 0.0, 0.1, 0.0, 0.0, 0.0, 0.2],
+        [0.5, -3.0, 0.0, 0.0, 0.0, -0.1, 0.0, 0.05, 0.0, -0.1],
+    ])
+    return Workload(name=f"bowen_york_binary_{n}", n=n, levels=levels, length=64.0,
+                    origin=(-32.0, -32.0, -32.0), bc=BC_ROBIN, precision=precision,
+                    solve_momentum=False, punctures=table)
 
 
 def scan_96(count: int = 96, size_seed: int = 12345,

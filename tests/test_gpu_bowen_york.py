@@ -1,0 +1,113 @@
+"""Bowen-York binary punctures on the HIP path (Key features, "Flexibility"):
+the puncture data against the oracle's, the residual with the background
+psi0 and A2 fields, single outer steps element by element (FP64), and
+converged binary solves in both precisions against the oracle's solution."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle import judge
+from paper_2501_13046_amd import grtmg as g
+from gpu_helpers import N, T, dev, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def problem(n, levels, precision=g.PREC_FP64):
+    w = synth.bowen_york_binary(n, precision, levels)
+    p = g.params(n, levels, w.bc, precision, w.length, w.origin)
+    psi0, A2 = g.bowen_york_sources(p, w.punctures, dev())
+    po0 = oracle.params(n, bc=w.bc, length=w.length, origin=w.origin)
+    opsi0, oA2 = oracle.bowen_york(po0, w.punctures)
+    po = oracle.params(n, levels=levels, bc=w.bc, length=w.length, origin=w.origin, bg_psi0=opsi0, bg_A2=oA2)
+    z = torch.zeros((n,) * 3, dtype=torch.float64, device=dev())
+    s = g.Solver(p, z, z)
+    s.set_background(psi0, A2)
+    return w, s, psi0, A2, po, opsi0, oA2
+
+
+def test_puncture_data_match_oracle():
+    w, s, psi0, A2, po, opsi0, oA2 = problem(32, 3)
+    assert rel_err(N(psi0), opsi0) < 1e-14
+    assert rel_err(N(A2), oA2) < 1e-13
+
+
+def test_residual_with_background_matches_oracle():
+    w, s, psi0, A2, po, opsi0, oA2 = problem(32, 3)
+    n = w.n
+    u = synth.uniform_random(100, (n,) * 3, 0.0, 0.05)
+    H, _, c = s.residual_fields(T(u), None, want_M=False)
+    z = np.zeros((n,) * 3)
+    z3 = np.zeros((3, n, n, n))
+    Ho, _, co = oracle.residuals(po, u, z3, z, z, z3)
+    assert rel_err(N(H), Ho) < 1e-12
+    assert rel_err(N(c), co) < 1e-12
+
+
+def test_single_steps_match_oracle():
+    w, s, psi0, A2, po, opsi0, oA2 = problem(32, 4)
+    n = w.n
+    u = torch.zeros((n,) * 3, dtype=torch.float64, device=dev())
+    uo = np.zeros((n,) * 3)
+    z = np.zeros((n,) * 3)
+    z3 = np.zeros((3, n, n, n))
+    for step in range(3):
+        s.vcycle(g.EQ_PSI, u, None)
+        oracle.step(po, 1, uo, z3, z, z, z3)
+        assert rel_err(N(u), uo) < 1e-11, step
+
+
+@pytest.mark.parametrize("precision", [g.PREC_FP64, g.PREC_FP32_IR])
+def test_binary_solve_matches_oracle(precision):
+    w, s, psi0, A2, po, opsi0, oA2 = problem(64, 5, precision)
+    n = w.n
+    u = torch.zeros((n,) * 3, dtype=torch.float64, device=dev())
+    rep10 = s.solve(u, None, tol=1e-10, max_outer=60)
+    u10 = N(u)
+    rep = s.solve(u, None, tol=1e-11, max_outer=60)
+    z = np.zeros((n,) * 3)
+    z3 = np.zeros((3, n, n, n))
+    uo = np.zeros((n,) * 3)
+    res = oracle.solve(po, uo, z3, z, z, z3, tol=1e-11, max_outer=60)
+    assert res.status == 0 and rep10["status"] == 0 and rep["status"] == 0
+    gr = judge.Grid(n, w.length, w.bc, w.origin)
+    H, _, _ = judge.residuals(gr, N(u), None, z, z, None, 0.0, psi0_field=opsi0, A2_bg=oA2)
+    e10 = np.max(np.abs(u10 - uo) / (opsi0 + uo))
+    e11 = np.max(np.abs(N(u) - uo) / (opsi0 + uo))
+    print(f"binary 64^3 prec={precision}: {rep10['outer_iters']} iterations to rms H {rep10['h_rms']:.2e} "
+          f"(psi err {e10:.2e}), +{rep['outer_iters']} to {rep['h_rms']:.2e} (psi err {e11:.2e}); "
+          f"oracle {res.iters}; judge rms H {judge.norms(H)[0]:.2e}; u in [{uo.min():.3e}, {uo.max():.3e}]")
+    assert judge.norms(H)[0] <= 1e-11
+    assert e11 < 1e-9
+
+
+def test_background_refused_for_momentum_context():
+    n = 16
+    p = g.params(n, 2, solve_momentum=True)
+    z = torch.zeros((n,) * 3, dtype=torch.float64, device=dev())
+    S = torch.zeros((3, n, n, n), dtype=torch.float64, device=dev())
+    s = g.Solver(p, z, z, S)
+    with pytest.raises(g.MGError):
+        s.set_background(z, z)
+
+
+def test_background_on_a_periodic_grid_of_marched_columns():
+    """A 128^3 periodic context would evaluate its residual in marched columns, which
+    carry no background: with a background set it must still match the oracle."""
+    n, K = 128, 1.3
+    p = g.params(n, 6, K=K)
+    psi0 = 1.0 + synth.uniform_random(110, (n,) * 3, 0.0, 0.1)
+    A2 = synth.uniform_random(111, (n,) * 3, 0.0, 0.5)
+    u = synth.uniform_random(112, (n,) * 3, -0.01, 0.01)
+    rho5 = synth.uniform_random(113, (n,) * 3, 0.0, 0.2)
+    z = np.zeros((n,) * 3)
+    s = g.Solver(p, T(rho5), T(z))
+    s.set_background(T(psi0), T(A2))
+    H, _, c = s.residual_fields(T(u), None, want_M=False)
+    po = oracle.params(n, levels=6, K=K, bg_psi0=psi0, bg_A2=A2)
+    z3 = np.zeros((3, n, n, n))
+    Ho, _, co = oracle.residuals(po, u, z3, rho5, z, z3)
+    assert rel_err(N(H), Ho) < 1e-12
+    assert rel_err(N(c), co) < 1e-12
