@@ -171,7 +171,9 @@ def bench_scan_96(g, synth, dev, args, log):
                status=int(st), converged=int(sum(1 for r in reps if r["status"] == 0)),
                outer_iters_min=min(its), outer_iters_max=max(its),
                worst_h_rms=max(r["h_rms"] for r in reps), worst_m_rms=max(r["m_rms"] for r in reps),
-               launch_mode={1: "graph", 2: "lanes"}.get(mode, str(mode)))
+               launch_mode={1: "graph", 2: "lanes", 3: "groups"}.get(mode, str(mode)),
+               tuning_ms_per_iteration={"graph": ms[0], "lanes": ms[1], "groups": ms[2]},
+               groups=batch.groups()[0])
     log(f"[bench] scan_96: {out['seconds'] * 1e3:.1f} ms/scan (median of {len(runs)}), {out['cells']} cells, "
         f"iterations {min(its)}-{max(its)}, worst rms H {out['worst_h_rms']:.2e} M {out['worst_m_rms']:.2e}, "
         f"mode {out['launch_mode']}")

@@ -367,27 +367,32 @@ mg_status mg_kernel_op(mg_ctx *ctx, int32_t op, int32_t level, int32_t arg, cons
                        void *d_out, const void *d_r, const void *d_c);
 
 /*
- * Batches of independent instances (a parameter scan of uneven grid sizes).
- * One batch context holds one member context per instance, all carved from
- * one caller-owned workspace; every member's outer iteration is captured on
- * the member's stream and added as an independent child graph of one batch
- * hipGraph, so each outer iteration of the whole batch is one graph launch
- * followed by one copy of every member's norms.  A member that has converged (or diverged)
- * keeps its state: its update kernels are gated by a device-side flag set by
- * a check kernel after each evaluation.
+ * Batches of independent instances (a parameter scan of uneven grid sizes; Key
+ * features: parameter studies of cosmological spacetimes).  Members whose
+ * parameters agree in everything but K form a group (a size class of the scan).
+ * All members are carved from one caller-owned workspace: every member owns a
+ * region holding its context workspace and its own copies of the sources and of
+ * the state (u, W), and the regions of a group are equally spaced, so that one
+ * kernel launch covers the whole group (the member index is the block index
+ * along z; every array address moves by the region stride).  A member that has
+ * converged (or diverged) keeps its state: its update kernels are gated by a
+ * device-side flag set by a check kernel after each evaluation.
  *  p: host array of count parameter sets (same precision for all; momentum
  *     members need periodic boundaries as for mg_setup).
  *  d_rho5, d_rho1, d_S: host arrays of count device pointers (n_i^3, n_i^3,
  *     3 n_i^3 FP64); d_S may be NULL when no member solves the momentum
- *     equation.  Sources are borrowed.
+ *     equation.  The sources are copied into the workspace at set-up.
  *  mg_solve_batch: d_u, d_W host arrays of device pointers (d_W may be NULL
- *     when no member solves the momentum equation); reps (may be NULL) gets
- *     count reports (no per-iteration history).  Returns MG_OK when every
- *     member converged, else the first non-OK member status.  Synchronises
- *     the batch's streams once per outer iteration.
+ *     when no member solves the momentum equation; W given or not must agree
+ *     within a group); the states are copied in before and out after the solve.
+ *     reps (may be NULL) gets count reports (no per-iteration history).  Returns
+ *     MG_OK when every member converged, else the first non-OK member status.
+ *     Synchronises once per outer iteration (one copy of every member's norms).
+ *  mg_batch_groups: the number of groups and (h_group_of, count entries, may be
+ *     NULL) each member's group.
  */
 typedef struct mg_batch mg_batch;
-enum { MG_BATCH_AUTO = 0, MG_BATCH_GRAPH = 1, MG_BATCH_LANES = 2 };
+enum { MG_BATCH_AUTO = 0, MG_BATCH_GRAPH = 1, MG_BATCH_LANES = 2, MG_BATCH_GROUPS = 3 };
 mg_status mg_batch_workspace_size(const mg_params *p, int32_t count, size_t *bytes);
 mg_status mg_setup_batch(const mg_params *p, int32_t count, void *d_workspace, size_t bytes, void *stream,
                          const double *const *d_rho5, const double *const *d_rho1,
@@ -395,20 +400,23 @@ mg_status mg_setup_batch(const mg_params *p, int32_t count, void *d_workspace, s
 mg_status mg_solve_batch(mg_batch *b, double *const *d_u, double *const *d_W, double tol, int32_t max_outer,
                          mg_report *reps);
 void mg_destroy_batch(mg_batch *b);
+mg_status mg_batch_groups(mg_batch *b, int32_t *h_ngroups, int32_t *h_group_of);
 
 /*
  * Launch mode of a batch's outer iterations (the autotuned choice of the
- * batched execution).  MG_BATCH_GRAPH: the one batch graph (every member runs,
- * converged members with their updates gated off).  MG_BATCH_LANES: every
- * still-active member's own graph, spread over 4 streams so that members run
- * concurrently, converged members skipped.  MG_BATCH_AUTO (the default): the
- * first solve times one outer iteration in each mode (wall clock, launch to
- * completion) and keeps the faster; both replay the same member graphs, so
- * results are identical in every mode.  request = -1 only queries.  *chosen
- * (may be NULL): the mode in use (MG_BATCH_AUTO until tuned); h_ms (may be
- * NULL): the tuning times in ms (graph, lanes; -1 if not measured).
+ * batched execution).  MG_BATCH_GROUPS: every group with an active member runs
+ * its captured outer iteration, one launch per kernel for the whole group (its
+ * converged members with their updates gated off), the groups concurrently on
+ * four streams.  MG_BATCH_GRAPH: one batch graph of every member's own outer
+ * iteration.  MG_BATCH_LANES: every still-active member's own graph, spread
+ * over four streams.  MG_BATCH_AUTO (the default): the first solve times one
+ * outer iteration in each mode (wall clock, launch to completion) and keeps the
+ * fastest; every mode runs the same kernels on the same arrays, so results are
+ * identical in every mode.  request = -1 only queries.  *chosen (may be NULL):
+ * the mode in use (MG_BATCH_AUTO until tuned); h_ms (may be NULL): the tuning
+ * times in ms (graph, lanes, groups; -1 if not measured).
  */
-mg_status mg_batch_launch_mode(mg_batch *b, int32_t request, int32_t *chosen, double h_ms[2]);
+mg_status mg_batch_launch_mode(mg_batch *b, int32_t request, int32_t *chosen, double h_ms[3]);
 
 /*
  * Kernel timing probe (measurement support).  mg_probe(ctx, kernel, level)

@@ -15,6 +15,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <vector>
 #include <type_traits>
 
 #include "grtmg.h"
@@ -41,6 +42,7 @@ enum {
     S_FLAG_PSI = 12,
     S_FLAG_W = 13,
     S_DIVERGED = 14,
+    S_K2 = 15, // K^2 of a batch member
     S_COUNT = 16
 };
 
@@ -127,6 +129,11 @@ struct mg_ctx {
     // instance's active flag, a convergence check after every evaluation
     bool batched, own_streams;
     double batch_tol;
+    // grouped batch launches: gz members (member z's arrays zs bytes after this
+    // context's) per launch; K^2 read per member from its scalar block
+    int gz;
+    long long zs;
+    const double *K2p;
     // outer-iteration graph (keyed by the state pointers it was captured for)
     hipGraphExec_t gexec;
     const double *g_u, *g_W;
@@ -329,9 +336,9 @@ void probe_launch(const Probe &pr, F kernel, const dim3 &grid, const dim3 &blk, 
 }
 
 template <typename T>
-void fill(hipStream_t s, T *a, int64_t count, T v)
+void fill(hipStream_t s, T *a, int64_t count, T v, int gz = 1, long long zs = 0)
 {
-    if (count > 0) hipLaunchKernelGGL(k_fill<T>, dim3(nblk(count)), dim3(kBlock), 0, s, a, count, v);
+    if (count > 0) hipLaunchKernelGGL(k_fill<T>, dim3(nblk(count), 1, gz), dim3(kBlock), 0, s, a, count, v, zs);
 }
 
 // Defect+restriction form: one thread per fine cell on grids of at most 32^3
@@ -354,9 +361,9 @@ void launch_coarse_wave(mg_ctx *c, int l, const T *r, T *x)
     const T *cf = (const T *)c->pc[l];
     double *flag = c->scal + S_FLAG_PSI;
     switch (c->m_psi) {
-    case 8: hipLaunchKernelGGL((k_coarse_psi_block<BC, T, 8>), dim3(1), dim3(kGjWaves * kWave), 0, c->s, g, cf, r, x, flag); break;
-    case 27: hipLaunchKernelGGL((k_coarse_psi_block<BC, T, 27>), dim3(1), dim3(kGjWaves * kWave), 0, c->s, g, cf, r, x, flag); break;
-    default: hipLaunchKernelGGL((k_coarse_psi_block<BC, T, 64>), dim3(1), dim3(kGjWaves * kWave), 0, c->s, g, cf, r, x, flag); break;
+    case 8: hipLaunchKernelGGL((k_coarse_psi_block<BC, T, 8>), dim3(1, 1, c->gz), dim3(kGjWaves * kWave), 0, c->s, g, cf, r, x, flag); break;
+    case 27: hipLaunchKernelGGL((k_coarse_psi_block<BC, T, 27>), dim3(1, 1, c->gz), dim3(kGjWaves * kWave), 0, c->s, g, cf, r, x, flag); break;
+    default: hipLaunchKernelGGL((k_coarse_psi_block<BC, T, 64>), dim3(1, 1, c->gz), dim3(kGjWaves * kWave), 0, c->s, g, cf, r, x, flag); break;
     }
 }
 
@@ -380,12 +387,12 @@ void coarse_psi(mg_ctx *c, const T *r, T *x)
         // conjugate gradients (periodic) or BiCGSTAB (Robin) on one block; a system it
         // does not solve to 1e-12 raises the singular flag
         if (c->p.bc == MG_BC_PERIODIC)
-            hipLaunchKernelGGL((k_coarse_psi_krylov<kBcPeriodic, T>), dim3(1), dim3(kGjWaves * kWave), 0, c->s,
+            hipLaunchKernelGGL((k_coarse_psi_krylov<kBcPeriodic, T>), dim3(1, 1, c->gz), dim3(kGjWaves * kWave), 0, c->s,
                                c->geo[l], m, (const T *)c->pc[l], r, x, c->scal + S_FLAG_PSI);
         else
             with_bc(c->p.bc, [&](auto bcx) {
                 constexpr int BCX = decltype(bcx)::value;
-                hipLaunchKernelGGL((k_coarse_psi_krylov<BCX, T>), dim3(1), dim3(kGjWaves * kWave), 0, c->s,
+                hipLaunchKernelGGL((k_coarse_psi_krylov<BCX, T>), dim3(1, 1, c->gz), dim3(kGjWaves * kWave), 0, c->s,
                                    c->geo[l], m, (const T *)c->pc[l], r, x, c->scal + S_FLAG_PSI);
             });
         return;
@@ -401,8 +408,8 @@ void coarse_psi(mg_ctx *c, const T *r, T *x)
                                c->geo[l], (const T *)c->pc[l], c->A_psi);
         });
     factor(c->s, c->A_psi, c->aug_psi, c->inv_psi, m, c->scal + S_FLAG_PSI);
-    hipLaunchKernelGGL(k_coarse_apply<T>, dim3((m + kApplyRows - 1) / kApplyRows), dim3(kBlock),
-                       m * sizeof(double), c->s, (const double *)c->inv_psi, m, r, x, 0);
+    hipLaunchKernelGGL(k_coarse_apply<T>, dim3((m + kApplyRows - 1) / kApplyRows, 1, c->gz), dim3(kBlock),
+                       m * sizeof(double), c->s, (const double *)c->inv_psi, m, r, x, 0, c->zs);
 }
 
 template <typename T>
@@ -410,8 +417,8 @@ void coarse_W(mg_ctx *c, const T *r, T *x)
 {
     const int m = c->m_W;
     Probe pr(c, MG_PROBE_COARSE, c->L - 1);
-    hipLaunchKernelGGL(k_coarse_apply<T>, dim3((m + kApplyRows - 1) / kApplyRows), dim3(kBlock),
-                       m * sizeof(double), c->s, (const double *)c->inv_W, m, r, x, 3);
+    hipLaunchKernelGGL(k_coarse_apply<T>, dim3((m + kApplyRows - 1) / kApplyRows, 1, c->gz), dim3(kBlock),
+                       m * sizeof(double), c->s, (const double *)c->inv_W, m, r, x, 3, c->zs);
 }
 
 // ---- psi V-cycle ----------------------------------------------------------------------
@@ -420,7 +427,7 @@ template <int BC, typename T>
 void launch_psi_tiled(hipStream_t s, const Geo &g, const TileMap &tm, const T *in, T *out, const T *r, const T *cf,
                       int colour)
 {
-    const dim3 blk(kLanes, kTY), grid(ntiles(tm));
+    const dim3 blk(kLanes, kTY), grid(ntiles(tm), 1, g.gz);
     switch (tm.tx) {
     case 2: hipLaunchKernelGGL((k_pass_psi_tiled<BC, T, 2>), grid, blk, 0, s, g, tm, in, out, r, cf, colour); break;
     case 8: hipLaunchKernelGGL((k_pass_psi_tiled<BC, T, 8>), grid, blk, 0, s, g, tm, in, out, r, cf, colour); break;
@@ -447,15 +454,15 @@ void pass_psi(mg_ctx *c, int l, const T *in, T *out, int colour)
         return;
     }
     if (c->p.bc == MG_BC_PERIODIC && c->n[l] % 2 == 0)
-        hipLaunchKernelGGL(k_pass_psi_pairs<T>, dim3(nblk(c->cells[l] / 2)), dim3(kBlock), 0, c->s, g, in, out,
+        hipLaunchKernelGGL(k_pass_psi_pairs<T>, dim3(nblk(c->cells[l] / 2), 1, c->gz), dim3(kBlock), 0, c->s, g, in, out,
                            (const T *)c->pr[l], (const T *)c->pc[l], colour);
     else if (c->p.bc == MG_BC_PERIODIC)
-        hipLaunchKernelGGL((k_pass_psi<kBcPeriodic, T>), dim3(nb), dim3(kBlock), 0, c->s, g, in, out,
+        hipLaunchKernelGGL((k_pass_psi<kBcPeriodic, T>), dim3(nb, 1, c->gz), dim3(kBlock), 0, c->s, g, in, out,
                            (const T *)c->pr[l], (const T *)c->pc[l], colour);
     else
         with_bc(c->p.bc, [&](auto bcx) {
             constexpr int BCX = decltype(bcx)::value;
-            hipLaunchKernelGGL((k_pass_psi<BCX, T>), dim3(nb), dim3(kBlock), 0, c->s, g, in, out,
+            hipLaunchKernelGGL((k_pass_psi<BCX, T>), dim3(nb, 1, c->gz), dim3(kBlock), 0, c->s, g, in, out,
                                (const T *)c->pr[l], (const T *)c->pc[l], colour);
         });
 }
@@ -481,23 +488,23 @@ void defect_restrict_psi(mg_ctx *c, int l, const T *d, const T *r, const T *cf, 
     if (fine_threads(c->n[l])) {
         const unsigned nb = nblk(8 * c->cells[l + 1]);
         if (c->p.bc == MG_BC_PERIODIC)
-            hipLaunchKernelGGL((k_defect_restrict_psi_fine<kBcPeriodic, T>), dim3(nb), dim3(kBlock), 0, c->s, g, d, r,
+            hipLaunchKernelGGL((k_defect_restrict_psi_fine<kBcPeriodic, T>), dim3(nb, 1, c->gz), dim3(kBlock), 0, c->s, g, d, r,
                                cf, rc, cc, d1, gc);
         else
             with_bc(c->p.bc, [&](auto bcx) {
                 constexpr int BCX = decltype(bcx)::value;
-                hipLaunchKernelGGL((k_defect_restrict_psi_fine<BCX, T>), dim3(nb), dim3(kBlock), 0, c->s, g, d, r,
+                hipLaunchKernelGGL((k_defect_restrict_psi_fine<BCX, T>), dim3(nb, 1, c->gz), dim3(kBlock), 0, c->s, g, d, r,
                                    cf, rc, cc, d1, gc);
             });
     } else {
         const unsigned nb = nblk(c->cells[l + 1]);
         if (c->p.bc == MG_BC_PERIODIC)
-            hipLaunchKernelGGL((k_defect_restrict_psi<kBcPeriodic, T>), dim3(nb), dim3(kBlock), 0, c->s, g, d, r, cf,
+            hipLaunchKernelGGL((k_defect_restrict_psi<kBcPeriodic, T>), dim3(nb, 1, c->gz), dim3(kBlock), 0, c->s, g, d, r, cf,
                                rc, cc, d1, gc);
         else
             with_bc(c->p.bc, [&](auto bcx) {
                 constexpr int BCX = decltype(bcx)::value;
-                hipLaunchKernelGGL((k_defect_restrict_psi<BCX, T>), dim3(nb), dim3(kBlock), 0, c->s, g, d, r, cf,
+                hipLaunchKernelGGL((k_defect_restrict_psi<BCX, T>), dim3(nb, 1, c->gz), dim3(kBlock), 0, c->s, g, d, r, cf,
                                    rc, cc, d1, gc);
             });
     }
@@ -513,16 +520,16 @@ void defect_restrict_W(mg_ctx *c, int l, const T *d, const T *r, T *rc, T *d1 = 
     const TileMap tm = w_tileable(n) ? make_marchmap<8, 128>(n) : TileMap{0, 0, 0, 0};
     const TileMap tm64 = w_tileable(n) ? make_marchmap<kMarch64Defect, 64>(n) : TileMap{0, 0, 0, 0};
     if (tm.tx > 0)
-        hipLaunchKernelGGL((k_defect_restrict_W_march<T, 8, 128>), dim3(ntiles(tm)), dim3(kLanes, kTY), 0, c->s,
+        hipLaunchKernelGGL((k_defect_restrict_W_march<T, 8, 128>), dim3(ntiles(tm), 1, c->gz), dim3(kLanes, kTY), 0, c->s,
                            c->geo[l], tm, d, r, rc, d1, idiag);
     else if (tm64.tx > 0)
-        hipLaunchKernelGGL((k_defect_restrict_W_march<T, kMarch64Defect, 64>), dim3(ntiles(tm64)),
+        hipLaunchKernelGGL((k_defect_restrict_W_march<T, kMarch64Defect, 64>), dim3(ntiles(tm64), 1, c->gz),
                            dim3(kLanes, kTY), 0, c->s, c->geo[l], tm64, d, r, rc, d1, idiag);
     else if (fine_threads(n))
-        hipLaunchKernelGGL(k_defect_restrict_W_quad<T>, dim3(nblk(32 * c->cells[l + 1])), dim3(kBlock), 0, c->s,
+        hipLaunchKernelGGL(k_defect_restrict_W_quad<T>, dim3(nblk(32 * c->cells[l + 1]), 1, c->gz), dim3(kBlock), 0, c->s,
                            c->geo[l], d, r, rc, d1, idiag);
     else
-        hipLaunchKernelGGL(k_defect_restrict_W<T>, dim3(nblk(c->cells[l + 1])), dim3(kBlock), 0, c->s, c->geo[l], d,
+        hipLaunchKernelGGL(k_defect_restrict_W<T>, dim3(nblk(c->cells[l + 1]), 1, c->gz), dim3(kBlock), 0, c->s, c->geo[l], d,
                            r, rc, d1, idiag);
 }
 
@@ -533,12 +540,12 @@ void prolong_add(mg_ctx *c, int lc, const T *coarse, T *fine, int ncomp)
     const Geo &gc = c->geo[lc];
     const unsigned nb = nblk(c->cells[lc - 1]);
     if (c->p.bc == MG_BC_PERIODIC) // one thread per fine z pair
-        hipLaunchKernelGGL(k_prolong_add_pairs<T>, dim3(nblk(c->cells[lc - 1] / 2)), dim3(kBlock), 0, c->s, gc,
+        hipLaunchKernelGGL(k_prolong_add_pairs<T>, dim3(nblk(c->cells[lc - 1] / 2), 1, c->gz), dim3(kBlock), 0, c->s, gc,
                            coarse, fine, ncomp);
     else
         with_bc(c->p.bc, [&](auto bcx) {
             constexpr int BCX = decltype(bcx)::value;
-            hipLaunchKernelGGL((k_prolong_add<BCX, T>), dim3(nb), dim3(kBlock), 0, c->s, gc, coarse,
+            hipLaunchKernelGGL((k_prolong_add<BCX, T>), dim3(nb, 1, c->gz), dim3(kBlock), 0, c->s, gc, coarse,
                                fine, ncomp);
         });
 }
@@ -559,8 +566,8 @@ void restrict_coefficients(mg_ctx *c)
 {
     if (c_with_defect(c)) return; // each level's c comes with its defect restriction
     for (int l = 0; l + 1 < c->L; l++)
-        hipLaunchKernelGGL(k_restrict<T>, dim3(nblk(c->cells[l + 1])), dim3(kBlock), 0, c->s, c->n[l],
-                           (const T *)c->pc[l], (T *)c->pc[l + 1]);
+        hipLaunchKernelGGL(k_restrict<T>, dim3(nblk(c->cells[l + 1]), 1, c->gz), dim3(kBlock), 0, c->s, c->n[l],
+                           (const T *)c->pc[l], (T *)c->pc[l + 1], c->zs);
     const int l = c->L - 1;
     const int m = c->m_psi;
     if (wave_solvable(m) || m <= kKrylovMax) return; // solved directly at the bottom of the V-cycle
@@ -599,7 +606,7 @@ void tail_psi(mg_ctx *c)
 {
     Probe pr(c, MG_PROBE_COARSE, c->L - 1);
     const TailArgs<T> a = tail_args<T>(c, c->tail_psi, false);
-    const dim3 g1(1), blk(kTailThreads);
+    const dim3 g1(1, 1, c->gz), blk(kTailThreads);
     if (c->p.bc == MG_BC_PERIODIC) {
         switch (c->m_psi) {
         case 8: hipLaunchKernelGGL((k_tail_psi<kBcPeriodic, T, 8>), g1, blk, 0, c->s, a); break;
@@ -637,12 +644,12 @@ void vcycle_psi(mg_ctx *c, int l, bool first_done = false)
             return;
         }
         Probe pr(c, MG_PROBE_COARSE, l);
-        hipLaunchKernelGGL(k_coarse_apply<T>, dim3((m + kApplyRows - 1) / kApplyRows), dim3(kBlock),
+        hipLaunchKernelGGL(k_coarse_apply<T>, dim3((m + kApplyRows - 1) / kApplyRows, 1, c->gz), dim3(kBlock),
                            m * sizeof(double), c->s, (const double *)c->inv_psi, m, (const T *)c->pr[l],
-                           (T *)c->pd0[l], 0);
+                           (T *)c->pd0[l], 0, c->zs);
         return;
     }
-    if (!first_done) fill<T>(c->s, (T *)c->pd0[l], c->cells[l], T(0));
+    if (!first_done) fill<T>(c->s, (T *)c->pd0[l], c->cells[l], T(0), c->gz, c->zs);
     smooth_psi<T>(c, l, c->p.nu_pre, first_done);
     // the next level's first pass comes with its defect when that level is
     // smoothed by grid launches (a tail starts from zero in LDS)
@@ -661,7 +668,7 @@ template <typename T>
 void launch_W_tiled(const Probe &pr, hipStream_t s, const Geo &g, const TileMap &tm, const T *in, T *out, const T *r,
                     int colour)
 {
-    const dim3 blk(kLanes, kTY), grid(ntiles(tm));
+    const dim3 blk(kLanes, kTY), grid(ntiles(tm), 1, g.gz);
     if (tm.tx == 8)
         probe_launch(pr, k_pass_W_march<T, 8, 128>, grid, blk, s, g, tm, in, out, r, colour);
     else if (tm.tx == 16)
@@ -686,13 +693,13 @@ void pass_W(mg_ctx *c, int l, const T *in, T *out, const T *r, int colour)
     if (tm.tx > 0)
         launch_W_tiled<T>(pr, c->s, c->geo[l], tm, in, out, r, colour);
     else if (tm64.tx > 0)
-        probe_launch(pr, k_pass_W_march<T, kMarch64Pass, 64>, dim3(ntiles(tm64)), dim3(kLanes, kTY), c->s,
+        probe_launch(pr, k_pass_W_march<T, kMarch64Pass, 64>, dim3(ntiles(tm64), 1, c->gz), dim3(kLanes, kTY), c->s,
                      c->geo[l], tm64, in, out, r, colour);
     else if (c->n[l] % 2 == 0 && c->n[l] <= 32)
-        probe_launch(pr, k_pass_W_quad<T>, dim3(nblk(2 * c->cells[l])), dim3(kBlock), c->s, c->geo[l], in, out, r,
+        probe_launch(pr, k_pass_W_quad<T>, dim3(nblk(2 * c->cells[l]), 1, c->gz), dim3(kBlock), c->s, c->geo[l], in, out, r,
                      colour);
     else
-        probe_launch(pr, k_pass_W<T>, dim3(nblk(c->cells[l])), dim3(kBlock), c->s, c->geo[l], in, out, r, colour);
+        probe_launch(pr, k_pass_W<T>, dim3(nblk(c->cells[l]), 1, c->gz), dim3(kBlock), c->s, c->geo[l], in, out, r, colour);
 }
 
 template <typename T>
@@ -709,14 +716,14 @@ void vcycle_W(mg_ctx *c, int l, bool first_done = false)
 {
     if (c->tail_W_on && l == c->tail_W) {
         Probe pr(c, MG_PROBE_COARSE, c->L - 1);
-        hipLaunchKernelGGL(k_tail_W<T>, dim3(1), dim3(kTailThreads), 0, c->s, tail_args<T>(c, l, true));
+        hipLaunchKernelGGL(k_tail_W<T>, dim3(1, 1, c->gz), dim3(kTailThreads), 0, c->s, tail_args<T>(c, l, true));
         return;
     }
     if (l == c->L - 1) {
         coarse_W<T>(c, (const T *)c->wr[l], (T *)c->wd0[l]);
         return;
     }
-    if (!first_done) fill<T>(c->s, (T *)c->wd0[l], 3 * c->cells[l], T(0));
+    if (!first_done) fill<T>(c->s, (T *)c->wd0[l], 3 * c->cells[l], T(0), c->gz, c->zs);
     smooth_W<T>(c, l, c->p.nu_pre, first_done);
     // the next level is smoothed by grid launches (not the coarsest, not a tail)
     const bool next_first = l + 2 < c->L && !(c->tail_W_on && l + 1 == c->tail_W);
@@ -738,17 +745,17 @@ void source_mean(mg_ctx *c, const double *u, bool sums_ready = false)
     const Geo &g = c->geo[0];
     const int64_t nb = sum_blocks(c->cells[0]);
     if (c->p.bc == MG_BC_PERIODIC && !sums_ready)
-        hipLaunchKernelGGL(k_source_sum<kBcPeriodic>, dim3(nb), dim3(kBlock), 0, c->s, g, u, c->S,
+        hipLaunchKernelGGL(k_source_sum<kBcPeriodic>, dim3(nb, 1, c->gz), dim3(kBlock), 0, c->s, g, u, c->S,
                            c->p.puncture_mass, (c->p.flags & MG_FLAG_CONFORMAL_MATTER) ? 1 : 0,
                            c->part);
-    hipLaunchKernelGGL(k_reduce_final<3>, dim3(1), dim3(kBlock), 0, c->s, (const double *)c->part, nb,
-                       0u, 1.0 / (double)c->cells[0], c->scal + S_MEANS);
+    hipLaunchKernelGGL(k_reduce_final<3>, dim3(1, 1, c->gz), dim3(kBlock), 0, c->s, (const double *)c->part, nb,
+                       0u, 1.0 / (double)c->cells[0], c->scal + S_MEANS, c->zs);
 }
 
 template <int BC, typename T, int TX>
 void launch_residual_tx(hipStream_t s, const Geo &g, const TileMap &tm, const ResArgs &a, bool hasW)
 {
-    const dim3 blk(kLanes, kTY), grid(ntiles(tm));
+    const dim3 blk(kLanes, kTY), grid(ntiles(tm), 1, g.gz);
     if (hasW)
         hipLaunchKernelGGL((k_residual_tiled<BC, T, TX, true>), grid, blk, 0, s, g, tm, a);
     else
@@ -758,7 +765,7 @@ void launch_residual_tx(hipStream_t s, const Geo &g, const TileMap &tm, const Re
 template <typename T, int LX>
 void launch_residual_march(hipStream_t s, const Geo &g, const TileMap &tm, const ResArgs &a, bool hasW)
 {
-    const dim3 blk(kLanes, kTY), grid(ntiles(tm));
+    const dim3 blk(kLanes, kTY), grid(ntiles(tm), 1, g.gz);
     if (hasW)
         hipLaunchKernelGGL((k_residual_march<T, LX, true>), grid, blk, 0, s, g, tm, a);
     else
@@ -791,6 +798,7 @@ void residual(mg_ctx *c, const double *u, const double *W, bool want_M, double *
     a.u = u;
     a.psi0f = c->bg_psi0;
     a.A2bg = c->bg_A2;
+    a.K2p = c->K2p;
     a.W = W;
     a.rho5 = c->rho5;
     a.rho1 = c->rho1;
@@ -827,16 +835,16 @@ void residual(mg_ctx *c, const double *u, const double *W, bool want_M, double *
                     launch_residual_tiled<BCX, T>(c->s, c->geo[0], tm, a, W != nullptr);
                 });
         } else if (c->p.bc == MG_BC_PERIODIC)
-            hipLaunchKernelGGL((k_residual<kBcPeriodic, T>), dim3(nb), dim3(kBlock), 0, c->s, c->geo[0], a);
+            hipLaunchKernelGGL((k_residual<kBcPeriodic, T>), dim3(nb, 1, c->gz), dim3(kBlock), 0, c->s, c->geo[0], a);
         else
             with_bc(c->p.bc, [&](auto bcx) {
                 constexpr int BCX = decltype(bcx)::value;
-                hipLaunchKernelGGL((k_residual<BCX, T>), dim3(nb), dim3(kBlock), 0, c->s, c->geo[0], a);
+                hipLaunchKernelGGL((k_residual<BCX, T>), dim3(nb, 1, c->gz), dim3(kBlock), 0, c->s, c->geo[0], a);
             });
     }
     if (norms)
-        hipLaunchKernelGGL(k_reduce_final<4>, dim3(1), dim3(kBlock), 0, c->s, (const double *)c->part, nb,
-                           0xAu, 0.0, c->scal + S_NORM);
+        hipLaunchKernelGGL(k_reduce_final<4>, dim3(1, 1, c->gz), dim3(kBlock), 0, c->s, (const double *)c->part, nb,
+                           0xAu, 0.0, c->scal + S_NORM, c->zs);
 }
 
 template <typename T>
@@ -850,14 +858,14 @@ void step_W(mg_ctx *c, const double *u, double *W, bool residual_done)
     vcycle_W<T>(c, 0, true);
     const int64_t m = c->cells[0];
     const int64_t nb = nblk(m), sb = sum_blocks(m);
-    hipLaunchKernelGGL(k_sum3<T>, dim3(sb), dim3(kBlock), 0, c->s, (const T *)c->wd0[0], m, c->part);
-    hipLaunchKernelGGL(k_reduce_final<3>, dim3(1), dim3(kBlock), 0, c->s, (const double *)c->part, sb, 0u,
-                       1.0 / (double)m, c->scal + S_MEAND);
+    hipLaunchKernelGGL(k_sum3<T>, dim3(sb, 1, c->gz), dim3(kBlock), 0, c->s, (const T *)c->wd0[0], m, c->part, c->zs);
+    hipLaunchKernelGGL(k_reduce_final<3>, dim3(1, 1, c->gz), dim3(kBlock), 0, c->s, (const double *)c->part, sb, 0u,
+                       1.0 / (double)m, c->scal + S_MEAND, c->zs);
     {
         Probe pr(c, MG_PROBE_UPDATE, 0);
-        hipLaunchKernelGGL(k_update_W<T>, dim3(nb), dim3(kBlock), 0, c->s, W, (const T *)c->wd0[0],
+        hipLaunchKernelGGL(k_update_W<T>, dim3(nb, 1, c->gz), dim3(kBlock), 0, c->s, W, (const T *)c->wd0[0],
                            (const double *)(c->scal + S_MEAND), m,
-                           c->batched ? (const double *)(c->scal + S_ACTIVE) : nullptr);
+                           c->batched ? (const double *)(c->scal + S_ACTIVE) : nullptr, c->zs);
     }
     c->vc_W++;
 }
@@ -875,12 +883,12 @@ void step_psi(mg_ctx *c, double *u, const double *W, bool residual_done)
         Probe pr(c, MG_PROBE_UPDATE, 0);
         const double *gate = c->batched ? (const double *)(c->scal + S_ACTIVE) : nullptr;
         if (source_mean_needed(c)) // the update also sums the periodic source of the next evaluation
-            hipLaunchKernelGGL((k_update_u_source<kBcPeriodic, T>), dim3(sum_blocks(m)), dim3(kBlock), 0, c->s,
+            hipLaunchKernelGGL((k_update_u_source<kBcPeriodic, T>), dim3(sum_blocks(m), 1, c->gz), dim3(kBlock), 0, c->s,
                                c->geo[0], u, (const T *)c->pd0[0], gate, c->S, c->p.puncture_mass,
                                (c->p.flags & MG_FLAG_CONFORMAL_MATTER) ? 1 : 0, c->part);
         else
-            hipLaunchKernelGGL(k_update_u<T>, dim3(nblk(m)), dim3(kBlock), 0, c->s, u, (const T *)c->pd0[0], m,
-                               gate);
+            hipLaunchKernelGGL(k_update_u<T>, dim3(nblk(m), 1, c->gz), dim3(kBlock), 0, c->s, u, (const T *)c->pd0[0], m,
+                               gate, c->zs);
     }
     c->vc_psi++;
 }
@@ -943,9 +951,9 @@ void evaluate(mg_ctx *c, const double *u, const double *W, bool want_M, bool aft
     else
         residual<T>(c, u, W, want_M, nullptr, nullptr, nullptr, c->pr[0], c->pc[0], nullptr, true, true);
     if (c->batched)
-        hipLaunchKernelGGL(k_batch_check, dim3(1), dim3(64), 0, c->s, c->scal, (int)S_ACTIVE, (int)S_ITERS,
+        hipLaunchKernelGGL(k_batch_check, dim3(1, 1, c->gz), dim3(64), 0, c->s, c->scal, (int)S_ACTIVE, (int)S_ITERS,
                            (int)S_DIVERGED, 1.0 / (double)c->cells[0], c->batch_tol, c->momentum ? 1 : 0,
-                           after_update ? 1 : 0);
+                           after_update ? 1 : 0, c->zs);
 }
 
 // One outer update (W step, psi step) followed by the evaluation of the new state.
@@ -1039,7 +1047,7 @@ mg_status solve(mg_ctx *c, double *u, double *W, double tol, int max_outer, mg_r
         w1 = c->cont_prev;
     }
     c->cont_valid = false;
-    fill<double>(c->s, c->scal + S_FLAG_PSI, 2, 0.0);
+    fill<double>(c->s, c->scal + S_FLAG_PSI, 2, 0.0, c->gz, c->zs);
     if (!resume) {
         evaluate<T>(c, u, W, want_M);
         if (post_norms(c, 0) != MG_OK) return MG_ERR_HIP;
@@ -1473,6 +1481,9 @@ mg_status ctx_create(const mg_params *p, void *d_workspace, size_t bytes, hipStr
     c->bg_psi0 = nullptr;
     c->bg_A2 = nullptr;
     c->K2 = p->K * p->K;
+    c->gz = 1;
+    c->zs = 0;
+    c->K2p = nullptr;
     Carver cv{(char *)d_workspace};
     carve(c, cv);
     init_geo(c);
@@ -1514,36 +1525,102 @@ mg_status ctx_create(const mg_params *p, void *d_workspace, size_t bytes, hipStr
 
 constexpr int kBatchLanes = 4; // concurrent branches (stream pairs) of a batch
 
+// A batch.  Members with the same parameters (all but K) form a group; the members
+// of a group own equal workspace regions placed region_g bytes apart, each region
+// holding the member's context workspace and its own copies of the sources and of
+// the state, so that one launch with gridDim.z = group size runs a kernel for the
+// whole group (MG_BATCH_GROUPS, through a group context whose launches span the
+// group) and the member contexts run it member by member (MG_BATCH_GRAPH,
+// MG_BATCH_LANES).
 struct mg_batch {
-    int count;
-    mg_ctx **ctx;
+    int count, ngroups;
+    mg_ctx **ctx;    // member contexts
+    mg_ctx **gctx;   // per group: a context over member 0's region spanning the group (or member 0's own)
+    bool *gown;      // gctx[g] is a context of its own (group of more than one member)
+    int *gfirst;     // members of group g: order[gfirst[g] .. gfirst[g + 1])
+    int *order;      // region order -> member index
+    int *slot;       // member index -> block of scal_all
+    int *gof;        // member index -> group
+    size_t *gstride; // per group: bytes between consecutive members' regions
+    double **cu, **cW, **c5, **c1, **cS; // per member: device copies in its region
+    bool *hasW;      // per member: the caller passes W
     hipStream_t user_s, s;
     hipStream_t lane_s[kBatchLanes];
     hipEvent_t ev_in, ev_out, ev_root;
     hipEvent_t *ev_join;
-    double *scal_all; // device: count x S_COUNT, the members' scalar blocks
+    double *scal_all; // device: count x S_COUNT, the members' scalar blocks gathered after each iteration
     double *hpin;     // pinned copy of scal_all
     hipGraphExec_t gexec; // the whole batch as one graph (launch mode MG_BATCH_GRAPH)
-    double **g_u, **g_W;  // state pointers the graphs were captured for
+    bool captured_members, captured_groups;
     double g_tol;
     // launch mode: requested (MG_BATCH_AUTO tunes on the first solve), in use,
     // and the wall time of the tuning iteration in each mode
     int mode_req, mode;
-    double ms_graph, ms_lanes;
+    double ms_mode[3]; // graph, lanes, groups
 };
 
 namespace {
 
-size_t batch_layout(const mg_params *p, int count, size_t *offsets)
+// Parameters that must agree within a group (everything but K).
+bool same_group(const mg_params &a, const mg_params &b)
 {
-    size_t off = align_up((size_t)count * S_COUNT * sizeof(double), 256);
+    mg_params x = a, y = b;
+    x.K = y.K = 0.0;
+    return std::memcmp(&x, &y, sizeof(mg_params)) == 0;
+}
+
+// A group runs as one launch per kernel only if every kernel of its path takes the
+// member stride: the coarsest psi system must be solved by the Krylov kernels.
+bool groupable(const mg_params &p)
+{
+    const int nc = p.n >> (p.levels - 1);
+    return nc * nc * nc <= kKrylovMax;
+}
+
+struct BatchPlan {
+    int ngroups;
+    std::vector<int> gfirst, order, gof;
+    std::vector<size_t> gbase, gstride;
+    size_t total;
+};
+
+size_t member_region(const mg_params &p)
+{
+    size_t wb = 0;
+    mg_workspace_size(&p, &wb);
+    const size_t m = (size_t)p.n * p.n * p.n * sizeof(double);
+    // workspace, rho5, rho1, S (3), u, W (3)
+    return align_up(wb, 256) + 2 * align_up(m, 256) + align_up(3 * m, 256) + align_up(m, 256) + align_up(3 * m, 256);
+}
+
+BatchPlan batch_plan(const mg_params *p, int count)
+{
+    BatchPlan pl;
+    pl.gof.assign(count, -1);
     for (int i = 0; i < count; i++) {
-        size_t b = 0;
-        mg_workspace_size(&p[i], &b);
-        if (offsets) offsets[i] = off;
-        off = align_up(off + b, 256);
+        if (pl.gof[i] >= 0) continue;
+        const int g = (int)pl.gfirst.size();
+        pl.gfirst.push_back((int)pl.order.size());
+        pl.gof[i] = g;
+        pl.order.push_back(i);
+        if (!groupable(p[i])) continue;
+        for (int j = i + 1; j < count; j++)
+            if (pl.gof[j] < 0 && same_group(p[i], p[j])) {
+                pl.gof[j] = g;
+                pl.order.push_back(j);
+            }
     }
-    return off;
+    pl.ngroups = (int)pl.gfirst.size();
+    pl.gfirst.push_back(count);
+    size_t off = align_up((size_t)count * S_COUNT * sizeof(double), 256);
+    for (int g = 0; g < pl.ngroups; g++) {
+        const size_t r = align_up(member_region(p[pl.order[pl.gfirst[g]]]), 256);
+        pl.gbase.push_back(off);
+        pl.gstride.push_back(r);
+        off += r * (size_t)(pl.gfirst[g + 1] - pl.gfirst[g]);
+    }
+    pl.total = off;
+    return pl;
 }
 
 void batch_release(mg_batch *b)
@@ -1551,6 +1628,9 @@ void batch_release(mg_batch *b)
     if (!b) return;
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     if (b->s) (void)hipStreamSynchronize(b->s);
+    if (b->gctx && b->gown)
+        for (int g = 0; g < b->ngroups; g++)
+            if (b->gctx[g] && b->gown[g]) release(b->gctx[g]);
     if (b->ctx)
         for (int i = 0; i < b->count; i++)
             if (b->ctx[i]) release(b->ctx[i]);
@@ -1567,8 +1647,19 @@ void batch_release(mg_batch *b)
     if (b->s) (void)hipStreamDestroy(b->s);
     if (b->hpin) (void)hipHostFree(b->hpin);
     delete[] b->ctx;
-    delete[] b->g_u;
-    delete[] b->g_W;
+    delete[] b->gctx;
+    delete[] b->gown;
+    delete[] b->gfirst;
+    delete[] b->order;
+    delete[] b->slot;
+    delete[] b->gof;
+    delete[] b->gstride;
+    delete[] b->cu;
+    delete[] b->cW;
+    delete[] b->c5;
+    delete[] b->c1;
+    delete[] b->cS;
+    delete[] b->hasW;
     delete b;
 }
 
@@ -1586,11 +1677,29 @@ void batch_fork_join(mg_batch *b, F fn)
     }
 }
 
+// The same for the groups, on their lanes.
+template <typename F>
+void group_fork_join(mg_batch *b, F fn)
+{
+    (void)hipEventRecord(b->ev_root, b->s);
+    for (int g = 0; g < b->ngroups; g++) {
+        mg_ctx *c = b->gctx[g];
+        (void)hipStreamWaitEvent(c->s, b->ev_root, 0);
+        fn(g, c);
+        (void)hipEventRecord(b->ev_join[g], c->s);
+        (void)hipStreamWaitEvent(b->s, b->ev_join[g], 0);
+    }
+}
+
+double *member_W(const mg_batch *b, int i) { return b->hasW[i] ? b->cW[i] : nullptr; }
+bool want_M_of(const mg_batch *b, int i) { return b->ctx[i]->momentum || (b->ctx[i]->S && b->hasW[i]); }
+
 // Capture every member's outer iteration on the member's stream: each member
 // keeps its own executable graph (launch mode MG_BATCH_LANES) and the batch
-// graph holds them all as independent children (MG_BATCH_GRAPH).
+// graph holds them all as independent children (MG_BATCH_GRAPH).  The state
+// arrays are the members' own copies, so the graphs stay valid for every solve.
 template <typename T>
-mg_status batch_capture(mg_batch *b, double *const *u, double *const *W, double tol)
+mg_status batch_capture_members(mg_batch *b)
 {
     const int n = b->count;
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
@@ -1602,7 +1711,7 @@ mg_status batch_capture(mg_batch *b, double *const *u, double *const *W, double 
         mg_ctx *c = b->ctx[i];
         drop_graph(c);
         hipGraph_t g = nullptr;
-        st = capture_graph<T>(c, u[i], W[i], c->momentum || (c->S && W[i]), &g);
+        st = capture_graph<T>(c, b->cu[i], member_W(b, i), want_M_of(b, i), &g);
         if (st != MG_OK) break;
         hipGraphNode_t node = nullptr;
         if (hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
@@ -1611,8 +1720,8 @@ mg_status batch_capture(mg_batch *b, double *const *u, double *const *W, double 
         } else if (hipGraphAddChildGraphNode(&node, parent, nullptr, 0, g) != hipSuccess) {
             st = MG_ERR_HIP;
         }
-        c->g_u = u[i];
-        c->g_W = W[i];
+        c->g_u = b->cu[i];
+        c->g_W = member_W(b, i);
         (void)hipGraphDestroy(g);
     }
     if (st == MG_OK && hipGraphInstantiate(&b->gexec, parent, nullptr, nullptr, 0) != hipSuccess) {
@@ -1620,29 +1729,64 @@ mg_status batch_capture(mg_batch *b, double *const *u, double *const *W, double 
         st = MG_ERR_HIP;
     }
     (void)hipGraphDestroy(parent);
-    if (st != MG_OK) return st;
-    for (int i = 0; i < n; i++) {
-        b->g_u[i] = u[i];
-        b->g_W[i] = W[i];
+    if (st == MG_OK) b->captured_members = true;
+    return st;
+}
+
+// Capture every group's outer iteration on its group context: one launch per kernel
+// for all members of the group (MG_BATCH_GROUPS).
+template <typename T>
+mg_status batch_capture_groups(mg_batch *b)
+{
+    for (int g = 0; g < b->ngroups; g++) {
+        mg_ctx *c = b->gctx[g];
+        const int i = b->order[b->gfirst[g]];
+        drop_graph(c);
+        hipGraph_t gr = nullptr;
+        mg_status st = capture_graph<T>(c, b->cu[i], member_W(b, i), want_M_of(b, i), &gr);
+        if (st != MG_OK) return st;
+        const bool ok = hipGraphInstantiate(&c->gexec, gr, nullptr, nullptr, 0) == hipSuccess;
+        (void)hipGraphDestroy(gr);
+        if (!ok) {
+            c->gexec = nullptr;
+            return MG_ERR_HIP;
+        }
+        c->g_u = b->cu[i];
+        c->g_W = member_W(b, i);
     }
-    b->g_tol = tol;
+    b->captured_groups = true;
     return MG_OK;
 }
 
-// One outer iteration of the batch in launch mode `mode`: the batch graph on
-// the batch stream, or every still-active member's graph on the lane streams
-// (members spread round-robin over kBatchLanes streams, joined on the batch
-// stream).
+// Group g has an active member (host copy of the gathered scalars).
+bool group_active(const mg_batch *b, int g)
+{
+    for (int q = b->gfirst[g]; q < b->gfirst[g + 1]; q++)
+        if (b->hpin[b->slot[b->order[q]] * S_COUNT + S_ACTIVE] != 0.0) return true;
+    return false;
+}
+
+// One outer iteration of the batch in launch mode `mode`: the batch graph on the
+// batch stream, every still-active member's graph on the lane streams (members
+// spread round-robin over kBatchLanes streams), or every still-active group's
+// graph on its lane; joined on the batch stream.
 mg_status batch_launch(mg_batch *b, int mode)
 {
     if (mode == MG_BATCH_GRAPH) return hipGraphLaunch(b->gexec, b->s) == hipSuccess ? MG_OK : MG_ERR_HIP;
-    const int lanes = std::min(kBatchLanes, b->count);
+    const int lanes = std::min(kBatchLanes, mode == MG_BATCH_GROUPS ? b->ngroups : b->count);
     if (hipEventRecord(b->ev_root, b->s) != hipSuccess) return MG_ERR_HIP;
     for (int q = 0; q < lanes; q++)
         if (hipStreamWaitEvent(b->lane_s[q], b->ev_root, 0) != hipSuccess) return MG_ERR_HIP;
-    for (int i = 0; i < b->count; i++) {
-        if (b->hpin[i * S_COUNT + S_ACTIVE] == 0.0) continue; // converged or diverged: nothing to do
-        if (hipGraphLaunch(b->ctx[i]->gexec, b->ctx[i]->s) != hipSuccess) return MG_ERR_HIP;
+    if (mode == MG_BATCH_GROUPS) {
+        for (int g = 0; g < b->ngroups; g++) {
+            if (!group_active(b, g)) continue; // every member converged or diverged
+            if (hipGraphLaunch(b->gctx[g]->gexec, b->gctx[g]->s) != hipSuccess) return MG_ERR_HIP;
+        }
+    } else {
+        for (int i = 0; i < b->count; i++) {
+            if (b->hpin[b->slot[i] * S_COUNT + S_ACTIVE] == 0.0) continue; // nothing to do
+            if (hipGraphLaunch(b->ctx[i]->gexec, b->ctx[i]->s) != hipSuccess) return MG_ERR_HIP;
+        }
     }
     for (int q = 0; q < lanes; q++) {
         if (hipEventRecord(b->ev_join[q], b->lane_s[q]) != hipSuccess ||
@@ -1652,58 +1796,101 @@ mg_status batch_launch(mg_batch *b, int mode)
     return MG_OK;
 }
 
+// Every member's scalar block into scal_all (block slot[i]) and to the host.
+mg_status batch_read(mg_batch *b)
+{
+    for (int g = 0; g < b->ngroups; g++) {
+        const int k = b->gfirst[g + 1] - b->gfirst[g];
+        mg_ctx *c0 = b->ctx[b->order[b->gfirst[g]]];
+        hipLaunchKernelGGL(k_gather_scal, dim3(1, 1, k), dim3(64), 0, b->s, (const double *)c0->scal,
+                           (long long)b->gstride[g], (int)S_COUNT, b->scal_all + (size_t)b->gfirst[g] * S_COUNT);
+    }
+    if (hipMemcpyAsync(b->hpin, b->scal_all, (size_t)b->count * S_COUNT * sizeof(double), hipMemcpyDeviceToHost,
+                       b->s) != hipSuccess ||
+        hipStreamSynchronize(b->s) != hipSuccess)
+        return MG_ERR_HIP;
+    return MG_OK;
+}
+
 template <typename T>
 mg_status batch_solve(mg_batch *b, double *const *u, double *const *W, double tol, int max_outer, mg_report *reps)
 {
     auto t0 = std::chrono::steady_clock::now();
     const int n = b->count;
-    for (int i = 0; i < n; i++) b->ctx[i]->batch_tol = tol;
-    // reset flags; evaluate every member (eager)
-    batch_fork_join(b, [&](int i, mg_ctx *c) {
-        fill<double>(c->s, c->scal + S_FLAG_PSI, 2, 0.0);
-        fill<double>(c->s, c->scal + S_ITERS, 1, 0.0);
-        fill<double>(c->s, c->scal + S_DIVERGED, 1, 0.0);
-        fill<double>(c->s, c->scal + S_ACTIVE, 1, 1.0);
-        evaluate<T>(c, u[i], W[i], c->momentum || (c->S && W[i]), false);
-    });
-    bool same = b->gexec && b->g_tol == tol;
-    for (int i = 0; same && i < n; i++) same = b->g_u[i] == u[i] && b->g_W[i] == W[i];
-    if (!same) {
-        mg_status st = batch_capture<T>(b, u, W, tol);
-        if (st != MG_OK) return st;
+    // the callers' states into the members' copies
+    for (int i = 0; i < n; i++) {
+        const int64_t m = b->ctx[i]->cells[0];
+        if (hipMemcpyAsync(b->cu[i], u[i], m * sizeof(double), hipMemcpyDeviceToDevice, b->s) != hipSuccess)
+            return MG_ERR_HIP;
+        if (b->hasW[i] &&
+            hipMemcpyAsync(b->cW[i], W[i], 3 * m * sizeof(double), hipMemcpyDeviceToDevice, b->s) != hipSuccess)
+            return MG_ERR_HIP;
     }
+    if (b->g_tol != tol) {
+        for (int i = 0; i < n; i++) b->ctx[i]->batch_tol = tol;
+        for (int g = 0; g < b->ngroups; g++) b->gctx[g]->batch_tol = tol;
+        b->captured_members = b->captured_groups = false; // the check kernel carries tol
+        b->g_tol = tol;
+    }
+    // reset the flags and evaluate every member (eager, group launches)
+    group_fork_join(b, [&](int g, mg_ctx *c) {
+        const int i = b->order[b->gfirst[g]];
+        fill<double>(c->s, c->scal + S_FLAG_PSI, 2, 0.0, c->gz, c->zs);
+        fill<double>(c->s, c->scal + S_ITERS, 1, 0.0, c->gz, c->zs);
+        fill<double>(c->s, c->scal + S_DIVERGED, 1, 0.0, c->gz, c->zs);
+        fill<double>(c->s, c->scal + S_ACTIVE, 1, 1.0, c->gz, c->zs);
+        evaluate<T>(c, b->cu[i], member_W(b, i), want_M_of(b, i), false);
+    });
     int it = 0;
     for (;; it++) {
-        if (hipMemcpyAsync(b->hpin, b->scal_all, (size_t)n * S_COUNT * sizeof(double), hipMemcpyDeviceToHost,
-                           b->s) != hipSuccess ||
-            hipStreamSynchronize(b->s) != hipSuccess)
-            return MG_ERR_HIP;
+        mg_status rs = batch_read(b);
+        if (rs != MG_OK) return rs;
         int active = 0;
-        for (int i = 0; i < n; i++) active += b->hpin[i * S_COUNT + S_ACTIVE] != 0.0;
+        for (int i = 0; i < n; i++) active += b->hpin[b->slot[i] * S_COUNT + S_ACTIVE] != 0.0;
         if (active == 0 || it >= max_outer) break;
-        // launch-mode tuning: one timed outer iteration in each mode (the two
-        // modes replay the same member graphs, so the results do not change)
+        // launch-mode tuning: one timed outer iteration in each mode (every mode runs
+        // the same kernels on the same arrays, so the results do not change)
         int mode = b->mode;
         const bool tune = b->mode_req == MG_BATCH_AUTO && b->mode == MG_BATCH_AUTO;
-        if (tune) mode = (b->ms_graph < 0.0) ? MG_BATCH_GRAPH : MG_BATCH_LANES;
+        if (tune) mode = b->ms_mode[0] < 0.0 ? MG_BATCH_GRAPH : b->ms_mode[1] < 0.0 ? MG_BATCH_LANES : MG_BATCH_GROUPS;
+        if ((mode == MG_BATCH_GRAPH || mode == MG_BATCH_LANES) && !b->captured_members) {
+            mg_status cs = batch_capture_members<T>(b);
+            if (cs != MG_OK) return cs;
+        }
+        if (mode == MG_BATCH_GROUPS && !b->captured_groups) {
+            mg_status cs = batch_capture_groups<T>(b);
+            if (cs != MG_OK) return cs;
+        }
+        if (tune && hipStreamSynchronize(b->s) != hipSuccess) return MG_ERR_HIP;
         const auto l0 = std::chrono::steady_clock::now();
         mg_status ls = batch_launch(b, mode);
         if (ls != MG_OK) return ls;
         if (tune) {
             if (hipStreamSynchronize(b->s) != hipSuccess) return MG_ERR_HIP;
-            const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - l0).count();
-            if (mode == MG_BATCH_GRAPH)
-                b->ms_graph = ms;
-            else {
-                b->ms_lanes = ms;
-                b->mode = b->ms_lanes < b->ms_graph ? MG_BATCH_LANES : MG_BATCH_GRAPH;
+            b->ms_mode[mode - 1] =
+                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - l0).count();
+            if (mode == MG_BATCH_GROUPS) {
+                int best = MG_BATCH_GRAPH;
+                for (int q = MG_BATCH_LANES; q <= MG_BATCH_GROUPS; q++)
+                    if (b->ms_mode[q - 1] < b->ms_mode[best - 1]) best = q;
+                b->mode = best;
             }
         }
     }
+    // the members' states back to the callers' arrays
+    for (int i = 0; i < n; i++) {
+        const int64_t m = b->ctx[i]->cells[0];
+        if (hipMemcpyAsync(u[i], b->cu[i], m * sizeof(double), hipMemcpyDeviceToDevice, b->s) != hipSuccess)
+            return MG_ERR_HIP;
+        if (b->hasW[i] &&
+            hipMemcpyAsync(W[i], b->cW[i], 3 * m * sizeof(double), hipMemcpyDeviceToDevice, b->s) != hipSuccess)
+            return MG_ERR_HIP;
+    }
+    if (hipStreamSynchronize(b->s) != hipSuccess) return MG_ERR_HIP;
     auto t1 = std::chrono::steady_clock::now();
     mg_status worst = MG_OK;
     for (int i = 0; i < n; i++) {
-        const double *h = b->hpin + i * S_COUNT;
+        const double *h = b->hpin + (size_t)b->slot[i] * S_COUNT;
         const double inv = 1.0 / (double)b->ctx[i]->cells[0];
         mg_status st = h[S_ACTIVE] != 0.0 ? MG_ERR_NOT_CONVERGED : MG_OK;
         if (h[S_DIVERGED] != 0.0) st = MG_ERR_DIVERGED;
@@ -1778,7 +1965,7 @@ mg_status scalar_sources(const mg_params *p, int n_phi, const double *h_phi_mode
     if (want_mean) {
         double *res = scratch_d + kSrcBlocks;
         hipLaunchKernelGGL(k_reduce_final<1>, dim3(1), dim3(kBlock), 0, s, (const double *)part,
-                           (int64_t)nb, 0u, 1.0 / (double)m, res);
+                           (int64_t)nb, 0u, 1.0 / (double)m, res, 0LL);
         double mean = 0.0;
         if (hipMemcpyAsync(&mean, res, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
             return MG_ERR_HIP;
@@ -1843,7 +2030,7 @@ mg_status mg_batch_workspace_size(const mg_params *p, int32_t count, size_t *byt
         if (st != MG_OK) return st;
         if (p[i].precision != p[0].precision) return MG_ERR_INVALID;
     }
-    *bytes = batch_layout(p, count, nullptr);
+    *bytes = batch_plan(p, count).total;
     return MG_OK;
 }
 
@@ -1862,21 +2049,43 @@ mg_status mg_setup_batch(const mg_params *p, int32_t count, void *d_workspace, s
         if (p[i].solve_momentum && (!d_S || !d_S[i])) return MG_ERR_INVALID;
     }
     if (!d_workspace || bytes < need || ((uintptr_t)d_workspace % 256) != 0) return MG_ERR_WORKSPACE;
+    const BatchPlan pl = batch_plan(p, count);
     mg_batch *b = new (std::nothrow) mg_batch;
     if (!b) return MG_ERR_INVALID;
     std::memset(b, 0, sizeof(*b));
     b->count = count;
+    b->ngroups = pl.ngroups;
     b->user_s = (hipStream_t)stream;
     b->mode_req = b->mode = MG_BATCH_AUTO;
-    b->ms_graph = b->ms_lanes = -1.0;
+    b->ms_mode[0] = b->ms_mode[1] = b->ms_mode[2] = -1.0;
+    b->g_tol = -1.0;
     b->ctx = new (std::nothrow) mg_ctx *[count]();
+    b->gctx = new (std::nothrow) mg_ctx *[pl.ngroups]();
+    b->gown = new (std::nothrow) bool[pl.ngroups]();
+    b->gfirst = new (std::nothrow) int[pl.ngroups + 1]();
+    b->order = new (std::nothrow) int[count]();
+    b->slot = new (std::nothrow) int[count]();
+    b->gof = new (std::nothrow) int[count]();
+    b->gstride = new (std::nothrow) size_t[pl.ngroups]();
+    b->cu = new (std::nothrow) double *[count]();
+    b->cW = new (std::nothrow) double *[count]();
+    b->c5 = new (std::nothrow) double *[count]();
+    b->c1 = new (std::nothrow) double *[count]();
+    b->cS = new (std::nothrow) double *[count]();
+    b->hasW = new (std::nothrow) bool[count]();
     b->ev_join = new (std::nothrow) hipEvent_t[count]();
-    b->g_u = new (std::nothrow) double *[count]();
-    b->g_W = new (std::nothrow) double *[count]();
-    if (!b->ctx || !b->ev_join || !b->g_u || !b->g_W) {
+    if (!b->ctx || !b->gctx || !b->gown || !b->gfirst || !b->order || !b->slot || !b->gof || !b->gstride || !b->cu ||
+        !b->cW || !b->c5 || !b->c1 || !b->cS || !b->hasW || !b->ev_join) {
         batch_release(b);
         return MG_ERR_INVALID;
     }
+    for (int g = 0; g <= pl.ngroups; g++) b->gfirst[g] = pl.gfirst[g];
+    for (int q = 0; q < count; q++) {
+        b->order[q] = pl.order[q];
+        b->slot[pl.order[q]] = q;
+        b->gof[q] = pl.gof[q];
+    }
+    for (int g = 0; g < pl.ngroups; g++) b->gstride[g] = pl.gstride[g];
     bool ok = hipStreamCreateWithFlags(&b->s, hipStreamNonBlocking) == hipSuccess;
     for (int q = 0; q < kBatchLanes && ok; q++)
         ok = hipStreamCreateWithFlags(&b->lane_s[q], hipStreamNonBlocking) == hipSuccess;
@@ -1885,43 +2094,79 @@ mg_status mg_setup_batch(const mg_params *p, int32_t count, void *d_workspace, s
          hipEventCreateWithFlags(&b->ev_root, hipEventDisableTiming) == hipSuccess;
     for (int i = 0; i < count && ok; i++)
         ok = hipEventCreateWithFlags(&b->ev_join[i], hipEventDisableTiming) == hipSuccess;
-    ok = ok && hipHostMalloc((void **)&b->hpin, (size_t)count * S_COUNT * sizeof(double),
-                             hipHostMallocDefault) == hipSuccess;
+    ok = ok && hipHostMalloc((void **)&b->hpin, (size_t)count * S_COUNT * sizeof(double), hipHostMallocDefault) ==
+                   hipSuccess;
     if (!ok) {
         batch_release(b);
         return MG_ERR_HIP;
     }
     b->scal_all = (double *)d_workspace;
-    size_t *offs = new (std::nothrow) size_t[count];
-    if (!offs) {
-        batch_release(b);
-        return MG_ERR_INVALID;
-    }
-    batch_layout(p, count, offs);
     // members run after the work already on the caller's stream
     (void)hipEventRecord(b->ev_in, b->user_s);
     for (int q = 0; q < kBatchLanes; q++) (void)hipStreamWaitEvent(b->lane_s[q], b->ev_in, 0);
-    for (int i = 0; i < count; i++) {
-        size_t wb = 0;
-        mg_workspace_size(&p[i], &wb);
-        st = ctx_create(&p[i], (char *)d_workspace + offs[i], wb, b->lane_s[i % kBatchLanes], d_rho5[i],
-                        d_rho1[i], d_S ? d_S[i] : nullptr, nullptr, b->lane_s[i % kBatchLanes], &b->ctx[i]);
-        if (st != MG_OK) {
-            delete[] offs;
-            batch_release(b);
-            return st;
+    for (int g = 0; g < pl.ngroups && st == MG_OK; g++) {
+        hipStream_t ls = b->lane_s[g % kBatchLanes];
+        for (int q = pl.gfirst[g]; q < pl.gfirst[g + 1] && st == MG_OK; q++) {
+            const int i = pl.order[q];
+            size_t wb = 0;
+            mg_workspace_size(&p[i], &wb);
+            const size_t m = (size_t)p[i].n * p[i].n * p[i].n * sizeof(double);
+            char *r = (char *)d_workspace + pl.gbase[g] + (size_t)(q - pl.gfirst[g]) * pl.gstride[g];
+            char *cp = r + align_up(wb, 256);
+            b->c5[i] = (double *)cp;
+            b->c1[i] = (double *)(cp + align_up(m, 256));
+            b->cS[i] = (double *)(cp + 2 * align_up(m, 256));
+            b->cu[i] = (double *)(cp + 2 * align_up(m, 256) + align_up(3 * m, 256));
+            b->cW[i] = (double *)(cp + 3 * align_up(m, 256) + align_up(3 * m, 256));
+            const bool hasS = d_S && d_S[i];
+            if (hipMemcpyAsync(b->c5[i], d_rho5[i], m, hipMemcpyDeviceToDevice, ls) != hipSuccess ||
+                hipMemcpyAsync(b->c1[i], d_rho1[i], m, hipMemcpyDeviceToDevice, ls) != hipSuccess ||
+                (hasS && hipMemcpyAsync(b->cS[i], d_S[i], 3 * m, hipMemcpyDeviceToDevice, ls) != hipSuccess)) {
+                st = MG_ERR_HIP;
+                break;
+            }
+            st = ctx_create(&p[i], r, wb, ls, b->c5[i], b->c1[i], hasS ? b->cS[i] : nullptr, nullptr, ls, &b->ctx[i]);
+            if (st != MG_OK) break;
+            mg_ctx *c = b->ctx[i];
+            c->batched = true;
+            c->user_s = b->s;
+            c->K2p = c->scal + S_K2;
         }
-        mg_ctx *c = b->ctx[i];
-        c->batched = true;
-        c->scal = b->scal_all + (size_t)i * S_COUNT;
-        c->user_s = b->s;
-        fill<double>(c->s, c->scal, S_COUNT, 0.0);
+        if (st != MG_OK) break;
+        // the group's context: member 0's region, launches spanning the group
+        const int k = pl.gfirst[g + 1] - pl.gfirst[g];
+        const int i0 = pl.order[pl.gfirst[g]];
+        if (k == 1) {
+            b->gctx[g] = b->ctx[i0];
+            continue;
+        }
+        size_t wb = 0;
+        mg_workspace_size(&p[i0], &wb);
+        char *r0 = (char *)d_workspace + pl.gbase[g];
+        st = ctx_create(&p[i0], r0, wb, ls, b->c5[i0], b->c1[i0], b->ctx[i0]->S, nullptr, ls, &b->gctx[g]);
+        if (st != MG_OK) break;
+        b->gown[g] = true;
+        mg_ctx *gc = b->gctx[g];
+        gc->batched = true;
+        gc->user_s = b->s;
+        gc->K2p = gc->scal + S_K2;
+        gc->gz = k;
+        gc->zs = (long long)pl.gstride[g];
+        for (int l = 0; l < gc->L; l++) {
+            gc->geo[l].gz = k;
+            gc->geo[l].zs = gc->zs;
+        }
     }
-    delete[] offs;
+    // K^2 of every member into its scalar block (after every context's set-up)
+    for (int i = 0; i < count && st == MG_OK; i++) {
+        mg_ctx *c = b->ctx[i];
+        fill<double>(c->s, c->scal + S_K2, 1, p[i].K * p[i].K);
+    }
     for (int q = 0; q < kBatchLanes; q++) (void)hipStreamSynchronize(b->lane_s[q]);
-    if (hip_status() != MG_OK) {
+    if (st == MG_OK && hip_status() != MG_OK) st = MG_ERR_HIP;
+    if (st != MG_OK) {
         batch_release(b);
-        return MG_ERR_HIP;
+        return st;
     }
     *out = b;
     return MG_OK;
@@ -1935,6 +2180,19 @@ mg_status mg_solve_batch(mg_batch *b, double *const *d_u, double *const *d_W, do
         if (!d_u[i]) return MG_ERR_INVALID;
         if (b->ctx[i]->momentum && (!d_W || !d_W[i])) return MG_ERR_INVALID;
     }
+    // W given or not must agree within a group (one launch serves all of them)
+    for (int g = 0; g < b->ngroups; g++)
+        for (int q = b->gfirst[g]; q < b->gfirst[g + 1]; q++) {
+            const int i = b->order[q], i0 = b->order[b->gfirst[g]];
+            if ((d_W && d_W[i]) != (d_W && d_W[i0])) return MG_ERR_INVALID;
+        }
+    bool changed = false;
+    for (int i = 0; i < b->count; i++) {
+        const bool h = d_W && d_W[i];
+        changed = changed || h != b->hasW[i];
+        b->hasW[i] = h;
+    }
+    if (changed) b->captured_members = b->captured_groups = false;
     (void)hipEventRecord(b->ev_in, b->user_s);
     (void)hipStreamWaitEvent(b->s, b->ev_in, 0);
     double *const *W = d_W;
@@ -1954,19 +2212,26 @@ mg_status mg_solve_batch(mg_batch *b, double *const *d_u, double *const *d_W, do
 
 void mg_destroy_batch(mg_batch *b) { batch_release(b); }
 
-mg_status mg_batch_launch_mode(mg_batch *b, int32_t request, int32_t *chosen, double h_ms[2])
+mg_status mg_batch_launch_mode(mg_batch *b, int32_t request, int32_t *chosen, double h_ms[3])
 {
-    if (!b || request < -1 || request > MG_BATCH_LANES) return MG_ERR_INVALID;
+    if (!b || request < -1 || request > MG_BATCH_GROUPS) return MG_ERR_INVALID;
     if (request >= 0) {
         b->mode_req = request;
         b->mode = request;
-        if (request == MG_BATCH_AUTO) b->ms_graph = b->ms_lanes = -1.0;
+        if (request == MG_BATCH_AUTO) b->ms_mode[0] = b->ms_mode[1] = b->ms_mode[2] = -1.0;
     }
     if (chosen) *chosen = b->mode;
-    if (h_ms) {
-        h_ms[0] = b->ms_graph;
-        h_ms[1] = b->ms_lanes;
-    }
+    if (h_ms)
+        for (int q = 0; q < 3; q++) h_ms[q] = b->ms_mode[q];
+    return MG_OK;
+}
+
+mg_status mg_batch_groups(mg_batch *b, int32_t *h_ngroups, int32_t *h_group_of)
+{
+    if (!b) return MG_ERR_INVALID;
+    if (h_ngroups) *h_ngroups = b->ngroups;
+    if (h_group_of)
+        for (int i = 0; i < b->count; i++) h_group_of[i] = b->gof[i];
     return MG_OK;
 }
 

@@ -32,6 +32,12 @@ struct Geo {
     double inv144h2; // 1 / (144 h^2)
     double org[3];
     double ctr[3];
+    // Grouped launches of a batch: gz members of one size run in one launch, member
+    // blockIdx.z on arrays zs bytes after member 0's (every array of a member lies in
+    // one workspace region, the regions of a group zs bytes apart).  gz = 1, zs = 0
+    // for a single instance.
+    int gz;
+    long long zs;
 };
 
 __host__ __device__ inline Geo make_geo(int n, int bc, double length, const double org[3],
@@ -48,7 +54,20 @@ __host__ __device__ inline Geo make_geo(int n, int bc, double length, const doub
         g.org[a] = org[a];
         g.ctr[a] = ctr[a];
     }
+    g.gz = 1;
+    g.zs = 0;
     return g;
+}
+
+// Pointer p of member 0 moved to this block's member (blockIdx.z) of a grouped
+// launch; null stays null.
+// The move is byte arithmetic on the pointer itself, so that the result stays based
+// on the (restrict-qualified) argument for the compiler's aliasing analysis.
+template <typename P>
+__device__ __forceinline__ P *zsh(P *p, long long zs)
+{
+    using B = std::conditional_t<std::is_const_v<P>, const char, char>;
+    return p ? reinterpret_cast<P *>(reinterpret_cast<B *>(p) + (long long)blockIdx.z * zs) : p;
 }
 
 __device__ __forceinline__ int64_t lidx(int n, int i, int j, int k)

@@ -48,6 +48,7 @@ struct ResArgs {
     // of an analytic traceless extrinsic curvature added to the one of W
     const double *psi0f, *A2bg;
     const double *meanS; // device, 3 values (periodic momentum source mean)
+    const double *K2p;   // device K^2 of the member (grouped batches), else null: K2
     double K2, pmass;
     double *H, *M, *c;
     void *r, *rc, *rW; // T
@@ -59,6 +60,32 @@ struct ResArgs {
     int want_M;        // compute momentum residual
     int conformal;     // matter given as rho_bar = psi^8 rho, S_bar = psi^6 S
 };
+
+// Every array of a ResArgs moved to this block's member of a grouped launch.
+__device__ __forceinline__ ResArgs res_shift(ResArgs a, long long zs)
+{
+    if (zs == 0) return a;
+    a.u = zsh(a.u, zs);
+    a.W = zsh(a.W, zs);
+    a.rho5 = zsh(a.rho5, zs);
+    a.rho1 = zsh(a.rho1, zs);
+    a.S = zsh(a.S, zs);
+    a.f = zsh(a.f, zs);
+    a.psi0f = zsh(a.psi0f, zs);
+    a.A2bg = zsh(a.A2bg, zs);
+    a.meanS = zsh(a.meanS, zs);
+    a.K2p = zsh(a.K2p, zs);
+    a.H = zsh(a.H, zs);
+    a.M = zsh(a.M, zs);
+    a.c = zsh(a.c, zs);
+    a.r = zsh(a.r, zs);
+    a.rc = zsh(a.rc, zs);
+    a.rW = zsh(a.rW, zs);
+    a.partials = zsh(a.partials, zs);
+    a.d1 = zsh(a.d1, zs);
+    a.d1W = zsh(a.d1W, zs);
+    return a;
+}
 
 // The finest level's first colour pass from a zero correction at cell (x, y, z),
 // written beside the right-hand side (colour 0: r / diag as the pass kernels
@@ -86,6 +113,8 @@ __device__ __forceinline__ void first_pass_fine(const Geo &g, const ResArgs &a, 
 template <int BC, typename T>
 __global__ void __launch_bounds__(kBlock) k_residual(Geo g, ResArgs a)
 {
+    a = res_shift(a, g.zs);
+    if (a.K2p) a.K2 = *a.K2p;
     const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int n = g.n;
     const int64_t m = (int64_t)n * n * n;
@@ -202,6 +231,9 @@ __global__ void __launch_bounds__(kBlock) k_source_sum(Geo g, const double *u, c
                                                        double pmass, int conformal,
                                                        double *partials)
 {
+    u = zsh(u, g.zs);
+    S = zsh(S, g.zs);
+    partials = zsh(partials, g.zs);
     const int n = g.n;
     const int64_t m = (int64_t)n * n * n;
     double v[3] = {0.0, 0.0, 0.0};
@@ -221,8 +253,10 @@ __global__ void __launch_bounds__(kBlock) k_source_sum(Geo g, const double *u, c
 
 // Per-block partial sums of the three components of a vector field.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_sum3(const T *a, int64_t m, double *partials)
+__global__ void __launch_bounds__(kBlock) k_sum3(const T *a, int64_t m, double *partials, long long zs)
 {
+    a = zsh(a, zs);
+    partials = zsh(partials, zs);
     double v[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int c = 0; c < kSumCells; c++) {
@@ -241,8 +275,10 @@ __global__ void __launch_bounds__(kBlock) k_sum3(const T *a, int64_t m, double *
 template <int NV>
 __global__ void __launch_bounds__(kBlock) k_reduce_final(const double *partials, int64_t nblocks,
                                                          unsigned max_mask, double scale,
-                                                         double *out)
+                                                         double *out, long long zs)
 {
+    partials = zsh(partials, zs);
+    out = zsh(out, zs);
     double v[NV];
 #pragma unroll
     for (int q = 0; q < NV; q++) v[q] = 0.0;
@@ -295,6 +331,10 @@ __global__ void __launch_bounds__(kBlock) k_pass_psi(Geo g, const T *__restrict_
                                                      T *__restrict__ out, const T *__restrict__ r,
                                                      const T *__restrict__ c, int colour)
 {
+    in = zsh(in, g.zs);
+    out = zsh(out, g.zs);
+    r = zsh(r, g.zs);
+    c = zsh(c, g.zs);
     const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     int i, j, k;
     if (!cell_of(tid, g.n, i, j, k)) return;
@@ -437,6 +477,9 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock) k_pass_W_quad(Geo g, const T *__restrict__ in, T *__restrict__ out,
                                                         const T *__restrict__ r, int colour)
 {
+    in = zsh(in, g.zs);
+    out = zsh(out, g.zs);
+    r = zsh(r, g.zs);
     const int n = g.n;
     const unsigned t = blockIdx.x * kBlock + threadIdx.x;
     const int f = (int)(t & 3u);
@@ -465,6 +508,10 @@ __global__ void __launch_bounds__(kBlock) k_defect_restrict_W_quad(Geo g, const 
                                                                    const T *__restrict__ r, T *__restrict__ rc_out,
                                                                    T *__restrict__ d1_out, T idiag_c)
 {
+    d = zsh(d, g.zs);
+    r = zsh(r, g.zs);
+    rc_out = zsh(rc_out, g.zs);
+    d1_out = zsh(d1_out, g.zs);
     const int n = g.n, nc = n / 2;
     const unsigned t = blockIdx.x * kBlock + threadIdx.x;
     const int f = (int)(t & 3u), ch = (int)((t >> 2) & 7u);
@@ -494,6 +541,10 @@ __global__ void __launch_bounds__(kBlock) k_pass_psi_pairs(Geo g, const T *__res
                                                            const T *__restrict__ r, const T *__restrict__ c,
                                                            int colour)
 {
+    in = zsh(in, g.zs);
+    out = zsh(out, g.zs);
+    r = zsh(r, g.zs);
+    c = zsh(c, g.zs);
     const int n = g.n;
     int i, j, ka, kb;
     if (!pair_of(blockIdx.x * kBlock + threadIdx.x, n, colour, i, j, ka, kb)) return;
@@ -514,6 +565,9 @@ __global__ void __launch_bounds__(kBlock) k_pass_W(Geo g, const T *__restrict__ 
                                                    T *__restrict__ out, const T *__restrict__ r,
                                                    int colour)
 {
+    in = zsh(in, g.zs);
+    out = zsh(out, g.zs);
+    r = zsh(r, g.zs);
     const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     int i, j, k;
     if (!cell_of(tid, g.n, i, j, k)) return;
@@ -606,6 +660,12 @@ __global__ void __launch_bounds__(kBlock) k_defect_restrict_psi(Geo g, const T *
                                                                 T *__restrict__ cc_out, T *__restrict__ d1_out,
                                                                 Geo gc)
 {
+    d = zsh(d, g.zs);
+    r = zsh(r, g.zs);
+    c = zsh(c, g.zs);
+    rc_out = zsh(rc_out, g.zs);
+    cc_out = zsh(cc_out, g.zs);
+    d1_out = zsh(d1_out, g.zs);
     const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     int I, J, K;
     if (!cell_of(tid, g.n / 2, I, J, K)) return;
@@ -650,6 +710,12 @@ __global__ void __launch_bounds__(kBlock) k_defect_restrict_psi_fine(Geo g, cons
                                                                      T *__restrict__ cc_out, T *__restrict__ d1_out,
                                                                      Geo gc)
 {
+    d = zsh(d, g.zs);
+    r = zsh(r, g.zs);
+    c = zsh(c, g.zs);
+    rc_out = zsh(rc_out, g.zs);
+    cc_out = zsh(cc_out, g.zs);
+    d1_out = zsh(d1_out, g.zs);
     defect_restrict_psi_child<BC, T>(g, d, r, c, rc_out, cc_out, (int64_t)blockIdx.x * kBlock + threadIdx.x, d1_out,
                                      &gc);
 }
@@ -689,6 +755,10 @@ __global__ void __launch_bounds__(kBlock) k_defect_restrict_W(Geo g, const T *__
                                                               T *__restrict__ rc_out, T *__restrict__ d1_out,
                                                               T idiag_c)
 {
+    d = zsh(d, g.zs);
+    r = zsh(r, g.zs);
+    rc_out = zsh(rc_out, g.zs);
+    d1_out = zsh(d1_out, g.zs);
     const int nc = g.n / 2;
     const int64_t mf = (int64_t)g.n * g.n * g.n, mc = (int64_t)nc * nc * nc;
     const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -770,6 +840,8 @@ template <int BC, typename T>
 __global__ void __launch_bounds__(kBlock) k_prolong_add(Geo gc, const T *__restrict__ coarse,
                                                         T *__restrict__ fine, int ncomp)
 {
+    coarse = zsh(coarse, gc.zs);
+    fine = zsh(fine, gc.zs);
     const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     int i, j, k;
     if (!cell_of(tid, 2 * gc.n, i, j, k)) return;
@@ -965,8 +1037,11 @@ constexpr int kApplySplit = 16;
 constexpr int kApplyRows = kBlock / kApplySplit;
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_coarse_apply(const double *Ainv, int m,
-                                                         const T *r, T *x, int ncomp_project)
+                                                         const T *r, T *x, int ncomp_project, long long zs)
 {
+    Ainv = zsh(Ainv, zs);
+    r = zsh(r, zs);
+    x = zsh(x, zs);
     extern __shared__ double rs[];
     for (int q = threadIdx.x; q < m; q += kBlock) rs[q] = (double)r[q];
     __syncthreads();
@@ -1000,8 +1075,10 @@ __global__ void __launch_bounds__(kBlock) k_coarse_apply(const double *Ainv, int
 // coarse = average of the 8 children of fine (coefficient restriction alone);
 // same summation order as the fused defect-restriction kernels.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_restrict(int nf, const T *__restrict__ fine, T *__restrict__ coarse)
+__global__ void __launch_bounds__(kBlock) k_restrict(int nf, const T *__restrict__ fine, T *__restrict__ coarse, long long zs)
 {
+    fine = zsh(fine, zs);
+    coarse = zsh(coarse, zs);
     const int nc = nf / 2;
     const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     int I, J, K;
@@ -1420,6 +1497,10 @@ template <int BC, typename T>
 __global__ void __launch_bounds__(kGjWaves *kWave) k_coarse_psi_krylov(Geo g, int m, const T *c, const T *r, T *x,
                                                                       double *flag)
 {
+    c = zsh(c, g.zs);
+    r = zsh(r, g.zs);
+    x = zsh(x, g.zs);
+    flag = zsh(flag, g.zs);
     const bool ok = coarse_psi_krylov_block<BC, T>(g, m, c, r, x);
     if (!ok && threadIdx.x == 0) *flag = 1.0;
 }
@@ -1534,6 +1615,10 @@ template <int BC, typename T, int M>
 __global__ void __launch_bounds__(kGjWaves * kWave) k_coarse_psi_block(Geo g, const T *c, const T *r, T *x,
                                                                       double *flag)
 {
+    c = zsh(c, g.zs);
+    r = zsh(r, g.zs);
+    x = zsh(x, g.zs);
+    flag = zsh(flag, g.zs);
     coarse_psi_block_solve<BC, T, M>(g, c, r, x, flag);
 }
 
@@ -1642,6 +1727,14 @@ __device__ __forceinline__ void tail_psi_pass(const Geo &g, T *d, const T *r, co
 template <int BC, typename T, int M>
 __global__ void __launch_bounds__(kTailThreads) k_tail_psi(TailArgs<T> a)
 {
+    {
+        const long long zs = a.geo[0].zs;
+        a.r0 = zsh(a.r0, zs);
+        a.c0 = zsh(a.c0, zs);
+        a.d0 = zsh(a.d0, zs);
+        a.inv = zsh(a.inv, zs);
+        a.flag = zsh(a.flag, zs);
+    }
     __shared__ T buf[3 * TailCap<T>::kPsi];
     const int L = a.nl;
     int off[kMaxTail] = {0, 0, 0, 0};
@@ -1820,6 +1913,14 @@ __device__ __forceinline__ void tail_W_pass(const Geo &g, T *d, const T *r, T *s
 template <typename T>
 __global__ void __launch_bounds__(kTailThreads) k_tail_W(TailArgs<T> a)
 {
+    {
+        const long long zs = a.geo[0].zs;
+        a.r0 = zsh(a.r0, zs);
+        a.c0 = zsh(a.c0, zs);
+        a.d0 = zsh(a.d0, zs);
+        a.inv = zsh(a.inv, zs);
+        a.flag = zsh(a.flag, zs);
+    }
     __shared__ T buf[6 * TailCap<T>::kW];
     __shared__ T stage[kTailWStage];
     __shared__ double rs[1536];
@@ -1917,8 +2018,9 @@ __global__ void __launch_bounds__(kTailThreads) k_tail_W(TailArgs<T> a)
 // Elementwise helpers
 // ---------------------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_fill(T *a, int64_t count, T v)
+__global__ void __launch_bounds__(kBlock) k_fill(T *a, int64_t count, T v, long long zs)
 {
+    a = zsh(a, zs);
     const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (q < count) a[q] = v;
 }
@@ -1926,8 +2028,11 @@ __global__ void __launch_bounds__(kBlock) k_fill(T *a, int64_t count, T v)
 // u += d.  gate (nullable): the update is skipped when *gate == 0 (an instance
 // of a batch that has already converged).
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_update_u(double *u, const T *d, int64_t m, const double *gate)
+__global__ void __launch_bounds__(kBlock) k_update_u(double *u, const T *d, int64_t m, const double *gate, long long zs)
 {
+    u = zsh(u, zs);
+    d = zsh(d, zs);
+    gate = zsh(gate, zs);
     if (gate && *gate == 0.0) return;
     const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (q < m) u[q] += (double)d[q];
@@ -1941,6 +2046,11 @@ __global__ void __launch_bounds__(kBlock) k_update_u_source(Geo g, double *u, co
                                                             const double *S, double pmass, int conformal,
                                                             double *partials)
 {
+    u = zsh(u, g.zs);
+    d = zsh(d, g.zs);
+    gate = zsh(gate, g.zs);
+    S = zsh(S, g.zs);
+    partials = zsh(partials, g.zs);
     const bool upd = !(gate && *gate == 0.0);
     const int n = g.n;
     const int64_t m = (int64_t)n * n * n;
@@ -1967,8 +2077,12 @@ __global__ void __launch_bounds__(kBlock) k_update_u_source(Geo g, double *u, co
 // W_a += dW_a - mean_a (mean: device, 3 values); gate as for k_update_u
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_update_W(double *W, const T *d, const double *mean,
-                                                     int64_t m, const double *gate)
+                                                     int64_t m, const double *gate, long long zs)
 {
+    W = zsh(W, zs);
+    d = zsh(d, zs);
+    mean = zsh(mean, zs);
+    gate = zsh(gate, zs);
     if (gate && *gate == 0.0) return;
     const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (q >= m) return;
@@ -1983,8 +2097,9 @@ __global__ void __launch_bounds__(kBlock) k_update_W(double *W, const T *d, cons
 // instance stays active while rms H > tol or (momentum) rms |M| > tol and the
 // norms are finite; a non-finite norm marks it diverged.
 __global__ void k_batch_check(double *scal, int active_slot, int iters_slot, int div_slot, double inv_cells,
-                              double tol, int momentum, int count_update)
+                              double tol, int momentum, int count_update, long long zs)
 {
+    scal = zsh(scal, zs);
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const double was = scal[active_slot];
     if (was == 0.0) return;
@@ -1996,6 +2111,14 @@ __global__ void k_batch_check(double *scal, int active_slot, int iters_slot, int
         return;
     }
     if (h <= tol && (!momentum || mm <= tol)) scal[active_slot] = 0.0;
+}
+
+// The device scalars of the members of a group (block z: the member zs bytes after
+// member 0's block src) copied to consecutive blocks of dst, for one host copy.
+__global__ void k_gather_scal(const double *src, long long zs, int count, double *dst)
+{
+    src = zsh(src, zs);
+    if ((int)threadIdx.x < count) dst[(int64_t)blockIdx.z * count + threadIdx.x] = src[threadIdx.x];
 }
 
 // ---------------------------------------------------------------------------------------

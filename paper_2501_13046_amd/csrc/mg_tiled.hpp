@@ -75,6 +75,8 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock) k_prolong_add_pairs(Geo gc, const T *__restrict__ coarse,
                                                              T *__restrict__ fine, int ncomp)
 {
+    coarse = zsh(coarse, gc.zs);
+    fine = zsh(fine, gc.zs);
     using V2 = typename Vec2<T>::type;
     const int nc = gc.n, nf = 2 * nc;
     const unsigned pairs = (unsigned)nf * nf * nc;
@@ -296,6 +298,10 @@ __global__ void __launch_bounds__(kTY *kLanes) k_pass_psi_tiled(Geo g, TileMap t
                                                                T *__restrict__ out, const T *__restrict__ r,
                                                                const T *__restrict__ c, int colour)
 {
+    in = zsh(in, g.zs);
+    out = zsh(out, g.zs);
+    r = zsh(r, g.zs);
+    c = zsh(c, g.zs);
     __shared__ T lds[TX + 4][kPY][kPZ];
     int x0, y0, z0;
     brick_of(tm, x0, y0, z0);
@@ -406,6 +412,9 @@ __global__ void __launch_bounds__(kTY *kLanes) k_pass_W_tiled(Geo g, TileMap tm,
                                                              T *__restrict__ out, const T *__restrict__ r,
                                                              int colour)
 {
+    in = zsh(in, g.zs);
+    out = zsh(out, g.zs);
+    r = zsh(r, g.zs);
     __shared__ T lds[2][TX + 4][kPY][kPZ];
     int x0, y0, z0;
     brick_of(tm, x0, y0, z0);
@@ -609,6 +618,9 @@ __global__ void __launch_bounds__(kTY *kLanes) k_pass_W_march(Geo g, TileMap tm,
                                                              T *__restrict__ out, const T *__restrict__ r,
                                                              int colour)
 {
+    in = zsh(in, g.zs);
+    out = zsh(out, g.zs);
+    r = zsh(r, g.zs);
     using G = ZGeom<BZ>;
     __shared__ T lds[kRing][G::kNR][G::kPZB];
     int x0, y0, z0;
@@ -689,6 +701,10 @@ __global__ void __launch_bounds__(kTY *kLanes) k_defect_restrict_W_march(Geo g, 
                                                                         T *__restrict__ rc_out, T *__restrict__ d1_out,
                                                                         T idiag_c)
 {
+    d = zsh(d, g.zs);
+    r = zsh(r, g.zs);
+    rc_out = zsh(rc_out, g.zs);
+    d1_out = zsh(d1_out, g.zs);
     using G = ZGeom<BZ>;
     static_assert(LX % 2 == 0 && G::kTYB % 2 == 0, "whole coarse cells per column");
     using V2 = typename Vec2<T>::type;
@@ -925,7 +941,7 @@ __device__ __forceinline__ void residual_cell(const Geo &g, const ResArgs &a, in
 {
     const int n = g.n;
     const int m = n * n * n;
-    const double K2 = a.K2;
+    const double K2 = a.K2p ? *a.K2p : a.K2;
     const double third = 1.0 / 3.0, two_thirds = 2.0 / 3.0;
     const unsigned q = ((unsigned)x * (unsigned)n + (unsigned)y) * (unsigned)n + (unsigned)z;
     const double uc = elt(a.u, q);
@@ -1051,6 +1067,7 @@ __device__ __forceinline__ void residual_cell(const Geo &g, const ResArgs &a, in
 template <int BC, typename T, int TX, bool HAS_W>
 __global__ void __launch_bounds__(kTY *kLanes) k_residual_tiled(Geo g, TileMap tm, ResArgs a)
 {
+    a = res_shift(a, g.zs);
     __shared__ double lds[HAS_W ? 3 : 1][TX + 4][kPY][kRPZ];
     const int total = tm.nx * tm.ny * tm.nz;
     int logical = blockIdx.x;
@@ -1146,6 +1163,7 @@ struct RRing {
 template <typename T, int LX, bool HAS_W>
 __global__ void __launch_bounds__(kTY *kLanes) k_residual_march(Geo g, TileMap tm, ResArgs a)
 {
+    a = res_shift(a, g.zs);
     __shared__ double ring[HAS_W ? kRing : 1][HAS_W ? kRSlot : 1];
     const int total = tm.nx * tm.ny * tm.nz;
     int logical = blockIdx.x;

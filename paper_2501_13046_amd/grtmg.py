@@ -103,6 +103,7 @@ def lib() -> C.CDLL:
         L.mg_autotune.argtypes = [vp, vp, vp, i32, C.POINTER(MgTune), i32, C.POINTER(i32)]
         L.mg_set_tile.argtypes = [vp, i32, i32, i32]
         L.mg_batch_launch_mode.argtypes = [vp, i32, C.POINTER(i32), dp]
+        L.mg_batch_groups.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
         L.mg_fmg_start.argtypes = [vp, vp, vp, vp, C.c_double, i32, vp, vp, C.POINTER(MgReport)]
         L.mg_probe.argtypes = [vp, i32, i32]
         L.mg_probe_result.argtypes = [vp, C.POINTER(i32), C.POINTER(C.c_double)]
@@ -111,7 +112,7 @@ def lib() -> C.CDLL:
                   "mg_scalar_field_sources_static", "mg_set_background", "mg_bowen_york_sources",
                   "mg_shell_field_sources", "mg_interp_cubic", "mg_kernel_op", "mg_probe",
                   "mg_probe_result", "mg_batch_workspace_size", "mg_setup_batch", "mg_solve_batch",
-                  "mg_fmg_start", "mg_batch_launch_mode", "mg_autotune", "mg_set_tile"):
+                  "mg_fmg_start", "mg_batch_launch_mode", "mg_batch_groups", "mg_autotune", "mg_set_tile"):
             getattr(L, f).restype = st
         _lib = L
     return _lib
@@ -277,7 +278,7 @@ def _ptr_array(ts, dtype=torch.float64):
     return arr
 
 
-BATCH_AUTO, BATCH_GRAPH, BATCH_LANES = 0, 1, 2
+BATCH_AUTO, BATCH_GRAPH, BATCH_LANES, BATCH_GROUPS = 0, 1, 2, 3
 
 
 class Batch:
@@ -313,11 +314,18 @@ class Batch:
             pass
 
     def launch_mode(self, request: int = -1):
-        """Set (request >= 0) and/or query the launch mode: (mode in use, [ms graph, ms lanes])."""
+        """Set (request >= 0) and/or query the launch mode: (mode in use, [ms graph, ms lanes, ms groups])."""
         chosen = C.c_int32(0)
-        ms = (C.c_double * 2)()
+        ms = (C.c_double * 3)()
         _check(lib().mg_batch_launch_mode(self.b, request, C.byref(chosen), ms), "mg_batch_launch_mode")
-        return chosen.value, [ms[0], ms[1]]
+        return chosen.value, [ms[0], ms[1], ms[2]]
+
+    def groups(self):
+        """(number of groups, group of every member)."""
+        ng = C.c_int32(0)
+        of = (C.c_int32 * self.count)()
+        _check(lib().mg_batch_groups(self.b, C.byref(ng), of), "mg_batch_groups")
+        return ng.value, list(of)
 
     def solve(self, us, Ws=None, tol=1e-10, max_outer=100, raise_on_failure=True):
         reps = (MgReport * self.count)()

@@ -1,6 +1,6 @@
-"""The batched solve (one graph launch per outer iteration for all members):
-every member equals its own single-instance solve bitwise, and members agree
-with the CPU oracle."""
+"""The batched solve (grouped launches: one launch per kernel for every member of
+a size class; or member by member): every member equals its own single-instance
+solve bitwise in every launch mode, and members agree with the CPU oracle."""
 import numpy as np
 import pytest
 import torch
@@ -27,10 +27,17 @@ def make_members(ws_list, precision):
 
 
 @pytest.mark.parametrize("precision", [g.PREC_FP32_IR, g.PREC_FP64])
-def test_batch_members_equal_single_solves(precision):
+@pytest.mark.parametrize("mode", [g.BATCH_GROUPS, g.BATCH_LANES])
+def test_batch_members_equal_single_solves(precision, mode):
+    """Members of three sizes (groups of 3, 3 and 1): the grouped launches and the
+    member-by-member launches give every member its single solve, bit for bit."""
     ws = synth.scan_96(count=7, sizes=(32, 48, 64))
     plist, r5s, r1s, Ss, Ks = make_members(ws, precision)
     batch = g.Batch(plist, r5s, r1s, Ss)
+    batch.launch_mode(mode)
+    ng, of = batch.groups()
+    assert ng == len({w.n for w in ws}) and all(of[i] == of[j] for i in range(7) for j in range(7)
+                                                 if ws[i].n == ws[j].n)
     us = [torch.zeros((w.n,) * 3, dtype=torch.float64, device=dev()) for w in ws]
     Ws = [torch.zeros((3,) + (w.n,) * 3, dtype=torch.float64, device=dev()) for w in ws]
     st, reps = batch.solve(us, Ws, tol=1e-10, max_outer=60)
@@ -95,7 +102,7 @@ def test_batch_launch_modes_agree_and_autotune():
     plist, r5s, r1s, Ss, Ks = make_members(ws, g.PREC_FP32_IR)
     batch = g.Batch(plist, r5s, r1s, Ss)
     results = {}
-    for mode in (g.BATCH_GRAPH, g.BATCH_LANES, g.BATCH_AUTO):
+    for mode in (g.BATCH_GRAPH, g.BATCH_LANES, g.BATCH_GROUPS, g.BATCH_AUTO):
         batch.launch_mode(mode)
         us = [torch.zeros((w.n,) * 3, dtype=torch.float64, device=dev()) for w in ws]
         Ws = [torch.zeros((3,) + (w.n,) * 3, dtype=torch.float64, device=dev()) for w in ws]
@@ -103,9 +110,10 @@ def test_batch_launch_modes_agree_and_autotune():
         assert st == 0
         results[mode] = ([N(u) for u in us], [r["outer_iters"] for r in reps])
     chosen, ms = batch.launch_mode()
-    print(f"autotuned launch mode {chosen}: graph {ms[0]:.2f} ms, lanes {ms[1]:.2f} ms per outer iteration")
-    assert chosen in (g.BATCH_GRAPH, g.BATCH_LANES) and ms[0] > 0 and ms[1] > 0
-    for mode in (g.BATCH_LANES, g.BATCH_AUTO):
+    print(f"autotuned launch mode {chosen}: graph {ms[0]:.2f} ms, lanes {ms[1]:.2f} ms, groups {ms[2]:.2f} ms "
+          f"per outer iteration")
+    assert chosen in (g.BATCH_GRAPH, g.BATCH_LANES, g.BATCH_GROUPS) and min(ms) > 0
+    for mode in (g.BATCH_LANES, g.BATCH_GROUPS, g.BATCH_AUTO):
         assert results[mode][1] == results[g.BATCH_GRAPH][1]
         for a, b in zip(results[mode][0], results[g.BATCH_GRAPH][0]):
             assert np.array_equal(a, b)
