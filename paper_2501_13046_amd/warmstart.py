@@ -172,6 +172,18 @@ def evaluate(net: gn.Net, nm: gn.NnNorm, seeds: List[int], n: int, device, log=p
     return rows
 
 
+def fmg_learned_start(net: gn.Net, nm: gn.NnNorm, coarse: g.Solver, fine: g.Solver, r5c, r1c, Sc, uc, Wc, uf, Wf,
+                      tol_c: float, max_outer: int = 100):
+    """Full-multigrid start with a learned coarse start: the network (trained on the
+    coarse problem) predicts (u, W) on the coarse grid, one coarse outer iteration
+    checks it against the zero start (the library's fallback rule), the coarse solve
+    continues to tol_c, and the cubic interpolation fills the fine arrays.  Returns
+    (prediction kept, coarse report of the continued solve)."""
+    used, _ = net.warm_start(coarse, r5c, r1c, Sc, nm, uc, Wc)
+    rc = g.fmg_start(coarse, fine, uc, Wc, uf, Wf, tol=tol_c, max_outer=max_outer)
+    return used, rc
+
+
 def save(path: str, params: torch.Tensor, nm: gn.NnNorm, cfg: gn.NnConfig, meta: dict):
     np.savez(path, params=params.detach().cpu().numpy().astype(np.float32),
              norm=json.dumps(norm_to_dict(nm)),
