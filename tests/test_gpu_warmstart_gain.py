@@ -17,6 +17,7 @@ from gpu_helpers import N, dev
 pytestmark = pytest.mark.gpu
 WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2501_13046_amd",
                        "weights", "warmstart_128.npz")
+WEIGHTS_64 = os.path.join(os.path.dirname(WEIGHTS), "warmstart_64.npz")
 
 
 def test_trained_warm_start_cuts_outer_iterations():
@@ -49,3 +50,71 @@ def test_trained_warm_start_cuts_outer_iterations():
     print(f"mean outer iterations: zero start {zero:.2f}, warm start {warm:.2f}")
     assert all(q[2] for q in rows)
     assert warm < zero
+
+
+def _event_ms(fn):
+    """Device time of fn() on the current stream (HIP events), in ms."""
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    out = fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b), out
+
+
+def test_learned_coarse_start_saves_time_on_held_out_seeds():
+    """The network trained on the 64^3 problem as the coarse start of the full-multigrid
+    start of the 128^3 solve: on held-out seeds it saves coarse iterations and time
+    against the same start from zero (event-timed, median over seeds), and reaches the
+    same 128^3 solution."""
+    from paper_2501_13046_amd import grtmg as g
+    import synth
+    cfg, nm, params, meta = ws.load(WEIGHTS_64, dev())
+    assert cfg.n == 64 and meta["train_seeds"] >= 2000
+    net = gn.Net(cfg, training=False, device=dev())
+    net.load(params)
+    saved, its = [], []
+    for seed in range(10000, 10004):
+        pf, r5, r1, S = ws.problem(seed, 128, dev())
+        wc = synth.coupled(64, seed=seed, precision=g.PREC_FP32_IR)
+        pc = g.params(64, wc.levels, wc.bc, g.PREC_FP32_IR, wc.length, wc.origin, pf.K, wc.nu_pre, wc.nu_post, True)
+        r5c, r1c, Sc, _ = g.scalar_field_sources(pc, wc.phi_modes, wc.pi_modes, wc.scalar_mass, dev())
+        fine, coarse = g.Solver(pf, r5, r1, S), g.Solver(pc, r5c, r1c, Sc)
+        z = lambda n: torch.zeros((n,) * 3, dtype=torch.float64, device=dev())
+        zw = lambda n: torch.zeros((3, n, n, n), dtype=torch.float64, device=dev())
+        uc, Wc, uf, Wf = z(64), zw(64), z(128), zw(128)
+        tol_c = g.fmg_coarse_tol(coarse, fine, uc, Wc, uf, Wf)
+
+        def plain():
+            uc.zero_(); Wc.zero_()
+            rc = g.fmg_start(coarse, fine, uc, Wc, uf, Wf, tol=tol_c)
+            return rc, fine.solve(uf, Wf, tol=1e-10, max_outer=100)
+
+        def learned():
+            used, rc = ws.fmg_learned_start(net, nm, coarse, fine, r5c, r1c, Sc, uc, Wc, uf, Wf, tol_c)
+            return used, rc, fine.solve(uf, Wf, tol=1e-10, max_outer=100)
+
+        plain(), learned()  # warm-up: graphs captured, kernels loaded
+        t0 = []
+        for _ in range(3):
+            ms, (rc0, rf0) = _event_ms(plain)
+            t0.append(ms)
+        u0, W0 = uf.clone(), Wf.clone()
+        t1 = []
+        for _ in range(3):
+            ms, (used, rc1, rf1) = _event_ms(learned)
+            t1.append(ms)
+        assert used and rf1["h_rms"] <= 1e-10 and rf1["m_rms"] <= 1e-10
+        psi_err = float(torch.max(torch.abs(uf - u0) / (1.0 + u0)))
+        assert psi_err < 1e-9
+        saved.append(float(np.median(t0) - np.median(t1)))
+        its.append((rc0["outer_iters"], rc1["outer_iters"] + 1, rf0["outer_iters"], rf1["outer_iters"]))
+        print(f"seed {seed}: FMG from zero {np.median(t0):.3f} ms (coarse {rc0['outer_iters']} + fine "
+              f"{rf0['outer_iters']}), learned coarse start {np.median(t1):.3f} ms (coarse {rc1['outer_iters']} + 1 "
+              f"+ fine {rf1['outer_iters']}); psi diff {psi_err:.1e}", flush=True)
+        fine.close()
+        coarse.close()
+    print(f"time saved per solve (median over seeds): {np.median(saved):.3f} ms")
+    assert all(c1 < c0 for c0, c1, _, _ in its)
+    assert np.median(saved) > 0.0
