@@ -2456,12 +2456,12 @@ mg_status mg_interp_cubic(const mg_params *pc, const double *d_coarse, double *d
     const Geo gc = make_geo(pc->n, pc->bc, pc->length, pc->origin, pc->puncture_pos);
     const int64_t mf = 8 * (int64_t)pc->n * pc->n * pc->n;
     if (pc->bc == MG_BC_PERIODIC)
-        hipLaunchKernelGGL(k_interp_cubic<kBcPeriodic>, dim3(nblk(mf)), dim3(kBlock), 0, (hipStream_t)stream,
+        hipLaunchKernelGGL(k_interp_cubic<kBcPeriodic>, dim3(nblk(mf / 8)), dim3(kBlock), 0, (hipStream_t)stream,
                            gc, d_coarse, d_fine);
     else
         with_bc(pc->bc, [&](auto bcx) {
             constexpr int BCX = decltype(bcx)::value;
-            hipLaunchKernelGGL(k_interp_cubic<BCX>, dim3(nblk(mf)), dim3(kBlock), 0, (hipStream_t)stream, gc,
+            hipLaunchKernelGGL(k_interp_cubic<BCX>, dim3(nblk(mf / 8)), dim3(kBlock), 0, (hipStream_t)stream, gc,
                                d_coarse, d_fine);
         });
     return hip_status();
@@ -2488,11 +2488,11 @@ mg_status mg_fmg_start(mg_ctx *cc, mg_ctx *cf, double *d_uc, double *d_Wc, doubl
         const double *src = q == 0 ? d_uc : d_Wc + (q - 1) * mc;
         double *dst = q == 0 ? d_uf : d_Wf + (q - 1) * mf;
         if (a.bc == MG_BC_PERIODIC)
-            hipLaunchKernelGGL(k_interp_cubic<kBcPeriodic>, dim3(nblk(mf)), dim3(kBlock), 0, cf->s, gc, src, dst);
+            hipLaunchKernelGGL(k_interp_cubic<kBcPeriodic>, dim3(nblk(mf / 8)), dim3(kBlock), 0, cf->s, gc, src, dst);
         else
             with_bc(a.bc, [&](auto bcx) {
                 constexpr int BCX = decltype(bcx)::value;
-                hipLaunchKernelGGL(k_interp_cubic<BCX>, dim3(nblk(mf)), dim3(kBlock), 0, cf->s, gc, src, dst);
+                hipLaunchKernelGGL(k_interp_cubic<BCX>, dim3(nblk(mf / 8)), dim3(kBlock), 0, cf->s, gc, src, dst);
             });
     }
     leave(cf);

@@ -848,37 +848,65 @@ __global__ void __launch_bounds__(kBlock) k_prolong_add(Geo gc, const T *__restr
     prolong_cell<BC, T>(gc, coarse, fine, ncomp, tid, i, j, k);
 }
 
-// Four-point cubic interpolation (FP64), fine = Q coarse.
+// Four-point cubic interpolation (FP64), fine = Q coarse.  One thread per coarse cell
+// (I, J, K) writes its 8 fine children from the 5^3 coarse neighbourhood I-2 .. I+2:
+// child parity p along an axis uses nodes p .. p+3 of that window with the weights
+// (-5, 35, 105, -7)/128 (p = 0, offset -1/4) or their mirror (p = 1, offset +1/4).  The
+// sums are separable and taken in the order of the plain triple sum over (x, y, z)
+// nodes: z innermost, then y, then x.
 template <int BC>
 __global__ void __launch_bounds__(kBlock) k_interp_cubic(Geo gc, const double *__restrict__ coarse,
                                                          double *__restrict__ fine)
 {
-    const int nf = 2 * gc.n;
+    const int nc = gc.n, nf = 2 * nc;
     const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    int i, j, k;
-    if (!cell_of(tid, nf, i, j, k)) return;
-    // weights for nodes base..base+3 (even fine index: base = I-2, offset -1/4;
-    // odd: base = I-1, offset +1/4)
-    const double we[4] = {-5.0 / 128.0, 35.0 / 128.0, 105.0 / 128.0, -7.0 / 128.0};
-    const double wo[4] = {-7.0 / 128.0, 105.0 / 128.0, 35.0 / 128.0, -5.0 / 128.0};
-    const double *wi = (i & 1) ? wo : we;
-    const double *wj = (j & 1) ? wo : we;
-    const double *wk = (k & 1) ? wo : we;
-    const int bi = (i >> 1) - ((i & 1) ? 1 : 2);
-    const int bj = (j >> 1) - ((j & 1) ? 1 : 2);
-    const int bk = (k >> 1) - ((k & 1) ? 1 : 2);
+    int I, J, K;
+    if (!cell_of(tid, nc, I, J, K)) return;
+    const double w[2][4] = {{-5.0 / 128.0, 35.0 / 128.0, 105.0 / 128.0, -7.0 / 128.0},
+                            {-7.0 / 128.0, 105.0 / 128.0, 35.0 / 128.0, -5.0 / 128.0}};
     Acc<BC, double> C{coarse, gc};
-    double s = 0.0;
-    for (int a = 0; a < 4; a++) {
-        double sa = 0.0;
-        for (int b = 0; b < 4; b++) {
-            double sb = 0.0;
-            for (int e = 0; e < 4; e++) sb += wk[e] * C(bi + a, bj + b, bk + e);
-            sa += wj[b] * sb;
+    double yz[2][2][5]; // [z parity][y parity][x node]
+#pragma unroll
+    for (int a = 0; a < 5; a++) {
+        double zc[2][5]; // [z parity][y node] at x node a
+#pragma unroll
+        for (int b = 0; b < 5; b++) {
+            double v[5];
+#pragma unroll
+            for (int e = 0; e < 5; e++) v[e] = C(I - 2 + a, J - 2 + b, K - 2 + e);
+#pragma unroll
+            for (int pk = 0; pk < 2; pk++) {
+                double sb = 0.0;
+#pragma unroll
+                for (int e = 0; e < 4; e++) sb += w[pk][e] * v[e + pk];
+                zc[pk][b] = sb;
+            }
         }
-        s += wi[a] * sa;
+#pragma unroll
+        for (int pk = 0; pk < 2; pk++)
+#pragma unroll
+            for (int pj = 0; pj < 2; pj++) {
+                double sa = 0.0;
+#pragma unroll
+                for (int b = 0; b < 4; b++) sa += w[pj][b] * zc[pk][b + pj];
+                yz[pk][pj][a] = sa;
+            }
     }
-    fine[tid] = s;
+#pragma unroll
+    for (int pi = 0; pi < 2; pi++)
+#pragma unroll
+        for (int pj = 0; pj < 2; pj++) {
+            double out[2];
+#pragma unroll
+            for (int pk = 0; pk < 2; pk++) {
+                double s = 0.0;
+#pragma unroll
+                for (int a = 0; a < 4; a++) s += w[pi][a] * yz[pk][pj][a + pi];
+                out[pk] = s;
+            }
+            const int64_t q = ((int64_t)(2 * I + pi) * nf + (2 * J + pj)) * nf + 2 * K;
+            *reinterpret_cast<double2 *>(fine + q) = make_double2(out[0], out[1]);
+        }
 }
 
 // ---------------------------------------------------------------------------------------
