@@ -17,8 +17,10 @@ brute-force dense solves, 4th-order convergence to manufactured solutions,
 the smoothers' diagonals against the operator's impulse response (periodic
 and Robin, psi with its Newton coefficient, all three W components), the
 exact solution as a fixed point of every colour pass, the colour convention,
-the cycle order and contraction of both V-cycles; each smoother pin is shown
-to fail on a copy of the oracle with a planted mistake (``planted``).  No
+the cycle order and contraction of both V-cycles; the CTTK and CTTK-Hybrid
+methods against the Friedmann trace and the judge's direct evaluation of eqs.
+Ham and Mom with a varying K; each such pin is shown to fail on a copy of the
+oracle with a planted mistake (``planted``).  No
 oracle function is left "parity unpinned".
 """
 from __future__ import annotations
@@ -133,13 +135,17 @@ def _bind(L):
         "orc_num_threads": [],
         "orc_bowen_york_tensor": [ip, dp, dp, dp],
         "orc_bowen_york": [pp, ip, dp, dp, dp],
+        "orc_cttk_hybrid_sources": [pp, dp, dp, dp, dp, dp],
+        "orc_cttk_update": [pp, dp, dp, dp, dp, dp, dp, dp, dp, dp],
+        "orc_cttk_solve": [pp, dp, dp, dp, dp, dp, dp, dp, C.c_double, ip, dp, ip,
+                           C.POINTER(C.c_int), dp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
         f.argtypes = args
         f.restype = C.c_int if name in ("orc_coarse_solve_psi", "orc_coarse_solve_W",
                                         "orc_vcycle_psi", "orc_vcycle_W", "orc_step",
-                                        "orc_solve", "orc_num_threads") else None
+                                        "orc_solve", "orc_cttk_solve", "orc_num_threads") else None
     return L
 
 
@@ -355,6 +361,40 @@ def solve(p, u, W, rho5, rho1, S, f=None, tol=1e-10, max_outer=60):
     st = lib().orc_solve(C.byref(p), _ptr(u), _ptr(W), _ptr(rho5), _ptr(rho1), _ptr(S), _ptr(f),
                          tol, max_outer, _ptr(hist), max_outer + 1, C.byref(it), _ptr(nr))
     return SolveResult(st, it.value, hist[: min(it.value + 1, max_outer + 1)], nr)
+
+
+# ---- CTTK and CTTK-Hybrid (spatially varying K; readings stated in mg_oracle.c) ---------
+
+def cttk_hybrid_sources(p, rho5, rho1, S):
+    """CTTK-Hybrid sources: returns (rho5_h, S_h, K, K0) with rho5_h = 0,
+    S_h = S + D K / (12 pi), K^2 = 24 pi (rho5 + <rho1>), K0^2 = 24 pi <rho1>."""
+    r5 = np.array(rho5, dtype=np.float64, order="C")
+    Sh = np.array(S, dtype=np.float64, order="C")
+    K = _z(p.n)
+    K0 = np.zeros(1)
+    lib().orc_cttk_hybrid_sources(C.byref(p), _ptr(r5), _ptr(np.ascontiguousarray(rho1)), _ptr(Sh), _ptr(K),
+                                  _ptr(K0))
+    return r5, Sh, K, float(K0[0])
+
+
+def cttk_update(p, u, W, rho5, rho1, S, f=None):
+    """CTTK: (rho5_eff, S_eff, K) at (u, W), K^2 = 12 H_h(K=0) / psi^5."""
+    n = p.n
+    r5, Se, K = _z(n), _z(n, 3), _z(n)
+    lib().orc_cttk_update(C.byref(p), _ptr(u), _ptr(W), _ptr(rho5), _ptr(rho1), _ptr(S), _ptr(f), _ptr(r5),
+                          _ptr(Se), _ptr(K))
+    return r5, Se, K
+
+
+def cttk_solve(p, u, W, rho5, rho1, S, f=None, tol=1e-10, max_outer=60):
+    """CTTK solve in place on W (u is data); returns (SolveResult, K)."""
+    hist = np.zeros((max_outer + 1, 4))
+    it = C.c_int(0)
+    nr = np.zeros(4)
+    K = _z(p.n)
+    st = lib().orc_cttk_solve(C.byref(p), _ptr(u), _ptr(W), _ptr(rho5), _ptr(rho1), _ptr(S), _ptr(f), _ptr(K),
+                              tol, max_outer, _ptr(hist), max_outer + 1, C.byref(it), _ptr(nr))
+    return SolveResult(st, it.value, hist[: min(it.value + 1, max_outer + 1)], nr), K
 
 
 # ---- Bowen-York punctures -----------------------------------------------------------

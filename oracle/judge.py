@@ -138,7 +138,10 @@ def residuals(g: Grid, u, W, rho5, rho1, S, K, puncture_mass=0.0, f=None,
     conformal_matter: sources are rho_bar = psi^8 rho (= rho5 + rho1) and
     S_bar = psi^6 S, entering as 2 pi rho_bar psi^-3 and 8 pi S_bar.
     psi0_field replaces 1 + M/(2r) (several punctures); A2_bg is added to the
-    A2 of W (an analytic extrinsic curvature such as Bowen-York's)."""
+    A2 of W (an analytic extrinsic curvature such as Bowen-York's).
+    K may be a field (the CTTK methods): eq. Ham then takes K(x)^2 per cell and
+    eq. Mom the term -(2/3) psi^6 D_a K beside the matter source (both inside the
+    mean removal of periodic grids)."""
     psi = (psi0(g, puncture_mass) if psi0_field is None else psi0_field) + u
     a2 = A2(g, W) if W is not None else 0.0
     if A2_bg is not None:
@@ -159,6 +162,9 @@ def residuals(g: Grid, u, W, rho5, rho1, S, K, puncture_mass=0.0, f=None,
     if W is not None:
         w6 = 1.0 if conformal_matter else psi[None] ** 6
         src = 8 * np.pi * w6 * S
+        if np.ndim(K) == 3:
+            Kp = g.pad(K)
+            src = src + 2.0 / 3.0 * w6 * np.stack([d1(g, Kp, a) for a in range(3)])
         if g.bc == BC_PERIODIC:
             src = src - src.mean(axis=(1, 2, 3), keepdims=True)
         M = deltaL(g, W) - src

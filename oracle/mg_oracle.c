@@ -39,6 +39,10 @@
  *   c   = -6 pi rho_bar psi^-4 - (5 K^2/12) psi^4 - (7/8) A2 psi^-8
  *   M_h = Delta_L,h W - (8 pi S - mean(8 pi S))
  *
+ * Methods with a spatially varying K (Key features, "Methods": CTTK and
+ * CTTK-Hybrid): the readings and their shifted sources are stated with
+ * orc_cttk_hybrid_sources / orc_cttk_update below.
+ *
  * Boundary conditions (Key features, "Boundary conditions": extrapolating,
  * reflective and periodic; the 1/r Robin rule serves the isolated black hole):
  * periodic wrap; Robin: a ghost value a(g) = a(b) |x_b| / |x_g| with b the grid
@@ -931,6 +935,141 @@ int orc_solve(const orc_params *p, double *u, double *W, const double *rho5, con
     if (iters) *iters = it;
     hier_free(&HP);
     if (p->solve_momentum) hier_free(&HW);
+    free(H);
+    free(M);
+    return status;
+}
+
+/* ---- CTTK and CTTK-Hybrid (Summary and Key features, "Methods") -----------
+ *
+ * The two CTT variants the paper implements let the trace K vary in space; their
+ * equations are given in the formalism the paper cites, not in the paper, so this
+ * is a reading of eqs. Ham and Mom with a spatially varying K (conformally flat,
+ * A_ij = psi^-2 Abar_ij, gamma^ij = psi^-4 delta_ij).  Eq. Mom then reads
+ *   Delta_L W_a - (2/3) psi^6 d_a K - 8 pi psi^6 S_a = 0,
+ * and eq. Ham keeps its -(K^2/12) psi^5 term, now with K = K(x).  Both new terms
+ * carry the psi power of an existing matter term, so the CTT residuals take them
+ * as shifted sources:
+ *   S_a  -> S_a + D_a K / (12 pi)           (8 pi psi^6 times it gives both terms)
+ *   rho5 -> rho5 - (K^2 - K0^2) / (24 pi)   (2 pi psi^5 times it, with constant K0)
+ *
+ * CTTK-Hybrid: K^2(x) = 24 pi (rho5(x) + <rho1>): the psi-independent energy density is
+ * carried by K locally (so rho5 -> 0), the gradient energy by psi, solved as in CTT
+ * with the constant trace K0, K0^2 = 24 pi <rho1>.  K is fixed before the solve.
+ *
+ * CTTK: psi is free data (u is left as given) and eq. Ham is solved for K:
+ *   K^2 = 12 H0 / psi^5,   H0 = H_h at K = 0,
+ * after every W step; with it H_h vanishes and rho5 -> rho5 - K^2 / (24 pi) (K0 = 0).
+ * A negative K^2 has no real trace: K and the shifted rho5 are NaN there.
+ */
+
+/* CTTK-Hybrid: rho5 (in place) -> 0, S (in place) -> S + D K / (12 pi), K (out) the
+ * field, *K0 = sqrt(24 pi <rho1>). */
+void orc_cttk_hybrid_sources(const orc_params *p, double *rho5, const double *rho1, double *S, double *K,
+                             double *K0)
+{
+    const int n = p->n;
+    const long m = cells(n);
+    geom g = make_geom(p, n);
+    double mean1 = 0.0;
+    for (long q = 0; q < m; q++) mean1 += rho1[q];
+    mean1 /= (double)m;
+    for (long q = 0; q < m; q++) {
+        K[q] = sqrt(24.0 * M_PI * (rho5[q] + mean1));
+        rho5[q] = 0.0;
+    }
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n; i++)
+        for (int j = 0; j < n; j++)
+            for (int k = 0; k < n; k++) {
+                long q = idx3(n, i, j, k);
+                for (int a = 0; a < 3; a++) S[a * m + q] += D1(&g, K, i, j, k, a) / (12.0 * M_PI);
+            }
+    *K0 = sqrt(24.0 * M_PI * mean1);
+}
+
+/* CTTK: K from eq. Ham at (u, W) (K^2 = 12 H0 / psi^5), and the shifted sources
+ * rho5_eff = rho5 - K^2 / (24 pi), S_eff = S + D K / (12 pi).  p->K is not used. */
+void orc_cttk_update(const orc_params *p, const double *u, const double *W, const double *rho5,
+                     const double *rho1, const double *S, const double *f, double *rho5_eff, double *S_eff,
+                     double *K)
+{
+    const int n = p->n;
+    const long m = cells(n);
+    geom g = make_geom(p, n);
+    orc_params p0 = *p;
+    p0.K = 0.0;
+    orc_residuals(&p0, u, W, rho5, rho1, S, f, K, NULL, NULL); /* H0 into K */
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n; i++)
+        for (int j = 0; j < n; j++)
+            for (int k = 0; k < n; k++) {
+                long q = idx3(n, i, j, k);
+                double psi = psi0_at(p, &g, i, j, k) + u[q];
+                double K2 = 12.0 * K[q] / pow(psi, 5);
+                if (!(K2 >= 0.0)) K2 = NAN;
+                K[q] = sqrt(K2);
+                rho5_eff[q] = rho5[q] - K2 / (24.0 * M_PI);
+            }
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n; i++)
+        for (int j = 0; j < n; j++)
+            for (int k = 0; k < n; k++) {
+                long q = idx3(n, i, j, k);
+                for (int a = 0; a < 3; a++)
+                    S_eff[a * m + q] = (S ? S[a * m + q] : 0.0) + D1(&g, K, i, j, k, a) / (12.0 * M_PI);
+            }
+}
+
+/*
+ * CTTK solve: u is data; W is solved.  Every iteration: K and the shifted sources
+ * from (u, W), the norms of H_h and M_h with them (H_h vanishes up to rounding), the
+ * convergence test, then one W step.  K receives the trace of the final state.
+ * Status and outputs as orc_solve (p->solve_momentum must be 1).
+ */
+int orc_cttk_solve(const orc_params *p, const double *u, double *W, const double *rho5, const double *rho1,
+                   const double *S, const double *f, double *K, double tol, int max_outer, double *hist,
+                   int hist_cap, int *iters, double out_norms[4])
+{
+    const long m = cells(p->n);
+    orc_params p0 = *p;
+    p0.K = 0.0;
+    double *r5 = (double *)malloc(m * sizeof(double));
+    double *Se = (double *)malloc(3 * m * sizeof(double));
+    double *H = (double *)malloc(m * sizeof(double));
+    double *M = (double *)malloc(3 * m * sizeof(double));
+    sources s = {r5, rho1, Se, f};
+    hier HW;
+    hier_init(&HW, &p0, 3);
+    int status = 4, it = 0;
+    for (;; it++) {
+        double nr[4];
+        orc_cttk_update(&p0, u, W, rho5, rho1, S, f, r5, Se, K);
+        orc_residuals(&p0, u, W, r5, rho1, Se, f, H, M, NULL);
+        orc_norms(p0.n, H, M, nr);
+        if (hist && it < hist_cap) memcpy(hist + 4 * it, nr, sizeof(nr));
+        if (out_norms) memcpy(out_norms, nr, sizeof(nr));
+        if (!isfinite(nr[0]) || !isfinite(nr[1])) {
+            status = 5;
+            break;
+        }
+        if (nr[0] <= tol && nr[1] <= tol) {
+            status = 0;
+            break;
+        }
+        if (it >= max_outer) {
+            status = 4;
+            break;
+        }
+        if (step_W(&HW, &p0, u, W, &s)) {
+            status = 1;
+            break;
+        }
+    }
+    if (iters) *iters = it;
+    hier_free(&HW);
+    free(r5);
+    free(Se);
     free(H);
     free(M);
     return status;
