@@ -65,7 +65,7 @@ typedef enum mg_status {
 enum { MG_BC_PERIODIC = 0, MG_BC_ROBIN = 1, MG_BC_REFLECT = 2, MG_BC_EXTRAP = 3 };
 enum { MG_PREC_FP64 = 0, MG_PREC_FP32_IR = 1 };
 enum { MG_EQ_PSI = 1, MG_EQ_W = 2, MG_EQ_BOTH = 3 };
-enum { MG_FLAG_CONFORMAL_MATTER = 1, MG_FLAG_EAGER = 2 };
+enum { MG_FLAG_CONFORMAL_MATTER = 1, MG_FLAG_EAGER = 2, MG_FLAG_CTTK = 4 };
 
 /*
  * Problem and solver parameters.
@@ -96,7 +96,22 @@ enum { MG_FLAG_CONFORMAL_MATTER = 1, MG_FLAG_EAGER = 2 };
  *                 textbook CTT rescaling that keeps dH_h/dpsi negative).
  *                 bit MG_FLAG_EAGER: launch every kernel from the host instead
  *                 of replaying the captured outer-iteration graph (results are
- *                 identical; for measurement and tests).  Other bits must be 0.
+ *                 identical; for measurement and tests).
+ *                 bit MG_FLAG_CTTK: the CTTK method (Key features, "Methods";
+ *                 read from eqs. Ham and Mom with a spatially varying K): psi =
+ *                 1 + u is free data that no call changes, and eq. Ham is solved
+ *                 for the trace instead, K^2 = 12 H0 / psi^5 with H0 = H_h at
+ *                 K = 0 (the caller's rho5, rho1 and f).  Every evaluation of a
+ *                 state (u, W) first forms that K and the shifted sources
+ *                 rho5 - K^2/(24 pi) and S + D K/(12 pi) (the -(2/3) psi^6 d_a K of
+ *                 eq. Mom), so H_h vanishes up to rounding and M_h carries the
+ *                 trace term; an outer iteration is the W step alone.  Where
+ *                 K^2 < 0 (a psi whose Laplacian outweighs the energy density)
+ *                 K is NaN and a solve ends with MG_ERR_DIVERGED.  Requires
+ *                 solve_momentum = 1, periodic boundaries, K = 0, no puncture and
+ *                 no conformal matter; not in batches, mg_fmg_start or
+ *                 nn_warm_start (MG_ERR_INVALID).  The workspace grows by
+ *                 5 n^3 doubles.  Other bits must be 0.
  *  length, origin box side L and corner of the box (cell centres at
  *                 origin + (i + 1/2) L/n).
  *  K              constant trace of the extrinsic curvature.
@@ -218,6 +233,31 @@ mg_status mg_set_background(mg_ctx *ctx, const double *d_psi0, const double *d_A
  */
 mg_status mg_bowen_york_sources(const mg_params *p, int32_t count, const double *h_table, double *d_psi0,
                                 double *d_A2, void *stream);
+
+/*
+ * CTTK trace (Key features, "Methods"; a context set up with MG_FLAG_CTTK): writes
+ * d_K (n^3 FP64) = K of the state (d_u, d_W) from eq. Ham, K^2 = 12 H0 / psi^5, the
+ * trace a solve of that state used.  MG_ERR_INVALID for other contexts.  Enqueued
+ * only.
+ */
+mg_status mg_cttk_trace(mg_ctx *ctx, const double *d_u, const double *d_W, double *d_K);
+
+/*
+ * CTTK-Hybrid sources (Key features, "Methods"; read from eqs. Ham and Mom with a
+ * spatially varying K): the psi-independent energy density rho5 is carried by a
+ * local trace, the gradient energy by psi as in CTT with a constant trace K0:
+ *   K^2(x) = 24 pi (rho5(x) + <rho1>),  K0^2 = 24 pi <rho1>.
+ * Transforms the CTT sources in place into those of an ordinary mg_setup context
+ * with trace K0 (p->K = *h_K0): d_rho5 -> 0 and d_S -> d_S + D K / (12 pi) (the
+ * -(2/3) psi^6 d_a K of eq. Mom; D the fourth-order first derivative), and writes
+ * d_K = K(x) (all FP64 n^3, d_S 3 n^3).  Periodic grids only (p: n 4..4096,
+ * length, origin).  d_scratch: caller-owned device scratch, 256-byte aligned, of at
+ * least MG_SOURCES_SCRATCH_BYTES for the mean of rho1 (MG_ERR_WORKSPACE otherwise).
+ * If h_K0 is not NULL, K0 is returned there and the call synchronises the stream.
+ * The solution (u, W) with K(x) then satisfies eqs. Ham and Mom as written.
+ */
+mg_status mg_cttk_hybrid_sources(const mg_params *p, double *d_rho5, const double *d_rho1, double *d_S,
+                                 double *d_K, void *d_scratch, size_t scratch_bytes, double *h_K0, void *stream);
 
 void mg_destroy(mg_ctx *ctx);
 const char *mg_status_str(mg_status s);

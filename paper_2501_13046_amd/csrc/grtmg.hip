@@ -21,6 +21,7 @@
 #include "grtmg.h"
 #include "mg_kernels.hpp"
 #include "mg_tiled.hpp"
+#include "mg_cttk.hpp"
 #include "mg_internal.h"
 
 using namespace grtmg;
@@ -124,6 +125,12 @@ struct mg_ctx {
     const double *rho5, *rho1, *S, *f;
     const double *bg_psi0, *bg_A2; // optional background fields (mg_set_background), borrowed
     double K2;
+    // CTTK (MG_FLAG_CTTK): psi is data, K follows from eq. Ham after every W step; the
+    // residuals read the shifted rho5_eff and S_eff (rho5 and S point at them) made
+    // from the caller's rho5_in and S_in, and Kf holds K of the last evaluated state
+    bool cttk;
+    const double *rho5_in, *S_in;
+    double *rho5_eff, *S_eff, *Kf;
     int vc_psi, vc_W;
     // batch membership: streams borrowed from the batch, updates gated by the
     // instance's active flag, a convergence check after every evaluation
@@ -166,7 +173,12 @@ mg_status validate(const mg_params *p)
     // the W kernels address one component with 32-bit byte offsets
     if (p->solve_momentum && (double)p->n * p->n * (double)p->n * sizeof(double) >= 4294967296.0)
         return MG_ERR_INVALID;
-    if ((p->flags & ~(MG_FLAG_CONFORMAL_MATTER | MG_FLAG_EAGER)) != 0) return MG_ERR_INVALID;
+    if ((p->flags & ~(MG_FLAG_CONFORMAL_MATTER | MG_FLAG_EAGER | MG_FLAG_CTTK)) != 0) return MG_ERR_INVALID;
+    // CTTK: the coupled periodic solve with psi = 1 + u as data, K from eq. Ham
+    if ((p->flags & MG_FLAG_CTTK) &&
+        (!p->solve_momentum || p->bc != MG_BC_PERIODIC || p->K != 0.0 || p->puncture_mass != 0.0 ||
+         (p->flags & MG_FLAG_CONFORMAL_MATTER)))
+        return MG_ERR_INVALID;
     if (!(p->length > 0.0) || !std::isfinite(p->length)) return MG_ERR_INVALID;
     if (!std::isfinite(p->K) || !(p->puncture_mass >= 0.0) || !std::isfinite(p->puncture_mass))
         return MG_ERR_INVALID;
@@ -208,6 +220,14 @@ void carve(mg_ctx *c, Carver &cv)
     }
     const int64_t nb = nblk(c->cells[0]);
     c->part = (double *)cv.take((size_t)nb * 4 * sizeof(double));
+    if (p.flags & MG_FLAG_CTTK) {
+        const size_t m0 = (size_t)c->cells[0] * sizeof(double);
+        c->rho5_eff = (double *)cv.take(m0);
+        c->S_eff = (double *)cv.take(3 * m0);
+        c->Kf = (double *)cv.take(m0);
+    } else {
+        c->rho5_eff = c->S_eff = c->Kf = nullptr;
+    }
     c->scal = (double *)cv.take(S_COUNT * sizeof(double));
     c->m_psi = (int)c->cells[c->L - 1];
     const size_t mp = (size_t)c->m_psi;
@@ -939,12 +959,30 @@ mg_status read_norms(mg_ctx *c, int slot, double out[4], double *flag_psi)
     return MG_OK;
 }
 
+// CTTK: K of the state (u, W) from eq. Ham, K^2 = 12 H0 / psi^5 with H0 the
+// Hamiltonian residual at K = 0 from the caller's rho5 (written into Kf first),
+// then the shifted sources rho5_eff and S_eff the residuals read.
+template <typename T>
+void cttk_update(mg_ctx *c, const double *u, const double *W)
+{
+    const int64_t m = c->cells[0];
+    const double *r5 = c->rho5;
+    c->rho5 = c->rho5_in;
+    residual<T>(c, u, W, false, c->Kf, nullptr, nullptr, nullptr, nullptr, nullptr, false);
+    c->rho5 = r5;
+    hipLaunchKernelGGL(k_cttk_K, dim3(nblk(m)), dim3(kBlock), 0, c->s, m, u, c->rho5_in, c->Kf, c->rho5_eff);
+    hipLaunchKernelGGL(k_cttk_shift_S<kBcPeriodic>, dim3(nblk(m)), dim3(kBlock), 0, c->s, c->geo[0],
+                       (const double *)c->Kf, c->S_in, c->S_eff);
+}
+
 // Evaluation of a state: norms (+ the residual the next update step uses);
-// batch members also update their convergence flags.
+// batch members also update their convergence flags.  CTTK: K and the shifted
+// sources of the state first.
 template <typename T>
 void evaluate(mg_ctx *c, const double *u, const double *W, bool want_M, bool after_update = true,
               bool sums_ready = false)
 {
+    if (c->cttk) cttk_update<T>(c, u, W);
     source_mean(c, u, sums_ready);
     if (c->momentum)
         residual<T>(c, u, W, true, nullptr, nullptr, nullptr, nullptr, nullptr, c->wr[0], true, true);
@@ -957,9 +995,15 @@ void evaluate(mg_ctx *c, const double *u, const double *W, bool want_M, bool aft
 }
 
 // One outer update (W step, psi step) followed by the evaluation of the new state.
+// CTTK: the W step alone (psi is data; the evaluation updates K).
 template <typename T>
 void outer_body(mg_ctx *c, double *u, double *W, bool want_M)
 {
+    if (c->cttk) {
+        step_W<T>(c, u, W, true);
+        evaluate<T>(c, u, W, want_M, true, false);
+        return;
+    }
     if (c->momentum) {
         step_W<T>(c, u, W, true);
         step_psi<T>(c, u, W, false);
@@ -1057,7 +1101,7 @@ mg_status solve(mg_ctx *c, double *u, double *W, double tol, int max_outer, mg_r
             mg_status gs = capture_body<T>(c, u, W, want_M);
             if (gs != MG_OK) return gs;
             if (hipGraphLaunch(c->gexec, c->s) != hipSuccess) return MG_ERR_HIP;
-            c->vc_psi++;
+            if (!c->cttk) c->vc_psi++;
             if (mom) c->vc_W++;
         } else {
             outer_body<T>(c, u, W, want_M);
@@ -1297,6 +1341,7 @@ mg_status autotune(mg_ctx *c, const double *u, const double *W, int reps, mg_tun
     const int probe = c->probe_kernel;
     c->probe_kernel = MG_PROBE_NONE;
     const bool wantM = c->momentum || (c->S != nullptr && W != nullptr);
+    if (c->cttk) cttk_update<T>(c, u, W);
     source_mean(c, u);
     residual<T>(c, u, W, false, nullptr, nullptr, nullptr, c->pr[0], c->pc[0], nullptr, false);
     restrict_coefficients<T>(c);
@@ -1486,6 +1531,13 @@ mg_status ctx_create(const mg_params *p, void *d_workspace, size_t bytes, hipStr
     c->K2p = nullptr;
     Carver cv{(char *)d_workspace};
     carve(c, cv);
+    c->cttk = (p->flags & MG_FLAG_CTTK) != 0;
+    if (c->cttk) {
+        c->rho5_in = d_rho5;
+        c->S_in = d_S;
+        c->rho5 = c->rho5_eff;
+        c->S = c->S_eff;
+    }
     init_geo(c);
     if (create_streams(c) != MG_OK ||
         hipHostMalloc((void **)&c->hpin, 2 * S_COUNT * sizeof(double), hipHostMallocDefault) != hipSuccess) {
@@ -2045,7 +2097,7 @@ mg_status mg_setup_batch(const mg_params *p, int32_t count, void *d_workspace, s
     if (st != MG_OK) return st;
     if (!d_rho5 || !d_rho1) return MG_ERR_INVALID;
     for (int i = 0; i < count; i++) {
-        if (!d_rho5[i] || !d_rho1[i]) return MG_ERR_INVALID;
+        if (!d_rho5[i] || !d_rho1[i] || (p[i].flags & MG_FLAG_CTTK)) return MG_ERR_INVALID;
         if (p[i].solve_momentum && (!d_S || !d_S[i])) return MG_ERR_INVALID;
     }
     if (!d_workspace || bytes < need || ((uintptr_t)d_workspace % 256) != 0) return MG_ERR_WORKSPACE;
@@ -2239,12 +2291,15 @@ mg_status mg_vcycle(mg_ctx *c, int32_t eq, double *d_u, double *d_W)
 {
     if (!c || !d_u || eq < 1 || eq > 3) return MG_ERR_INVALID;
     if ((eq & MG_EQ_W) && (!c->momentum || !d_W)) return MG_ERR_INVALID;
+    if (c->cttk && eq != MG_EQ_W) return MG_ERR_INVALID; // psi is data
     c->cont_valid = false;
     enter(c);
     if (c->f32) {
+        if (c->cttk) cttk_update<float>(c, d_u, d_W); // the W step reads this state's shifted sources
         if (eq & MG_EQ_W) step_W<float>(c, d_u, d_W, false);
         if (eq & MG_EQ_PSI) step_psi<float>(c, d_u, d_W, false);
     } else {
+        if (c->cttk) cttk_update<double>(c, d_u, d_W);
         if (eq & MG_EQ_W) step_W<double>(c, d_u, d_W, false);
         if (eq & MG_EQ_PSI) step_psi<double>(c, d_u, d_W, false);
     }
@@ -2284,8 +2339,15 @@ mg_status mg_residual_norm(mg_ctx *c, const double *d_u, const double *d_W, doub
 {
     if (!c || !d_u || !out) return MG_ERR_INVALID;
     const bool want_M = c->S != nullptr;
+    if (c->cttk && !d_W) return MG_ERR_INVALID;
     c->cont_valid = false;
     enter(c);
+    if (c->cttk) {
+        if (c->f32)
+            cttk_update<float>(c, d_u, d_W);
+        else
+            cttk_update<double>(c, d_u, d_W);
+    }
     source_mean(c, d_u);
     if (c->f32)
         residual<float>(c, d_u, d_W, want_M, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, true);
@@ -2303,11 +2365,55 @@ mg_status mg_residual_fields(mg_ctx *c, const double *d_u, const double *d_W, do
     if (!c || !d_u) return MG_ERR_INVALID;
     const bool want_M = d_M != nullptr;
     if (want_M && !c->S) return MG_ERR_INVALID;
+    if (c->cttk && !d_W) return MG_ERR_INVALID;
     c->cont_valid = false;
     enter(c);
+    if (c->cttk) cttk_update<double>(c, d_u, d_W);
     source_mean(c, d_u);
     residual<double>(c, d_u, d_W, want_M, d_H, d_M, d_c, nullptr, nullptr, nullptr, false);
     leave(c);
+    return hip_status();
+}
+
+mg_status mg_cttk_trace(mg_ctx *c, const double *d_u, const double *d_W, double *d_K)
+{
+    if (!c || !c->cttk || !d_u || !d_W || !d_K) return MG_ERR_INVALID;
+    c->cont_valid = false;
+    enter(c);
+    if (c->f32)
+        cttk_update<float>(c, d_u, d_W);
+    else
+        cttk_update<double>(c, d_u, d_W);
+    const bool ok = hipMemcpyAsync(d_K, c->Kf, (size_t)c->cells[0] * sizeof(double), hipMemcpyDeviceToDevice,
+                                   c->s) == hipSuccess;
+    leave(c);
+    return ok ? hip_status() : MG_ERR_HIP;
+}
+
+mg_status mg_cttk_hybrid_sources(const mg_params *p, double *d_rho5, const double *d_rho1, double *d_S,
+                                 double *d_K, void *d_scratch, size_t scratch_bytes, double *h_K0, void *stream)
+{
+    if (!p || p->n < 4 || p->n > 4096 || !(p->length > 0.0) || p->bc != MG_BC_PERIODIC) return MG_ERR_INVALID;
+    if (!d_rho5 || !d_rho1 || !d_S || !d_K) return MG_ERR_INVALID;
+    if (!d_scratch || scratch_bytes < kSourcesScratchNeed || ((uintptr_t)d_scratch % 256) != 0)
+        return MG_ERR_WORKSPACE;
+    const hipStream_t s = (hipStream_t)stream;
+    const Geo g = make_geo(p->n, p->bc, p->length, p->origin, p->puncture_pos);
+    const int64_t m = (int64_t)p->n * p->n * p->n;
+    const unsigned nb = std::min<unsigned>(nblk(m), kSrcBlocks);
+    double *part = (double *)d_scratch, *mean = part + kSrcBlocks;
+    hipLaunchKernelGGL(k_sum_field, dim3(nb), dim3(kBlock), 0, s, d_rho1, m, part);
+    hipLaunchKernelGGL(k_reduce_final<1>, dim3(1), dim3(kBlock), 0, s, (const double *)part, (int64_t)nb, 0u,
+                       1.0 / (double)m, mean, 0LL);
+    hipLaunchKernelGGL(k_cttk_hybrid_K, dim3(nblk(m)), dim3(kBlock), 0, s, m, (const double *)mean, d_rho5, d_K);
+    hipLaunchKernelGGL(k_cttk_shift_S<kBcPeriodic>, dim3(nblk(m)), dim3(kBlock), 0, s, g, (const double *)d_K,
+                       (const double *)d_S, d_S);
+    if (h_K0) {
+        double mv = 0.0;
+        if (hipMemcpyAsync(&mv, mean, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess) return MG_ERR_HIP;
+        if (hipStreamSynchronize(s) != hipSuccess) return MG_ERR_HIP;
+        *h_K0 = std::sqrt(24.0 * M_PI * mv);
+    }
     return hip_status();
 }
 
@@ -2474,6 +2580,7 @@ mg_status mg_fmg_start(mg_ctx *cc, mg_ctx *cf, double *d_uc, double *d_Wc, doubl
     cc->cont_valid = cf->cont_valid = false;
     const mg_params &a = cc->p, &b = cf->p;
     if (b.n != 2 * a.n || a.bc != b.bc || a.length != b.length || cc->momentum != cf->momentum) return MG_ERR_INVALID;
+    if (cc->cttk || cf->cttk) return MG_ERR_INVALID; // CTTK: psi is data, not interpolated
     for (int q = 0; q < 3; q++)
         if (a.origin[q] != b.origin[q] || a.puncture_pos[q] != b.puncture_pos[q]) return MG_ERR_INVALID;
     if (cf->momentum && (!d_Wc || !d_Wf)) return MG_ERR_INVALID;
@@ -2560,6 +2667,7 @@ SolverShape solver_shape(const mg_ctx *c)
     sh.n = c->p.n;
     sh.bc = c->p.bc;
     sh.momentum = c->momentum;
+    sh.cttk = c->cttk;
     sh.user_stream = (void *)c->user_s;
     return sh;
 }

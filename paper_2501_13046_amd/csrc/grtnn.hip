@@ -750,10 +750,10 @@ mg_status nn_warm_start(nn_ctx *c, mg_ctx *solver, const double *d_rho5, const d
         return MG_ERR_INVALID;
     // the prediction is written into the solver's arrays and checked by its own
     // iteration: both must describe the same periodic grid, the solver must
-    // update W, and both must order their work on the same stream (the check
+    // update W and psi (not CTTK, where psi is data), and both must order their work on the same stream (the check
     // iteration then follows the unpacked prediction)
     const grtmg::SolverShape sh = grtmg::solver_shape(solver);
-    if (sh.n != c->cfg.n || sh.bc != MG_BC_PERIODIC || !sh.momentum || sh.user_stream != (void *)c->s)
+    if (sh.n != c->cfg.n || sh.bc != MG_BC_PERIODIC || !sh.momentum || sh.cttk || sh.user_stream != (void *)c->s)
         return MG_ERR_INVALID;
     const int64_t V = c->V[0];
     double zero[4], pred[4];

@@ -23,10 +23,11 @@ void cancel_continue(mg_ctx *c);
 
 // Shape of a solver context for callers that hand it arrays sized elsewhere:
 // cells per axis of the finest level, boundary rule, whether it solves the
-// momentum equation, and the caller stream given at setup.
+// momentum equation, whether psi is data (CTTK), and the caller stream given at setup.
 struct SolverShape {
     int n, bc;
     bool momentum;
+    bool cttk; // psi is data (MG_FLAG_CTTK)
     void *user_stream;
 };
 SolverShape solver_shape(const mg_ctx *c);

@@ -23,6 +23,7 @@ PREC_FP64, PREC_FP32_IR = 0, 1
 EQ_PSI, EQ_W, EQ_BOTH = 1, 2, 3
 FLAG_CONFORMAL_MATTER = 1
 FLAG_EAGER = 2
+FLAG_CTTK = 4
 OP_PASS_PSI, OP_PASS_W, OP_DEFECT_RESTRICT_PSI, OP_DEFECT_RESTRICT_W = 1, 2, 3, 4
 OP_PROLONG_ADD, OP_COARSE_PSI, OP_COARSE_W = 5, 6, 7
 PROBE_NONE, PROBE_PASS_PSI, PROBE_PASS_W, PROBE_RESIDUAL = 0, 1, 2, 3
@@ -92,6 +93,8 @@ def lib() -> C.CDLL:
         L.mg_interp_cubic.argtypes = [pp, vp, vp, vp]
         L.mg_set_background.argtypes = [vp, vp, vp]
         L.mg_bowen_york_sources.argtypes = [pp, i32, dp, vp, vp, vp]
+        L.mg_cttk_trace.argtypes = [vp, vp, vp, vp]
+        L.mg_cttk_hybrid_sources.argtypes = [pp, vp, vp, vp, vp, vp, C.c_size_t, dp, vp]
         L.mg_kernel_op.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp]
         L.mg_batch_workspace_size.argtypes = [pp, i32, C.POINTER(C.c_size_t)]
         L.mg_setup_batch.argtypes = [pp, i32, vp, C.c_size_t, vp, C.POINTER(vp), C.POINTER(vp),
@@ -112,7 +115,8 @@ def lib() -> C.CDLL:
                   "mg_scalar_field_sources_static", "mg_set_background", "mg_bowen_york_sources",
                   "mg_shell_field_sources", "mg_interp_cubic", "mg_kernel_op", "mg_probe",
                   "mg_probe_result", "mg_batch_workspace_size", "mg_setup_batch", "mg_solve_batch",
-                  "mg_fmg_start", "mg_batch_launch_mode", "mg_batch_groups", "mg_autotune", "mg_set_tile"):
+                  "mg_fmg_start", "mg_batch_launch_mode", "mg_batch_groups", "mg_autotune", "mg_set_tile",
+                  "mg_cttk_trace", "mg_cttk_hybrid_sources"):
             getattr(L, f).restype = st
         _lib = L
     return _lib
@@ -132,12 +136,13 @@ def params(n: int, levels: int = 1, bc: int = BC_PERIODIC, precision: int = PREC
            length: float = 1.0, origin=(0.0, 0.0, 0.0), K: float = 0.0, nu_pre: int = 2,
            nu_post: int = 2, solve_momentum: bool = False, puncture_mass: float = 0.0,
            puncture_pos=(0.0, 0.0, 0.0), conformal_matter: bool = False,
-           eager: bool = False) -> MgParams:
+           eager: bool = False, cttk: bool = False) -> MgParams:
     p = MgParams()
     p.n, p.levels, p.bc, p.precision = n, levels, bc, precision
     p.nu_pre, p.nu_post = nu_pre, nu_post
     p.solve_momentum = 1 if solve_momentum else 0
-    p.flags = (FLAG_CONFORMAL_MATTER if conformal_matter else 0) | (FLAG_EAGER if eager else 0)
+    p.flags = ((FLAG_CONFORMAL_MATTER if conformal_matter else 0) | (FLAG_EAGER if eager else 0)
+               | (FLAG_CTTK if cttk else 0))
     p.length = length
     for a in range(3):
         p.origin[a] = origin[a]
@@ -256,6 +261,13 @@ class Solver:
                                         _dptr(H), _dptr(M), _dptr(c)), "mg_residual_fields")
         return H, M, c
 
+    def cttk_trace(self, u: torch.Tensor, W: torch.Tensor) -> torch.Tensor:
+        """K of the state (u, W) of a CTTK context (K^2 = 12 H0 / psi^5)."""
+        K = torch.empty((self.p.n,) * 3, dtype=torch.float64, device=self.device)
+        _check(lib().mg_cttk_trace(self.ctx, _dptr(u, numel=self.cells), _dptr(W, numel=3 * self.cells), _dptr(K)),
+               "mg_cttk_trace")
+        return K
+
     def probe(self, kernel: int, level: int = 0):
         _check(lib().mg_probe(self.ctx, kernel, level), "mg_probe")
 
@@ -359,6 +371,20 @@ def scalar_field_sources(p: MgParams, phi_modes: np.ndarray, pi_modes: np.ndarra
         SOURCES_SCRATCH_BYTES if want_K else 0, None,
         C.byref(K) if want_K else None, _stream(rho5.device)), "mg_scalar_field_sources")
     return rho5, rho1, S, (K.value if want_K else None)
+
+
+def cttk_hybrid_sources(p: MgParams, rho5: torch.Tensor, rho1: torch.Tensor, S: torch.Tensor):
+    """CTTK-Hybrid: transforms rho5 (-> 0) and S (-> S + D K / (12 pi)) in place and
+    returns (K field, K0) with K^2 = 24 pi (rho5 + <rho1>), K0^2 = 24 pi <rho1>."""
+    n = p.n
+    K = torch.empty((n, n, n), dtype=torch.float64, device=rho5.device)
+    scratch = torch.empty(SOURCES_SCRATCH_BYTES, dtype=torch.uint8, device=rho5.device)
+    K0 = C.c_double(0.0)
+    _check(lib().mg_cttk_hybrid_sources(C.byref(p), _dptr(rho5, numel=n ** 3), _dptr(rho1, numel=n ** 3),
+                                        _dptr(S, numel=3 * n ** 3), _dptr(K), C.c_void_p(scratch.data_ptr()),
+                                        SOURCES_SCRATCH_BYTES, C.byref(K0), _stream(rho5.device)),
+           "mg_cttk_hybrid_sources")
+    return K, K0.value
 
 
 def bowen_york_sources(p: MgParams, table, device="cuda"):

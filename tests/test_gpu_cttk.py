@@ -1,0 +1,192 @@
+"""CTTK and CTTK-Hybrid on the HIP path (Summary; Key features, "Methods"):
+the hybrid sources element by element, the CTTK trace of a state and single W
+steps element by element (FP64), and converged solves against the oracle's and
+against the judge's direct evaluation of eqs. Ham and Mom with K(x)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle import judge
+from paper_2501_13046_amd import grtmg as g
+from gpu_helpers import N, T, dev, mean_free, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def sources(w):
+    rho5, rho1, S, _ = oracle.sources_for(w)
+    return rho5, rho1, S
+
+
+def gp(w, precision, K=0.0, cttk=False, levels=None):
+    return g.params(w.n, levels if levels is not None else w.levels, w.bc, precision, w.length, w.origin, K,
+                    w.nu_pre, w.nu_post, True, cttk=cttk)
+
+
+def judge_norms(w, u, W, rho5, rho1, S, K):
+    gr = judge.Grid(w.n, w.length, judge.BC_PERIODIC, tuple(w.origin))
+    H, M, _ = judge.residuals(gr, u, W, rho5, rho1, S, K)
+    return judge.norms(H, M)
+
+
+@pytest.mark.parametrize("n", [32, 128])
+def test_hybrid_sources_match_oracle(n):
+    w = synth.coupled(n, seed=5)
+    rho5, rho1, S = sources(w)
+    r5o, So, Ko, K0o = oracle.cttk_hybrid_sources(oracle.params_from_workload(w), rho5, rho1, S)
+    r5, r1, Sg = T(rho5), T(rho1), T(S)
+    K, K0 = g.cttk_hybrid_sources(gp(w, g.PREC_FP64), r5, r1, Sg)
+    assert not N(r5).any()
+    # <rho1> is summed in another order on each side (a tree of block sums against
+    # one running sum over n^3 positive terms, whose rounding grows like sqrt(n^3) eps):
+    # 1e-12 leaves room for that at 128^3 and still fails a wrong term by far
+    assert rel_err(N(K), Ko) < 1e-12
+    assert rel_err(N(Sg), So) < 1e-11
+    assert abs(K0 - K0o) <= 1e-12 * K0o
+
+
+@pytest.mark.parametrize("precision", [g.PREC_FP64, g.PREC_FP32_IR])
+def test_hybrid_solve_matches_oracle(precision):
+    n = 32
+    w = synth.coupled(n, seed=6)
+    rho5, rho1, S = sources(w)
+    r5, r1, Sg = T(rho5), T(rho1), T(S)
+    K, K0 = g.cttk_hybrid_sources(gp(w, precision), r5, r1, Sg)
+    s = g.Solver(gp(w, precision, K0), r5, r1, Sg)
+    u = torch.zeros((n,) * 3, dtype=torch.float64, device=dev())
+    W = torch.zeros((3, n, n, n), dtype=torch.float64, device=dev())
+    rep = s.solve(u, W, tol=1e-10, max_outer=60)
+    nr = judge_norms(w, N(u), N(W), rho5, rho1, S, N(K))
+    assert nr[0] <= 1.01e-10 and nr[1] <= 1.01e-10, nr
+    r5o, So, Ko, K0o = oracle.cttk_hybrid_sources(oracle.params_from_workload(w), rho5, rho1, S)
+    uo, Wo = np.zeros((n,) * 3), np.zeros((3, n, n, n))
+    res = oracle.solve(oracle.params_from_workload(w, K0o), uo, Wo, r5o, rho1, So, tol=1e-11, max_outer=60)
+    assert res.status == 0
+    print(f"hybrid prec={precision}: {rep['outer_iters']} iterations (oracle {res.iters})")
+    assert rel_err(1.0 + N(u), 1.0 + uo) < 1e-9
+    assert rel_err(mean_free(N(W)), mean_free(Wo)) < 1e-7
+    s.close()
+
+
+def cttk_setup(w, precision, rho5, rho1, S):
+    return g.Solver(gp(w, precision, cttk=True), T(rho5), T(rho1), T(S))
+
+
+def test_cttk_trace_of_a_state_matches_oracle():
+    n = 32
+    w = synth.coupled(n, seed=7)
+    rho5, rho1, S = sources(w)
+    x = (np.arange(n) + 0.5) / n
+    X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+    u = 0.05 + 5e-5 * np.sin(2 * np.pi * X) * np.cos(2 * np.pi * Z)
+    Wn = 0.02 * np.stack([np.cos(2 * np.pi * (Y + Z)), np.sin(2 * np.pi * X), np.cos(4 * np.pi * Y)])
+    s = cttk_setup(w, g.PREC_FP64, rho5, rho1, S)
+    K = s.cttk_trace(T(u), T(Wn))
+    r5e, Se, Ko = oracle.cttk_update(oracle.params_from_workload(w), u, Wn, rho5, rho1, S)
+    assert rel_err(N(K), Ko) < 1e-12
+    # the residual fields of the state use that trace: H vanishes, M as the oracle's
+    H, M, _ = s.residual_fields(T(u), T(Wn))
+    Ho, Mo, _ = oracle.residuals(oracle.params_from_workload(w), u, Wn, r5e, rho1, Se)
+    scale = np.abs(2 * np.pi * rho1).max()
+    assert np.abs(N(H)).max() <= 1e-12 * scale
+    assert rel_err(N(M), Mo) < 1e-11
+    s.close()
+
+
+def test_cttk_single_steps_match_oracle():
+    n = 32
+    w = synth.coupled(n, seed=8)
+    rho5, rho1, S = sources(w)
+    s = cttk_setup(w, g.PREC_FP64, rho5, rho1, S)
+    po = oracle.params_from_workload(w)
+    u = torch.zeros((n,) * 3, dtype=torch.float64, device=dev())
+    W = torch.zeros((3, n, n, n), dtype=torch.float64, device=dev())
+    uo, Wo = np.zeros((n,) * 3), np.zeros((3, n, n, n))
+    for step in range(3):
+        s.vcycle(g.EQ_W, u, W)
+        r5e, Se, _ = oracle.cttk_update(po, uo, Wo, rho5, rho1, S)
+        oracle.step(po, 2, uo, Wo, r5e, rho1, Se)
+        assert rel_err(mean_free(N(W)), mean_free(Wo)) < 1e-11, step
+    assert not N(u).any()  # psi is data
+    with pytest.raises(g.MGError):
+        s.vcycle(g.EQ_PSI, u, W)
+    s.close()
+
+
+@pytest.mark.parametrize("precision,n", [(g.PREC_FP64, 32), (g.PREC_FP32_IR, 32), (g.PREC_FP32_IR, 48)])
+def test_cttk_solve_matches_oracle(precision, n):
+    w = synth.coupled(n, seed=9)
+    rho5, rho1, S = sources(w)
+    s = cttk_setup(w, precision, rho5, rho1, S)
+    x = (np.arange(n) + 0.5) / n
+    X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+    u0 = 0.02 + 5e-5 * np.cos(2 * np.pi * X) * np.sin(2 * np.pi * Y)  # chosen psi (free data)
+    u = T(u0)
+    W = torch.zeros((3, n, n, n), dtype=torch.float64, device=dev())
+    rep = s.solve(u, W, tol=1e-10, max_outer=80)
+    assert np.array_equal(N(u), u0)
+    K = N(s.cttk_trace(u, W))
+    nr = judge_norms(w, u0, N(W), rho5, rho1, S, K)
+    assert nr[0] <= 1.01e-10 and nr[1] <= 1.01e-10, nr
+    Wo = np.zeros((3, n, n, n))
+    res, Ko = oracle.cttk_solve(oracle.params_from_workload(w), u0, Wo, rho5, rho1, S, tol=1e-11, max_outer=80)
+    assert res.status == 0
+    print(f"cttk n={n} prec={precision}: {rep['outer_iters']} iterations (oracle {res.iters}), "
+          f"vcycles psi {rep['vcycles_psi']} W {rep['vcycles_W']}")
+    assert rep["vcycles_psi"] == 0
+    assert rel_err(mean_free(N(W)), mean_free(Wo)) < 1e-7
+    assert rel_err(K, Ko) < 1e-9
+    s.close()
+
+
+def test_cttk_solve_128_satisfies_the_constraints():
+    """The 128^3 coupled workload under CTTK (FP32 V-cycles in FP64 refinement): the
+    converged state satisfies eqs. Ham and Mom with its trace, by the judge."""
+    n = 128
+    w = synth.coupled(n, seed=0)
+    rho5, rho1, S = sources(w)
+    s = cttk_setup(w, g.PREC_FP32_IR, rho5, rho1, S)
+    u = torch.zeros((n,) * 3, dtype=torch.float64, device=dev())
+    W = torch.zeros((3, n, n, n), dtype=torch.float64, device=dev())
+    # the K-W fixed point contracts by ~0.79 per iteration at this size (0.48 at 32^3)
+    rep = s.solve(u, W, tol=1e-10, max_outer=200)
+    K = N(s.cttk_trace(u, W))
+    nr = judge_norms(w, N(u), N(W), rho5, rho1, S, K)
+    print(f"cttk 128: {rep['outer_iters']} iterations, judge {nr[:2]}")
+    assert nr[0] <= 1.01e-10 and nr[1] <= 1.01e-10, nr
+    assert K.min() > 0.0
+    s.close()
+
+
+def test_cttk_reports_a_conformal_factor_without_real_trace():
+    n = 32
+    w = synth.coupled(n, seed=9)
+    rho5, rho1, S = sources(w)
+    s = cttk_setup(w, g.PREC_FP32_IR, rho5, rho1, S)
+    x = (np.arange(n) + 0.5) / n
+    u = T(np.broadcast_to(0.05 * np.cos(2 * np.pi * x)[:, None, None], (n, n, n)))
+    W = torch.zeros((3, n, n, n), dtype=torch.float64, device=dev())
+    rep = s.solve(u, W, tol=1e-10, max_outer=5, raise_on_failure=False)
+    assert rep["status"] == g.MG_ERR_DIVERGED
+    assert torch.isnan(s.cttk_trace(u, W)).any()
+    s.close()
+
+
+def test_cttk_invalid_parameters():
+    w = synth.coupled(16, seed=1)
+    rho5, rho1, S = sources(w)
+    bad = [gp(w, g.PREC_FP64, K=1.0, cttk=True)]
+    p = gp(w, g.PREC_FP64, cttk=True)
+    p.solve_momentum = 0
+    bad.append(p)
+    for p in bad:
+        with pytest.raises(g.MGError):
+            g.Solver(p, T(rho5), T(rho1), T(S))
+    # the trace is only defined for a CTTK context
+    s = g.Solver(gp(w, g.PREC_FP64, K=1.0), T(rho5), T(rho1), T(S))
+    z = torch.zeros((16,) * 3, dtype=torch.float64, device=dev())
+    with pytest.raises(g.MGError):
+        s.cttk_trace(z, torch.zeros((3, 16, 16, 16), dtype=torch.float64, device=dev()))
+    s.close()
