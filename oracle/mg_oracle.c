@@ -1024,8 +1024,13 @@ void orc_cttk_update(const orc_params *p, const double *u, const double *W, cons
 /*
  * CTTK solve: u is data; W is solved.  Every iteration: K and the shifted sources
  * from (u, W), the norms of H_h and M_h with them (H_h vanishes up to rounding), the
- * convergence test, then one W step.  K receives the trace of the final state.
- * Status and outputs as orc_solve (p->solve_momentum must be 1).
+ * convergence test, then one W step, W -> W + f.  The K-W coupling makes this a
+ * fixed-point iteration whose contraction grows with resolution, so the steps are
+ * combined by one-step Anderson mixing (a secant method on the fixed point): with
+ * dF = f - f_prev and dW = W - W_prev from the previous iteration,
+ *   gamma = <dF, f> / <dF, dF>,   W -> W + f - gamma (dW + dF)
+ * (gamma = 0 on the first iteration or when dF = 0).  K receives the trace of the
+ * final state.  Status and outputs as orc_solve (p->solve_momentum must be 1).
  */
 int orc_cttk_solve(const orc_params *p, const double *u, double *W, const double *rho5, const double *rho1,
                    const double *S, const double *f, double *K, double tol, int max_outer, double *hist,
@@ -1038,6 +1043,9 @@ int orc_cttk_solve(const orc_params *p, const double *u, double *W, const double
     double *Se = (double *)malloc(3 * m * sizeof(double));
     double *H = (double *)malloc(m * sizeof(double));
     double *M = (double *)malloc(3 * m * sizeof(double));
+    double *Wk = (double *)malloc(3 * m * sizeof(double));
+    double *Wp = (double *)malloc(3 * m * sizeof(double));
+    double *fp = (double *)malloc(3 * m * sizeof(double));
     sources s = {r5, rho1, Se, f};
     hier HW;
     hier_init(&HW, &p0, 3);
@@ -1061,13 +1069,33 @@ int orc_cttk_solve(const orc_params *p, const double *u, double *W, const double
             status = 4;
             break;
         }
+        memcpy(Wk, W, 3 * m * sizeof(double));
         if (step_W(&HW, &p0, u, W, &s)) {
             status = 1;
             break;
         }
+        /* W now holds W_k + f; Anderson mixing with the previous step */
+        double sfd = 0.0, sdd = 0.0;
+        if (it > 0)
+            for (long q = 0; q < 3 * m; q++) {
+                double fk = W[q] - Wk[q], dF = fk - fp[q];
+                sfd += dF * fk;
+                sdd += dF * dF;
+            }
+        double gamma = (it > 0 && sdd > 0.0) ? sfd / sdd : 0.0;
+        for (long q = 0; q < 3 * m; q++) {
+            double fk = W[q] - Wk[q];
+            double dF = fk - fp[q], dW = Wk[q] - Wp[q];
+            W[q] = Wk[q] + fk - (it > 0 ? gamma * (dW + dF) : 0.0);
+            Wp[q] = Wk[q];
+            fp[q] = fk;
+        }
     }
     if (iters) *iters = it;
     hier_free(&HW);
+    free(Wk);
+    free(Wp);
+    free(fp);
     free(r5);
     free(Se);
     free(H);

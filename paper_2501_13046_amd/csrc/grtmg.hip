@@ -44,7 +44,8 @@ enum {
     S_FLAG_W = 13,
     S_DIVERGED = 14,
     S_K2 = 15, // K^2 of a batch member
-    S_COUNT = 16
+    S_AA = 16, // CTTK Anderson mixing: <dF, f>, <dF, dF>, steps taken, gamma
+    S_COUNT = 20
 };
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -131,6 +132,7 @@ struct mg_ctx {
     bool cttk;
     const double *rho5_in, *S_in;
     double *rho5_eff, *S_eff, *Kf;
+    double *aa_W, *aa_f; // Anderson mixing history of the CTTK solve: previous W and step (3 n^3 each)
     int vc_psi, vc_W;
     // batch membership: streams borrowed from the batch, updates gated by the
     // instance's active flag, a convergence check after every evaluation
@@ -225,8 +227,10 @@ void carve(mg_ctx *c, Carver &cv)
         c->rho5_eff = (double *)cv.take(m0);
         c->S_eff = (double *)cv.take(3 * m0);
         c->Kf = (double *)cv.take(m0);
+        c->aa_W = (double *)cv.take(3 * m0);
+        c->aa_f = (double *)cv.take(3 * m0);
     } else {
-        c->rho5_eff = c->S_eff = c->Kf = nullptr;
+        c->rho5_eff = c->S_eff = c->Kf = c->aa_W = c->aa_f = nullptr;
     }
     c->scal = (double *)cv.take(S_COUNT * sizeof(double));
     c->m_psi = (int)c->cells[c->L - 1];
@@ -867,8 +871,9 @@ void residual(mg_ctx *c, const double *u, const double *W, bool want_M, double *
                            0xAu, 0.0, c->scal + S_NORM, c->zs);
 }
 
+// mix: the CTTK solve's Anderson-mixed update in place of W += d - mean(d).
 template <typename T>
-void step_W(mg_ctx *c, const double *u, double *W, bool residual_done)
+void step_W(mg_ctx *c, const double *u, double *W, bool residual_done, bool mix = false)
 {
     if (!residual_done) {
         source_mean(c, u);
@@ -881,7 +886,18 @@ void step_W(mg_ctx *c, const double *u, double *W, bool residual_done)
     hipLaunchKernelGGL(k_sum3<T>, dim3(sb, 1, c->gz), dim3(kBlock), 0, c->s, (const T *)c->wd0[0], m, c->part, c->zs);
     hipLaunchKernelGGL(k_reduce_final<3>, dim3(1, 1, c->gz), dim3(kBlock), 0, c->s, (const double *)c->part, sb, 0u,
                        1.0 / (double)m, c->scal + S_MEAND, c->zs);
-    {
+    if (mix) {
+        // two partials per block in c->part (4 per block of the finest level)
+        const unsigned db = std::min<unsigned>(std::min<unsigned>(nblk(3 * m), kSrcBlocks), 2 * (unsigned)nb);
+        hipLaunchKernelGGL(k_aa_dots<T>, dim3(db), dim3(kBlock), 0, c->s, (const T *)c->wd0[0],
+                           (const double *)(c->scal + S_MEAND), (const double *)c->aa_f, m, c->part);
+        hipLaunchKernelGGL(k_reduce_final<2>, dim3(1), dim3(kBlock), 0, c->s, (const double *)c->part, (int64_t)db,
+                           0u, 0.0, c->scal + S_AA, 0LL);
+        hipLaunchKernelGGL(k_aa_gamma, dim3(1), dim3(64), 0, c->s, c->scal + S_AA);
+        Probe pr(c, MG_PROBE_UPDATE, 0);
+        hipLaunchKernelGGL(k_aa_update<T>, dim3(nblk(3 * m)), dim3(kBlock), 0, c->s, W, (const T *)c->wd0[0],
+                           (const double *)(c->scal + S_MEAND), c->aa_W, c->aa_f, (const double *)(c->scal + S_AA), m);
+    } else {
         Probe pr(c, MG_PROBE_UPDATE, 0);
         hipLaunchKernelGGL(k_update_W<T>, dim3(nb, 1, c->gz), dim3(kBlock), 0, c->s, W, (const T *)c->wd0[0],
                            (const double *)(c->scal + S_MEAND), m,
@@ -1000,7 +1016,7 @@ template <typename T>
 void outer_body(mg_ctx *c, double *u, double *W, bool want_M)
 {
     if (c->cttk) {
-        step_W<T>(c, u, W, true);
+        step_W<T>(c, u, W, true, true);
         evaluate<T>(c, u, W, want_M, true, false);
         return;
     }
@@ -1092,6 +1108,7 @@ mg_status solve(mg_ctx *c, double *u, double *W, double tol, int max_outer, mg_r
     }
     c->cont_valid = false;
     fill<double>(c->s, c->scal + S_FLAG_PSI, 2, 0.0, c->gz, c->zs);
+    if (c->cttk) fill<double>(c->s, c->scal + S_AA, 4, 0.0); // the mixing restarts with every solve
     if (!resume) {
         evaluate<T>(c, u, W, want_M);
         if (post_norms(c, 0) != MG_OK) return MG_ERR_HIP;

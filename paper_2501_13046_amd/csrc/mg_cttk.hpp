@@ -76,4 +76,54 @@ __global__ void __launch_bounds__(kBlock) k_cttk_shift_S(Geo g, const double *__
     for (int a = 0; a < 3; a++) S_out[a * m + q] = (S_in ? S_in[a * m + q] : 0.0) + d[a] * s;
 }
 
+// ---- Anderson mixing of the CTTK fixed point ------------------------------------------
+// The K-W coupling makes the CTTK outer iteration a fixed-point iteration whose
+// contraction grows with resolution; consecutive W steps are combined by one-step
+// Anderson mixing (a secant method on the fixed point).  With f = d - mean(d) the
+// W step's correction, dF = f - f_prev and dW = W - W_prev from the previous
+// iteration:  gamma = <dF, f> / <dF, dF>,  W -> W + f - gamma (dW + dF).
+// aa: device scalars {<dF, f>, <dF, dF>, steps taken, gamma}.
+
+// Block partial sums of <dF, f> and <dF, dF> over the three components (grid-stride).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_aa_dots(const T *__restrict__ d, const double *__restrict__ mean,
+                                                    const double *__restrict__ f_prev, int64_t m,
+                                                    double *__restrict__ partials)
+{
+    double v[2] = {0.0, 0.0};
+    for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < 3 * m; q += (int64_t)gridDim.x * kBlock) {
+        const double f = (double)d[q] - mean[q / m];
+        const double dF = f - f_prev[q];
+        v[0] += dF * f;
+        v[1] += dF * dF;
+    }
+    block_reduce_store<2>(v, 0u, partials + 2 * (int64_t)blockIdx.x);
+}
+
+// gamma from the reduced sums (0 on the first step or when dF = 0); counts the step.
+__global__ void k_aa_gamma(double *aa)
+{
+    if (threadIdx.x != 0) return;
+    aa[3] = (aa[2] > 0.0 && aa[1] > 0.0) ? aa[0] / aa[1] : 0.0;
+    aa[2] += 1.0;
+}
+
+// W -> W + f - gamma (dW + dF); the history becomes W_prev = W, f_prev = f.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_aa_update(double *__restrict__ W, const T *__restrict__ d,
+                                                      const double *__restrict__ mean, double *__restrict__ W_prev,
+                                                      double *__restrict__ f_prev, const double *__restrict__ aa,
+                                                      int64_t m)
+{
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q >= 3 * m) return;
+    const double gamma = aa[3];
+    const double f = (double)d[q] - mean[q / m];
+    const double w = W[q];
+    const double mix = gamma != 0.0 ? gamma * ((w - W_prev[q]) + (f - f_prev[q])) : 0.0;
+    W[q] = w + f - mix;
+    W_prev[q] = w;
+    f_prev[q] = f;
+}
+
 } // namespace grtmg
