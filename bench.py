@@ -181,6 +181,52 @@ def bench_scan_96(g, synth, dev, args, log):
     return out
 
 
+def bench_methods(g, w, K, rho5, rho1, S, args, log):
+    """The paper's two CTT variants on the headline workload (mixed precision, zero
+    start, tolerance as the headline): CTTK-Hybrid (K^2 = 24 pi (rho5 + <rho1>) in
+    place, psi solved with K0) and CTTK (psi = 1 as data, K from eq. Ham after every
+    W step).  Setup and tuning off the clock."""
+    import torch
+    n = w.n
+    out = {}
+    r5h, Sh = rho5.clone(), S.clone()
+    ph = g.params(n, w.levels, w.bc, g.PREC_FP32_IR, w.length, w.origin, 0.0, w.nu_pre, w.nu_post, True)
+    Kf, K0 = g.cttk_hybrid_sources(ph, r5h, rho1, Sh)
+    ph.K = K0
+    pc = g.params(n, w.levels, w.bc, g.PREC_FP32_IR, w.length, w.origin, 0.0, w.nu_pre, w.nu_post, True, cttk=True)
+    for name, p, srcs in (("cttk_hybrid", ph, (r5h, rho1, Sh)), ("cttk", pc, (rho5, rho1, S))):
+        s = g.Solver(p, *srcs)
+        u = torch.zeros((n,) * 3, dtype=torch.float64, device=rho5.device)
+        W = torch.zeros((3, n, n, n), dtype=torch.float64, device=rho5.device)
+        if args.tune_cache:
+            g.autotune_cached(s, u, W, path=args.tune_cache, reps=20)
+        else:
+            s.autotune(u, W, reps=20)
+
+        def run():
+            u.zero_()
+            W.zero_()
+            return s.solve(u, W, tol=args.tol, max_outer=200)
+
+        run()
+        torch.cuda.synchronize()
+        reps = max(1, args.steps // 2)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = run()
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / reps
+        Kt = s.cttk_trace(u, W) if name == "cttk" else Kf
+        out[f"{name}_{n}"] = dict(seconds=sec, outer_iters=r["outer_iters"], vcycles_psi=r["vcycles_psi"],
+                                  vcycles_W=r["vcycles_W"], h_rms=r["h_rms"], m_rms=r["m_rms"],
+                                  K_min=float(Kt.min()), K_max=float(Kt.max()),
+                                  K0=K0 if name == "cttk_hybrid" else None)
+        log(f"[bench] {name}_{n}: {sec * 1e3:.3f} ms/solve, outer={r['outer_iters']}, K {float(Kt.min()):.3f}.."
+            f"{float(Kt.max()):.3f} (CTT K = {K:.3f})")
+        s.close()
+    return out
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -263,7 +309,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-runs", type=int, default=1, help="oracle solves of the 128^3 workload to time")
-    ap.add_argument("--no-extra", action="store_true", help="skip the 256^3 puncture and 96-instance scan legs")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 256^3 puncture, 96-instance scan and CTTK / CTTK-Hybrid legs")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison solves")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain device copy of 256 MiB (the reference dispatch that scales "
@@ -504,6 +551,7 @@ def main():
         extra["puncture_shell_256"] = bench_puncture_256(g, synth, dev, args, log)
         extra["bowen_york_binary_256"] = bench_bowen_york_256(g, synth, dev, args, log)
         extra["scan_96"] = bench_scan_96(g, synth, dev, args, log)
+        extra["methods"] = bench_methods(g, w, K, rho5, rho1, S, args, log)
 
     # ---- CPU oracle: the same workload solved to the same tolerance on the host cores
     cpu = None

@@ -1259,9 +1259,11 @@ __device__ __forceinline__ bool coarse_psi_krylov_wave(const Geo &g, const T *c,
     double xv = 0.0;
     bool ok = false;
     if constexpr (BC == kBcPeriodic) {
+        // conjugate gradients end within M steps in exact arithmetic; a system that needs
+        // many more is ill-conditioned or indefinite, and elimination is then quicker
         double rr = b, p = b, rz = bb;
 #pragma unroll 1
-        for (int it = 0; it < 4 * M + 32; it++) {
+        for (int it = 0; it < M + 16; it++) {
             const double ap = apply(p);
             const double pap = wave_sum_dpp(p * ap);
             if (!(pap != 0.0)) break;
