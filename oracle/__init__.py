@@ -19,8 +19,12 @@ and Robin, psi with its Newton coefficient, all three W components), the
 exact solution as a fixed point of every colour pass, the colour convention,
 the cycle order and contraction of both V-cycles; the CTTK and CTTK-Hybrid
 methods against the Friedmann trace and the judge's direct evaluation of eqs.
-Ham and Mom with a varying K; each such pin is shown to fail on a copy of the
-oracle with a planted mistake (``planted``).  No
+Ham and Mom with a varying K; the two-level mesh refinement (``refine.py``)
+against a dense solve of independently written composite equations and the
+accuracy of a uniform grid of the box's spacing, with the zero ghost rule
+against the embedded periodic operator; each such pin is shown to fail on a
+copy of the oracle with a planted mistake (``planted``, or a patched function
+of ``refine.py``).  No
 oracle function is left "parity unpinned".
 """
 from __future__ import annotations
@@ -41,6 +45,7 @@ BC_PERIODIC = 0
 BC_ROBIN = 1
 BC_REFLECT = 2
 BC_EXTRAP = 3
+BC_ZERO = 4
 FLAG_CONFORMAL_MATTER = 1
 
 

@@ -19,6 +19,7 @@ BC_PERIODIC = 0
 BC_ROBIN = 1
 BC_REFLECT = 2
 BC_EXTRAP = 3
+BC_ZERO = 4
 
 
 class Grid:
@@ -46,6 +47,8 @@ class Grid:
             return np.pad(a, 2, mode="wrap")
         if self.bc == BC_REFLECT:   # mirror across each face, edge cell repeated
             return np.pad(a, 2, mode="symmetric")
+        if self.bc == BC_ZERO:      # homogeneous ghosts
+            return np.pad(a, 2, mode="constant")
         if self.bc == BC_EXTRAP:    # the cell next to each face continued outwards
             return np.pad(a, 2, mode="edge")
         ii = np.arange(-2, n + 2)
@@ -234,7 +237,7 @@ def _at(g: Grid, a, i, j, k):
     n = g.n
     if g.bc == BC_PERIODIC:
         return a[i % n, j % n, k % n]
-    if g.bc in (BC_REFLECT, BC_EXTRAP):
+    if g.bc in (BC_REFLECT, BC_EXTRAP, BC_ZERO):
         return g.pad(a)[i + 2, j + 2, k + 2]
     ci, cj, ck = np.clip(i, 0, n - 1), np.clip(j, 0, n - 1), np.clip(k, 0, n - 1)
 

@@ -49,7 +49,9 @@
  * cell nearest to g (coordinates clamped into the grid), radii measured from
  * the puncture position; reflective: the mirror image of the grid across the
  * boundary face (even parity); extrapolating: zeroth-order extrapolation along
- * the face normal (each ghost takes the value of the grid cell next to the face).
+ * the face normal (each ghost takes the value of the grid cell next to the face);
+ * zero: homogeneous ghosts (every ghost is 0), the rule of a refined box whose
+ * interface ghosts enter as a forcing (see oracle/refine.py).
  *
  * Multigrid (Key features, "Fast": errors reduced across a hierarchy of
  * discretisations): V(nu_pre, nu_post) cycles with double-buffered red-black
@@ -74,6 +76,7 @@
 #define OBC_ROBIN 1
 #define OBC_REFLECT 2
 #define OBC_EXTRAP 3
+#define OBC_ZERO 4
 #define OMAXLEV 16
 
 /* flags bit 0: conformally rescaled matter (see orc_residuals) */
@@ -170,6 +173,7 @@ static double at(const geom *g, const double *a, int i, int j, int k)
     if (g->bc == OBC_PERIODIC)
         return a[idx3(n, wrapi(i, n), wrapi(j, n), wrapi(k, n))];
     if (inside(n, i, j, k)) return a[idx3(n, i, j, k)];
+    if (g->bc == OBC_ZERO) return 0.0; /* homogeneous ghosts (the interface of a refined box) */
     if (g->bc == OBC_REFLECT || g->bc == OBC_EXTRAP) {
         int I[2], J[2], K[2];
         double wi[2], wj[2], wk[2], s = 0.0;
@@ -192,6 +196,7 @@ static double self_weight(const geom *g, int i, int j, int k, int di, int dj, in
     if (g->bc == OBC_PERIODIC)
         return (wrapi(ii, n) == i && wrapi(jj, n) == j && wrapi(kk, n) == k) ? 1.0 : 0.0;
     if (inside(n, ii, jj, kk)) return (di == 0 && dj == 0 && dk == 0) ? 1.0 : 0.0;
+    if (g->bc == OBC_ZERO) return 0.0;
     if (g->bc == OBC_REFLECT || g->bc == OBC_EXTRAP) {
         int I[2], J[2], K[2];
         double wi[2], wj[2], wk[2], s = 0.0;
