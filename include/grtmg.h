@@ -62,7 +62,7 @@ typedef enum mg_status {
     MG_ERR_SINGULAR = 6       /* coarsest-level matrix could not be factorised      */
 } mg_status;
 
-enum { MG_BC_PERIODIC = 0, MG_BC_ROBIN = 1, MG_BC_REFLECT = 2, MG_BC_EXTRAP = 3 };
+enum { MG_BC_PERIODIC = 0, MG_BC_ROBIN = 1, MG_BC_REFLECT = 2, MG_BC_EXTRAP = 3, MG_BC_ZERO = 4 };
 enum { MG_PREC_FP64 = 0, MG_PREC_FP32_IR = 1 };
 enum { MG_EQ_PSI = 1, MG_EQ_W = 2, MG_EQ_BOTH = 3 };
 enum { MG_FLAG_CONFORMAL_MATTER = 1, MG_FLAG_EAGER = 2, MG_FLAG_CTTK = 4 };
@@ -82,6 +82,9 @@ enum { MG_FLAG_CONFORMAL_MATTER = 1, MG_FLAG_EAGER = 2, MG_FLAG_CTTK = 4 };
  *                 MG_BC_REFLECT: mirror image across the face (a(-1) = a(0),
  *                 a(-2) = a(1); even parity).  MG_BC_EXTRAP: zeroth-order
  *                 extrapolation along the face normal (a(-1) = a(-2) = a(0)).
+ *                 MG_BC_ZERO: homogeneous ghosts (a(-1) = a(-2) = 0), the rule of a
+ *                 refined box whose interface values enter through the forcing f
+ *                 (see mg_refine_solve).
  *                 The momentum equation is supported on periodic grids only.
  *  precision      MG_PREC_FP64: every kernel in FP64.  MG_PREC_FP32_IR: V-cycle
  *                 interior (smoothers, transfers, defects) in FP32 inside FP64
@@ -258,6 +261,40 @@ mg_status mg_cttk_trace(mg_ctx *ctx, const double *d_u, const double *d_W, doubl
  */
 mg_status mg_cttk_hybrid_sources(const mg_params *p, double *d_rho5, const double *d_rho1, double *d_S,
                                  double *d_K, void *d_scratch, size_t scratch_bytes, double *h_K0, void *stream);
+
+/*
+ * Two-level static mesh refinement of eq. Ham (Key features, "Adaptive Mesh
+ * Refinement": a block-structured hierarchy of refined boxes, here one static box;
+ * "Fast": multigrid over the hierarchy).  The composite grid is the base context
+ * cb's grid (n_c^3 cells of spacing h) and the box context cx's grid: 2m cells per
+ * axis of spacing h/2 covering the m^3 base cells from base cell (b0, b0, b0) on,
+ * set up with boundary rule MG_BC_ZERO, length m h and origin = base origin + b0 h
+ * (same K, puncture, conformal-matter flag; both psi-only, not CTTK, not in a
+ * batch, no background fields; margin b0 >= 3 and b0 + m + 3 <= n_c).  Both
+ * contexts must have been set up with a forcing array d_f, which this call
+ * overwrites, and with the same caller stream.
+ * Composite equations: H_h of the box with its two ghost layers taken from the base
+ * grid by the cubic of mg_interp_cubic (the box solves them under the zero rule with
+ * the ghost taps as its forcing), H_h of the base cells the box does not cover, and
+ * base values under the box equal to the average of their 8 children.
+ * Iteration (a two-level FAS cycle, Brandt's multi-level adaptive technique): base
+ * cells under the box take their children's average; nu_box Newton-multigrid steps
+ * of the box; the base forcing tau = R H_f - H_c(R u_f) on covered cells (0
+ * elsewhere); nu_base steps of the base grid; the box adds the cubic interpolation
+ * of the base grid's change.  Stops when the composite norm
+ * sqrt((sum_box H^2 (h/2)^3 + sum_uncovered H^2 h^3) / L^3) <= tol, or after
+ * max_outer iterations.  d_uc (n_c^3) and d_uf ((2m)^3) hold the initial guess and
+ * the result (u of psi = psi0 + u on each grid; on return the base cells under the
+ * box hold their children's average).  d_work: caller-owned device workspace,
+ * 256-byte aligned, of mg_refine_workspace_size bytes.  rep (may be NULL): iterations,
+ * status, h_rms / h_max = composite rms and max |H| (m_* = 0), history of
+ * (rms, 0, max, 0).  Synchronises once per iteration.  Returns MG_OK,
+ * MG_ERR_NOT_CONVERGED, MG_ERR_DIVERGED, MG_ERR_INVALID or MG_ERR_WORKSPACE.
+ */
+mg_status mg_refine_workspace_size(const mg_params *base, const mg_params *box, int32_t b0, size_t *bytes);
+mg_status mg_refine_solve(mg_ctx *cb, mg_ctx *cx, int32_t b0, double *d_uc, double *d_uf, void *d_work,
+                          size_t work_bytes, double tol, int32_t max_outer, int32_t nu_box, int32_t nu_base,
+                          mg_report *rep);
 
 void mg_destroy(mg_ctx *ctx);
 const char *mg_status_str(mg_status s);

@@ -22,6 +22,7 @@
 #include "mg_kernels.hpp"
 #include "mg_tiled.hpp"
 #include "mg_cttk.hpp"
+#include "mg_refine.hpp"
 #include "mg_internal.h"
 
 using namespace grtmg;
@@ -64,7 +65,7 @@ struct Carver {
 
 unsigned nblk(int64_t count) { return (unsigned)((count + kBlock - 1) / kBlock); }
 
-// Calls f with a non-periodic boundary rule (Robin, reflective, extrapolating) as a
+// Calls f with a non-periodic boundary rule (Robin, reflective, extrapolating, zero) as a
 // compile-time constant: f(std::integral_constant<int, kBc...>{}).
 template <typename F>
 void with_bc(int bc, F &&f)
@@ -72,6 +73,7 @@ void with_bc(int bc, F &&f)
     switch (bc) {
     case MG_BC_REFLECT: f(std::integral_constant<int, kBcReflect>{}); break;
     case MG_BC_EXTRAP: f(std::integral_constant<int, kBcExtrap>{}); break;
+    case MG_BC_ZERO: f(std::integral_constant<int, kBcZero>{}); break;
     default: f(std::integral_constant<int, kBcRobin>{}); break;
     }
 }
@@ -165,7 +167,7 @@ mg_status validate(const mg_params *p)
     if (p->n < 3 || p->n > 4096) return MG_ERR_INVALID;
     // cell indices are 32-bit (n^3 < 2^32, n <= 1625)
     if ((double)p->n * p->n * (double)p->n >= 4294967296.0) return MG_ERR_INVALID;
-    if (p->bc < MG_BC_PERIODIC || p->bc > MG_BC_EXTRAP) return MG_ERR_INVALID;
+    if (p->bc < MG_BC_PERIODIC || p->bc > MG_BC_ZERO) return MG_ERR_INVALID;
     if (p->precision != MG_PREC_FP64 && p->precision != MG_PREC_FP32_IR) return MG_ERR_INVALID;
     if (p->nu_pre < 0 || p->nu_post < 0 || p->nu_pre + p->nu_post < 1 || p->nu_pre > 16 ||
         p->nu_post > 16)
@@ -2571,11 +2573,195 @@ mg_status mg_shell_field_sources(const mg_params *p, double amp, double r0, doub
     return hip_status();
 }
 
+// ---- two-level static mesh refinement ----------------------------------------------------
+
+} // extern "C"
+
+namespace {
+
+// Geometry of a refined box over a base grid (corner at base cell b0 on every axis,
+// m base cells per axis, 2m box cells): both psi-only, the box under the zero rule,
+// a margin of 3 base cells, matching spacing, origin and physics.
+mg_status refine_check(const mg_params &pb, const mg_params &px, int b0)
+{
+    if (validate(&pb) != MG_OK || validate(&px) != MG_OK) return MG_ERR_INVALID;
+    if (pb.solve_momentum || px.solve_momentum || px.bc != MG_BC_ZERO || pb.bc == MG_BC_ZERO) return MG_ERR_INVALID;
+    if ((pb.flags | px.flags) & MG_FLAG_CTTK) return MG_ERR_INVALID;
+    if ((pb.flags & MG_FLAG_CONFORMAL_MATTER) != (px.flags & MG_FLAG_CONFORMAL_MATTER)) return MG_ERR_INVALID;
+    if (px.n % 2 != 0) return MG_ERR_INVALID;
+    const int m = px.n / 2;
+    if (b0 < 3 || b0 + m + 3 > pb.n) return MG_ERR_INVALID;
+    const double h = pb.length / pb.n, tol = 1e-12 * pb.length;
+    if (std::fabs(px.length - m * h) > tol) return MG_ERR_INVALID;
+    for (int a = 0; a < 3; a++)
+        if (std::fabs(px.origin[a] - (pb.origin[a] + b0 * h)) > tol || px.puncture_pos[a] != pb.puncture_pos[a])
+            return MG_ERR_INVALID;
+    if (px.K != pb.K || px.puncture_mass != pb.puncture_mass) return MG_ERR_INVALID;
+    return MG_OK;
+}
+
+struct RefineWork {
+    double *uc_old, *Hf, *Hc, *part, *res;
+    size_t bytes;
+};
+
+RefineWork refine_layout(const mg_params &pb, const mg_params &px, char *base)
+{
+    Carver cv{base};
+    const size_t mc = (size_t)pb.n * pb.n * pb.n, mf = (size_t)px.n * px.n * px.n;
+    RefineWork w;
+    w.uc_old = (double *)cv.take(mc * sizeof(double));
+    w.Hf = (double *)cv.take(mf * sizeof(double));
+    w.Hc = (double *)cv.take(mc * sizeof(double));
+    w.part = (double *)cv.take(2 * (size_t)kSrcBlocks * sizeof(double));
+    w.res = (double *)cv.take(2 * sizeof(double));
+    w.bytes = align_up(cv.off, 256);
+    return w;
+}
+
+// One Newton-multigrid step of eq. Ham on a context, on its own stream (ordered
+// after and before the caller's stream).
+void psi_step(mg_ctx *c, double *u)
+{
+    enter(c);
+    if (c->f32)
+        step_psi<float>(c, u, nullptr, false);
+    else
+        step_psi<double>(c, u, nullptr, false);
+    leave(c);
+}
+
+// H_h of a context at u (its forcing included) into H.
+void residual_field(mg_ctx *c, const double *u, double *H)
+{
+    enter(c);
+    residual<double>(c, u, nullptr, false, H, nullptr, nullptr, nullptr, nullptr, nullptr, false);
+    leave(c);
+}
+
+} // namespace
+
+extern "C" {
+
+mg_status mg_refine_workspace_size(const mg_params *base, const mg_params *box, int32_t b0, size_t *bytes)
+{
+    if (!base || !box || !bytes) return MG_ERR_INVALID;
+    const mg_status st = refine_check(*base, *box, b0);
+    if (st != MG_OK) return st;
+    *bytes = refine_layout(*base, *box, nullptr).bytes;
+    return MG_OK;
+}
+
+mg_status mg_refine_solve(mg_ctx *cb, mg_ctx *cx, int32_t b0, double *d_uc, double *d_uf, void *d_work,
+                          size_t work_bytes, double tol, int32_t max_outer, int32_t nu_box, int32_t nu_base,
+                          mg_report *rep)
+{
+    if (!cb || !cx || !d_uc || !d_uf || !(tol > 0.0) || max_outer < 0 || nu_box < 1 || nu_base < 1) return MG_ERR_INVALID;
+    if (rep && rep->history && rep->history_cap < 0) return MG_ERR_INVALID;
+    if (refine_check(cb->p, cx->p, b0) != MG_OK || cb->batched || cx->batched) return MG_ERR_INVALID;
+    if (!cb->f || !cx->f || cb->user_s != cx->user_s) return MG_ERR_INVALID;
+    if (cb->bg_psi0 || cb->bg_A2 || cx->bg_psi0 || cx->bg_A2) return MG_ERR_INVALID;
+    const RefineWork w = refine_layout(cb->p, cx->p, (char *)d_work);
+    if (!d_work || work_bytes < w.bytes || ((uintptr_t)d_work % 256) != 0) return MG_ERR_WORKSPACE;
+    auto t0 = std::chrono::steady_clock::now();
+    cb->cont_valid = cx->cont_valid = false;
+    cb->vc_psi = cx->vc_psi = 0;
+    const hipStream_t s = cb->user_s;
+    const int nc = cb->p.n, m = cx->p.n / 2, nf = 2 * m;
+    const int64_t mc = (int64_t)nc * nc * nc, mf = (int64_t)nf * nf * nf, mm = (int64_t)m * m * m;
+    const BoxGeo bx{nc, b0, m};
+    double *fc = const_cast<double *>(cb->f), *ff = const_cast<double *>(cx->f);
+    const double hc = cb->p.length / nc, hf = hc / 2, vol = cb->p.length * cb->p.length * cb->p.length;
+    const unsigned nbn = std::min<unsigned>(nblk(mf + mc), kSrcBlocks);
+    auto sync = [&]() { hipLaunchKernelGGL(k_box_restrict, dim3(nblk(mm)), dim3(kBlock), 0, s, bx, (const double *)d_uf, d_uc); };
+    auto ghosts = [&]() {
+        hipLaunchKernelGGL(k_box_ghost_forcing, dim3(nblk(mf)), dim3(kBlock), 0, s, bx, cx->geo[0].inv12h2,
+                           (const double *)d_uc, ff);
+    };
+    // H_f with the current ghosts and H_c without base forcing, at the synchronised state
+    auto residuals = [&]() {
+        sync();
+        ghosts();
+        residual_field(cx, d_uf, w.Hf);
+        fill<double>(s, fc, mc, 0.0);
+        residual_field(cb, d_uc, w.Hc);
+    };
+    mg_status st = MG_ERR_NOT_CONVERGED;
+    double nr[4] = {0, 0, 0, 0}, first = -1.0;
+    int it = 0, hist = 0;
+    for (;; it++) {
+        residuals();
+        hipLaunchKernelGGL(k_box_norm, dim3(nbn), dim3(kBlock), 0, s, bx, hf * hf * hf, hc * hc * hc,
+                           (const double *)w.Hf, (const double *)w.Hc, w.part);
+        hipLaunchKernelGGL(k_reduce_final<2>, dim3(1), dim3(kBlock), 0, s, (const double *)w.part, (int64_t)nbn, 0x2u,
+                           0.0, w.res, 0LL);
+        if (hipMemcpyAsync(cb->hpin, w.res, 2 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return MG_ERR_HIP;
+        nr[0] = std::sqrt(cb->hpin[0] / vol);
+        nr[2] = cb->hpin[1];
+        if (rep && rep->history && hist < rep->history_cap) {
+            std::memcpy(rep->history + 4 * hist, nr, sizeof(nr));
+            hist++;
+        }
+        if (!std::isfinite(nr[0]) || !std::isfinite(nr[2])) {
+            st = MG_ERR_DIVERGED;
+            break;
+        }
+        if (first < 0.0) first = nr[0];
+        if (nr[0] <= tol) {
+            st = MG_OK;
+            break;
+        }
+        if (nr[0] > 1e6 * std::fmax(first, tol)) {
+            st = MG_ERR_DIVERGED;
+            break;
+        }
+        if (it >= max_outer) {
+            st = MG_ERR_NOT_CONVERGED;
+            break;
+        }
+        // box steps with the interface ghosts of the current base values
+        for (int q = 0; q < nu_box; q++) {
+            sync();
+            ghosts();
+            psi_step(cx, d_uf);
+        }
+        // base steps on the FAS problem H_c(u_c) + tau = 0
+        residuals();
+        hipLaunchKernelGGL(k_box_tau, dim3(nblk(mc)), dim3(kBlock), 0, s, bx, (const double *)w.Hf,
+                           (const double *)w.Hc, fc);
+        if (hipMemcpyAsync(w.uc_old, d_uc, mc * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return MG_ERR_HIP;
+        for (int q = 0; q < nu_base; q++) psi_step(cb, d_uc);
+        hipLaunchKernelGGL(k_box_correct, dim3(nblk(mm)), dim3(kBlock), 0, s, bx, (const double *)d_uc,
+                           (const double *)w.uc_old, d_uf);
+        if (hip_status() != MG_OK) return MG_ERR_HIP;
+    }
+    // the base values under the box end as their children's average
+    sync();
+    if (hip_status() != MG_OK) return MG_ERR_HIP;
+    auto t1 = std::chrono::steady_clock::now();
+    if (rep) {
+        rep->outer_iters = it;
+        rep->vcycles_psi = cb->vc_psi + cx->vc_psi;
+        rep->vcycles_W = 0;
+        rep->status = st;
+        rep->h_rms = nr[0];
+        rep->m_rms = 0.0;
+        rep->h_max = nr[2];
+        rep->m_max = 0.0;
+        rep->seconds = std::chrono::duration<double>(t1 - t0).count();
+        rep->history_len = hist;
+    }
+    return st;
+}
+
 mg_status mg_interp_cubic(const mg_params *pc, const double *d_coarse, double *d_fine, void *stream)
 {
     if (!pc || pc->n < 2 || pc->n > 2048 || !(pc->length > 0.0) || !d_coarse || !d_fine)
         return MG_ERR_INVALID;
-    if (pc->bc < MG_BC_PERIODIC || pc->bc > MG_BC_EXTRAP) return MG_ERR_INVALID;
+    if (pc->bc < MG_BC_PERIODIC || pc->bc > MG_BC_ZERO) return MG_ERR_INVALID;
     const Geo gc = make_geo(pc->n, pc->bc, pc->length, pc->origin, pc->puncture_pos);
     const int64_t mf = 8 * (int64_t)pc->n * pc->n * pc->n;
     if (pc->bc == MG_BC_PERIODIC)

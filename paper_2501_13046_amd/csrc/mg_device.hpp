@@ -22,6 +22,7 @@ constexpr int kBcPeriodic = 0;
 constexpr int kBcRobin = 1;
 constexpr int kBcReflect = 2; // mirror image across each boundary face (even parity)
 constexpr int kBcExtrap = 3;  // zeroth-order extrapolation along the face normal
+constexpr int kBcZero = 4;    // homogeneous ghosts (a refined box: its interface ghosts enter as a forcing)
 
 struct Geo {
     int n;
@@ -115,6 +116,11 @@ __device__ __forceinline__ double ghost_source(const Geo &g, int i, int j, int k
             bj = mirror(j, n);
             bk = mirror(k, n);
             return 1.0;
+        } else if constexpr (BC == kBcZero) {
+            bi = clampc(i, n); // any grid cell: the ghost depends on none
+            bj = clampc(j, n);
+            bk = clampc(k, n);
+            return 0.0;
         } else {
             bi = clampc(i, n);
             bj = clampc(j, n);
@@ -142,6 +148,8 @@ struct Acc {
                 int bi = clampc(i, n), bj = clampc(j, n), bk = clampc(k, n);
                 double v = (double)a[lidx(n, bi, bj, bk)] * cell_radius(g, bi, bj, bk);
                 return (T)(v / cell_radius(g, i, j, k));
+            } else if constexpr (BC == kBcZero) {
+                return T(0);
             } else if constexpr (BC == kBcReflect) {
                 return a[lidx(n, mirror(i, n), mirror(j, n), mirror(k, n))];
             } else {

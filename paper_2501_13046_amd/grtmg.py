@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_PKG, "libgrtmg.so")
 
 MG_OK, MG_ERR_INVALID, MG_ERR_WORKSPACE, MG_ERR_HIP = 0, 1, 2, 3
 MG_ERR_NOT_CONVERGED, MG_ERR_DIVERGED, MG_ERR_SINGULAR = 4, 5, 6
-BC_PERIODIC, BC_ROBIN, BC_REFLECT, BC_EXTRAP = 0, 1, 2, 3
+BC_PERIODIC, BC_ROBIN, BC_REFLECT, BC_EXTRAP, BC_ZERO = 0, 1, 2, 3, 4
 PREC_FP64, PREC_FP32_IR = 0, 1
 EQ_PSI, EQ_W, EQ_BOTH = 1, 2, 3
 FLAG_CONFORMAL_MATTER = 1
@@ -94,6 +94,9 @@ def lib() -> C.CDLL:
         L.mg_set_background.argtypes = [vp, vp, vp]
         L.mg_bowen_york_sources.argtypes = [pp, i32, dp, vp, vp, vp]
         L.mg_cttk_trace.argtypes = [vp, vp, vp, vp]
+        L.mg_refine_workspace_size.argtypes = [pp, pp, i32, C.POINTER(C.c_size_t)]
+        L.mg_refine_solve.argtypes = [vp, vp, i32, vp, vp, vp, C.c_size_t, C.c_double, i32, i32, i32,
+                                      C.POINTER(MgReport)]
         L.mg_cttk_hybrid_sources.argtypes = [pp, vp, vp, vp, vp, vp, C.c_size_t, dp, vp]
         L.mg_kernel_op.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp]
         L.mg_batch_workspace_size.argtypes = [pp, i32, C.POINTER(C.c_size_t)]
@@ -116,7 +119,7 @@ def lib() -> C.CDLL:
                   "mg_shell_field_sources", "mg_interp_cubic", "mg_kernel_op", "mg_probe",
                   "mg_probe_result", "mg_batch_workspace_size", "mg_setup_batch", "mg_solve_batch",
                   "mg_fmg_start", "mg_batch_launch_mode", "mg_batch_groups", "mg_autotune", "mg_set_tile",
-                  "mg_cttk_trace", "mg_cttk_hybrid_sources"):
+                  "mg_cttk_trace", "mg_cttk_hybrid_sources", "mg_refine_workspace_size", "mg_refine_solve"):
             getattr(L, f).restype = st
         _lib = L
     return _lib
@@ -371,6 +374,39 @@ def scalar_field_sources(p: MgParams, phi_modes: np.ndarray, pi_modes: np.ndarra
         SOURCES_SCRATCH_BYTES if want_K else 0, None,
         C.byref(K) if want_K else None, _stream(rho5.device)), "mg_scalar_field_sources")
     return rho5, rho1, S, (K.value if want_K else None)
+
+
+def box_params(base: MgParams, b0: int, m: int, levels: int, precision: Optional[int] = None) -> MgParams:
+    """Parameters of a box refined by 2 over the m^3 base cells from base cell (b0, b0, b0):
+    2m cells, zero ghost rule, the base grid's physics."""
+    h = base.length / base.n
+    p = params(2 * m, levels, BC_ZERO, base.precision if precision is None else precision, m * h,
+               tuple(base.origin[a] + b0 * h for a in range(3)), base.K, base.nu_pre, base.nu_post, False,
+               base.puncture_mass, tuple(base.puncture_pos[a] for a in range(3)))
+    p.flags = base.flags & FLAG_CONFORMAL_MATTER
+    return p
+
+
+def refine_solve(base: "Solver", box: "Solver", b0: int, uc: torch.Tensor, uf: torch.Tensor, tol: float = 1e-10,
+                 max_outer: int = 60, nu_box: int = 1, nu_base: int = 1, raise_on_failure: bool = True) -> dict:
+    """Two-level composite solve (mg_refine_solve): in place on uc (base) and uf (box).
+    Both solvers must have been built with a forcing array f, which this overwrites."""
+    nbytes = C.c_size_t(0)
+    _check(lib().mg_refine_workspace_size(C.byref(base.p), C.byref(box.p), b0, C.byref(nbytes)),
+           "mg_refine_workspace_size")
+    work = torch.empty(nbytes.value, dtype=torch.uint8, device=uc.device)
+    hist = np.zeros((max_outer + 2, 4))
+    rep = MgReport()
+    rep.history = hist.ctypes.data_as(C.POINTER(C.c_double))
+    rep.history_cap = max_outer + 2
+    st = lib().mg_refine_solve(base.ctx, box.ctx, b0, _dptr(uc, numel=base.cells), _dptr(uf, numel=box.cells),
+                               C.c_void_p(work.data_ptr()), nbytes.value, tol, max_outer, nu_box, nu_base,
+                               C.byref(rep))
+    out = dict(status=st, outer_iters=rep.outer_iters, vcycles_psi=rep.vcycles_psi, h_rms=rep.h_rms,
+               h_max=rep.h_max, seconds=rep.seconds, history=hist[: rep.history_len].copy())
+    if raise_on_failure:
+        _check(st, "mg_refine_solve")
+    return out
 
 
 def cttk_hybrid_sources(p: MgParams, rho5: torch.Tensor, rho1: torch.Tensor, S: torch.Tensor):
