@@ -101,6 +101,60 @@ def bench_puncture_256(g, synth, dev, args, log):
     log(f"[bench] puncture_shell_256 mixed: {out['seconds'] * 1e3:.2f} ms/solve (median of {len(runs)}), "
         f"outer={rep['outer_iters']} rms H={rep['h_rms']:.2e}")
     s.close()
+    return out, u
+
+
+def bench_refined_puncture(g, synth, dev, args, log, u256):
+    """The same black hole on a 128^3 base grid (h = 0.5) with the central 64^3 base cells
+    refined by 2 (a 128^3 box, h = 0.25 around the puncture), as one composite solve; its
+    box is compared with the uniform 256^3 solution (the same spacing everywhere) over the
+    box, and so is the base grid solved alone (no refinement)."""
+    import torch
+    nc, m, b0 = 128, 64, 32
+    w = synth.puncture_shell(nc, precision=g.PREC_FP32_IR, levels=6)
+    pb = g.params(nc, 6, w.bc, g.PREC_FP32_IR, w.length, w.origin, 0.0, w.nu_pre, w.nu_post, False, w.puncture_mass,
+                  w.puncture_pos, w.conformal_matter)
+    px = g.box_params(pb, b0, m, 6)
+    sh = w.shell
+    r5c, r1c, _ = g.shell_field_sources(pb, sh["amplitude"], sh["r0"], sh["width2"], w.scalar_mass, dev)
+    r5f, r1f, _ = g.shell_field_sources(px, sh["amplitude"], sh["r0"], sh["width2"], w.scalar_mass, dev)
+    fc = torch.zeros((nc,) * 3, dtype=torch.float64, device=dev)
+    ff = torch.zeros((2 * m,) * 3, dtype=torch.float64, device=dev)
+    sb, sx = g.Solver(pb, r5c, r1c, None, fc), g.Solver(px, r5f, r1f, None, ff)
+    uc = torch.zeros((nc,) * 3, dtype=torch.float64, device=dev)
+    uf = torch.zeros((2 * m,) * 3, dtype=torch.float64, device=dev)
+    sb.autotune(uc, None, reps=10)
+    sx.autotune(uf, None, reps=10)
+    runs, rep = [], None
+    for k in range(1 + max(1, args.steps // 2)):
+        uc.zero_()
+        uf.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep = g.refine_solve(sb, sx, b0, uc, uf, tol=args.tol, max_outer=60)
+        torch.cuda.synchronize()
+        if k:
+            runs.append(time.perf_counter() - t0)
+    runs.sort()
+    out = dict(seconds=runs[len(runs) // 2], runs=len(runs), base_n=nc, box_cells=2 * m, box_origin_cell=b0,
+               outer_iters=rep["outer_iters"], vcycles_psi=rep["vcycles_psi"], composite_rms=rep["h_rms"],
+               composite_max=rep["h_max"])
+    if u256 is not None:
+        box = u256[2 * b0:2 * (b0 + m), 2 * b0:2 * (b0 + m), 2 * b0:2 * (b0 + m)]
+        out["box_vs_uniform_256_max"] = float((uf - box).abs().max())
+        # the base grid alone, without refinement
+        fc.zero_()
+        u1 = torch.zeros((nc,) * 3, dtype=torch.float64, device=dev)
+        sb.solve(u1, None, tol=args.tol, max_outer=60)
+        coarse = box.reshape(m, 2, m, 2, m, 2).mean(dim=(1, 3, 5))
+        out["base_alone_vs_uniform_256_max"] = float((u1[b0:b0 + m, b0:b0 + m, b0:b0 + m] - coarse).abs().max())
+        out["refined_vs_uniform_256_max_base"] = float((uc[b0:b0 + m, b0:b0 + m, b0:b0 + m] - coarse).abs().max())
+    log(f"[bench] refined puncture (128^3 base + 128^3 box): {out['seconds'] * 1e3:.2f} ms/solve (median of "
+        f"{len(runs)}), {rep['outer_iters']} composite iterations, rms {rep['h_rms']:.2e}; against uniform 256^3 over "
+        f"the box: {out.get('box_vs_uniform_256_max', float('nan')):.2e} (base alone "
+        f"{out.get('base_alone_vs_uniform_256_max', float('nan')):.2e})")
+    sb.close()
+    sx.close()
     return out
 
 
@@ -310,7 +364,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-runs", type=int, default=1, help="oracle solves of the 128^3 workload to time")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the 256^3 puncture, 96-instance scan and CTTK / CTTK-Hybrid legs")
+                    help="skip the 256^3 puncture, refined puncture, 96-instance scan and CTTK / CTTK-Hybrid legs")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison solves")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain device copy of 256 MiB (the reference dispatch that scales "
@@ -548,7 +602,9 @@ def main():
     # shell (Robin boundaries, mixed precision) and the 96-instance parameter scan
     extra = {}
     if not args.no_extra:
-        extra["puncture_shell_256"] = bench_puncture_256(g, synth, dev, args, log)
+        extra["puncture_shell_256"], u256 = bench_puncture_256(g, synth, dev, args, log)
+        extra["refined_puncture_128_box_128"] = bench_refined_puncture(g, synth, dev, args, log, u256)
+        del u256
         extra["bowen_york_binary_256"] = bench_bowen_york_256(g, synth, dev, args, log)
         extra["scan_96"] = bench_scan_96(g, synth, dev, args, log)
         extra["methods"] = bench_methods(g, w, K, rho5, rho1, S, args, log)

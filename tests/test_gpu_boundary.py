@@ -1,5 +1,5 @@
 """The reflective and extrapolating boundary rules (Key features, "Boundary
-conditions") on the HIP path: single outer steps against the oracle element by
+conditions") and the zero ghost rule of a refined box on the HIP path: single outer steps against the oracle element by
 element (FP64), converged solves in both precisions against the oracle's
 solution, and the workgroup-resident V-cycle tail under each rule."""
 import copy
@@ -15,7 +15,7 @@ from paper_2501_13046_amd import grtmg as g
 from gpu_helpers import N, T, dev, gparams, oracle_problem, psi_rel_err, rel_err
 
 pytestmark = pytest.mark.gpu
-RULES = [g.BC_REFLECT, g.BC_EXTRAP]
+RULES = [g.BC_REFLECT, g.BC_EXTRAP, g.BC_ZERO]
 
 
 def workload(bc, n=32, seed=2, precision=g.PREC_FP64):

@@ -80,7 +80,7 @@ def _ctx(n, levels, bc=g.BC_PERIODIC, momentum=True):
     return g.Solver(p, z, z, S), po
 
 
-@pytest.mark.parametrize("bc", [g.BC_PERIODIC, g.BC_ROBIN, g.BC_REFLECT, g.BC_EXTRAP])
+@pytest.mark.parametrize("bc", [g.BC_PERIODIC, g.BC_ROBIN, g.BC_REFLECT, g.BC_EXTRAP, g.BC_ZERO])
 def test_smoother_and_transfer_ops(bc):
     n, levels = 16, 3
     s, po = _ctx(n, levels, bc)
@@ -167,7 +167,7 @@ def test_residual_fields_conformal_matter():
     assert rel_err(N(c), co) < 1e-13
 
 
-@pytest.mark.parametrize("bc", [g.BC_PERIODIC, g.BC_ROBIN, g.BC_REFLECT, g.BC_EXTRAP])
+@pytest.mark.parametrize("bc", [g.BC_PERIODIC, g.BC_ROBIN, g.BC_REFLECT, g.BC_EXTRAP, g.BC_ZERO])
 @pytest.mark.parametrize("n,levels", [(16, 2), (24, 3), (20, 2), (12, 2)])
 def test_coarse_psi_krylov_sizes(bc, n, levels):
     """Coarsest psi systems of 6^3 .. 10^3 cells (block conjugate gradients or
@@ -184,7 +184,7 @@ def test_coarse_psi_krylov_sizes(bc, n, levels):
     assert rel_err(N(out), ref) < 1e-11
 
 
-@pytest.mark.parametrize("bc", [g.BC_PERIODIC, g.BC_ROBIN, g.BC_REFLECT, g.BC_EXTRAP])
+@pytest.mark.parametrize("bc", [g.BC_PERIODIC, g.BC_ROBIN, g.BC_REFLECT, g.BC_EXTRAP, g.BC_ZERO])
 def test_coarse_psi_4_indefinite(bc):
     """A 4^3 coarsest system whose coefficient makes the matrix indefinite: the
     Krylov solve or, if it is not accepted, the elimination must still give the

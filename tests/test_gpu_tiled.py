@@ -15,7 +15,7 @@ n = 128
 
 
 @pytest.mark.parametrize("precision", [g.PREC_FP64, g.PREC_FP32_IR])
-@pytest.mark.parametrize("bc", [g.BC_PERIODIC, g.BC_ROBIN, g.BC_REFLECT, g.BC_EXTRAP])
+@pytest.mark.parametrize("bc", [g.BC_PERIODIC, g.BC_ROBIN, g.BC_REFLECT, g.BC_EXTRAP, g.BC_ZERO])
 def test_tiled_psi_pass(precision, bc):
     L, org = (1.0, (0.0,) * 3) if bc == g.BC_PERIODIC else (64.0, (-32.0,) * 3)
     p = g.params(n, 6, bc=bc, precision=precision, length=L, origin=org)
@@ -146,7 +146,7 @@ def test_tiled_residual_robin_puncture():
     assert rel_err(N(c), co) < 1e-13
 
 
-@pytest.mark.parametrize("bc", [g.BC_REFLECT, g.BC_EXTRAP])
+@pytest.mark.parametrize("bc", [g.BC_REFLECT, g.BC_EXTRAP, g.BC_ZERO])
 @pytest.mark.parametrize("depth", [2, 4])
 def test_tiled_residual_reflect_extrap(bc, depth):
     """Residual bricks under the reflective and extrapolating rules, frozen W."""
