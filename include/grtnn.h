@@ -146,6 +146,20 @@ mg_status nn_warm_start(nn_ctx *ctx, mg_ctx *solver, const double *d_rho5, const
                         const double *d_S, const nn_norm *norm, double *d_u, double *d_W,
                         int32_t *h_used, double h_norms[4]);
 
+/*
+ * The same with the fallback comparing like with like: the prediction is kept only
+ * if, after its check iteration, max(rms H, rms M) is below keep_ratio (0 < keep_ratio
+ * <= 1) times that of the zero state, where the caller passes for keep_ratio the
+ * contraction of one outer iteration from the zero start on this workload (measured
+ * once, e.g. with mg_solve_constraints at max_outer = 1).  A kept prediction then
+ * leaves a state at least as good as one zero-start iteration would.  keep_ratio = 1
+ * is nn_warm_start.  MG_ERR_INVALID for keep_ratio outside (0, 1]; otherwise as
+ * nn_warm_start.
+ */
+mg_status nn_warm_start_ratio(nn_ctx *ctx, mg_ctx *solver, const double *d_rho5, const double *d_rho1,
+                              const double *d_S, const nn_norm *norm, double *d_u, double *d_W,
+                              double keep_ratio, int32_t *h_used, double h_norms[4]);
+
 void nn_destroy(nn_ctx *ctx);
 
 /*

@@ -742,8 +742,15 @@ mg_status nn_moments(nn_ctx *c, const double *d_x, const double *d_y, int64_t co
     return MG_OK;
 }
 
-mg_status nn_warm_start(nn_ctx *c, mg_ctx *solver, const double *d_rho5, const double *d_rho1, const double *d_S,
-                        const nn_norm *norm, double *d_u, double *d_W, int32_t *h_used, double h_norms[4])
+} // extern "C"
+
+namespace {
+
+// keep_ratio: the prediction is kept when, after its check iteration, the worse of
+// rms H and rms M is below keep_ratio times that of the zero state.
+mg_status warm_start(nn_ctx *c, mg_ctx *solver, const double *d_rho5, const double *d_rho1, const double *d_S,
+                     const nn_norm *norm, double *d_u, double *d_W, double keep_ratio, int32_t *h_used,
+                     double h_norms[4])
 {
     if (!c || !solver || !d_rho5 || !d_rho1 || !d_S || !d_u || !d_W || !h_used || !norm_ok(norm) ||
         c->cfg.c_in != 4 || c->cfg.c_out != 4)
@@ -785,7 +792,7 @@ mg_status nn_warm_start(nn_ctx *c, mg_ctx *solver, const double *d_rho5, const d
     if (st == MG_ERR_DIVERGED && std::isfinite(pred[0]) && std::isfinite(pred[1]))
         pred[0] = pred[1] = std::numeric_limits<double>::infinity(); // never kept
     const double wz = std::max(zero[0], zero[1]), wp = std::max(pred[0], pred[1]);
-    const bool keep = std::isfinite(pred[0]) && std::isfinite(pred[1]) && wp < wz;
+    const bool keep = std::isfinite(pred[0]) && std::isfinite(pred[1]) && wp < keep_ratio * wz;
     if (!keep) {
         grtmg::cancel_continue(solver);
         if (hipMemsetAsync(d_u, 0, V * sizeof(double), c->s) != hipSuccess ||
@@ -802,6 +809,24 @@ mg_status nn_warm_start(nn_ctx *c, mg_ctx *solver, const double *d_rho5, const d
         h_norms[3] = zero[1];
     }
     return MG_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+mg_status nn_warm_start(nn_ctx *c, mg_ctx *solver, const double *d_rho5, const double *d_rho1, const double *d_S,
+                        const nn_norm *norm, double *d_u, double *d_W, int32_t *h_used, double h_norms[4])
+{
+    return warm_start(c, solver, d_rho5, d_rho1, d_S, norm, d_u, d_W, 1.0, h_used, h_norms);
+}
+
+mg_status nn_warm_start_ratio(nn_ctx *c, mg_ctx *solver, const double *d_rho5, const double *d_rho1,
+                              const double *d_S, const nn_norm *norm, double *d_u, double *d_W, double keep_ratio,
+                              int32_t *h_used, double h_norms[4])
+{
+    if (!(keep_ratio > 0.0 && keep_ratio <= 1.0)) return MG_ERR_INVALID;
+    return warm_start(c, solver, d_rho5, d_rho1, d_S, norm, d_u, d_W, keep_ratio, h_used, h_norms);
 }
 
 // ---- single operations ------------------------------------------------------------------

@@ -376,6 +376,20 @@ def scalar_field_sources(p: MgParams, phi_modes: np.ndarray, pi_modes: np.ndarra
     return rho5, rho1, S, (K.value if want_K else None)
 
 
+def zero_start_contraction(solver: "Solver", u: torch.Tensor, W: Optional[torch.Tensor] = None) -> float:
+    """Contraction of max(rms H, rms M) over one outer iteration from the zero start
+    (the keep ratio of the warm start's like-with-like fallback); leaves u, W zero."""
+    u.zero_()
+    if W is not None:
+        W.zero_()
+    r = solver.solve(u, W, tol=1e-300, max_outer=1, raise_on_failure=False)
+    h = r["history"]
+    u.zero_()
+    if W is not None:
+        W.zero_()
+    return float(max(h[1][0], h[1][1]) / max(h[0][0], h[0][1]))
+
+
 def box_params(base: MgParams, b0: int, m: int, levels: int, precision: Optional[int] = None) -> MgParams:
     """Parameters of a box refined by 2 over the m^3 base cells from base cell (b0, b0, b0):
     2m cells, zero ghost rule, the base grid's physics."""

@@ -51,6 +51,7 @@ def lib() -> C.CDLL:
         L.nn_unpack_output.argtypes = [vp, vp, np_, vp, vp]
         L.nn_moments.argtypes = [vp, vp, vp, i64, dp]
         L.nn_warm_start.argtypes = [vp, vp, vp, vp, vp, np_, vp, vp, C.POINTER(i32), dp]
+        L.nn_warm_start_ratio.argtypes = [vp, vp, vp, vp, vp, np_, vp, vp, C.c_double, C.POINTER(i32), dp]
         L.nn_destroy.argtypes = [vp]
         L.nn_destroy.restype = None
         L.nn_op_scratch_bytes.argtypes = [i32, i32, i32]
@@ -60,7 +61,7 @@ def lib() -> C.CDLL:
         L.nn_conv3_backward_weight.argtypes = [i32, i32, i32, vp, i32, vp, vp, vp, vp, C.c_size_t, vp]
         for f in ("nn_param_count", "nn_workspace_size", "nn_setup", "nn_load_params", "nn_forward",
                   "nn_mse", "nn_backward", "nn_adam_step", "nn_pack_input", "nn_pack_target",
-                  "nn_unpack_output", "nn_moments", "nn_warm_start", "nn_conv3_forward",
+                  "nn_unpack_output", "nn_moments", "nn_warm_start", "nn_warm_start_ratio", "nn_conv3_forward",
                   "nn_conv3_backward_data", "nn_conv3_backward_weight"):
             getattr(L, f).restype = C.c_int
         _bound = True
@@ -197,15 +198,20 @@ class Net:
                                 x.numel(), out), "nn_moments")
         return out[0], out[1]
 
-    def warm_start(self, solver: "_mg.Solver", rho5, rho1, S, nm: NnNorm, u, W):
+    def warm_start(self, solver: "_mg.Solver", rho5, rho1, S, nm: NnNorm, u, W, keep_ratio: float = None):
+        """keep_ratio: the zero start's one-iteration contraction (nn_warm_start_ratio);
+        None keeps a prediction that beats the zero state itself (nn_warm_start)."""
         if solver.cells != self.cells:
             raise MGError(_mg.MG_ERR_INVALID, "nn_warm_start: solver and network grids differ")
         used = C.c_int32(0)
         norms = (C.c_double * 4)()
-        _check(lib().nn_warm_start(self.ctx, solver.ctx, _dptr(rho5, numel=self.cells),
-                                   _dptr(rho1, numel=self.cells), _dptr(S, numel=3 * self.cells),
-                                   C.byref(nm), _dptr(u, numel=self.cells), _dptr(W, numel=3 * self.cells),
-                                   C.byref(used), norms), "nn_warm_start")
+        args = (self.ctx, solver.ctx, _dptr(rho5, numel=self.cells), _dptr(rho1, numel=self.cells),
+                _dptr(S, numel=3 * self.cells), C.byref(nm), _dptr(u, numel=self.cells),
+                _dptr(W, numel=3 * self.cells))
+        if keep_ratio is None:
+            _check(lib().nn_warm_start(*args, C.byref(used), norms), "nn_warm_start")
+        else:
+            _check(lib().nn_warm_start_ratio(*args, keep_ratio, C.byref(used), norms), "nn_warm_start_ratio")
         return bool(used.value), list(norms)
 
 

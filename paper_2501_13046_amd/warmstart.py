@@ -173,13 +173,14 @@ def evaluate(net: gn.Net, nm: gn.NnNorm, seeds: List[int], n: int, device, log=p
 
 
 def fmg_learned_start(net: gn.Net, nm: gn.NnNorm, coarse: g.Solver, fine: g.Solver, r5c, r1c, Sc, uc, Wc, uf, Wf,
-                      tol_c: float, max_outer: int = 100):
+                      tol_c: float, max_outer: int = 100, keep_ratio: float = None):
     """Full-multigrid start with a learned coarse start: the network (trained on the
     coarse problem) predicts (u, W) on the coarse grid, one coarse outer iteration
-    checks it against the zero start (the library's fallback rule), the coarse solve
+    checks it against the zero start (the library's fallback rule; keep_ratio: the zero
+    start's one-iteration contraction, for the like-with-like form), the coarse solve
     continues to tol_c, and the cubic interpolation fills the fine arrays.  Returns
     (prediction kept, coarse report of the continued solve)."""
-    used, _ = net.warm_start(coarse, r5c, r1c, Sc, nm, uc, Wc)
+    used, _ = net.warm_start(coarse, r5c, r1c, Sc, nm, uc, Wc, keep_ratio)
     rc = g.fmg_start(coarse, fine, uc, Wc, uf, Wf, tol=tol_c, max_outer=max_outer)
     return used, rc
 

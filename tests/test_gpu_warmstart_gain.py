@@ -85,6 +85,7 @@ def test_learned_coarse_start_saves_time_on_held_out_seeds():
         zw = lambda n: torch.zeros((3, n, n, n), dtype=torch.float64, device=dev())
         uc, Wc, uf, Wf = z(64), zw(64), z(128), zw(128)
         tol_c = g.fmg_coarse_tol(coarse, fine, uc, Wc, uf, Wf)
+        ratio = g.zero_start_contraction(coarse, uc, Wc)  # the like-with-like fallback's bar
 
         def plain():
             uc.zero_(); Wc.zero_()
@@ -92,7 +93,8 @@ def test_learned_coarse_start_saves_time_on_held_out_seeds():
             return rc, fine.solve(uf, Wf, tol=1e-10, max_outer=100)
 
         def learned():
-            used, rc = ws.fmg_learned_start(net, nm, coarse, fine, r5c, r1c, Sc, uc, Wc, uf, Wf, tol_c)
+            used, rc = ws.fmg_learned_start(net, nm, coarse, fine, r5c, r1c, Sc, uc, Wc, uf, Wf, tol_c,
+                                            keep_ratio=ratio)
             return used, rc, fine.solve(uf, Wf, tol=1e-10, max_outer=100)
 
         plain(), learned()  # warm-up: graphs captured, kernels loaded
@@ -118,3 +120,35 @@ def test_learned_coarse_start_saves_time_on_held_out_seeds():
     print(f"time saved per solve (median over seeds): {np.median(saved):.3f} ms")
     assert all(c1 < c0 for c0, c1, _, _ in its)
     assert np.median(saved) > 0.0
+
+
+def test_fallback_compares_with_one_zero_start_iteration():
+    """The like-with-like fallback (nn_warm_start_ratio): the prediction is kept only if,
+    after its check iteration, it beats what one outer iteration from the zero start
+    achieves (keep_ratio = that iteration's measured contraction); an unreachable bar
+    falls back to the zero state, and a bar outside (0, 1] is refused."""
+    from paper_2501_13046_amd import grtmg as g
+    import synth
+    cfg, nm, params, meta = ws.load(WEIGHTS_64, dev())
+    net = gn.Net(cfg, training=False, device=dev())
+    net.load(params)
+    seed = 10005
+    pf, _, _, _ = ws.problem(seed, 128, dev())
+    wc = synth.coupled(64, seed=seed, precision=g.PREC_FP32_IR)
+    pc = g.params(64, wc.levels, wc.bc, g.PREC_FP32_IR, wc.length, wc.origin, pf.K, wc.nu_pre, wc.nu_post, True)
+    r5c, r1c, Sc, _ = g.scalar_field_sources(pc, wc.phi_modes, wc.pi_modes, wc.scalar_mass, dev())
+    coarse = g.Solver(pc, r5c, r1c, Sc)
+    uc = torch.zeros((64,) * 3, dtype=torch.float64, device=dev())
+    Wc = torch.zeros((3, 64, 64, 64), dtype=torch.float64, device=dev())
+    ratio = g.zero_start_contraction(coarse, uc, Wc)
+    used, norms = net.warm_start(coarse, r5c, r1c, Sc, nm, uc, Wc, keep_ratio=ratio)
+    pred, zero = max(norms[0], norms[1]), max(norms[2], norms[3])
+    print(f"zero-start contraction {ratio:.3f}; prediction after its check iteration {pred / zero:.4f} of the "
+          f"zero state")
+    assert 0.0 < ratio < 1.0
+    assert used and pred < ratio * zero
+    used, _ = net.warm_start(coarse, r5c, r1c, Sc, nm, uc, Wc, keep_ratio=1e-9)
+    assert not used and not uc.any() and not Wc.any()
+    with pytest.raises(gn.MGError):
+        net.warm_start(coarse, r5c, r1c, Sc, nm, uc, Wc, keep_ratio=1.5)
+    coarse.close()
