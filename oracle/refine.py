@@ -1,41 +1,42 @@
-"""Two-level static mesh refinement of the Hamiltonian constraint (test
+"""Static mesh refinement of the Hamiltonian constraint by nested boxes (test
 infrastructure only, like the rest of ``oracle/``).
 
 Key features, "Adaptive Mesh Refinement" (a block-structured hierarchy of
 refined boxes, tagged where the sources are) and "Fast" (multigrid over the
-hierarchy of discretisations).  This is the static form of that hierarchy: a
-base grid of n_c^3 cells (spacing h) and one box of m^3 base cells, offset b0
-cells from the base grid's corner on every axis, refined by 2 (n_f = 2m cells of
-spacing h/2).  The paper gives no composite-grid discretisation; the reading:
+hierarchy of discretisations).  This is the static form of that hierarchy:
+level 0 is a base grid; level k >= 1 is a box of m_k^3 cells of level k-1,
+offset b_k cells from that level's corner on every axis, refined by 2 (n_k = 2 m_k
+cells of half the spacing).  Every box lies inside its parent with a margin of at
+least 3 parent cells.  The paper gives no composite-grid discretisation; the
+reading:
 
-* unknowns: u on the fine box, and u on the base cells the box does not cover;
-  the base value of a covered cell is the average of its 8 children;
-* fine equations: H_h of the box with two ghost layers taken from the base grid
-  by the cubic interpolation of the FMG start (the ghosts are the children of the
-  base cells in the layer around the box), so the 4th-order stencil of every
-  fine cell is complete;
-* base equations: H_h of the uncovered cells (their stencils reach into covered
-  cells, which hold the averages);
-* composite norm: volume-weighted RMS of H over fine cells and uncovered base
-  cells, sqrt((sum_f H^2 h_f^3 + sum_c H^2 h^3) / L^3).
+* unknowns: u on every level's cells that no finer box covers; a covered cell's
+  value is the average of its 8 children;
+* box equations: H_h of the box with two ghost layers taken from its parent by
+  the cubic interpolation of the FMG start (the ghosts are the children of the
+  parent cells in the layer around the box), so every 4th-order stencil is
+  complete;
+* equations of the uncovered cells of every level: H_h of that level (stencils
+  reaching into covered cells see the averages);
+* composite norm: volume-weighted RMS of H over the uncovered cells of all
+  levels, sqrt(sum_k sum_uncovered H^2 h_k^3 / L^3).
 
-The fine box is solved as a grid of its own with homogeneous ghosts (the zero
-boundary rule) plus a forcing that carries the interpolated ghosts:
-f = sum over the stencil taps outside the box of w g / (12 (h/2)^2), w the tap
+A box is solved as a grid of its own with homogeneous ghosts (the zero boundary
+rule) plus a forcing that carries the interpolated ghosts:
+f = sum over the stencil taps outside the box of w g / (12 h_k^2), w the tap
 weight (16 or -1) and g the interpolated ghost value.  Its V-cycles then see the
 true Jacobian of the box problem (the ghosts do not depend on the box's own
 values); an extrapolating rule in their place makes the box operator Neumann-like
 and the iteration diverges on its near-constant mode.
 
-Iteration (Brandt's multi-level adaptive technique, a two-level FAS cycle):
-  1. base cells under the box take the average of their children;
-  2. nu_f Newton-multigrid steps on the box (the ghost forcing formed before each);
-  3. base forcing on covered cells tau = R H_f - H_c(R u_f) (zero elsewhere), so that
-     the base problem H_c(u_c) + tau = 0 has the restricted fine residual there;
-  4. nu_c Newton-multigrid steps on the base grid with that forcing;
-  5. the fine box adds the cubic interpolation of the base grid's change.
-The box needs a margin of at least 3 base cells on every side (the cubic stencils
-of the ghost layer stay inside the base grid).
+Iteration (Brandt's multi-level adaptive technique, FAS over the levels): every
+covered cell takes the average of its children; then from the finest level down
+to level 1: nu_f Newton-multigrid steps of the level (its ghost forcing formed
+before each, plus the fixed FAS forcing tau from the level above it), then the
+FAS forcing of its parent on the covered cells, tau = R H_k - H_{k-1}(R u_k), where
+H_{k-1} carries the parent's own ghost forcing; nu_c steps of the base grid with
+its tau; then from level 1 up, every box adds the cubic interpolation of its
+parent's change.  With two levels this is the two-level FAS cycle.
 """
 from __future__ import annotations
 
@@ -67,8 +68,8 @@ def _cubic_axis(a, axis):
 
 
 def cubic_children(uc, lo, count):
-    """Children (at spacing h/2) of the base cells lo .. lo + count - 1 on every axis,
-    by the 4-point cubic: an array of (2 count)^3."""
+    """Children (at half the spacing) of the parent cells lo .. lo + count - 1 on every
+    axis, by the 4-point cubic: an array of (2 count)^3."""
     a = uc[lo - 2:lo + count + 2, lo - 2:lo + count + 2, lo - 2:lo + count + 2]
     for axis in range(3):
         a = _cubic_axis(a, axis)
@@ -86,7 +87,7 @@ def _d2(ap, axis, n, h):
 
 
 def padded_fine(uc, uf, b0):
-    """The box with two ghost layers: interior uf, ghosts interpolated from uc."""
+    """The box with two ghost layers: interior uf, ghosts interpolated from its parent uc."""
     m = uf.shape[0] // 2
     P = cubic_children(uc, b0 - 1, m + 2)
     P[2:-2, 2:-2, 2:-2] = uf
@@ -102,44 +103,71 @@ def ghost_forcing(uc, uf, b0, h_f):
     return sum(_d2(G, a, n, h_f) for a in range(3))
 
 
-class Problem:
-    """Base and box parameters (oracle params) and sources of a two-level composite grid."""
+class Nested:
+    """Levels 0 .. L-1: oracle params (level 0 any rule, boxes the zero rule), the
+    offsets b[k] of box k in level k-1 (b[0] unused), and the sources of every level."""
 
-    def __init__(self, pc, pf, b0, rho5c, rho1c, rho5f, rho1f):
-        m = pf.n // 2
-        assert pf.bc == oracle.BC_ZERO and pc.n >= b0 + m + 3 and b0 >= 3
-        assert abs(pf.length - pc.length * m / pc.n) <= 1e-12 * pc.length
-        self.pc, self.pf, self.b0, self.m = pc, pf, b0, m
-        self.rc5, self.rc1, self.rf5, self.rf1 = rho5c, rho1c, rho5f, rho1f
-        self.cov = (slice(b0, b0 + m),) * 3
-        self.h_c = pc.length / pc.n
-        self.h_f = pf.length / pf.n
+    def __init__(self, params, offsets, rho5, rho1):
+        self.p, self.b, self.r5, self.r1 = list(params), list(offsets), list(rho5), list(rho1)
+        self.L = len(self.p)
+        self.h = [p.length / p.n for p in self.p]
+        for k in range(1, self.L):
+            pc, pf, b0 = self.p[k - 1], self.p[k], self.b[k]
+            m = pf.n // 2
+            assert pf.bc == oracle.BC_ZERO and pf.n % 2 == 0 and b0 >= 3 and pc.n >= b0 + m + 3
+            assert abs(pf.length - pc.length * m / pc.n) <= 1e-12 * self.p[0].length
+        self.vol = self.p[0].length ** 3
 
-    def residuals(self, uc, uf, fc=None):
-        """(H_f with the interpolated ghosts, H_c) after the base cells under the box
-        took their children's average (uc is updated in place)."""
-        uc[self.cov] = oracle.restrict(uf)
-        ff = ghost_forcing(uc, uf, self.b0, self.h_f)
-        Hf = oracle.residuals(self.pf, uf, None, self.rf5, self.rf1, None, ff)[0]
-        Hc = oracle.residuals(self.pc, uc, None, self.rc5, self.rc1, None, fc)[0]
-        return Hf, Hc, ff
+    def covered(self, k):
+        """Cells of level k covered by box k + 1."""
+        b0, m = self.b[k + 1], self.p[k + 1].n // 2
+        return (slice(b0, b0 + m),) * 3
 
-    def norm(self, Hf, Hc):
-        mask = np.ones(Hc.shape, dtype=bool)
-        mask[self.cov] = False
-        s = np.sum(Hf * Hf) * self.h_f ** 3 + np.sum(Hc[mask] ** 2) * self.h_c ** 3
-        return float(np.sqrt(s / self.pc.length ** 3)), float(max(np.abs(Hf).max(), np.abs(Hc[mask]).max()))
+    def sync(self, u):
+        for k in range(self.L - 1, 0, -1):
+            u[k - 1][self.covered(k - 1)] = oracle.restrict(u[k])
+
+    def ghosts(self, u, k):
+        return ghost_forcing(u[k - 1], u[k], self.b[k], self.h[k]) if k > 0 else np.zeros_like(u[0])
+
+    def H(self, u, k, f):
+        return oracle.residuals(self.p[k], u[k], None, self.r5[k], self.r1[k], None, f)[0]
+
+    def residuals(self, u):
+        """H of every level (ghost forcing included, no FAS forcing) at the
+        synchronised state (u is updated in place)."""
+        self.sync(u)
+        return [self.H(u, k, self.ghosts(u, k) if k else None) for k in range(self.L)]
+
+    def norm(self, Hs):
+        s, mx = 0.0, 0.0
+        for k, Hk in enumerate(Hs):
+            mask = np.ones(Hk.shape, dtype=bool)
+            if k + 1 < self.L:
+                mask[self.covered(k)] = False
+            s += np.sum(Hk[mask] ** 2) * self.h[k] ** 3
+            mx = max(mx, float(np.abs(Hk[mask]).max()))
+        return float(np.sqrt(s / self.vol)), mx
 
 
-def solve(prob: Problem, uc, uf, tol=1e-10, max_outer=60, nu_f=1, nu_c=1):
-    """Two-level FAS iteration in place on (uc, uf); returns (iterations, history of
-    (rms, max) composite norms, status 0 / 4 / 5 as the single-grid oracle)."""
+def solve_nested(prob: Nested, u, tol=1e-10, max_outer=60, nu_f=1, nu_c=1):
+    """FAS iteration over the nested levels, in place on the list u (one array per
+    level); returns (iterations, history of (rms, max) composite norms, status 0 / 4 / 5
+    as the single-grid oracle)."""
+    L = prob.L
     hist = []
     it = 0
     status = 4
+
+    def to_parent(k):  # the parent's cells under box k take their children's average
+        u[k - 1][prob.covered(k - 1)] = oracle.restrict(u[k])
+
+    def forcing(k, tau):
+        f = prob.ghosts(u, k)
+        return f + tau[k] if tau[k] is not None else f
+
     for it in range(max_outer + 1):
-        Hf, Hc, _ = prob.residuals(uc, uf)
-        nr = prob.norm(Hf, Hc)
+        nr = Nested.norm(prob, Nested.residuals(prob, u))  # the per-level forms (Problem names its own)
         hist.append(nr)
         if not np.isfinite(nr[0]):
             status = 5
@@ -149,15 +177,61 @@ def solve(prob: Problem, uc, uf, tol=1e-10, max_outer=60, nu_f=1, nu_c=1):
             break
         if it == max_outer:
             break
-        for _ in range(nu_f):
-            uc[prob.cov] = oracle.restrict(uf)
-            ff = ghost_forcing(uc, uf, prob.b0, prob.h_f)
-            oracle.step(prob.pf, 1, uf, None, prob.rf5, prob.rf1, None, ff)
-        Hf, Hc, _ = prob.residuals(uc, uf)
-        fc = np.zeros_like(uc)
-        fc[prob.cov] = oracle.restrict(Hf) - Hc[prob.cov]
-        before = uc.copy()
+        tau = [None] * L
+        before = [None] * L
+        for k in range(L - 1, 0, -1):
+            for _ in range(nu_f):
+                to_parent(k)
+                oracle.step(prob.p[k], 1, u[k], None, prob.r5[k], prob.r1[k], None, forcing(k, tau))
+            to_parent(k)
+            # FAS forcing of the parent on the cells under box k: the restricted residual
+            # of the box's own (FAS) equation minus the parent's operator at the average
+            Hk = prob.H(u, k, forcing(k, tau))
+            Hp = prob.H(u, k - 1, prob.ghosts(u, k - 1) if k > 1 else None)
+            t = np.zeros_like(u[k - 1])
+            cov = prob.covered(k - 1)
+            t[cov] = oracle.restrict(Hk) - Hp[cov]
+            tau[k - 1] = t
+            before[k - 1] = u[k - 1].copy()
+            if k > 1:  # the intermediate level's own steps follow with this tau
+                continue
         for _ in range(nu_c):
-            oracle.step(prob.pc, 1, uc, None, prob.rc5, prob.rc1, None, fc)
-        uf += cubic_children(uc - before, prob.b0, prob.m)
+            oracle.step(prob.p[0], 1, u[0], None, prob.r5[0], prob.r1[0], None, tau[0])
+        for k in range(1, L):
+            u[k] += cubic_children(u[k - 1] - before[k - 1], prob.b[k], prob.p[k].n // 2)
     return it, hist, status
+
+
+class Problem(Nested):
+    """Two levels: a base grid and one box (the names of the two-level tests)."""
+
+    def __init__(self, pc, pf, b0, rho5c, rho1c, rho5f, rho1f):
+        super().__init__([pc, pf], [0, b0], [rho5c, rho5f], [rho1c, rho1f])
+        self.pc, self.pf, self.b0, self.m = pc, pf, b0, pf.n // 2
+        self.rc5, self.rc1, self.rf5, self.rf1 = rho5c, rho1c, rho5f, rho1f
+        self.h_c, self.h_f = self.h[0], self.h[1]
+
+    @property
+    def cov(self):
+        """Base cells under the box."""
+        return self.covered(0)
+
+    def residuals(self, uc, uf, fc=None):
+        """(H_f with the interpolated ghosts, H_c, ghost forcing) after the base cells
+        under the box took their children's average (uc is updated in place)."""
+        uc[self.covered(0)] = oracle.restrict(uf)
+        ff = ghost_forcing(uc, uf, self.b0, self.h_f)
+        Hf = oracle.residuals(self.pf, uf, None, self.rf5, self.rf1, None, ff)[0]
+        Hc = oracle.residuals(self.pc, uc, None, self.rc5, self.rc1, None, fc)[0]
+        return Hf, Hc, ff
+
+    def norm(self, Hf, Hc=None):
+        if Hc is None:  # the nested form: a list of per-level residuals
+            return super().norm(Hf)
+        return super().norm([Hc, Hf])
+
+
+def solve(prob: Problem, uc, uf, tol=1e-10, max_outer=60, nu_f=1, nu_c=1):
+    """Two-level FAS iteration in place on (uc, uf)."""
+    u = [uc, uf]
+    return solve_nested(prob, u, tol, max_outer, nu_f, nu_c)

@@ -262,3 +262,149 @@ def test_planted_zero_rule_is_caught():
         with pytest.raises(AssertionError):
             check_zero_rule()
     check_zero_rule()
+
+
+# ---- nested boxes ---------------------------------------------------------------------
+
+def nested_problem(nc, boxes, levels, L=None, shell=None, length=None):
+    """Base grid on [-L/2, L/2]^3 (Robin rule, puncture of mass 1 at the centre, a scalar
+    shell, conformal matter) and boxes (m, b): box k over m cells of level k-1 from its
+    cell b, refined by 2."""
+    length = 64.0 if length is None else length
+    sh = SHELL if shell is None else shell
+    h = length / nc
+    org = np.full(3, -length / 2)
+    ps = [oracle.params(nc, levels=levels[0], bc=oracle.BC_ROBIN, length=length, origin=tuple(org), nu_pre=2,
+                        nu_post=2, puncture_mass=1.0, conformal_matter=True)]
+    bs = [0]
+    for (m, b), lv in zip(boxes, levels[1:]):
+        org = org + b * h
+        h = h / 2
+        ps.append(oracle.params(2 * m, levels=lv, bc=oracle.BC_ZERO, length=2 * m * h, origin=tuple(org), nu_pre=2,
+                                nu_post=2, puncture_mass=1.0, conformal_matter=True))
+        bs.append(b)
+    src = [oracle.shell_sources(p, sh["amplitude"], sh["r0"], sh["width2"]) for p in ps]
+    return refine.Nested(ps, bs, [q[0] for q in src], [q[1] for q in src])
+
+
+def lagrange_rows_pair(nc_parent, b0, m, h):
+    """Cubic rows of the children -2 .. 2m+1 (along one axis) of box (b0, m) from its parent."""
+    W = np.zeros((2 * m + 4, nc_parent))
+    for F in range(-2, 2 * m + 2):
+        x = (2 * b0 + F + 0.5) * h / 2
+        I = (2 * b0 + F) // 2
+        nodes = [I - 2, I - 1, I, I + 1] if (2 * b0 + F) % 2 == 0 else [I - 1, I, I + 1, I + 2]
+        xs = [(q + 0.5) * h for q in nodes]
+        for a, q in enumerate(nodes):
+            W[F + 2, q] = np.prod([(x - xs[b]) / (xs[a] - xs[b]) for b in range(4) if b != a])
+    return W
+
+
+def nested_residual(x, prob, masks, rows):
+    """The nested composite equations written out (as composite_residual, level by level)."""
+    L = prob.L
+    u, off = [], 0
+    for k in range(L):
+        n = prob.p[k].n
+        uk = np.zeros((n,) * 3)
+        cnt = int(masks[k].sum())
+        uk[masks[k]] = x[off:off + cnt]
+        off += cnt
+        u.append(uk)
+    for k in range(L - 1, 0, -1):
+        m, b = prob.p[k].n // 2, prob.b[k]
+        u[k - 1][b:b + m, b:b + m, b:b + m] = u[k].reshape(m, 2, m, 2, m, 2).mean(axis=(1, 3, 5))
+    out = []
+    for k in range(L):
+        p = prob.p[k]
+        if k == 0:
+            g0 = judge.Grid(p.n, p.length, judge.BC_ROBIN, tuple(p.origin))
+            Hk, _, _ = judge.residuals(g0, u[0], None, prob.r5[0], prob.r1[0], None, 0.0, 1.0, conformal_matter=True)
+        else:
+            gk = judge.Grid(p.n, p.length, judge.BC_ZERO, tuple(p.origin))
+            Hk, _, _ = judge.residuals(gk, u[k], None, prob.r5[k], prob.r1[k], None, 0.0, 1.0, conformal_matter=True)
+            Wr = rows[k]
+            G = np.einsum("ai,bj,ck,ijk->abc", Wr, Wr, Wr, u[k - 1])
+            G[2:-2, 2:-2, 2:-2] = 0.0
+            Hk = Hk + sum(judge.d2(gk, G, a) for a in range(3))
+        out.append(Hk[masks[k]])
+    return np.concatenate(out)
+
+
+def check_nested_brute_force():
+    # base 12^3 on [-12, 12]^3, box 1: 4^3 base cells at 4 (8^3, [-4, 4]), box 2: 2^3 cells of
+    # box 1 at 3 (4^3, [-1, 1]) around the puncture
+    prob = nested_problem(NC, [(4, 4), (2, 3)], [2, 2, 1], length=L)
+    masks = []
+    for k in range(prob.L):
+        mk = np.ones((prob.p[k].n,) * 3, dtype=bool)
+        if k + 1 < prob.L:
+            mk[prob.covered(k)] = False
+        masks.append(mk)
+    rows = [None] + [lagrange_rows_pair(prob.p[k - 1].n, prob.b[k], prob.p[k].n // 2, prob.h[k - 1])
+                     for k in range(1, prob.L)]
+    nx = sum(int(mk.sum()) for mk in masks)
+    if "nested" in _DENSE:
+        x = _DENSE["nested"]
+    else:
+        x = dense_nested_solution(prob, masks, rows, nx)
+        _DENSE["nested"] = x
+    u = [np.zeros((p.n,) * 3) for p in prob.p]
+    it, hist, st = refine.solve_nested(prob, u, tol=1e-12, max_outer=80)
+    assert st == 0, hist[-3:]
+    got = np.concatenate([u[k][masks[k]] for k in range(prob.L)])
+    assert np.abs(got - x).max() <= 1e-9 * np.abs(x).max(), np.abs(got - x).max()
+
+
+def dense_nested_solution(prob, masks, rows, nx):
+    x = np.zeros(nx)
+    F0 = nested_residual(x, prob, masks, rows)
+    J = np.zeros((nx, nx))
+    eps = 1e-7
+    for j in range(nx):
+        e = np.zeros(nx)
+        e[j] = eps
+        J[:, j] = (nested_residual(x + e, prob, masks, rows) - F0) / eps
+    import scipy.linalg
+    lu = scipy.linalg.lu_factor(J)
+    for _ in range(40):
+        F = nested_residual(x, prob, masks, rows)
+        if np.abs(F).max() <= 1e-13:
+            break
+        x = x - scipy.linalg.lu_solve(lu, F)
+    assert np.abs(nested_residual(x, prob, masks, rows)).max() <= 1e-12
+    return x
+
+
+def test_nested_composite_solution_matches_a_dense_solve():
+    check_nested_brute_force()
+
+
+def test_nested_boxes_agree_with_one_box_of_the_same_spacing():
+    """Base 32^3 with two nested boxes (h = 2, 1, 0.5 around the puncture) against base 64^3
+    with one box (h = 1, 0.5): the innermost boxes cover the same cells at the same spacing
+    and differ only through the base grids far away."""
+    shell = dict(amplitude=0.1, r0=10.0, width2=4.0)
+    p3 = nested_problem(32, [(16, 8), (16, 8)], [4, 4, 4], shell=shell)
+    u3 = [np.zeros((p.n,) * 3) for p in p3.p]
+    assert refine.solve_nested(p3, u3, tol=1e-10, max_outer=40)[2] == 0
+    p2 = nested_problem(64, [(16, 24)], [5, 4], shell=shell)
+    u2 = [np.zeros((p.n,) * 3) for p in p2.p]
+    assert refine.solve_nested(p2, u2, tol=1e-10, max_outer=40)[2] == 0
+    d = np.abs(u3[2] - u2[1]).max()
+    print(f"innermost boxes differ by {d:.2e} (|u| up to {np.abs(u2[1]).max():.3f})")
+    assert d <= 2e-5
+
+
+def test_planted_nested_tau_without_the_inner_forcing_is_caught(monkeypatch):
+    # the FAS forcing of a parent built from the level's residual without its own tau
+    real_H = refine.Nested.H
+
+    def H_no_tau(self, u, k, f):
+        if f is not None and k > 0 and k + 1 < self.L:
+            f = self.ghosts(u, k)  # drops the tau a middle level received
+        return real_H(self, u, k, f)
+
+    monkeypatch.setattr(refine.Nested, "H", H_no_tau)
+    with pytest.raises(AssertionError):
+        check_nested_brute_force()
