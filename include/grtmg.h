@@ -296,6 +296,28 @@ mg_status mg_refine_solve(mg_ctx *cb, mg_ctx *cx, int32_t b0, double *d_uc, doub
                           size_t work_bytes, double tol, int32_t max_outer, int32_t nu_box, int32_t nu_base,
                           mg_report *rep);
 
+/*
+ * Nested boxes (the same reading, 2..8 levels): ctx[0] is the base context, ctx[k]
+ * (k >= 1) a box over m_k^3 cells of ctx[k-1] from its cell (b0[k], b0[k], b0[k]) on
+ * (b0[0] unused), each with the requirements mg_refine_solve states for a box and its
+ * base (zero rule, margin of 3 parent cells, matching spacing, origin and physics,
+ * forcing arrays that are overwritten, one caller stream); d_u[k] holds u of level k.
+ * A cell under a finer box holds the average of its children; every box's ghosts come
+ * from its parent.  One iteration: from the finest level down to level 1, nu_box steps
+ * of the level (interface-ghost forcing formed before each, plus the FAS forcing it
+ * received from the box inside it), then the FAS forcing of its parent,
+ * tau = R (H of the level, its own FAS forcing included) - H_parent(R u) on the cells
+ * under it; nu_base steps of the base grid; from level 1 up, every box adds the cubic
+ * interpolation of its parent's change.  The composite norm sums every level over the
+ * cells no finer box covers.  Two levels give mg_refine_solve.  Workspace:
+ * mg_refine_nested_workspace_size (p[k]: the levels' parameters).
+ */
+mg_status mg_refine_nested_workspace_size(int32_t levels, const mg_params *const *p, const int32_t *b0,
+                                          size_t *bytes);
+mg_status mg_refine_solve_nested(int32_t levels, mg_ctx *const *ctx, const int32_t *b0, double *const *d_u,
+                                 void *d_work, size_t work_bytes, double tol, int32_t max_outer, int32_t nu_box,
+                                 int32_t nu_base, mg_report *rep);
+
 void mg_destroy(mg_ctx *ctx);
 const char *mg_status_str(mg_status s);
 

@@ -2573,19 +2573,21 @@ mg_status mg_shell_field_sources(const mg_params *p, double amp, double r0, doub
     return hip_status();
 }
 
-// ---- two-level static mesh refinement ----------------------------------------------------
+// ---- static mesh refinement by nested boxes ---------------------------------------------
 
 } // extern "C"
 
 namespace {
 
-// Geometry of a refined box over a base grid (corner at base cell b0 on every axis,
-// m base cells per axis, 2m box cells): both psi-only, the box under the zero rule,
-// a margin of 3 base cells, matching spacing, origin and physics.
+constexpr int kMaxRefineLevels = 8;
+
+// Geometry of a box over its parent (corner at parent cell b0 on every axis, m parent
+// cells per axis, 2m box cells): both psi-only, the box under the zero rule, a margin
+// of 3 parent cells, matching spacing, origin and physics.
 mg_status refine_check(const mg_params &pb, const mg_params &px, int b0)
 {
     if (validate(&pb) != MG_OK || validate(&px) != MG_OK) return MG_ERR_INVALID;
-    if (pb.solve_momentum || px.solve_momentum || px.bc != MG_BC_ZERO || pb.bc == MG_BC_ZERO) return MG_ERR_INVALID;
+    if (pb.solve_momentum || px.solve_momentum || px.bc != MG_BC_ZERO) return MG_ERR_INVALID;
     if ((pb.flags | px.flags) & MG_FLAG_CTTK) return MG_ERR_INVALID;
     if ((pb.flags & MG_FLAG_CONFORMAL_MATTER) != (px.flags & MG_FLAG_CONFORMAL_MATTER)) return MG_ERR_INVALID;
     if (px.n % 2 != 0) return MG_ERR_INVALID;
@@ -2600,20 +2602,39 @@ mg_status refine_check(const mg_params &pb, const mg_params &px, int b0)
     return MG_OK;
 }
 
+mg_status refine_check_all(int L, const mg_params *const *p, const int32_t *b0)
+{
+    if (L < 2 || L > kMaxRefineLevels || !p || !b0) return MG_ERR_INVALID;
+    for (int k = 0; k < L; k++)
+        if (!p[k]) return MG_ERR_INVALID;
+    if (p[0]->bc == MG_BC_ZERO) return MG_ERR_INVALID;
+    for (int k = 1; k < L; k++) {
+        const mg_status st = refine_check(*p[k - 1], *p[k], b0[k]);
+        if (st != MG_OK) return st;
+    }
+    return MG_OK;
+}
+
+// Workspace: per level its residual field, the old values (all but the finest) and
+// the FAS forcing of intermediate levels, then the norm partials and result.
 struct RefineWork {
-    double *uc_old, *Hf, *Hc, *part, *res;
+    double *H[kMaxRefineLevels], *old[kMaxRefineLevels], *tau[kMaxRefineLevels];
+    double *part, *res;
     size_t bytes;
 };
 
-RefineWork refine_layout(const mg_params &pb, const mg_params &px, char *base)
+RefineWork refine_layout(int L, const mg_params *const *p, char *base)
 {
     Carver cv{base};
-    const size_t mc = (size_t)pb.n * pb.n * pb.n, mf = (size_t)px.n * px.n * px.n;
     RefineWork w;
-    w.uc_old = (double *)cv.take(mc * sizeof(double));
-    w.Hf = (double *)cv.take(mf * sizeof(double));
-    w.Hc = (double *)cv.take(mc * sizeof(double));
-    w.part = (double *)cv.take(2 * (size_t)kSrcBlocks * sizeof(double));
+    std::memset(&w, 0, sizeof(w));
+    for (int k = 0; k < L; k++) {
+        const size_t bytes = (size_t)p[k]->n * p[k]->n * p[k]->n * sizeof(double);
+        w.H[k] = (double *)cv.take(bytes);
+        if (k + 1 < L) w.old[k] = (double *)cv.take(bytes);
+        if (k > 0 && k + 1 < L) w.tau[k] = (double *)cv.take(bytes);
+    }
+    w.part = (double *)cv.take(2 * (size_t)L * kSrcBlocks * sizeof(double));
     w.res = (double *)cv.take(2 * sizeof(double));
     w.bytes = align_up(cv.off, 256);
     return w;
@@ -2639,67 +2660,77 @@ void residual_field(mg_ctx *c, const double *u, double *H)
     leave(c);
 }
 
-} // namespace
-
-extern "C" {
-
-mg_status mg_refine_workspace_size(const mg_params *base, const mg_params *box, int32_t b0, size_t *bytes)
+mg_status refine_solve(int L, mg_ctx *const *c, const int32_t *b0, double *const *u, void *d_work, size_t work_bytes,
+                       double tol, int max_outer, int nu_box, int nu_base, mg_report *rep)
 {
-    if (!base || !box || !bytes) return MG_ERR_INVALID;
-    const mg_status st = refine_check(*base, *box, b0);
-    if (st != MG_OK) return st;
-    *bytes = refine_layout(*base, *box, nullptr).bytes;
-    return MG_OK;
-}
-
-mg_status mg_refine_solve(mg_ctx *cb, mg_ctx *cx, int32_t b0, double *d_uc, double *d_uf, void *d_work,
-                          size_t work_bytes, double tol, int32_t max_outer, int32_t nu_box, int32_t nu_base,
-                          mg_report *rep)
-{
-    if (!cb || !cx || !d_uc || !d_uf || !(tol > 0.0) || max_outer < 0 || nu_box < 1 || nu_base < 1) return MG_ERR_INVALID;
+    if (L < 2 || L > kMaxRefineLevels || !c || !b0 || !u || !(tol > 0.0) || max_outer < 0 || nu_box < 1 ||
+        nu_base < 1)
+        return MG_ERR_INVALID;
     if (rep && rep->history && rep->history_cap < 0) return MG_ERR_INVALID;
-    if (refine_check(cb->p, cx->p, b0) != MG_OK || cb->batched || cx->batched) return MG_ERR_INVALID;
-    if (!cb->f || !cx->f || cb->user_s != cx->user_s) return MG_ERR_INVALID;
-    if (cb->bg_psi0 || cb->bg_A2 || cx->bg_psi0 || cx->bg_A2) return MG_ERR_INVALID;
-    const RefineWork w = refine_layout(cb->p, cx->p, (char *)d_work);
+    const mg_params *p[kMaxRefineLevels];
+    for (int k = 0; k < L; k++) {
+        if (!c[k] || !u[k] || c[k]->batched || !c[k]->f || c[k]->user_s != c[0]->user_s || c[k]->bg_psi0 ||
+            c[k]->bg_A2)
+            return MG_ERR_INVALID;
+        for (int q = 0; q < k; q++)
+            if (c[q] == c[k] || u[q] == u[k]) return MG_ERR_INVALID;
+        p[k] = &c[k]->p;
+    }
+    if (refine_check_all(L, p, b0) != MG_OK) return MG_ERR_INVALID;
+    const RefineWork w = refine_layout(L, p, (char *)d_work);
     if (!d_work || work_bytes < w.bytes || ((uintptr_t)d_work % 256) != 0) return MG_ERR_WORKSPACE;
     auto t0 = std::chrono::steady_clock::now();
-    cb->cont_valid = cx->cont_valid = false;
-    cb->vc_psi = cx->vc_psi = 0;
-    const hipStream_t s = cb->user_s;
-    const int nc = cb->p.n, m = cx->p.n / 2, nf = 2 * m;
-    const int64_t mc = (int64_t)nc * nc * nc, mf = (int64_t)nf * nf * nf, mm = (int64_t)m * m * m;
-    const BoxGeo bx{nc, b0, m};
-    double *fc = const_cast<double *>(cb->f), *ff = const_cast<double *>(cx->f);
-    const double hc = cb->p.length / nc, hf = hc / 2, vol = cb->p.length * cb->p.length * cb->p.length;
-    const unsigned nbn = std::min<unsigned>(nblk(mf + mc), kSrcBlocks);
-    auto sync = [&]() { hipLaunchKernelGGL(k_box_restrict, dim3(nblk(mm)), dim3(kBlock), 0, s, bx, (const double *)d_uf, d_uc); };
-    auto ghosts = [&]() {
-        hipLaunchKernelGGL(k_box_ghost_forcing, dim3(nblk(mf)), dim3(kBlock), 0, s, bx, cx->geo[0].inv12h2,
-                           (const double *)d_uc, ff);
+    const hipStream_t s = c[0]->user_s;
+    BoxGeo bx[kMaxRefineLevels]; // bx[k]: level k as the box of level k - 1
+    int64_t cells[kMaxRefineLevels];
+    double *f[kMaxRefineLevels], vol[kMaxRefineLevels];
+    for (int k = 0; k < L; k++) {
+        c[k]->cont_valid = false;
+        c[k]->vc_psi = 0;
+        cells[k] = (int64_t)p[k]->n * p[k]->n * p[k]->n;
+        f[k] = const_cast<double *>(c[k]->f);
+        const double h = p[k]->length / p[k]->n;
+        vol[k] = h * h * h;
+        bx[k] = k ? BoxGeo{p[k - 1]->n, b0[k], p[k]->n / 2} : BoxGeo{0, 0, 0};
+    }
+    const double total = p[0]->length * p[0]->length * p[0]->length;
+    // a parent's cells under box k take their children's average
+    auto to_parent = [&](int k) {
+        hipLaunchKernelGGL(k_box_restrict, dim3(nblk((int64_t)bx[k].m * bx[k].m * bx[k].m)), dim3(kBlock), 0, s, bx[k],
+                           (const double *)u[k], u[k - 1]);
     };
-    // H_f with the current ghosts and H_c without base forcing, at the synchronised state
-    auto residuals = [&]() {
-        sync();
-        ghosts();
-        residual_field(cx, d_uf, w.Hf);
-        fill<double>(s, fc, mc, 0.0);
-        residual_field(cb, d_uc, w.Hc);
+    // the forcing of level k: interface ghosts from its parent (+ its FAS forcing);
+    // the base level: its FAS forcing or zero
+    auto forcing = [&](int k, const double *tau) {
+        if (k > 0)
+            hipLaunchKernelGGL(k_box_ghost_forcing, dim3(nblk(cells[k])), dim3(kBlock), 0, s, bx[k],
+                               c[k]->geo[0].inv12h2, (const double *)u[k - 1], tau, f[k]);
+        else
+            fill<double>(s, f[0], cells[0], 0.0);
     };
+    const unsigned nbn = kSrcBlocks;
     mg_status st = MG_ERR_NOT_CONVERGED;
     double nr[4] = {0, 0, 0, 0}, first = -1.0;
     int it = 0, hist = 0;
     for (;; it++) {
-        residuals();
-        hipLaunchKernelGGL(k_box_norm, dim3(nbn), dim3(kBlock), 0, s, bx, hf * hf * hf, hc * hc * hc,
-                           (const double *)w.Hf, (const double *)w.Hc, w.part);
-        hipLaunchKernelGGL(k_reduce_final<2>, dim3(1), dim3(kBlock), 0, s, (const double *)w.part, (int64_t)nbn, 0x2u,
-                           0.0, w.res, 0LL);
-        if (hipMemcpyAsync(cb->hpin, w.res, 2 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        // composite norm of the synchronised state
+        for (int k = L - 1; k > 0; k--) to_parent(k);
+        for (int k = 0; k < L; k++) {
+            forcing(k, nullptr);
+            residual_field(c[k], u[k], w.H[k]);
+            const BoxGeo child = k + 1 < L ? bx[k + 1] : BoxGeo{0, 0, 0};
+            const unsigned nb = std::min<unsigned>(nblk(cells[k]), nbn);
+            fill<double>(s, w.part + 2 * (size_t)k * nbn, 2 * (int64_t)nbn, 0.0);
+            hipLaunchKernelGGL(k_level_norm, dim3(nb), dim3(kBlock), 0, s, p[k]->n, child, vol[k],
+                               (const double *)w.H[k], w.part + 2 * (size_t)k * nbn);
+        }
+        hipLaunchKernelGGL(k_reduce_final<2>, dim3(1), dim3(kBlock), 0, s, (const double *)w.part,
+                           (int64_t)L * nbn, 0x2u, 0.0, w.res, 0LL);
+        if (hipMemcpyAsync(c[0]->hpin, w.res, 2 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
             return MG_ERR_HIP;
-        nr[0] = std::sqrt(cb->hpin[0] / vol);
-        nr[2] = cb->hpin[1];
+        nr[0] = std::sqrt(c[0]->hpin[0] / total);
+        nr[2] = c[0]->hpin[1];
         if (rep && rep->history && hist < rep->history_cap) {
             std::memcpy(rep->history + 4 * hist, nr, sizeof(nr));
             hist++;
@@ -2721,30 +2752,43 @@ mg_status mg_refine_solve(mg_ctx *cb, mg_ctx *cx, int32_t b0, double *d_uc, doub
             st = MG_ERR_NOT_CONVERGED;
             break;
         }
-        // box steps with the interface ghosts of the current base values
-        for (int q = 0; q < nu_box; q++) {
-            sync();
-            ghosts();
-            psi_step(cx, d_uf);
+        // down the levels: box steps, then the FAS forcing of the parent
+        for (int k = L - 1; k > 0; k--) {
+            const double *tau_k = k + 1 < L ? w.tau[k] : nullptr;
+            for (int q = 0; q < nu_box; q++) {
+                to_parent(k);
+                forcing(k, tau_k);
+                psi_step(c[k], u[k]);
+            }
+            to_parent(k);
+            forcing(k, tau_k);
+            residual_field(c[k], u[k], w.H[k]);
+            forcing(k - 1, nullptr);
+            residual_field(c[k - 1], u[k - 1], w.H[k - 1]);
+            double *dst = k - 1 > 0 ? w.tau[k - 1] : f[0];
+            hipLaunchKernelGGL(k_box_tau, dim3(nblk(cells[k - 1])), dim3(kBlock), 0, s, bx[k], (const double *)w.H[k],
+                               (const double *)w.H[k - 1], dst);
+            if (hipMemcpyAsync(w.old[k - 1], u[k - 1], cells[k - 1] * sizeof(double), hipMemcpyDeviceToDevice, s) !=
+                hipSuccess)
+                return MG_ERR_HIP;
         }
-        // base steps on the FAS problem H_c(u_c) + tau = 0
-        residuals();
-        hipLaunchKernelGGL(k_box_tau, dim3(nblk(mc)), dim3(kBlock), 0, s, bx, (const double *)w.Hf,
-                           (const double *)w.Hc, fc);
-        if (hipMemcpyAsync(w.uc_old, d_uc, mc * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
-            return MG_ERR_HIP;
-        for (int q = 0; q < nu_base; q++) psi_step(cb, d_uc);
-        hipLaunchKernelGGL(k_box_correct, dim3(nblk(mm)), dim3(kBlock), 0, s, bx, (const double *)d_uc,
-                           (const double *)w.uc_old, d_uf);
+        // the base grid with its FAS forcing (f[0] holds tau)
+        for (int q = 0; q < nu_base; q++) psi_step(c[0], u[0]);
+        // up the levels: every box adds the cubic interpolation of its parent's change
+        for (int k = 1; k < L; k++)
+            hipLaunchKernelGGL(k_box_correct, dim3(nblk((int64_t)bx[k].m * bx[k].m * bx[k].m)), dim3(kBlock), 0, s,
+                               bx[k], (const double *)u[k - 1], (const double *)w.old[k - 1], u[k]);
         if (hip_status() != MG_OK) return MG_ERR_HIP;
     }
-    // the base values under the box end as their children's average
-    sync();
+    // the parents' cells under every box end as their children's average
+    for (int k = L - 1; k > 0; k--) to_parent(k);
     if (hip_status() != MG_OK) return MG_ERR_HIP;
     auto t1 = std::chrono::steady_clock::now();
     if (rep) {
+        int vc = 0;
+        for (int k = 0; k < L; k++) vc += c[k]->vc_psi;
         rep->outer_iters = it;
-        rep->vcycles_psi = cb->vc_psi + cx->vc_psi;
+        rep->vcycles_psi = vc;
         rep->vcycles_W = 0;
         rep->status = st;
         rep->h_rms = nr[0];
@@ -2755,6 +2799,43 @@ mg_status mg_refine_solve(mg_ctx *cb, mg_ctx *cx, int32_t b0, double *d_uc, doub
         rep->history_len = hist;
     }
     return st;
+}
+
+} // namespace
+
+extern "C" {
+
+mg_status mg_refine_workspace_size(const mg_params *base, const mg_params *box, int32_t b0, size_t *bytes)
+{
+    const mg_params *p[2] = {base, box};
+    const int32_t off[2] = {0, b0};
+    return mg_refine_nested_workspace_size(2, p, off, bytes);
+}
+
+mg_status mg_refine_nested_workspace_size(int32_t levels, const mg_params *const *p, const int32_t *b0, size_t *bytes)
+{
+    if (!bytes) return MG_ERR_INVALID;
+    const mg_status st = refine_check_all(levels, p, b0);
+    if (st != MG_OK) return st;
+    *bytes = refine_layout(levels, p, nullptr).bytes;
+    return MG_OK;
+}
+
+mg_status mg_refine_solve(mg_ctx *cb, mg_ctx *cx, int32_t b0, double *d_uc, double *d_uf, void *d_work,
+                          size_t work_bytes, double tol, int32_t max_outer, int32_t nu_box, int32_t nu_base,
+                          mg_report *rep)
+{
+    mg_ctx *c[2] = {cb, cx};
+    const int32_t off[2] = {0, b0};
+    double *u[2] = {d_uc, d_uf};
+    return refine_solve(2, c, off, u, d_work, work_bytes, tol, max_outer, nu_box, nu_base, rep);
+}
+
+mg_status mg_refine_solve_nested(int32_t levels, mg_ctx *const *ctx, const int32_t *b0, double *const *d_u,
+                                 void *d_work, size_t work_bytes, double tol, int32_t max_outer, int32_t nu_box,
+                                 int32_t nu_base, mg_report *rep)
+{
+    return refine_solve(levels, ctx, b0, d_u, d_work, work_bytes, tol, max_outer, nu_box, nu_base, rep);
 }
 
 mg_status mg_interp_cubic(const mg_params *pc, const double *d_coarse, double *d_fine, void *stream)

@@ -1,16 +1,17 @@
-// mg_refine.hpp -- kernels of the two-level static mesh refinement (Key features,
-// "Adaptive Mesh Refinement": refined boxes over the base grid; "Fast").
+// mg_refine.hpp -- kernels of the static mesh refinement by nested boxes (Key
+// features, "Adaptive Mesh Refinement": refined boxes over the base grid; "Fast").
 //
-// Composite grid: a base grid of nc^3 cells and one box of m^3 base cells whose
-// corner is base cell (b0, b0, b0), refined by 2 (nf = 2m cells per axis).  The
-// base value of a covered cell is the average of its 8 children; the box's two
-// ghost layers are the children of the base cells around it by the 4-point cubic
-// (weights (-5, 35, 105, -7)/128 and mirror).  The box is solved as a grid of its
-// own under the zero ghost rule with a forcing that carries the interpolated
-// ghosts, f = sum over stencil taps outside the box of w g / (12 (h/2)^2); the base
-// grid takes the FAS forcing tau = R H_f - H_c(R u_f) on covered cells.  The box
-// keeps a margin of at least 3 base cells, so every cubic stencil stays inside the
-// base grid and no boundary rule is needed here.
+// Levels: a base grid, then boxes, each refined by 2 over m^3 cells of its parent
+// whose corner is parent cell (b0, b0, b0) (nf = 2m cells per axis).  A parent
+// cell under a box holds the average of its 8 children; a box's two ghost layers
+// are the children of the parent cells around it by the 4-point cubic (weights
+// (-5, 35, 105, -7)/128 and mirror).  A box is solved as a grid of its own under
+// the zero ghost rule with a forcing that carries the interpolated ghosts,
+// f = sum over stencil taps outside the box of w g / (12 h_box^2); a parent takes
+// the FAS forcing tau = R H_box - H_parent(R u_box) on the cells under the box.  A
+// box keeps a margin of at least 3 parent cells, so every cubic stencil stays inside
+// the parent and no boundary rule is needed here.  BoxGeo names a parent-box pair:
+// nc is the parent's cells per axis.
 #pragma once
 
 #include "mg_device.hpp"
@@ -86,9 +87,10 @@ __global__ void __launch_bounds__(kBlock) k_box_restrict(BoxGeo bx, const double
 }
 
 // Forcing of the box under the zero rule: the taps of every fine cell that fall
-// outside the box, on the interpolated ghosts, times 1/(12 (h/2)^2).
+// outside the box, on the interpolated ghosts, times 1/(12 (h/2)^2), plus the box's
+// own FAS forcing tau from a finer box inside it (null: none).
 __global__ void __launch_bounds__(kBlock) k_box_ghost_forcing(BoxGeo bx, double inv12h2, const double *__restrict__ uc,
-                                                              double *__restrict__ ff)
+                                                              const double *__restrict__ tau, double *__restrict__ ff)
 {
     const int nf = 2 * bx.m;
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -108,7 +110,7 @@ __global__ void __launch_bounds__(kBlock) k_box_ghost_forcing(BoxGeo bx, double 
             f += wt[d + 2] * box_cubic_at(bx, uc, nullptr, gi, gj, gk);
         }
     }
-    ff[t] = f * inv12h2;
+    ff[t] = f * inv12h2 + (tau ? tau[t] : 0.0);
 }
 
 // FAS forcing of the base grid: tau = R H_f - H_c on covered cells, zero elsewhere.
@@ -153,29 +155,20 @@ __global__ void __launch_bounds__(kBlock) k_box_correct(BoxGeo bx, const double 
             }
 }
 
-// Composite norm partials: sum of H^2 times the cell volume over the box cells and the
-// uncovered base cells, and max |H|; grid-stride over nf^3 + nc^3 items.
-__global__ void __launch_bounds__(kBlock) k_box_norm(BoxGeo bx, double vf, double vc, const double *__restrict__ Hf,
-                                                     const double *__restrict__ Hc, double *__restrict__ partials)
+// Composite norm partials of one level: sum of H^2 times the cell volume over the
+// cells no finer box covers (child.m = 0: no finer box), and max |H|; grid-stride.
+__global__ void __launch_bounds__(kBlock) k_level_norm(int n, BoxGeo child, double vol, const double *__restrict__ H,
+                                                       double *__restrict__ partials)
 {
-    const int nc = bx.nc, nf = 2 * bx.m;
-    const int64_t mf = (int64_t)nf * nf * nf, mc = (int64_t)nc * nc * nc;
+    const int64_t m3 = (int64_t)n * n * n;
     double v[2] = {0.0, 0.0};
-    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < mf + mc; t += (int64_t)gridDim.x * kBlock) {
-        double h, w;
-        if (t < mf) {
-            h = Hf[t];
-            w = vf;
-        } else {
-            const int64_t q = t - mf;
-            const int K = (int)(q % nc) - bx.b0, J = (int)((q / nc) % nc) - bx.b0, I = (int)(q / ((int64_t)nc * nc)) - bx.b0;
-            if ((unsigned)I < (unsigned)bx.m && (unsigned)J < (unsigned)bx.m && (unsigned)K < (unsigned)bx.m) continue;
-            h = Hc[q];
-            w = vc;
-        }
-        v[0] += w * h * h;
+    for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < m3; q += (int64_t)gridDim.x * kBlock) {
+        const int K = (int)(q % n) - child.b0, J = (int)((q / n) % n) - child.b0, I = (int)(q / ((int64_t)n * n)) - child.b0;
+        if ((unsigned)I < (unsigned)child.m && (unsigned)J < (unsigned)child.m && (unsigned)K < (unsigned)child.m)
+            continue;
+        const double h = H[q];
+        v[0] += vol * h * h;
         v[1] = fmax(v[1], fabs(h));
-        if (h != h) v[1] = h; // a NaN survives the max
     }
     block_reduce_store<2>(v, 0x2u, partials + 2 * (int64_t)blockIdx.x);
 }

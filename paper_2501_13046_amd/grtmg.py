@@ -97,6 +97,9 @@ def lib() -> C.CDLL:
         L.mg_refine_workspace_size.argtypes = [pp, pp, i32, C.POINTER(C.c_size_t)]
         L.mg_refine_solve.argtypes = [vp, vp, i32, vp, vp, vp, C.c_size_t, C.c_double, i32, i32, i32,
                                       C.POINTER(MgReport)]
+        L.mg_refine_nested_workspace_size.argtypes = [i32, C.POINTER(pp), C.POINTER(i32), C.POINTER(C.c_size_t)]
+        L.mg_refine_solve_nested.argtypes = [i32, C.POINTER(vp), C.POINTER(i32), C.POINTER(vp), vp, C.c_size_t,
+                                             C.c_double, i32, i32, i32, C.POINTER(MgReport)]
         L.mg_cttk_hybrid_sources.argtypes = [pp, vp, vp, vp, vp, vp, C.c_size_t, dp, vp]
         L.mg_kernel_op.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp]
         L.mg_batch_workspace_size.argtypes = [pp, i32, C.POINTER(C.c_size_t)]
@@ -119,7 +122,8 @@ def lib() -> C.CDLL:
                   "mg_shell_field_sources", "mg_interp_cubic", "mg_kernel_op", "mg_probe",
                   "mg_probe_result", "mg_batch_workspace_size", "mg_setup_batch", "mg_solve_batch",
                   "mg_fmg_start", "mg_batch_launch_mode", "mg_batch_groups", "mg_autotune", "mg_set_tile",
-                  "mg_cttk_trace", "mg_cttk_hybrid_sources", "mg_refine_workspace_size", "mg_refine_solve"):
+                  "mg_cttk_trace", "mg_cttk_hybrid_sources", "mg_refine_workspace_size", "mg_refine_solve",
+                  "mg_refine_nested_workspace_size", "mg_refine_solve_nested"):
             getattr(L, f).restype = st
         _lib = L
     return _lib
@@ -420,6 +424,31 @@ def refine_solve(base: "Solver", box: "Solver", b0: int, uc: torch.Tensor, uf: t
                h_max=rep.h_max, seconds=rep.seconds, history=hist[: rep.history_len].copy())
     if raise_on_failure:
         _check(st, "mg_refine_solve")
+    return out
+
+
+def refine_solve_nested(solvers, offsets, us, tol: float = 1e-10, max_outer: int = 60, nu_box: int = 1,
+                        nu_base: int = 1, raise_on_failure: bool = True) -> dict:
+    """Nested-box composite solve (mg_refine_solve_nested): solvers[0] the base, solvers[k]
+    a box over solvers[k-1] at cell offsets[k] (offsets[0] unused); in place on us."""
+    L = len(solvers)
+    pp = (C.POINTER(MgParams) * L)(*[C.pointer(s.p) for s in solvers])
+    off = (C.c_int32 * L)(*[int(b) for b in offsets])
+    nbytes = C.c_size_t(0)
+    _check(lib().mg_refine_nested_workspace_size(L, pp, off, C.byref(nbytes)), "mg_refine_nested_workspace_size")
+    work = torch.empty(nbytes.value, dtype=torch.uint8, device=us[0].device)
+    ctx = (C.c_void_p * L)(*[s.ctx.value for s in solvers])
+    ua = (C.c_void_p * L)(*[_dptr(u, numel=s.cells).value for u, s in zip(us, solvers)])
+    hist = np.zeros((max_outer + 2, 4))
+    rep = MgReport()
+    rep.history = hist.ctypes.data_as(C.POINTER(C.c_double))
+    rep.history_cap = max_outer + 2
+    st = lib().mg_refine_solve_nested(L, ctx, off, ua, C.c_void_p(work.data_ptr()), nbytes.value, tol, max_outer,
+                                      nu_box, nu_base, C.byref(rep))
+    out = dict(status=st, outer_iters=rep.outer_iters, vcycles_psi=rep.vcycles_psi, h_rms=rep.h_rms,
+               h_max=rep.h_max, seconds=rep.seconds, history=hist[: rep.history_len].copy())
+    if raise_on_failure:
+        _check(st, "mg_refine_solve_nested")
     return out
 
 

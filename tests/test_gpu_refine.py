@@ -100,3 +100,57 @@ def test_refine_rejects_bad_geometry():
             g.refine_solve(sb, sx, bad_b0, uc, uf, max_outer=1)
     with pytest.raises(g.MGError):  # the base grid as its own box
         g.refine_solve(sb, sb, b0, uc, uc, max_outer=1)
+
+
+def nested(nc, boxes, levels, precision):
+    """The black hole of the 64 M box on a base grid of nc^3 with nested boxes (m, b)
+    around the puncture, on both sides."""
+    w = synth.puncture_shell(nc, precision=precision, levels=levels[0])
+    pb = g.params(nc, levels[0], w.bc, precision, w.length, w.origin, 0.0, w.nu_pre, w.nu_post, False,
+                  w.puncture_mass, w.puncture_pos, True)
+    ps, pos = [pb], [oracle.params_from_workload(w)]
+    offs = [0]
+    for (m, b), lv in zip(boxes, levels[1:]):
+        ps.append(g.box_params(ps[-1], b, m, lv))
+        q = ps[-1]
+        pos.append(oracle.params(q.n, levels=lv, bc=oracle.BC_ZERO, length=q.length, origin=tuple(q.origin),
+                                 nu_pre=w.nu_pre, nu_post=w.nu_post, puncture_mass=w.puncture_mass,
+                                 puncture_pos=w.puncture_pos, conformal_matter=True))
+        offs.append(b)
+    sh = w.shell
+    src = [oracle.shell_sources(po, sh["amplitude"], sh["r0"], sh["width2"], w.scalar_mass) for po in pos]
+    prob = refine.Nested(pos, offs, [q[0] for q in src], [q[1] for q in src])
+    keep, solvers = [], []
+    for p, (r5, r1, _) in zip(ps, src):
+        t = [T(r5), T(r1), torch.zeros((p.n,) * 3, dtype=torch.float64, device=dev())]
+        keep.append(t)
+        solvers.append(g.Solver(p, t[0], t[1], None, t[2]))
+    return prob, solvers, offs, keep
+
+
+@pytest.mark.parametrize("precision", [g.PREC_FP64, g.PREC_FP32_IR])
+def test_nested_boxes_match_oracle(precision):
+    prob, solvers, offs, _ = nested(32, [(16, 8), (16, 8)], [4, 4, 4], precision)
+    us = [torch.zeros((s.p.n,) * 3, dtype=torch.float64, device=dev()) for s in solvers]
+    rep = g.refine_solve_nested(solvers, offs, us, tol=1e-11, max_outer=60)
+    uo = [np.zeros((p.n,) * 3) for p in prob.p]
+    it, hist, st = refine.solve_nested(prob, uo, tol=1e-11, max_outer=60)
+    assert st == 0
+    print(f"nested prec={precision}: {rep['outer_iters']} iterations (oracle {it}), rms {rep['h_rms']:.2e}")
+    for k in range(3):
+        assert np.abs(N(us[k]) - uo[k]).max() <= 1e-9 * (1.0 + np.abs(uo[k]).max()), k
+
+
+def test_nested_boxes_full_size():
+    """Base 128^3 (h = 0.5) with boxes of 64^3 parent cells refined twice (128^3 at
+    h = 0.25 over [-16, 16]^3, 128^3 at h = 0.125 over [-8, 8]^3): the oracle's composite
+    residual of the result is below the tolerance."""
+    prob, solvers, offs, _ = nested(128, [(64, 32), (64, 32)], [6, 6, 6], g.PREC_FP32_IR)
+    us = [torch.zeros((s.p.n,) * 3, dtype=torch.float64, device=dev()) for s in solvers]
+    rep = g.refine_solve_nested(solvers, offs, us, tol=1e-10, max_outer=40)
+    u = [N(x) for x in us]
+    rms, mx = refine.Nested.norm(prob, refine.Nested.residuals(prob, u))
+    print(f"nested 3 x 128^3: {rep['outer_iters']} iterations, {rep['seconds'] * 1e3:.1f} ms, oracle composite rms "
+          f"{rms:.2e} (GPU {rep['h_rms']:.2e})")
+    assert rms <= 1.01e-10
+    assert abs(rms - rep["h_rms"]) <= 1e-3 * rms + 1e-14
