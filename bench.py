@@ -149,6 +149,29 @@ def bench_refined_puncture(g, synth, dev, args, log, u256):
         coarse = box.reshape(m, 2, m, 2, m, 2).mean(dim=(1, 3, 5))
         out["base_alone_vs_uniform_256_max"] = float((u1[b0:b0 + m, b0:b0 + m, b0:b0 + m] - coarse).abs().max())
         out["refined_vs_uniform_256_max_base"] = float((uc[b0:b0 + m, b0:b0 + m, b0:b0 + m] - coarse).abs().max())
+    # a second box inside the first (64^3 of its cells refined again: h = 0.125 over [-8, 8]^3)
+    p2 = g.box_params(px, b0, m, 6)
+    r5g, r1g, _ = g.shell_field_sources(p2, sh["amplitude"], sh["r0"], sh["width2"], w.scalar_mass, dev)
+    fg = torch.zeros((2 * m,) * 3, dtype=torch.float64, device=dev)
+    sg = g.Solver(p2, r5g, r1g, None, fg)
+    ug = torch.zeros((2 * m,) * 3, dtype=torch.float64, device=dev)
+    sg.autotune(ug, None, reps=10)
+    runs3, rep3 = [], None
+    for k in range(1 + max(1, args.steps // 2)):
+        for x in (uc, uf, ug):
+            x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep3 = g.refine_solve_nested([sb, sx, sg], [0, b0, b0], [uc, uf, ug], tol=args.tol, max_outer=60)
+        torch.cuda.synchronize()
+        if k:
+            runs3.append(time.perf_counter() - t0)
+    runs3.sort()
+    out["nested_three_levels"] = dict(seconds=runs3[len(runs3) // 2], outer_iters=rep3["outer_iters"],
+                                      composite_rms=rep3["h_rms"], spacings=[0.5, 0.25, 0.125])
+    sg.close()
+    log(f"[bench] nested boxes (three 128^3 levels, h down to 0.125): {out['nested_three_levels']['seconds'] * 1e3:.2f} "
+        f"ms/solve, {rep3['outer_iters']} composite iterations, rms {rep3['h_rms']:.2e}")
     log(f"[bench] refined puncture (128^3 base + 128^3 box): {out['seconds'] * 1e3:.2f} ms/solve (median of "
         f"{len(runs)}), {rep['outer_iters']} composite iterations, rms {rep['h_rms']:.2e}; against uniform 256^3 over "
         f"the box: {out.get('box_vs_uniform_256_max', float('nan')):.2e} (base alone "
