@@ -1063,6 +1063,31 @@ __global__ void __launch_bounds__(kGjThreads) k_gauss_jordan(const double *A, do
 // Each block covers 16 rows with 16 threads per row (interleaved columns).
 constexpr int kApplySplit = 16;
 constexpr int kApplyRows = kBlock / kApplySplit;
+
+// sum over col = part, part + STRIDE, ... < m of Ainv[col * m + row] * rs[col], in
+// that order; the loads of each chunk of columns are issued together, so that a
+// thread waits for global memory once per chunk instead of once per column.
+template <int STRIDE>
+__device__ __forceinline__ double inv_row_dot(const double *Ainv, int m, int row, int part, const double *rs)
+{
+    constexpr int kChunk = 12;
+    double s = 0.0;
+    for (int c0 = part; c0 < m; c0 += kChunk * STRIDE) {
+        double v[kChunk];
+#pragma unroll
+        for (int e = 0; e < kChunk; e++) {
+            const int col = c0 + e * STRIDE;
+            v[e] = col < m ? Ainv[(int64_t)col * m + row] : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < kChunk; e++) {
+            const int col = c0 + e * STRIDE;
+            if (col < m) s += v[e] * rs[col];
+        }
+    }
+    return s;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_coarse_apply(const double *Ainv, int m,
                                                          const T *r, T *x, int ncomp_project, long long zs)
@@ -1087,9 +1112,7 @@ __global__ void __launch_bounds__(kBlock) k_coarse_apply(const double *Ainv, int
     }
     const int row = blockIdx.x * kApplyRows + threadIdx.x % kApplyRows;
     const int part = threadIdx.x / kApplyRows;
-    double s = 0.0;
-    if (row < m)
-        for (int col = part; col < m; col += kApplySplit) s += Ainv[(int64_t)col * m + row] * rs[col];
+    const double s = row < m ? inv_row_dot<kApplySplit>(Ainv, m, row, part, rs) : 0.0;
     __shared__ double red[kApplySplit][kApplyRows];
     red[part][threadIdx.x % kApplyRows] = s;
     __syncthreads();
@@ -2010,9 +2033,7 @@ __global__ void __launch_bounds__(kTailThreads) k_tail_W(TailArgs<T> a)
         const int rl = threadIdx.x % kWave, part = threadIdx.x / kWave;
         for (int rb = 0; rb < m; rb += kWave) {
             const int row = rb + rl;
-            double s = 0.0;
-            if (row < m)
-                for (int col = part; col < m; col += kParts) s += a.inv[(int64_t)col * m + row] * rs[col];
+            const double s = row < m ? inv_row_dot<kParts>(a.inv, m, row, part, rs) : 0.0;
             red[part][rl] = s;
             __syncthreads();
             if (threadIdx.x < kWave && row < m) {
