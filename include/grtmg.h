@@ -427,8 +427,21 @@ mg_status mg_fmg_start(mg_ctx *cc, mg_ctx *cf, double *d_uc, double *d_Wc, doubl
  * most 4680 (psi, FP32, periodic) or 1971 (psi otherwise; W), spanning at
  * most 4 levels (e.g. 16^3 for psi and 8^3 for W, FP32 periodic).  Their `level`
  * is the tail's first level; mg_autotune times one whole V-cycle each way.
+ * MG_TUNE_FOURIER_W (FP32 periodic contexts with momentum whose levels include a
+ * 16^3 one below the finest; `level` is that level): the W V-cycle solves that
+ * level exactly by discrete Fourier modes in one workgroup (1, the default) or
+ * runs it and the levels below as multigrid (0).  The exact solve changes the
+ * V-cycle (it is an exact coarse correction), not the equations: solutions agree
+ * to the solve tolerance.
  */
-enum { MG_TUNE_PASS_PSI = 1, MG_TUNE_PASS_W = 2, MG_TUNE_RESIDUAL = 3, MG_TUNE_TAIL_PSI = 4, MG_TUNE_TAIL_W = 5 };
+enum {
+    MG_TUNE_PASS_PSI = 1,
+    MG_TUNE_PASS_W = 2,
+    MG_TUNE_RESIDUAL = 3,
+    MG_TUNE_TAIL_PSI = 4,
+    MG_TUNE_TAIL_W = 5,
+    MG_TUNE_FOURIER_W = 6
+};
 typedef struct mg_tune {
     int32_t family, level, chosen, ncand;
     int32_t cand[4];
@@ -451,6 +464,9 @@ mg_status mg_set_tile(mg_ctx *ctx, int32_t family, int32_t level, int32_t tx);
  *                   arg = number of components
  *  MG_OP_COARSE_PSI out = (L_h + c)^-1 r on the coarsest level (r = in)
  *  MG_OP_COARSE_W   out = mean-free Delta_L,h^-1 (r - mean r) on the coarsest level
+ *  MG_OP_FOURIER_W  out = mean-free Delta_L,h^-1 (r - mean r) on a 16^3 level of an FP32
+ *                   periodic context, by discrete Fourier modes (r = in; in and out
+ *                   16-byte aligned): the exact bottom of the W V-cycle
  * Unused pointers may be NULL.  Enqueued only.
  */
 enum {
@@ -460,7 +476,8 @@ enum {
     MG_OP_DEFECT_RESTRICT_W = 4,
     MG_OP_PROLONG_ADD = 5,
     MG_OP_COARSE_PSI = 6,
-    MG_OP_COARSE_W = 7
+    MG_OP_COARSE_W = 7,
+    MG_OP_FOURIER_W = 8
 };
 mg_status mg_kernel_op(mg_ctx *ctx, int32_t op, int32_t level, int32_t arg, const void *d_in,
                        void *d_out, const void *d_r, const void *d_c);

@@ -23,6 +23,7 @@
 #include "mg_tiled.hpp"
 #include "mg_cttk.hpp"
 #include "mg_refine.hpp"
+#include "mg_fourier.hpp"
 #include "mg_internal.h"
 
 using namespace grtmg;
@@ -117,6 +118,8 @@ struct mg_ctx {
     TileMap tileR;             // brick map of the finest-level residual
     int tail_psi, tail_W;      // first level of the workgroup-resident V-cycle tail (-1: not possible)
     bool tail_psi_on, tail_W_on; // tail in use (chosen by mg_autotune / mg_set_tile; off by default)
+    int fourier_W;               // level solved exactly by k_fourier_W in the W V-cycle (-1: none)
+    bool fourier_W_on;           // in use (on by default; mg_autotune / mg_set_tile may turn it off)
     void *pd0[kMaxLevels], *pd1[kMaxLevels], *pr[kMaxLevels], *pc[kMaxLevels];
     void *wd0[kMaxLevels], *wd1[kMaxLevels], *wr[kMaxLevels];
     double *part;
@@ -326,7 +329,21 @@ void init_geo(mg_ctx *c)
                 c->tail_W = l;
                 break;
             }
+    // exact bottom of the W V-cycle: the 16^3 level below the finest (FP32, periodic)
+    c->fourier_W = -1;
+    c->fourier_W_on = false;
+    if (c->momentum && c->f32 && c->p.bc == MG_BC_PERIODIC)
+        for (int l = 1; l < c->L; l++)
+            if (c->n[l] == kFourierN) {
+                c->fourier_W = l;
+                c->fourier_W_on = true;
+                break;
+            }
 }
+
+// Level l of the W V-cycle is solved by k_fourier_W (its float4 accesses need the
+// members of a batch 16-byte apart).
+bool fourier_at(const mg_ctx *c, int l) { return c->fourier_W_on && l == c->fourier_W && c->zs % 16 == 0; }
 
 
 // Records an event pair around the launches in its scope when (kernel, level)
@@ -738,8 +755,22 @@ void smooth_W(mg_ctx *c, int l, int sweeps, bool first_done = false)
 }
 
 template <typename T>
+void fourier_W(mg_ctx *c, int l, const T *r, T *x)
+{
+    if constexpr (sizeof(T) == sizeof(float)) {
+        Probe pr(c, MG_PROBE_COARSE, l);
+        hipLaunchKernelGGL(k_fourier_W, dim3(1, 1, c->gz), dim3(kFourierThreads), 0, c->s, c->geo[l], (const float *)r,
+                           (float *)x);
+    }
+}
+
+template <typename T>
 void vcycle_W(mg_ctx *c, int l, bool first_done = false)
 {
+    if (fourier_at(c, l)) {
+        fourier_W<T>(c, l, (const T *)c->wr[l], (T *)c->wd0[l]);
+        return;
+    }
     if (c->tail_W_on && l == c->tail_W) {
         Probe pr(c, MG_PROBE_COARSE, c->L - 1);
         hipLaunchKernelGGL(k_tail_W<T>, dim3(1, 1, c->gz), dim3(kTailThreads), 0, c->s, tail_args<T>(c, l, true));
@@ -752,7 +783,7 @@ void vcycle_W(mg_ctx *c, int l, bool first_done = false)
     if (!first_done) fill<T>(c->s, (T *)c->wd0[l], 3 * c->cells[l], T(0), c->gz, c->zs);
     smooth_W<T>(c, l, c->p.nu_pre, first_done);
     // the next level is smoothed by grid launches (not the coarsest, not a tail)
-    const bool next_first = l + 2 < c->L && !(c->tail_W_on && l + 1 == c->tail_W);
+    const bool next_first = l + 2 < c->L && !(c->tail_W_on && l + 1 == c->tail_W) && !fourier_at(c, l + 1);
     defect_restrict_W<T>(c, l, (const T *)c->wd0[l], (const T *)c->wr[l], (T *)c->wr[l + 1],
                          next_first ? (T *)c->wd1[l + 1] : nullptr);
     vcycle_W<T>(c, l + 1, next_first);
@@ -1309,6 +1340,12 @@ mg_status kernel_op(mg_ctx *c, int op, int l, int arg, const void *in, void *out
         if (!in || !out || !coarsest || !c->momentum) return MG_ERR_INVALID;
         coarse_W<T>(c, (const T *)in, (T *)out);
         break;
+    case MG_OP_FOURIER_W:
+        if (!in || !out || !c->f32 || c->p.bc != MG_BC_PERIODIC || c->n[l] != kFourierN ||
+            ((uintptr_t)in | (uintptr_t)out) % 16 != 0)
+            return MG_ERR_INVALID;
+        fourier_W<T>(c, l, (const T *)in, (T *)out);
+        break;
     default:
         return MG_ERR_INVALID;
     }
@@ -1385,10 +1422,12 @@ mg_status autotune(mg_ctx *c, const double *u, const double *W, int reps, mg_tun
     int k = 0;
     // V-cycle tails: one whole V-cycle (with the coefficient restriction it needs)
     // timed with the tail off and on
-    for (int family = MG_TUNE_TAIL_PSI; family <= MG_TUNE_TAIL_W && st == MG_OK; family++) {
-        const int start = family == MG_TUNE_TAIL_PSI ? c->tail_psi : c->tail_W;
+    // (the exact W bottom first: while it is on, the W tail below it never runs)
+    for (int family : {MG_TUNE_FOURIER_W, MG_TUNE_TAIL_PSI, MG_TUNE_TAIL_W}) {
+        if (st != MG_OK) break;
+        const int start = family == MG_TUNE_TAIL_PSI ? c->tail_psi : family == MG_TUNE_TAIL_W ? c->tail_W : c->fourier_W;
         if (start < 0) continue;
-        bool &on = family == MG_TUNE_TAIL_PSI ? c->tail_psi_on : c->tail_W_on;
+        bool &on = family == MG_TUNE_TAIL_PSI ? c->tail_psi_on : family == MG_TUNE_TAIL_W ? c->tail_W_on : c->fourier_W_on;
         mg_tune e;
         std::memset(&e, 0, sizeof(e));
         e.family = family;
@@ -2910,10 +2949,11 @@ mg_status mg_set_tile(mg_ctx *c, int32_t family, int32_t level, int32_t tx)
 {
     if (!c || level < 0 || level >= c->L) return MG_ERR_INVALID;
     c->cont_valid = false;
-    if (family == MG_TUNE_TAIL_PSI || family == MG_TUNE_TAIL_W) {
-        const int start = family == MG_TUNE_TAIL_PSI ? c->tail_psi : c->tail_W;
+    if (family == MG_TUNE_TAIL_PSI || family == MG_TUNE_TAIL_W || family == MG_TUNE_FOURIER_W) {
+        const int start = family == MG_TUNE_TAIL_PSI ? c->tail_psi : family == MG_TUNE_TAIL_W ? c->tail_W : c->fourier_W;
         if (start < 0 || level != start || (tx != 0 && tx != 1)) return MG_ERR_INVALID;
-        (family == MG_TUNE_TAIL_PSI ? c->tail_psi_on : c->tail_W_on) = tx != 0;
+        (family == MG_TUNE_TAIL_PSI ? c->tail_psi_on : family == MG_TUNE_TAIL_W ? c->tail_W_on : c->fourier_W_on) =
+            tx != 0;
         drop_graph(c);
         return MG_OK;
     }

@@ -25,7 +25,7 @@ FLAG_CONFORMAL_MATTER = 1
 FLAG_EAGER = 2
 FLAG_CTTK = 4
 OP_PASS_PSI, OP_PASS_W, OP_DEFECT_RESTRICT_PSI, OP_DEFECT_RESTRICT_W = 1, 2, 3, 4
-OP_PROLONG_ADD, OP_COARSE_PSI, OP_COARSE_W = 5, 6, 7
+OP_PROLONG_ADD, OP_COARSE_PSI, OP_COARSE_W, OP_FOURIER_W = 5, 6, 7, 8
 PROBE_NONE, PROBE_PASS_PSI, PROBE_PASS_W, PROBE_RESIDUAL = 0, 1, 2, 3
 PROBE_DEFECT_RESTRICT_PSI, PROBE_DEFECT_RESTRICT_W, PROBE_PROLONG = 4, 5, 6
 PROBE_COARSE, PROBE_UPDATE = 7, 8
@@ -49,7 +49,16 @@ class MgReport(C.Structure):
                 ("history_len", C.c_int32)]
 
 
-TUNE_PASS_PSI, TUNE_PASS_W, TUNE_RESIDUAL, TUNE_TAIL_PSI, TUNE_TAIL_W = 1, 2, 3, 4, 5
+TUNE_PASS_PSI, TUNE_PASS_W, TUNE_RESIDUAL, TUNE_TAIL_PSI, TUNE_TAIL_W, TUNE_FOURIER_W = 1, 2, 3, 4, 5, 6
+
+
+def fourier_level(p) -> int:
+    """Level of the W V-cycle solved exactly by discrete Fourier modes (the 16^3 level
+    below the finest of an FP32 periodic context that solves the momentum
+    constraint), or -1."""
+    if p.precision != PREC_FP32_IR or p.bc != BC_PERIODIC or not p.solve_momentum:
+        return -1
+    return next((l for l in range(1, p.levels) if p.n >> l == 16 and p.n % (1 << l) == 0), -1)
 
 
 class MgTune(C.Structure):

@@ -36,13 +36,19 @@ def test_every_candidate_gives_the_same_solve(precision, tmp_path):
     entries = s.autotune(torch.zeros((128,) * 3, dtype=torch.float64, device=dev()),
                          torch.zeros((3, 128, 128, 128), dtype=torch.float64, device=dev()), reps=10)
     fams = {e["family"] for e in entries}
-    assert fams == {g.TUNE_PASS_PSI, g.TUNE_PASS_W, g.TUNE_RESIDUAL, g.TUNE_TAIL_PSI, g.TUNE_TAIL_W}
-    # the tails change the grouping of restriction sums (results agree to rounding, not bitwise):
-    # keep them off while checking that every brick depth gives bitwise the same solve
+    expected = {g.TUNE_PASS_PSI, g.TUNE_PASS_W, g.TUNE_RESIDUAL, g.TUNE_TAIL_PSI, g.TUNE_TAIL_W}
+    if precision == g.PREC_FP32_IR:
+        expected.add(g.TUNE_FOURIER_W)  # the exact W bottom on the 16^3 level
+    assert fams == expected
+    # the tails change the grouping of restriction sums and the exact W bottom the
+    # V-cycle itself (results agree to rounding or to the tolerance, not bitwise): back to
+    # their defaults (tails off, exact bottom on) while checking that every brick depth
+    # gives bitwise the same solve
+    whole = (g.TUNE_TAIL_PSI, g.TUNE_TAIL_W, g.TUNE_FOURIER_W)
     for e in entries:
-        if e["family"] in (g.TUNE_TAIL_PSI, g.TUNE_TAIL_W):
-            s.set_tile(e["family"], e["level"], 0)
-    entries_tiles = [e for e in entries if e["family"] not in (g.TUNE_TAIL_PSI, g.TUNE_TAIL_W)]
+        if e["family"] in whole:
+            s.set_tile(e["family"], e["level"], 1 if e["family"] == g.TUNE_FOURIER_W else 0)
+    entries_tiles = [e for e in entries if e["family"] not in whole]
     for e in entries:
         print(f"family {e['family']} level {e['level']}: chosen {e['chosen']}, us {e['candidates']}")
         times = {k: v for k, v in e["candidates"].items() if v > 0}

@@ -282,6 +282,8 @@ def test_vcycle_tail_matches_separate_launches(case):
         else:
             r5, r1, S, p.K = g.scalar_field_sources(p, w.phi_modes, w.pi_modes, w.scalar_mass, dev())
         s = g.Solver(p, r5, r1, S if w.solve_momentum else None)
+        if g.fourier_level(s.p) >= 0:  # the W tail runs below the 16^3 level, not under its exact solve
+            s.set_tile(g.TUNE_FOURIER_W, g.fourier_level(s.p), 0)
         if not no_tail:
             # the tail's first level: the first from which the cells of all levels
             # down to the coarsest fit its LDS arrays (at most 4 levels)
