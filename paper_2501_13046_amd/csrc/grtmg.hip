@@ -118,8 +118,9 @@ struct mg_ctx {
     TileMap tileR;             // brick map of the finest-level residual
     int tail_psi, tail_W;      // first level of the workgroup-resident V-cycle tail (-1: not possible)
     bool tail_psi_on, tail_W_on; // tail in use (chosen by mg_autotune / mg_set_tile; off by default)
-    int fourier_W;               // level solved exactly by k_fourier_W in the W V-cycle (-1: none)
+    int fourier_W;               // level solved exactly by discrete Fourier modes in the W V-cycle (-1: none)
     bool fourier_W_on;           // in use (on by default; mg_autotune / mg_set_tile may turn it off)
+    float2 *specZ;               // complex buffer of that solve on 32^3 and 64^3 levels (3 n^3)
     void *pd0[kMaxLevels], *pd1[kMaxLevels], *pr[kMaxLevels], *pc[kMaxLevels];
     void *wd0[kMaxLevels], *wd1[kMaxLevels], *wr[kMaxLevels];
     double *part;
@@ -203,6 +204,17 @@ mg_status validate(const mg_params *p)
     return MG_OK;
 }
 
+// The level of the W V-cycle solved exactly by discrete Fourier modes: the first one
+// below the finest with 16, 32 or 64 cells per axis, in FP32 periodic contexts with
+// momentum; -1 if none.
+int spectral_level(const mg_ctx *c)
+{
+    if (!c->momentum || !c->f32 || c->p.bc != MG_BC_PERIODIC) return -1;
+    for (int l = 1; l < c->L; l++)
+        if (c->n[l] == 16 || c->n[l] == 32 || c->n[l] == 64) return l;
+    return -1;
+}
+
 // Lay out (or measure, when base is null) every device buffer of a context.
 void carve(mg_ctx *c, Carver &cv)
 {
@@ -225,6 +237,8 @@ void carve(mg_ctx *c, Carver &cv)
         }
         n /= 2;
     }
+    const int ls = spectral_level(c);
+    c->specZ = ls >= 0 && c->n[ls] > kFourierN ? (float2 *)cv.take(3 * c->cells[ls] * sizeof(float2)) : nullptr;
     const int64_t nb = nblk(c->cells[0]);
     c->part = (double *)cv.take((size_t)nb * 4 * sizeof(double));
     if (p.flags & MG_FLAG_CTTK) {
@@ -329,20 +343,13 @@ void init_geo(mg_ctx *c)
                 c->tail_W = l;
                 break;
             }
-    // exact bottom of the W V-cycle: the 16^3 level below the finest (FP32, periodic)
-    c->fourier_W = -1;
-    c->fourier_W_on = false;
-    if (c->momentum && c->f32 && c->p.bc == MG_BC_PERIODIC)
-        for (int l = 1; l < c->L; l++)
-            if (c->n[l] == kFourierN) {
-                c->fourier_W = l;
-                c->fourier_W_on = true;
-                break;
-            }
+    // exact bottom of the W V-cycle
+    c->fourier_W = spectral_level(c);
+    c->fourier_W_on = c->fourier_W >= 0;
 }
 
-// Level l of the W V-cycle is solved by k_fourier_W (its float4 accesses need the
-// members of a batch 16-byte apart).
+// Level l of the W V-cycle is solved by discrete Fourier modes (the float4 accesses
+// need the members of a batch 16-byte apart).
 bool fourier_at(const mg_ctx *c, int l) { return c->fourier_W_on && l == c->fourier_W && c->zs % 16 == 0; }
 
 
@@ -759,8 +766,23 @@ void fourier_W(mg_ctx *c, int l, const T *r, T *x)
 {
     if constexpr (sizeof(T) == sizeof(float)) {
         Probe pr(c, MG_PROBE_COARSE, l);
-        hipLaunchKernelGGL(k_fourier_W, dim3(1, 1, c->gz), dim3(kFourierThreads), 0, c->s, c->geo[l], (const float *)r,
-                           (float *)x);
+        const Geo &g = c->geo[l];
+        const float *rf = (const float *)r;
+        float *xf = (float *)x;
+        const int n = c->n[l];
+        if (n == kFourierN) {
+            hipLaunchKernelGGL(k_fourier_W, dim3(1, 1, c->gz), dim3(kFourierThreads), 0, c->s, g, rf, xf);
+        } else if (n == 32) {
+            hipLaunchKernelGGL(k_spec_fwd<32>, dim3(32, 1, c->gz), dim3(96), 0, c->s, g, rf, c->specZ);
+            hipLaunchKernelGGL(k_spec_solve<32>, dim3(32 * 32 / kSpecPencils, 1, c->gz), dim3(3 * kSpecPencils), 0,
+                               c->s, g, c->specZ);
+            hipLaunchKernelGGL(k_spec_inv<32>, dim3(32, 1, c->gz), dim3(96), 0, c->s, g, (const float2 *)c->specZ, xf);
+        } else {
+            hipLaunchKernelGGL(k_spec_fwd<64>, dim3(64, 1, c->gz), dim3(192), 0, c->s, g, rf, c->specZ);
+            hipLaunchKernelGGL(k_spec_solve<64>, dim3(64 * 64 / kSpecPencils, 1, c->gz), dim3(3 * kSpecPencils), 0,
+                               c->s, g, c->specZ);
+            hipLaunchKernelGGL(k_spec_inv<64>, dim3(64, 1, c->gz), dim3(192), 0, c->s, g, (const float2 *)c->specZ, xf);
+        }
     }
 }
 
@@ -1341,9 +1363,7 @@ mg_status kernel_op(mg_ctx *c, int op, int l, int arg, const void *in, void *out
         coarse_W<T>(c, (const T *)in, (T *)out);
         break;
     case MG_OP_FOURIER_W:
-        if (!in || !out || !c->f32 || c->p.bc != MG_BC_PERIODIC || c->n[l] != kFourierN ||
-            ((uintptr_t)in | (uintptr_t)out) % 16 != 0)
-            return MG_ERR_INVALID;
+        if (!in || !out || l != c->fourier_W || ((uintptr_t)in | (uintptr_t)out) % 16 != 0) return MG_ERR_INVALID;
         fourier_W<T>(c, l, (const T *)in, (T *)out);
         break;
     default:

@@ -1,8 +1,8 @@
-// mg_fourier.hpp -- exact solve of the momentum equation's defect equation on a small
-// periodic level inside one workgroup: the bottom of the W V-cycle of the FP32
-// contexts (Key features, "Fast").  Delta_L,h has constant coefficients on a periodic
-// grid, so each discrete Fourier mode of the three components decouples into a 3x3
-// system built from the stencils' symbols; with t_a = 2 pi k_a / N,
+// mg_fourier.hpp -- exact solve of the momentum equation's defect equation on a
+// coarse periodic level: the bottom of the W V-cycle of the FP32 contexts (Key
+// features, "Fast").  Delta_L,h has constant coefficients on a periodic grid, so each
+// discrete Fourier mode of the three components decouples into a 3x3 system built
+// from the stencils' symbols; with t_a = 2 pi k_a / N,
 //   D_aa -> lam_a = (-2 cos 2t_a + 32 cos t_a - 30) / (12 h^2)
 //   D_a  -> i s_a,   s_a = (8 sin t_a - sin 2t_a) / (6 h)
 //   (Delta_L)_aa = sum_c lam_c + lam_a / 3,   (Delta_L)_ab = -s_a s_b / 3  (a != b)
@@ -10,19 +10,42 @@
 // mode is set to 0: the result is the mean-free solution for r - mean(r), as the
 // coarsest-level inverse gives.
 //
-// Layout: the three components' N^3 complex values stay in LDS, each z row padded to
-// N + 1 entries so that rows read by neighbouring lanes start in different banks.  The
-// z transforms run on the way in from global memory and on the way out; the y and x
-// transforms are passes over LDS, one line of N points per thread, as a radix-2 FFT
-// in registers.
+// Line transforms of N points run in the registers of one thread (radix-2, decimation
+// in time, twiddles fixed at compile time).  Two forms:
+//  * N = 16: one workgroup per batch member holds all 3 N^3 complex values in LDS
+//    (z transforms on the way in from and out to global memory, y and x as LDS passes);
+//  * N = 32, 64: three launches over a complex buffer Z of 3 N^3 values: k_spec_fwd (one
+//    workgroup per x plane: z then y transforms), k_spec_solve (pencils along x: x
+//    transforms, the 3x3 solves, inverse x transforms), k_spec_inv (per x plane: inverse y
+//    then z transforms, real parts scaled by 1/N^3).
+// Every LDS row that neighbouring lanes read or write whole is padded to N + 1 entries so
+// that the rows start in different banks.
 #pragma once
 
 #include "mg_device.hpp"
 
 namespace grtmg {
 
-constexpr int kFourierN = 16;
-constexpr int kFourierThreads = 1024;
+// cos and sin of x in [0, pi] from their Taylor series (compile time only).
+__host__ __device__ constexpr double series_cos(double x)
+{
+    double term = 1.0, sum = 1.0;
+    for (int k = 1; k < 40; k++) {
+        term *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+        sum += term;
+    }
+    return sum;
+}
+__host__ __device__ constexpr double series_sin(double x)
+{
+    double term = x, sum = x;
+    for (int k = 1; k < 40; k++) {
+        term *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+        sum += term;
+    }
+    return sum;
+}
+constexpr double kTwoPi = 6.283185307179586476925286766559;
 
 __host__ __device__ constexpr int bit_reverse(int i, int bits)
 {
@@ -30,48 +53,96 @@ __host__ __device__ constexpr int bit_reverse(int i, int bits)
     for (int b = 0; b < bits; b++) r |= ((i >> b) & 1) << (bits - 1 - b);
     return r;
 }
+__host__ __device__ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 
-// In-place FFT of N = 16 complex values: v[k] <- sum_j v[j] exp(-+ 2 pi i jk / N)
-// (INV: the + sign, no scaling).  Radix 2, decimation in time.
-template <bool INV>
-__device__ __forceinline__ void fft16(float2 (&v)[kFourierN])
+// In-place FFT of N complex values in registers: v[k] <- sum_j v[j] exp(-+ 2 pi i jk / N)
+// (INV: the + sign; no scaling).
+template <int N, bool INV>
+__device__ __forceinline__ void fft_reg(float2 (&v)[N])
 {
-    constexpr int N = kFourierN, kBits = 4;
-    // cos and sin of 2 pi t / 16, t = 0 .. 7
-    constexpr float kC[8] = {1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f,
-                             0.0f, -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f};
-    constexpr float kS[8] = {0.0f, 0.38268343236508977f, 0.70710678118654752f, 0.92387953251128674f,
-                             1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f};
-#pragma unroll
-    for (int i = 0; i < N; i++) {
-        const int j = bit_reverse(i, kBits);
-        if (i < j) {
+    constexpr int B = ilog2(N);
+    static_assert((1 << B) == N, "power-of-two lines");
+    static_for<N>([&](auto ii) {
+        constexpr int i = decltype(ii)::value, j = bit_reverse(i, B);
+        if constexpr (i < j) {
             const float2 t = v[i];
             v[i] = v[j];
             v[j] = t;
         }
-    }
-#pragma unroll
-    for (int len = 2; len <= N; len <<= 1) {
-#pragma unroll
-        for (int st = 0; st < N; st += len) {
-#pragma unroll
-            for (int j = 0; j < len / 2; j++) {
-                const int t = j * (N / len);
-                const float2 a = v[st + j], b = v[st + j + len / 2];
-                float2 tb;
-                if (t == 0) {
-                    tb = b;
-                } else {
-                    const float wr = kC[t], wi = INV ? kS[t] : -kS[t];
-                    tb = make_float2(b.x * wr - b.y * wi, b.x * wi + b.y * wr);
-                }
-                v[st + j] = make_float2(a.x + tb.x, a.y + tb.y);
-                v[st + j + len / 2] = make_float2(a.x - tb.x, a.y - tb.y);
+    });
+    static_for<B>([&](auto ss) {
+        constexpr int half = 1 << decltype(ss)::value, len = 2 * half;
+        static_for<N / 2>([&](auto bb) {
+            constexpr int b = decltype(bb)::value, j = b % half, lo = (b / half) * len + j, hi = lo + half;
+            constexpr int t = j * (N / len); // twiddle exp(-+ 2 pi i t / N)
+            const float2 a = v[lo], x = v[hi];
+            float2 wx;
+            if constexpr (t == 0) {
+                wx = x;
+            } else if constexpr (4 * t == N) { // times -i (forward) or +i (inverse)
+                wx = INV ? make_float2(-x.y, x.x) : make_float2(x.y, -x.x);
+            } else {
+                constexpr float wr = (float)series_cos(kTwoPi * t / N);
+                constexpr float wi = (float)(INV ? series_sin(kTwoPi * t / N) : -series_sin(kTwoPi * t / N));
+                wx = make_float2(x.x * wr - x.y * wi, x.x * wi + x.y * wr);
             }
-        }
+            v[lo] = make_float2(a.x + wx.x, a.y + wx.y);
+            v[hi] = make_float2(a.x - wx.x, a.y - wx.y);
+        });
+    });
+}
+
+// Symbols of the second and first derivative stencils at t = 2 pi q / N.
+__device__ __forceinline__ void stencil_symbols(int q, int N, double h, float &lam, float &s)
+{
+    const double t = 2.0 * M_PI * q / N;
+    lam = (float)((-2.0 * cos(2.0 * t) + 32.0 * cos(t) - 30.0) / (12.0 * h * h));
+    s = (float)((8.0 * sin(t) - sin(2.0 * t)) / (6.0 * h));
+}
+
+// b <- (Delta_L symbol)^-1 b for one mode (the symmetric 3x3 system through its adjugate).
+__device__ __forceinline__ void mode_solve(float la, float lb, float lc, float sa, float sb, float sc, float2 &b0,
+                                           float2 &b1, float2 &b2)
+{
+    const float ls = la + lb + lc, third = 1.f / 3.f;
+    const float a00 = ls + la * third, a11 = ls + lb * third, a22 = ls + lc * third;
+    const float a01 = -sa * sb * third, a02 = -sa * sc * third, a12 = -sb * sc * third;
+    const float c00 = a11 * a22 - a12 * a12, c01 = a02 * a12 - a01 * a22, c02 = a01 * a12 - a02 * a11;
+    const float c11 = a00 * a22 - a02 * a02, c12 = a01 * a02 - a00 * a12, c22 = a00 * a11 - a01 * a01;
+    const float inv = 1.f / (a00 * c00 + a01 * c01 + a02 * c02);
+    const float2 x0 = b0, x1 = b1, x2 = b2;
+    b0 = make_float2((c00 * x0.x + c01 * x1.x + c02 * x2.x) * inv, (c00 * x0.y + c01 * x1.y + c02 * x2.y) * inv);
+    b1 = make_float2((c01 * x0.x + c11 * x1.x + c12 * x2.x) * inv, (c01 * x0.y + c11 * x1.y + c12 * x2.y) * inv);
+    b2 = make_float2((c02 * x0.x + c12 * x1.x + c22 * x2.x) * inv, (c02 * x0.y + c12 * x1.y + c22 * x2.y) * inv);
+}
+
+template <int N>
+__device__ __forceinline__ void load_real_row(const float *src, float2 (&v)[N])
+{
+    const float4 *s4 = reinterpret_cast<const float4 *>(src);
+#pragma unroll
+    for (int e = 0; e < N / 4; e++) {
+        const float4 q = s4[e];
+        v[4 * e] = make_float2(q.x, 0.f);
+        v[4 * e + 1] = make_float2(q.y, 0.f);
+        v[4 * e + 2] = make_float2(q.z, 0.f);
+        v[4 * e + 3] = make_float2(q.w, 0.f);
     }
 }
+
+template <int N>
+__device__ __forceinline__ void store_real_row(float *dst, const float2 (&v)[N], float scale)
+{
+    float4 *d4 = reinterpret_cast<float4 *>(dst);
+#pragma unroll
+    for (int e = 0; e < N / 4; e++)
+        d4[e] = make_float4(v[4 * e].x * scale, v[4 * e + 1].x * scale, v[4 * e + 2].x * scale, v[4 * e + 3].x * scale);
+}
+
+// ---- N = 16: one workgroup ---------------------------------------------------------------
+
+constexpr int kFourierN = 16;
+constexpr int kFourierThreads = 1024;
 
 // One pass of line transforms along y (AXIS = 1) or x (AXIS = 0) over the three
 // components in LDS (component stride P, cell (i, j, k) at (i N + j)(N + 1) + k).
@@ -87,7 +158,7 @@ __device__ __forceinline__ void fourier_pass_lds(float2 *F)
         float2 v[N];
 #pragma unroll
         for (int t = 0; t < N; t++) v[t] = F[base + t * stride];
-        fft16<INV>(v);
+        fft_reg<N, INV>(v);
 #pragma unroll
         for (int t = 0; t < N; t++) F[base + t * stride] = v[t];
     }
@@ -104,25 +175,13 @@ __global__ void __launch_bounds__(kFourierThreads) k_fourier_W(Geo g, const floa
     x = zsh(x, g.zs);
     __shared__ float2 F[3 * P];
     __shared__ float lam[N], sv[N];
-    if (threadIdx.x < N) {
-        const double t = 2.0 * M_PI * threadIdx.x / N;
-        lam[threadIdx.x] = (float)((-2.0 * cos(2.0 * t) + 32.0 * cos(t) - 30.0) / (12.0 * g.h * g.h));
-        sv[threadIdx.x] = (float)((8.0 * sin(t) - sin(2.0 * t)) / (6.0 * g.h));
-    }
+    if (threadIdx.x < N) stencil_symbols(threadIdx.x, N, g.h, lam[threadIdx.x], sv[threadIdx.x]);
     // z transforms of the rows of r, into LDS
     for (int L = threadIdx.x; L < 3 * N * N; L += kFourierThreads) {
         const int comp = L / (N * N), row = L % (N * N);
-        const float4 *src = reinterpret_cast<const float4 *>(r + (size_t)comp * M + (size_t)row * N);
         float2 v[N];
-#pragma unroll
-        for (int e = 0; e < N / 4; e++) {
-            const float4 q = src[e];
-            v[4 * e] = make_float2(q.x, 0.f);
-            v[4 * e + 1] = make_float2(q.y, 0.f);
-            v[4 * e + 2] = make_float2(q.z, 0.f);
-            v[4 * e + 3] = make_float2(q.w, 0.f);
-        }
-        fft16<false>(v);
+        load_real_row<N>(r + (size_t)comp * M + (size_t)row * N, v);
+        fft_reg<N, false>(v);
         float2 *dst = F + comp * P + row * R;
 #pragma unroll
         for (int t = 0; t < N; t++) dst[t] = v[t];
@@ -132,7 +191,6 @@ __global__ void __launch_bounds__(kFourierThreads) k_fourier_W(Geo g, const floa
     __syncthreads();
     fourier_pass_lds<0, false>(F);
     __syncthreads();
-    // every mode: the symmetric 3x3 symbol system, solved through its adjugate
     for (int q = threadIdx.x; q < M; q += kFourierThreads) {
         const int i = q / (N * N), j = (q / N) % N, k = q % N;
         const int o = (i * N + j) * R + k;
@@ -140,19 +198,7 @@ __global__ void __launch_bounds__(kFourierThreads) k_fourier_W(Geo g, const floa
             F[o] = F[P + o] = F[2 * P + o] = make_float2(0.f, 0.f);
             continue;
         }
-        const float la = lam[i], lb = lam[j], lc = lam[k], sa = sv[i], sb = sv[j], sc = sv[k];
-        const float ls = la + lb + lc, third = 1.f / 3.f;
-        const float a00 = ls + la * third, a11 = ls + lb * third, a22 = ls + lc * third;
-        const float a01 = -sa * sb * third, a02 = -sa * sc * third, a12 = -sb * sc * third;
-        const float c00 = a11 * a22 - a12 * a12, c01 = a02 * a12 - a01 * a22, c02 = a01 * a12 - a02 * a11;
-        const float c11 = a00 * a22 - a02 * a02, c12 = a01 * a02 - a00 * a12, c22 = a00 * a11 - a01 * a01;
-        const float inv = 1.f / (a00 * c00 + a01 * c01 + a02 * c02);
-        const float2 b0 = F[o], b1 = F[P + o], b2 = F[2 * P + o];
-        F[o] = make_float2((c00 * b0.x + c01 * b1.x + c02 * b2.x) * inv, (c00 * b0.y + c01 * b1.y + c02 * b2.y) * inv);
-        F[P + o] = make_float2((c01 * b0.x + c11 * b1.x + c12 * b2.x) * inv,
-                               (c01 * b0.y + c11 * b1.y + c12 * b2.y) * inv);
-        F[2 * P + o] = make_float2((c02 * b0.x + c12 * b1.x + c22 * b2.x) * inv,
-                                   (c02 * b0.y + c12 * b1.y + c22 * b2.y) * inv);
+        mode_solve(lam[i], lam[j], lam[k], sv[i], sv[j], sv[k], F[o], F[P + o], F[2 * P + o]);
     }
     __syncthreads();
     fourier_pass_lds<0, true>(F);
@@ -160,20 +206,101 @@ __global__ void __launch_bounds__(kFourierThreads) k_fourier_W(Geo g, const floa
     fourier_pass_lds<1, true>(F);
     __syncthreads();
     // inverse z transforms out of LDS; the real parts, scaled by 1/N^3, to x
-    constexpr float kScale = 1.f / (float)M;
     for (int L = threadIdx.x; L < 3 * N * N; L += kFourierThreads) {
         const int comp = L / (N * N), row = L % (N * N);
         const float2 *srcl = F + comp * P + row * R;
         float2 v[N];
 #pragma unroll
         for (int t = 0; t < N; t++) v[t] = srcl[t];
-        fft16<true>(v);
-        float4 *dst = reinterpret_cast<float4 *>(x + (size_t)comp * M + (size_t)row * N);
-#pragma unroll
-        for (int e = 0; e < N / 4; e++)
-            dst[e] = make_float4(v[4 * e].x * kScale, v[4 * e + 1].x * kScale, v[4 * e + 2].x * kScale,
-                                 v[4 * e + 3].x * kScale);
+        fft_reg<N, true>(v);
+        store_real_row<N>(x + (size_t)comp * M + (size_t)row * N, v, 1.f / (float)M);
     }
+}
+
+// ---- N = 32, 64: three launches over the complex buffer Z ---------------------------------
+
+constexpr int kSpecPencils = 32; // pencils along x per workgroup of k_spec_solve
+
+// One workgroup (3 N threads) per x plane i: z transforms of the plane's rows of r,
+// then y transforms of its columns, into Z (component-major, (i N + j) N + k).
+template <int N>
+__global__ void __launch_bounds__(3 * N) k_spec_fwd(Geo g, const float *__restrict__ r, float2 *__restrict__ Z)
+{
+    constexpr int R = N + 1, P = N * R, M = N * N * N;
+    r = zsh(r, g.zs);
+    Z = zsh(Z, g.zs);
+    __shared__ float2 S[3 * P];
+    const int i = blockIdx.x, comp = threadIdx.x / N, q = threadIdx.x % N;
+    float2 v[N];
+    load_real_row<N>(r + (size_t)comp * M + ((size_t)i * N + q) * N, v); // row j = q
+    fft_reg<N, false>(v);
+#pragma unroll
+    for (int k = 0; k < N; k++) S[comp * P + q * R + k] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < N; j++) v[j] = S[comp * P + j * R + q]; // column k = q
+    fft_reg<N, false>(v);
+#pragma unroll
+    for (int j = 0; j < N; j++) Z[(size_t)comp * M + ((size_t)i * N + j) * N + q] = v[j];
+}
+
+// One workgroup (3 kSpecPencils threads) per run of kSpecPencils pencils along x at
+// fixed j: x transforms, the 3x3 solve of every mode, inverse x transforms, in place.
+template <int N>
+__global__ void __launch_bounds__(3 * kSpecPencils) k_spec_solve(Geo g, float2 *__restrict__ Z)
+{
+    constexpr int KW = kSpecPencils, RW = KW + 1, P = N * RW, M = N * N * N;
+    Z = zsh(Z, g.zs);
+    __shared__ float2 Q[3 * P];
+    __shared__ float lam[N], sv[N];
+    const int j = blockIdx.x / (N / KW), k0 = (blockIdx.x % (N / KW)) * KW;
+    const int comp = threadIdx.x / KW, kk = threadIdx.x % KW;
+    for (int q = threadIdx.x; q < N; q += 3 * KW) stencil_symbols(q, N, g.h, lam[q], sv[q]);
+    float2 *line = Z + (size_t)comp * M + (size_t)j * N + k0 + kk;
+    float2 v[N];
+#pragma unroll
+    for (int i = 0; i < N; i++) v[i] = line[(size_t)i * N * N];
+    fft_reg<N, false>(v);
+#pragma unroll
+    for (int i = 0; i < N; i++) Q[comp * P + i * RW + kk] = v[i];
+    __syncthreads();
+    for (int q = threadIdx.x; q < N * KW; q += 3 * KW) {
+        const int i = q / KW, kq = q % KW, k = k0 + kq, o = i * RW + kq;
+        if (i == 0 && j == 0 && k == 0) {
+            Q[o] = Q[P + o] = Q[2 * P + o] = make_float2(0.f, 0.f);
+            continue;
+        }
+        mode_solve(lam[i], lam[j], lam[k], sv[i], sv[j], sv[k], Q[o], Q[P + o], Q[2 * P + o]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < N; i++) v[i] = Q[comp * P + i * RW + kk];
+    fft_reg<N, true>(v);
+#pragma unroll
+    for (int i = 0; i < N; i++) line[(size_t)i * N * N] = v[i];
+}
+
+// One workgroup (3 N threads) per x plane i: inverse y transforms of the plane's
+// columns of Z, then inverse z transforms of its rows; real parts / N^3 into x.
+template <int N>
+__global__ void __launch_bounds__(3 * N) k_spec_inv(Geo g, const float2 *__restrict__ Z, float *__restrict__ x)
+{
+    constexpr int R = N + 1, P = N * R, M = N * N * N;
+    Z = zsh(Z, g.zs);
+    x = zsh(x, g.zs);
+    __shared__ float2 S[3 * P];
+    const int i = blockIdx.x, comp = threadIdx.x / N, q = threadIdx.x % N;
+    float2 v[N];
+#pragma unroll
+    for (int j = 0; j < N; j++) v[j] = Z[(size_t)comp * M + ((size_t)i * N + j) * N + q]; // column k = q
+    fft_reg<N, true>(v);
+#pragma unroll
+    for (int j = 0; j < N; j++) S[comp * P + j * R + q] = v[j];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < N; k++) v[k] = S[comp * P + q * R + k]; // row j = q
+    fft_reg<N, true>(v);
+    store_real_row<N>(x + (size_t)comp * M + ((size_t)i * N + q) * N, v, 1.f / (float)M);
 }
 
 } // namespace grtmg

@@ -53,12 +53,12 @@ TUNE_PASS_PSI, TUNE_PASS_W, TUNE_RESIDUAL, TUNE_TAIL_PSI, TUNE_TAIL_W, TUNE_FOUR
 
 
 def fourier_level(p) -> int:
-    """Level of the W V-cycle solved exactly by discrete Fourier modes (the 16^3 level
-    below the finest of an FP32 periodic context that solves the momentum
-    constraint), or -1."""
+    """Level of the W V-cycle solved exactly by discrete Fourier modes (the first level
+    below the finest with 16, 32 or 64 cells per axis, in an FP32 periodic context that
+    solves the momentum constraint), or -1."""
     if p.precision != PREC_FP32_IR or p.bc != BC_PERIODIC or not p.solve_momentum:
         return -1
-    return next((l for l in range(1, p.levels) if p.n >> l == 16 and p.n % (1 << l) == 0), -1)
+    return next((l for l in range(1, p.levels) if p.n >> l in (16, 32, 64)), -1)
 
 
 class MgTune(C.Structure):

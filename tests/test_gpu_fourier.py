@@ -1,5 +1,5 @@
 """The exact bottom of the W V-cycle in FP32 contexts (Key features, "Fast"): the
-discrete-Fourier solve of Delta_L,h x = r - mean(r) on the 16^3 level against the
+discrete-Fourier solve of Delta_L,h x = r - mean(r) on a coarse level against the
 oracle's FFT solve of the same discrete operator (FP64, numpy's FFT) and against the
 oracle's own operator, and whole solves with the exact bottom on and off."""
 import numpy as np
@@ -22,16 +22,18 @@ def coupled_solver(n, levels, seed=2):
     return g.Solver(p, r5, r1, S), (r5, r1, S)
 
 
-@pytest.mark.parametrize("n,levels", [(64, 4), (32, 3)])
-def test_fourier_bottom_matches_oracle(n, levels):
+@pytest.mark.parametrize("n,levels,nf", [(128, 6, 64), (64, 4, 32), (32, 3, 16)])
+def test_fourier_bottom_matches_oracle(n, levels, nf):
+    """The exact bottom on the first level with 64, 32 or 16 cells per axis (three
+    launches over a complex buffer at 64^3 and 32^3, one workgroup at 16^3)."""
     s, _ = coupled_solver(n, levels)
     lf = g.fourier_level(s.p)
-    assert lf >= 1 and n >> lf == 16
-    h = s.p.length / 16
+    assert lf == 1 and n >> lf == nf
+    h = s.p.length / nf
     for seed in (40, 41):
-        r = synth.uniform_random(seed, (3, 16, 16, 16))
+        r = synth.uniform_random(seed, (3, nf, nf, nf))
         r[1] += 0.5  # a nonzero mean: the solve sees r - mean(r)
-        out = torch.full((3, 16, 16, 16), np.nan, dtype=torch.float32, device=dev())
+        out = torch.full((3, nf, nf, nf), np.nan, dtype=torch.float32, device=dev())
         s.kernel_op(g.OP_FOURIER_W, lf, 0, torch.from_numpy(r.astype(np.float32)).to(dev()), out)
         x = N(out).astype(np.float64)
         rf = r.astype(np.float32).astype(np.float64)  # the FP32 input the kernel saw
@@ -39,7 +41,7 @@ def test_fourier_bottom_matches_oracle(n, levels):
         ref = judge.fft_solve_W(f, h)
         assert rel_err(x, ref) < 2e-5
         # the oracle's Delta_L,h of the result gives back the mean-free right-hand side
-        po = oracle.params(16, 1, length=s.p.length, solve_momentum=True)
+        po = oracle.params(nf, 1, length=s.p.length, solve_momentum=True)
         assert rel_err(oracle.apply_deltaL(po, x), f) < 1e-3
         assert np.abs(x.mean(axis=(1, 2, 3))).max() < 1e-6 * np.abs(x).max()
 
