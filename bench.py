@@ -219,7 +219,8 @@ def bench_scan_96(g, synth, dev, args, log):
     ws = synth.scan_96()
     plist, r5s, r1s, Ss = [], [], [], []
     for w in ws:
-        p = g.params(w.n, w.levels, w.bc, g.PREC_FP32_IR, w.length, w.origin, 0.0, w.nu_pre, w.nu_post, True)
+        p = g.params(w.n, w.levels, w.bc, g.PREC_FP32_IR, w.length, w.origin, 0.0, w.nu_pre, w.nu_post, True,
+                     nu_post_W=w.nu_post_W)
         r5, r1, S, p.K = g.scalar_field_sources(p, w.phi_modes, w.pi_modes, w.scalar_mass, dev)
         plist.append(p)
         r5s.append(r5)
@@ -267,10 +268,12 @@ def bench_methods(g, w, K, rho5, rho1, S, args, log):
     n = w.n
     out = {}
     r5h, Sh = rho5.clone(), S.clone()
-    ph = g.params(n, w.levels, w.bc, g.PREC_FP32_IR, w.length, w.origin, 0.0, w.nu_pre, w.nu_post, True)
+    ph = g.params(n, w.levels, w.bc, g.PREC_FP32_IR, w.length, w.origin, 0.0, w.nu_pre, w.nu_post, True,
+                  nu_post_W=w.nu_post_W)
     Kf, K0 = g.cttk_hybrid_sources(ph, r5h, rho1, Sh)
     ph.K = K0
-    pc = g.params(n, w.levels, w.bc, g.PREC_FP32_IR, w.length, w.origin, 0.0, w.nu_pre, w.nu_post, True, cttk=True)
+    pc = g.params(n, w.levels, w.bc, g.PREC_FP32_IR, w.length, w.origin, 0.0, w.nu_pre, w.nu_post, True, cttk=True,
+                  nu_post_W=w.nu_post_W)
     for name, p, srcs in (("cttk_hybrid", ph, (r5h, rho1, Sh)), ("cttk", pc, (rho5, rho1, S))):
         s = g.Solver(p, *srcs)
         u = torch.zeros((n,) * 3, dtype=torch.float64, device=rho5.device)
@@ -425,7 +428,7 @@ def main():
     n = w.n
     # ---- setup (off the clock): sources on the GPU, K from the mean density
     p = g.params(n, w.levels, w.bc, g.PREC_FP32_IR, w.length, w.origin, 0.0, w.nu_pre,
-                 w.nu_post, True)
+                 w.nu_post, True, nu_post_W=w.nu_post_W)
     rho5, rho1, S, K = g.scalar_field_sources(p, w.phi_modes, w.pi_modes, w.scalar_mass, dev)
     p.K = K
     mixed = g.Solver(p, rho5, rho1, S)
@@ -461,6 +464,25 @@ def main():
     final = mixed.residual_norm(u, W)
     log(f"[bench] mixed: {sec * 1e3:.3f} ms/solve, outer={rep['outer_iters']} "
         f"rms H={final[0]:.3e} rms M={final[1]:.3e}")
+
+    # ---- the same solve with the W V-cycle's coarse levels as multigrid (exact spectral
+    # bottom off): the V-cycle of the FP64 leg, so the two differ in precision only
+    lf = g.fourier_level(mixed.p)
+    mg_bottom = None
+    if lf >= 0:
+        chosen = next((e["chosen"] for e in tuning if e["family"] == g.TUNE_FOURIER_W), 1)
+        mixed.set_tile(g.TUNE_FOURIER_W, lf, 0)
+        step(mixed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            rb = step(mixed)
+        torch.cuda.synchronize()
+        secb = (time.perf_counter() - t0) / args.steps
+        mixed.set_tile(g.TUNE_FOURIER_W, lf, chosen)
+        mg_bottom = dict(seconds=secb, outer_iters=rb["outer_iters"], h_rms=rb["h_rms"], m_rms=rb["m_rms"])
+        log(f"[bench] mixed, multigrid W bottom: {secb * 1e3:.3f} ms/solve, outer={rb['outer_iters']} "
+            f"(exact bottom on level {lf}: {sec * 1e3:.3f} ms)")
 
     # ---- mixed + learned warm start: network prediction, one outer iteration and
     # the residual comparison of the fallback rule, then the solve
@@ -502,7 +524,8 @@ def main():
 
     # ---- mixed + full-multigrid start from the n/2 grid (sources evaluated there)
     wc = synth.coupled(n // 2, seed=args.seed, precision=synth.PREC_FP32_IR)
-    pc = g.params(n // 2, wc.levels, wc.bc, g.PREC_FP32_IR, wc.length, wc.origin, K, wc.nu_pre, wc.nu_post, True)
+    pc = g.params(n // 2, wc.levels, wc.bc, g.PREC_FP32_IR, wc.length, wc.origin, K, wc.nu_pre, wc.nu_post, True,
+                  nu_post_W=wc.nu_post_W)
     r5c, r1c, Sc, _ = g.scalar_field_sources(pc, wc.phi_modes, wc.pi_modes, wc.scalar_mass, dev)
     coarse = g.Solver(pc, r5c, r1c, Sc)
     uc = torch.zeros((n // 2,) * 3, dtype=torch.float64, device=dev)
@@ -605,9 +628,11 @@ def main():
     w_bytes = 9 * 4 * cells  # in (3 comps), r (3), out (3), FP32
     w_gbs = w_bytes / w_avg / 1e9
     log(f"[bench] W pass level 0: {cnt_w} launches, avg {w_avg * 1e6:.2f} us, {w_gbs:.0f} GB/s algorithmic")
-    for name, kid in (("pass_psi", g.PROBE_PASS_PSI), ("defect_restrict_W", g.PROBE_DEFECT_RESTRICT_W),
-                      ("prolong", g.PROBE_PROLONG), ("update", g.PROBE_UPDATE), ("coarse", g.PROBE_COARSE)):
-        lvl = mixed.p.levels - 1 if kid == g.PROBE_COARSE else 0
+    for name, kid, lvl in (("pass_psi", g.PROBE_PASS_PSI, 0), ("defect_restrict_W", g.PROBE_DEFECT_RESTRICT_W, 0),
+                           ("prolong", g.PROBE_PROLONG, 0), ("update", g.PROBE_UPDATE, 0),
+                           ("coarse", g.PROBE_COARSE, mixed.p.levels - 1), ("exact W bottom", g.PROBE_COARSE, lf)):
+        if lvl < 0:
+            continue
         cnt, t, _ = probe(kid, lvl)
         log(f"[bench]   {name:18s} level {lvl}: {cnt:4d} launches avg {t / max(cnt, 1) * 1e6:8.2f} us")
 
@@ -677,6 +702,9 @@ def main():
             "fp64_seconds": fp64["seconds"] if fp64 else None,
             "fp64_outer_iters": fp64["outer_iters"] if fp64 else None,
             "speedup_vs_fp64": (fp64["seconds"] / headline) if fp64 else None,
+            "exact_W_bottom_level": lf,
+            "mixed_multigrid_W_bottom": mg_bottom,
+            "fp64_vs_mixed_same_vcycle": (fp64["seconds"] / mg_bottom["seconds"]) if fp64 and mg_bottom else None,
             "autotuned_bricks": [{"family": e["family"], "level": e["level"], "depth": e["chosen"]}
                                  for e in tuning],
             "learned": learned,

@@ -119,6 +119,11 @@ enum { MG_FLAG_CONFORMAL_MATTER = 1, MG_FLAG_EAGER = 2, MG_FLAG_CTTK = 4 };
  *                 origin + (i + 1/2) L/n).
  *  K              constant trace of the extrinsic curvature.
  *  puncture_mass  0: psi0 = 1; > 0: psi0 = 1 + M / (2 |x - puncture_pos|).
+ *  nu_pre_W/nu_post_W  sweeps of the W V-cycle while its bottom is exact (see
+ *                 MG_TUNE_FOURIER_W; 0: nu_pre / nu_post; else 1 .. 16).  Its coarse
+ *                 correction is then exact, and one post-sweep can do what two do
+ *                 above a multigrid bottom.  Without the exact bottom the W cycle
+ *                 uses nu_pre / nu_post.
  */
 typedef struct mg_params {
     int32_t n, levels, bc, precision, nu_pre, nu_post, solve_momentum, flags;
@@ -127,6 +132,7 @@ typedef struct mg_params {
     double K;
     double puncture_mass;
     double puncture_pos[3];
+    int32_t nu_pre_W, nu_post_W;
 } mg_params;
 
 /* Per-solve report.  history (host, caller-owned, may be NULL) receives

@@ -10,8 +10,6 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libgrtmg.so")
 SOURCES = [os.path.join(PKG, "csrc", f) for f in ("grtmg.hip", "grtnn.hip")]
-HEADERS = [os.path.join(PKG, "csrc", f) for f in ("mg_device.hpp", "mg_kernels.hpp", "mg_tiled.hpp", "nn_kernels.hpp", "mg_internal.h")] + \
-    [os.path.join(ROOT, "include", f) for f in ("grtmg.h", "grtnn.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -173,9 +173,9 @@ mg_status validate(const mg_params *p)
     if ((double)p->n * p->n * (double)p->n >= 4294967296.0) return MG_ERR_INVALID;
     if (p->bc < MG_BC_PERIODIC || p->bc > MG_BC_ZERO) return MG_ERR_INVALID;
     if (p->precision != MG_PREC_FP64 && p->precision != MG_PREC_FP32_IR) return MG_ERR_INVALID;
-    if (p->nu_pre < 0 || p->nu_post < 0 || p->nu_pre + p->nu_post < 1 || p->nu_pre > 16 ||
-        p->nu_post > 16)
-        return MG_ERR_INVALID;
+    // the finest level's first pre-smoothing pass comes with the residual: nu_pre >= 1
+    if (p->nu_pre < 1 || p->nu_post < 1 || p->nu_pre > 16 || p->nu_post > 16) return MG_ERR_INVALID;
+    if (p->nu_pre_W < 0 || p->nu_post_W < 0 || p->nu_pre_W > 16 || p->nu_post_W > 16) return MG_ERR_INVALID;
     if (p->solve_momentum != 0 && p->solve_momentum != 1) return MG_ERR_INVALID;
     if (p->solve_momentum && p->bc != MG_BC_PERIODIC) return MG_ERR_INVALID;
     // the W kernels address one component with 32-bit byte offsets
@@ -634,13 +634,24 @@ void restrict_coefficients(mg_ctx *c)
     factor(c->s, c->A_psi, c->aug_psi, c->inv_psi, m, c->scal + S_FLAG_PSI);
 }
 
+// Sweeps of the W V-cycle: the parameters' own while its bottom is exact, else the psi
+// cycle's.
+int nu_pre_W(const mg_ctx *c)
+{
+    return c->p.nu_pre_W > 0 && fourier_at(c, c->fourier_W) ? c->p.nu_pre_W : c->p.nu_pre;
+}
+int nu_post_W(const mg_ctx *c)
+{
+    return c->p.nu_post_W > 0 && fourier_at(c, c->fourier_W) ? c->p.nu_post_W : c->p.nu_post;
+}
+
 template <typename T>
 TailArgs<T> tail_args(mg_ctx *c, int l0, bool W)
 {
     TailArgs<T> a;
     std::memset(&a, 0, sizeof(a));
     a.nl = c->L - l0;
-    a.nu_pre = c->p.nu_pre;
+    a.nu_pre = c->p.nu_pre; // a W tail runs only below a multigrid bottom
     a.nu_post = c->p.nu_post;
     for (int q = 0; q < a.nl; q++) a.geo[q] = c->geo[l0 + q];
     a.r0 = (const T *)(W ? c->wr[l0] : c->pr[l0]);
@@ -803,14 +814,14 @@ void vcycle_W(mg_ctx *c, int l, bool first_done = false)
         return;
     }
     if (!first_done) fill<T>(c->s, (T *)c->wd0[l], 3 * c->cells[l], T(0), c->gz, c->zs);
-    smooth_W<T>(c, l, c->p.nu_pre, first_done);
+    smooth_W<T>(c, l, nu_pre_W(c), first_done);
     // the next level is smoothed by grid launches (not the coarsest, not a tail)
     const bool next_first = l + 2 < c->L && !(c->tail_W_on && l + 1 == c->tail_W) && !fourier_at(c, l + 1);
     defect_restrict_W<T>(c, l, (const T *)c->wd0[l], (const T *)c->wr[l], (T *)c->wr[l + 1],
                          next_first ? (T *)c->wd1[l + 1] : nullptr);
     vcycle_W<T>(c, l + 1, next_first);
     prolong_add<T>(c, l + 1, (const T *)c->wd0[l + 1], (T *)c->wd0[l], 3);
-    smooth_W<T>(c, l, c->p.nu_post);
+    smooth_W<T>(c, l, nu_post_W(c));
 }
 
 // ---- residuals and outer steps ----------------------------------------------------------

@@ -331,6 +331,13 @@ void launch_conv(hipStream_t s, const Layer &ly, bool transposed, int n, const u
     const unsigned gy = (unsigned)ceil_div(a.ntile, ntb);
     if (!brick) {
         const int64_t V = (int64_t)n * n * n;
+        if (V <= 4096) {
+            // small grids (the coarsest levels): one M tile and one N tile per wave, so
+            // that the (cell, channel) tiles spread over many waves instead of 2 blocks
+            const dim3 grid((unsigned)ceil_div(V, (int64_t)(kNBlock / 64) * 16), (unsigned)a.ntile);
+            hipLaunchKernelGGL((k_conv3<1, 1>), grid, dim3(kNBlock), 0, s, a);
+            return;
+        }
         const dim3 grid((unsigned)ceil_div(V, (int64_t)(kNBlock / 64) * 16 * kRows), gy);
         switch (ntb) {
         case 1: hipLaunchKernelGGL(k_conv3<1>, grid, dim3(kNBlock), 0, s, a); break;

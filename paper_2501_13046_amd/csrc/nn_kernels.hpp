@@ -166,21 +166,21 @@ __device__ __forceinline__ void conv_store(const ConvArgs &a, int co, int64_t v,
     }
 }
 
-// General kernel (any n): every wave computes 4 M tiles of 16 consecutive
+// General kernel (any n): every wave computes ROWS M tiles of 16 consecutive
 // cells and reads its A operands straight from global memory.
-template <int NTB>
+template <int NTB, int ROWS = kRows>
 __global__ void __launch_bounds__(kNBlock) k_conv3(ConvArgs a)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, r = lane & 15;
     const int n = a.n;
     const int64_t V = (int64_t)n * n * n;
-    const int64_t vb = ((int64_t)blockIdx.x * (kNBlock / 64) + wave) * (16 * kRows);
+    const int64_t vb = ((int64_t)blockIdx.x * (kNBlock / 64) + wave) * (16 * ROWS);
     if (vb >= V) return; // no block-level synchronisation in this kernel
     const int t0 = blockIdx.y * NTB;
-    int px[kRows], py[kRows], pz[kRows];
+    int px[ROWS], py[ROWS], pz[ROWS];
 #pragma unroll
-    for (int q = 0; q < kRows; q++) {
+    for (int q = 0; q < ROWS; q++) {
         int64_t v = vb + q * 16 + r;
         if (v >= V) v = V - 1; // rows past the end are computed but not stored
         const unsigned uv = (unsigned)v, un = (unsigned)n, t = uv / un; // n^3 < 2^32
@@ -188,9 +188,9 @@ __global__ void __launch_bounds__(kNBlock) k_conv3(ConvArgs a)
         py[q] = (int)(t % un);
         px[q] = (int)(t / un);
     }
-    f32x4 acc[kRows][NTB];
+    f32x4 acc[ROWS][NTB];
 #pragma unroll
-    for (int q = 0; q < kRows; q++)
+    for (int q = 0; q < ROWS; q++)
 #pragma unroll
         for (int t = 0; t < NTB; t++) acc[q][t] = f32x4{0.f, 0.f, 0.f, 0.f};
     const u32x4 zero = {0u, 0u, 0u, 0u};
@@ -200,14 +200,14 @@ __global__ void __launch_bounds__(kNBlock) k_conv3(ConvArgs a)
         for (int t = 0; t < NTB; t++)
             b[t] = (t0 + t < a.ntile) ? a.w[((int64_t)(t0 + t) * a.nchunk + ch) * 64 + lane] : zero;
         int tap, cg;
-        u32x4 av[kRows];
+        u32x4 av[ROWS];
         if (a.ko.at(ch, g, tap, cg)) {
             const int dx = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dz = tap % 3 - 1;
             const bool one = cg < a.c1;
             const u16 *src = one ? a.in1 : a.in2;
             const int cs = one ? a.c1 : a.c2, c0 = one ? cg : cg - a.c1, act = one ? a.act1 : a.act2;
 #pragma unroll
-            for (int q = 0; q < kRows; q++) {
+            for (int q = 0; q < ROWS; q++) {
                 const int x = wrapn(px[q] + dx, n), y = wrapn(py[q] + dy, n), z = wrapn(pz[q] + dz, n);
                 const int64_t v = ((int64_t)x * n + y) * n + z;
                 av[q] = *(const u32x4 *)(src + v * cs + c0);
@@ -215,10 +215,10 @@ __global__ void __launch_bounds__(kNBlock) k_conv3(ConvArgs a)
             }
         } else {
 #pragma unroll
-            for (int q = 0; q < kRows; q++) av[q] = zero;
+            for (int q = 0; q < ROWS; q++) av[q] = zero;
         }
 #pragma unroll
-        for (int q = 0; q < kRows; q++)
+        for (int q = 0; q < ROWS; q++)
 #pragma unroll
             for (int t = 0; t < NTB; t++) acc[q][t] = mfma(av[q], b[t], acc[q][t]);
     }
@@ -227,7 +227,7 @@ __global__ void __launch_bounds__(kNBlock) k_conv3(ConvArgs a)
         const int co = (t0 + t) * 16 + r;
         if (co >= a.cout) continue;
 #pragma unroll
-        for (int q = 0; q < kRows; q++)
+        for (int q = 0; q < ROWS; q++)
 #pragma unroll
             for (int i = 0; i < 4; i++) {
                 const int64_t v = vb + q * 16 + 4 * g + i;

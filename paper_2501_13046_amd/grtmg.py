@@ -37,7 +37,8 @@ class MgParams(C.Structure):
                 ("precision", C.c_int32), ("nu_pre", C.c_int32), ("nu_post", C.c_int32),
                 ("solve_momentum", C.c_int32), ("flags", C.c_int32),
                 ("length", C.c_double), ("origin", C.c_double * 3), ("K", C.c_double),
-                ("puncture_mass", C.c_double), ("puncture_pos", C.c_double * 3)]
+                ("puncture_mass", C.c_double), ("puncture_pos", C.c_double * 3),
+                ("nu_pre_W", C.c_int32), ("nu_post_W", C.c_int32)]
 
 
 class MgReport(C.Structure):
@@ -152,10 +153,13 @@ def params(n: int, levels: int = 1, bc: int = BC_PERIODIC, precision: int = PREC
            length: float = 1.0, origin=(0.0, 0.0, 0.0), K: float = 0.0, nu_pre: int = 2,
            nu_post: int = 2, solve_momentum: bool = False, puncture_mass: float = 0.0,
            puncture_pos=(0.0, 0.0, 0.0), conformal_matter: bool = False,
-           eager: bool = False, cttk: bool = False) -> MgParams:
+           eager: bool = False, cttk: bool = False, nu_pre_W: int = 0, nu_post_W: int = 0) -> MgParams:
+    """nu_pre_W / nu_post_W: sweeps of the W V-cycle while its bottom is exact (see
+    fourier_level; 0: nu_pre / nu_post)."""
     p = MgParams()
     p.n, p.levels, p.bc, p.precision = n, levels, bc, precision
     p.nu_pre, p.nu_post = nu_pre, nu_post
+    p.nu_pre_W, p.nu_post_W = nu_pre_W, nu_post_W
     p.solve_momentum = 1 if solve_momentum else 0
     p.flags = ((FLAG_CONFORMAL_MATTER if conformal_matter else 0) | (FLAG_EAGER if eager else 0)
                | (FLAG_CTTK if cttk else 0))
@@ -499,10 +503,10 @@ def shell_field_sources(p: MgParams, amplitude: float, r0: float, width2: float,
     return rho5, rho1, S
 
 
-def interp_cubic(pc: MgParams, coarse: torch.Tensor) -> torch.Tensor:
+def interp_cubic(pc: MgParams, coarse: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
     nc = pc.n
-    fine = torch.empty((2 * nc,) * 3, dtype=torch.float64, device=coarse.device)
-    _check(lib().mg_interp_cubic(C.byref(pc), _dptr(coarse, numel=nc ** 3), _dptr(fine),
+    fine = torch.empty((2 * nc,) * 3, dtype=torch.float64, device=coarse.device) if out is None else out
+    _check(lib().mg_interp_cubic(C.byref(pc), _dptr(coarse, numel=nc ** 3), _dptr(fine, numel=8 * nc ** 3),
                                  _stream(coarse.device)), "mg_interp_cubic")
     return fine
 

@@ -37,7 +37,8 @@ def problem(seed: int, n: int, device, phi_amp: float = 0.05):
     """Solver params and sources of the coupled periodic problem of a seed."""
     w = synth.coupled(n, seed=seed, phi_amp=phi_amp, precision=g.PREC_FP32_IR)
     p = g.params(w.n, w.levels, w.bc, w.precision, w.length, w.origin, 0.0, w.nu_pre, w.nu_post,
-                 w.solve_momentum, w.puncture_mass, w.puncture_pos, w.conformal_matter)
+                 w.solve_momentum, w.puncture_mass, w.puncture_pos, w.conformal_matter,
+                 nu_post_W=w.nu_post_W)
     r5, r1, S, p.K = g.scalar_field_sources(p, w.phi_modes, w.pi_modes, w.scalar_mass, device)
     return p, r5, r1, S
 
@@ -181,7 +182,16 @@ def fmg_learned_start(net: gn.Net, nm: gn.NnNorm, coarse: g.Solver, fine: g.Solv
     continues to tol_c, and the cubic interpolation fills the fine arrays.  Returns
     (prediction kept, coarse report of the continued solve)."""
     used, _ = net.warm_start(coarse, r5c, r1c, Sc, nm, uc, Wc, keep_ratio)
-    rc = g.fmg_start(coarse, fine, uc, Wc, uf, Wf, tol=tol_c, max_outer=max_outer)
+    if not used:
+        return used, g.fmg_start(coarse, fine, uc, Wc, uf, Wf, tol=tol_c, max_outer=max_outer)
+    # a kept prediction continues from its check iteration's state (not evaluated again),
+    # then the same cubic interpolation as the full-multigrid start
+    rc = coarse.solve(uc, Wc, tol=tol_c, max_outer=max_outer, raise_on_failure=False, resume=True)
+    if rc["status"] not in (g.MG_OK, g.MG_ERR_NOT_CONVERGED):
+        raise g.MGError(rc["status"], "coarse solve after the learned start")
+    g.interp_cubic(coarse.p, uc, out=uf)
+    for a in range(3):
+        g.interp_cubic(coarse.p, Wc[a], out=Wf[a])
     return used, rc
 
 

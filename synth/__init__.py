@@ -75,6 +75,9 @@ class Workload:
     solve_momentum: bool = False
     nu_pre: int = 2
     nu_post: int = 2
+    # W V-cycle sweeps while its bottom is exact (0: nu_pre / nu_post)
+    nu_pre_W: int = 0
+    nu_post_W: int = 0
     scalar_mass: float = 1.0
     phi_modes: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 5)))
     pi_modes: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 5)))
@@ -115,12 +118,13 @@ def coupled(n: int = 128, seed: int = 0, phi_amp: float = 0.05,
     rng_phi = np.random.default_rng(seed)
     rng_pi = np.random.default_rng([seed, 1])
     # V(1,2) cycles: of nu_pre, nu_post in 1..4 the fastest to rms 1e-10 at 128^3
-    # (17 outer iterations against 15 with V(2,2), each ~15% cheaper)
+    # (17 outer iterations against 15 with V(2,2), each ~15% cheaper); V(1,1) for W where
+    # its bottom is exact (the same 16 outer iterations at 128^3 as V(1,2), 8% faster)
     return Workload(name=f"coupled_{n}", n=n,
                     levels=levels if levels is not None else coarsest_levels(n),
                     seed=seed, phi_modes=fourier_modes(rng_phi, 8, phi_amp),
                     pi_modes=fourier_modes(rng_pi, 8, 0.02),
-                    precision=precision, solve_momentum=True, nu_pre=1, nu_post=2)
+                    precision=precision, solve_momentum=True, nu_pre=1, nu_post=2, nu_post_W=1)
 
 
 def coupled_128(seed: int = 0, precision: int = PREC_FP32_IR) -> Workload:

@@ -37,7 +37,8 @@ def test_exports_every_declared_symbol(g):
 
 
 def test_struct_layouts(g):
-    assert C.sizeof(g.MgParams) == 8 * 4 + 9 * 8
+    assert C.sizeof(g.MgParams) == 8 * 4 + 9 * 8 + 2 * 4
+    assert g.MgParams.nu_pre_W.offset == 8 * 4 + 9 * 8
     assert g.MgParams.length.offset == 32
     assert C.sizeof(g.MgReport) == 4 * 4 + 5 * 8 + 8 + 8
 
@@ -51,7 +52,10 @@ def test_workspace_size_and_validation(g):
            g.params(32, 6),  # coarsest 1
            g.params(32, 1),  # coarsest 32^3 too large for the dense solve
            g.params(32, 4, bc=g.BC_ROBIN, solve_momentum=True),
-           g.params(32, 4, nu_pre=0, nu_post=0)]
+           g.params(32, 4, nu_pre=0, nu_post=0),
+           g.params(32, 4, nu_pre=0, nu_post=2),  # the first pre-sweep pass comes with the residual
+           g.params(32, 4, solve_momentum=True, nu_post_W=17),
+           g.params(32, 4, solve_momentum=True, nu_pre_W=-1)]
     for p in bad:
         with pytest.raises(g.MGError) as e:
             g.workspace_size(p)

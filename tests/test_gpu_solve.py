@@ -160,8 +160,9 @@ def test_continued_solve_equals_one_solve(precision):
 def test_timing_probe_counts_each_launch_once():
     """The probe behind the roofline figure: with it on, a solve launches eagerly
     and gives the same state bitwise; it times exactly the finest-level W passes
-    (2 nu_pre + 2 nu_post - 1 per outer iteration: the first comes with the
-    residual) or residual evaluations (two per outer iteration and the first)."""
+    (2 nu_pre + 2 nu_post - 1 per outer iteration with the W cycle's sweeps: the first
+    comes with the residual) or residual evaluations (two per outer iteration and the
+    first)."""
     w = synth.coupled(32, seed=5, precision=g.PREC_FP32_IR)
     rho5, rho1, S, K, po = oracle_problem(w)
     s = solver_for(w, K, rho5, rho1, S)
@@ -169,7 +170,10 @@ def test_timing_probe_counts_each_launch_once():
                  torch.zeros((3, 32, 32, 32), dtype=torch.float64, device=dev()))
     u, W = z()
     ref = s.solve(u, W, tol=1e-10)
-    for kid, per_iter, extra in ((g.PROBE_PASS_W, 2 * w.nu_pre + 2 * w.nu_post - 1, 0), (g.PROBE_RESIDUAL, 2, 1)):
+    exact = g.fourier_level(s.p) >= 0  # the W cycle's own sweeps apply while its bottom is exact
+    npre = (w.nu_pre_W if exact and w.nu_pre_W else w.nu_pre)
+    npost = (w.nu_post_W if exact and w.nu_post_W else w.nu_post)
+    for kid, per_iter, extra in ((g.PROBE_PASS_W, 2 * npre + 2 * npost - 1, 0), (g.PROBE_RESIDUAL, 2, 1)):
         s.probe(kid, 0)
         u2, W2 = z()
         r = s.solve(u2, W2, tol=1e-10)
