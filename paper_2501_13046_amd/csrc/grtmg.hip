@@ -783,16 +783,18 @@ void fourier_W(mg_ctx *c, int l, const T *r, T *x)
         const int n = c->n[l];
         if (n == kFourierN) {
             hipLaunchKernelGGL(k_fourier_W, dim3(1, 1, c->gz), dim3(kFourierThreads), 0, c->s, g, rf, xf);
-        } else if (n == 32) {
-            hipLaunchKernelGGL(k_spec_fwd<32>, dim3(32, 1, c->gz), dim3(96), 0, c->s, g, rf, c->specZ);
-            hipLaunchKernelGGL(k_spec_solve<32>, dim3(32 * 32 / kSpecPencils, 1, c->gz), dim3(3 * kSpecPencils), 0,
+        } else if (n == 32) { // a quad of threads per line transform; x planes x components
+            hipLaunchKernelGGL(k_spec_fwd<32>, dim3(32, 3, c->gz), dim3(4 * 32), 0, c->s, g, rf, c->specZ);
+            hipLaunchKernelGGL(k_spec_solve<32>, dim3(32 * 32 / kSpecPencils, 1, c->gz), dim3(12 * kSpecPencils), 0,
                                c->s, g, c->specZ);
-            hipLaunchKernelGGL(k_spec_inv<32>, dim3(32, 1, c->gz), dim3(96), 0, c->s, g, (const float2 *)c->specZ, xf);
+            hipLaunchKernelGGL(k_spec_inv<32>, dim3(32, 3, c->gz), dim3(4 * 32), 0, c->s, g, (const float2 *)c->specZ,
+                               xf);
         } else {
-            hipLaunchKernelGGL(k_spec_fwd<64>, dim3(64, 1, c->gz), dim3(192), 0, c->s, g, rf, c->specZ);
-            hipLaunchKernelGGL(k_spec_solve<64>, dim3(64 * 64 / kSpecPencils, 1, c->gz), dim3(3 * kSpecPencils), 0,
+            hipLaunchKernelGGL(k_spec_fwd<64>, dim3(64, 3, c->gz), dim3(4 * 64), 0, c->s, g, rf, c->specZ);
+            hipLaunchKernelGGL(k_spec_solve<64>, dim3(64 * 64 / kSpecPencils, 1, c->gz), dim3(12 * kSpecPencils), 0,
                                c->s, g, c->specZ);
-            hipLaunchKernelGGL(k_spec_inv<64>, dim3(64, 1, c->gz), dim3(192), 0, c->s, g, (const float2 *)c->specZ, xf);
+            hipLaunchKernelGGL(k_spec_inv<64>, dim3(64, 3, c->gz), dim3(4 * 64), 0, c->s, g, (const float2 *)c->specZ,
+                               xf);
         }
     }
 }

@@ -10,14 +10,16 @@
 // mode is set to 0: the result is the mean-free solution for r - mean(r), as the
 // coarsest-level inverse gives.
 //
-// Line transforms of N points run in the registers of one thread (radix-2, decimation
-// in time, twiddles fixed at compile time).  Two forms:
+// Line transforms run in registers (radix 2, decimation in time, twiddles fixed at
+// compile time).  Two forms:
 //  * N = 16: one workgroup per batch member holds all 3 N^3 complex values in LDS
 //    (z transforms on the way in from and out to global memory, y and x as LDS passes);
 //  * N = 32, 64: three launches over a complex buffer Z of 3 N^3 values: k_spec_fwd (one
-//    workgroup per x plane: z then y transforms), k_spec_solve (pencils along x: x
-//    transforms, the 3x3 solves, inverse x transforms), k_spec_inv (per x plane: inverse y
-//    then z transforms, real parts scaled by 1/N^3).
+//    workgroup per x plane and component: z then y transforms), k_spec_solve (pencils along
+//    x, three components: x transforms, the 3x3 solves, inverse x transforms), k_spec_inv
+//    (per x plane and component: inverse y then z transforms, real parts scaled by 1/N^3);
+//    each line transform is shared by the four threads of a quad (below), and the launches
+//    hold 3 N or N^2 / 16 workgroups so that the work spreads over the chip.
 // Every LDS row that neighbouring lanes read or write whole is padded to N + 1 entries so
 // that the rows start in different banks.
 #pragma once
@@ -92,12 +94,29 @@ __device__ __forceinline__ void fft_reg(float2 (&v)[N])
     });
 }
 
-// Symbols of the second and first derivative stencils at t = 2 pi q / N.
+// cos and sin of 2 pi q / 64, q < 64, fixed at compile time (the unit circle of every
+// transform length that divides 64).
+struct UnitCircle64 {
+    double c[64], s[64];
+};
+constexpr UnitCircle64 make_unit_circle64()
+{
+    UnitCircle64 u{};
+    for (int q = 0; q < 64; q++) {
+        const int r = q <= 32 ? q : 64 - q; // angle reduced to [0, pi]
+        u.c[q] = series_cos(kTwoPi * r / 64);
+        u.s[q] = q <= 32 ? series_sin(kTwoPi * r / 64) : -series_sin(kTwoPi * r / 64);
+    }
+    return u;
+}
+__constant__ const UnitCircle64 kUnit64 = make_unit_circle64();
+
+// Symbols of the second and first derivative stencils at t = 2 pi q / N (N divides 64).
 __device__ __forceinline__ void stencil_symbols(int q, int N, double h, float &lam, float &s)
 {
-    const double t = 2.0 * M_PI * q / N;
-    lam = (float)((-2.0 * cos(2.0 * t) + 32.0 * cos(t) - 30.0) / (12.0 * h * h));
-    s = (float)((8.0 * sin(t) - sin(2.0 * t)) / (6.0 * h));
+    const int i1 = q * (64 / N), i2 = (2 * i1) & 63;
+    lam = (float)((-2.0 * kUnit64.c[i2] + 32.0 * kUnit64.c[i1] - 30.0) / (12.0 * h * h));
+    s = (float)((8.0 * kUnit64.s[i1] - kUnit64.s[i2]) / (6.0 * h));
 }
 
 // b <- (Delta_L symbol)^-1 b for one mode (the symmetric 3x3 system through its adjugate).
@@ -218,89 +237,181 @@ __global__ void __launch_bounds__(kFourierThreads) k_fourier_W(Geo g, const floa
 }
 
 // ---- N = 32, 64: three launches over the complex buffer Z ---------------------------------
+//
+// A line of N = 4Q points is shared by the four threads t of a quad (adjacent lanes): thread t
+// holds x[4m + t] (m < Q) and transforms it with Q points in registers (F_t); with
+// G_t[k1] = w^(t k1) F_t[k1], w = exp(-+ 2 pi i / N), the outputs are the 4-point transforms
+// X[k1 + Q k2] = sum_t (-+i)^(t k2) G_t[k1] (k2 < 4), formed after an exchange of the G through
+// the line's N slots in LDS: thread t takes k1 = E t .. E t + E - 1 (E = Q / 4).  Each thread
+// runs a quarter of the line's arithmetic, so a transform's latency is a quarter of one thread's.
 
-constexpr int kSpecPencils = 32; // pencils along x per workgroup of k_spec_solve
+constexpr int kSpecPencils = 16; // pencils along x per workgroup of k_spec_solve
 
-// One workgroup (3 N threads) per x plane i: z transforms of the plane's rows of r,
-// then y transforms of its columns, into Z (component-major, (i N + j) N + k).
-template <int N>
-__global__ void __launch_bounds__(3 * N) k_spec_fwd(Geo g, const float *__restrict__ r, float2 *__restrict__ Z)
+// tw[q] = exp(-2 pi i q / N), q < N (the inverse takes the conjugate).
+__device__ __forceinline__ float2 spec_twiddle(int q, int N)
 {
-    constexpr int R = N + 1, P = N * R, M = N * N * N;
-    r = zsh(r, g.zs);
-    Z = zsh(Z, g.zs);
-    __shared__ float2 S[3 * P];
-    const int i = blockIdx.x, comp = threadIdx.x / N, q = threadIdx.x % N;
-    float2 v[N];
-    load_real_row<N>(r + (size_t)comp * M + ((size_t)i * N + q) * N, v); // row j = q
-    fft_reg<N, false>(v);
-#pragma unroll
-    for (int k = 0; k < N; k++) S[comp * P + q * R + k] = v[k];
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < N; j++) v[j] = S[comp * P + j * R + q]; // column k = q
-    fft_reg<N, false>(v);
-#pragma unroll
-    for (int j = 0; j < N; j++) Z[(size_t)comp * M + ((size_t)i * N + j) * N + q] = v[j];
+    const int i = q * (64 / N);
+    return make_float2((float)kUnit64.c[i], (float)-kUnit64.s[i]);
 }
 
-// One workgroup (3 kSpecPencils threads) per run of kSpecPencils pencils along x at
-// fixed j: x transforms, the 3x3 solve of every mode, inverse x transforms, in place.
-template <int N>
-__global__ void __launch_bounds__(3 * kSpecPencils) k_spec_solve(Geo g, float2 *__restrict__ Z)
+// The quad transform above.  In: v[m] = x[4m + t].  Out: v[k2 E + e] = X[E t + e + Q k2].
+// xch: the line's N slots in LDS (stride xs), used by this quad alone; every thread of the
+// block calls this equally often (two barriers).
+template <int N, bool INV>
+__device__ __forceinline__ void fft_quad(float2 (&v)[N / 4], int t, float2 *xch, int xs, const float2 *tw)
 {
-    constexpr int KW = kSpecPencils, RW = KW + 1, P = N * RW, M = N * N * N;
+    constexpr int Q = N / 4, E = Q / 4;
+    fft_reg<Q, INV>(v);
+#pragma unroll
+    for (int k1 = 0; k1 < Q; k1++) {
+        float2 w = tw[t * k1];
+        if (INV) w.y = -w.y;
+        const float2 a = v[k1];
+        xch[(t * Q + k1) * xs] = make_float2(a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x);
+    }
+    __syncthreads();
+    float2 gq[E][4];
+#pragma unroll
+    for (int e = 0; e < E; e++)
+#pragma unroll
+        for (int u = 0; u < 4; u++) gq[e][u] = xch[(u * Q + E * t + e) * xs];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+        const float2 a0 = gq[e][0], a1 = gq[e][1], a2 = gq[e][2], a3 = gq[e][3];
+        const float2 s02 = make_float2(a0.x + a2.x, a0.y + a2.y), d02 = make_float2(a0.x - a2.x, a0.y - a2.y);
+        const float2 s13 = make_float2(a1.x + a3.x, a1.y + a3.y), d13 = make_float2(a1.x - a3.x, a1.y - a3.y);
+        // -i d13 (forward) or +i d13 (inverse)
+        const float2 jd = INV ? make_float2(-d13.y, d13.x) : make_float2(d13.y, -d13.x);
+        v[e] = make_float2(s02.x + s13.x, s02.y + s13.y);
+        v[E + e] = make_float2(d02.x + jd.x, d02.y + jd.y);
+        v[2 * E + e] = make_float2(s02.x - s13.x, s02.y - s13.y);
+        v[3 * E + e] = make_float2(d02.x - jd.x, d02.y - jd.y);
+    }
+}
+
+// One workgroup (4 N threads: a quad per line) per x plane i and component (blockIdx.y): z
+// transforms of the plane's rows of r, then y transforms of its columns, into Z
+// (component-major, (i N + j) N + k).
+template <int N>
+__global__ void __launch_bounds__(4 * N) k_spec_fwd(Geo g, const float *__restrict__ r, float2 *__restrict__ Z)
+{
+    constexpr int Q = N / 4, E = Q / 4, R = N + 1, M = N * N * N;
+    r = zsh(r, g.zs);
     Z = zsh(Z, g.zs);
-    __shared__ float2 Q[3 * P];
+    __shared__ float2 S[N * R];
+    __shared__ float2 tw[N];
+    const int i = blockIdx.x, comp = blockIdx.y, tid = threadIdx.x;
+    const int t = tid & 3, line = tid >> 2;
+    if (tid < N) tw[tid] = spec_twiddle(tid, N);
+    float2 v[Q];
+    const float *row = r + (size_t)comp * M + ((size_t)i * N + line) * N; // row j = line
+#pragma unroll
+    for (int m = 0; m < Q; m++) v[m] = make_float2(row[4 * m + t], 0.f);
+    __syncthreads();
+    float2 *Sr = S + line * R;
+    fft_quad<N, false>(v, t, Sr, 1, tw);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; k2++)
+#pragma unroll
+        for (int e = 0; e < E; e++) Sr[E * t + e + Q * k2] = v[k2 * E + e];
+    __syncthreads();
+    float2 *Sc = S + line; // column k = line
+#pragma unroll
+    for (int m = 0; m < Q; m++) v[m] = Sc[(4 * m + t) * R];
+    __syncthreads();
+    fft_quad<N, false>(v, t, Sc, R, tw);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; k2++)
+#pragma unroll
+        for (int e = 0; e < E; e++) {
+            const int j = E * t + e + Q * k2;
+            Z[(size_t)comp * M + ((size_t)i * N + j) * N + line] = v[k2 * E + e];
+        }
+}
+
+// One workgroup (12 kSpecPencils threads) per run of kSpecPencils pencils along x at fixed j:
+// x transforms, the 3x3 solve of every mode, inverse x transforms, in place.
+template <int N>
+__global__ void __launch_bounds__(12 * kSpecPencils) k_spec_solve(Geo g, float2 *__restrict__ Z)
+{
+    constexpr int KW = kSpecPencils, RW = KW + 1, P = N * RW, Q = N / 4, E = Q / 4, M = N * N * N;
+    Z = zsh(Z, g.zs);
+    __shared__ float2 QB[3 * P];
+    __shared__ float2 tw[N];
     __shared__ float lam[N], sv[N];
     const int j = blockIdx.x / (N / KW), k0 = (blockIdx.x % (N / KW)) * KW;
-    const int comp = threadIdx.x / KW, kk = threadIdx.x % KW;
-    for (int q = threadIdx.x; q < N; q += 3 * KW) stencil_symbols(q, N, g.h, lam[q], sv[q]);
-    float2 *line = Z + (size_t)comp * M + (size_t)j * N + k0 + kk;
-    float2 v[N];
+    const int tid = threadIdx.x, t = tid & 3, kk = (tid >> 2) % KW, comp = tid / (4 * KW);
+    if (tid < N) {
+        tw[tid] = spec_twiddle(tid, N);
+        stencil_symbols(tid, N, g.h, lam[tid], sv[tid]);
+    }
+    float2 *line = Z + (size_t)comp * M + (size_t)j * N + k0 + kk; // x stride N^2
+    float2 v[Q];
 #pragma unroll
-    for (int i = 0; i < N; i++) v[i] = line[(size_t)i * N * N];
-    fft_reg<N, false>(v);
-#pragma unroll
-    for (int i = 0; i < N; i++) Q[comp * P + i * RW + kk] = v[i];
+    for (int m = 0; m < Q; m++) v[m] = line[(size_t)(4 * m + t) * N * N];
     __syncthreads();
-    for (int q = threadIdx.x; q < N * KW; q += 3 * KW) {
-        const int i = q / KW, kq = q % KW, k = k0 + kq, o = i * RW + kq;
-        if (i == 0 && j == 0 && k == 0) {
-            Q[o] = Q[P + o] = Q[2 * P + o] = make_float2(0.f, 0.f);
+    float2 *xq = QB + comp * P + kk; // the pencil's slots, stride RW
+    fft_quad<N, false>(v, t, xq, RW, tw);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; k2++)
+#pragma unroll
+        for (int e = 0; e < E; e++) xq[(E * t + e + Q * k2) * RW] = v[k2 * E + e];
+    __syncthreads();
+    for (int q = tid; q < N * KW; q += 12 * KW) {
+        const int ix = q / KW, kq = q % KW, k = k0 + kq, o = ix * RW + kq;
+        if (ix == 0 && j == 0 && k == 0) {
+            QB[o] = QB[P + o] = QB[2 * P + o] = make_float2(0.f, 0.f);
             continue;
         }
-        mode_solve(lam[i], lam[j], lam[k], sv[i], sv[j], sv[k], Q[o], Q[P + o], Q[2 * P + o]);
+        mode_solve(lam[ix], lam[j], lam[k], sv[ix], sv[j], sv[k], QB[o], QB[P + o], QB[2 * P + o]);
     }
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < N; i++) v[i] = Q[comp * P + i * RW + kk];
-    fft_reg<N, true>(v);
+    for (int m = 0; m < Q; m++) v[m] = xq[(4 * m + t) * RW];
+    __syncthreads();
+    fft_quad<N, true>(v, t, xq, RW, tw);
 #pragma unroll
-    for (int i = 0; i < N; i++) line[(size_t)i * N * N] = v[i];
+    for (int k2 = 0; k2 < 4; k2++)
+#pragma unroll
+        for (int e = 0; e < E; e++) line[(size_t)(E * t + e + Q * k2) * N * N] = v[k2 * E + e];
 }
 
-// One workgroup (3 N threads) per x plane i: inverse y transforms of the plane's
-// columns of Z, then inverse z transforms of its rows; real parts / N^3 into x.
+// One workgroup (4 N threads) per x plane i and component: inverse y transforms of the
+// plane's columns of Z, then inverse z transforms of its rows; real parts / N^3 into x.
 template <int N>
-__global__ void __launch_bounds__(3 * N) k_spec_inv(Geo g, const float2 *__restrict__ Z, float *__restrict__ x)
+__global__ void __launch_bounds__(4 * N) k_spec_inv(Geo g, const float2 *__restrict__ Z, float *__restrict__ x)
 {
-    constexpr int R = N + 1, P = N * R, M = N * N * N;
+    constexpr int Q = N / 4, E = Q / 4, R = N + 1, M = N * N * N;
     Z = zsh(Z, g.zs);
     x = zsh(x, g.zs);
-    __shared__ float2 S[3 * P];
-    const int i = blockIdx.x, comp = threadIdx.x / N, q = threadIdx.x % N;
-    float2 v[N];
+    __shared__ float2 S[N * R];
+    __shared__ float2 tw[N];
+    const int i = blockIdx.x, comp = blockIdx.y, tid = threadIdx.x;
+    const int t = tid & 3, line = tid >> 2;
+    if (tid < N) tw[tid] = spec_twiddle(tid, N);
+    float2 v[Q];
 #pragma unroll
-    for (int j = 0; j < N; j++) v[j] = Z[(size_t)comp * M + ((size_t)i * N + j) * N + q]; // column k = q
-    fft_reg<N, true>(v);
-#pragma unroll
-    for (int j = 0; j < N; j++) S[comp * P + j * R + q] = v[j];
+    for (int m = 0; m < Q; m++) v[m] = Z[(size_t)comp * M + ((size_t)i * N + 4 * m + t) * N + line]; // column k = line
     __syncthreads();
+    float2 *Sc = S + line;
+    fft_quad<N, true>(v, t, Sc, R, tw);
 #pragma unroll
-    for (int k = 0; k < N; k++) v[k] = S[comp * P + q * R + k]; // row j = q
-    fft_reg<N, true>(v);
-    store_real_row<N>(x + (size_t)comp * M + ((size_t)i * N + q) * N, v, 1.f / (float)M);
+    for (int k2 = 0; k2 < 4; k2++)
+#pragma unroll
+        for (int e = 0; e < E; e++) Sc[(E * t + e + Q * k2) * R] = v[k2 * E + e];
+    __syncthreads();
+    float2 *Sr = S + line * R; // row j = line
+#pragma unroll
+    for (int m = 0; m < Q; m++) v[m] = Sr[4 * m + t];
+    __syncthreads();
+    fft_quad<N, true>(v, t, Sr, 1, tw);
+    constexpr float kScale = 1.f / (float)M;
+    float *row = x + (size_t)comp * M + ((size_t)i * N + line) * N;
+#pragma unroll
+    for (int k2 = 0; k2 < 4; k2++)
+#pragma unroll
+        for (int e = 0; e < E; e++) row[E * t + e + Q * k2] = v[k2 * E + e].x * kScale;
 }
 
 } // namespace grtmg
