@@ -431,8 +431,12 @@ mg_status mg_fmg_start(mg_ctx *cc, mg_ctx *cf, double *d_uc, double *d_Wc, doubl
  * differently, so results agree to rounding).  The tail starts at the first
  * level from which the cells of all levels down to the coarsest sum to at
  * most 4680 (psi, FP32, periodic) or 1971 (psi otherwise; W), spanning at
- * most 4 levels (e.g. 16^3 for psi and 8^3 for W, FP32 periodic).  Their `level`
- * is the tail's first level; mg_autotune times one whole V-cycle each way.
+ * most 4 levels (e.g. 16^3 for psi and 8^3 for W, FP32 periodic), or from any
+ * level below it down to the one above the coarsest.  Their `level` is the tail's
+ * first level: mg_autotune times one whole V-cycle with the tail off and starting
+ * at each such level and reports the fastest start (chosen 1) or the fastest
+ * start tried (chosen 0, the tail off); mg_set_tile(family, level, 1) starts the
+ * tail at `level`, (family, level, 0) turns it off.
  * MG_TUNE_FOURIER_W (FP32 periodic contexts with momentum whose levels include a
  * 16^3 one below the finest; `level` is that level): the W V-cycle solves that
  * level exactly by discrete Fourier modes in one workgroup (1, the default) or

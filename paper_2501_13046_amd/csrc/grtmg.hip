@@ -117,6 +117,7 @@ struct mg_ctx {
     TileMap tileW[kMaxLevels]; // brick map of the W smoother per level
     TileMap tileR;             // brick map of the finest-level residual
     int tail_psi, tail_W;      // first level of the workgroup-resident V-cycle tail (-1: not possible)
+    int tail_psi_min, tail_W_min; // the highest level a tail can start from (its arrays fit in LDS)
     bool tail_psi_on, tail_W_on; // tail in use (chosen by mg_autotune / mg_set_tile; off by default)
     int fourier_W;               // level solved exactly by discrete Fourier modes in the W V-cycle (-1: none)
     bool fourier_W_on;           // in use (on by default; mg_autotune / mg_set_tile may turn it off)
@@ -343,6 +344,8 @@ void init_geo(mg_ctx *c)
                 c->tail_W = l;
                 break;
             }
+    c->tail_psi_min = c->tail_psi;
+    c->tail_W_min = c->tail_W;
     // exact bottom of the W V-cycle
     c->fourier_W = spectral_level(c);
     c->fourier_W_on = c->fourier_W >= 0;
@@ -1456,21 +1459,32 @@ mg_status autotune(mg_ctx *c, const double *u, const double *W, int reps, mg_tun
     // V-cycle tails: one whole V-cycle (with the coefficient restriction it needs)
     // timed with the tail off and on
     // (the exact W bottom first: while it is on, the W tail below it never runs)
+    // A tail is timed off and starting at every level from the highest that fits down to
+    // the one above the coarsest; the entry reports the fastest start as its level.
     for (int family : {MG_TUNE_FOURIER_W, MG_TUNE_TAIL_PSI, MG_TUNE_TAIL_W}) {
         if (st != MG_OK) break;
-        const int start = family == MG_TUNE_TAIL_PSI ? c->tail_psi : family == MG_TUNE_TAIL_W ? c->tail_W : c->fourier_W;
-        if (start < 0) continue;
+        const bool tail = family != MG_TUNE_FOURIER_W;
+        const int first = family == MG_TUNE_TAIL_PSI ? c->tail_psi_min
+                          : family == MG_TUNE_TAIL_W ? c->tail_W_min
+                                                     : c->fourier_W;
+        if (first < 0) continue;
         bool &on = family == MG_TUNE_TAIL_PSI ? c->tail_psi_on : family == MG_TUNE_TAIL_W ? c->tail_W_on : c->fourier_W_on;
+        int &start = family == MG_TUNE_TAIL_PSI ? c->tail_psi : family == MG_TUNE_TAIL_W ? c->tail_W : c->fourier_W;
         mg_tune e;
         std::memset(&e, 0, sizeof(e));
         e.family = family;
         e.level = start;
         e.ncand = 2;
+        e.us[1] = 1e300;
         double best = 1e300;
         bool best_on = on;
-        for (int q = 0; q < 2 && st == MG_OK; q++) {
-            e.cand[q] = kCandTail[q];
-            on = kCandTail[q] != 0;
+        int best_start = start;
+        const int last = tail ? c->L - 2 : first;
+        for (int q = 0; q < 2 + (last - first) && st == MG_OK; q++) {
+            const int cq = q == 0 ? 0 : 1;
+            e.cand[cq] = kCandTail[cq];
+            on = cq != 0;
+            if (q > 0) start = first + (q - 1);
             auto cycle = [&]() {
                 if (family == MG_TUNE_TAIL_PSI) {
                     restrict_coefficients<T>(c);
@@ -1487,14 +1501,22 @@ mg_status autotune(mg_ctx *c, const double *u, const double *W, int reps, mg_tun
                                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
                 st = MG_ERR_HIP;
             if (st != MG_OK) break;
-            e.us[q] = 1e3 * ms / reps;
-            if (e.us[q] < best) {
-                best = e.us[q];
+            const double us = 1e3 * ms / reps;
+            if (q == 0 || us < e.us[1]) {
+                e.us[cq] = us;
+                if (q > 0) e.level = start;
+            }
+            if (us < best) {
+                best = us;
                 best_on = on;
-                e.chosen = kCandTail[q];
+                best_start = start;
+                e.chosen = kCandTail[cq];
             }
         }
         on = best_on;
+        start = best_start;
+        if (!best_on && tail) start = first;
+        if (best_on) e.level = best_start;
         if (out && k < cap) out[k] = e;
         k++;
     }
@@ -2982,11 +3004,18 @@ mg_status mg_set_tile(mg_ctx *c, int32_t family, int32_t level, int32_t tx)
 {
     if (!c || level < 0 || level >= c->L) return MG_ERR_INVALID;
     c->cont_valid = false;
-    if (family == MG_TUNE_TAIL_PSI || family == MG_TUNE_TAIL_W || family == MG_TUNE_FOURIER_W) {
-        const int start = family == MG_TUNE_TAIL_PSI ? c->tail_psi : family == MG_TUNE_TAIL_W ? c->tail_W : c->fourier_W;
-        if (start < 0 || level != start || (tx != 0 && tx != 1)) return MG_ERR_INVALID;
-        (family == MG_TUNE_TAIL_PSI ? c->tail_psi_on : family == MG_TUNE_TAIL_W ? c->tail_W_on : c->fourier_W_on) =
-            tx != 0;
+    if (family == MG_TUNE_FOURIER_W) {
+        if (c->fourier_W < 0 || level != c->fourier_W || (tx != 0 && tx != 1)) return MG_ERR_INVALID;
+        c->fourier_W_on = tx != 0;
+        drop_graph(c);
+        return MG_OK;
+    }
+    if (family == MG_TUNE_TAIL_PSI || family == MG_TUNE_TAIL_W) {
+        // a tail may start at any level from the highest that fits down to the one above the coarsest
+        const int first = family == MG_TUNE_TAIL_PSI ? c->tail_psi_min : c->tail_W_min;
+        if (first < 0 || level < first || level > c->L - 2 || (tx != 0 && tx != 1)) return MG_ERR_INVALID;
+        (family == MG_TUNE_TAIL_PSI ? c->tail_psi : c->tail_W) = tx != 0 ? level : first;
+        (family == MG_TUNE_TAIL_PSI ? c->tail_psi_on : c->tail_W_on) = tx != 0;
         drop_graph(c);
         return MG_OK;
     }
