@@ -465,24 +465,28 @@ def main():
     log(f"[bench] mixed: {sec * 1e3:.3f} ms/solve, outer={rep['outer_iters']} "
         f"rms H={final[0]:.3e} rms M={final[1]:.3e}")
 
-    # ---- the same solve with the W V-cycle's coarse levels as multigrid (exact spectral
-    # bottom off): the V-cycle of the FP64 leg, so the two differ in precision only
+    # ---- the same solve with the FP64 leg's V-cycle (its sweeps, the W V-cycle's coarse
+    # levels as multigrid: exact spectral bottom off), so that the two differ in precision only
+    w64 = synth.coupled(n, seed=args.seed, precision=synth.PREC_FP64)
     lf = g.fourier_level(mixed.p)
     mg_bottom = None
     if lf >= 0:
-        chosen = next((e["chosen"] for e in tuning if e["family"] == g.TUNE_FOURIER_W), 1)
-        mixed.set_tile(g.TUNE_FOURIER_W, lf, 0)
-        step(mixed)
+        pb = g.params(n, w.levels, w.bc, g.PREC_FP32_IR, w.length, w.origin, K, w64.nu_pre, w64.nu_post, True)
+        sb = g.Solver(pb, rho5, rho1, S)
+        sb.autotune(u, W, reps=10)
+        sb.set_tile(g.TUNE_FOURIER_W, lf, 0)
+        step(sb)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            rb = step(mixed)
+            rb = step(sb)
         torch.cuda.synchronize()
         secb = (time.perf_counter() - t0) / args.steps
-        mixed.set_tile(g.TUNE_FOURIER_W, lf, chosen)
-        mg_bottom = dict(seconds=secb, outer_iters=rb["outer_iters"], h_rms=rb["h_rms"], m_rms=rb["m_rms"])
-        log(f"[bench] mixed, multigrid W bottom: {secb * 1e3:.3f} ms/solve, outer={rb['outer_iters']} "
-            f"(exact bottom on level {lf}: {sec * 1e3:.3f} ms)")
+        sb.close()
+        mg_bottom = dict(seconds=secb, outer_iters=rb["outer_iters"], h_rms=rb["h_rms"], m_rms=rb["m_rms"],
+                         nu=[w64.nu_pre, w64.nu_post])
+        log(f"[bench] mixed, FP64 leg's V({w64.nu_pre},{w64.nu_post}) with the multigrid W bottom: "
+            f"{secb * 1e3:.3f} ms/solve, outer={rb['outer_iters']} (exact bottom on level {lf}: {sec * 1e3:.3f} ms)")
 
     # ---- mixed + learned warm start: network prediction, one outer iteration and
     # the residual comparison of the fallback rule, then the solve
@@ -639,7 +643,7 @@ def main():
     # ---- plain FP64 GPU multigrid on the same input
     fp64 = None
     if not args.no_fp64:
-        p64 = g.params(n, w.levels, w.bc, g.PREC_FP64, w.length, w.origin, K, w.nu_pre, w.nu_post, True)
+        p64 = g.params(n, w.levels, w.bc, g.PREC_FP64, w.length, w.origin, K, w64.nu_pre, w64.nu_post, True)
         s64 = g.Solver(p64, rho5, rho1, S)
         step(s64)
         torch.cuda.synchronize()
@@ -649,7 +653,8 @@ def main():
             r64 = step(s64)
         torch.cuda.synchronize()
         sec64 = (time.perf_counter() - t0) / k64
-        fp64 = dict(seconds=sec64, outer_iters=r64["outer_iters"], h_rms=r64["h_rms"], m_rms=r64["m_rms"])
+        fp64 = dict(seconds=sec64, outer_iters=r64["outer_iters"], h_rms=r64["h_rms"], m_rms=r64["m_rms"],
+                    nu=[w64.nu_pre, w64.nu_post])
         log(f"[bench] fp64: {sec64 * 1e3:.3f} ms/solve, outer={r64['outer_iters']}")
         s64.close()
 

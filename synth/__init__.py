@@ -117,9 +117,11 @@ def coupled(n: int = 128, seed: int = 0, phi_amp: float = 0.05,
             precision: int = PREC_FP32_IR, levels: Optional[int] = None) -> Workload:
     rng_phi = np.random.default_rng(seed)
     rng_pi = np.random.default_rng([seed, 1])
-    # V(1,2) cycles: of nu_pre, nu_post in 1..4 the fastest to rms 1e-10 at 128^3
-    # (17 outer iterations against 15 with V(2,2), each ~15% cheaper); V(1,1) for W where
-    # its bottom is exact (the same 16 outer iterations at 128^3 as V(1,2), 8% faster)
+    # V(1,2) cycles: the fastest to rms 1e-10 at 128^3 in FP64 (17 outer iterations,
+    # 15.1 ms; V(1,3) and V(2,2) 15 iterations, 16.1 ms).  With FP32 V-cycles and the exact W
+    # bottom, W V(1,1) (16 iterations as with V(1,2), 8% faster); psi V(1,3) would need 14 from
+    # the zero start (~4% faster) but makes the learned coarse start lose to the plain one
+    # (its coarse solve stops earlier and the fine solve needs one iteration more)
     return Workload(name=f"coupled_{n}", n=n,
                     levels=levels if levels is not None else coarsest_levels(n),
                     seed=seed, phi_modes=fourier_modes(rng_phi, 8, phi_amp),
