@@ -473,7 +473,10 @@ def main():
     if lf >= 0:
         pb = g.params(n, w.levels, w.bc, g.PREC_FP32_IR, w.length, w.origin, K, w64.nu_pre, w64.nu_post, True)
         sb = g.Solver(pb, rho5, rho1, S)
-        sb.autotune(u, W, reps=10)
+        if args.tune_cache:  # the same configuration key as the mixed solver: its stored choices
+            g.autotune_cached(sb, u, W, path=args.tune_cache, reps=10)
+        else:
+            sb.autotune(u, W, reps=10)
         sb.set_tile(g.TUNE_FOURIER_W, lf, 0)
         step(sb)
         torch.cuda.synchronize()
