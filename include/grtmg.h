@@ -65,7 +65,7 @@ typedef enum mg_status {
 enum { MG_BC_PERIODIC = 0, MG_BC_ROBIN = 1, MG_BC_REFLECT = 2, MG_BC_EXTRAP = 3, MG_BC_ZERO = 4 };
 enum { MG_PREC_FP64 = 0, MG_PREC_FP32_IR = 1 };
 enum { MG_EQ_PSI = 1, MG_EQ_W = 2, MG_EQ_BOTH = 3 };
-enum { MG_FLAG_CONFORMAL_MATTER = 1, MG_FLAG_EAGER = 2, MG_FLAG_CTTK = 4 };
+enum { MG_FLAG_CONFORMAL_MATTER = 1, MG_FLAG_EAGER = 2, MG_FLAG_CTTK = 4, MG_FLAG_CUBIC_PROLONG = 8 };
 
 /*
  * Problem and solver parameters.
@@ -114,7 +114,12 @@ enum { MG_FLAG_CONFORMAL_MATTER = 1, MG_FLAG_EAGER = 2, MG_FLAG_CTTK = 4 };
  *                 solve_momentum = 1, periodic boundaries, K = 0, no puncture and
  *                 no conformal matter; not in batches, mg_fmg_start or
  *                 nn_warm_start (MG_ERR_INVALID).  The workspace grows by
- *                 5 n^3 doubles.  Other bits must be 0.
+ *                 5 n^3 doubles.
+ *                 bit MG_FLAG_CUBIC_PROLONG: the V-cycles prolong corrections with
+ *                 the 4-point cubic of mg_interp_cubic (weights (-5, 35, 105, -7)/128
+ *                 and mirror per axis, ghosts by the boundary rule) instead of
+ *                 trilinearly; no V-cycle tails (MG_TUNE_TAIL_* unavailable).
+ *                 Other bits must be 0.
  *  length, origin box side L and corner of the box (cell centres at
  *                 origin + (i + 1/2) L/n).
  *  K              constant trace of the extrinsic curvature.

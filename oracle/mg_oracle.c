@@ -58,7 +58,8 @@
  * Gauss-Seidel (colour (i+j+k) mod 2, red first; every value read by a colour
  * pass is the value before that pass), defect restriction by the average of
  * the 8 children, rediscretised coarse operators, exact dense LU with partial
- * pivoting on the coarsest level, trilinear cell-centred prolongation.  The
+ * pivoting on the coarsest level, trilinear cell-centred prolongation (or, with
+ * flags bit 1, the 4-point cubic of the FMG start for the corrections too).  The
  * outer loop is a segregated inexact Newton iteration: W cycle, W update,
  * re-linearise, psi cycle, psi update; the constraint norms are recorded at
  * every iteration (Key features, "Diagnostics").
@@ -79,8 +80,10 @@
 #define OBC_ZERO 4
 #define OMAXLEV 16
 
-/* flags bit 0: conformally rescaled matter (see orc_residuals) */
+/* flags bit 0: conformally rescaled matter (see orc_residuals); bit 1: corrections
+ * prolonged by the 4-point cubic of orc_interp_cubic instead of trilinearly */
 #define OFLAG_CONFORMAL_MATTER 1
+#define OFLAG_CUBIC_PROLONG 2
 
 typedef struct {
     int32_t n, levels, bc, nu_pre, nu_post, solve_momentum, flags, pad1;
@@ -537,10 +540,21 @@ static void lin_taps(int i, int *I0, int *I1)
     *I1 = (i % 2 == 0) ? I - 1 : I + 1;
 }
 
-/* fine += trilinear interpolation of coarse (cell-centred, weights 3/4, 1/4). */
+void orc_interp_cubic(const orc_params *p, int nc, const double *coarse, double *fine);
+
+/* fine += trilinear interpolation of coarse (cell-centred, weights 3/4, 1/4), or, with
+ * OFLAG_CUBIC_PROLONG, fine += the 4-point cubic interpolation of coarse. */
 void orc_prolong_add(const orc_params *p, int nc, const double *coarse, double *fine)
 {
     int nf = 2 * nc;
+    if (p->flags & OFLAG_CUBIC_PROLONG) {
+        long mf = (long)nf * nf * nf;
+        double *q = (double *)malloc(mf * sizeof(double));
+        orc_interp_cubic(p, nc, coarse, q);
+        for (long i = 0; i < mf; i++) fine[i] += q[i];
+        free(q);
+        return;
+    }
     geom gc = make_geom(p, nc);
 #pragma omp parallel for schedule(static)
     for (int i = 0; i < nf; i++)

@@ -182,7 +182,8 @@ mg_status validate(const mg_params *p)
     // the W kernels address one component with 32-bit byte offsets
     if (p->solve_momentum && (double)p->n * p->n * (double)p->n * sizeof(double) >= 4294967296.0)
         return MG_ERR_INVALID;
-    if ((p->flags & ~(MG_FLAG_CONFORMAL_MATTER | MG_FLAG_EAGER | MG_FLAG_CTTK)) != 0) return MG_ERR_INVALID;
+    if ((p->flags & ~(MG_FLAG_CONFORMAL_MATTER | MG_FLAG_EAGER | MG_FLAG_CTTK | MG_FLAG_CUBIC_PROLONG)) != 0)
+        return MG_ERR_INVALID;
     // CTTK: the coupled periodic solve with psi = 1 + u as data, K from eq. Ham
     if ((p->flags & MG_FLAG_CTTK) &&
         (!p->solve_momentum || p->bc != MG_BC_PERIODIC || p->K != 0.0 || p->puncture_mass != 0.0 ||
@@ -344,6 +345,8 @@ void init_geo(mg_ctx *c)
                 c->tail_W = l;
                 break;
             }
+    // the tails prolong trilinearly inside: none with cubic prolongation
+    if (c->p.flags & MG_FLAG_CUBIC_PROLONG) c->tail_psi = c->tail_W = -1;
     c->tail_psi_min = c->tail_psi;
     c->tail_W_min = c->tail_W;
     // exact bottom of the W V-cycle
@@ -591,6 +594,25 @@ void prolong_add(mg_ctx *c, int lc, const T *coarse, T *fine, int ncomp)
 {
     Probe pr(c, MG_PROBE_PROLONG, lc - 1);
     const Geo &gc = c->geo[lc];
+    if (c->p.flags & MG_FLAG_CUBIC_PROLONG) {
+        const int nc = c->n[lc];
+        const bool staged = nc % kCubZ == 0 && nc % kCubY == 0 && nc % kCubX == 0;
+        const unsigned nbk = staged ? (unsigned)((nc / kCubX) * (nc / kCubY) * (nc / kCubZ)) : nblk(c->cells[lc]);
+        auto launch = [&](auto bcx) {
+            constexpr int BCX = decltype(bcx)::value;
+            if (staged)
+                hipLaunchKernelGGL((k_prolong_cubic_add_staged<BCX, T>), dim3(nbk, 1, c->gz), dim3(kBlock), 0, c->s, gc,
+                                   coarse, fine, ncomp);
+            else
+                hipLaunchKernelGGL((k_prolong_cubic_add<BCX, T>), dim3(nbk, 1, c->gz), dim3(kBlock), 0, c->s, gc,
+                                   coarse, fine, ncomp);
+        };
+        if (c->p.bc == MG_BC_PERIODIC)
+            launch(std::integral_constant<int, kBcPeriodic>{});
+        else
+            with_bc(c->p.bc, launch);
+        return;
+    }
     const unsigned nb = nblk(c->cells[lc - 1]);
     if (c->p.bc == MG_BC_PERIODIC) // one thread per fine z pair
         hipLaunchKernelGGL(k_prolong_add_pairs<T>, dim3(nblk(c->cells[lc - 1] / 2), 1, c->gz), dim3(kBlock), 0, c->s, gc,

@@ -910,6 +910,116 @@ __global__ void __launch_bounds__(kBlock) k_interp_cubic(Geo gc, const double *_
 }
 
 // ---------------------------------------------------------------------------------------
+// Cubic prolongation of corrections (MG_FLAG_CUBIC_PROLONG): fine += Q coarse with Q the
+// 4-point cubic of the FMG start (tensor product of the weights (-5, 35, 105, -7)/128 and
+// their mirror), ghosts by the level's rule.  A coarse cell writes its 8 children from its
+// 5^3 neighbourhood with the separable sums of k_interp_cubic (z, then y, then x).
+// ---------------------------------------------------------------------------------------
+template <typename T, typename Src>
+__device__ __forceinline__ void cubic_children_add(const Src &S, T *__restrict__ fine, int nf, int I, int J, int K)
+{
+    const T w[2][4] = {{T(-5.0 / 128.0), T(35.0 / 128.0), T(105.0 / 128.0), T(-7.0 / 128.0)},
+                       {T(-7.0 / 128.0), T(105.0 / 128.0), T(35.0 / 128.0), T(-5.0 / 128.0)}};
+    T yz[2][2][5]; // [z parity][y parity][x node]
+#pragma unroll
+    for (int a = 0; a < 5; a++) {
+        T zc[2][5]; // [z parity][y node] at x node a
+#pragma unroll
+        for (int b = 0; b < 5; b++) {
+            T v[5];
+#pragma unroll
+            for (int e = 0; e < 5; e++) v[e] = S(a, b, e);
+#pragma unroll
+            for (int pk = 0; pk < 2; pk++) {
+                T sb = T(0);
+#pragma unroll
+                for (int e = 0; e < 4; e++) sb += w[pk][e] * v[e + pk];
+                zc[pk][b] = sb;
+            }
+        }
+#pragma unroll
+        for (int pk = 0; pk < 2; pk++)
+#pragma unroll
+            for (int pj = 0; pj < 2; pj++) {
+                T sa = T(0);
+#pragma unroll
+                for (int b = 0; b < 4; b++) sa += w[pj][b] * zc[pk][b + pj];
+                yz[pk][pj][a] = sa;
+            }
+    }
+    using V2 = std::conditional_t<sizeof(T) == 4, float2, double2>;
+#pragma unroll
+    for (int pi = 0; pi < 2; pi++)
+#pragma unroll
+        for (int pj = 0; pj < 2; pj++) {
+            T out[2];
+#pragma unroll
+            for (int pk = 0; pk < 2; pk++) {
+                T acc = T(0);
+#pragma unroll
+                for (int a = 0; a < 4; a++) acc += w[pi][a] * yz[pk][pj][a + pi];
+                out[pk] = acc;
+            }
+            V2 *f = reinterpret_cast<V2 *>(fine + ((int64_t)(2 * I + pi) * nf + (2 * J + pj)) * nf + 2 * K);
+            V2 v = *f;
+            v.x += out[0];
+            v.y += out[1];
+            *f = v;
+        }
+}
+
+// Any coarse size: one thread per coarse cell, neighbours through the boundary rule.
+template <int BC, typename T>
+__global__ void __launch_bounds__(kBlock) k_prolong_cubic_add(Geo gc, const T *__restrict__ coarse,
+                                                              T *__restrict__ fine, int ncomp)
+{
+    coarse = zsh(coarse, gc.zs);
+    fine = zsh(fine, gc.zs);
+    const int nc = gc.n, nf = 2 * nc;
+    const int64_t mc = (int64_t)nc * nc * nc, mf = 8 * mc;
+    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int I, J, K;
+    if (!cell_of(tid, nc, I, J, K)) return;
+    for (int s = 0; s < ncomp; s++) {
+        const Acc<BC, T> C{coarse + s * mc, gc};
+        cubic_children_add<T>([&](int a, int b, int e) { return C(I - 2 + a, J - 2 + b, K - 2 + e); }, fine + s * mf,
+                              nf, I, J, K);
+    }
+}
+
+// Coarse sizes divisible by 16: a block of 4 x 4 x 16 coarse cells stages their 8 x 8 x 20
+// neighbourhood in LDS (each value loaded once) and reads the 5^3 taps from there.
+constexpr int kCubX = 4, kCubY = 4, kCubZ = 16;
+constexpr int kCubSX = kCubX + 4, kCubSY = kCubY + 4, kCubSZ = kCubZ + 4;
+template <int BC, typename T>
+__global__ void __launch_bounds__(kBlock) k_prolong_cubic_add_staged(Geo gc, const T *__restrict__ coarse,
+                                                                     T *__restrict__ fine, int ncomp)
+{
+    static_assert(kCubX * kCubY * kCubZ == kBlock, "one coarse cell per thread");
+    coarse = zsh(coarse, gc.zs);
+    fine = zsh(fine, gc.zs);
+    __shared__ T S[kCubSX][kCubSY][kCubSZ];
+    const int nc = gc.n, nf = 2 * nc;
+    const int64_t mc = (int64_t)nc * nc * nc, mf = 8 * mc;
+    const int nby = nc / kCubY, nbz = nc / kCubZ;
+    const int bz = blockIdx.x % nbz, by = (blockIdx.x / nbz) % nby, bx = blockIdx.x / (nbz * nby);
+    const int I0 = bx * kCubX, J0 = by * kCubY, K0 = bz * kCubZ;
+    const int t = threadIdx.x, kz = t % kCubZ, jy = (t / kCubZ) % kCubY, ix = t / (kCubZ * kCubY);
+    constexpr int kStaged = kCubSX * kCubSY * kCubSZ;
+    for (int s = 0; s < ncomp; s++) {
+        const Acc<BC, T> C{coarse + s * mc, gc};
+        if (s > 0) __syncthreads(); // the previous component's taps are read
+        for (int q = t; q < kStaged; q += kBlock) {
+            const int a = q / (kCubSY * kCubSZ), rem = q % (kCubSY * kCubSZ), b = rem / kCubSZ, e = rem % kCubSZ;
+            S[a][b][e] = C(I0 - 2 + a, J0 - 2 + b, K0 - 2 + e);
+        }
+        __syncthreads();
+        cubic_children_add<T>([&](int a, int b, int e) { return S[ix + a][jy + b][kz + e]; }, fine + s * mf, nf,
+                              I0 + ix, J0 + jy, K0 + kz);
+    }
+}
+
+// ---------------------------------------------------------------------------------------
 // Coarsest level: dense operator assembly, Gauss-Jordan inverse (partial
 // pivoting, FP64, one workgroup), and x = A^-1 r as a column-major mat-vec.
 // ---------------------------------------------------------------------------------------

@@ -24,6 +24,7 @@ EQ_PSI, EQ_W, EQ_BOTH = 1, 2, 3
 FLAG_CONFORMAL_MATTER = 1
 FLAG_EAGER = 2
 FLAG_CTTK = 4
+FLAG_CUBIC_PROLONG = 8
 OP_PASS_PSI, OP_PASS_W, OP_DEFECT_RESTRICT_PSI, OP_DEFECT_RESTRICT_W = 1, 2, 3, 4
 OP_PROLONG_ADD, OP_COARSE_PSI, OP_COARSE_W, OP_FOURIER_W = 5, 6, 7, 8
 PROBE_NONE, PROBE_PASS_PSI, PROBE_PASS_W, PROBE_RESIDUAL = 0, 1, 2, 3
@@ -153,16 +154,18 @@ def params(n: int, levels: int = 1, bc: int = BC_PERIODIC, precision: int = PREC
            length: float = 1.0, origin=(0.0, 0.0, 0.0), K: float = 0.0, nu_pre: int = 2,
            nu_post: int = 2, solve_momentum: bool = False, puncture_mass: float = 0.0,
            puncture_pos=(0.0, 0.0, 0.0), conformal_matter: bool = False,
-           eager: bool = False, cttk: bool = False, nu_pre_W: int = 0, nu_post_W: int = 0) -> MgParams:
+           eager: bool = False, cttk: bool = False, nu_pre_W: int = 0, nu_post_W: int = 0,
+           cubic_prolong: bool = False) -> MgParams:
     """nu_pre_W / nu_post_W: sweeps of the W V-cycle while its bottom is exact (see
-    fourier_level; 0: nu_pre / nu_post)."""
+    fourier_level; 0: nu_pre / nu_post).  cubic_prolong: corrections prolonged by the
+    4-point cubic (MG_FLAG_CUBIC_PROLONG)."""
     p = MgParams()
     p.n, p.levels, p.bc, p.precision = n, levels, bc, precision
     p.nu_pre, p.nu_post = nu_pre, nu_post
     p.nu_pre_W, p.nu_post_W = nu_pre_W, nu_post_W
     p.solve_momentum = 1 if solve_momentum else 0
     p.flags = ((FLAG_CONFORMAL_MATTER if conformal_matter else 0) | (FLAG_EAGER if eager else 0)
-               | (FLAG_CTTK if cttk else 0))
+               | (FLAG_CTTK if cttk else 0) | (FLAG_CUBIC_PROLONG if cubic_prolong else 0))
     p.length = length
     for a in range(3):
         p.origin[a] = origin[a]
@@ -414,7 +417,7 @@ def box_params(base: MgParams, b0: int, m: int, levels: int, precision: Optional
     p = params(2 * m, levels, BC_ZERO, base.precision if precision is None else precision, m * h,
                tuple(base.origin[a] + b0 * h for a in range(3)), base.K, base.nu_pre, base.nu_post, False,
                base.puncture_mass, tuple(base.puncture_pos[a] for a in range(3)))
-    p.flags = base.flags & FLAG_CONFORMAL_MATTER
+    p.flags = base.flags & (FLAG_CONFORMAL_MATTER | FLAG_CUBIC_PROLONG)
     return p
 
 

@@ -78,6 +78,8 @@ class Workload:
     # W V-cycle sweeps while its bottom is exact (0: nu_pre / nu_post)
     nu_pre_W: int = 0
     nu_post_W: int = 0
+    # corrections prolonged by the 4-point cubic instead of trilinearly
+    cubic_prolong: bool = False
     scalar_mass: float = 1.0
     phi_modes: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 5)))
     pi_modes: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 5)))
@@ -126,7 +128,7 @@ def coupled(n: int = 128, seed: int = 0, phi_amp: float = 0.05,
                     levels=levels if levels is not None else coarsest_levels(n),
                     seed=seed, phi_modes=fourier_modes(rng_phi, 8, phi_amp),
                     pi_modes=fourier_modes(rng_pi, 8, 0.02),
-                    precision=precision, solve_momentum=True, nu_pre=1, nu_post=2, nu_post_W=1)
+                    precision=precision, solve_momentum=True, nu_pre=1, nu_post=2, nu_post_W=1, cubic_prolong=True)
 
 
 def coupled_128(seed: int = 0, precision: int = PREC_FP32_IR) -> Workload:

@@ -23,7 +23,8 @@ def gparams(w, K=0.0, precision=None, levels=None):
     return g.params(w.n, levels if levels is not None else w.levels, w.bc,
                     w.precision if precision is None else precision, w.length, w.origin, K,
                     w.nu_pre, w.nu_post, w.solve_momentum, w.puncture_mass, w.puncture_pos,
-                    w.conformal_matter, nu_pre_W=w.nu_pre_W, nu_post_W=w.nu_post_W)
+                    w.conformal_matter, nu_pre_W=w.nu_pre_W, nu_post_W=w.nu_post_W,
+                    cubic_prolong=w.cubic_prolong)
 
 
 def oracle_problem(w):

@@ -139,6 +139,28 @@ def test_momentum_ops():
     assert rel_err(N(out), ref) < 1e-11
 
 
+@pytest.mark.parametrize("n,levels,bc", [(16, 3, g.BC_PERIODIC), (64, 4, g.BC_PERIODIC), (20, 3, g.BC_PERIODIC),
+                                         (16, 3, g.BC_ROBIN), (16, 3, g.BC_REFLECT), (16, 3, g.BC_ZERO)])
+def test_cubic_prolongation_matches_oracle(n, levels, bc):
+    """Corrections prolonged by the 4-point cubic (MG_FLAG_CUBIC_PROLONG): the staged
+    kernel (coarse sides divisible by 16: 32^3 -> 64^3) and the per-cell one, every
+    boundary rule, one and three components, against the oracle's prolongation."""
+    p = g.params(n, levels, bc, length=3.0, origin=(-1.5, -1.5, -1.5), puncture_pos=(0.1, 0.2, 0.3),
+                 cubic_prolong=True)
+    po = oracle.params(n, levels, bc=bc, length=3.0, origin=(-1.5, -1.5, -1.5), puncture_pos=(0.1, 0.2, 0.3),
+                       cubic_prolong=True)
+    s = g.Solver(p, T(synth.uniform_random(1, (n,) * 3, 0, 1)), T(synth.uniform_random(2, (n,) * 3, 0, 1)))
+    nc = n // 2
+    for ncomp in (1, 3):
+        coarse = synth.uniform_random(40 + ncomp, (ncomp,) + (nc,) * 3)
+        fine0 = synth.uniform_random(50 + ncomp, (ncomp,) + (n,) * 3)
+        out = torch.from_numpy(fine0.copy()).to(dev())
+        s.kernel_op(g.OP_PROLONG_ADD, 0, ncomp, T(coarse), out)
+        ref = np.stack([oracle.prolong_add(po, np.ascontiguousarray(coarse[a]), fine0[a].copy())
+                        for a in range(ncomp)])
+        assert rel_err(N(out), ref) < 1e-14, (ncomp, bc)
+
+
 @pytest.mark.parametrize("bc", [g.BC_PERIODIC, g.BC_ROBIN])
 def test_cubic_interp_matches_oracle(bc):
     nc = 12

@@ -277,6 +277,7 @@ def test_vcycle_tail_matches_separate_launches(case, shift):
         w = sy.hamiltonian_32(seed=1)
     elif case == "coupled_64":
         w = sy.coupled(64, seed=5, precision=g.PREC_FP32_IR)
+        w.cubic_prolong = False  # the tails prolong trilinearly
     else:
         w = sy.puncture_shell(128, precision=g.PREC_FP32_IR, levels=6)
     out = {}

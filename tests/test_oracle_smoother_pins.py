@@ -131,15 +131,18 @@ def two_level_psi(p, c, r):
     defect = r - (judge.lap(g, d) + c * d)
     pc = oracle.params(p.n // 2, bc=p.bc, length=p.length, origin=tuple(p.origin))
     dc = oracle.coarse_solve_psi(pc, oracle.restrict(c), oracle.restrict(defect))
-    d = oracle.prolong_add(p, dc, d)
+    if p.flags & oracle.FLAG_CUBIC_PROLONG:  # the cubic of the FMG start, added
+        d = d + oracle.interp_cubic(pc, dc)
+    else:
+        d = oracle.prolong_add(p, dc, d)
     for _ in range(p.nu_post):
         for colour in (0, 1):
             d = oracle.pass_psi(p, d, r, c, colour)
     return d
 
 
-def check_cycle_order(n):
-    p = oracle.params(n, levels=2, nu_pre=1, nu_post=2, **PERIODIC)
+def check_cycle_order(n, cubic=False):
+    p = oracle.params(n, levels=2, nu_pre=1, nu_post=2, cubic_prolong=cubic, **PERIODIC)
     c = -2.0 - RNG.uniform(0, 3, (n, n, n))
     r = RNG.standard_normal((n, n, n))
     got = oracle.vcycle_psi(p, c, r)
@@ -190,6 +193,10 @@ def test_colour_zero_is_even_parity():
 
 def test_vcycle_runs_red_then_black_around_an_exact_coarse_solve():
     check_cycle_order(8)
+
+
+def test_vcycle_with_cubic_prolongation_of_the_correction():
+    check_cycle_order(8, cubic=True)
 
 
 def test_W_vcycle_contracts():

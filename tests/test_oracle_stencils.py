@@ -127,6 +127,30 @@ def test_cubic_interp_exact_on_cubics():
     np.testing.assert_allclose(fine[sl], cub(Xf, Yf, Zf)[sl], rtol=0, atol=1e-11)
 
 
+def test_cubic_prolongation_of_corrections():
+    """With the cubic flag the V-cycles' prolongation adds the 4-point cubic
+    interpolation: exact on cubics in the interior (the trilinear one is not even
+    exact on quadratics), constants reproduced on a periodic grid, and an added
+    field, not a replaced one."""
+    nc = 10
+    pc = oracle.params(nc, bc=oracle.BC_ROBIN, length=3.0, origin=(-1.3, -0.7, -1.1),
+                       puncture_pos=(5.0, 5.0, 5.0), cubic_prolong=True)
+    X, Y, Z = cell_coords(pc)
+    cub = lambda x, y, z: x ** 3 - 2 * x * y * z + y ** 2 * z + z ** 3 - 0.5 * y + 1.0
+    pf = robin_params(2 * nc)
+    Xf, Yf, Zf = cell_coords(pf)
+    base = RNG.standard_normal((2 * nc,) * 3)
+    fine = oracle.prolong_add(pc, np.ascontiguousarray(cub(X, Y, Z)), base.copy())
+    sl = (slice(4, -4),) * 3
+    np.testing.assert_allclose((fine - base)[sl], cub(Xf, Yf, Zf)[sl], rtol=0, atol=1e-11)
+    quad = lambda x, y, z: x * x + y * z
+    lin = oracle.prolong_add(robin_params(nc), np.ascontiguousarray(quad(X, Y, Z)), np.zeros((2 * nc,) * 3))
+    assert np.abs(lin[sl] - quad(Xf, Yf, Zf)[sl]).max() > 1e-3
+    pp = oracle.params(nc, cubic_prolong=True)
+    fine = oracle.prolong_add(pp, np.full((nc,) * 3, 1.7), np.zeros((2 * nc,) * 3))
+    np.testing.assert_allclose(fine, 1.7, rtol=0, atol=1e-13)
+
+
 def _dense(op, shape):
     m = int(np.prod(shape))
     A = np.zeros((m, m))
