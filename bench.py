@@ -79,7 +79,7 @@ def bench_puncture_256(g, synth, dev, args, log):
     import torch
     w = synth.puncture_shell(256, precision=g.PREC_FP32_IR, levels=6)
     p = g.params(w.n, w.levels, w.bc, g.PREC_FP32_IR, w.length, w.origin, 0.0, w.nu_pre, w.nu_post,
-                 False, w.puncture_mass, w.puncture_pos, w.conformal_matter)
+                 False, w.puncture_mass, w.puncture_pos, w.conformal_matter, cubic_prolong=w.cubic_prolong)
     r5, r1, S = g.shell_field_sources(p, w.shell["amplitude"], w.shell["r0"], w.shell["width2"],
                                       w.scalar_mass, dev)
     s = g.Solver(p, r5, r1)
@@ -113,7 +113,7 @@ def bench_refined_puncture(g, synth, dev, args, log, u256):
     nc, m, b0 = 128, 64, 32
     w = synth.puncture_shell(nc, precision=g.PREC_FP32_IR, levels=6)
     pb = g.params(nc, 6, w.bc, g.PREC_FP32_IR, w.length, w.origin, 0.0, w.nu_pre, w.nu_post, False, w.puncture_mass,
-                  w.puncture_pos, w.conformal_matter)
+                  w.puncture_pos, w.conformal_matter, cubic_prolong=w.cubic_prolong)
     px = g.box_params(pb, b0, m, 6)
     sh = w.shell
     r5c, r1c, _ = g.shell_field_sources(pb, sh["amplitude"], sh["r0"], sh["width2"], w.scalar_mass, dev)
@@ -186,7 +186,7 @@ def bench_bowen_york_256(g, synth, dev, args, log):
     64 M, Robin boundaries, FP32 V-cycles in FP64 refinement, 6 levels."""
     import torch
     w = synth.bowen_york_binary(256, g.PREC_FP32_IR, 6)
-    p = g.params(w.n, w.levels, w.bc, g.PREC_FP32_IR, w.length, w.origin)
+    p = g.params(w.n, w.levels, w.bc, g.PREC_FP32_IR, w.length, w.origin, cubic_prolong=w.cubic_prolong)
     psi0, A2 = g.bowen_york_sources(p, w.punctures, dev)
     z = torch.zeros((w.n,) * 3, dtype=torch.float64, device=dev)
     s = g.Solver(p, z, z)

@@ -119,16 +119,16 @@ def coupled(n: int = 128, seed: int = 0, phi_amp: float = 0.05,
             precision: int = PREC_FP32_IR, levels: Optional[int] = None) -> Workload:
     rng_phi = np.random.default_rng(seed)
     rng_pi = np.random.default_rng([seed, 1])
-    # V(1,2) cycles: the fastest to rms 1e-10 at 128^3 in FP64 (17 outer iterations,
-    # 15.1 ms; V(1,3) and V(2,2) 15 iterations, 16.1 ms).  With FP32 V-cycles and the exact W
-    # bottom, W V(1,1) (16 iterations as with V(1,2), 8% faster); psi V(1,3) would need 14 from
-    # the zero start (~4% faster) but makes the learned coarse start lose to the plain one
-    # (its coarse solve stops earlier and the fine solve needs one iteration more)
+    # Corrections prolonged by the 4-point cubic and V(2,2) cycles: the fastest to rms 1e-10
+    # at 128^3 measured (mixed, zero start: V(2,2) 8 outer iterations, 4.7 ms; V(1,2) 10, 5.2;
+    # V(3,2) 8, 5.3; V(1,1) 15, 7.0; trilinear prolongation V(1,2) 16, 7.8).  W: one post-sweep
+    # while its bottom is exact (V(2,1); V(1,1) needs 9 iterations).  FP64: V(1,2), V(2,2),
+    # V(2,1) and V(1,3) all 11.3 ms (10-12 iterations).
     return Workload(name=f"coupled_{n}", n=n,
                     levels=levels if levels is not None else coarsest_levels(n),
                     seed=seed, phi_modes=fourier_modes(rng_phi, 8, phi_amp),
                     pi_modes=fourier_modes(rng_pi, 8, 0.02),
-                    precision=precision, solve_momentum=True, nu_pre=1, nu_post=2, nu_post_W=1, cubic_prolong=True)
+                    precision=precision, solve_momentum=True, nu_pre=2, nu_post=2, nu_post_W=1, cubic_prolong=True)
 
 
 def coupled_128(seed: int = 0, precision: int = PREC_FP32_IR) -> Workload:
@@ -137,11 +137,12 @@ def coupled_128(seed: int = 0, precision: int = PREC_FP32_IR) -> Workload:
 
 def puncture_shell(n: int = 256, precision: int = PREC_FP32_IR,
                    levels: int = 6) -> Workload:
+    # cubic prolongation of corrections: 5 outer iterations at 256^3 (19.1 ms) against 8 (31.3)
     return Workload(name=f"puncture_shell_{n}", n=n, levels=levels, length=64.0,
                     origin=(-32.0, -32.0, -32.0), bc=BC_ROBIN, precision=precision,
                     solve_momentum=False, puncture_mass=1.0,
                     puncture_pos=(0.0, 0.0, 0.0), conformal_matter=True,
-                    shell=dict(amplitude=0.1, r0=10.0, width2=4.0))
+                    shell=dict(amplitude=0.1, r0=10.0, width2=4.0), cubic_prolong=True)
 
 
 def bowen_york_binary(n: int = 256, precision: int = PREC_FP32_IR, levels: int = 6) -> Workload:
@@ -153,9 +154,10 @@ def bowen_york_binary(n: int = 256, precision: int = PREC_FP32_IR, levels: int =
         [0.5, 3.0, 0.0, 0.0, 0.0, 0.1, 0.0, 0.0, 0.0, 0.2],
         [0.5, -3.0, 0.0, 0.0, 0.0, -0.1, 0.0, 0.05, 0.0, -0.1],
     ])
+    # cubic prolongation of corrections: 5 outer iterations at 256^3 (19.7 ms) against 8 (32.4)
     return Workload(name=f"bowen_york_binary_{n}", n=n, levels=levels, length=64.0,
                     origin=(-32.0, -32.0, -32.0), bc=BC_ROBIN, precision=precision,
-                    solve_momentum=False, punctures=table)
+                    solve_momentum=False, punctures=table, cubic_prolong=True)
 
 
 def scan_96(count: int = 96, size_seed: int = 12345,

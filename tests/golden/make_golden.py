@@ -28,10 +28,12 @@ def sample_cells(n, seed=2024):
 
 
 def run(name):
+    # the puncture box's smallest eigenvalue (~5e-3) bounds psi only to ~200x the residual,
+    # so its reference solution is driven two orders further
     if name == "coupled_128":
-        w = synth.coupled_128(seed=0, precision=synth.PREC_FP64)
+        w, tol = synth.coupled_128(seed=0, precision=synth.PREC_FP64), 1e-11
     elif name == "puncture_shell_128":
-        w = synth.puncture_shell(128, precision=synth.PREC_FP64, levels=6)
+        w, tol = synth.puncture_shell(128, precision=synth.PREC_FP64, levels=6), 1e-13
     else:
         raise SystemExit(f"unknown workload {name}")
     rho5, rho1, S, K = oracle.sources_for(w)
@@ -40,13 +42,13 @@ def run(name):
     u = np.zeros((n,) * 3)
     W = np.zeros((3, n, n, n))
     t0 = time.time()
-    res = oracle.solve(p, u, W, rho5, rho1, S, tol=1e-11, max_outer=80)
+    res = oracle.solve(p, u, W, rho5, rho1, S, tol=tol, max_outer=80)
     dt = time.time() - t0
     assert res.status == 0, res
     cells = sample_cells(n)
     i, j, k = cells[:, 0], cells[:, 1], cells[:, 2]
     Wm = W - W.mean(axis=(1, 2, 3), keepdims=True)
-    out = dict(workload=name, n=n, levels=w.levels, K=K, tol=1e-11, status=res.status,
+    out = dict(workload=name, n=n, levels=w.levels, K=K, tol=tol, status=res.status,
                outer_iters=res.iters, seconds=dt, threads=oracle.num_threads(),
                history=res.history.tolist(), cells=cells.tolist(), u=u[i, j, k].tolist(),
                W_meanfree=[Wm[a][i, j, k].tolist() for a in range(3)],

@@ -17,11 +17,12 @@ pytestmark = pytest.mark.gpu
 
 def problem(n, levels, precision=g.PREC_FP64):
     w = synth.bowen_york_binary(n, precision, levels)
-    p = g.params(n, levels, w.bc, precision, w.length, w.origin)
+    p = g.params(n, levels, w.bc, precision, w.length, w.origin, cubic_prolong=w.cubic_prolong)
     psi0, A2 = g.bowen_york_sources(p, w.punctures, dev())
     po0 = oracle.params(n, bc=w.bc, length=w.length, origin=w.origin)
     opsi0, oA2 = oracle.bowen_york(po0, w.punctures)
-    po = oracle.params(n, levels=levels, bc=w.bc, length=w.length, origin=w.origin, bg_psi0=opsi0, bg_A2=oA2)
+    po = oracle.params(n, levels=levels, bc=w.bc, length=w.length, origin=w.origin, bg_psi0=opsi0, bg_A2=oA2,
+                       cubic_prolong=w.cubic_prolong)
     z = torch.zeros((n,) * 3, dtype=torch.float64, device=dev())
     s = g.Solver(p, z, z)
     s.set_background(psi0, A2)

@@ -84,14 +84,16 @@ def test_puncture_shell_128_matches_oracle():
     psi0 = judge.psi0(gr, w.puncture_mass)[i, j, k]
     uo = np.asarray(gold["u"])
     err10 = np.max(np.abs(N(u)[i, j, k] - uo) / (psi0 + uo))
-    # psi is compared after both sides reach 1e-11 (the wide Robin box has a
-    # small lowest eigenvalue, so 1e-10 bounds psi only to ~1e-8)
-    rep = s.solve(u, None, tol=1e-11, max_outer=60)
+    # psi is compared after the GPU reaches 1e-12 and the oracle 1e-13 (the wide Robin
+    # box has a lowest eigenvalue ~5e-3, so a residual bounds psi only to ~200 times it:
+    # 1e-10 to ~2e-8, 1e-12 to ~2e-10)
+    rep = s.solve(u, None, tol=1e-12, max_outer=60)
     err = np.max(np.abs(N(u)[i, j, k] - uo) / (psi0 + uo))
     print(f"puncture_shell_128: psi error vs oracle {err10:.2e} at rms H {rep10['h_rms']:.2e} "
           f"({rep10['outer_iters']} iterations), {err:.2e} at rms H {rep['h_rms']:.2e} "
-          f"(+{rep['outer_iters']} iterations; oracle {gold['outer_iters']} to 1e-11)")
-    assert rep["h_rms"] <= 1e-11
+          f"(+{rep['outer_iters']} iterations; oracle {gold['outer_iters']} to {gold['tol']:.0e})")
+    assert gold["tol"] <= 1e-13
+    assert rep["h_rms"] <= 1e-12
     assert err < 1e-9
 
 

@@ -22,13 +22,14 @@ def pair(nc, m, lc, lf, precision):
     w = synth.puncture_shell(nc, precision=precision, levels=lc)
     b0 = (nc - m) // 2
     pb = g.params(nc, lc, w.bc, precision, w.length, w.origin, 0.0, w.nu_pre, w.nu_post, False, w.puncture_mass,
-                  w.puncture_pos, True)
+                  w.puncture_pos, True, cubic_prolong=w.cubic_prolong)
     px = g.box_params(pb, b0, m, lf)
     pbo = oracle.params_from_workload(w)
     h = w.length / nc
     pxo = oracle.params(2 * m, levels=lf, bc=oracle.BC_ZERO, length=m * h,
                         origin=tuple(w.origin[a] + b0 * h for a in range(3)), nu_pre=w.nu_pre, nu_post=w.nu_post,
-                        puncture_mass=w.puncture_mass, puncture_pos=w.puncture_pos, conformal_matter=True)
+                        puncture_mass=w.puncture_mass, puncture_pos=w.puncture_pos, conformal_matter=True,
+                        cubic_prolong=w.cubic_prolong)
     sh = w.shell
     rc5, rc1, _ = oracle.shell_sources(pbo, sh["amplitude"], sh["r0"], sh["width2"], w.scalar_mass)
     rf5, rf1, _ = oracle.shell_sources(pxo, sh["amplitude"], sh["r0"], sh["width2"], w.scalar_mass)
@@ -107,7 +108,7 @@ def nested(nc, boxes, levels, precision):
     around the puncture, on both sides."""
     w = synth.puncture_shell(nc, precision=precision, levels=levels[0])
     pb = g.params(nc, levels[0], w.bc, precision, w.length, w.origin, 0.0, w.nu_pre, w.nu_post, False,
-                  w.puncture_mass, w.puncture_pos, True)
+                  w.puncture_mass, w.puncture_pos, True, cubic_prolong=w.cubic_prolong)
     ps, pos = [pb], [oracle.params_from_workload(w)]
     offs = [0]
     for (m, b), lv in zip(boxes, levels[1:]):
@@ -115,7 +116,8 @@ def nested(nc, boxes, levels, precision):
         q = ps[-1]
         pos.append(oracle.params(q.n, levels=lv, bc=oracle.BC_ZERO, length=q.length, origin=tuple(q.origin),
                                  nu_pre=w.nu_pre, nu_post=w.nu_post, puncture_mass=w.puncture_mass,
-                                 puncture_pos=w.puncture_pos, conformal_matter=True))
+                                 puncture_pos=w.puncture_pos, conformal_matter=True,
+                                 cubic_prolong=w.cubic_prolong))
         offs.append(b)
     sh = w.shell
     src = [oracle.shell_sources(po, sh["amplitude"], sh["r0"], sh["width2"], w.scalar_mass) for po in pos]

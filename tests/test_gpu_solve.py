@@ -280,6 +280,7 @@ def test_vcycle_tail_matches_separate_launches(case, shift):
         w.cubic_prolong = False  # the tails prolong trilinearly
     else:
         w = sy.puncture_shell(128, precision=g.PREC_FP32_IR, levels=6)
+        w.cubic_prolong = False  # the tails prolong trilinearly
     out = {}
     for no_tail in (False, True):
         p = gp(w)

@@ -1,13 +1,11 @@
 """What the trained warm-start networks gain over the zero start, on held-out
 seeds of the 128^3 coupled workload (seeds 10000+; training used 0-1999).  The
-network at 128^3: its prediction passes the fallback's bar and the solve from it
-reaches the same final residual and the same solution as the zero start (psi within
-1e-9 relative, W mean-free within 1e-9).  It no longer saves iterations: with the
-exact W bottom the zero start needs 16, the prediction 16 + 1 (after its check iteration
-it stands where one zero-start iteration does).  The network at 64^3
-as the coarse start of the full-multigrid start: fewer coarse iterations and less
-time.  The zero-start solve of this workload is compared with the oracle in
-test_gpu_fullsize."""
+network at 128^3: its prediction passes the fallback's bar (the zero state's residual),
+and the solve from it reaches the same final residual and the same solution as the
+zero start (psi within 1e-9 relative, W mean-free within 1e-9).  The network at 64^3
+as the coarse start of the full-multigrid start: fewer coarse iterations.  Neither
+saves time against the multigrid as it now converges (printed, not asserted).  The
+zero-start solve of this workload is compared with the oracle in test_gpu_fullsize."""
 import os
 
 import numpy as np
@@ -66,11 +64,14 @@ def _event_ms(fn):
     return a.elapsed_time(b), out
 
 
-def test_learned_coarse_start_saves_time_on_held_out_seeds():
+def test_learned_coarse_start_on_held_out_seeds():
     """The network trained on the 64^3 problem as the coarse start of the full-multigrid
-    start of the 128^3 solve: on held-out seeds it needs no more coarse iterations (its
-    check iteration counted) and saves time against the same start from zero
-    (event-timed, median over seeds), and reaches the same 128^3 solution."""
+    start of the 128^3 solve: on held-out seeds its prediction is kept, the coarse solve
+    needs fewer iterations (its check iteration counted), and the 128^3 solution is the
+    same.  The time it saves against the same start from zero is measured and printed:
+    with cubic correction prolongation and V(2,2) cycles the start from zero needs 3
+    coarse iterations and the learned start no longer saves time (the fine solve after it
+    takes one iteration more)."""
     from paper_2501_13046_amd import grtmg as g
     import synth
     cfg, nm, params, meta = ws.load(WEIGHTS_64, dev())
@@ -122,8 +123,7 @@ def test_learned_coarse_start_saves_time_on_held_out_seeds():
         fine.close()
         coarse.close()
     print(f"time saved per solve (median over seeds): {np.median(saved):.3f} ms")
-    assert all(c1 <= c0 for c0, c1, _, _ in its)  # the check iteration counted
-    assert np.median(saved) > 0.0
+    assert all(c1 < c0 for c0, c1, _, _ in its)  # the check iteration counted
 
 
 def test_fallback_compares_with_one_zero_start_iteration():
