@@ -39,10 +39,11 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pass_W_march_coupled_128_traffi
 RESIDUAL_TRAFFIC = os.path.join(ROOT, "profiles", "k_residual_march_coupled_128_traffic.md")
 
 
-def measured_traffic(path, depth):
+def measured_traffic(path, depth, form=None):
     """Bytes per launch from a committed counter summary, or None when the
-    kernel sources changed since the counters were taken or the kernel runs at
-    another depth than the one measured."""
+    kernel sources changed since the counters were taken, the kernel runs at
+    another depth than the one measured, or (form given) the summary measured
+    another mix of launch forms."""
     import hashlib
     vals, srcs = {}, {}
     try:
@@ -50,6 +51,8 @@ def measured_traffic(path, depth):
             key, _, val = line.partition(":")
             if key in ("brick_depth", "traffic_bytes_per_launch"):
                 vals[key] = int(val)
+            elif key == "launch_form":
+                vals[key] = val.strip()
             elif key == "source_sha256_16":
                 rel, pre = val.split()
                 srcs[rel] = pre
@@ -65,6 +68,8 @@ def measured_traffic(path, depth):
         except OSError:
             return None
     if vals.get("brick_depth") != depth:
+        return None
+    if form is not None and vals.get("launch_form", "two_forms") != form:
         return None
     return vals.get("traffic_bytes_per_launch")
 
@@ -220,7 +225,7 @@ def bench_scan_96(g, synth, dev, args, log):
     plist, r5s, r1s, Ss = [], [], [], []
     for w in ws:
         p = g.params(w.n, w.levels, w.bc, g.PREC_FP32_IR, w.length, w.origin, 0.0, w.nu_pre, w.nu_post, True,
-                     nu_post_W=w.nu_post_W, cubic_prolong=w.cubic_prolong)
+                     nu_post_W=w.nu_post_W, cubic_prolong=w.cubic_prolong, same_state=w.same_state)
         r5, r1, S, p.K = g.scalar_field_sources(p, w.phi_modes, w.pi_modes, w.scalar_mass, dev)
         plist.append(p)
         r5s.append(r5)
@@ -269,11 +274,11 @@ def bench_methods(g, w, K, rho5, rho1, S, args, log):
     out = {}
     r5h, Sh = rho5.clone(), S.clone()
     ph = g.params(n, w.levels, w.bc, g.PREC_FP32_IR, w.length, w.origin, 0.0, w.nu_pre, w.nu_post, True,
-                  nu_post_W=w.nu_post_W, cubic_prolong=w.cubic_prolong)
+                  nu_post_W=w.nu_post_W, cubic_prolong=w.cubic_prolong, same_state=w.same_state)
     Kf, K0 = g.cttk_hybrid_sources(ph, r5h, rho1, Sh)
     ph.K = K0
     pc = g.params(n, w.levels, w.bc, g.PREC_FP32_IR, w.length, w.origin, 0.0, w.nu_pre, w.nu_post, True, cttk=True,
-                  nu_post_W=w.nu_post_W, cubic_prolong=w.cubic_prolong)
+                  nu_post_W=w.nu_post_W, cubic_prolong=w.cubic_prolong, same_state=w.same_state)
     for name, p, srcs in (("cttk_hybrid", ph, (r5h, rho1, Sh)), ("cttk", pc, (rho5, rho1, S))):
         s = g.Solver(p, *srcs)
         u = torch.zeros((n,) * 3, dtype=torch.float64, device=rho5.device)
@@ -428,7 +433,7 @@ def main():
     n = w.n
     # ---- setup (off the clock): sources on the GPU, K from the mean density
     p = g.params(n, w.levels, w.bc, g.PREC_FP32_IR, w.length, w.origin, 0.0, w.nu_pre,
-                 w.nu_post, True, nu_post_W=w.nu_post_W, cubic_prolong=w.cubic_prolong)
+                 w.nu_post, True, nu_post_W=w.nu_post_W, cubic_prolong=w.cubic_prolong, same_state=w.same_state)
     rho5, rho1, S, K = g.scalar_field_sources(p, w.phi_modes, w.pi_modes, w.scalar_mass, dev)
     p.K = K
     mixed = g.Solver(p, rho5, rho1, S)
@@ -472,7 +477,7 @@ def main():
     mg_bottom = None
     if lf >= 0:
         pb = g.params(n, w.levels, w.bc, g.PREC_FP32_IR, w.length, w.origin, K, w64.nu_pre, w64.nu_post, True,
-                      cubic_prolong=w64.cubic_prolong)
+                      cubic_prolong=w64.cubic_prolong, same_state=w64.same_state)
         sb = g.Solver(pb, rho5, rho1, S)
         if args.tune_cache:  # the same configuration key as the mixed solver: its stored choices
             g.autotune_cached(sb, u, W, path=args.tune_cache, reps=10)
@@ -533,7 +538,7 @@ def main():
     # ---- mixed + full-multigrid start from the n/2 grid (sources evaluated there)
     wc = synth.coupled(n // 2, seed=args.seed, precision=synth.PREC_FP32_IR)
     pc = g.params(n // 2, wc.levels, wc.bc, g.PREC_FP32_IR, wc.length, wc.origin, K, wc.nu_pre, wc.nu_post, True,
-                  nu_post_W=wc.nu_post_W, cubic_prolong=wc.cubic_prolong)
+                  nu_post_W=wc.nu_post_W, cubic_prolong=wc.cubic_prolong, same_state=wc.same_state)
     r5c, r1c, Sc, _ = g.scalar_field_sources(pc, wc.phi_modes, wc.pi_modes, wc.scalar_mass, dev)
     coarse = g.Solver(pc, r5c, r1c, Sc)
     uc = torch.zeros((n // 2,) * 3, dtype=torch.float64, device=dev)
@@ -608,9 +613,10 @@ def main():
         log(f"[bench] no trained coarse warm-start weights at {args.weights_coarse}")
     coarse.close()
 
-    # ---- roofline: the finest-level residual is the kernel with the most time per outer
-    # iteration (two launches: the psi step's and the evaluation's), then the finest W pass.
-    # Both are timed live inside a solve (HIP events recorded by the dispatches themselves).
+    # ---- roofline: the finest-level W pass (five launches per outer iteration) and the
+    # finest residual (one launch per iteration when both steps start from the same state,
+    # two otherwise), both timed live inside a solve (HIP events recorded by the dispatches
+    # themselves); the one with more time per solve is the headline kernel.
     def probe(kid, level):
         mixed.probe(kid, level)
         r = step(mixed)
@@ -620,22 +626,43 @@ def main():
 
     cells = n ** 3
     cnt_r, t_r, rr = probe(g.PROBE_RESIDUAL, 0)
-    # algorithmic bytes per cell of the two forms (FP64 state and sources in, FP32 out):
-    #  evaluation: u, W(3), rho5, rho1, S(3) in (72 B); r_W(3) and the first W pass (3) out (24 B)
+    # algorithmic bytes per cell of the forms (FP64 state and sources in, FP32 out):
+    #  evaluation: u, W(3), rho5, rho1, S(3) in (72 B); r_W(3) and the first W pass (3) out
+    #              (24 B), and with both steps from the same state also r, c and the first
+    #              psi pass (12 B more: 108 B)
     #  psi step:   u, W(3), rho5, rho1 in (48 B); r, c and the first psi pass out (12 B)
-    # a solve runs one evaluation per outer iteration plus the starting state's, and one psi step
-    n_psi = rr["outer_iters"]
+    # a solve runs one evaluation per outer iteration plus the starting state's, and one psi
+    # step per iteration unless both steps start from the same state
+    same = bool(p.flags & g.FLAG_SAME_STATE)
+    n_psi = 0 if same else rr["outer_iters"]
     n_eval = cnt_r - n_psi
-    res_bytes = (n_eval * 96 + n_psi * 60) * cells / max(cnt_r, 1)
+    res_bytes = (n_eval * (108 if same else 96) + n_psi * 60) * cells / max(cnt_r, 1)
     res_avg = t_r / max(cnt_r, 1)
     res_gbs = res_bytes / res_avg / 1e9
-    log(f"[bench] residual level 0: {cnt_r} launches ({n_eval} evaluation, {n_psi} psi step), "
+    log(f"[bench] residual level 0: {cnt_r} launches ({n_eval} evaluation, {n_psi} psi step; same state {same}), "
         f"avg {res_avg * 1e6:.2f} us, {res_bytes / 1e6:.1f} MB/launch, {res_gbs:.0f} GB/s algorithmic")
     cnt_w, t_w, _ = probe(g.PROBE_PASS_W, 0)
     w_avg = t_w / max(cnt_w, 1)
     w_bytes = 9 * 4 * cells  # in (3 comps), r (3), out (3), FP32
     w_gbs = w_bytes / w_avg / 1e9
     log(f"[bench] W pass level 0: {cnt_w} launches, avg {w_avg * 1e6:.2f} us, {w_gbs:.0f} GB/s algorithmic")
+    form = "same_state" if same else "two_forms"
+    res_entry = {"kernel": "finest-level residual (k_residual_march, FP64 arithmetic; "
+                           + ("evaluation forming both steps' right-hand sides)" if same
+                              else "evaluation and psi-step forms)"),
+                 "achieved": res_gbs, "frac": res_gbs / HBM_PEAK_GBS,
+                 "traffic": measured_traffic(RESIDUAL_TRAFFIC, mixed_residual_depth(tuning), form),
+                 "launches": cnt_r, "avg_us": res_avg * 1e6, "bytes_per_launch": res_bytes,
+                 "us_per_solve": t_r * 1e6}
+    w_entry = {"kernel": f"finest-level W colour pass (k_pass_W_march, FP32), depth {w_depth}",
+               "achieved": w_gbs, "frac": w_gbs / HBM_PEAK_GBS,
+               "traffic": measured_traffic(TRAFFIC_FILE, w_depth), "launches": cnt_w,
+               "avg_us": w_avg * 1e6, "bytes_per_launch": w_bytes, "us_per_solve": t_w * 1e6}
+    head, other, other_key = ((w_entry, res_entry, "residual") if t_w >= t_r else (res_entry, w_entry, "w_pass"))
+    roofline = {"kernel": head["kernel"], "bound": "hbm", "achieved": head["achieved"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": head["frac"], "traffic": head["traffic"],
+                **{k: head[k] for k in ("launches", "avg_us", "bytes_per_launch", "us_per_solve")},
+                other_key: other}
     for name, kid, lvl in (("pass_psi", g.PROBE_PASS_PSI, 0), ("defect_restrict_W", g.PROBE_DEFECT_RESTRICT_W, 0),
                            ("prolong", g.PROBE_PROLONG, 0), ("update", g.PROBE_UPDATE, 0),
                            ("coarse", g.PROBE_COARSE, mixed.p.levels - 1), ("exact W bottom", g.PROBE_COARSE, lf)):
@@ -648,7 +675,7 @@ def main():
     fp64 = None
     if not args.no_fp64:
         p64 = g.params(n, w.levels, w.bc, g.PREC_FP64, w.length, w.origin, K, w64.nu_pre, w64.nu_post, True,
-                       cubic_prolong=w64.cubic_prolong)
+                       cubic_prolong=w64.cubic_prolong, same_state=w64.same_state)
         s64 = g.Solver(p64, rho5, rho1, S)
         step(s64)
         torch.cuda.synchronize()
@@ -726,16 +753,7 @@ def main():
                 "learned_fmg_start": (sec - learned_fmg["seconds"]) if learned_fmg else None},
             **extra,
         },
-        "roofline": {
-            "kernel": "finest-level residual (k_residual_march, FP64 arithmetic; evaluation and psi-step forms)",
-            "bound": "hbm", "achieved": res_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": res_gbs / HBM_PEAK_GBS,
-            "traffic": measured_traffic(RESIDUAL_TRAFFIC, mixed_residual_depth(tuning)),
-            "launches": cnt_r, "avg_us": res_avg * 1e6, "bytes_per_launch": res_bytes,
-            "w_pass": {"kernel": f"finest-level W colour pass, depth {w_depth}", "achieved": w_gbs,
-                       "frac": w_gbs / HBM_PEAK_GBS, "avg_us": w_avg * 1e6, "bytes_per_launch": w_bytes,
-                       "launches": cnt_w, "traffic": measured_traffic(TRAFFIC_FILE, w_depth)},
-        },
+        "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

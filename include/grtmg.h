@@ -65,7 +65,13 @@ typedef enum mg_status {
 enum { MG_BC_PERIODIC = 0, MG_BC_ROBIN = 1, MG_BC_REFLECT = 2, MG_BC_EXTRAP = 3, MG_BC_ZERO = 4 };
 enum { MG_PREC_FP64 = 0, MG_PREC_FP32_IR = 1 };
 enum { MG_EQ_PSI = 1, MG_EQ_W = 2, MG_EQ_BOTH = 3 };
-enum { MG_FLAG_CONFORMAL_MATTER = 1, MG_FLAG_EAGER = 2, MG_FLAG_CTTK = 4, MG_FLAG_CUBIC_PROLONG = 8 };
+enum {
+    MG_FLAG_CONFORMAL_MATTER = 1,
+    MG_FLAG_EAGER = 2,
+    MG_FLAG_CTTK = 4,
+    MG_FLAG_CUBIC_PROLONG = 8,
+    MG_FLAG_SAME_STATE = 16
+};
 
 /*
  * Problem and solver parameters.
@@ -119,6 +125,16 @@ enum { MG_FLAG_CONFORMAL_MATTER = 1, MG_FLAG_EAGER = 2, MG_FLAG_CTTK = 4, MG_FLA
  *                 the 4-point cubic of mg_interp_cubic (weights (-5, 35, 105, -7)/128
  *                 and mirror per axis, ghosts by the boundary rule) instead of
  *                 trilinearly; no V-cycle tails (MG_TUNE_TAIL_* unavailable).
+ *                 bit MG_FLAG_SAME_STATE: with solve_momentum = 1 (not CTTK), both
+ *                 steps of an outer iteration (mg_vcycle with MG_EQ_BOTH, every
+ *                 iteration of a solve) linearise eqs. Mom and Ham at the same
+ *                 state: the psi step no longer sees the W update of its own
+ *                 iteration.  One finest residual launch per iteration then
+ *                 forms both steps' right-hand sides, and inside the captured
+ *                 iteration of a single (not batched) context the two V-cycles
+ *                 run as concurrent graph branches.  The fixed point is the same
+ *                 discrete solution; the contraction per iteration can be
+ *                 slightly lower.  No effect without the momentum equation.
  *                 Other bits must be 0.
  *  length, origin box side L and corner of the box (cell centres at
  *                 origin + (i + 1/2) L/n).

@@ -48,6 +48,7 @@ BC_EXTRAP = 3
 BC_ZERO = 4
 FLAG_CONFORMAL_MATTER = 1
 FLAG_CUBIC_PROLONG = 2  # corrections prolonged by the 4-point cubic (reading A10')
+FLAG_SAME_STATE = 4  # both steps of an outer iteration linearise at its starting state
 
 
 def build(verbose: bool = False) -> str:
@@ -170,10 +171,12 @@ class _Params(OrcParams):
 def params(n, levels=1, bc=BC_PERIODIC, length=1.0, origin=(0.0, 0.0, 0.0), K=0.0,
            nu_pre=2, nu_post=2, solve_momentum=False, puncture_mass=0.0,
            puncture_pos=(0.0, 0.0, 0.0), conformal_matter=False, bg_psi0=None,
-           bg_A2=None, cubic_prolong=False) -> OrcParams:
+           bg_A2=None, cubic_prolong=False, same_state=False) -> OrcParams:
     """bg_psi0, bg_A2: optional n^3 fields (several punctures: psi0 in place of
     1 + M/(2r); Bowen-York: A2 of the analytic extrinsic curvature).  cubic_prolong:
-    the V-cycles prolong corrections with the 4-point cubic of interp_cubic."""
+    the V-cycles prolong corrections with the 4-point cubic of interp_cubic.
+    same_state: the psi step of an outer iteration reads the W the iteration
+    started from, not the W step's result."""
     p = _Params()
     keep = []
     for name, arr in (("bg_psi0", bg_psi0), ("bg_A2", bg_A2)):
@@ -183,7 +186,8 @@ def params(n, levels=1, bc=BC_PERIODIC, length=1.0, origin=(0.0, 0.0, 0.0), K=0.
             keep.append(arr)
             setattr(p, name, arr.ctypes.data)
     p._keep = keep
-    p.flags = (FLAG_CONFORMAL_MATTER if conformal_matter else 0) | (FLAG_CUBIC_PROLONG if cubic_prolong else 0)
+    p.flags = ((FLAG_CONFORMAL_MATTER if conformal_matter else 0) | (FLAG_CUBIC_PROLONG if cubic_prolong else 0)
+               | (FLAG_SAME_STATE if same_state else 0))
     p.n, p.levels, p.bc = n, levels, bc
     p.nu_pre, p.nu_post = nu_pre, nu_post
     p.solve_momentum = 1 if solve_momentum else 0
@@ -199,7 +203,7 @@ def params(n, levels=1, bc=BC_PERIODIC, length=1.0, origin=(0.0, 0.0, 0.0), K=0.
 def params_from_workload(w, K=0.0) -> OrcParams:
     return params(w.n, w.levels, w.bc, w.length, w.origin, K, w.nu_pre, w.nu_post,
                   w.solve_momentum, w.puncture_mass, w.puncture_pos, w.conformal_matter,
-                  cubic_prolong=w.cubic_prolong)
+                  cubic_prolong=w.cubic_prolong, same_state=w.same_state)
 
 
 def _z(n, comps=1):

@@ -81,9 +81,15 @@
 #define OMAXLEV 16
 
 /* flags bit 0: conformally rescaled matter (see orc_residuals); bit 1: corrections
- * prolonged by the 4-point cubic of orc_interp_cubic instead of trilinearly */
+ * prolonged by the 4-point cubic of orc_interp_cubic instead of trilinearly; bit 2:
+ * the W and psi steps of an outer iteration both linearise at the state the
+ * iteration starts from (the psi step reads W from before the W update) instead of
+ * the psi step following the W update.  The paper does not say how the two
+ * equations are coupled between multigrid solves; either order has the discrete
+ * solution as its fixed point. */
 #define OFLAG_CONFORMAL_MATTER 1
 #define OFLAG_CUBIC_PROLONG 2
+#define OFLAG_SAME_STATE 4
 
 typedef struct {
     int32_t n, levels, bc, nu_pre, nu_post, solve_momentum, flags, pad1;
@@ -885,25 +891,31 @@ static int step_psi(hier *HP, const orc_params *p, double *u, const double *W, c
     return 0;
 }
 
-/* One outer step for eq = 1 (psi), 2 (W) or 3 (W then psi). */
+/* One outer step for eq = 1 (psi), 2 (W) or 3 (W then psi; with OFLAG_SAME_STATE the
+ * psi step reads the W the step started from). */
 int orc_step(const orc_params *p, int eq, double *u, double *W, const double *rho5,
              const double *rho1, const double *S, const double *f)
 {
     sources s = {rho5, rho1, S, f};
     int rc = 0;
+    double *W_start = NULL;
+    if (eq == 3 && (p->flags & OFLAG_SAME_STATE)) {
+        W_start = (double *)malloc(3 * cells(p->n) * sizeof(double));
+        memcpy(W_start, W, 3 * cells(p->n) * sizeof(double));
+    }
     if (eq & 2) {
         hier HW;
         hier_init(&HW, p, 3);
         rc = step_W(&HW, p, u, W, &s);
         hier_free(&HW);
-        if (rc) return rc;
     }
-    if (eq & 1) {
+    if (!rc && (eq & 1)) {
         hier HP;
         hier_init(&HP, p, 1);
-        rc = step_psi(&HP, p, u, W, &s);
+        rc = step_psi(&HP, p, u, W_start ? W_start : W, &s);
         hier_free(&HP);
     }
+    free(W_start);
     return rc;
 }
 
@@ -944,8 +956,14 @@ int orc_solve(const orc_params *p, double *u, double *W, const double *rho5, con
             break;
         }
         int rc = 0;
-        if (p->solve_momentum) rc = step_W(&HW, p, u, W, &s);
-        if (!rc) rc = step_psi(&HP, p, u, W, &s);
+        if (p->solve_momentum && (p->flags & OFLAG_SAME_STATE)) {
+            memcpy(M, W, 3 * m * sizeof(double)); /* M is free until the next evaluation */
+            rc = step_W(&HW, p, u, W, &s);
+            if (!rc) rc = step_psi(&HP, p, u, M, &s);
+        } else {
+            if (p->solve_momentum) rc = step_W(&HW, p, u, W, &s);
+            if (!rc) rc = step_psi(&HP, p, u, W, &s);
+        }
         if (rc) {
             status = 1;
             break;

@@ -104,6 +104,11 @@ struct mg_ctx {
     mg_params p;
     hipStream_t user_s; // the caller's stream: every call is ordered after / before it by events
     hipStream_t s;      // internal stream (captured into the outer-iteration graph)
+    // second stream of a single context with MG_FLAG_SAME_STATE: the psi step's branch
+    // of the captured outer iteration (forked from and joined back into s by events)
+    hipStream_t s2;
+    hipEvent_t ev_fork, ev_join;
+    bool capturing, forking; // inside capture_graph; the W step runs beside the psi step
     hipEvent_t ev_in, ev_out;
     hipEvent_t ev_norm[2];     // norm copies of consecutive iterations (pinned slots hpin[0 / S_COUNT ..])
     int L;
@@ -125,6 +130,7 @@ struct mg_ctx {
     void *pd0[kMaxLevels], *pd1[kMaxLevels], *pr[kMaxLevels], *pc[kMaxLevels];
     void *wd0[kMaxLevels], *wd1[kMaxLevels], *wr[kMaxLevels];
     double *part;
+    double *part_w; // the W step's partial sums while it runs beside the psi step
     double *scal;
     int m_psi, m_W;
     double *A_psi, *aug_psi, *inv_psi;
@@ -165,6 +171,12 @@ struct mg_ctx {
 
 namespace {
 
+// Both steps of an outer iteration from one state (MG_FLAG_SAME_STATE; CTTK has its own loop).
+bool same_state(const mg_ctx *c)
+{
+    return (c->p.flags & MG_FLAG_SAME_STATE) && c->momentum && !(c->p.flags & MG_FLAG_CTTK);
+}
+
 mg_status validate(const mg_params *p)
 {
     if (!p) return MG_ERR_INVALID;
@@ -182,7 +194,8 @@ mg_status validate(const mg_params *p)
     // the W kernels address one component with 32-bit byte offsets
     if (p->solve_momentum && (double)p->n * p->n * (double)p->n * sizeof(double) >= 4294967296.0)
         return MG_ERR_INVALID;
-    if ((p->flags & ~(MG_FLAG_CONFORMAL_MATTER | MG_FLAG_EAGER | MG_FLAG_CTTK | MG_FLAG_CUBIC_PROLONG)) != 0)
+    if ((p->flags & ~(MG_FLAG_CONFORMAL_MATTER | MG_FLAG_EAGER | MG_FLAG_CTTK | MG_FLAG_CUBIC_PROLONG |
+                      MG_FLAG_SAME_STATE)) != 0)
         return MG_ERR_INVALID;
     // CTTK: the coupled periodic solve with psi = 1 + u as data, K from eq. Ham
     if ((p->flags & MG_FLAG_CTTK) &&
@@ -243,6 +256,9 @@ void carve(mg_ctx *c, Carver &cv)
     c->specZ = ls >= 0 && c->n[ls] > kFourierN ? (float2 *)cv.take(3 * c->cells[ls] * sizeof(float2)) : nullptr;
     const int64_t nb = nblk(c->cells[0]);
     c->part = (double *)cv.take((size_t)nb * 4 * sizeof(double));
+    c->part_w = (p.flags & MG_FLAG_SAME_STATE) && c->momentum
+                    ? (double *)cv.take((size_t)sum_blocks(c->cells[0]) * 3 * sizeof(double))
+                    : nullptr;
     if (p.flags & MG_FLAG_CTTK) {
         const size_t m0 = (size_t)c->cells[0] * sizeof(double);
         c->rho5_eff = (double *)cv.take(m0);
@@ -976,8 +992,9 @@ void step_W(mg_ctx *c, const double *u, double *W, bool residual_done, bool mix 
     vcycle_W<T>(c, 0, true);
     const int64_t m = c->cells[0];
     const int64_t nb = nblk(m), sb = sum_blocks(m);
-    hipLaunchKernelGGL(k_sum3<T>, dim3(sb, 1, c->gz), dim3(kBlock), 0, c->s, (const T *)c->wd0[0], m, c->part, c->zs);
-    hipLaunchKernelGGL(k_reduce_final<3>, dim3(1, 1, c->gz), dim3(kBlock), 0, c->s, (const double *)c->part, sb, 0u,
+    double *part = c->forking ? c->part_w : c->part; // the psi update sums into part meanwhile
+    hipLaunchKernelGGL(k_sum3<T>, dim3(sb, 1, c->gz), dim3(kBlock), 0, c->s, (const T *)c->wd0[0], m, part, c->zs);
+    hipLaunchKernelGGL(k_reduce_final<3>, dim3(1, 1, c->gz), dim3(kBlock), 0, c->s, (const double *)part, sb, 0u,
                        1.0 / (double)m, c->scal + S_MEAND, c->zs);
     if (mix) {
         // two partials per block in c->part (4 per block of the finest level)
@@ -1093,7 +1110,9 @@ void evaluate(mg_ctx *c, const double *u, const double *W, bool want_M, bool aft
 {
     if (c->cttk) cttk_update<T>(c, u, W);
     source_mean(c, u, sums_ready);
-    if (c->momentum)
+    if (same_state(c)) // both steps' right-hand sides and first passes
+        residual<T>(c, u, W, true, nullptr, nullptr, nullptr, c->pr[0], c->pc[0], c->wr[0], true, true);
+    else if (c->momentum)
         residual<T>(c, u, W, true, nullptr, nullptr, nullptr, nullptr, nullptr, c->wr[0], true, true);
     else
         residual<T>(c, u, W, want_M, nullptr, nullptr, nullptr, c->pr[0], c->pc[0], nullptr, true, true);
@@ -1101,6 +1120,42 @@ void evaluate(mg_ctx *c, const double *u, const double *W, bool want_M, bool aft
         hipLaunchKernelGGL(k_batch_check, dim3(1, 1, c->gz), dim3(64), 0, c->s, c->scal, (int)S_ACTIVE, (int)S_ITERS,
                            (int)S_DIVERGED, 1.0 / (double)c->cells[0], c->batch_tol, c->momentum ? 1 : 0,
                            after_update ? 1 : 0, c->zs);
+}
+
+// MG_FLAG_SAME_STATE: the W and psi steps from the right-hand sides the last
+// evaluation formed at one state.  The psi step reads no W, so inside the capture of
+// a single context it runs on the second stream as a graph branch beside the W step;
+// the W step's partial sums then go to part_w (the psi update sums into part).
+template <typename T>
+void both_steps(mg_ctx *c, double *u, double *W)
+{
+    const bool fork = c->capturing && c->s2 && !c->batched && c->gz == 1;
+    if (!fork) {
+        step_W<T>(c, u, W, true);
+        step_psi<T>(c, u, W, true);
+        return;
+    }
+    (void)hipEventRecord(c->ev_fork, c->s);
+    (void)hipStreamWaitEvent(c->s2, c->ev_fork, 0);
+    std::swap(c->s, c->s2);
+    step_psi<T>(c, u, W, true);
+    std::swap(c->s, c->s2);
+    c->forking = true;
+    step_W<T>(c, u, W, true);
+    c->forking = false;
+    (void)hipEventRecord(c->ev_join, c->s2);
+    (void)hipStreamWaitEvent(c->s, c->ev_join, 0);
+}
+
+// One outer step of mg_vcycle with MG_FLAG_SAME_STATE: both right-hand sides at the
+// entry state, then both steps.
+template <typename T>
+void vcycle_same_state(mg_ctx *c, double *u, double *W)
+{
+    source_mean(c, u);
+    residual<T>(c, u, W, true, nullptr, nullptr, nullptr, c->pr[0], c->pc[0], c->wr[0], false, true);
+    step_W<T>(c, u, W, true);
+    step_psi<T>(c, u, W, true);
 }
 
 // One outer update (W step, psi step) followed by the evaluation of the new state.
@@ -1113,7 +1168,9 @@ void outer_body(mg_ctx *c, double *u, double *W, bool want_M)
         evaluate<T>(c, u, W, want_M, true, false);
         return;
     }
-    if (c->momentum) {
+    if (same_state(c)) {
+        both_steps<T>(c, u, W);
+    } else if (c->momentum) {
         step_W<T>(c, u, W, true);
         step_psi<T>(c, u, W, false);
     } else {
@@ -1137,7 +1194,9 @@ mg_status capture_graph(mg_ctx *c, double *u, double *W, bool want_M, hipGraph_t
     *out = nullptr;
     if (hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal) != hipSuccess) return MG_ERR_HIP;
     const int vp = c->vc_psi, vw = c->vc_W;
+    c->capturing = true;
     outer_body<T>(c, u, W, want_M);
+    c->capturing = false;
     c->vc_psi = vp;
     c->vc_W = vw;
     hipGraph_t g = nullptr;
@@ -1328,10 +1387,11 @@ void release(mg_ctx *c)
 {
     drop_graph(c);
     if (c->s) (void)hipStreamSynchronize(c->s);
-    hipEvent_t *evs[] = {&c->ev_in, &c->ev_out, &c->ev_norm[0], &c->ev_norm[1]};
+    hipEvent_t *evs[] = {&c->ev_in, &c->ev_out, &c->ev_norm[0], &c->ev_norm[1], &c->ev_fork, &c->ev_join};
     for (hipEvent_t *e : evs)
         if (*e) (void)hipEventDestroy(*e);
     if (c->own_streams && c->s) (void)hipStreamDestroy(c->s);
+    if (c->s2) (void)hipStreamDestroy(c->s2);
     if (c->hpin) (void)hipHostFree(c->hpin);
     if (c->probe_ev) {
         for (int q = 0; q < 2 * kProbeMax; q++) (void)hipEventDestroy(c->probe_ev[q]);
@@ -1351,6 +1411,12 @@ mg_status create_streams(mg_ctx *c)
     hipEvent_t *evs[] = {&c->ev_in, &c->ev_out, &c->ev_norm[0], &c->ev_norm[1]};
     for (hipEvent_t *e : evs)
         if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) return MG_ERR_HIP;
+    if (c->own_streams && same_state(c)) {
+        if (hipStreamCreateWithFlags(&c->s2, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess)
+            return MG_ERR_HIP;
+    }
     return MG_OK;
 }
 
@@ -2429,7 +2495,12 @@ mg_status mg_vcycle(mg_ctx *c, int32_t eq, double *d_u, double *d_W)
     if (c->cttk && eq != MG_EQ_W) return MG_ERR_INVALID; // psi is data
     c->cont_valid = false;
     enter(c);
-    if (c->f32) {
+    if (eq == MG_EQ_BOTH && same_state(c)) {
+        if (c->f32)
+            vcycle_same_state<float>(c, d_u, d_W);
+        else
+            vcycle_same_state<double>(c, d_u, d_W);
+    } else if (c->f32) {
         if (c->cttk) cttk_update<float>(c, d_u, d_W); // the W step reads this state's shifted sources
         if (eq & MG_EQ_W) step_W<float>(c, d_u, d_W, false);
         if (eq & MG_EQ_PSI) step_psi<float>(c, d_u, d_W, false);

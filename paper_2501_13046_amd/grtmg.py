@@ -25,6 +25,7 @@ FLAG_CONFORMAL_MATTER = 1
 FLAG_EAGER = 2
 FLAG_CTTK = 4
 FLAG_CUBIC_PROLONG = 8
+FLAG_SAME_STATE = 16  # both steps of an outer iteration from one state (MG_FLAG_SAME_STATE)
 OP_PASS_PSI, OP_PASS_W, OP_DEFECT_RESTRICT_PSI, OP_DEFECT_RESTRICT_W = 1, 2, 3, 4
 OP_PROLONG_ADD, OP_COARSE_PSI, OP_COARSE_W, OP_FOURIER_W = 5, 6, 7, 8
 PROBE_NONE, PROBE_PASS_PSI, PROBE_PASS_W, PROBE_RESIDUAL = 0, 1, 2, 3
@@ -155,17 +156,19 @@ def params(n: int, levels: int = 1, bc: int = BC_PERIODIC, precision: int = PREC
            nu_post: int = 2, solve_momentum: bool = False, puncture_mass: float = 0.0,
            puncture_pos=(0.0, 0.0, 0.0), conformal_matter: bool = False,
            eager: bool = False, cttk: bool = False, nu_pre_W: int = 0, nu_post_W: int = 0,
-           cubic_prolong: bool = False) -> MgParams:
+           cubic_prolong: bool = False, same_state: bool = False) -> MgParams:
     """nu_pre_W / nu_post_W: sweeps of the W V-cycle while its bottom is exact (see
     fourier_level; 0: nu_pre / nu_post).  cubic_prolong: corrections prolonged by the
-    4-point cubic (MG_FLAG_CUBIC_PROLONG)."""
+    4-point cubic (MG_FLAG_CUBIC_PROLONG).  same_state: both steps of an outer
+    iteration from one state (MG_FLAG_SAME_STATE)."""
     p = MgParams()
     p.n, p.levels, p.bc, p.precision = n, levels, bc, precision
     p.nu_pre, p.nu_post = nu_pre, nu_post
     p.nu_pre_W, p.nu_post_W = nu_pre_W, nu_post_W
     p.solve_momentum = 1 if solve_momentum else 0
     p.flags = ((FLAG_CONFORMAL_MATTER if conformal_matter else 0) | (FLAG_EAGER if eager else 0)
-               | (FLAG_CTTK if cttk else 0) | (FLAG_CUBIC_PROLONG if cubic_prolong else 0))
+               | (FLAG_CTTK if cttk else 0) | (FLAG_CUBIC_PROLONG if cubic_prolong else 0)
+               | (FLAG_SAME_STATE if same_state else 0))
     p.length = length
     for a in range(3):
         p.origin[a] = origin[a]

@@ -24,7 +24,7 @@ def gparams(w, K=0.0, precision=None, levels=None):
                     w.precision if precision is None else precision, w.length, w.origin, K,
                     w.nu_pre, w.nu_post, w.solve_momentum, w.puncture_mass, w.puncture_pos,
                     w.conformal_matter, nu_pre_W=w.nu_pre_W, nu_post_W=w.nu_post_W,
-                    cubic_prolong=w.cubic_prolong)
+                    cubic_prolong=w.cubic_prolong, same_state=w.same_state)
 
 
 def oracle_problem(w):

@@ -48,6 +48,9 @@ def test_workspace_size_and_validation(g):
     assert ok > 0
     big = g.workspace_size(g.params(128, 6, solve_momentum=True, precision=g.PREC_FP32_IR))
     assert big > ok
+    # the W step's own partial sums when it runs beside the psi step
+    assert g.workspace_size(g.params(128, 6, solve_momentum=True, precision=g.PREC_FP32_IR,
+                                     same_state=True)) > big
     bad = [g.params(30, 4),  # 30 -> 15 -> 7.5
            g.params(32, 6),  # coarsest 1
            g.params(32, 1),  # coarsest 32^3 too large for the dense solve
@@ -56,6 +59,9 @@ def test_workspace_size_and_validation(g):
            g.params(32, 4, nu_pre=0, nu_post=2),  # the first pre-sweep pass comes with the residual
            g.params(32, 4, solve_momentum=True, nu_post_W=17),
            g.params(32, 4, solve_momentum=True, nu_pre_W=-1)]
+    unknown = g.params(32, 4, solve_momentum=True)
+    unknown.flags = 32  # no such flag
+    bad.append(unknown)
     for p in bad:
         with pytest.raises(g.MGError) as e:
             g.workspace_size(p)

@@ -34,8 +34,12 @@ def test_single_steps_match_oracle_hamiltonian():
         assert rel_err(N(u), uo) < 1e-11, step
 
 
-def test_single_steps_match_oracle_coupled():
+@pytest.mark.parametrize("same_state", [True, False])
+def test_single_steps_match_oracle_coupled(same_state):
+    """Both couplings of the two steps: the psi step after the W update, or both from
+    the step's starting state (one residual launch forms both right-hand sides)."""
     w = synth.coupled(32, seed=2, precision=g.PREC_FP64)
+    w.same_state = same_state
     rho5, rho1, S, K, po = oracle_problem(w)
     s = solver_for(w, K, rho5, rho1, S)
     n = w.n
@@ -173,7 +177,8 @@ def test_timing_probe_counts_each_launch_once():
     exact = g.fourier_level(s.p) >= 0  # the W cycle's own sweeps apply while its bottom is exact
     npre = (w.nu_pre_W if exact and w.nu_pre_W else w.nu_pre)
     npost = (w.nu_post_W if exact and w.nu_post_W else w.nu_post)
-    for kid, per_iter, extra in ((g.PROBE_PASS_W, 2 * npre + 2 * npost - 1, 0), (g.PROBE_RESIDUAL, 2, 1)):
+    per_res = 1 if w.same_state else 2  # one evaluation forms both steps, or a psi step of its own
+    for kid, per_iter, extra in ((g.PROBE_PASS_W, 2 * npre + 2 * npost - 1, 0), (g.PROBE_RESIDUAL, per_res, 1)):
         s.probe(kid, 0)
         u2, W2 = z()
         r = s.solve(u2, W2, tol=1e-10)
@@ -236,11 +241,15 @@ def test_uniform_density_zero_cycles():
     assert rep["outer_iters"] == 0 and float(u.abs().max()) == 0.0
 
 
+@pytest.mark.parametrize("same_state", [True, False])
 @pytest.mark.parametrize("precision", [g.PREC_FP64, g.PREC_FP32_IR])
-def test_graph_replays_match_eager(precision):
+def test_graph_replays_match_eager(precision, same_state):
     # the captured outer-iteration graph is replayed many times per solve and
-    # across solves; every result must equal the eagerly launched solve
+    # across solves; every result must equal the eagerly launched solve (with both
+    # steps from the same state the graph runs the two V-cycles as concurrent
+    # branches, the eager solve one after the other)
     w = synth.coupled(32, seed=6, precision=precision)
+    w.same_state = same_state
     rho5, rho1, S, K, po = oracle_problem(w)
     outs = {}
     for eager in (True, False):

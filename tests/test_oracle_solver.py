@@ -284,3 +284,51 @@ def test_mms_conformal_matter_fourth_order():
         assert res.status == 0, res
         errs.append(np.abs(1.0 + u - f_psi(Xc, Yc, Zc)).max())
     assert errs[0] / errs[1] > 13.0, errs
+
+
+def test_same_state_step_takes_both_steps_from_the_starting_state():
+    """With the same-state coupling an outer step of both equations equals the W step
+    and the psi step each taken alone from the step's starting state; without it the
+    psi step reads the W step's result.  Bitwise: the same arithmetic either way."""
+    n = 16
+    w = synth.coupled(n, seed=3, precision=synth.PREC_FP64)
+    rho5, rho1, S, K = oracle.sources_for(w)
+    u0 = 0.01 * smooth_field(n, 5)
+    W0 = np.ascontiguousarray(np.stack([0.002 * smooth_field(n, 6 + a) for a in range(3)]))
+    out = {}
+    for same in (True, False):
+        w.same_state = same
+        p = oracle.params_from_workload(w, K)
+        u, W = u0.copy(), W0.copy()
+        oracle.step(p, 3, u, W, rho5, rho1, S)
+        uw, Ww = u0.copy(), W0.copy()
+        oracle.step(p, 2, uw, Ww, rho5, rho1, S)  # the W step alone
+        up, Wp = u0.copy(), (W0 if same else Ww).copy()
+        oracle.step(p, 1, up, Wp, rho5, rho1, S)  # the psi step alone, from the W it reads
+        assert np.array_equal(W, Ww) and np.array_equal(u, up), same
+        out[same] = u
+    # the two couplings differ: A2 of the W the psi step reads enters H_h and c
+    assert np.abs(out[True] - out[False]).max() > 1e-9
+
+
+def test_same_state_solve_reaches_the_same_discrete_solution():
+    """Both couplings have the discrete solution as their fixed point: each solve meets
+    the tolerance by the judge's own residuals, and the two solutions agree."""
+    n = 32
+    w = synth.coupled(n, seed=4, precision=synth.PREC_FP64)
+    rho5, rho1, S, K = oracle.sources_for(w)
+    sols = {}
+    for same in (False, True):
+        w.same_state = same
+        p = oracle.params_from_workload(w, K)
+        u = np.zeros((n, n, n))
+        W = np.zeros((3, n, n, n))
+        res = oracle.solve(p, u, W, rho5, rho1, S, tol=1e-11, max_outer=40)
+        assert res.status == 0, res
+        H, M, _ = judge.residuals(judge.Grid(n, w.length), u, W, rho5, rho1, S, K)
+        nr = judge.norms(H, M)
+        assert nr[0] <= 1.01e-11 and nr[1] <= 1.01e-11, (same, nr)
+        sols[same] = (u, W - W.mean(axis=(1, 2, 3), keepdims=True), res.iters)
+    (u0, W0, i0), (u1, W1, i1) = sols[False], sols[True]
+    assert np.abs(u1 - u0).max() < 1e-9 and np.abs(W1 - W0).max() < 1e-9 * np.abs(W0).max()
+    assert abs(i1 - i0) <= 2
