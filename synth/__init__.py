@@ -121,20 +121,20 @@ def coupled(n: int = 128, seed: int = 0, phi_amp: float = 0.05,
             precision: int = PREC_FP32_IR, levels: Optional[int] = None) -> Workload:
     rng_phi = np.random.default_rng(seed)
     rng_pi = np.random.default_rng([seed, 1])
-    # Corrections prolonged by the 4-point cubic and V(2,2) cycles: the fastest to rms 1e-10
-    # at 128^3 measured (mixed, zero start: V(2,2) 8 outer iterations, 4.7 ms; V(1,2) 10, 5.2;
-    # V(3,2) 8, 5.3; V(1,1) 15, 7.0; trilinear prolongation V(1,2) 16, 7.8).  W: one post-sweep
-    # while its bottom is exact (V(2,1); V(1,1) needs 9 iterations).  FP64: V(1,2), V(2,2),
-    # V(2,1) and V(1,3) all 11.3 ms (10-12 iterations).  Both steps of an outer iteration
-    # linearised at its starting state: one finest residual per iteration and the two
-    # V-cycles side by side (mixed 4.26 ms / 9 iterations against 4.85 / 8 in sequence,
-    # FP64 10.5 against 12.1 ms / 10).
+    # Corrections prolonged by the 4-point cubic, both steps of an outer iteration from its
+    # starting state (one finest residual per iteration, the two V-cycles side by side), psi
+    # V(1,3) and W V(1,2) while its bottom is exact: the fastest to rms 1e-10 at 128^3 measured
+    # (mixed, FMG start / zero start: psi V(1,3) W V(1,2) 3.52 / 3.98 ms; W V(2,1) 3.60 / 4.06;
+    # psi V(2,2) W V(2,1) 3.72-3.78 / 4.11-4.19; psi V(1,2) W V(1,1) 3.76-3.97 / 3.87-3.92 with
+    # 10 iterations; psi V(1,4) 3.94 / 4.42; the two steps in sequence with V(2,2) 4.78 / 4.85).
+    # FP64 (the W cycle with the psi sweeps): V(1,3) 10.27 ms / 10 iterations, V(2,2) 10.50,
+    # V(1,2) 10.21 / 12, V(2,1) 10.49 / 12.
     return Workload(name=f"coupled_{n}", n=n,
                     levels=levels if levels is not None else coarsest_levels(n),
                     seed=seed, phi_modes=fourier_modes(rng_phi, 8, phi_amp),
                     pi_modes=fourier_modes(rng_pi, 8, 0.02),
-                    precision=precision, solve_momentum=True, nu_pre=2, nu_post=2, nu_post_W=1, cubic_prolong=True,
-                    same_state=True)
+                    precision=precision, solve_momentum=True, nu_pre=1, nu_post=3, nu_pre_W=1, nu_post_W=2,
+                    cubic_prolong=True, same_state=True)
 
 
 def coupled_128(seed: int = 0, precision: int = PREC_FP32_IR) -> Workload:

@@ -18,7 +18,7 @@ pytestmark = pytest.mark.gpu
 def coupled_solver(n, levels, seed=2, same_sweeps=False):
     w = synth.coupled(n, seed=seed, precision=g.PREC_FP32_IR)
     if same_sweeps:  # the W cycle keeps the psi cycle's sweeps with the exact bottom too
-        w.nu_post_W = 0
+        w.nu_pre_W = w.nu_post_W = 0
     p = gparams(w, levels=levels)
     r5, r1, S, p.K = g.scalar_field_sources(p, w.phi_modes, w.pi_modes, w.scalar_mass, dev())
     return g.Solver(p, r5, r1, S), (r5, r1, S)
