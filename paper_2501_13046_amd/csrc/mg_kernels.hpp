@@ -988,9 +988,13 @@ __global__ void __launch_bounds__(kBlock) k_prolong_cubic_add(Geo gc, const T *_
 }
 
 // Coarse sizes divisible by 16: a block of 4 x 4 x 16 coarse cells stages their 8 x 8 x 20
-// neighbourhood in LDS (each value loaded once) and reads the 5^3 taps from there.
+// neighbourhood in LDS (each value loaded once) and reads the 5^3 taps from there.  A wave
+// reads four z rows of 16 values at once; with rows kCubSZP = 48 values apart the rows
+// served together land on disjoint banks (float: word offsets 0, 48, 96, 144 fill four
+// distinct 16-bank quarters of 64 banks; double: consecutive rows 96 words apart fill the
+// two halves), where the unpadded stride of 20 put 2-4 rows on the same banks.
 constexpr int kCubX = 4, kCubY = 4, kCubZ = 16;
-constexpr int kCubSX = kCubX + 4, kCubSY = kCubY + 4, kCubSZ = kCubZ + 4;
+constexpr int kCubSX = kCubX + 4, kCubSY = kCubY + 4, kCubSZ = kCubZ + 4, kCubSZP = 48;
 template <int BC, typename T>
 __global__ void __launch_bounds__(kBlock) k_prolong_cubic_add_staged(Geo gc, const T *__restrict__ coarse,
                                                                      T *__restrict__ fine, int ncomp)
@@ -998,7 +1002,7 @@ __global__ void __launch_bounds__(kBlock) k_prolong_cubic_add_staged(Geo gc, con
     static_assert(kCubX * kCubY * kCubZ == kBlock, "one coarse cell per thread");
     coarse = zsh(coarse, gc.zs);
     fine = zsh(fine, gc.zs);
-    __shared__ T S[kCubSX][kCubSY][kCubSZ];
+    __shared__ T S[kCubSX][kCubSY][kCubSZP];
     const int nc = gc.n, nf = 2 * nc;
     const int64_t mc = (int64_t)nc * nc * nc, mf = 8 * mc;
     const int nby = nc / kCubY, nbz = nc / kCubZ;
