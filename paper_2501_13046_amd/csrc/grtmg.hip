@@ -1249,8 +1249,9 @@ mg_status solve(mg_ctx *c, double *u, double *W, double tol, int max_outer, mg_r
     // contraction of the last two iterations puts iteration it at least
     // kAheadMargin times above tol, so it cannot be the last one.  With one read
     // iteration only, the state must lie kFirstAhead times above tol (no outer
-    // iteration contracts by that much).
-    constexpr double kAheadMargin = 10.0, kFirstAhead = 1e4;
+    // iteration contracts by that much: the first ones contract by 15-30x; the
+    // coarse solve of a full-multigrid start begins ~4000x above its tolerance).
+    constexpr double kAheadMargin = 10.0, kFirstAhead = 1e3;
     double w1 = -1.0, w2 = -1.0; // worst norm after the last and the one-before-last read iteration
     double last_worst = -1.0;      // worst norm of the last read iteration
     double resumed[4] = {0, 0, 0, 0};
