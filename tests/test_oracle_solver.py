@@ -286,7 +286,7 @@ def test_mms_conformal_matter_fourth_order():
     assert errs[0] / errs[1] > 13.0, errs
 
 
-def test_same_state_step_takes_both_steps_from_the_starting_state():
+def check_same_state_step():
     """With the same-state coupling an outer step of both equations equals the W step
     and the psi step each taken alone from the step's starting state; without it the
     psi step reads the W step's result.  Bitwise: the same arithmetic either way."""
@@ -309,6 +309,49 @@ def test_same_state_step_takes_both_steps_from_the_starting_state():
         out[same] = u
     # the two couplings differ: A2 of the W the psi step reads enters H_h and c
     assert np.abs(out[True] - out[False]).max() > 1e-9
+
+
+def check_same_state_solve_iterates_the_step():
+    """The solve loop with the same-state coupling takes the pinned outer step: its state
+    after k iterations equals k steps from the same start."""
+    n = 16
+    w = synth.coupled(n, seed=3, precision=synth.PREC_FP64)
+    w.same_state = True
+    rho5, rho1, S, K = oracle.sources_for(w)
+    p = oracle.params_from_workload(w, K)
+    u, W = np.zeros((n, n, n)), np.zeros((3, n, n, n))
+    res = oracle.solve(p, u, W, rho5, rho1, S, tol=1e-30, max_outer=3)
+    assert res.iters == 3
+    us, Ws = np.zeros((n, n, n)), np.zeros((3, n, n, n))
+    for _ in range(3):
+        oracle.step(p, 3, us, Ws, rho5, rho1, S)
+    np.testing.assert_allclose(u, us, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(W, Ws, rtol=0, atol=1e-14)
+
+
+def test_same_state_step_takes_both_steps_from_the_starting_state():
+    check_same_state_step()
+
+
+def test_same_state_solve_iterates_the_pinned_step():
+    check_same_state_solve_iterates_the_step()
+
+
+# psi step of the same-state outer step reading the W step's result, in the step and in the
+# solve loop
+SAME_STATE_STEP = ("rc = step_psi(&HP, p, u, W_start ? W_start : W, &s);", "rc = step_psi(&HP, p, u, W, &s);")
+SAME_STATE_SOLVE = ("if (!rc) rc = step_psi(&HP, p, u, M, &s);", "if (!rc) rc = step_psi(&HP, p, u, W, &s);")
+
+
+@pytest.mark.parametrize("plant,check", [
+    (SAME_STATE_STEP, check_same_state_step),
+    (SAME_STATE_SOLVE, check_same_state_solve_iterates_the_step),
+], ids=["step", "solve-loop"])
+def test_same_state_planted_mistake_is_caught(plant, check):
+    with oracle.planted([plant]):
+        with pytest.raises(AssertionError):
+            check()
+    check()  # and the real oracle passes again
 
 
 def test_same_state_solve_reaches_the_same_discrete_solution():

@@ -128,6 +128,18 @@ def test_cubic_interp_exact_on_cubics():
 
 
 def test_cubic_prolongation_of_corrections():
+    check_cubic_prolongation_of_corrections()
+
+
+def test_cubic_prolongation_planted_mistake_is_caught():
+    # the flag ignored: corrections prolonged trilinearly, not exact on cubics
+    with oracle.planted([("    if (p->flags & OFLAG_CUBIC_PROLONG) {", "    if (0) {")]):
+        with pytest.raises(AssertionError):
+            check_cubic_prolongation_of_corrections()
+    check_cubic_prolongation_of_corrections()
+
+
+def check_cubic_prolongation_of_corrections():
     """With the cubic flag the V-cycles' prolongation adds the 4-point cubic
     interpolation: exact on cubics in the interior (the trilinear one is not even
     exact on quadratics), constants reproduced on a periodic grid, and an added
