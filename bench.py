@@ -731,6 +731,11 @@ def main():
             "workload": f"coupled_{n}",
             "n": n, "levels": w.levels, "cells": n ** 3, "seed": args.seed,
             "precision": "fp32 V-cycle in fp64 iterative refinement",
+            "outer_coupling": ("both steps linearised at the iteration's starting state (graph branches)"
+                               if p.flags & g.FLAG_SAME_STATE else "W step, then psi step"),
+            "cycles": {"psi": [w.nu_pre, w.nu_post],
+                       "W_exact_bottom": [w.nu_pre_W or w.nu_pre, w.nu_post_W or w.nu_post],
+                       "correction_prolongation": "cubic" if w.cubic_prolong else "trilinear"},
             "value_is": value_is,
             "mixed_seconds": sec,
             "tol": args.tol, "outer_iters": rep["outer_iters"],
