@@ -37,8 +37,11 @@
  *    the work already on that stream and that stream waits for the call's
  *    work.  Internally a context runs on a stream of its own (created at
  *    setup with default priority), whose outer-iteration body is captured
- *    once into a hipGraph and replayed.  Calls that return host scalars
- *    (norms, reports) wait for the context's own work only.
+ *    once into a hipGraph and replayed; a context with MG_FLAG_SAME_STATE
+ *    and the momentum equation creates a second one (default priority) for
+ *    the psi branch of that graph, forked from and joined back into the
+ *    first within every iteration.  Calls that return host scalars (norms,
+ *    reports) wait for the context's own work only.
  *  - No call throws.  Arguments are validated before any HIP call; a non-OK
  *    status leaves device arrays untouched unless stated otherwise.
  */
