@@ -225,7 +225,8 @@ def bench_scan_96(g, synth, dev, args, log):
     plist, r5s, r1s, Ss = [], [], [], []
     for w in ws:
         p = g.params(w.n, w.levels, w.bc, g.PREC_FP32_IR, w.length, w.origin, 0.0, w.nu_pre, w.nu_post, True,
-                     nu_post_W=w.nu_post_W, cubic_prolong=w.cubic_prolong, same_state=w.same_state)
+                     nu_pre_W=w.nu_pre_W, nu_post_W=w.nu_post_W, cubic_prolong=w.cubic_prolong,
+                     same_state=w.same_state)
         r5, r1, S, p.K = g.scalar_field_sources(p, w.phi_modes, w.pi_modes, w.scalar_mass, dev)
         plist.append(p)
         r5s.append(r5)
@@ -274,11 +275,13 @@ def bench_methods(g, w, K, rho5, rho1, S, args, log):
     out = {}
     r5h, Sh = rho5.clone(), S.clone()
     ph = g.params(n, w.levels, w.bc, g.PREC_FP32_IR, w.length, w.origin, 0.0, w.nu_pre, w.nu_post, True,
-                  nu_post_W=w.nu_post_W, cubic_prolong=w.cubic_prolong, same_state=w.same_state)
+                  nu_pre_W=w.nu_pre_W, nu_post_W=w.nu_post_W, cubic_prolong=w.cubic_prolong,
+                  same_state=w.same_state)
     Kf, K0 = g.cttk_hybrid_sources(ph, r5h, rho1, Sh)
     ph.K = K0
     pc = g.params(n, w.levels, w.bc, g.PREC_FP32_IR, w.length, w.origin, 0.0, w.nu_pre, w.nu_post, True, cttk=True,
-                  nu_post_W=w.nu_post_W, cubic_prolong=w.cubic_prolong, same_state=w.same_state)
+                  nu_pre_W=w.nu_pre_W, nu_post_W=w.nu_post_W, cubic_prolong=w.cubic_prolong,
+                  same_state=w.same_state)
     for name, p, srcs in (("cttk_hybrid", ph, (r5h, rho1, Sh)), ("cttk", pc, (rho5, rho1, S))):
         s = g.Solver(p, *srcs)
         u = torch.zeros((n,) * 3, dtype=torch.float64, device=rho5.device)
@@ -433,7 +436,8 @@ def main():
     n = w.n
     # ---- setup (off the clock): sources on the GPU, K from the mean density
     p = g.params(n, w.levels, w.bc, g.PREC_FP32_IR, w.length, w.origin, 0.0, w.nu_pre,
-                 w.nu_post, True, nu_post_W=w.nu_post_W, cubic_prolong=w.cubic_prolong, same_state=w.same_state)
+                 w.nu_post, True, nu_pre_W=w.nu_pre_W, nu_post_W=w.nu_post_W, cubic_prolong=w.cubic_prolong,
+                 same_state=w.same_state)
     rho5, rho1, S, K = g.scalar_field_sources(p, w.phi_modes, w.pi_modes, w.scalar_mass, dev)
     p.K = K
     mixed = g.Solver(p, rho5, rho1, S)
@@ -538,7 +542,8 @@ def main():
     # ---- mixed + full-multigrid start from the n/2 grid (sources evaluated there)
     wc = synth.coupled(n // 2, seed=args.seed, precision=synth.PREC_FP32_IR)
     pc = g.params(n // 2, wc.levels, wc.bc, g.PREC_FP32_IR, wc.length, wc.origin, K, wc.nu_pre, wc.nu_post, True,
-                  nu_post_W=wc.nu_post_W, cubic_prolong=wc.cubic_prolong, same_state=wc.same_state)
+                  nu_pre_W=wc.nu_pre_W, nu_post_W=wc.nu_post_W, cubic_prolong=wc.cubic_prolong,
+                  same_state=wc.same_state)
     r5c, r1c, Sc, _ = g.scalar_field_sources(pc, wc.phi_modes, wc.pi_modes, wc.scalar_mass, dev)
     coarse = g.Solver(pc, r5c, r1c, Sc)
     uc = torch.zeros((n // 2,) * 3, dtype=torch.float64, device=dev)

@@ -38,7 +38,8 @@ def problem(seed: int, n: int, device, phi_amp: float = 0.05):
     w = synth.coupled(n, seed=seed, phi_amp=phi_amp, precision=g.PREC_FP32_IR)
     p = g.params(w.n, w.levels, w.bc, w.precision, w.length, w.origin, 0.0, w.nu_pre, w.nu_post,
                  w.solve_momentum, w.puncture_mass, w.puncture_pos, w.conformal_matter,
-                 nu_post_W=w.nu_post_W, cubic_prolong=w.cubic_prolong, same_state=w.same_state)
+                 nu_pre_W=w.nu_pre_W, nu_post_W=w.nu_post_W, cubic_prolong=w.cubic_prolong,
+                 same_state=w.same_state)
     r5, r1, S, p.K = g.scalar_field_sources(p, w.phi_modes, w.pi_modes, w.scalar_mass, device)
     return p, r5, r1, S
 

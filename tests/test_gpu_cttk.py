@@ -22,7 +22,7 @@ def sources(w):
 
 def gp(w, precision, K=0.0, cttk=False, levels=None):
     return g.params(w.n, levels if levels is not None else w.levels, w.bc, precision, w.length, w.origin, K,
-                    w.nu_pre, w.nu_post, True, cttk=cttk, nu_post_W=w.nu_post_W,
+                    w.nu_pre, w.nu_post, True, cttk=cttk, nu_pre_W=w.nu_pre_W, nu_post_W=w.nu_post_W,
                     cubic_prolong=w.cubic_prolong, same_state=w.same_state)
 
 

@@ -83,7 +83,8 @@ def test_learned_coarse_start_on_held_out_seeds():
         pf, r5, r1, S = ws.problem(seed, 128, dev())
         wc = synth.coupled(64, seed=seed, precision=g.PREC_FP32_IR)
         pc = g.params(64, wc.levels, wc.bc, g.PREC_FP32_IR, wc.length, wc.origin, pf.K, wc.nu_pre, wc.nu_post, True,
-                      nu_post_W=wc.nu_post_W, cubic_prolong=wc.cubic_prolong, same_state=wc.same_state)
+                      nu_pre_W=wc.nu_pre_W, nu_post_W=wc.nu_post_W, cubic_prolong=wc.cubic_prolong,
+                      same_state=wc.same_state)
         r5c, r1c, Sc, _ = g.scalar_field_sources(pc, wc.phi_modes, wc.pi_modes, wc.scalar_mass, dev())
         fine, coarse = g.Solver(pf, r5, r1, S), g.Solver(pc, r5c, r1c, Sc)
         z = lambda n: torch.zeros((n,) * 3, dtype=torch.float64, device=dev())
@@ -140,7 +141,8 @@ def test_fallback_compares_with_one_zero_start_iteration():
     pf, _, _, _ = ws.problem(seed, 128, dev())
     wc = synth.coupled(64, seed=seed, precision=g.PREC_FP32_IR)
     pc = g.params(64, wc.levels, wc.bc, g.PREC_FP32_IR, wc.length, wc.origin, pf.K, wc.nu_pre, wc.nu_post, True,
-                  nu_post_W=wc.nu_post_W, cubic_prolong=wc.cubic_prolong, same_state=wc.same_state)
+                  nu_pre_W=wc.nu_pre_W, nu_post_W=wc.nu_post_W, cubic_prolong=wc.cubic_prolong,
+                  same_state=wc.same_state)
     r5c, r1c, Sc, _ = g.scalar_field_sources(pc, wc.phi_modes, wc.pi_modes, wc.scalar_mass, dev())
     coarse = g.Solver(pc, r5c, r1c, Sc)
     uc = torch.zeros((64,) * 3, dtype=torch.float64, device=dev())
