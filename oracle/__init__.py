@@ -64,7 +64,7 @@ def build(verbose: bool = False) -> str:
 class OrcParams(C.Structure):
     _fields_ = [("n", C.c_int32), ("levels", C.c_int32), ("bc", C.c_int32),
                 ("nu_pre", C.c_int32), ("nu_post", C.c_int32),
-                ("solve_momentum", C.c_int32), ("flags", C.c_int32), ("pad1", C.c_int32),
+                ("solve_momentum", C.c_int32), ("flags", C.c_int32), ("mix_depth", C.c_int32),
                 ("length", C.c_double), ("origin", C.c_double * 3), ("K", C.c_double),
                 ("puncture_mass", C.c_double), ("puncture_pos", C.c_double * 3),
                 ("bg_psi0", C.c_void_p), ("bg_A2", C.c_void_p)]
@@ -171,12 +171,13 @@ class _Params(OrcParams):
 def params(n, levels=1, bc=BC_PERIODIC, length=1.0, origin=(0.0, 0.0, 0.0), K=0.0,
            nu_pre=2, nu_post=2, solve_momentum=False, puncture_mass=0.0,
            puncture_pos=(0.0, 0.0, 0.0), conformal_matter=False, bg_psi0=None,
-           bg_A2=None, cubic_prolong=False, same_state=False) -> OrcParams:
+           bg_A2=None, cubic_prolong=False, same_state=False, mix_depth=0) -> OrcParams:
     """bg_psi0, bg_A2: optional n^3 fields (several punctures: psi0 in place of
     1 + M/(2r); Bowen-York: A2 of the analytic extrinsic curvature).  cubic_prolong:
     the V-cycles prolong corrections with the 4-point cubic of interp_cubic.
     same_state: the psi step of an outer iteration reads the W the iteration
-    started from, not the W step's result."""
+    started from, not the W step's result.  mix_depth: steps the CTTK solve's
+    Anderson mixing combines (0 or 1: the one-step secant form; at most 8)."""
     p = _Params()
     keep = []
     for name, arr in (("bg_psi0", bg_psi0), ("bg_A2", bg_A2)):
@@ -190,6 +191,8 @@ def params(n, levels=1, bc=BC_PERIODIC, length=1.0, origin=(0.0, 0.0, 0.0), K=0.
                | (FLAG_SAME_STATE if same_state else 0))
     p.n, p.levels, p.bc = n, levels, bc
     p.nu_pre, p.nu_post = nu_pre, nu_post
+    assert 0 <= mix_depth <= 8
+    p.mix_depth = mix_depth
     p.solve_momentum = 1 if solve_momentum else 0
     p.length = length
     for a in range(3):
@@ -203,7 +206,7 @@ def params(n, levels=1, bc=BC_PERIODIC, length=1.0, origin=(0.0, 0.0, 0.0), K=0.
 def params_from_workload(w, K=0.0) -> OrcParams:
     return params(w.n, w.levels, w.bc, w.length, w.origin, K, w.nu_pre, w.nu_post,
                   w.solve_momentum, w.puncture_mass, w.puncture_pos, w.conformal_matter,
-                  cubic_prolong=w.cubic_prolong, same_state=w.same_state)
+                  cubic_prolong=w.cubic_prolong, same_state=w.same_state, mix_depth=w.mix_depth)
 
 
 def _z(n, comps=1):

@@ -92,7 +92,7 @@
 #define OFLAG_SAME_STATE 4
 
 typedef struct {
-    int32_t n, levels, bc, nu_pre, nu_post, solve_momentum, flags, pad1;
+    int32_t n, levels, bc, nu_pre, nu_post, solve_momentum, flags, mix_depth;
     double length, origin[3], K, puncture_mass, puncture_pos[3];
     /* optional fields on the finest grid (NULL: not used): psi0 replacing
      * 1 + M/(2r) (several punctures), and Abar_ij Abar_ij of an analytic
@@ -1063,12 +1063,59 @@ void orc_cttk_update(const orc_params *p, const double *u, const double *W, cons
  * from (u, W), the norms of H_h and M_h with them (H_h vanishes up to rounding), the
  * convergence test, then one W step, W -> W + f.  The K-W coupling makes this a
  * fixed-point iteration whose contraction grows with resolution, so the steps are
- * combined by one-step Anderson mixing (a secant method on the fixed point): with
- * dF = f - f_prev and dW = W - W_prev from the previous iteration,
- *   gamma = <dF, f> / <dF, dF>,   W -> W + f - gamma (dW + dF)
- * (gamma = 0 on the first iteration or when dF = 0).  K receives the trace of the
- * final state.  Status and outputs as orc_solve (p->solve_momentum must be 1).
+ * combined by Anderson mixing over the last m = max(1, p->mix_depth) steps: with the
+ * differences dF_j = f_{j+1} - f_j and dW_j = W_{j+1} - W_j of consecutive steps
+ * (the newest m of them), gamma minimises |f - sum_j gamma_j dF_j| (its normal
+ * equations), and
+ *   W -> W + f - sum_j gamma_j (dW_j + dF_j).
+ * With one stored pair this is the secant step gamma = <dF, f> / <dF, dF> (gamma = 0 on
+ * the first iteration or when dF = 0).  With more, the normal equations carry a ridge of
+ * 1e-12 of their largest diagonal entry and are solved by Gaussian elimination with
+ * partial pivoting (gamma = 0 if that entry is 0).  K receives the trace of the final
+ * state.  Status and outputs as orc_solve (p->solve_momentum must be 1).
  */
+#define OMAXMIX 8
+
+/* gamma of the Anderson step from its normal equations A gamma = b (n x n, symmetric):
+ * one unknown, the secant quotient; more, a ridge of 1e-12 of the largest diagonal entry
+ * and Gaussian elimination with partial pivoting.  gamma = 0 when A vanishes. */
+static void mix_solve(double *A, double *b, int n, double *gam)
+{
+    if (n == 1) {
+        gam[0] = A[0] > 0.0 ? b[0] / A[0] : 0.0;
+        return;
+    }
+    double dmax = 0.0;
+    for (int i = 0; i < n; i++) dmax = fmax(dmax, A[i * n + i]);
+    if (!(dmax > 0.0)) return;
+    for (int i = 0; i < n; i++) A[i * n + i] += 1e-12 * dmax;
+    for (int k = 0; k < n; k++) {
+        int piv = k;
+        for (int i = k + 1; i < n; i++)
+            if (fabs(A[i * n + k]) > fabs(A[piv * n + k])) piv = i;
+        if (piv != k) {
+            for (int j = 0; j < n; j++) {
+                const double t = A[k * n + j];
+                A[k * n + j] = A[piv * n + j];
+                A[piv * n + j] = t;
+            }
+            const double t = b[k];
+            b[k] = b[piv];
+            b[piv] = t;
+        }
+        for (int i = k + 1; i < n; i++) {
+            const double l = A[i * n + k] / A[k * n + k];
+            for (int j = k; j < n; j++) A[i * n + j] -= l * A[k * n + j];
+            b[i] -= l * b[k];
+        }
+    }
+    for (int i = n - 1; i >= 0; i--) {
+        double v = b[i];
+        for (int j = i + 1; j < n; j++) v -= A[i * n + j] * gam[j];
+        gam[i] = v / A[i * n + i];
+    }
+}
+
 int orc_cttk_solve(const orc_params *p, const double *u, double *W, const double *rho5, const double *rho1,
                    const double *S, const double *f, double *K, double tol, int max_outer, double *hist,
                    int hist_cap, int *iters, double out_norms[4])
@@ -1083,6 +1130,10 @@ int orc_cttk_solve(const orc_params *p, const double *u, double *W, const double
     double *Wk = (double *)malloc(3 * m * sizeof(double));
     double *Wp = (double *)malloc(3 * m * sizeof(double));
     double *fp = (double *)malloc(3 * m * sizeof(double));
+    const int depth = p->mix_depth > 1 ? p->mix_depth : 1;
+    double *dWs = (double *)malloc((size_t)depth * 3 * m * sizeof(double));
+    double *dFs = (double *)malloc((size_t)depth * 3 * m * sizeof(double));
+    int count = 0, head = 0;
     sources s = {r5, rho1, Se, f};
     hier HW;
     hier_init(&HW, &p0, 3);
@@ -1111,19 +1162,38 @@ int orc_cttk_solve(const orc_params *p, const double *u, double *W, const double
             status = 1;
             break;
         }
-        /* W now holds W_k + f; Anderson mixing with the previous step */
-        double sfd = 0.0, sdd = 0.0;
-        if (it > 0)
+        /* W now holds W_k + f; Anderson mixing with the stored differences */
+        if (it > 0) { /* the newest difference pair replaces the oldest */
+            double *dWn = dWs + (long)head * 3 * m, *dFn = dFs + (long)head * 3 * m;
             for (long q = 0; q < 3 * m; q++) {
-                double fk = W[q] - Wk[q], dF = fk - fp[q];
-                sfd += dF * fk;
-                sdd += dF * dF;
+                dFn[q] = (W[q] - Wk[q]) - fp[q];
+                dWn[q] = Wk[q] - Wp[q];
             }
-        double gamma = (it > 0 && sdd > 0.0) ? sfd / sdd : 0.0;
+            if (count < depth) count++;
+            head = (head + 1) % depth;
+        }
+        double gam[OMAXMIX] = {0.0};
+        if (count > 0) {
+            double A[OMAXMIX * OMAXMIX], b[OMAXMIX];
+            for (int i = 0; i < count; i++) {
+                const double *Fi = dFs + (long)i * 3 * m;
+                double bi = 0.0;
+                for (long q = 0; q < 3 * m; q++) bi += Fi[q] * (W[q] - Wk[q]);
+                b[i] = bi;
+                for (int j = 0; j <= i; j++) {
+                    const double *Fj = dFs + (long)j * 3 * m;
+                    double a = 0.0;
+                    for (long q = 0; q < 3 * m; q++) a += Fi[q] * Fj[q];
+                    A[i * count + j] = A[j * count + i] = a;
+                }
+            }
+            mix_solve(A, b, count, gam);
+        }
         for (long q = 0; q < 3 * m; q++) {
-            double fk = W[q] - Wk[q];
-            double dF = fk - fp[q], dW = Wk[q] - Wp[q];
-            W[q] = Wk[q] + fk - (it > 0 ? gamma * (dW + dF) : 0.0);
+            const double fk = W[q] - Wk[q];
+            double corr = 0.0;
+            for (int j = 0; j < count; j++) corr += gam[j] * (dWs[(long)j * 3 * m + q] + dFs[(long)j * 3 * m + q]);
+            W[q] = Wk[q] + fk - corr;
             Wp[q] = Wk[q];
             fp[q] = fk;
         }
@@ -1133,6 +1203,8 @@ int orc_cttk_solve(const orc_params *p, const double *u, double *W, const double
     free(Wk);
     free(Wp);
     free(fp);
+    free(dWs);
+    free(dFs);
     free(r5);
     free(Se);
     free(H);

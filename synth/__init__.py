@@ -82,6 +82,8 @@ class Workload:
     cubic_prolong: bool = False
     # both steps of an outer iteration linearised at the state it starts from
     same_state: bool = False
+    # steps the CTTK solve's Anderson mixing combines (0 or 1: one step)
+    mix_depth: int = 0
     scalar_mass: float = 1.0
     phi_modes: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 5)))
     pi_modes: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 5)))

@@ -180,3 +180,78 @@ def test_planted_mistake_is_caught(plant, check):
         with pytest.raises(AssertionError):
             check()
     check()
+
+
+# ---- Anderson mixing over several steps ----------------------------------------------------
+
+def anderson_reference(w, rho5, rho1, S, depth, iters):
+    """The CTTK iteration written out over the oracle's own single steps (the trace and
+    shifted sources of the state, one W step at K = 0), mixed in numpy: gamma minimises
+    |f - sum_j gamma_j dF_j| over the newest `depth` difference pairs (the secant quotient
+    for one pair; a ridge of 1e-12 of the largest Gram diagonal entry for more), and
+    W -> W + f - sum_j gamma_j (dW_j + dF_j)."""
+    n = w.n
+    p0 = oracle.params_from_workload(w)
+    p0.K = 0.0
+    u = np.zeros((n,) * 3)
+    W = np.zeros((3, n, n, n))
+    dWs, dFs = [], []
+    Wp = fp = None
+    for it in range(iters):
+        r5e, Se, _ = oracle.cttk_update(p0, u, W, rho5, rho1, S)
+        Wk = W.copy()
+        oracle.step(p0, 2, u, W, r5e, rho1, Se)
+        f = W - Wk
+        if it > 0:
+            dFs.append(f - fp)
+            dWs.append(Wk - Wp)
+            dFs, dWs = dFs[-depth:], dWs[-depth:]
+        gam = np.zeros(len(dFs))
+        if dFs:
+            F = np.stack([d.ravel() for d in dFs])
+            A, b = F @ F.T, F @ f.ravel()
+            if len(dFs) == 1:
+                gam[0] = b[0] / A[0, 0] if A[0, 0] > 0 else 0.0
+            else:
+                A = A + 1e-12 * A.diagonal().max() * np.eye(len(dFs))
+                gam = np.linalg.solve(A, b)
+        W = Wk + f - sum(g * (dw + df) for g, dw, df in zip(gam, dWs, dFs))
+        Wp, fp = Wk, f
+    return W
+
+
+@pytest.mark.parametrize("depth", [1, 3, 5])
+def test_mixing_over_several_steps_matches_its_definition(depth):
+    w, rho5, rho1, S = workload()
+    w.mix_depth = depth
+    n = w.n
+    u = np.zeros((n,) * 3)
+    W = np.zeros((3, n, n, n))
+    res, _ = oracle.cttk_solve(oracle.params_from_workload(w), u, W, rho5, rho1, S, tol=1e-30, max_outer=7)
+    assert res.iters == 7
+    ref = anderson_reference(w, rho5, rho1, S, depth, 7)
+    assert np.abs(W - ref).max() <= 1e-9 * np.abs(ref).max()
+
+
+def test_deeper_mixing_needs_fewer_iterations():
+    w, rho5, rho1, S = workload(32)
+    its = {}
+    for depth in (1, 5):
+        w.mix_depth = depth
+        u = np.zeros((32,) * 3)
+        W = np.zeros((3, 32, 32, 32))
+        res, K = oracle.cttk_solve(oracle.params_from_workload(w), u, W, rho5, rho1, S, tol=1e-10, max_outer=200)
+        assert res.status == 0, res
+        H, M, _ = judge.residuals(grid(w), u, W, rho5, rho1, S, K)
+        assert max(judge.norms(H, M)[:2]) <= 1.01e-10
+        its[depth] = res.iters
+    print(f"CTTK 32^3 iterations: one-step mixing {its[1]}, five steps {its[5]}")
+    assert its[5] < its[1]
+
+
+def test_mixing_planted_mistake_is_caught():
+    # the newest difference pair stored with the wrong sign of dW
+    with oracle.planted([("dWn[q] = Wk[q] - Wp[q];", "dWn[q] = Wp[q] - Wk[q];")]):
+        with pytest.raises(AssertionError):
+            test_mixing_over_several_steps_matches_its_definition(3)
+    test_mixing_over_several_steps_matches_its_definition(3)
