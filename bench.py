@@ -281,7 +281,7 @@ def bench_methods(g, w, K, rho5, rho1, S, args, log):
     ph.K = K0
     pc = g.params(n, w.levels, w.bc, g.PREC_FP32_IR, w.length, w.origin, 0.0, w.nu_pre, w.nu_post, True, cttk=True,
                   nu_pre_W=w.nu_pre_W, nu_post_W=w.nu_post_W, cubic_prolong=w.cubic_prolong,
-                  same_state=w.same_state)
+                  same_state=w.same_state, mix_depth=w.mix_depth)
     for name, p, srcs in (("cttk_hybrid", ph, (r5h, rho1, Sh)), ("cttk", pc, (rho5, rho1, S))):
         s = g.Solver(p, *srcs)
         u = torch.zeros((n,) * 3, dtype=torch.float64, device=rho5.device)
@@ -308,7 +308,8 @@ def bench_methods(g, w, K, rho5, rho1, S, args, log):
         out[f"{name}_{n}"] = dict(seconds=sec, outer_iters=r["outer_iters"], vcycles_psi=r["vcycles_psi"],
                                   vcycles_W=r["vcycles_W"], h_rms=r["h_rms"], m_rms=r["m_rms"],
                                   K_min=float(Kt.min()), K_max=float(Kt.max()),
-                                  K0=K0 if name == "cttk_hybrid" else None)
+                                  K0=K0 if name == "cttk_hybrid" else None,
+                                  anderson_depth=max(1, w.mix_depth) if name == "cttk" else None)
         log(f"[bench] {name}_{n}: {sec * 1e3:.3f} ms/solve, outer={r['outer_iters']}, K {float(Kt.min()):.3f}.."
             f"{float(Kt.max()):.3f} (CTT K = {K:.3f})")
         s.close()

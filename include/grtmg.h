@@ -148,6 +148,11 @@ enum {
  *                 correction is then exact, and one post-sweep can do what two do
  *                 above a multigrid bottom.  Without the exact bottom the W cycle
  *                 uses nu_pre / nu_post.
+ *  mix_depth      MG_FLAG_CTTK solves: steps the Anderson mixing of the W fixed
+ *                 point combines (0 or 1: the one-step secant form; 2 .. 6: least
+ *                 squares over the newest mix_depth difference pairs, with a ridge of
+ *                 1e-12 of the largest Gram diagonal entry; the workspace grows by
+ *                 2 mix_depth 3 n^3 doubles).  Ignored without MG_FLAG_CTTK.
  */
 typedef struct mg_params {
     int32_t n, levels, bc, precision, nu_pre, nu_post, solve_momentum, flags;
@@ -157,6 +162,7 @@ typedef struct mg_params {
     double puncture_mass;
     double puncture_pos[3];
     int32_t nu_pre_W, nu_post_W;
+    int32_t mix_depth;
 } mg_params;
 
 /* Per-solve report.  history (host, caller-owned, may be NULL) receives

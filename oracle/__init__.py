@@ -177,7 +177,7 @@ def params(n, levels=1, bc=BC_PERIODIC, length=1.0, origin=(0.0, 0.0, 0.0), K=0.
     the V-cycles prolong corrections with the 4-point cubic of interp_cubic.
     same_state: the psi step of an outer iteration reads the W the iteration
     started from, not the W step's result.  mix_depth: steps the CTTK solve's
-    Anderson mixing combines (0 or 1: the one-step secant form; at most 8)."""
+    Anderson mixing combines (0 or 1: the one-step secant form; at most 6)."""
     p = _Params()
     keep = []
     for name, arr in (("bg_psi0", bg_psi0), ("bg_A2", bg_A2)):
@@ -191,7 +191,7 @@ def params(n, levels=1, bc=BC_PERIODIC, length=1.0, origin=(0.0, 0.0, 0.0), K=0.
                | (FLAG_SAME_STATE if same_state else 0))
     p.n, p.levels, p.bc = n, levels, bc
     p.nu_pre, p.nu_post = nu_pre, nu_post
-    assert 0 <= mix_depth <= 8
+    assert 0 <= mix_depth <= 6
     p.mix_depth = mix_depth
     p.solve_momentum = 1 if solve_momentum else 0
     p.length = length

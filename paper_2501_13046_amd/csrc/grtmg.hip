@@ -146,6 +146,9 @@ struct mg_ctx {
     const double *rho5_in, *S_in;
     double *rho5_eff, *S_eff, *Kf;
     double *aa_W, *aa_f; // Anderson mixing history of the CTTK solve: previous W and step (3 n^3 each)
+    // mixing over mix_depth >= 2 steps: rings of difference pairs dG = dW + dF and dF
+    // (mix_depth x 3 n^3 each) and its device state {pairs stored, next slot, steps, .., gamma_0 ..}
+    double *aa_dG, *aa_dF, *aa_st;
     int vc_psi, vc_W;
     // batch membership: streams borrowed from the batch, updates gated by the
     // instance's active flag, a convergence check after every evaluation
@@ -189,6 +192,7 @@ mg_status validate(const mg_params *p)
     // the finest level's first pre-smoothing pass comes with the residual: nu_pre >= 1
     if (p->nu_pre < 1 || p->nu_post < 1 || p->nu_pre > 16 || p->nu_post > 16) return MG_ERR_INVALID;
     if (p->nu_pre_W < 0 || p->nu_post_W < 0 || p->nu_pre_W > 16 || p->nu_post_W > 16) return MG_ERR_INVALID;
+    if (p->mix_depth < 0 || p->mix_depth > kMixMax) return MG_ERR_INVALID;
     if (p->solve_momentum != 0 && p->solve_momentum != 1) return MG_ERR_INVALID;
     if (p->solve_momentum && p->bc != MG_BC_PERIODIC) return MG_ERR_INVALID;
     // the W kernels address one component with 32-bit byte offsets
@@ -255,7 +259,8 @@ void carve(mg_ctx *c, Carver &cv)
     const int ls = spectral_level(c);
     c->specZ = ls >= 0 && c->n[ls] > kFourierN ? (float2 *)cv.take(3 * c->cells[ls] * sizeof(float2)) : nullptr;
     const int64_t nb = nblk(c->cells[0]);
-    c->part = (double *)cv.take((size_t)nb * 4 * sizeof(double));
+    // 4 partials per block of the finest level, and room for one block of the Anderson sums
+    c->part = (double *)cv.take((size_t)std::max<int64_t>(nb * 4, kMixState) * sizeof(double));
     c->part_w = (p.flags & MG_FLAG_SAME_STATE) && c->momentum
                     ? (double *)cv.take((size_t)sum_blocks(c->cells[0]) * 3 * sizeof(double))
                     : nullptr;
@@ -266,8 +271,16 @@ void carve(mg_ctx *c, Carver &cv)
         c->Kf = (double *)cv.take(m0);
         c->aa_W = (double *)cv.take(3 * m0);
         c->aa_f = (double *)cv.take(3 * m0);
+        if (p.mix_depth >= 2) {
+            c->aa_dG = (double *)cv.take((size_t)p.mix_depth * 3 * m0);
+            c->aa_dF = (double *)cv.take((size_t)p.mix_depth * 3 * m0);
+            c->aa_st = (double *)cv.take(kMixState * sizeof(double));
+        } else {
+            c->aa_dG = c->aa_dF = c->aa_st = nullptr;
+        }
     } else {
         c->rho5_eff = c->S_eff = c->Kf = c->aa_W = c->aa_f = nullptr;
+        c->aa_dG = c->aa_dF = c->aa_st = nullptr;
     }
     c->scal = (double *)cv.take(S_COUNT * sizeof(double));
     c->m_psi = (int)c->cells[c->L - 1];
@@ -980,6 +993,24 @@ void residual(mg_ctx *c, const double *u, const double *W, bool want_M, double *
                            0xAu, 0.0, c->scal + S_NORM, c->zs);
 }
 
+// The CTTK update mixed over the last D >= 2 steps: the newest difference pair and the
+// normal-equation sums in one pass, their reduction, gamma, the update.
+template <typename T, int D>
+void mix_ring(mg_ctx *c, double *W, int64_t m, unsigned db)
+{
+    constexpr int NV = mix_nv<D>();
+    hipLaunchKernelGGL((k_aa_push_dots<T, D>), dim3(db), dim3(kBlock), 0, c->s, (const T *)c->wd0[0],
+                       (const double *)(c->scal + S_MEAND), (const double *)W, (const double *)c->aa_W,
+                       (const double *)c->aa_f, c->aa_dG, c->aa_dF, (const double *)c->aa_st, m, c->part);
+    hipLaunchKernelGGL(k_reduce_final<NV>, dim3(1), dim3(kBlock), 0, c->s, (const double *)c->part, (int64_t)db, 0u,
+                       0.0, c->aa_st + kMixRed, 0LL);
+    hipLaunchKernelGGL(k_aa_solve<D>, dim3(1), dim3(64), 0, c->s, (const double *)(c->aa_st + kMixRed), c->aa_st);
+    Probe pr(c, MG_PROBE_UPDATE, 0);
+    hipLaunchKernelGGL((k_aa_update_ring<T, D>), dim3(nblk(3 * m)), dim3(kBlock), 0, c->s, W, (const T *)c->wd0[0],
+                       (const double *)(c->scal + S_MEAND), c->aa_W, c->aa_f, (const double *)c->aa_dG,
+                       (const double *)c->aa_st, m);
+}
+
 // mix: the CTTK solve's Anderson-mixed update in place of W += d - mean(d).
 template <typename T>
 void step_W(mg_ctx *c, const double *u, double *W, bool residual_done, bool mix = false)
@@ -996,7 +1027,19 @@ void step_W(mg_ctx *c, const double *u, double *W, bool residual_done, bool mix 
     hipLaunchKernelGGL(k_sum3<T>, dim3(sb, 1, c->gz), dim3(kBlock), 0, c->s, (const T *)c->wd0[0], m, part, c->zs);
     hipLaunchKernelGGL(k_reduce_final<3>, dim3(1, 1, c->gz), dim3(kBlock), 0, c->s, (const double *)part, sb, 0u,
                        1.0 / (double)m, c->scal + S_MEAND, c->zs);
-    if (mix) {
+    if (mix && c->aa_st) {
+        // mix_nv(D) partials per block in c->part (4 per block of the finest level)
+        const int D = c->p.mix_depth, nv = D + D * (D + 1) / 2;
+        const unsigned db = std::max<unsigned>(
+            1u, std::min<unsigned>(std::min<unsigned>(nblk(3 * m), kSrcBlocks), (unsigned)(4 * nb / nv)));
+        switch (D) {
+        case 2: mix_ring<T, 2>(c, W, m, db); break;
+        case 3: mix_ring<T, 3>(c, W, m, db); break;
+        case 4: mix_ring<T, 4>(c, W, m, db); break;
+        case 5: mix_ring<T, 5>(c, W, m, db); break;
+        default: mix_ring<T, 6>(c, W, m, db); break;
+        }
+    } else if (mix) {
         // two partials per block in c->part (4 per block of the finest level)
         const unsigned db = std::min<unsigned>(std::min<unsigned>(nblk(3 * m), kSrcBlocks), 2 * (unsigned)nb);
         hipLaunchKernelGGL(k_aa_dots<T>, dim3(db), dim3(kBlock), 0, c->s, (const T *)c->wd0[0],
@@ -1262,6 +1305,7 @@ mg_status solve(mg_ctx *c, double *u, double *W, double tol, int max_outer, mg_r
     c->cont_valid = false;
     fill<double>(c->s, c->scal + S_FLAG_PSI, 2, 0.0, c->gz, c->zs);
     if (c->cttk) fill<double>(c->s, c->scal + S_AA, 4, 0.0); // the mixing restarts with every solve
+    if (c->aa_st) fill<double>(c->s, c->aa_st, kMixState, 0.0);
     if (!resume) {
         evaluate<T>(c, u, W, want_M);
         if (post_norms(c, 0) != MG_OK) return MG_ERR_HIP;
@@ -1820,7 +1864,8 @@ bool same_group(const mg_params &a, const mg_params &b)
 {
     mg_params x = a, y = b;
     x.K = y.K = 0.0;
-    return std::memcmp(&x, &y, sizeof(mg_params)) == 0;
+    // the fields only: the struct's tail padding holds whatever the caller left there
+    return std::memcmp(&x, &y, offsetof(mg_params, mix_depth) + sizeof(x.mix_depth)) == 0;
 }
 
 // A group runs as one launch per kernel only if every kernel of its path takes the

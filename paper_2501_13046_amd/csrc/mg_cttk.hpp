@@ -126,4 +126,137 @@ __global__ void __launch_bounds__(kBlock) k_aa_update(double *__restrict__ W, co
     f_prev[q] = f;
 }
 
+// Anderson mixing over the last D >= 2 steps.  Ring slots j < D hold, for consecutive
+// steps, dF_j = f - f_prev and dG_j = dW_j + dF_j with dW_j = W - W_prev (slot j at
+// j * 3m; the update needs only their sum); the newest pair replaces the oldest.  st = {pairs stored, slot of the next pair, steps
+// taken, unused x5, gamma_0 .. gamma_{D-1}, unused up to 16, the reduced sums}.  gamma minimises |f - sum_j gamma_j dF_j|
+// through its normal equations: the secant quotient for one stored pair; for more, a
+// ridge of 1e-12 of the largest Gram diagonal entry and Gaussian elimination with
+// partial pivoting (gamma = 0 if that entry is 0); W -> W + f - sum_j gamma_j (dW_j + dF_j).
+constexpr int kMixMax = 6; // mix_nv<6>() = 27 sums: within the 32 of one reduction mask
+template <int D>
+constexpr int mix_nv()
+{
+    return D + D * (D + 1) / 2;
+}
+constexpr int kMixRed = 16; // offset of the reduced sums in the state
+constexpr int kMixState = kMixRed + mix_nv<kMixMax>();
+
+// One pass over the 3m values: from the second step on the newest pair (dG, dF) into its slot,
+// and block partials of <dF_i, f> (i < D), then <dF_i, dF_j> (j <= i), over the
+// stored pairs (zero for slots not yet filled).
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_aa_push_dots(const T *__restrict__ d, const double *__restrict__ mean,
+                                                         const double *__restrict__ W,
+                                                         const double *__restrict__ W_prev,
+                                                         const double *__restrict__ f_prev, double *__restrict__ dG_ring,
+                                                         double *__restrict__ dF_ring, const double *__restrict__ st,
+                                                         int64_t m, double *__restrict__ partials)
+{
+    constexpr int NV = mix_nv<D>();
+    const int64_t n3 = 3 * m;
+    const bool push = st[2] > 0.0;
+    const int head = (int)st[1];
+    const int cnt = min((int)st[0] + (push ? 1 : 0), D);
+    double v[NV];
+#pragma unroll
+    for (int k = 0; k < NV; k++) v[k] = 0.0;
+    for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < n3; q += (int64_t)gridDim.x * kBlock) {
+        const double f = (double)d[q] - mean[q / m];
+        const double dFn = push ? f - f_prev[q] : 0.0;
+        if (push) {
+            dF_ring[head * n3 + q] = dFn;
+            dG_ring[head * n3 + q] = (W[q] - W_prev[q]) + dFn;
+        }
+        double F[D];
+#pragma unroll
+        for (int i = 0; i < D; i++) F[i] = i >= cnt ? 0.0 : (push && i == head) ? dFn : dF_ring[i * n3 + q];
+        int k = D;
+#pragma unroll
+        for (int i = 0; i < D; i++) {
+            v[i] += F[i] * f;
+#pragma unroll
+            for (int j = 0; j <= i; j++) v[k++] += F[i] * F[j];
+        }
+    }
+    block_reduce_store<NV>(v, 0u, partials + (int64_t)NV * blockIdx.x);
+}
+
+// gamma from the reduced sums red (layout of k_aa_push_dots); counts the pair and the step.
+template <int D>
+__global__ void k_aa_solve(const double *__restrict__ red, double *__restrict__ st)
+{
+    if (threadIdx.x != 0) return;
+    const bool push = st[2] > 0.0;
+    const int cnt = min((int)st[0] + (push ? 1 : 0), D);
+    double A[D * D], b[D], g[D];
+    for (int i = 0; i < D; i++) g[i] = 0.0;
+    for (int i = 0; i < cnt; i++) {
+        b[i] = red[i];
+        for (int j = 0; j <= i; j++) A[i * cnt + j] = A[j * cnt + i] = red[D + i * (i + 1) / 2 + j];
+    }
+    if (cnt == 1) {
+        g[0] = A[0] > 0.0 ? b[0] / A[0] : 0.0;
+    } else if (cnt > 1) {
+        double dmax = 0.0;
+        for (int i = 0; i < cnt; i++) dmax = fmax(dmax, A[i * cnt + i]);
+        if (dmax > 0.0) {
+            for (int i = 0; i < cnt; i++) A[i * cnt + i] += 1e-12 * dmax;
+            for (int k = 0; k < cnt; k++) {
+                int piv = k;
+                for (int i = k + 1; i < cnt; i++)
+                    if (fabs(A[i * cnt + k]) > fabs(A[piv * cnt + k])) piv = i;
+                if (piv != k) {
+                    for (int j = 0; j < cnt; j++) {
+                        const double t = A[k * cnt + j];
+                        A[k * cnt + j] = A[piv * cnt + j];
+                        A[piv * cnt + j] = t;
+                    }
+                    const double t = b[k];
+                    b[k] = b[piv];
+                    b[piv] = t;
+                }
+                for (int i = k + 1; i < cnt; i++) {
+                    const double l = A[i * cnt + k] / A[k * cnt + k];
+                    for (int j = k; j < cnt; j++) A[i * cnt + j] -= l * A[k * cnt + j];
+                    b[i] -= l * b[k];
+                }
+            }
+            for (int i = cnt - 1; i >= 0; i--) {
+                double x = b[i];
+                for (int j = i + 1; j < cnt; j++) x -= A[i * cnt + j] * g[j];
+                g[i] = x / A[i * cnt + i];
+            }
+        }
+    }
+    for (int i = 0; i < D; i++) st[8 + i] = g[i];
+    st[0] = (double)cnt;
+    if (push) st[1] = (double)((int)(st[1] + 0.5) + 1 == D ? 0 : (int)(st[1] + 0.5) + 1);
+    st[2] += 1.0;
+}
+
+// W -> W + f - sum_j gamma_j dG_j over the stored pairs; the history becomes
+// W_prev = W, f_prev = f.
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_aa_update_ring(double *__restrict__ W, const T *__restrict__ d,
+                                                           const double *__restrict__ mean,
+                                                           double *__restrict__ W_prev, double *__restrict__ f_prev,
+                                                           const double *__restrict__ dG_ring,
+                                                           const double *__restrict__ st, int64_t m)
+{
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t n3 = 3 * m;
+    if (q >= n3) return;
+    const int cnt = (int)st[0];
+    const double f = (double)d[q] - mean[q / m];
+    const double w = W[q];
+    double mix = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; j++)
+        if (j < cnt) mix += st[8 + j] * dG_ring[j * n3 + q];
+    W[q] = w + f - mix;
+    W_prev[q] = w;
+    f_prev[q] = f;
+}
+
 } // namespace grtmg

@@ -277,6 +277,7 @@ __global__ void __launch_bounds__(kBlock) k_reduce_final(const double *partials,
                                                          unsigned max_mask, double scale,
                                                          double *out, long long zs)
 {
+    static_assert(NV >= 1 && NV <= 32, "max_mask holds one bit per value");
     partials = zsh(partials, zs);
     out = zsh(out, zs);
     double v[NV];

@@ -40,7 +40,7 @@ class MgParams(C.Structure):
                 ("solve_momentum", C.c_int32), ("flags", C.c_int32),
                 ("length", C.c_double), ("origin", C.c_double * 3), ("K", C.c_double),
                 ("puncture_mass", C.c_double), ("puncture_pos", C.c_double * 3),
-                ("nu_pre_W", C.c_int32), ("nu_post_W", C.c_int32)]
+                ("nu_pre_W", C.c_int32), ("nu_post_W", C.c_int32), ("mix_depth", C.c_int32)]
 
 
 class MgReport(C.Structure):
@@ -156,15 +156,17 @@ def params(n: int, levels: int = 1, bc: int = BC_PERIODIC, precision: int = PREC
            nu_post: int = 2, solve_momentum: bool = False, puncture_mass: float = 0.0,
            puncture_pos=(0.0, 0.0, 0.0), conformal_matter: bool = False,
            eager: bool = False, cttk: bool = False, nu_pre_W: int = 0, nu_post_W: int = 0,
-           cubic_prolong: bool = False, same_state: bool = False) -> MgParams:
+           cubic_prolong: bool = False, same_state: bool = False, mix_depth: int = 0) -> MgParams:
     """nu_pre_W / nu_post_W: sweeps of the W V-cycle while its bottom is exact (see
     fourier_level; 0: nu_pre / nu_post).  cubic_prolong: corrections prolonged by the
     4-point cubic (MG_FLAG_CUBIC_PROLONG).  same_state: both steps of an outer
-    iteration from one state (MG_FLAG_SAME_STATE)."""
+    iteration from one state (MG_FLAG_SAME_STATE).  mix_depth: steps the CTTK
+    solve's Anderson mixing combines (0 or 1: one step)."""
     p = MgParams()
     p.n, p.levels, p.bc, p.precision = n, levels, bc, precision
     p.nu_pre, p.nu_post = nu_pre, nu_post
     p.nu_pre_W, p.nu_post_W = nu_pre_W, nu_post_W
+    p.mix_depth = mix_depth
     p.solve_momentum = 1 if solve_momentum else 0
     p.flags = ((FLAG_CONFORMAL_MATTER if conformal_matter else 0) | (FLAG_EAGER if eager else 0)
                | (FLAG_CTTK if cttk else 0) | (FLAG_CUBIC_PROLONG if cubic_prolong else 0)

@@ -130,13 +130,15 @@ def coupled(n: int = 128, seed: int = 0, phi_amp: float = 0.05,
     # psi V(2,2) W V(2,1) 3.72-3.78 / 4.11-4.19; psi V(1,2) W V(1,1) 3.76-3.97 / 3.87-3.92 with
     # 10 iterations; psi V(1,4) 3.94 / 4.42; the two steps in sequence with V(2,2) 4.78 / 4.85).
     # FP64 (the W cycle with the psi sweeps): V(1,3) 10.27 ms / 10 iterations, V(2,2) 10.50,
-    # V(1,2) 10.21 / 12, V(2,1) 10.49 / 12.
+    # V(1,2) 10.21 / 12, V(2,1) 10.49 / 12.  CTTK on this workload mixes the last 3 W steps
+    # (128^3: 20.8 ms / 39 iterations; one step 23.4 / 51, 5 steps 21.1 / 34, 6 steps 23.4 / 35:
+    # each stored step costs two more passes over 3 n^3 doubles per iteration).
     return Workload(name=f"coupled_{n}", n=n,
                     levels=levels if levels is not None else coarsest_levels(n),
                     seed=seed, phi_modes=fourier_modes(rng_phi, 8, phi_amp),
                     pi_modes=fourier_modes(rng_pi, 8, 0.02),
                     precision=precision, solve_momentum=True, nu_pre=1, nu_post=3, nu_pre_W=1, nu_post_W=2,
-                    cubic_prolong=True, same_state=True)
+                    cubic_prolong=True, same_state=True, mix_depth=3)
 
 
 def coupled_128(seed: int = 0, precision: int = PREC_FP32_IR) -> Workload:

@@ -37,7 +37,7 @@ def test_exports_every_declared_symbol(g):
 
 
 def test_struct_layouts(g):
-    assert C.sizeof(g.MgParams) == 8 * 4 + 9 * 8 + 2 * 4
+    assert C.sizeof(g.MgParams) == 8 * 4 + 9 * 8 + 3 * 4 + 4  # padded to the 8-byte alignment of its doubles
     assert g.MgParams.nu_pre_W.offset == 8 * 4 + 9 * 8
     assert g.MgParams.length.offset == 32
     assert C.sizeof(g.MgReport) == 4 * 4 + 5 * 8 + 8 + 8
@@ -58,7 +58,8 @@ def test_workspace_size_and_validation(g):
            g.params(32, 4, nu_pre=0, nu_post=0),
            g.params(32, 4, nu_pre=0, nu_post=2),  # the first pre-sweep pass comes with the residual
            g.params(32, 4, solve_momentum=True, nu_post_W=17),
-           g.params(32, 4, solve_momentum=True, nu_pre_W=-1)]
+           g.params(32, 4, solve_momentum=True, nu_pre_W=-1),
+           g.params(32, 4, solve_momentum=True, cttk=True, mix_depth=7)]
     unknown = g.params(32, 4, solve_momentum=True)
     unknown.flags = 32  # no such flag
     bad.append(unknown)

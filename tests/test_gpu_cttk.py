@@ -23,7 +23,7 @@ def sources(w):
 def gp(w, precision, K=0.0, cttk=False, levels=None):
     return g.params(w.n, levels if levels is not None else w.levels, w.bc, precision, w.length, w.origin, K,
                     w.nu_pre, w.nu_post, True, cttk=cttk, nu_pre_W=w.nu_pre_W, nu_post_W=w.nu_post_W,
-                    cubic_prolong=w.cubic_prolong, same_state=w.same_state)
+                    cubic_prolong=w.cubic_prolong, same_state=w.same_state, mix_depth=w.mix_depth)
 
 
 def judge_norms(w, u, W, rho5, rho1, S, K):
@@ -192,3 +192,47 @@ def test_cttk_invalid_parameters():
     with pytest.raises(g.MGError):
         s.cttk_trace(z, torch.zeros((3, 16, 16, 16), dtype=torch.float64, device=dev()))
     s.close()
+
+
+@pytest.mark.parametrize("depth", [3, 5])
+def test_cttk_mixing_over_several_steps_matches_oracle(depth):
+    """Anderson mixing over the last `depth` steps (ring of difference pairs, the normal
+    equations solved on the device inside the captured iteration): the first seven mixed
+    iterations element by element (FP64), then the converged solve in both precisions
+    against the oracle's, in fewer iterations than the one-step mixing."""
+    n = 32
+    w = synth.coupled(n, seed=9)
+    w.mix_depth = depth
+    rho5, rho1, S = sources(w)
+    po = oracle.params_from_workload(w)
+    u0 = np.zeros((n,) * 3)
+    s = cttk_setup(w, g.PREC_FP64, rho5, rho1, S)
+    u = T(u0)
+    W = torch.zeros((3, n, n, n), dtype=torch.float64, device=dev())
+    s.solve(u, W, tol=1e-30, max_outer=7, raise_on_failure=False)
+    Wo = np.zeros((3, n, n, n))
+    oracle.cttk_solve(po, u0.copy(), Wo, rho5, rho1, S, tol=1e-30, max_outer=7)
+    assert rel_err(mean_free(N(W)), mean_free(Wo)) < 1e-10
+    s.close()
+    its = {}
+    for prec in (g.PREC_FP64, g.PREC_FP32_IR):
+        s = cttk_setup(w, prec, rho5, rho1, S)
+        W = torch.zeros((3, n, n, n), dtype=torch.float64, device=dev())
+        rep = s.solve(T(u0), W, tol=1e-10, max_outer=80)
+        K = N(s.cttk_trace(T(u0), W))
+        nr = judge_norms(w, u0, N(W), rho5, rho1, S, K)
+        assert nr[0] <= 1.01e-10 and nr[1] <= 1.01e-10, nr
+        its[prec] = rep["outer_iters"]
+        s.close()
+    Wo = np.zeros((3, n, n, n))
+    res, _ = oracle.cttk_solve(po, u0.copy(), Wo, rho5, rho1, S, tol=1e-11, max_outer=80)
+    assert res.status == 0
+    assert rel_err(mean_free(N(W)), mean_free(Wo)) < 1e-7
+    w1 = synth.coupled(n, seed=9)
+    w1.mix_depth = 1  # the one-step secant form
+    s1 = cttk_setup(w1, g.PREC_FP32_IR, rho5, rho1, S)
+    W1 = torch.zeros((3, n, n, n), dtype=torch.float64, device=dev())
+    one = s1.solve(T(u0), W1, tol=1e-10, max_outer=80)["outer_iters"]
+    s1.close()
+    print(f"cttk mixing depth {depth}: {its} iterations against {one} with one-step mixing")
+    assert its[g.PREC_FP32_IR] < one
