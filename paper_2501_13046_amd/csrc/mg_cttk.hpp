@@ -154,6 +154,7 @@ __global__ void __launch_bounds__(kBlock) k_aa_push_dots(const T *__restrict__ d
                                                          int64_t m, double *__restrict__ partials)
 {
     constexpr int NV = mix_nv<D>();
+    static_assert(NV <= 32, "block_reduce_store's max_mask holds one bit per value");
     const int64_t n3 = 3 * m;
     const bool push = st[2] > 0.0;
     const int head = (int)st[1];

@@ -279,7 +279,6 @@ template <int NV>
 __device__ __forceinline__ void block_reduce_store(double (&v)[NV], unsigned max_mask,
                                                    double *out)
 {
-    static_assert(NV >= 1 && NV <= 32, "max_mask holds one bit per value");
     __shared__ double sh[NV][kBlock / kWave];
     const int tid = threadIdx.x + threadIdx.y * blockDim.x;
     const int lane = tid % kWave, wid = tid / kWave;
