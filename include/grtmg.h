@@ -152,7 +152,8 @@ enum {
  *                 point combines (0 or 1: the one-step secant form; 2 .. 6: least
  *                 squares over the newest mix_depth difference pairs, with a ridge of
  *                 1e-12 of the largest Gram diagonal entry; the workspace grows by
- *                 2 mix_depth 3 n^3 doubles).  Ignored without MG_FLAG_CTTK.
+ *                 2 mix_depth 3 n^3 values of the working precision).  Ignored
+ *                 without MG_FLAG_CTTK.
  */
 typedef struct mg_params {
     int32_t n, levels, bc, precision, nu_pre, nu_post, solve_momentum, flags;

@@ -148,7 +148,8 @@ struct mg_ctx {
     double *aa_W, *aa_f; // Anderson mixing history of the CTTK solve: previous W and step (3 n^3 each)
     // mixing over mix_depth >= 2 steps: rings of difference pairs dG = dW + dF and dF
     // (mix_depth x 3 n^3 each) and its device state {pairs stored, next slot, steps, .., gamma_0 ..}
-    double *aa_dG, *aa_dF, *aa_st;
+    void *aa_dG, *aa_dF; // in the working type T
+    double *aa_st;
     int vc_psi, vc_W;
     // batch membership: streams borrowed from the batch, updates gated by the
     // instance's active flag, a convergence check after every evaluation
@@ -272,8 +273,9 @@ void carve(mg_ctx *c, Carver &cv)
         c->aa_W = (double *)cv.take(3 * m0);
         c->aa_f = (double *)cv.take(3 * m0);
         if (p.mix_depth >= 2) {
-            c->aa_dG = (double *)cv.take((size_t)p.mix_depth * 3 * m0);
-            c->aa_dF = (double *)cv.take((size_t)p.mix_depth * 3 * m0);
+            // in the working type: FP32 rings in FP32 contexts
+            c->aa_dG = cv.take((size_t)p.mix_depth * 3 * c->cells[0] * c->esz);
+            c->aa_dF = cv.take((size_t)p.mix_depth * 3 * c->cells[0] * c->esz);
             c->aa_st = (double *)cv.take(kMixState * sizeof(double));
         } else {
             c->aa_dG = c->aa_dF = c->aa_st = nullptr;
@@ -1001,13 +1003,13 @@ void mix_ring(mg_ctx *c, double *W, int64_t m, unsigned db)
     constexpr int NV = mix_nv<D>();
     hipLaunchKernelGGL((k_aa_push_dots<T, D>), dim3(db), dim3(kBlock), 0, c->s, (const T *)c->wd0[0],
                        (const double *)(c->scal + S_MEAND), (const double *)W, (const double *)c->aa_W,
-                       (const double *)c->aa_f, c->aa_dG, c->aa_dF, (const double *)c->aa_st, m, c->part);
+                       (const double *)c->aa_f, (T *)c->aa_dG, (T *)c->aa_dF, (const double *)c->aa_st, m, c->part);
     hipLaunchKernelGGL(k_reduce_final<NV>, dim3(1), dim3(kBlock), 0, c->s, (const double *)c->part, (int64_t)db, 0u,
                        0.0, c->aa_st + kMixRed, 0LL);
     hipLaunchKernelGGL(k_aa_solve<D>, dim3(1), dim3(64), 0, c->s, (const double *)(c->aa_st + kMixRed), c->aa_st);
     Probe pr(c, MG_PROBE_UPDATE, 0);
     hipLaunchKernelGGL((k_aa_update_ring<T, D>), dim3(nblk(3 * m)), dim3(kBlock), 0, c->s, W, (const T *)c->wd0[0],
-                       (const double *)(c->scal + S_MEAND), c->aa_W, c->aa_f, (const double *)c->aa_dG,
+                       (const double *)(c->scal + S_MEAND), c->aa_W, c->aa_f, (const T *)c->aa_dG,
                        (const double *)c->aa_st, m);
 }
 

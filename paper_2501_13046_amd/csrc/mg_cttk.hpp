@@ -128,7 +128,9 @@ __global__ void __launch_bounds__(kBlock) k_aa_update(double *__restrict__ W, co
 
 // Anderson mixing over the last D >= 2 steps.  Ring slots j < D hold, for consecutive
 // steps, dF_j = f - f_prev and dG_j = dW_j + dF_j with dW_j = W - W_prev (slot j at
-// j * 3m; the update needs only their sum); the newest pair replaces the oldest.  st = {pairs stored, slot of the next pair, steps
+// j * 3m; the update needs only their sum), stored in the context's working type T (FP32
+// in FP32 contexts: they steer the iteration, not its fixed point); the newest pair
+// replaces the oldest.  st = {pairs stored, slot of the next pair, steps
 // taken, unused x5, gamma_0 .. gamma_{D-1}, unused up to 16, the reduced sums}.  gamma minimises |f - sum_j gamma_j dF_j|
 // through its normal equations: the secant quotient for one stored pair; for more, a
 // ridge of 1e-12 of the largest Gram diagonal entry and Gaussian elimination with
@@ -149,8 +151,8 @@ template <typename T, int D>
 __global__ void __launch_bounds__(kBlock) k_aa_push_dots(const T *__restrict__ d, const double *__restrict__ mean,
                                                          const double *__restrict__ W,
                                                          const double *__restrict__ W_prev,
-                                                         const double *__restrict__ f_prev, double *__restrict__ dG_ring,
-                                                         double *__restrict__ dF_ring, const double *__restrict__ st,
+                                                         const double *__restrict__ f_prev, T *__restrict__ dG_ring,
+                                                         T *__restrict__ dF_ring, const double *__restrict__ st,
                                                          int64_t m, double *__restrict__ partials)
 {
     constexpr int NV = mix_nv<D>();
@@ -164,14 +166,14 @@ __global__ void __launch_bounds__(kBlock) k_aa_push_dots(const T *__restrict__ d
     for (int k = 0; k < NV; k++) v[k] = 0.0;
     for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < n3; q += (int64_t)gridDim.x * kBlock) {
         const double f = (double)d[q] - mean[q / m];
-        const double dFn = push ? f - f_prev[q] : 0.0;
+        const double dFn = push ? (double)(T)(f - f_prev[q]) : 0.0; // the stored value
         if (push) {
-            dF_ring[head * n3 + q] = dFn;
-            dG_ring[head * n3 + q] = (W[q] - W_prev[q]) + dFn;
+            dF_ring[head * n3 + q] = (T)dFn;
+            dG_ring[head * n3 + q] = (T)((W[q] - W_prev[q]) + dFn);
         }
         double F[D];
 #pragma unroll
-        for (int i = 0; i < D; i++) F[i] = i >= cnt ? 0.0 : (push && i == head) ? dFn : dF_ring[i * n3 + q];
+        for (int i = 0; i < D; i++) F[i] = i >= cnt ? 0.0 : (push && i == head) ? dFn : (double)dF_ring[i * n3 + q];
         int k = D;
 #pragma unroll
         for (int i = 0; i < D; i++) {
@@ -242,7 +244,7 @@ template <typename T, int D>
 __global__ void __launch_bounds__(kBlock) k_aa_update_ring(double *__restrict__ W, const T *__restrict__ d,
                                                            const double *__restrict__ mean,
                                                            double *__restrict__ W_prev, double *__restrict__ f_prev,
-                                                           const double *__restrict__ dG_ring,
+                                                           const T *__restrict__ dG_ring,
                                                            const double *__restrict__ st, int64_t m)
 {
     const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -254,7 +256,7 @@ __global__ void __launch_bounds__(kBlock) k_aa_update_ring(double *__restrict__ 
     double mix = 0.0;
 #pragma unroll
     for (int j = 0; j < D; j++)
-        if (j < cnt) mix += st[8 + j] * dG_ring[j * n3 + q];
+        if (j < cnt) mix += st[8 + j] * (double)dG_ring[j * n3 + q];
     W[q] = w + f - mix;
     W_prev[q] = w;
     f_prev[q] = f;
